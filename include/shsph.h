@@ -1,0 +1,192 @@
+/*
+ * shsph.h -- C ABI of the MI355X (gfx950) SPH hot path: on-the-fly Morton /
+ * radix tree, two-stage neighbour cache, smoothing-length iteration and the
+ * SPH force / energy equations, after Shamrock (arXiv 2503.09713).
+ *
+ * Conventions (every entry point):
+ *   - Returns SHSPH_OK (0) or a negative SHSPH_E* code; nothing throws.
+ *     shsph_last_error() gives a message for the last failure on a context.
+ *   - Particle arrays are DEVICE pointers owned by the caller, structure of
+ *     arrays, one element per particle, element type given by `dtype`
+ *     (float or double).  They are borrowed only for the duration of the
+ *     work enqueued by the call.
+ *   - Work is enqueued on the context's stream (shsph_set_stream).  A call
+ *     may synchronise that stream to read small counters (leaf count,
+ *     neighbour-cache sizes, the h-iteration outcome); results in caller
+ *     arrays are complete when the call returns.
+ *   - Indices into the neighbour cache and the tree are positions in Morton
+ *     (key) order; the permutation `eps` (sorted slot i <- input index
+ *     eps[i]) maps them back to the caller's order.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef SHSPH_H
+#define SHSPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHSPH_OK 0
+#define SHSPH_EINVAL (-1)     /* null pointer, size, dtype or box error, h <= 0 */
+#define SHSPH_ENOMEM (-2)     /* device allocation failed */
+#define SHSPH_ENOCONV (-3)    /* h iteration did not converge in max_iter; h is the last iterate */
+#define SHSPH_ECAPACITY (-4)  /* traversal stack or cache capacity exceeded */
+#define SHSPH_EHIP (-5)       /* HIP runtime failure */
+#define SHSPH_ESTATE (-6)     /* calls out of order (e.g. density before build_tree) */
+
+typedef enum { SHSPH_F32 = 0, SHSPH_F64 = 1 } shsph_dtype;
+
+typedef struct shsph_ctx shsph_ctx;
+
+/* Method parameters.  Defaults (shsph_params_default) follow the paper:
+ *   hfact = 1.2 for the M4 kernel and rho(h) = m (hfact/h)^3 (App. G, Eq. rhoh);
+ *   chi = 1.1 ghost/cache tolerance and lambda = 1.2 Newton clamp (App. G);
+ *   alpha_av = 1, beta_av = 2 artificial viscosity, beta_u = 1 conductivity
+ *   (Sect. 2.1 and Sect. 4.2); c_cour = 0.3, c_force = 0.25 (App. H.2);
+ *   gamma = 5/3 adiabatic EOS; eps_h = 1e-6 Newton tolerance (the paper
+ *   leaves it open), max_iter = 50; n_red = 3 reduction passes (App. D.2). */
+typedef struct {
+    double hfact;
+    double gamma;
+    double alpha_av;
+    double beta_av;
+    double beta_u;
+    double chi;
+    double lambda;
+    double eps_h;
+    double c_cour;
+    double c_force;
+    int32_t max_iter;
+    int32_t n_red;
+    int32_t max_restarts;   /* cache rebuilds allowed when h exceeds chi h (default 8) */
+    int32_t reserved;
+} shsph_params;
+
+/* One SPH instance.  x..h are read; h, rho, omega, ax..dudt are written as
+ * documented per call.  `pid` (optional) is a per-particle id carried
+ * through the reordering of shsph_step.  Equal-mass particles (mass).
+ * periodic = 1: box [lo, hi) with minimum-image separations (requires
+ * 2.2 max(h) < (hi-lo)/2 on every axis); periodic = 0: isolated, the box is
+ * the data extent (lo/hi are ignored). */
+typedef struct {
+    int64_t n;
+    int32_t dtype;          /* shsph_dtype */
+    int32_t periodic;
+    double mass;
+    double lo[3];
+    double hi[3];
+    void *x, *y, *z;        /* positions */
+    void *vx, *vy, *vz;     /* velocities */
+    void *u;                /* specific internal energy */
+    void *h;                /* smoothing length */
+    void *ax, *ay, *az;     /* dv/dt */
+    void *dudt;             /* du/dt */
+    void *rho, *omega;      /* optional outputs */
+    uint32_t *pid;          /* optional */
+} shsph_particles;
+
+/* Counters of the last build / evaluation / step. */
+typedef struct {
+    int64_t n;
+    int64_t n_leaf;          /* leaves after dedupe + reduction */
+    int64_t n_leaf_neigh;    /* stage-1 cache entries (leaf -> leaves) */
+    int64_t n_neigh;         /* stage-2 cache entries (particle -> particles) */
+    int32_t n_red;
+    int32_t restarts;        /* cache rebuilds caused by h > chi h_cache */
+    int32_t max_iter_seen;   /* largest Newton iteration count of any particle */
+    int32_t n_noconv;        /* particles that did not converge */
+    double dt_cfl;           /* CFL dt from the last force evaluation */
+    double dv_max;           /* max |dv| of the last corrector */
+    double dv2_sum;          /* sum |dv|^2 */
+    double v2_sum;           /* sum |v^{n+1}|^2 */
+} shsph_info;
+
+/* Host buffers receiving the tree of the last build (test and debug use).
+ * Any pointer may be NULL.  Sizes: n = particles, L = n_leaf, I = L - 1,
+ * NN = 2L - 1, E1 = n_leaf_neigh, E2 = n_neigh.  Node arrays are indexed by
+ * node: internal nodes 0..I-1, then leaves I..NN-1.  T = the dtype. */
+typedef struct {
+    uint64_t *keys;      /* n   Morton keys in the caller's order (App. C.1) */
+    uint32_t *eps;       /* n   sort permutation: key slot i <- input eps[i] */
+    uint64_t *mu;        /* n   sorted keys */
+    uint8_t *xi;         /* n   keep mask after reduction (App. D, Alg. 1) */
+    uint32_t *id;        /* L+1 first key slot of each leaf, id[L] = n */
+    uint64_t *mu_leaf;   /* L   leaf codes */
+    uint32_t *lchild, *rchild, *endrange;  /* I  Karras tables (App. C.7) */
+    uint8_t *lflag, *rflag;                /* I */
+    uint32_t *parent;    /* NN  (root: 0xffffffff) */
+    void *bmin;          /* 3*NN T  tight box lower corner */
+    void *bmax;          /* 3*NN T  tight box upper corner */
+    void *hmax;          /* NN  T   max h of the cell */
+    uint32_t *pbox;      /* 6*NN  integer prefix box X0 Y0 Z0 X1 Y1 Z1 (App. C.6) */
+    int32_t *plen;       /* NN    prefix length of the box */
+    uint64_t *leaf_off;  /* L+1  stage-1 offsets */
+    uint32_t *leaf_list; /* E1   neighbour leaves (ascending) */
+    uint64_t *neigh_off; /* n+1  stage-2 offsets (Alg. 5) */
+    uint32_t *neigh_list;/* E2   neighbours in key slots (ascending, self included) */
+    void *h_sorted;      /* n T  h in key order (after a density call: converged h) */
+} shsph_tree_export;
+
+/* Fill *p with the defaults listed above. */
+void shsph_params_default(shsph_params *p);
+
+/* Create a context on HIP device `device` (parameters copied; NULL = defaults).
+ * EINVAL for a bad device or parameter, EHIP on runtime failure. */
+int shsph_create(int device, const shsph_params *p, shsph_ctx **out);
+
+/* Release the context and all its device memory (waits for its stream). */
+int shsph_destroy(shsph_ctx *ctx);
+
+/* Use `stream` (a hipStream_t, NULL = the null stream) for all later work. */
+int shsph_set_stream(shsph_ctx *ctx, void *stream);
+
+/* Message of the last failure on this context ("" if none).  Valid until the
+ * next call on the context. */
+const char *shsph_last_error(const shsph_ctx *ctx);
+
+/* Steps a2-a8 of the hot path on the particles as given (App. C-F):
+ * Morton keys (App. C.1) -> stable radix sort -> keep mask + n_red reduction
+ * passes (App. D, Alg. 1) -> compaction -> Karras radix tree (App. C.7) ->
+ * bottom-up tight cell boxes with h_max -> two-stage neighbour cache with the
+ * chi-extended object-object criterion (App. E.4, Alg. 5, App. F).
+ * Reads x, y, z, h.  The tree and caches stay in the context until the next
+ * build or step.  EINVAL on bad input, ECAPACITY if the traversal stack
+ * overflows. */
+int shsph_build_tree(shsph_ctx *ctx, const shsph_particles *p);
+
+/* Step a9 (App. G, Alg. 7; Sect. 2.1 Eq. sphomega): self-consistent h and
+ * rho = m (hfact/h)^3 by per-particle Newton iteration over the cache, with
+ * cache rebuilds when h leaves chi times its cache h; then Omega.  Needs a
+ * build on the same particles.  Writes h (in place), rho and omega (if
+ * non-NULL) in the caller's order.  Reads u (if non-NULL) for the pressure
+ * used by a following shsph_force.  ENOCONV if some particle did not
+ * converge (its h is the last iterate). */
+int shsph_density(shsph_ctx *ctx, shsph_particles *p);
+
+/* Step a10 (Sect. 2.1 Eqs. sphvel, sphuint, with artificial viscosity and
+ * conductivity): writes ax, ay, az, dudt in the caller's order from the h,
+ * rho, Omega of the preceding shsph_density and the caller's v and u.  Also
+ * reduces the CFL dt (App. H.2), readable with shsph_get_info.  ESTATE if no
+ * density result is held. */
+int shsph_force(shsph_ctx *ctx, shsph_particles *p);
+
+/* Steps a1-a11: one kick-drift-kick step (App. H.1) of dt (dt <= 0: the CFL
+ * dt of the previous force evaluation).  Reads the state at t^n and
+ * ax..dudt = derivatives at t^n; writes the state at t^{n+1} with its
+ * derivatives, h, and rho/omega/pid when non-NULL.  The particles come back
+ * REORDERED into the new Morton order (all arrays consistently).  dt_used
+ * (optional) receives the dt taken.  Errors as for the calls above. */
+int shsph_step(shsph_ctx *ctx, shsph_particles *p, double dt, double *dt_used);
+
+/* Counters of the last build / density / force / step. */
+int shsph_get_info(shsph_ctx *ctx, shsph_info *out);
+
+/* Copy the tree of the last build to host buffers (see shsph_tree_export). */
+int shsph_export_tree(shsph_ctx *ctx, const shsph_tree_export *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHSPH_H */

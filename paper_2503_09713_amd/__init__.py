@@ -1,0 +1,263 @@
+"""Python binding of ``libshsph.so``, the MI355X SPH hot path.
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device memory comes from PyTorch tensors (``device='cuda'``); the
+library never falls back to anything else and this module raises if the
+library has not been built (``python -m paper_2503_09713_amd.build``).
+
+Entry points mirror ``include/shsph.h``: ``Context.build_tree``,
+``Context.density``, ``Context.force``, ``Context.step``,
+``Context.get_info`` and ``Context.export_tree``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libshsph.so")
+_lib = None
+
+SHSPH_OK, SHSPH_EINVAL, SHSPH_ENOMEM, SHSPH_ENOCONV = 0, -1, -2, -3
+SHSPH_ECAPACITY, SHSPH_EHIP, SHSPH_ESTATE = -4, -5, -6
+ERRORS = {SHSPH_EINVAL: "EINVAL", SHSPH_ENOMEM: "ENOMEM", SHSPH_ENOCONV: "ENOCONV",
+          SHSPH_ECAPACITY: "ECAPACITY", SHSPH_EHIP: "EHIP", SHSPH_ESTATE: "ESTATE"}
+F32, F64 = 0, 1
+
+
+class ShsphError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("hfact", C.c_double), ("gamma", C.c_double), ("alpha_av", C.c_double),
+                ("beta_av", C.c_double), ("beta_u", C.c_double), ("chi", C.c_double),
+                ("lambda_", C.c_double), ("eps_h", C.c_double), ("c_cour", C.c_double),
+                ("c_force", C.c_double), ("max_iter", C.c_int32), ("n_red", C.c_int32),
+                ("max_restarts", C.c_int32), ("reserved", C.c_int32)]
+
+
+class CParticles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dtype", C.c_int32), ("periodic", C.c_int32),
+                ("mass", C.c_double), ("lo", C.c_double * 3), ("hi", C.c_double * 3)] + \
+               [(k, C.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay",
+                                          "az", "dudt", "rho", "omega")] + [("pid", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_leaf", C.c_int64), ("n_leaf_neigh", C.c_int64),
+                ("n_neigh", C.c_int64), ("n_red", C.c_int32), ("restarts", C.c_int32),
+                ("max_iter_seen", C.c_int32), ("n_noconv", C.c_int32), ("dt_cfl", C.c_double),
+                ("dv_max", C.c_double), ("dv2_sum", C.c_double), ("v2_sum", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_EXPORT_FIELDS = ["keys", "eps", "mu", "xi", "id", "mu_leaf", "lchild", "rchild", "endrange",
+                  "lflag", "rflag", "parent", "bmin", "bmax", "hmax", "pbox", "plen", "leaf_off",
+                  "leaf_list", "neigh_off", "neigh_list", "h_sorted"]
+
+
+class TreeExport(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in _EXPORT_FIELDS]
+
+
+def lib():
+    """Load libshsph.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2503_09713_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, ip = C.c_void_p, C.c_int
+    L.shsph_params_default.argtypes = [C.POINTER(Params)]
+    L.shsph_params_default.restype = None
+    L.shsph_create.argtypes = [ip, C.POINTER(Params), C.POINTER(vp)]
+    L.shsph_destroy.argtypes = [vp]
+    L.shsph_set_stream.argtypes = [vp, vp]
+    L.shsph_last_error.argtypes = [vp]
+    L.shsph_last_error.restype = C.c_char_p
+    for fn in ("shsph_build_tree", "shsph_density", "shsph_force"):
+        getattr(L, fn).argtypes = [vp, C.POINTER(CParticles)]
+    L.shsph_step.argtypes = [vp, C.POINTER(CParticles), C.c_double, C.POINTER(C.c_double)]
+    L.shsph_get_info.argtypes = [vp, C.POINTER(Info)]
+    L.shsph_export_tree.argtypes = [vp, C.POINTER(TreeExport)]
+    for fn in ("shsph_create", "shsph_destroy", "shsph_set_stream", "shsph_build_tree",
+               "shsph_density", "shsph_force", "shsph_step", "shsph_get_info",
+               "shsph_export_tree"):
+        getattr(L, fn).restype = ip
+    _lib = L
+    return L
+
+
+def default_params() -> Params:
+    p = Params()
+    lib().shsph_params_default(C.byref(p))
+    return p
+
+
+class ParticleSet:
+    """Device-resident SoA particle arrays (torch tensors) of one instance."""
+
+    FIELDS = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay", "az", "dudt", "rho", "omega")
+
+    def __init__(self, arrays: dict, mass: float, lo, hi, periodic: bool, device="cuda"):
+        import torch
+        self.torch = torch
+        x = np.asarray(arrays["x"])
+        self.dtype = x.dtype
+        if self.dtype not in (np.float32, np.float64):
+            raise TypeError(self.dtype)
+        tdt = torch.float32 if self.dtype == np.float32 else torch.float64
+        self.n = int(x.shape[0])
+        self.t = {}
+        for k in self.FIELDS:
+            if k in arrays and arrays[k] is not None:
+                a = np.ascontiguousarray(np.asarray(arrays[k], dtype=self.dtype))
+                self.t[k] = torch.from_numpy(a).to(device)
+            else:
+                self.t[k] = torch.zeros(self.n, dtype=tdt, device=device)
+        pid = arrays.get("pid")
+        if pid is None:
+            pid = np.arange(self.n, dtype=np.int32)
+        self.t["pid"] = torch.from_numpy(np.ascontiguousarray(np.asarray(pid).astype(np.int32))).to(device)
+        self.mass = float(mass)
+        self.lo = tuple(float(v) for v in lo)
+        self.hi = tuple(float(v) for v in hi)
+        self.periodic = bool(periodic)
+
+    @classmethod
+    def from_particles(cls, p, device="cuda"):
+        """From a ``gen.Particles``-like object (numpy fields, mass, box)."""
+        return cls(p.fields(), p.mass, p.lo, p.hi, p.periodic, device=device)
+
+    def cstruct(self) -> CParticles:
+        c = CParticles()
+        c.n = self.n
+        c.dtype = F32 if self.dtype == np.float32 else F64
+        c.periodic = 1 if self.periodic else 0
+        c.mass = self.mass
+        c.lo[:] = self.lo
+        c.hi[:] = self.hi
+        for k in self.FIELDS:
+            setattr(c, k, self.t[k].data_ptr())
+        c.pid = self.t["pid"].data_ptr()
+        return c
+
+    def host(self, *keys) -> dict:
+        keys = keys or (self.FIELDS + ("pid",))
+        out = {k: self.t[k].cpu().numpy() for k in keys}
+        if "pid" in out:
+            out["pid"] = out["pid"].view(np.uint32)
+        return out
+
+
+class Context:
+    """A shsph context bound to one device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, params: Params | None = None, stream=None, **kw):
+        L = lib()
+        if params is None:
+            params = default_params()
+        for k, v in kw.items():
+            setattr(params, "lambda_" if k == "lambda" else k, v)
+        self.params = params
+        h = C.c_void_p()
+        rc = L.shsph_create(int(device), C.byref(params), C.byref(h))
+        if rc != SHSPH_OK:
+            raise ShsphError(rc, "shsph_create failed")
+        self.h = h
+        self.L = L
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.set_stream(stream)
+
+    def _check(self, rc: int, allow=()):
+        if rc != SHSPH_OK and rc not in allow:
+            raise ShsphError(rc, self.L.shsph_last_error(self.h).decode())
+        return rc
+
+    def set_stream(self, stream) -> None:
+        self._check(self.L.shsph_set_stream(self.h, C.c_void_p(int(stream) if stream else 0)))
+
+    def build_tree(self, ps: ParticleSet) -> None:
+        self._cp = ps.cstruct()
+        self._check(self.L.shsph_build_tree(self.h, C.byref(self._cp)))
+
+    def density(self, ps: ParticleSet, allow_noconv: bool = False) -> int:
+        self._cp = ps.cstruct()
+        allow = (SHSPH_ENOCONV,) if allow_noconv else ()
+        return self._check(self.L.shsph_density(self.h, C.byref(self._cp)), allow)
+
+    def force(self, ps: ParticleSet) -> None:
+        self._cp = ps.cstruct()
+        self._check(self.L.shsph_force(self.h, C.byref(self._cp)))
+
+    def step(self, ps: ParticleSet, dt: float = 0.0, want_dt: bool = False):
+        self._cp = ps.cstruct()
+        used = C.c_double(0.0)
+        self._check(self.L.shsph_step(self.h, C.byref(self._cp), float(dt),
+                                      C.byref(used) if want_dt else None))
+        return used.value if want_dt else None
+
+    def get_info(self) -> dict:
+        o = Info()
+        self._check(self.L.shsph_get_info(self.h, C.byref(o)))
+        return o.as_dict()
+
+    def export_tree(self, dtype=np.float32, fields=None) -> dict:
+        """Copy the last tree / caches to host numpy arrays."""
+        info = self.get_info()
+        n, nl = info["n"], info["n_leaf"]
+        ni, nn = nl - 1, 2 * nl - 1
+        e1, e2 = info["n_leaf_neigh"], info["n_neigh"]
+        T = np.dtype(dtype)
+        shapes = dict(keys=(n, np.uint64), eps=(n, np.uint32), mu=(n, np.uint64), xi=(n, np.uint8),
+                      id=(nl + 1, np.uint32), mu_leaf=(nl, np.uint64), lchild=(ni, np.uint32),
+                      rchild=(ni, np.uint32), endrange=(ni, np.uint32), lflag=(ni, np.uint8),
+                      rflag=(ni, np.uint8), parent=(nn, np.uint32), bmin=((nn, 3), T),
+                      bmax=((nn, 3), T), hmax=(nn, T), pbox=((nn, 6), np.uint32),
+                      plen=(nn, np.int32), leaf_off=(nl + 1, np.uint64),
+                      leaf_list=(e1, np.uint32), neigh_off=(n + 1, np.uint64),
+                      neigh_list=(e2, np.uint32), h_sorted=(n, T))
+        want = fields or list(shapes)
+        out, ex = {}, TreeExport()
+        for k in want:
+            shp, dt = shapes[k]
+            a = np.zeros(shp, dt)
+            out[k] = a
+            setattr(ex, k, a.ctypes.data if a.size else None)
+        self._check(self.L.shsph_export_tree(self.h, C.byref(ex)))
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            self.L.shsph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def exported_symbols():
+    """Names declared in include/shsph.h (for the ABI check)."""
+    hdr = os.path.join(_HERE, "..", "include", "shsph.h")
+    import re
+    txt = open(hdr).read()
+    return sorted(set(re.findall(r"\b(shsph_[a-z_]+)\s*\(", txt)))

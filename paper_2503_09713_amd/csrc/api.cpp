@@ -1,0 +1,731 @@
+// Host side of the shsph C ABI: context, device buffers, and the sequences
+// of kernel launches behind shsph_build_tree / _density / _force / _step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/shsph.h"
+#include "kernels.hpp"
+
+using namespace shsph;
+
+namespace {
+
+struct Buf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+enum State { ST_NONE = 0, ST_TREE = 1, ST_DENSITY = 2, ST_FORCE = 3 };
+
+}  // namespace
+
+struct shsph_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    shsph_params prm;
+    std::string err;
+
+    // shape of the current build
+    int dtype = 0;
+    i64 n = 0;
+    int ninst = 0;
+    i64 n_leaf = 0, n_internal = 0, n_lneigh = 0, n_neigh = 0;
+    int state = ST_NONE;
+    int restarts = 0;
+    int vals_sel = 0;       // which value buffer holds eps after the sort
+    int xi_sel = 0;         // which mask buffer holds the final keep mask
+
+    // device buffers (grown on demand, never shrunk)
+    Buf keys[2], vals[2], hist, hist_scan, scan_tmp, bbox;
+    Buf posh, velu, vhalf, hn, hcache, pid_s, thermo, omega, acc, vsig, status;
+    Buf xi[2], xscan, id, mu_leaf;
+    Buf lchild, rchild, endrange, lflag, rflag, child, parent, arrive, blo, bhi;
+    Buf lcnt, loff, llist, ncnt, noff, nlist, overflow;
+    Buf inst_d, poff_d, leaf_off_d, ioff_d, root_d, stat_d, dt_inst_d, dt_host_d;
+    Buf pbox, plen;
+
+    // pinned host staging for counters
+    void* pinned = nullptr;
+
+    std::vector<InstDev> inst_h;
+    std::vector<i64> poff_h;
+};
+
+namespace {
+
+const size_t PINNED_BYTES = 4096;
+
+int fail(shsph_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPTRY(ctx, expr)                                                                \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? SHSPH_ENOMEM : SHSPH_EHIP,       \
+                        std::string(#expr ": ") + hipGetErrorString(e_));                \
+    } while (0)
+
+#define TRY(expr)                                                                        \
+    do {                                                                                 \
+        int r_ = (expr);                                                                 \
+        if (r_ != SHSPH_OK) return r_;                                                   \
+    } while (0)
+
+// Make `b` hold at least `bytes`; grows by 25 % beyond the request.
+int ensure(shsph_ctx* c, Buf& b, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    if (b.cap >= bytes) return SHSPH_OK;
+    if (b.p) {
+        HIPTRY(c, hipStreamSynchronize(c->stream));
+        HIPTRY(c, hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    want = (want + 255) & ~(size_t)255;
+    HIPTRY(c, hipMalloc(&b.p, want));
+    b.cap = want;
+    return SHSPH_OK;
+}
+
+template <class T> T* P(Buf& b) { return (T*)b.p; }
+
+int check_launch(shsph_ctx* c, const char* where)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, SHSPH_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+    return SHSPH_OK;
+}
+
+// Copy `bytes` from device to the pinned staging area and wait.
+int read_back(shsph_ctx* c, const void* dev, size_t bytes, size_t off = 0)
+{
+    HIPTRY(c, hipMemcpyAsync((char*)c->pinned + off, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    return SHSPH_OK;
+}
+
+bool finite_box(const shsph_particles* p)
+{
+    for (int d = 0; d < 3; ++d)
+        if (!(std::isfinite(p->lo[d]) && std::isfinite(p->hi[d]) && p->hi[d] > p->lo[d])) return false;
+    return true;
+}
+
+int validate(shsph_ctx* c, const shsph_particles* p, bool need_v, bool need_a)
+{
+    if (!p) return fail(c, SHSPH_EINVAL, "particles is NULL");
+    if (p->n < 1 || p->n > (int64_t)0x7fffffff) return fail(c, SHSPH_EINVAL, "n must be in [1, 2^31)");
+    if (p->dtype != SHSPH_F32 && p->dtype != SHSPH_F64) return fail(c, SHSPH_EINVAL, "bad dtype");
+    if (!p->x || !p->y || !p->z || !p->h) return fail(c, SHSPH_EINVAL, "x, y, z, h are required");
+    if (p->periodic && !finite_box(p)) return fail(c, SHSPH_EINVAL, "periodic box needs hi > lo");
+    if (!(p->mass > 0) || !std::isfinite(p->mass)) return fail(c, SHSPH_EINVAL, "mass must be > 0");
+    if (need_v && (!p->vx || !p->vy || !p->vz || !p->u))
+        return fail(c, SHSPH_EINVAL, "vx, vy, vz, u are required");
+    if (need_a && (!p->ax || !p->ay || !p->az || !p->dudt))
+        return fail(c, SHSPH_EINVAL, "ax, ay, az, dudt are required");
+    return SHSPH_OK;
+}
+
+SphParams sph_params(const shsph_params& q)
+{
+    SphParams s;
+    s.hfact = q.hfact; s.gamma = q.gamma; s.alpha = q.alpha_av; s.beta = q.beta_av;
+    s.beta_u = q.beta_u; s.chi = q.chi; s.lambda = q.lambda; s.eps_h = q.eps_h;
+    s.c_cour = q.c_cour; s.c_force = q.c_force; s.r_kern = 2.0; s.max_iter = q.max_iter;
+    return s;
+}
+
+template <class T> FieldPtrs<T> fields(const shsph_particles* p)
+{
+    FieldPtrs<T> f;
+    f.x = (const T*)p->x; f.y = (const T*)p->y; f.z = (const T*)p->z;
+    f.vx = (const T*)p->vx; f.vy = (const T*)p->vy; f.vz = (const T*)p->vz;
+    f.u = (const T*)p->u; f.h = (const T*)p->h;
+    f.ax = (const T*)p->ax; f.ay = (const T*)p->ay; f.az = (const T*)p->az;
+    f.du = (const T*)p->dudt;
+    f.pid = p->pid;
+    return f;
+}
+
+template <class T> SortedPtrs<T> sorted(shsph_ctx* c, bool with_step)
+{
+    SortedPtrs<T> s;
+    s.posh = P<vec4<T>>(c->posh);
+    s.velu = P<vec4<T>>(c->velu);
+    s.vhalf = with_step ? P<vec4<T>>(c->vhalf) : nullptr;
+    s.hn = P<T>(c->hn);
+    s.hcache = P<T>(c->hcache);
+    s.pid = P<u32>(c->pid_s);
+    return s;
+}
+
+// Instance table for a single instance.
+int set_single_instance(shsph_ctx* c, const shsph_particles* p)
+{
+    c->ninst = 1;
+    c->inst_h.assign(1, InstDev());
+    InstDev& in = c->inst_h[0];
+    in.p_off = 0;
+    in.p_cnt = p->n;
+    for (int d = 0; d < 3; ++d) { in.lo[d] = p->lo[d]; in.hi[d] = p->hi[d]; }
+    in.mass = p->mass;
+    in.periodic = p->periodic ? 1 : 0;
+    in.pad = 0;
+    c->poff_h = { 0, p->n };
+    TRY(ensure(c, c->inst_d, sizeof(InstDev)));
+    TRY(ensure(c, c->poff_d, 2 * sizeof(i64)));
+    TRY(ensure(c, c->stat_d, sizeof(InstStat)));
+    TRY(ensure(c, c->dt_inst_d, sizeof(double)));
+    TRY(ensure(c, c->dt_host_d, sizeof(double)));
+    TRY(ensure(c, c->leaf_off_d, 2 * sizeof(i64)));
+    TRY(ensure(c, c->ioff_d, 2 * sizeof(i64)));
+    TRY(ensure(c, c->root_d, sizeof(u32)));
+    TRY(ensure(c, c->bbox, 6 * sizeof(u64)));
+    HIPTRY(c, hipMemcpyAsync(c->inst_d.p, c->inst_h.data(), sizeof(InstDev), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPTRY(c, hipMemcpyAsync(c->poff_d.p, c->poff_h.data(), 2 * sizeof(i64), hipMemcpyHostToDevice,
+                             c->stream));
+    return SHSPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tree build: keys -> sort -> gather -> mask/reduce/compact -> Karras ->
+// boxes -> caches.  `dt_dev` non-NULL: positions are the leapfrog-predicted
+// ones (stepping); the gather then also forms v*, u*, v^{n+1/2}, u^{n+1/2}.
+// ---------------------------------------------------------------------------
+template <class T> int build_caches(shsph_ctx* c);
+
+template <class T> int build(shsph_ctx* c, const shsph_particles* p, const double* dt_dev, bool step)
+{
+    const i64 n = p->n;
+    hipStream_t st = c->stream;
+    const int nred = c->prm.n_red < 0 ? 3 : c->prm.n_red;
+    const FieldPtrs<T> f = fields<T>(p);
+
+    TRY(ensure(c, c->keys[0], n * sizeof(u64)));
+    TRY(ensure(c, c->keys[1], n * sizeof(u64)));
+    TRY(ensure(c, c->vals[0], n * sizeof(u32)));
+    TRY(ensure(c, c->vals[1], n * sizeof(u32)));
+    const size_t nh = radix_hist_count(n);
+    TRY(ensure(c, c->hist, nh * sizeof(u32)));
+    TRY(ensure(c, c->hist_scan, (nh + 1) * sizeof(u32)));
+    TRY(ensure(c, c->scan_tmp, scan_tmp_bytes(std::max<i64>(n + 1, (i64)nh + 1))));
+    TRY(ensure(c, c->posh, n * sizeof(vec4<T>)));
+    TRY(ensure(c, c->velu, n * sizeof(vec4<T>)));
+    if (step) TRY(ensure(c, c->vhalf, n * sizeof(vec4<T>)));
+    TRY(ensure(c, c->hn, n * sizeof(T)));
+    TRY(ensure(c, c->hcache, n * sizeof(T)));
+    TRY(ensure(c, c->pid_s, n * sizeof(u32)));
+    TRY(ensure(c, c->xi[0], n));
+    TRY(ensure(c, c->xi[1], n));
+    TRY(ensure(c, c->xscan, (n + 1) * sizeof(u32)));
+    TRY(ensure(c, c->id, (n + 1) * sizeof(u32)));
+    TRY(ensure(c, c->mu_leaf, n * sizeof(u64)));
+
+    InstDev* inst = P<InstDev>(c->inst_d);
+    const i64* poff = P<i64>(c->poff_d);
+    const int ninst = c->ninst;
+
+    // a1 (+ isolated box) and a2: predicted positions -> Morton keys
+    bool any_isolated = false;
+    for (const InstDev& in : c->inst_h) any_isolated |= !in.periodic;
+    if (any_isolated) launch_bbox<T>(f, n, inst, poff, ninst, dt_dev, P<u64>(c->bbox), st);
+    launch_predict_morton<T>(f, n, inst, poff, ninst, dt_dev, P<u64>(c->keys[0]), P<u32>(c->vals[0]), st);
+    TRY(check_launch(c, "morton"));
+    // a3: stable radix sort of (key, index), then gather into key order
+    const int sel = radix_sort_pairs(P<u64>(c->keys[0]), P<u32>(c->vals[0]), P<u64>(c->keys[1]),
+                                     P<u32>(c->vals[1]), n, 63, poff, ninst, P<u32>(c->hist),
+                                     P<u32>(c->hist_scan), c->scan_tmp.p, st);
+    c->vals_sel = sel;
+    const u64* mu = P<u64>(c->keys[sel]);
+    const u32* eps = P<u32>(c->vals[sel]);
+    TRY(check_launch(c, "sort"));
+    SortedPtrs<T> s = sorted<T>(c, step);
+    launch_gather<T>(f, n, inst, poff, ninst, dt_dev, eps, s, st);
+    TRY(check_launch(c, "gather"));
+    // a4: keep mask, reduction passes (double-buffered), compaction
+    launch_mask_init(mu, n, poff, ninst, P<u8>(c->xi[0]), st);
+    int xs = 0;
+    for (int r = 0; r < nred; ++r) {
+        launch_reduce_pass(mu, n, poff, ninst, P<u8>(c->xi[xs]), P<u8>(c->xi[xs ^ 1]), st);
+        xs ^= 1;
+    }
+    c->xi_sel = xs;
+    scan_u8_u32(P<u8>(c->xi[xs]), P<u32>(c->xscan), n, c->scan_tmp.p, st);
+    launch_compact(mu, P<u8>(c->xi[xs]), P<u32>(c->xscan), n, P<u32>(c->id), P<u64>(c->mu_leaf), st);
+    TRY(check_launch(c, "compact"));
+    TRY(read_back(c, P<u32>(c->xscan) + n, sizeof(u32)));
+    const i64 nl = *(u32*)c->pinned;
+    c->n_leaf = nl;
+    c->n_internal = nl - ninst;
+    // a5: Karras tables + parents
+    const i64 ni = c->n_internal, nn = ni + nl;
+    TRY(ensure(c, c->lchild, std::max<i64>(ni, 1) * sizeof(u32)));
+    TRY(ensure(c, c->rchild, std::max<i64>(ni, 1) * sizeof(u32)));
+    TRY(ensure(c, c->endrange, std::max<i64>(ni, 1) * sizeof(u32)));
+    TRY(ensure(c, c->lflag, std::max<i64>(ni, 1)));
+    TRY(ensure(c, c->rflag, std::max<i64>(ni, 1)));
+    TRY(ensure(c, c->child, 2 * std::max<i64>(ni, 1) * sizeof(u32)));
+    TRY(ensure(c, c->parent, nn * sizeof(u32)));
+    TRY(ensure(c, c->arrive, std::max<i64>(ni, 1) * sizeof(u32)));
+    TRY(ensure(c, c->blo, nn * sizeof(vec4<T>)));
+    TRY(ensure(c, c->bhi, nn * sizeof(vec4<T>)));
+    launch_inst_leaves(poff, ninst, P<u32>(c->xscan), n, P<i64>(c->leaf_off_d), P<i64>(c->ioff_d),
+                       P<u32>(c->root_d), P<u32>(c->parent), ni, st);
+    TreePtrs t;
+    t.lchild = P<u32>(c->lchild); t.rchild = P<u32>(c->rchild); t.endrange = P<u32>(c->endrange);
+    t.lflag = P<u8>(c->lflag); t.rflag = P<u8>(c->rflag);
+    t.child = P<u32>(c->child); t.parent = P<u32>(c->parent);
+    launch_karras(P<u64>(c->mu_leaf), P<i64>(c->leaf_off_d), P<i64>(c->ioff_d), ninst, ni, t, st);
+    TRY(check_launch(c, "karras"));
+    c->restarts = 0;
+    return build_caches<T>(c);
+}
+
+// a6-a8 on the current tree with h_cache = posh.w: boxes, stage 1, stage 2.
+template <class T> int build_caches(shsph_ctx* c)
+{
+    hipStream_t st = c->stream;
+    const i64 n = c->n, nl = c->n_leaf, ni = c->n_internal;
+    const InstDev* inst = P<InstDev>(c->inst_d);
+    const i64* poff = P<i64>(c->poff_d);
+    const int ninst = c->ninst;
+    const vec4<T>* posh = P<vec4<T>>(c->posh);
+    // a6: bottom-up boxes and h_max
+    launch_fill_u32(P<u32>(c->arrive), std::max<i64>(ni, 1), 0u, st);
+    launch_boxes_up<T>(posh, P<u32>(c->id), nl, ni, P<u32>(c->child), P<u32>(c->parent),
+                       P<u32>(c->arrive), P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), st);
+    TRY(check_launch(c, "boxes"));
+    // a7: stage 1, leaf -> leaves
+    const double rk = 2.0 * c->prm.chi;
+    TRY(ensure(c, c->lcnt, (nl + 1) * sizeof(u32)));
+    TRY(ensure(c, c->loff, (nl + 1) * sizeof(u64)));
+    TRY(ensure(c, c->overflow, sizeof(u32)));
+    TRY(ensure(c, c->scan_tmp, scan_tmp_bytes(n + 1)));
+    launch_fill_u32(P<u32>(c->overflow), 1, 0u, st);
+    launch_leaf_neigh<T>(false, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child), ni, nl,
+                         P<i64>(c->leaf_off_d), ninst, P<u32>(c->root_d), inst, rk, nullptr,
+                         P<u32>(c->lcnt), nullptr, P<u32>(c->overflow), st);
+    scan_u32_u64(P<u32>(c->lcnt), P<u64>(c->loff), nl, c->scan_tmp.p, st);
+    TRY(check_launch(c, "stage1 count"));
+    HIPTRY(c, hipMemcpyAsync(c->pinned, P<u64>(c->loff) + nl, sizeof(u64), hipMemcpyDeviceToHost, st));
+    HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 8, c->overflow.p, sizeof(u32), hipMemcpyDeviceToHost, st));
+    HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 16, P<vec4<T>>(c->blo), sizeof(vec4<T>),
+                             hipMemcpyDeviceToHost, st));
+    HIPTRY(c, hipStreamSynchronize(st));
+    const i64 e1 = (i64)*(u64*)c->pinned;
+    if (*(u32*)((char*)c->pinned + 8)) return fail(c, SHSPH_ECAPACITY, "tree traversal stack overflow");
+    // periodic minimum image needs the cache radius below half the box
+    for (int k = 0; k < ninst; ++k) {
+        const InstDev& in = c->inst_h[k];
+        if (!in.periodic) continue;
+        // node 0 is the root of a single instance (internal node, or the only leaf)
+        const double hmax = (ninst == 1) ? (double)((vec4<T>*)((char*)c->pinned + 16))->w : 0.0;
+        for (int d = 0; d < 3; ++d)
+            if (rk * hmax >= 0.5 * (in.hi[d] - in.lo[d]))
+                return fail(c, SHSPH_EINVAL, "periodic box smaller than twice the cache radius");
+    }
+    c->n_lneigh = e1;
+    TRY(ensure(c, c->llist, std::max<i64>(e1, 1) * sizeof(u32)));
+    launch_leaf_neigh<T>(true, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child), ni, nl,
+                         P<i64>(c->leaf_off_d), ninst, P<u32>(c->root_d), inst, rk, P<u64>(c->loff),
+                         nullptr, P<u32>(c->llist), P<u32>(c->overflow), st);
+    TRY(check_launch(c, "stage1 fill"));
+    // a8: stage 2, particle -> particles (exact criterion in T)
+    TRY(ensure(c, c->ncnt, (n + 1) * sizeof(u32)));
+    TRY(ensure(c, c->noff, (n + 1) * sizeof(u64)));
+    launch_part_neigh<T>(false, posh, P<u32>(c->xscan), P<u32>(c->id), P<u64>(c->loff),
+                         P<u32>(c->llist), n, poff, ninst, inst, rk, P<u32>(c->ncnt), nullptr,
+                         nullptr, P<u32>(c->overflow), st);
+    scan_u32_u64(P<u32>(c->ncnt), P<u64>(c->noff), n, c->scan_tmp.p, st);
+    TRY(check_launch(c, "stage2 count"));
+    TRY(read_back(c, P<u64>(c->noff) + n, sizeof(u64)));
+    const i64 e2 = (i64)*(u64*)c->pinned;
+    c->n_neigh = e2;
+    TRY(ensure(c, c->nlist, std::max<i64>(e2, 1) * sizeof(u32)));
+    launch_part_neigh<T>(true, posh, P<u32>(c->xscan), P<u32>(c->id), P<u64>(c->loff),
+                         P<u32>(c->llist), n, poff, ninst, inst, rk, nullptr, P<u64>(c->noff),
+                         P<u32>(c->nlist), P<u32>(c->overflow), st);
+    TRY(check_launch(c, "stage2 fill"));
+    return SHSPH_OK;
+}
+
+// a9: density / h iteration with cache rebuilds while some h leaves chi h_cache.
+template <class T> int run_density(shsph_ctx* c, bool with_thermo)
+{
+    hipStream_t st = c->stream;
+    const i64 n = c->n;
+    TRY(ensure(c, c->omega, n * sizeof(T)));
+    TRY(ensure(c, c->thermo, n * sizeof(vec4<T>)));
+    TRY(ensure(c, c->status, n));
+    const SphParams sp = sph_params(c->prm);
+    SortedPtrs<T> s = sorted<T>(c, false);
+    if (!with_thermo) s.velu = nullptr;
+    for (int attempt = 0;; ++attempt) {
+        launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
+        launch_density<T>(s, P<u64>(c->noff), P<u32>(c->nlist), n, P<i64>(c->poff_d), c->ninst,
+                          P<InstDev>(c->inst_d), sp, P<T>(c->omega),
+                          with_thermo ? P<vec4<T>>(c->thermo) : nullptr, P<u8>(c->status),
+                          P<InstStat>(c->stat_d), st);
+        TRY(check_launch(c, "density"));
+        std::vector<InstStat> hs(c->ninst);
+        const size_t sb = std::min(c->ninst * sizeof(InstStat), PINNED_BYTES - 16);
+        HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 16, c->stat_d.p, sb, hipMemcpyDeviceToHost, st));
+        TRY(read_back(c, c->overflow.p, sizeof(u32)));
+        if (*(u32*)c->pinned) return fail(c, SHSPH_ECAPACITY, "neighbour cache fill exceeded its count");
+        memcpy(hs.data(), (char*)c->pinned + 16, sb);
+        u32 ex = 0, nc = 0;
+        for (const InstStat& q : hs) { ex += q.n_exceed; nc += q.n_noconv; }
+        if (ex == 0) {
+            if (nc) return fail(c, SHSPH_ENOCONV, "h iteration did not converge for " + std::to_string(nc) + " particles");
+            return SHSPH_OK;
+        }
+        if (attempt >= c->prm.max_restarts)
+            return fail(c, SHSPH_ENOCONV, "h kept exceeding the cache tolerance after rebuilds");
+        // rebuild the caches with the current h as the cache h
+        ++c->restarts;
+        launch_copy_h<T>(s.posh, s.hcache, n, st);
+        TRY(build_caches<T>(c));
+    }
+}
+
+template <class T> int do_build(shsph_ctx* c, const shsph_particles* p)
+{
+    TRY(set_single_instance(c, p));
+    c->n = p->n;
+    c->dtype = p->dtype;
+    c->state = ST_NONE;
+    TRY(build<T>(c, p, nullptr, false));
+    c->state = ST_TREE;
+    return SHSPH_OK;
+}
+
+template <class T> int do_density(shsph_ctx* c, shsph_particles* p)
+{
+    hipStream_t st = c->stream;
+    const i64 n = c->n;
+    const u32* eps = P<u32>(c->vals[c->vals_sel]);
+    const bool with_u = p->u && p->vx && p->vy && p->vz;
+    if (with_u)
+        launch_gather_velu<T>(eps, n, (const T*)p->vx, (const T*)p->vy, (const T*)p->vz,
+                              (const T*)p->u, P<vec4<T>>(c->velu), st);
+    // the velocity part is only used by force; zeros are fine when absent
+    int rc = run_density<T>(c, with_u);
+    if (rc != SHSPH_OK && rc != SHSPH_ENOCONV) return rc;
+    launch_scatter<T>(eps, n, P<vec4<T>>(c->posh), 3, nullptr, (T*)p->h, st);
+    launch_scatter<T>(eps, n, nullptr, 0, P<T>(c->omega), (T*)p->omega, st);
+    launch_scatter_rho<T>(eps, n, P<vec4<T>>(c->posh), P<i64>(c->poff_d), c->ninst,
+                          P<InstDev>(c->inst_d), c->prm.hfact, (T*)p->rho, st);
+    TRY(check_launch(c, "density scatter"));
+    HIPTRY(c, hipStreamSynchronize(st));
+    c->state = ST_DENSITY;
+    return rc;
+}
+
+template <class T> int do_force(shsph_ctx* c, shsph_particles* p)
+{
+    hipStream_t st = c->stream;
+    const i64 n = c->n;
+    const u32* eps = P<u32>(c->vals[c->vals_sel]);
+    TRY(ensure(c, c->acc, n * sizeof(vec4<T>)));
+    TRY(ensure(c, c->vsig, n * sizeof(T)));
+    launch_gather_velu<T>(eps, n, (const T*)p->vx, (const T*)p->vy, (const T*)p->vz, (const T*)p->u,
+                          P<vec4<T>>(c->velu), st);
+    launch_thermo<T>(P<vec4<T>>(c->posh), P<vec4<T>>(c->velu), P<T>(c->omega), n, P<i64>(c->poff_d),
+                     c->ninst, P<InstDev>(c->inst_d), c->prm.hfact, c->prm.gamma,
+                     P<vec4<T>>(c->thermo), st);
+    launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
+    const SphParams sp = sph_params(c->prm);
+    launch_force<T>(sorted<T>(c, false), P<vec4<T>>(c->thermo), P<u64>(c->noff), P<u32>(c->nlist), n,
+                    P<i64>(c->poff_d), c->ninst, P<InstDev>(c->inst_d), sp, P<vec4<T>>(c->acc),
+                    P<T>(c->vsig), P<InstStat>(c->stat_d), st);
+    TRY(check_launch(c, "force"));
+    const vec4<T>* acc = P<vec4<T>>(c->acc);
+    launch_scatter<T>(eps, n, acc, 0, nullptr, (T*)p->ax, st);
+    launch_scatter<T>(eps, n, acc, 1, nullptr, (T*)p->ay, st);
+    launch_scatter<T>(eps, n, acc, 2, nullptr, (T*)p->az, st);
+    launch_scatter<T>(eps, n, acc, 3, nullptr, (T*)p->dudt, st);
+    TRY(check_launch(c, "force scatter"));
+    HIPTRY(c, hipStreamSynchronize(st));
+    c->state = ST_FORCE;
+    return SHSPH_OK;
+}
+
+template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, double* dt_used)
+{
+    hipStream_t st = c->stream;
+    // dt for this step: caller's value, else the CFL dt of the last force pass
+    if (!(dt > 0) && c->state != ST_FORCE)
+        return fail(c, SHSPH_ESTATE, "dt <= 0 needs a preceding force evaluation (CFL dt)");
+    const bool keep_stat = c->stat_d.p && c->ninst == 1;
+    TRY(set_single_instance(c, p));
+    if (!keep_stat && !(dt > 0)) return fail(c, SHSPH_ESTATE, "no CFL dt available");
+    *(double*)c->pinned = dt;
+    HIPTRY(c, hipMemcpyAsync(c->dt_host_d.p, c->pinned, sizeof(double), hipMemcpyHostToDevice, st));
+    launch_dt_select(P<double>(c->dt_inst_d), P<InstStat>(c->stat_d), P<double>(c->dt_host_d), 1, st);
+    c->n = p->n;
+    c->dtype = p->dtype;
+    c->state = ST_NONE;
+    const double* dt_dev = P<double>(c->dt_inst_d);
+    TRY(build<T>(c, p, dt_dev, true));
+    c->state = ST_TREE;
+    int rc = run_density<T>(c, true);
+    if (rc != SHSPH_OK) return rc;
+    const i64 n = c->n;
+    TRY(ensure(c, c->acc, n * sizeof(vec4<T>)));
+    launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
+    const SphParams sp = sph_params(c->prm);
+    launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u64>(c->noff), P<u32>(c->nlist), n,
+                    P<i64>(c->poff_d), c->ninst, P<InstDev>(c->inst_d), sp, P<vec4<T>>(c->acc),
+                    nullptr, P<InstStat>(c->stat_d), st);
+    TRY(check_launch(c, "force"));
+    OutPtrs<T> o;
+    o.x = (T*)p->x; o.y = (T*)p->y; o.z = (T*)p->z;
+    o.vx = (T*)p->vx; o.vy = (T*)p->vy; o.vz = (T*)p->vz;
+    o.u = (T*)p->u; o.h = (T*)p->h;
+    o.ax = (T*)p->ax; o.ay = (T*)p->ay; o.az = (T*)p->az; o.du = (T*)p->dudt;
+    o.rho = (T*)p->rho; o.omega = (T*)p->omega; o.pid = p->pid;
+    launch_correct<T>(sorted<T>(c, true), P<vec4<T>>(c->acc), P<T>(c->omega), n, P<i64>(c->poff_d),
+                      c->ninst, P<InstDev>(c->inst_d), dt_dev, c->prm.hfact, o,
+                      P<InstStat>(c->stat_d), st);
+    TRY(check_launch(c, "correct"));
+    if (dt_used) {
+        TRY(read_back(c, dt_dev, sizeof(double)));
+        *dt_used = *(double*)c->pinned;
+    }
+    c->state = ST_FORCE;
+    return SHSPH_OK;
+}
+
+}  // namespace
+
+// =========================================================== C interface ===
+extern "C" {
+
+void shsph_params_default(shsph_params* p)
+{
+    if (!p) return;
+    p->hfact = 1.2;
+    p->gamma = 5.0 / 3.0;
+    p->alpha_av = 1.0;
+    p->beta_av = 2.0;
+    p->beta_u = 1.0;
+    p->chi = 1.1;
+    p->lambda = 1.2;
+    p->eps_h = 1e-6;
+    p->c_cour = 0.3;
+    p->c_force = 0.25;
+    p->max_iter = 50;
+    p->n_red = 3;
+    p->max_restarts = 8;
+    p->reserved = 0;
+}
+
+int shsph_create(int device, const shsph_params* p, shsph_ctx** out)
+{
+    if (!out) return SHSPH_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SHSPH_EINVAL;
+    shsph_ctx* c = new shsph_ctx();
+    c->device = device;
+    if (p) c->prm = *p; else shsph_params_default(&c->prm);
+    if (!(c->prm.hfact > 0) || !(c->prm.chi >= 1) || !(c->prm.lambda > 1) || !(c->prm.eps_h > 0) ||
+        c->prm.max_iter < 1 || c->prm.n_red > 20 || c->prm.max_restarts < 0) {
+        delete c;
+        return SHSPH_EINVAL;
+    }
+    if (hipSetDevice(device) != hipSuccess || hipHostMalloc(&c->pinned, PINNED_BYTES) != hipSuccess) {
+        delete c;
+        return SHSPH_EHIP;
+    }
+    c->stream = nullptr;
+    *out = c;
+    return SHSPH_OK;
+}
+
+int shsph_destroy(shsph_ctx* c)
+{
+    if (!c) return SHSPH_EINVAL;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    Buf* all[] = { &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->hist, &c->hist_scan,
+                   &c->scan_tmp, &c->bbox, &c->posh, &c->velu, &c->vhalf, &c->hn, &c->hcache,
+                   &c->pid_s, &c->thermo, &c->omega, &c->acc, &c->vsig, &c->status, &c->xi[0],
+                   &c->xi[1], &c->xscan, &c->id, &c->mu_leaf, &c->lchild, &c->rchild, &c->endrange,
+                   &c->lflag, &c->rflag, &c->child, &c->parent, &c->arrive, &c->blo, &c->bhi,
+                   &c->lcnt, &c->loff, &c->llist, &c->ncnt, &c->noff, &c->nlist, &c->overflow,
+                   &c->inst_d, &c->poff_d, &c->leaf_off_d, &c->ioff_d, &c->root_d, &c->stat_d,
+                   &c->dt_inst_d, &c->dt_host_d, &c->pbox, &c->plen };
+    for (Buf* b : all)
+        if (b->p) hipFree(b->p);
+    if (c->pinned) hipHostFree(c->pinned);
+    delete c;
+    return SHSPH_OK;
+}
+
+int shsph_set_stream(shsph_ctx* c, void* stream)
+{
+    if (!c) return SHSPH_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return SHSPH_OK;
+}
+
+const char* shsph_last_error(const shsph_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int shsph_build_tree(shsph_ctx* c, const shsph_particles* p)
+{
+    if (!c) return SHSPH_EINVAL;
+    c->err.clear();
+    TRY(validate(c, p, false, false));
+    HIPTRY(c, hipSetDevice(c->device));
+    return p->dtype == SHSPH_F32 ? do_build<float>(c, p) : do_build<double>(c, p);
+}
+
+int shsph_density(shsph_ctx* c, shsph_particles* p)
+{
+    if (!c) return SHSPH_EINVAL;
+    c->err.clear();
+    TRY(validate(c, p, false, false));
+    if (c->state < ST_TREE || p->n != c->n || p->dtype != c->dtype)
+        return fail(c, SHSPH_ESTATE, "shsph_density needs shsph_build_tree on the same particles");
+    HIPTRY(c, hipSetDevice(c->device));
+    return p->dtype == SHSPH_F32 ? do_density<float>(c, p) : do_density<double>(c, p);
+}
+
+int shsph_force(shsph_ctx* c, shsph_particles* p)
+{
+    if (!c) return SHSPH_EINVAL;
+    c->err.clear();
+    TRY(validate(c, p, true, true));
+    if (c->state < ST_DENSITY || p->n != c->n || p->dtype != c->dtype)
+        return fail(c, SHSPH_ESTATE, "shsph_force needs shsph_density on the same particles");
+    HIPTRY(c, hipSetDevice(c->device));
+    return p->dtype == SHSPH_F32 ? do_force<float>(c, p) : do_force<double>(c, p);
+}
+
+int shsph_step(shsph_ctx* c, shsph_particles* p, double dt, double* dt_used)
+{
+    if (!c) return SHSPH_EINVAL;
+    c->err.clear();
+    TRY(validate(c, p, true, true));
+    if (!std::isfinite(dt)) return fail(c, SHSPH_EINVAL, "dt must be finite");
+    HIPTRY(c, hipSetDevice(c->device));
+    return p->dtype == SHSPH_F32 ? do_step<float>(c, p, dt, dt_used)
+                                 : do_step<double>(c, p, dt, dt_used);
+}
+
+int shsph_get_info(shsph_ctx* c, shsph_info* o)
+{
+    if (!c || !o) return SHSPH_EINVAL;
+    memset(o, 0, sizeof(*o));
+    o->n = c->n;
+    o->n_leaf = c->n_leaf;
+    o->n_leaf_neigh = c->n_lneigh;
+    o->n_neigh = c->n_neigh;
+    o->n_red = c->prm.n_red;
+    o->restarts = c->restarts;
+    if (c->stat_d.p && c->ninst >= 1) {
+        InstStat s;
+        HIPTRY(c, hipMemcpyAsync(c->pinned, c->stat_d.p, sizeof(InstStat), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPTRY(c, hipStreamSynchronize(c->stream));
+        memcpy(&s, c->pinned, sizeof(s));
+        float dt, dv;
+        memcpy(&dt, &s.dt_bits, 4);
+        memcpy(&dv, &s.dvmax_bits, 4);
+        o->dt_cfl = dt;
+        o->dv_max = dv;
+        o->dv2_sum = s.dv2_sum;
+        o->v2_sum = s.v2_sum;
+        o->max_iter_seen = (int32_t)s.max_iter_seen;
+        o->n_noconv = (int32_t)s.n_noconv;
+    }
+    return SHSPH_OK;
+}
+
+int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
+{
+    if (!c || !o) return SHSPH_EINVAL;
+    if (c->state < ST_TREE) return fail(c, SHSPH_ESTATE, "no tree built");
+    HIPTRY(c, hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    const i64 n = c->n, nl = c->n_leaf, ni = c->n_internal, nn = ni + nl;
+    const size_t T = c->dtype == SHSPH_F32 ? 4 : 8;
+    auto cp = [&](void* dst, const void* src, size_t bytes) -> int {
+        if (dst && bytes) HIPTRY(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+        return SHSPH_OK;
+    };
+    // keys in caller order are not kept after the sort: recompute them
+    if (o->keys) {
+        // scatter the sorted keys back through eps
+        std::vector<u64> mu(n);
+        std::vector<u32> eps(n);
+        HIPTRY(c, hipMemcpyAsync(mu.data(), c->keys[c->vals_sel].p, n * 8, hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipMemcpyAsync(eps.data(), c->vals[c->vals_sel].p, n * 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipStreamSynchronize(st));
+        for (i64 i = 0; i < n; ++i) o->keys[eps[i]] = mu[i];
+    }
+    TRY(cp(o->eps, c->vals[c->vals_sel].p, n * 4));
+    TRY(cp(o->mu, c->keys[c->vals_sel].p, n * 8));
+    TRY(cp(o->xi, c->xi[c->xi_sel].p, n));
+    TRY(cp(o->id, c->id.p, (nl + 1) * 4));
+    TRY(cp(o->mu_leaf, c->mu_leaf.p, nl * 8));
+    if (ni > 0) {
+        TRY(cp(o->lchild, c->lchild.p, ni * 4));
+        TRY(cp(o->rchild, c->rchild.p, ni * 4));
+        TRY(cp(o->endrange, c->endrange.p, ni * 4));
+        TRY(cp(o->lflag, c->lflag.p, ni));
+        TRY(cp(o->rflag, c->rflag.p, ni));
+    }
+    TRY(cp(o->parent, c->parent.p, nn * 4));
+    if (o->bmin || o->bmax || o->hmax) {
+        std::vector<char> lo(nn * 4 * T), hi(nn * 4 * T);
+        HIPTRY(c, hipMemcpyAsync(lo.data(), c->blo.p, nn * 4 * T, hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipMemcpyAsync(hi.data(), c->bhi.p, nn * 4 * T, hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipStreamSynchronize(st));
+        for (i64 v = 0; v < nn; ++v) {
+            for (int d = 0; d < 3; ++d) {
+                if (o->bmin) memcpy((char*)o->bmin + (3 * v + d) * T, &lo[(4 * v + d) * T], T);
+                if (o->bmax) memcpy((char*)o->bmax + (3 * v + d) * T, &hi[(4 * v + d) * T], T);
+            }
+            if (o->hmax) memcpy((char*)o->hmax + v * T, &lo[(4 * v + 3) * T], T);
+        }
+    }
+    if (o->pbox || o->plen) {
+        TRY(ensure(c, c->pbox, std::max<size_t>(n * sizeof(u64), 6 * nn * sizeof(u32))));
+        TRY(ensure(c, c->plen, nn * sizeof(i32)));
+        launch_prefix_boxes(P<u64>(c->mu_leaf), P<i64>(c->leaf_off_d), P<i64>(c->ioff_d), c->ninst,
+                            ni, nl, P<u32>(c->endrange), P<u32>(c->parent), P<u32>(c->pbox),
+                            P<i32>(c->plen), st);
+        TRY(check_launch(c, "prefix boxes"));
+        TRY(cp(o->pbox, c->pbox.p, 6 * nn * 4));
+        TRY(cp(o->plen, c->plen.p, nn * 4));
+    }
+    TRY(cp(o->leaf_off, c->loff.p, (nl + 1) * 8));
+    TRY(cp(o->leaf_list, c->llist.p, c->n_lneigh * 4));
+    TRY(cp(o->neigh_off, c->noff.p, (n + 1) * 8));
+    TRY(cp(o->neigh_list, c->nlist.p, c->n_neigh * 4));
+    if (o->h_sorted) {
+        std::vector<char> ph(n * 4 * T);
+        HIPTRY(c, hipMemcpyAsync(ph.data(), c->posh.p, n * 4 * T, hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipStreamSynchronize(st));
+        for (i64 i = 0; i < n; ++i) memcpy((char*)o->h_sorted + i * T, &ph[(4 * i + 3) * T], T);
+    }
+    HIPTRY(c, hipStreamSynchronize(st));
+    return SHSPH_OK;
+}
+
+}  // extern "C"

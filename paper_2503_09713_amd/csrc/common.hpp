@@ -1,0 +1,230 @@
+// Device-side building blocks shared by the shsph kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace shsph {
+
+typedef uint8_t u8;
+typedef uint32_t u32;
+typedef uint64_t u64;
+typedef int32_t i32;
+typedef int64_t i64;
+
+constexpr int WAVE = 64;
+constexpr int MORTON_BITS = 21;             // per axis, 63-bit keys (App. C.1)
+constexpr u32 MORTON_MAX = (1u << MORTON_BITS) - 1u;
+
+// ---------------------------------------------------------------- vectors --
+template <class T> struct V4;
+template <> struct V4<float> { typedef float4 type; };
+template <> struct V4<double> { typedef double4 type; };
+template <class T> using vec4 = typename V4<T>::type;
+
+template <class T> __host__ __device__ inline vec4<T> mk4(T a, T b, T c, T d)
+{
+    vec4<T> v; v.x = a; v.y = b; v.z = c; v.w = d; return v;
+}
+
+// ------------------------------------------------------- instance table ----
+// One row per independent SPH instance; the plain API is a table of one.
+struct InstDev {
+    i64 p_off, p_cnt;        // particle range in the (batched) arrays
+    double lo[3], hi[3];     // box; isolated instances get the data extent
+    double mass;
+    i32 periodic;
+    i32 pad;
+};
+
+// Per-instance reductions written by the step kernels.
+struct InstStat {
+    u32 dt_bits;             // CFL dt as the bit pattern of a positive float
+    u32 dvmax_bits;          // max |dv| (positive float bits)
+    double dv2_sum;          // sum |dv|^2
+    double v2_sum;           // sum |v|^2
+    u32 n_exceed, n_noconv;  // h iteration outcome counters
+    u32 max_iter_seen, pad;
+};
+
+// Largest k with off[k] <= i, for a sorted table off[0..n] (binary search).
+__device__ inline int find_seg(const i64* off, int n, i64 i)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------ wave primitives ----
+__device__ inline u64 lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+template <class T> __device__ inline T wave_incl_scan(T x)
+{
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T y = __shfl_up(x, d, WAVE);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+template <class T> __device__ inline T wave_sum(T x)
+{
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, WAVE);
+    return x;
+}
+
+template <class T> __device__ inline T wave_max(T x)
+{
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) { T y = __shfl_xor(x, d, WAVE); x = y > x ? y : x; }
+    return x;
+}
+
+template <class T> __device__ inline T wave_min(T x)
+{
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) { T y = __shfl_xor(x, d, WAVE); x = y < x ? y : x; }
+    return x;
+}
+
+// Exclusive scan over a block of BLOCK threads; `lds` holds BLOCK/64 slots.
+template <int BLOCK, class T> __device__ inline T block_excl_scan(T v, T* lds, T& total)
+{
+    const int lane = __lane_id(), wid = threadIdx.x / WAVE;
+    T x = wave_incl_scan(v);
+    if (lane == WAVE - 1) lds[wid] = x;
+    __syncthreads();
+    T off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / WAVE; ++w) {
+        T s = lds[w];
+        off += (w < wid) ? s : T(0);
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return off + x - v;
+}
+
+// Lanes of the wave whose `bits`-bit digit equals this lane's, among `active`.
+template <int BITS> __device__ inline u64 match_digit(u32 d, u64 active)
+{
+    u64 m = active;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const bool s = (d >> b) & 1u;
+        const u64 bal = __ballot(s);
+        m &= s ? bal : ~bal;
+    }
+    return m;
+}
+
+// ---------------------------------------------- exact float arithmetic ----
+// The neighbour decision must be bit-identical to the CPU definition, so it
+// is written with explicit round-to-nearest operations (no contraction).
+__device__ inline float add_rn(float a, float b) { return __fadd_rn(a, b); }
+__device__ inline float sub_rn(float a, float b) { return __fsub_rn(a, b); }
+__device__ inline float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ inline double add_rn(double a, double b) { return __dadd_rn(a, b); }
+__device__ inline double sub_rn(double a, double b) { return __dsub_rn(a, b); }
+__device__ inline double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+
+// Periodic box constants in the storage type: L = (T)(hi-lo),
+// halfL = (T)(0.5*(hi-lo)).
+template <class T> struct Box {
+    T L[3], halfL[3];
+    T lo[3], hi[3];
+    int periodic;
+};
+
+template <class T> __device__ inline Box<T> make_box(const InstDev& in)
+{
+    Box<T> b;
+    for (int d = 0; d < 3; ++d) {
+        b.L[d] = (T)(in.hi[d] - in.lo[d]);
+        b.halfL[d] = (T)(0.5 * (in.hi[d] - in.lo[d]));
+        b.lo[d] = (T)in.lo[d];
+        b.hi[d] = (T)in.hi[d];
+    }
+    b.periodic = in.periodic;
+    return b;
+}
+
+// Minimum image applied once: d -> d - L if d > L/2, d + L if d < -L/2.
+template <class T> __device__ inline T min_image(T d, T L, T halfL, int periodic)
+{
+    if (periodic) {
+        if (d > halfL) d = sub_rn(d, L);
+        else if (d < -halfL) d = add_rn(d, L);
+    }
+    return d;
+}
+
+// Object-object criterion of the cache (App. F, chi-extended radius), in T:
+//   dx = x_b - x_a (min image), r2 = (dx*dx + dy*dy) + dz*dz,
+//   rc = rkc * max(h_a, h_b), accept iff r2 < rc*rc.
+template <class T>
+__device__ inline bool cache_crit(T xa, T ya, T za, T ha, T xb, T yb, T zb, T hb,
+                                  const Box<T>& bx, T rkc)
+{
+    T dx = min_image(sub_rn(xb, xa), bx.L[0], bx.halfL[0], bx.periodic);
+    T dy = min_image(sub_rn(yb, ya), bx.L[1], bx.halfL[1], bx.periodic);
+    T dz = min_image(sub_rn(zb, za), bx.L[2], bx.halfL[2], bx.periodic);
+    T r2 = add_rn(add_rn(mul_rn(dx, dx), mul_rn(dy, dy)), mul_rn(dz, dz));
+    T hm = ha > hb ? ha : hb;
+    T rc = mul_rn(rkc, hm);
+    return r2 < mul_rn(rc, rc);
+}
+
+// ------------------------------------------------------------- M4 spline --
+// f(q) = 1 - 3/2 q^2 + 3/4 q^3 (q<1), (2-q)^3/4 (1<=q<2), 0 beyond;
+// C_norm = 1/pi in 3D; the support radius is 2h (Sect. 2.1).
+template <class T> __device__ inline void m4(T q, T& f, T& df)
+{
+    if (q < T(1)) {
+        f = T(1) - T(1.5) * q * q + T(0.75) * q * q * q;
+        df = q * (T(2.25) * q - T(3));
+    } else if (q < T(2)) {
+        T t = T(2) - q;
+        f = T(0.25) * t * t * t;
+        df = T(-0.75) * t * t;
+    } else {
+        f = T(0);
+        df = T(0);
+    }
+}
+
+template <class T> __device__ inline T m4_df(T q)
+{
+    if (q < T(1)) return q * (T(2.25) * q - T(3));
+    if (q < T(2)) { T t = T(2) - q; return T(-0.75) * t * t; }
+    return T(0);
+}
+
+template <class T> __device__ inline T inv_pi() { return T(0.318309886183790671537767526745); }
+
+// Positive-float atomic min/max through the integer order of the bit pattern.
+__device__ inline void atomic_min_posf(u32* addr, float v) { atomicMin(addr, __float_as_uint(v)); }
+__device__ inline void atomic_max_posf(u32* addr, float v) { atomicMax(addr, __float_as_uint(v)); }
+
+// Block-wide reductions (BLOCK threads); results valid in every thread.
+template <int BLOCK, class T, class Op> __device__ inline T block_reduce(T v, T* lds, Op op)
+{
+    const int lane = __lane_id(), wid = threadIdx.x / WAVE;
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v = op(v, __shfl_xor(v, d, WAVE));
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    T r = lds[0];
+#pragma unroll
+    for (int w = 1; w < BLOCK / WAVE; ++w) r = op(r, lds[w]);
+    __syncthreads();
+    return r;
+}
+
+}  // namespace shsph

@@ -1,0 +1,126 @@
+// Host-callable launchers of the shsph kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "common.hpp"
+
+namespace shsph {
+
+// Caller-order particle fields (structure of arrays, storage type T).
+template <class T> struct FieldPtrs {
+    const T *x, *y, *z, *vx, *vy, *vz, *u, *h, *ax, *ay, *az, *du;
+    const u32* pid;
+};
+
+// Key-order working arrays owned by the context.
+template <class T> struct SortedPtrs {
+    vec4<T>* posh;     // x, y, z, h (h = current smoothing length)
+    vec4<T>* velu;     // v*, u* (velocity and energy the derivatives use)
+    vec4<T>* vhalf;    // v^{n+1/2}, u^{n+1/2} (stepping only)
+    T* hn;             // h at the start of the step (normalises the h iteration)
+    T* hcache;         // h the neighbour cache was built with (chi check)
+    u32* pid;          // particle ids carried through the reordering
+};
+
+// Karras tables (App. C.7) plus node-indexed links for the traversals.
+struct TreePtrs {
+    u32 *lchild, *rchild, *endrange;   // local leaf/internal ids per instance
+    u8 *lflag, *rflag;
+    u32* child;                        // 2 per internal node: global node ids
+    u32* parent;                       // per node (internal, then leaves)
+};
+
+// Caller-order outputs of a step (written at the particle's key-order slot).
+template <class T> struct OutPtrs {
+    T *x, *y, *z, *vx, *vy, *vz, *u, *h, *ax, *ay, *az, *du, *rho, *omega;
+    u32* pid;
+};
+
+struct SphParams {
+    double hfact, gamma, alpha, beta, beta_u, chi, lambda, eps_h, c_cour, c_force, r_kern;
+    int max_iter;
+};
+
+// scan.hip
+size_t scan_tmp_bytes(i64 n);
+void scan_u8_u32(const u8* in, u32* out, i64 n, void* tmp, hipStream_t st);
+void scan_u32_u32(const u32* in, u32* out, i64 n, void* tmp, hipStream_t st);
+void scan_u32_u64(const u32* in, u64* out, i64 n, void* tmp, hipStream_t st);
+
+// sort.hip
+size_t radix_hist_count(i64 n);
+int radix_sort_pairs(u64* k0, u32* v0, u64* k1, u32* v1, i64 n, int key_bits, const i64* seg_off,
+                     int nseg, u32* hist, u32* hist_scan, void* scan_tmp, hipStream_t st);
+
+// tree.hip
+template <class T>
+void launch_predict_morton(const FieldPtrs<T>& f, i64 n, const InstDev* inst, const i64* p_off,
+                           int ninst, const double* dt_inst, u64* keys, u32* vals, hipStream_t st);
+template <class T>
+void launch_gather(const FieldPtrs<T>& f, i64 n, const InstDev* inst, const i64* p_off, int ninst,
+                   const double* dt_inst, const u32* eps, const SortedPtrs<T>& s, hipStream_t st);
+template <class T>
+void launch_bbox(const FieldPtrs<T>& f, i64 n, InstDev* inst, const i64* p_off, int ninst,
+                 const double* dt_inst, u64* bb, hipStream_t st);
+void launch_mask_init(const u64* mu, i64 n, const i64* p_off, int ninst, u8* xi, hipStream_t st);
+void launch_reduce_pass(const u64* mu, i64 n, const i64* p_off, int ninst, const u8* xold, u8* xnew,
+                        hipStream_t st);
+void launch_compact(const u64* mu, const u8* xi, const u32* xscan, i64 n, u32* id, u64* mu_leaf,
+                    hipStream_t st);
+void launch_inst_leaves(const i64* p_off, int ninst, const u32* xscan, i64 n, i64* leaf_off,
+                        i64* ioff, u32* root, u32* parent, i64 n_internal, hipStream_t st);
+void launch_karras(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
+                   i64 n_internal, const TreePtrs& t, hipStream_t st);
+template <class T>
+void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 n_leaf, i64 n_internal,
+                     const u32* child, const u32* parent, u32* arrive, vec4<T>* blo, vec4<T>* bhi,
+                     hipStream_t st);
+void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
+                         i64 n_internal, i64 n_leaf, const u32* endrange, const u32* parent,
+                         u32* pbox, i32* plen, hipStream_t st);
+
+// neigh.hip
+template <class T>
+void launch_leaf_neigh(bool fill, const vec4<T>* blo, const vec4<T>* bhi, const u32* child,
+                       i64 n_internal, i64 n_leaf, const i64* leaf_off, int ninst, const u32* root,
+                       const InstDev* inst, double rk, const u64* off, u32* cnt, u32* list,
+                       u32* overflow, hipStream_t st);
+template <class T>
+void launch_part_neigh(bool fill, const vec4<T>* posh, const u32* xscan, const u32* id,
+                       const u64* loff, const u32* llist, i64 n, const i64* p_off, int ninst,
+                       const InstDev* inst, double rkc, u32* cnt, const u64* noff, u32* nlist,
+                       u32* overflow, hipStream_t st);
+
+// sph.hip
+void launch_fill_u32(u32* p, i64 n, u32 v, hipStream_t st);
+void launch_stat_reset(InstStat* s, int ninst, hipStream_t st);
+void launch_dt_select(double* dt_inst, const InstStat* s, const double* dt_host, int ninst,
+                      hipStream_t st);
+template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStream_t st);
+template <class T>
+void launch_density(const SortedPtrs<T>& s, const u64* noff, const u32* nlist, i64 n,
+                    const i64* p_off, int ninst, const InstDev* inst, const SphParams& P,
+                    T* omega, vec4<T>* thermo, u8* status, InstStat* stat, hipStream_t st);
+template <class T>
+void launch_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u64* noff, const u32* nlist,
+                  i64 n, const i64* p_off, int ninst, const InstDev* inst, const SphParams& P,
+                  vec4<T>* acc, T* vsig, InstStat* stat, hipStream_t st);
+template <class T>
+void launch_correct(const SortedPtrs<T>& s, const vec4<T>* acc, const T* omega, i64 n,
+                    const i64* p_off, int ninst, const InstDev* inst, const double* dt_inst,
+                    double hfact, const OutPtrs<T>& o, InstStat* stat, hipStream_t st);
+template <class T>
+void launch_gather_velu(const u32* eps, i64 n, const T* vx, const T* vy, const T* vz, const T* u,
+                        vec4<T>* velu, hipStream_t st);
+template <class T>
+void launch_thermo(const vec4<T>* posh, const vec4<T>* velu, const T* omega, i64 n,
+                   const i64* p_off, int ninst, const InstDev* inst, double hfact, double gamma,
+                   vec4<T>* thermo, hipStream_t st);
+template <class T>
+void launch_scatter(const u32* eps, i64 n, const vec4<T>* src4, int comp, const T* src1,
+                    T* dst, hipStream_t st);
+template <class T>
+void launch_scatter_rho(const u32* eps, i64 n, const vec4<T>* posh, const i64* p_off, int ninst,
+                        const InstDev* inst, double hfact, T* dst, hipStream_t st);
+
+}  // namespace shsph

@@ -1,0 +1,486 @@
+// SPH loops over the neighbour cache: the smoothing-length / density
+// iteration with Omega (App. G, Alg. 7; Sect. 2.1 Eq. sphomega), the force and
+// energy equations with artificial viscosity and conductivity (Sect. 2.1
+// Eqs. sphvel, sphuint), the leapfrog corrector and the timestep reductions
+// (App. H).  One thread per particle in key order; arithmetic and
+// accumulation in the storage type.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace shsph {
+
+static inline dim3 grid_for(i64 n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
+
+__global__ void k_fill_u32(u32* p, i64 n, u32 v)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_stat_reset(InstStat* s, int ninst)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ninst) return;
+    InstStat z;
+    z.dt_bits = 0x7f800000u;   // +inf
+    z.dvmax_bits = 0u;
+    z.dv2_sum = 0.0;
+    z.v2_sum = 0.0;
+    z.n_exceed = 0u;
+    z.n_noconv = 0u;
+    z.max_iter_seen = 0u;
+    z.pad = 0u;
+    s[k] = z;
+}
+
+// dt for the coming step: the caller's value when positive, else the CFL dt
+// left by the previous force evaluation.
+__global__ void k_dt_select(double* dt_inst, const InstStat* s, const double* dt_host, int ninst)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ninst) return;
+    const double h = dt_host[k];
+    dt_inst[k] = (h > 0.0) ? h : (double)__uint_as_float(s[k].dt_bits);
+}
+
+template <class T> __global__ void k_copy_h(const vec4<T>* __restrict__ posh, T* __restrict__ hc, i64 n)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) hc[i] = posh[i].w;
+}
+
+// Wave-aggregated per-instance counter increment.
+__device__ inline void wave_count(u32* dst_base_stride0, bool pred, int k, size_t stride_bytes)
+{
+    const u64 m = __ballot(pred);
+    if (!m) return;
+    const int k0 = __shfl(k, __ffsll((unsigned long long)m) - 1, WAVE);
+    const bool uniform = __ballot(pred && k != k0) == 0;
+    if (uniform) {
+        if (__lane_id() == __ffsll((unsigned long long)m) - 1)
+            atomicAdd((u32*)((char*)dst_base_stride0 + stride_bytes * k0), (u32)__popcll(m));
+    } else if (pred) {
+        atomicAdd((u32*)((char*)dst_base_stride0 + stride_bytes * k), 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// h iteration (App. G, Alg. 7), per particle, over the cached neighbours:
+//   rho_sum = sum_b m W(r_ab, h),   W = f(r/h)/(pi h^3)
+//   drho = rho_sum - m (hfact/h)^3,  d(drho)/dh = sum_b m dW/dh + 3 rho(h)/h
+//   Newton step, clamped to [h/lambda, h lambda]; eps = |h' - h| / h^n.
+// The particle stops when eps < eps_h.  If h' exceeds chi times the h the
+// cache was built with, h' is clamped there and the particle is flagged: the
+// caller rebuilds the cache with the new h and iterates again (the
+// single-device form of the ghost re-exchange).
+// Final values: rho = m (hfact/h)^3 (App. G uses rho(h), not the sum) and
+// Omega = 1 + h/(3 rho) sum_b m dW/dh (Eq. sphomega with dh/drho = -h/(3 rho)),
+// both taken at the last h where the sums were evaluated.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256)
+k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restrict__ hc,
+          const vec4<T>* __restrict__ velu, const u64* __restrict__ noff,
+          const u32* __restrict__ nlist, i64 n, const i64* __restrict__ p_off, int ninst,
+          const InstDev* __restrict__ inst, SphParams P, T* __restrict__ omega,
+          vec4<T>* __restrict__ thermo, u8* __restrict__ status, InstStat* __restrict__ stat)
+{
+    const i64 a = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = a < n;
+    const i64 ai = live ? a : n - 1;
+    const int k = find_seg(p_off, ninst, ai);
+    const InstDev in = inst[k];
+    const Box<T> bx = make_box<T>(in);
+    const vec4<T> pa = posh[ai];
+    const T m = (T)in.mass, hfact = (T)P.hfact, lam = (T)P.lambda, chi = (T)P.chi;
+    const T h_n = hn[ai], h_c = hc[ai];
+    const u64 j0 = noff[ai], j1 = noff[ai + 1];
+    T h = pa.w, h_eval = pa.w, dsum = T(0);
+    int st = 1;   // 0 converged, 1 not converged, 2 chi exceeded
+    int it = 0;
+    for (; it < P.max_iter; ++it) {
+        const T hinv = T(1) / h;
+        const T h2x4 = T(4) * h * h;
+        T s = T(0), ds = T(0);
+        for (u64 j = j0; j < j1; ++j) {
+            const vec4<T> pb = posh[nlist[j]];
+            const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
+            const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
+            const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < h2x4) {
+                const T q = sqrt(r2) * hinv;
+                T f, df;
+                m4<T>(q, f, df);
+                s += f;
+                ds -= T(3) * f + q * df;
+            }
+        }
+        const T hinv3 = hinv * hinv * hinv;
+        const T rho_sum = m * s * hinv3 * inv_pi<T>();
+        const T dsum_h = m * ds * hinv3 * hinv * inv_pi<T>();
+        const T hf = hfact * hinv;
+        const T rho_h = m * hf * hf * hf;
+        const T ddrho = dsum_h + T(3) * rho_h * hinv;
+        T hnew = h - (rho_sum - rho_h) / ddrho;
+        if (hnew > h * lam) hnew = h * lam;
+        else if (hnew < h / lam) hnew = h / lam;
+        const T eps = fabs(hnew - h) / h_n;
+        h_eval = h;
+        dsum = dsum_h;
+        if (hnew > h_c * chi) { h = h_c * chi; st = 2; ++it; break; }
+        h = hnew;
+        if (eps < (T)P.eps_h) { st = 0; ++it; break; }
+    }
+    if (!live) st = 0;
+    // per-instance outcome counters
+    wave_count(&stat[0].n_exceed, live && st == 2, k, sizeof(InstStat));
+    wave_count(&stat[0].n_noconv, live && st == 1, k, sizeof(InstStat));
+    {
+        const int k0 = __shfl(k, 0, WAVE);
+        const u32 itw = live ? (u32)it : 0u;
+        if (__ballot(k != k0) == 0) {
+            const u32 mx = wave_max(itw);
+            if (__lane_id() == 0) atomicMax(&stat[k0].max_iter_seen, mx);
+        } else if (live) {
+            atomicMax(&stat[k].max_iter_seen, itw);
+        }
+    }
+    if (!live) return;
+    const T hf = hfact / h_eval;
+    const T rho_e = m * hf * hf * hf;
+    const T om = T(1) + h_eval / (T(3) * rho_e) * dsum;
+    const T hfo = hfact / h;
+    const T rho = m * hfo * hfo * hfo;
+    posh[a].w = h;
+    omega[a] = om;
+    status[a] = (u8)st;
+    if (thermo) {
+        const T u = velu ? velu[a].w : T(0);
+        const T g = (T)P.gamma;
+        const T Pr = (g - T(1)) * rho * u;
+        const T cs = sqrt(g * (g - T(1)) * u);
+        const T B = T(1) / (rho * om);
+        thermo[a] = mk4<T>(Pr * B / rho, B, cs, Pr);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Force and energy (Sect. 2.1):
+//   dv_a/dt = -sum_b m [(P_a+q^a)/(rho_a^2 Om_a) F_a + (P_b+q^b)/(rho_b^2 Om_b) F_b] rhat_ab
+//   du_a/dt =  sum_b m (P_a+q^a)/(rho_a^2 Om_a) (v_ab . rhat_ab) F_a + Lambda_cond
+// F_x = f'(r/h_x)/(pi h_x^4) (= rhat . grad W), q^x = -rho_x vsig_x w / 2 for
+// w = v_ab . rhat_ab < 0, vsig_x = alpha c_x + beta |w|.  With
+// A = P/(rho^2 Om) and B = 1/(rho Om): (P+q)/(rho^2 Om) = A - vsig w B / 2.
+// Conductivity: m beta_u vsig_u (u_a-u_b) (F_a B_a + F_b B_b)/2 with
+// vsig_u = sqrt(|P_a - P_b| / ((rho_a+rho_b)/2)).
+// The timestep signal speed is the largest vsig_a over the pairs (floor c_a);
+// dt_a = min(C_cour h/vsig, C_force sqrt(h/|a|)) is min-reduced per instance.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256)
+k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
+        const vec4<T>* __restrict__ thermo, const u64* __restrict__ noff,
+        const u32* __restrict__ nlist, i64 n, const i64* __restrict__ p_off, int ninst,
+        const InstDev* __restrict__ inst, SphParams P, vec4<T>* __restrict__ acc,
+        T* __restrict__ vsig_out, InstStat* __restrict__ stat)
+{
+    const i64 a = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = a < n;
+    const i64 ai = live ? a : n - 1;
+    const int k = find_seg(p_off, ninst, ai);
+    const InstDev in = inst[k];
+    const Box<T> bx = make_box<T>(in);
+    const T m = (T)in.mass, hfact = (T)P.hfact;
+    const T alpha = (T)P.alpha, beta = (T)P.beta, beta_u = (T)P.beta_u;
+    const vec4<T> pa = posh[ai], va = velu[ai], ta = thermo[ai];
+    const T ha = pa.w, hia = T(1) / ha;
+    const T hia4 = hia * hia * hia * hia * inv_pi<T>();
+    const T hfa = hfact * hia;
+    const T rhoa = m * hfa * hfa * hfa;
+    const T Aa = ta.x, Ba = ta.y, ca = ta.z, Pa = ta.w;
+    T ax = T(0), ay = T(0), az = T(0), du = T(0), lam = T(0), vmax = ca;
+    const u64 j0 = noff[ai], j1 = noff[ai + 1];
+    for (u64 j = j0; j < j1; ++j) {
+        const u32 b = nlist[j];
+        const vec4<T> pb = posh[b];
+        const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
+        const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
+        const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const T hb = pb.w;
+        const T hm = ha > hb ? ha : hb;
+        if (!(r2 > T(0)) || !(r2 < T(4) * hm * hm)) continue;
+        const vec4<T> vb = velu[b], tb = thermo[b];
+        const T r = sqrt(r2), rinv = T(1) / r;
+        const T ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+        const T w = (va.x - vb.x) * ex + (va.y - vb.y) * ey + (va.z - vb.z) * ez;
+        const T hib = T(1) / hb;
+        const T Fa = m4_df<T>(r * hia) * hia4;
+        const T Fb = m4_df<T>(r * hib) * (hib * hib * hib * hib * inv_pi<T>());
+        const T aw = fabs(w);
+        const T vsa = alpha * ca + beta * aw;
+        const T vsb = alpha * tb.z + beta * aw;
+        const T wn = w < T(0) ? w : T(0);
+        const T ka = (Aa - T(0.5) * vsa * wn * Ba) * Fa;
+        const T kb = (tb.x - T(0.5) * vsb * wn * tb.y) * Fb;
+        const T fab = m * (ka + kb);
+        ax -= fab * ex;
+        ay -= fab * ey;
+        az -= fab * ez;
+        du += m * ka * w;
+        const T hfb = hfact * hib;
+        const T rhob = m * hfb * hfb * hfb;
+        const T vsu = sqrt(fabs(Pa - tb.w) / (T(0.5) * (rhoa + rhob)));
+        lam += m * beta_u * vsu * (va.w - vb.w) * T(0.5) * (Fa * Ba + Fb * tb.y);
+        vmax = vsa > vmax ? vsa : vmax;
+    }
+    float dta = __int_as_float(0x7f800000);
+    if (live) {
+        acc[a] = mk4<T>(ax, ay, az, du + lam);
+        if (vsig_out) vsig_out[a] = vmax;
+        const T am = sqrt(ax * ax + ay * ay + az * az);
+        const T t1 = vmax > T(0) ? (T)P.c_cour * ha / vmax : T(INFINITY);
+        const T t2 = am > T(0) ? (T)P.c_force * sqrt(ha / am) : T(INFINITY);
+        dta = (float)(t1 < t2 ? t1 : t2);
+    }
+    // per-instance min of dt_a
+    const int k0 = __shfl(k, 0, WAVE);
+    if (__ballot(k != k0) == 0) {
+        const float wmin = wave_min(dta);
+        if (__lane_id() == 0 && wmin < __int_as_float(0x7f800000))
+            atomic_min_posf(&stat[k0].dt_bits, wmin);
+    } else if (live) {
+        atomic_min_posf(&stat[k].dt_bits, dta);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Leapfrog corrector (App. H.1): v^{n+1} = v^{n+1/2} + dt/2 a^{n+1}
+// (= v* + dt/2 (a^{n+1} - a^n)), same for u.  Writes the new state into the
+// caller's arrays at the particle's key-order position and reduces
+// max|dv|, sum|dv|^2 and sum|v|^2 per instance for the reversibility check.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256)
+k_correct(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
+          const vec4<T>* __restrict__ vhalf, const vec4<T>* __restrict__ acc,
+          const T* __restrict__ omega, const u32* __restrict__ pid, i64 n,
+          const i64* __restrict__ p_off, int ninst, const InstDev* __restrict__ inst,
+          const double* __restrict__ dt_inst, double hfact, OutPtrs<T> o,
+          InstStat* __restrict__ stat)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < n;
+    const i64 ii = live ? i : n - 1;
+    const int k = find_seg(p_off, ninst, ii);
+    const T hdt = (T)(0.5 * dt_inst[k]);
+    const vec4<T> p = posh[ii], vs = velu[ii], vh = vhalf[ii], a = acc[ii];
+    const T vx = vh.x + hdt * a.x, vy = vh.y + hdt * a.y, vz = vh.z + hdt * a.z;
+    const T u = vh.w + hdt * a.w;
+    const T dvx = vx - vs.x, dvy = vy - vs.y, dvz = vz - vs.z;
+    float dv = 0.f;
+    double dv2 = 0.0, v2 = 0.0;
+    if (live) {
+        o.x[i] = p.x; o.y[i] = p.y; o.z[i] = p.z; o.h[i] = p.w;
+        o.vx[i] = vx; o.vy[i] = vy; o.vz[i] = vz; o.u[i] = u;
+        o.ax[i] = a.x; o.ay[i] = a.y; o.az[i] = a.z; o.du[i] = a.w;
+        if (o.pid) o.pid[i] = pid[i];
+        if (o.omega) o.omega[i] = omega[i];
+        if (o.rho) {
+            const double hf = hfact / (double)p.w;
+            o.rho[i] = (T)(inst[k].mass * hf * hf * hf);
+        }
+        dv2 = (double)dvx * dvx + (double)dvy * dvy + (double)dvz * dvz;
+        dv = (float)sqrt(dv2);
+        v2 = (double)vx * vx + (double)vy * vy + (double)vz * vz;
+    }
+    const int k0 = __shfl(k, 0, WAVE);
+    if (__ballot(k != k0) == 0) {
+        const float m = wave_max(dv);
+        const double s1 = wave_sum(dv2), s2 = wave_sum(v2);
+        if (__lane_id() == 0) {
+            atomic_max_posf(&stat[k0].dvmax_bits, m);
+            atomicAdd(&stat[k0].dv2_sum, s1);
+            atomicAdd(&stat[k0].v2_sum, s2);
+        }
+    } else if (live) {
+        atomic_max_posf(&stat[k].dvmax_bits, dv);
+        atomicAdd(&stat[k].dv2_sum, dv2);
+        atomicAdd(&stat[k].v2_sum, v2);
+    }
+}
+
+// Pressure terms for the force from h, Omega and u* (key order):
+// thermo = (P/(rho^2 Om), 1/(rho Om), c_s, P), P = (gamma-1) rho u,
+// c_s = sqrt(gamma (gamma-1) u), rho = m (hfact/h)^3.
+template <class T>
+__global__ void k_thermo(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
+                         const T* __restrict__ omega, i64 n, const i64* __restrict__ p_off,
+                         int ninst, const InstDev* __restrict__ inst, double hfact, double gamma,
+                         vec4<T>* __restrict__ thermo)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = find_seg(p_off, ninst, i);
+    const T hf = (T)hfact / posh[i].w;
+    const T rho = (T)inst[k].mass * hf * hf * hf;
+    const T om = omega[i], u = velu[i].w, g = (T)gamma;
+    const T Pr = (g - T(1)) * rho * u;
+    const T B = T(1) / (rho * om);
+    thermo[i] = mk4<T>(Pr * B / rho, B, sqrt(g * (g - T(1)) * u), Pr);
+}
+
+// Gather v, u into key order for a derivative evaluation outside a step.
+template <class T>
+__global__ void k_gather_velu(const u32* __restrict__ eps, i64 n, const T* vx, const T* vy,
+                              const T* vz, const T* u, vec4<T>* __restrict__ velu)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const u32 j = eps[i];
+    velu[i] = mk4<T>(vx[j], vy[j], vz[j], u ? u[j] : T(0));
+}
+
+// Scatter a key-order quantity back to caller order: dst[eps[i]] = src[i].
+template <class T>
+__global__ void k_scatter(const u32* __restrict__ eps, i64 n, const vec4<T>* __restrict__ src4,
+                          int comp, const T* __restrict__ src1, T* __restrict__ dst)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T v;
+    if (src4) {
+        const vec4<T> s = src4[i];
+        v = comp == 0 ? s.x : comp == 1 ? s.y : comp == 2 ? s.z : s.w;
+    } else {
+        v = src1[i];
+    }
+    dst[eps[i]] = v;
+}
+
+template <class T>
+__global__ void k_scatter_rho(const u32* __restrict__ eps, i64 n, const vec4<T>* __restrict__ posh,
+                              const i64* __restrict__ p_off, int ninst,
+                              const InstDev* __restrict__ inst, double hfact, T* __restrict__ dst)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = find_seg(p_off, ninst, i);
+    const T hf = (T)hfact / posh[i].w;
+    dst[eps[i]] = (T)inst[k].mass * hf * hf * hf;
+}
+
+// ------------------------------------------------------------ launchers ----
+void launch_fill_u32(u32* p, i64 n, u32 v, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u32, grid_for(n, 256), dim3(256), 0, st, p, n, v);
+}
+
+void launch_stat_reset(InstStat* s, int ninst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stat_reset, grid_for(ninst, 64), dim3(64), 0, st, s, ninst);
+}
+
+void launch_dt_select(double* dt_inst, const InstStat* s, const double* dt_host, int ninst,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dt_select, grid_for(ninst, 64), dim3(64), 0, st, dt_inst, s, dt_host, ninst);
+}
+
+template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL((k_copy_h<T>), grid_for(n, 256), dim3(256), 0, st, posh, hc, n);
+}
+
+template <class T>
+void launch_density(const SortedPtrs<T>& s, const u64* noff, const u32* nlist, i64 n,
+                    const i64* p_off, int ninst, const InstDev* inst, const SphParams& P,
+                    T* omega, vec4<T>* thermo, u8* status, InstStat* stat, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_density<T>), grid_for(n, 256), dim3(256), 0, st, s.posh, s.hn, s.hcache,
+                       s.velu, noff, nlist, n, p_off, ninst, inst, P, omega, thermo, status, stat);
+}
+
+template <class T>
+void launch_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u64* noff, const u32* nlist,
+                  i64 n, const i64* p_off, int ninst, const InstDev* inst, const SphParams& P,
+                  vec4<T>* acc, T* vsig, InstStat* stat, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_force<T>), grid_for(n, 256), dim3(256), 0, st, s.posh, s.velu, thermo,
+                       noff, nlist, n, p_off, ninst, inst, P, acc, vsig, stat);
+}
+
+template <class T>
+void launch_correct(const SortedPtrs<T>& s, const vec4<T>* acc, const T* omega, i64 n,
+                    const i64* p_off, int ninst, const InstDev* inst, const double* dt_inst,
+                    double hfact, const OutPtrs<T>& o, InstStat* stat, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_correct<T>), grid_for(n, 256), dim3(256), 0, st, s.posh, s.velu, s.vhalf,
+                       acc, omega, s.pid, n, p_off, ninst, inst, dt_inst, hfact, o, stat);
+}
+
+template <class T>
+void launch_gather_velu(const u32* eps, i64 n, const T* vx, const T* vy, const T* vz, const T* u,
+                        vec4<T>* velu, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL((k_gather_velu<T>), grid_for(n, 256), dim3(256), 0, st, eps, n, vx, vy,
+                           vz, u, velu);
+}
+
+template <class T>
+void launch_thermo(const vec4<T>* posh, const vec4<T>* velu, const T* omega, i64 n,
+                   const i64* p_off, int ninst, const InstDev* inst, double hfact, double gamma,
+                   vec4<T>* thermo, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL((k_thermo<T>), grid_for(n, 256), dim3(256), 0, st, posh, velu, omega, n,
+                           p_off, ninst, inst, hfact, gamma, thermo);
+}
+
+template <class T>
+void launch_scatter(const u32* eps, i64 n, const vec4<T>* src4, int comp, const T* src1, T* dst,
+                    hipStream_t st)
+{
+    if (n > 0 && dst)
+        hipLaunchKernelGGL((k_scatter<T>), grid_for(n, 256), dim3(256), 0, st, eps, n, src4, comp,
+                           src1, dst);
+}
+
+template <class T>
+void launch_scatter_rho(const u32* eps, i64 n, const vec4<T>* posh, const i64* p_off, int ninst,
+                        const InstDev* inst, double hfact, T* dst, hipStream_t st)
+{
+    if (n > 0 && dst)
+        hipLaunchKernelGGL((k_scatter_rho<T>), grid_for(n, 256), dim3(256), 0, st, eps, n, posh,
+                           p_off, ninst, inst, hfact, dst);
+}
+
+#define INST(T)                                                                                   \
+    template void launch_copy_h<T>(const vec4<T>*, T*, i64, hipStream_t);                         \
+    template void launch_density<T>(const SortedPtrs<T>&, const u64*, const u32*, i64,            \
+                                    const i64*, int, const InstDev*, const SphParams&, T*,        \
+                                    vec4<T>*, u8*, InstStat*, hipStream_t);                        \
+    template void launch_force<T>(const SortedPtrs<T>&, const vec4<T>*, const u64*, const u32*,   \
+                                  i64, const i64*, int, const InstDev*, const SphParams&,         \
+                                  vec4<T>*, T*, InstStat*, hipStream_t);                           \
+    template void launch_correct<T>(const SortedPtrs<T>&, const vec4<T>*, const T*, i64,          \
+                                    const i64*, int, const InstDev*, const double*, double,       \
+                                    const OutPtrs<T>&, InstStat*, hipStream_t);                    \
+    template void launch_gather_velu<T>(const u32*, i64, const T*, const T*, const T*, const T*,  \
+                                        vec4<T>*, hipStream_t);                                   \
+    template void launch_thermo<T>(const vec4<T>*, const vec4<T>*, const T*, i64, const i64*,     \
+                                   int, const InstDev*, double, double, vec4<T>*, hipStream_t);   \
+    template void launch_scatter<T>(const u32*, i64, const vec4<T>*, int, const T*, T*,           \
+                                    hipStream_t);                                                 \
+    template void launch_scatter_rho<T>(const u32*, i64, const vec4<T>*, const i64*, int,         \
+                                        const InstDev*, double, T*, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace shsph

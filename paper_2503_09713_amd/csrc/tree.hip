@@ -1,0 +1,551 @@
+// Tree build kernels: leapfrog predict + Morton keys, gather into key order,
+// keep mask and leaf reduction, compaction, Karras radix tree and the
+// bottom-up cell boxes.  All kernels work on a table of independent
+// instances (segments of the particle arrays); a plain run is one instance.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace shsph {
+
+static inline dim3 grid_for(i64 n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
+
+// ---------------------------------------------------------------------------
+// Leapfrog predictor (App. H.1): v^{n+1/2} = v + dt/2 a, r^{n+1} = r + dt v^{n+1/2},
+// v* = v^{n+1/2} + dt/2 a, and the same for u; periodic positions are wrapped
+// into [lo, hi).  Written with explicit roundings so that every kernel that
+// evaluates it obtains bit-identical positions.
+// ---------------------------------------------------------------------------
+template <class T> struct Pred {
+    T x[3], vh[3], vs[3], uh, us;
+};
+
+template <class T>
+__device__ inline void predict(const T* const* xp, const T* const* vp, const T* const* ap,
+                               const T* u, const T* du, i64 j, T dt, const Box<T>& bx,
+                               Pred<T>& o)
+{
+    const T hdt = mul_rn(T(0.5), dt);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T a = ap ? ap[d][j] : T(0);
+        const T v = vp ? vp[d][j] : T(0);
+        const T vh = add_rn(v, mul_rn(hdt, a));
+        T x = add_rn(xp[d][j], mul_rn(dt, vh));
+        if (bx.periodic) {
+            if (x >= bx.hi[d]) x = sub_rn(x, bx.L[d]);
+            if (x < bx.lo[d]) x = add_rn(x, bx.L[d]);
+            if (x >= bx.hi[d]) x = bx.lo[d];
+        }
+        o.x[d] = x;
+        o.vh[d] = vh;
+        o.vs[d] = add_rn(vh, mul_rn(hdt, a));
+    }
+    const T uu = u ? u[j] : T(0);
+    const T dd = du ? du[j] : T(0);
+    o.uh = add_rn(uu, mul_rn(hdt, dd));
+    o.us = add_rn(o.uh, mul_rn(hdt, dd));
+}
+
+// Morton key (App. C.1): X = min(2^21-1, max(0, floor((x - lo) * 2^21/(hi - lo))))
+// in FP64, interleaved X0 Y0 Z0 X1 Y1 Z1 ... (bit 63 unused).
+__device__ inline u64 spread3(u32 v)
+{
+    u64 x = v & 0x1fffffu;
+    x = (x | (x << 32)) & 0x001f00000000ffffull;
+    x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ inline u32 quantize(double v, double lo, double scale)
+{
+    const double t = __dmul_rn(__dsub_rn(v, lo), scale);
+    const double f = floor(t);
+    if (!(f >= 0.0)) return 0u;
+    if (f > (double)MORTON_MAX) return MORTON_MAX;
+    return (u32)f;
+}
+
+__device__ inline u64 morton_key(double x, double y, double z, const InstDev& in)
+{
+    const double g = (double)(1u << MORTON_BITS);
+    const u32 X = quantize(x, in.lo[0], g / (in.hi[0] - in.lo[0]));
+    const u32 Y = quantize(y, in.lo[1], g / (in.hi[1] - in.lo[1]));
+    const u32 Z = quantize(z, in.lo[2], g / (in.hi[2] - in.lo[2]));
+    return (spread3(X) << 2) | (spread3(Y) << 1) | spread3(Z);
+}
+
+template <class T>
+__global__ void k_predict_morton(FieldPtrs<T> f, i64 n, const InstDev* __restrict__ inst,
+                                 const i64* __restrict__ p_off, int ninst,
+                                 const double* __restrict__ dt_inst, u64* __restrict__ keys,
+                                 u32* __restrict__ vals)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = find_seg(p_off, ninst, i);
+    const InstDev in = inst[k];
+    double x, y, z;
+    if (dt_inst) {
+        const Box<T> bx = make_box<T>(in);
+        const T* xp[3] = { f.x, f.y, f.z };
+        const T* vp[3] = { f.vx, f.vy, f.vz };
+        const T* ap[3] = { f.ax, f.ay, f.az };
+        Pred<T> o;
+        predict<T>(xp, vp, f.ax ? ap : nullptr, f.u, f.du, i, (T)dt_inst[k], bx, o);
+        x = o.x[0]; y = o.x[1]; z = o.x[2];
+    } else {
+        x = f.x[i]; y = f.y[i]; z = f.z[i];
+    }
+    keys[i] = morton_key(x, y, z, in);
+    vals[i] = (u32)i;
+}
+
+// Gather the fields into key order: sorted slot i takes original index eps[i].
+template <class T>
+__global__ void k_gather(FieldPtrs<T> f, i64 n, const InstDev* __restrict__ inst,
+                         const i64* __restrict__ p_off, int ninst, const double* __restrict__ dt_inst,
+                         const u32* __restrict__ eps, SortedPtrs<T> s)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const i64 j = eps[i];
+    const T h = f.h[j];
+    if (dt_inst) {
+        const int k = find_seg(p_off, ninst, i);
+        const Box<T> bx = make_box<T>(inst[k]);
+        const T* xp[3] = { f.x, f.y, f.z };
+        const T* vp[3] = { f.vx, f.vy, f.vz };
+        const T* ap[3] = { f.ax, f.ay, f.az };
+        Pred<T> o;
+        predict<T>(xp, vp, f.ax ? ap : nullptr, f.u, f.du, j, (T)dt_inst[k], bx, o);
+        s.posh[i] = mk4<T>(o.x[0], o.x[1], o.x[2], h);
+        s.velu[i] = mk4<T>(o.vs[0], o.vs[1], o.vs[2], o.us);
+        if (s.vhalf) s.vhalf[i] = mk4<T>(o.vh[0], o.vh[1], o.vh[2], o.uh);
+    } else {
+        s.posh[i] = mk4<T>(f.x[j], f.y[j], f.z[j], h);
+        if (s.velu && f.vx)
+            s.velu[i] = mk4<T>(f.vx[j], f.vy[j], f.vz[j], f.u ? f.u[j] : T(0));
+    }
+    s.hn[i] = h;
+    s.hcache[i] = h;
+    if (s.pid) s.pid[i] = f.pid ? f.pid[j] : (u32)j;
+}
+
+// ---------------------------------------------------------------------------
+// Keep mask and reduction (App. D, Alg. 1).  Duplicates are dropped, then
+// each pass removes code i when delta(i-2,i-1) < delta(i-1,i) > delta(i,i+1)
+// over the currently kept codes, i.e. when i is the second leaf of a pair of
+// sibling leaves.  Passes read the old mask and write a new one; neighbours
+// outside the instance count as prefix length -1.
+// ---------------------------------------------------------------------------
+__device__ inline int delta_k(u64 a, u64 b) { return __clzll(a ^ b); }
+
+__global__ void k_mask_init(const u64* __restrict__ mu, i64 n, const i64* __restrict__ p_off,
+                            int ninst, u8* __restrict__ xi)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = find_seg(p_off, ninst, i);
+    xi[i] = (i == p_off[k]) ? 1 : (mu[i] != mu[i - 1]);
+}
+
+__global__ void k_reduce_pass(const u64* __restrict__ mu, i64 n, const i64* __restrict__ p_off,
+                              int ninst, const u8* __restrict__ xold, u8* __restrict__ xnew)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!xold[i]) { xnew[i] = 0; return; }
+    const int k = find_seg(p_off, ninst, i);
+    const i64 f = p_off[k], l = p_off[k + 1];
+    i64 im1 = i - 1;
+    while (im1 >= f && !xold[im1]) --im1;
+    i64 im2 = im1 - 1;
+    while (im2 >= f && !xold[im2]) --im2;
+    i64 ip1 = i + 1;
+    while (ip1 < l && !xold[ip1]) ++ip1;
+    const u64 m = mu[i];
+    const int d0 = (ip1 < l) ? delta_k(m, mu[ip1]) : -1;
+    const int dm1 = (im1 >= f) ? delta_k(mu[im1], m) : -1;
+    const int dm2 = (im1 >= f && im2 >= f) ? delta_k(mu[im2], mu[im1]) : -1;
+    xnew[i] = ((d0 < dm1) && (dm2 < dm1)) ? 0 : 1;
+}
+
+// Compaction: id[k] = index of the k-th kept code, mu_leaf[k] its code,
+// id[n_leaf] = n (App. E.1, Fig. mortonlistbuild).
+__global__ void k_compact(const u64* __restrict__ mu, const u8* __restrict__ xi,
+                          const u32* __restrict__ xscan, i64 n, u32* __restrict__ id,
+                          u64* __restrict__ mu_leaf)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (xi[i]) {
+        const u32 k = xscan[i];
+        id[k] = (u32)i;
+        mu_leaf[k] = mu[i];
+    }
+    if (i == 0) id[xscan[n]] = (u32)n;
+}
+
+// Per-instance leaf ranges: leaf_off[k] = number of kept codes before the
+// instance's first particle; root node of each instance.
+__global__ void k_inst_leaves(const i64* __restrict__ p_off, int ninst, const u32* __restrict__ xscan,
+                              i64 n, i64* __restrict__ leaf_off, i64* __restrict__ ioff,
+                              u32* __restrict__ root, u32* __restrict__ parent, i64 n_internal)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > ninst) return;
+    const i64 lo = xscan[p_off[k]];
+    leaf_off[k] = lo;
+    ioff[k] = lo - k;
+    if (k < ninst) {
+        const i64 hi = xscan[p_off[k + 1]];
+        const u32 r = (hi - lo > 1) ? (u32)(lo - k) : (u32)(n_internal + lo);
+        root[k] = r;
+        parent[r] = 0xffffffffu;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Karras radix tree (App. C.7): one thread per internal node, no ordering
+// between nodes.  Direction from the larger of the neighbouring prefix
+// lengths, range end by exponential + binary search, split by binary search
+// for the last code sharing more than delta_node bits with node i.
+// ---------------------------------------------------------------------------
+__device__ inline int dlt(const u64* m, i64 nl, i64 i, i64 j)
+{
+    if (j < 0 || j >= nl) return -1;
+    return __clzll(m[i] ^ m[j]);
+}
+
+__global__ void k_karras(const u64* __restrict__ mu_leaf, const i64* __restrict__ leaf_off,
+                         const i64* __restrict__ ioff, int ninst, i64 n_internal,
+                         TreePtrs t)
+{
+    const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_internal) return;
+    const int k = find_seg(ioff, ninst, g);
+    const i64 L0 = leaf_off[k];
+    const i64 nl = leaf_off[k + 1] - L0;
+    const i64 i = g - ioff[k];
+    const u64* m = mu_leaf + L0;
+    const int d = (dlt(m, nl, i, i + 1) - dlt(m, nl, i, i - 1)) > 0 ? 1 : -1;
+    const int dmin = dlt(m, nl, i, i - d);
+    i64 lmax = 2;
+    while (dlt(m, nl, i, i + lmax * d) > dmin) lmax <<= 1;
+    i64 l = 0;
+    for (i64 s = lmax >> 1; s >= 1; s >>= 1)
+        if (dlt(m, nl, i, i + (l + s) * d) > dmin) l += s;
+    const i64 j = i + l * d;
+    const int dnode = dlt(m, nl, i, j);
+    i64 s = 0, step = l;
+    do {
+        step = (step + 1) >> 1;
+        if (dlt(m, nl, i, i + (s + step) * d) > dnode) s += step;
+    } while (step > 1);
+    const i64 gam = i + s * d + (d < 0 ? -1 : 0);
+    const i64 lo = i < j ? i : j, hi = i < j ? j : i;
+    const bool lleaf = (lo == gam), rleaf = (hi == gam + 1);
+    t.lchild[g] = (u32)gam;
+    t.rchild[g] = (u32)(gam + 1);
+    t.lflag[g] = lleaf;
+    t.rflag[g] = rleaf;
+    t.endrange[g] = (u32)j;
+    const u32 cl = lleaf ? (u32)(n_internal + L0 + gam) : (u32)(ioff[k] + gam);
+    const u32 cr = rleaf ? (u32)(n_internal + L0 + gam + 1) : (u32)(ioff[k] + gam + 1);
+    t.child[2 * g] = cl;
+    t.child[2 * g + 1] = cr;
+    t.parent[cl] = (u32)g;
+    t.parent[cr] = (u32)g;
+}
+
+// ---------------------------------------------------------------------------
+// Cell boxes, bottom-up: each leaf computes the tight AABB and h_max of its
+// particles (h = posh.w, the h the neighbour cache is built with), then climbs; the second thread to reach an internal node merges
+// the two children and continues (arrival counters, device-scope fences).
+// Node layout: lo = (xmin, ymin, zmin, hmax), hi = (xmax, ymax, zmax, 0).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_boxes_up(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 n_leaf, i64 n_internal,
+                           const u32* __restrict__ child, const u32* __restrict__ parent,
+                           u32* __restrict__ arrive, vec4<T>* blo, vec4<T>* bhi)
+{
+    const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_leaf) return;
+    const u32 b0 = id[g], b1 = id[g + 1];
+    vec4<T> p = posh[b0];
+    T lo0 = p.x, lo1 = p.y, lo2 = p.z, hi0 = p.x, hi1 = p.y, hi2 = p.z, hm = p.w;
+    for (u32 b = b0 + 1; b < b1; ++b) {
+        p = posh[b];
+        lo0 = fmin(lo0, p.x); lo1 = fmin(lo1, p.y); lo2 = fmin(lo2, p.z);
+        hi0 = fmax(hi0, p.x); hi1 = fmax(hi1, p.y); hi2 = fmax(hi2, p.z);
+        hm = fmax(hm, p.w);
+    }
+    u32 node = (u32)(n_internal + g);
+    blo[node] = mk4<T>(lo0, lo1, lo2, hm);
+    bhi[node] = mk4<T>(hi0, hi1, hi2, T(0));
+    while (true) {
+        const u32 par = parent[node];
+        if (par == 0xffffffffu) break;
+        __threadfence();
+        const u32 prev = atomicAdd(&arrive[par], 1u);
+        if (prev == 0) break;              // the sibling's thread will continue
+        __threadfence();
+        const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
+        const u32 other = (c0 == node) ? c1 : c0;
+        const vec4<T> ol = blo[other];
+        const vec4<T> oh = bhi[other];
+        lo0 = fmin(lo0, ol.x); lo1 = fmin(lo1, ol.y); lo2 = fmin(lo2, ol.z); hm = fmax(hm, ol.w);
+        hi0 = fmax(hi0, oh.x); hi1 = fmax(hi1, oh.y); hi2 = fmax(hi2, oh.z);
+        blo[par] = mk4<T>(lo0, lo1, lo2, hm);
+        bhi[par] = mk4<T>(hi0, hi1, hi2, T(0));
+        node = par;
+    }
+}
+
+// Integer prefix boxes (App. C.6, Eqs. lowboundbox/highboundbox): internal
+// nodes use delta(first, last) bits of their codes, leaves their parent's
+// length + 1; corners p0 = code & mask, p1 = p0 | ~mask, de-interleaved.
+__device__ inline u32 compact3(u64 x)
+{
+    x &= 0x1249249249249249ull;
+    x = (x | (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x | (x >> 8)) & 0x001f0000ff0000ffull;
+    x = (x | (x >> 16)) & 0x001f00000000ffffull;
+    x = (x | (x >> 32)) & 0x00000000001fffffull;
+    return (u32)x;
+}
+
+__global__ void k_prefix_boxes(const u64* __restrict__ mu_leaf, const i64* __restrict__ leaf_off,
+                               const i64* __restrict__ ioff, int ninst, i64 n_internal, i64 n_leaf,
+                               const u32* __restrict__ endrange, const u32* __restrict__ parent,
+                               u32* __restrict__ pbox, i32* __restrict__ plen)
+{
+    const i64 v = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_internal + n_leaf) return;
+    auto range_len = [&](i64 g) {
+        const int k = find_seg(ioff, ninst, g);
+        const i64 L0 = leaf_off[k];
+        const i64 i = g - ioff[k], j = endrange[g];
+        return __clzll(mu_leaf[L0 + i] ^ mu_leaf[L0 + j]);
+    };
+    int len;
+    u64 code;
+    if (v < n_internal) {
+        const int k = find_seg(ioff, ninst, v);
+        const i64 i = v - ioff[k], j = endrange[v];
+        code = mu_leaf[leaf_off[k] + (i < j ? i : j)];
+        len = range_len(v);
+    } else {
+        code = mu_leaf[v - n_internal];
+        const u32 p = parent[v];
+        len = (p == 0xffffffffu) ? 0 : range_len(p) + 1;
+    }
+    const u64 mask = (len >= 64) ? ~0ull : ~((~0ull) >> len);
+    const u64 p0 = code & mask;
+    const u64 p1 = p0 | (~mask & 0x7fffffffffffffffull);
+    u32* o = pbox + 6 * v;
+    o[0] = compact3(p0 >> 2); o[1] = compact3(p0 >> 1); o[2] = compact3(p0);
+    o[3] = compact3(p1 >> 2); o[4] = compact3(p1 >> 1); o[5] = compact3(p1);
+    plen[v] = len;
+}
+
+// ---------------------------------------------------------------------------
+// Isolated instances: the box is the extent of the (predicted) positions.
+// Reduced as order-preserving 64-bit integers of the FP64 values.
+// ---------------------------------------------------------------------------
+__device__ inline u64 ord64(double d)
+{
+    const u64 b = (u64)__double_as_longlong(d);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ inline double unord64(u64 k)
+{
+    const u64 b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+__global__ void k_bbox_init(u64* bb, int ninst)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ninst) return;
+    for (int d = 0; d < 3; ++d) { bb[6 * k + d] = ~0ull; bb[6 * k + 3 + d] = 0ull; }
+}
+
+constexpr int BB_ITEMS = 16;
+
+template <class T>
+__global__ void k_bbox_reduce(FieldPtrs<T> f, i64 n, const InstDev* __restrict__ inst,
+                              const i64* __restrict__ p_off, int ninst,
+                              const double* __restrict__ dt_inst, u64* __restrict__ bb)
+{
+    const i64 i0 = ((i64)blockIdx.x * blockDim.x + threadIdx.x) * BB_ITEMS;
+    const bool live = i0 < n;
+    int k = find_seg(p_off, ninst, live ? i0 : n - 1);
+    u64 mn[3] = { ~0ull, ~0ull, ~0ull }, mx[3] = { 0ull, 0ull, 0ull };
+    bool any = false;
+    auto flush_lane = [&](int kk) {
+        if (any && !inst[kk].periodic)
+            for (int d = 0; d < 3; ++d) { atomicMin(&bb[6 * kk + d], mn[d]); atomicMax(&bb[6 * kk + 3 + d], mx[d]); }
+        for (int d = 0; d < 3; ++d) { mn[d] = ~0ull; mx[d] = 0ull; }
+        any = false;
+    };
+    if (live) {
+        for (int t = 0; t < BB_ITEMS; ++t) {
+            const i64 i = i0 + t;
+            if (i >= n) break;
+            if (i >= p_off[k + 1]) { flush_lane(k); k = find_seg(p_off, ninst, i); }
+            const InstDev in = inst[k];
+            if (in.periodic) continue;
+            double p[3];
+            if (dt_inst) {
+                const Box<T> bx = make_box<T>(in);
+                const T* xp[3] = { f.x, f.y, f.z };
+                const T* vp[3] = { f.vx, f.vy, f.vz };
+                const T* ap[3] = { f.ax, f.ay, f.az };
+                Pred<T> o;
+                predict<T>(xp, vp, f.ax ? ap : nullptr, f.u, f.du, i, (T)dt_inst[k], bx, o);
+                p[0] = o.x[0]; p[1] = o.x[1]; p[2] = o.x[2];
+            } else {
+                p[0] = f.x[i]; p[1] = f.y[i]; p[2] = f.z[i];
+            }
+            for (int d = 0; d < 3; ++d) {
+                const u64 o = ord64(p[d]);
+                mn[d] = o < mn[d] ? o : mn[d];
+                mx[d] = o > mx[d] ? o : mx[d];
+            }
+            any = true;
+        }
+    }
+    // the wave's lanes usually share one instance: reduce, one atomic per wave
+    const int k0 = __shfl(k, 0, WAVE);
+    const bool uni = __ballot(live && k != k0) == 0;
+    if (uni) {
+        const bool anyw = __ballot(any) != 0;
+        for (int d = 0; d < 3; ++d) {
+            u64 a = mn[d], b = mx[d];
+            for (int s = WAVE / 2; s > 0; s >>= 1) {
+                const u64 oa = __shfl_xor(a, s, WAVE), ob = __shfl_xor(b, s, WAVE);
+                a = oa < a ? oa : a;
+                b = ob > b ? ob : b;
+            }
+            mn[d] = a; mx[d] = b;
+        }
+        if (__lane_id() == 0 && anyw && !inst[k0].periodic)
+            for (int d = 0; d < 3; ++d) { atomicMin(&bb[6 * k0 + d], mn[d]); atomicMax(&bb[6 * k0 + 3 + d], mx[d]); }
+    } else if (live) {
+        flush_lane(k);
+    }
+}
+
+__global__ void k_bbox_finish(InstDev* inst, const u64* bb, int ninst)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ninst || inst[k].periodic) return;
+    for (int d = 0; d < 3; ++d) {
+        inst[k].lo[d] = unord64(bb[6 * k + d]);
+        inst[k].hi[d] = unord64(bb[6 * k + 3 + d]);
+    }
+}
+
+template <class T>
+void launch_bbox(const FieldPtrs<T>& f, i64 n, InstDev* inst, const i64* p_off, int ninst,
+                 const double* dt_inst, u64* bb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bbox_init, grid_for(ninst, 64), dim3(64), 0, st, bb, ninst);
+    const i64 nt = (n + BB_ITEMS - 1) / BB_ITEMS;
+    if (nt > 0)
+        hipLaunchKernelGGL((k_bbox_reduce<T>), grid_for(nt, 256), dim3(256), 0, st, f, n, inst, p_off,
+                           ninst, dt_inst, bb);
+    hipLaunchKernelGGL(k_bbox_finish, grid_for(ninst, 64), dim3(64), 0, st, inst, bb, ninst);
+}
+
+// ------------------------------------------------------------ launchers ----
+template <class T>
+void launch_predict_morton(const FieldPtrs<T>& f, i64 n, const InstDev* inst, const i64* p_off,
+                           int ninst, const double* dt_inst, u64* keys, u32* vals, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_predict_morton<T>), grid_for(n, 256), dim3(256), 0, st, f, n, inst, p_off,
+                       ninst, dt_inst, keys, vals);
+}
+
+template <class T>
+void launch_gather(const FieldPtrs<T>& f, i64 n, const InstDev* inst, const i64* p_off, int ninst,
+                   const double* dt_inst, const u32* eps, const SortedPtrs<T>& s, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_gather<T>), grid_for(n, 256), dim3(256), 0, st, f, n, inst, p_off, ninst,
+                       dt_inst, eps, s);
+}
+
+void launch_mask_init(const u64* mu, i64 n, const i64* p_off, int ninst, u8* xi, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mask_init, grid_for(n, 256), dim3(256), 0, st, mu, n, p_off, ninst, xi);
+}
+
+void launch_reduce_pass(const u64* mu, i64 n, const i64* p_off, int ninst, const u8* xold, u8* xnew,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_pass, grid_for(n, 256), dim3(256), 0, st, mu, n, p_off, ninst, xold,
+                       xnew);
+}
+
+void launch_compact(const u64* mu, const u8* xi, const u32* xscan, i64 n, u32* id, u64* mu_leaf,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(k_compact, grid_for(n, 256), dim3(256), 0, st, mu, xi, xscan, n, id, mu_leaf);
+}
+
+void launch_inst_leaves(const i64* p_off, int ninst, const u32* xscan, i64 n, i64* leaf_off,
+                        i64* ioff, u32* root, u32* parent, i64 n_internal, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_inst_leaves, grid_for(ninst + 1, 64), dim3(64), 0, st, p_off, ninst, xscan,
+                       n, leaf_off, ioff, root, parent, n_internal);
+}
+
+void launch_karras(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
+                   i64 n_internal, const TreePtrs& t, hipStream_t st)
+{
+    if (n_internal <= 0) return;
+    hipLaunchKernelGGL(k_karras, grid_for(n_internal, 256), dim3(256), 0, st, mu_leaf, leaf_off,
+                       ioff, ninst, n_internal, t);
+}
+
+template <class T>
+void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 n_leaf, i64 n_internal,
+                     const u32* child, const u32* parent, u32* arrive, vec4<T>* blo, vec4<T>* bhi,
+                     hipStream_t st)
+{
+    if (n_leaf <= 0) return;
+    hipLaunchKernelGGL((k_boxes_up<T>), grid_for(n_leaf, 256), dim3(256), 0, st, posh, id,
+                       n_leaf, n_internal, child, parent, arrive, blo, bhi);
+}
+
+void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
+                         i64 n_internal, i64 n_leaf, const u32* endrange, const u32* parent,
+                         u32* pbox, i32* plen, hipStream_t st)
+{
+    const i64 nn = n_internal + n_leaf;
+    if (nn <= 0) return;
+    hipLaunchKernelGGL(k_prefix_boxes, grid_for(nn, 256), dim3(256), 0, st, mu_leaf, leaf_off, ioff,
+                       ninst, n_internal, n_leaf, endrange, parent, pbox, plen);
+}
+
+#define INST(T)                                                                                   \
+    template void launch_predict_morton<T>(const FieldPtrs<T>&, i64, const InstDev*, const i64*,  \
+                                           int, const double*, u64*, u32*, hipStream_t);          \
+    template void launch_gather<T>(const FieldPtrs<T>&, i64, const InstDev*, const i64*, int,     \
+                                   const double*, const u32*, const SortedPtrs<T>&, hipStream_t); \
+    template void launch_bbox<T>(const FieldPtrs<T>&, i64, InstDev*, const i64*, int,            \
+                                 const double*, u64*, hipStream_t);                               \
+    template void launch_boxes_up<T>(const vec4<T>*, const u32*, i64, i64, const u32*,            \
+                                     const u32*, u32*, vec4<T>*, vec4<T>*, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace shsph

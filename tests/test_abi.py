@@ -1,0 +1,61 @@
+"""The C-ABI library loads and exports every entry point the header declares
+(no compute calls: no GPU is needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2503_09713_amd as shsph
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "shsph.h")
+
+
+def _declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(shsph_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib_path():
+    if not os.path.exists(shsph.LIB_PATH):
+        from paper_2503_09713_amd import build
+        build.build(verbose=False)
+    return shsph.LIB_PATH
+
+
+def test_header_declares_the_core_entry_points():
+    names = _declared()
+    for want in ("shsph_create", "shsph_destroy", "shsph_build_tree", "shsph_density",
+                 "shsph_force", "shsph_step", "shsph_export_tree", "shsph_get_info"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(lib_path):
+    lib = ctypes.CDLL(lib_path)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", lib_path], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r" T (shsph_\w+)", out))
+    assert set(_declared()) <= exported
+
+
+def test_params_default_matches_paper_values(lib_path):
+    p = shsph.default_params()
+    assert p.hfact == 1.2 and p.chi == 1.1 and p.lambda_ == 1.2
+    assert p.alpha_av == 1.0 and p.beta_av == 2.0 and p.beta_u == 1.0
+    assert p.c_cour == 0.3 and p.c_force == 0.25
+    assert abs(p.gamma - 5.0 / 3.0) < 1e-15
+    assert ctypes.sizeof(shsph.CParticles) == 8 + 4 + 4 + 8 + 48 + 15 * 8
+
+
+def test_binding_has_no_fallback(monkeypatch, tmp_path):
+    # with the library absent, the binding raises instead of computing elsewhere
+    monkeypatch.setattr(shsph, "_lib", None)
+    monkeypatch.setattr(shsph, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        shsph.lib()
