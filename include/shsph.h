@@ -146,7 +146,7 @@ int shsph_set_stream(shsph_ctx *ctx, void *stream);
  * next call on the context. */
 const char *shsph_last_error(const shsph_ctx *ctx);
 
-/* Steps a2-a8 of the hot path on the particles as given (App. C-F):
+/* The tree half of the hot path, on the particles as given (App. C-F):
  * Morton keys (App. C.1) -> stable radix sort -> keep mask + n_red reduction
  * passes (App. D, Alg. 1) -> compaction -> Karras radix tree (App. C.7) ->
  * bottom-up tight cell boxes with h_max -> two-stage neighbour cache with the
@@ -156,7 +156,7 @@ const char *shsph_last_error(const shsph_ctx *ctx);
  * overflows. */
 int shsph_build_tree(shsph_ctx *ctx, const shsph_particles *p);
 
-/* Step a9 (App. G, Alg. 7; Sect. 2.1 Eq. sphomega): self-consistent h and
+/* Smoothing length and density (App. G, Alg. 7; Sect. 2.1 Eq. sphomega): h and
  * rho = m (hfact/h)^3 by per-particle Newton iteration over the cache, with
  * cache rebuilds when h leaves chi times its cache h; then Omega.  Needs a
  * build on the same particles.  Writes h (in place), rho and omega (if
@@ -165,14 +165,14 @@ int shsph_build_tree(shsph_ctx *ctx, const shsph_particles *p);
  * converge (its h is the last iterate). */
 int shsph_density(shsph_ctx *ctx, shsph_particles *p);
 
-/* Step a10 (Sect. 2.1 Eqs. sphvel, sphuint, with artificial viscosity and
+/* Derivatives (Sect. 2.1 Eqs. sphvel, sphuint, with artificial viscosity and
  * conductivity): writes ax, ay, az, dudt in the caller's order from the h,
  * rho, Omega of the preceding shsph_density and the caller's v and u.  Also
  * reduces the CFL dt (App. H.2), readable with shsph_get_info.  ESTATE if no
  * density result is held. */
 int shsph_force(shsph_ctx *ctx, shsph_particles *p);
 
-/* Steps a1-a11: one kick-drift-kick step (App. H.1) of dt (dt <= 0: the CFL
+/* The whole hot path: one kick-drift-kick step (App. H.1) of dt (dt <= 0: the CFL
  * dt of the previous force evaluation).  Reads the state at t^n and
  * ax..dudt = derivatives at t^n; writes the state at t^{n+1} with its
  * derivatives, h, and rho/omega/pid when non-NULL.  The particles come back
@@ -185,6 +185,19 @@ int shsph_get_info(shsph_ctx *ctx, shsph_info *out);
 
 /* Copy the tree of the last build to host buffers (see shsph_tree_export). */
 int shsph_export_tree(shsph_ctx *ctx, const shsph_tree_export *out);
+
+/* Optional per-stage timing: with `on`, every stage of the calls above is
+ * bracketed by HIP events on the context's stream and the calls wait for
+ * them at their end.  Turning it on (or off) clears the totals. */
+#define SHSPH_NUM_STAGES 12
+int shsph_set_profiling(shsph_ctx *ctx, int on);
+
+/* Totals since profiling was turned on: ms[i] = summed event time of stage i,
+ * launches[i] = how many times it ran (arrays of n <= SHSPH_NUM_STAGES). */
+int shsph_get_stage_times(shsph_ctx *ctx, double *ms, int64_t *launches, int32_t n);
+
+/* Name of stage i ("" when out of range); static storage. */
+const char *shsph_stage_name(int32_t i);
 
 #ifdef __cplusplus
 }

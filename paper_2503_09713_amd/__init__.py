@@ -25,6 +25,7 @@ SHSPH_ECAPACITY, SHSPH_EHIP, SHSPH_ESTATE = -4, -5, -6
 ERRORS = {SHSPH_EINVAL: "EINVAL", SHSPH_ENOMEM: "ENOMEM", SHSPH_ENOCONV: "ENOCONV",
           SHSPH_ECAPACITY: "ECAPACITY", SHSPH_EHIP: "EHIP", SHSPH_ESTATE: "ESTATE"}
 F32, F64 = 0, 1
+NUM_STAGES = 12
 
 
 class ShsphError(RuntimeError):
@@ -88,9 +89,13 @@ def lib():
     L.shsph_step.argtypes = [vp, C.POINTER(CParticles), C.c_double, C.POINTER(C.c_double)]
     L.shsph_get_info.argtypes = [vp, C.POINTER(Info)]
     L.shsph_export_tree.argtypes = [vp, C.POINTER(TreeExport)]
+    L.shsph_set_profiling.argtypes = [vp, ip]
+    L.shsph_get_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+    L.shsph_stage_name.argtypes = [C.c_int32]
+    L.shsph_stage_name.restype = C.c_char_p
     for fn in ("shsph_create", "shsph_destroy", "shsph_set_stream", "shsph_build_tree",
                "shsph_density", "shsph_force", "shsph_step", "shsph_get_info",
-               "shsph_export_tree"):
+               "shsph_export_tree", "shsph_set_profiling", "shsph_get_stage_times"):
         getattr(L, fn).restype = ip
     _lib = L
     return L
@@ -236,6 +241,17 @@ class Context:
             setattr(ex, k, a.ctypes.data if a.size else None)
         self._check(self.L.shsph_export_tree(self.h, C.byref(ex)))
         return out
+
+    def set_profiling(self, on: bool = True) -> None:
+        self._check(self.L.shsph_set_profiling(self.h, 1 if on else 0))
+
+    def stage_times(self) -> dict:
+        """{stage: (total_ms, launches)} since profiling was turned on."""
+        n = NUM_STAGES
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        self._check(self.L.shsph_get_stage_times(self.h, ms, cnt, n))
+        return {self.L.shsph_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(n)}
 
     def close(self) -> None:
         if getattr(self, "h", None):

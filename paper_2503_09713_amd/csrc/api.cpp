@@ -23,6 +23,25 @@ struct Buf {
 
 enum State { ST_NONE = 0, ST_TREE = 1, ST_DENSITY = 2, ST_FORCE = 3 };
 
+// Stages timed by the optional HIP-event profiler (one entry per launch group).
+enum Stage {
+    S_MORTON, S_SORT, S_GATHER, S_LEAVES, S_KARRAS, S_BOXES, S_STAGE1, S_STAGE2_COUNT,
+    S_STAGE2_FILL, S_DENSITY, S_FORCE, S_CORRECT, S_NUM
+};
+const char* const STAGE_NAMES[S_NUM] = {
+    "predict_morton", "radix_sort", "gather", "mask_reduce_compact", "karras", "boxes_up",
+    "leaf_cache", "particle_cache_count", "particle_cache_fill", "density", "force", "correct"
+};
+
+struct Prof {
+    bool on = false;
+    std::vector<int> stage;
+    std::vector<hipEvent_t> ev;     // 2 per record
+    size_t used = 0;
+    double ms[S_NUM] = {};
+    long long launches[S_NUM] = {};
+};
+
 }  // namespace
 
 struct shsph_ctx {
@@ -55,6 +74,7 @@ struct shsph_ctx {
 
     std::vector<InstDev> inst_h;
     std::vector<i64> poff_h;
+    Prof prof;
 };
 
 namespace {
@@ -66,6 +86,8 @@ int fail(shsph_ctx* c, int code, const std::string& msg)
     if (c) c->err = msg;
     return code;
 }
+
+
 
 #define HIPTRY(ctx, expr)                                                                \
     do {                                                                                 \
@@ -100,6 +122,45 @@ int ensure(shsph_ctx* c, Buf& b, size_t bytes)
 }
 
 template <class T> T* P(Buf& b) { return (T*)b.p; }
+
+// --- optional stage timing with HIP events on the context's stream -----------
+void prof_begin(shsph_ctx* c, int stage)
+{
+    Prof& p = c->prof;
+    if (!p.on) return;
+    if (p.used == p.stage.size()) {
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return;
+        p.stage.push_back(stage);
+        p.ev.push_back(e0);
+        p.ev.push_back(e1);
+    }
+    p.stage[p.used] = stage;
+    hipEventRecord(p.ev[2 * p.used], c->stream);
+}
+
+void prof_end(shsph_ctx* c)
+{
+    Prof& p = c->prof;
+    if (!p.on || p.used >= p.stage.size()) return;
+    hipEventRecord(p.ev[2 * p.used + 1], c->stream);
+    ++p.used;
+}
+
+void prof_collect(shsph_ctx* c)
+{
+    Prof& p = c->prof;
+    if (!p.on || p.used == 0) return;
+    hipEventSynchronize(p.ev[2 * p.used - 1]);
+    for (size_t i = 0; i < p.used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.ev[2 * i], p.ev[2 * i + 1]) == hipSuccess) {
+            p.ms[p.stage[i]] += ms;
+            p.launches[p.stage[i]] += 1;
+        }
+    }
+    p.used = 0;
+}
 
 int check_launch(shsph_ctx* c, const char* where)
 {
@@ -238,24 +299,31 @@ template <class T> int build(shsph_ctx* c, const shsph_particles* p, const doubl
     const i64* poff = P<i64>(c->poff_d);
     const int ninst = c->ninst;
 
-    // a1 (+ isolated box) and a2: predicted positions -> Morton keys
+    // leapfrog prediction (+ isolated box) -> Morton keys
     bool any_isolated = false;
     for (const InstDev& in : c->inst_h) any_isolated |= !in.periodic;
     if (any_isolated) launch_bbox<T>(f, n, inst, poff, ninst, dt_dev, P<u64>(c->bbox), st);
+    prof_begin(c, S_MORTON);
     launch_predict_morton<T>(f, n, inst, poff, ninst, dt_dev, P<u64>(c->keys[0]), P<u32>(c->vals[0]), st);
+    prof_end(c);
     TRY(check_launch(c, "morton"));
-    // a3: stable radix sort of (key, index), then gather into key order
+    // stable radix sort of (key, index), then gather into key order
+    prof_begin(c, S_SORT);
     const int sel = radix_sort_pairs(P<u64>(c->keys[0]), P<u32>(c->vals[0]), P<u64>(c->keys[1]),
                                      P<u32>(c->vals[1]), n, 63, poff, ninst, P<u32>(c->hist),
                                      P<u32>(c->hist_scan), c->scan_tmp.p, st);
+    prof_end(c);
     c->vals_sel = sel;
     const u64* mu = P<u64>(c->keys[sel]);
     const u32* eps = P<u32>(c->vals[sel]);
     TRY(check_launch(c, "sort"));
     SortedPtrs<T> s = sorted<T>(c, step);
+    prof_begin(c, S_GATHER);
     launch_gather<T>(f, n, inst, poff, ninst, dt_dev, eps, s, st);
+    prof_end(c);
     TRY(check_launch(c, "gather"));
-    // a4: keep mask, reduction passes (double-buffered), compaction
+    // keep mask, reduction passes (double-buffered), compaction
+    prof_begin(c, S_LEAVES);
     launch_mask_init(mu, n, poff, ninst, P<u8>(c->xi[0]), st);
     int xs = 0;
     for (int r = 0; r < nred; ++r) {
@@ -265,12 +333,13 @@ template <class T> int build(shsph_ctx* c, const shsph_particles* p, const doubl
     c->xi_sel = xs;
     scan_u8_u32(P<u8>(c->xi[xs]), P<u32>(c->xscan), n, c->scan_tmp.p, st);
     launch_compact(mu, P<u8>(c->xi[xs]), P<u32>(c->xscan), n, P<u32>(c->id), P<u64>(c->mu_leaf), st);
+    prof_end(c);
     TRY(check_launch(c, "compact"));
     TRY(read_back(c, P<u32>(c->xscan) + n, sizeof(u32)));
     const i64 nl = *(u32*)c->pinned;
     c->n_leaf = nl;
     c->n_internal = nl - ninst;
-    // a5: Karras tables + parents
+    // Karras tables + parents
     const i64 ni = c->n_internal, nn = ni + nl;
     TRY(ensure(c, c->lchild, std::max<i64>(ni, 1) * sizeof(u32)));
     TRY(ensure(c, c->rchild, std::max<i64>(ni, 1) * sizeof(u32)));
@@ -282,6 +351,7 @@ template <class T> int build(shsph_ctx* c, const shsph_particles* p, const doubl
     TRY(ensure(c, c->arrive, std::max<i64>(ni, 1) * sizeof(u32)));
     TRY(ensure(c, c->blo, nn * sizeof(vec4<T>)));
     TRY(ensure(c, c->bhi, nn * sizeof(vec4<T>)));
+    prof_begin(c, S_KARRAS);
     launch_inst_leaves(poff, ninst, P<u32>(c->xscan), n, P<i64>(c->leaf_off_d), P<i64>(c->ioff_d),
                        P<u32>(c->root_d), P<u32>(c->parent), ni, st);
     TreePtrs t;
@@ -289,12 +359,13 @@ template <class T> int build(shsph_ctx* c, const shsph_particles* p, const doubl
     t.lflag = P<u8>(c->lflag); t.rflag = P<u8>(c->rflag);
     t.child = P<u32>(c->child); t.parent = P<u32>(c->parent);
     launch_karras(P<u64>(c->mu_leaf), P<i64>(c->leaf_off_d), P<i64>(c->ioff_d), ninst, ni, t, st);
+    prof_end(c);
     TRY(check_launch(c, "karras"));
     c->restarts = 0;
     return build_caches<T>(c);
 }
 
-// a6-a8 on the current tree with h_cache = posh.w: boxes, stage 1, stage 2.
+// Boxes, stage-1 and stage-2 caches on the current tree, with h_cache = posh.w.
 template <class T> int build_caches(shsph_ctx* c)
 {
     hipStream_t st = c->stream;
@@ -303,22 +374,26 @@ template <class T> int build_caches(shsph_ctx* c)
     const i64* poff = P<i64>(c->poff_d);
     const int ninst = c->ninst;
     const vec4<T>* posh = P<vec4<T>>(c->posh);
-    // a6: bottom-up boxes and h_max
+    // bottom-up boxes and h_max
+    prof_begin(c, S_BOXES);
     launch_fill_u32(P<u32>(c->arrive), std::max<i64>(ni, 1), 0u, st);
     launch_boxes_up<T>(posh, P<u32>(c->id), nl, ni, P<u32>(c->child), P<u32>(c->parent),
                        P<u32>(c->arrive), P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), st);
+    prof_end(c);
     TRY(check_launch(c, "boxes"));
-    // a7: stage 1, leaf -> leaves
+    // stage 1, leaf -> leaves
     const double rk = 2.0 * c->prm.chi;
     TRY(ensure(c, c->lcnt, (nl + 1) * sizeof(u32)));
     TRY(ensure(c, c->loff, (nl + 1) * sizeof(u64)));
     TRY(ensure(c, c->overflow, sizeof(u32)));
     TRY(ensure(c, c->scan_tmp, scan_tmp_bytes(n + 1)));
     launch_fill_u32(P<u32>(c->overflow), 1, 0u, st);
+    prof_begin(c, S_STAGE1);
     launch_leaf_neigh<T>(false, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child), ni, nl,
                          P<i64>(c->leaf_off_d), ninst, P<u32>(c->root_d), inst, rk, nullptr,
                          P<u32>(c->lcnt), nullptr, P<u32>(c->overflow), st);
     scan_u32_u64(P<u32>(c->lcnt), P<u64>(c->loff), nl, c->scan_tmp.p, st);
+    prof_end(c);
     TRY(check_launch(c, "stage1 count"));
     HIPTRY(c, hipMemcpyAsync(c->pinned, P<u64>(c->loff) + nl, sizeof(u64), hipMemcpyDeviceToHost, st));
     HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 8, c->overflow.p, sizeof(u32), hipMemcpyDeviceToHost, st));
@@ -339,30 +414,36 @@ template <class T> int build_caches(shsph_ctx* c)
     }
     c->n_lneigh = e1;
     TRY(ensure(c, c->llist, std::max<i64>(e1, 1) * sizeof(u32)));
+    prof_begin(c, S_STAGE1);
     launch_leaf_neigh<T>(true, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child), ni, nl,
                          P<i64>(c->leaf_off_d), ninst, P<u32>(c->root_d), inst, rk, P<u64>(c->loff),
                          nullptr, P<u32>(c->llist), P<u32>(c->overflow), st);
+    prof_end(c);
     TRY(check_launch(c, "stage1 fill"));
-    // a8: stage 2, particle -> particles (exact criterion in T)
+    // stage 2, particle -> particles (exact criterion in T)
     TRY(ensure(c, c->ncnt, (n + 1) * sizeof(u32)));
     TRY(ensure(c, c->noff, (n + 1) * sizeof(u64)));
+    prof_begin(c, S_STAGE2_COUNT);
     launch_part_neigh<T>(false, posh, P<u32>(c->xscan), P<u32>(c->id), P<u64>(c->loff),
                          P<u32>(c->llist), n, poff, ninst, inst, rk, P<u32>(c->ncnt), nullptr,
                          nullptr, P<u32>(c->overflow), st);
     scan_u32_u64(P<u32>(c->ncnt), P<u64>(c->noff), n, c->scan_tmp.p, st);
+    prof_end(c);
     TRY(check_launch(c, "stage2 count"));
     TRY(read_back(c, P<u64>(c->noff) + n, sizeof(u64)));
     const i64 e2 = (i64)*(u64*)c->pinned;
     c->n_neigh = e2;
     TRY(ensure(c, c->nlist, std::max<i64>(e2, 1) * sizeof(u32)));
+    prof_begin(c, S_STAGE2_FILL);
     launch_part_neigh<T>(true, posh, P<u32>(c->xscan), P<u32>(c->id), P<u64>(c->loff),
                          P<u32>(c->llist), n, poff, ninst, inst, rk, nullptr, P<u64>(c->noff),
                          P<u32>(c->nlist), P<u32>(c->overflow), st);
+    prof_end(c);
     TRY(check_launch(c, "stage2 fill"));
     return SHSPH_OK;
 }
 
-// a9: density / h iteration with cache rebuilds while some h leaves chi h_cache.
+// Density / h iteration with cache rebuilds while some h leaves chi h_cache.
 template <class T> int run_density(shsph_ctx* c, bool with_thermo)
 {
     hipStream_t st = c->stream;
@@ -375,10 +456,12 @@ template <class T> int run_density(shsph_ctx* c, bool with_thermo)
     if (!with_thermo) s.velu = nullptr;
     for (int attempt = 0;; ++attempt) {
         launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
+        prof_begin(c, S_DENSITY);
         launch_density<T>(s, P<u64>(c->noff), P<u32>(c->nlist), n, P<i64>(c->poff_d), c->ninst,
                           P<InstDev>(c->inst_d), sp, P<T>(c->omega),
                           with_thermo ? P<vec4<T>>(c->thermo) : nullptr, P<u8>(c->status),
                           P<InstStat>(c->stat_d), st);
+        prof_end(c);
         TRY(check_launch(c, "density"));
         std::vector<InstStat> hs(c->ninst);
         const size_t sb = std::min(c->ninst * sizeof(InstStat), PINNED_BYTES - 16);
@@ -408,6 +491,7 @@ template <class T> int do_build(shsph_ctx* c, const shsph_particles* p)
     c->dtype = p->dtype;
     c->state = ST_NONE;
     TRY(build<T>(c, p, nullptr, false));
+    prof_collect(c);
     c->state = ST_TREE;
     return SHSPH_OK;
 }
@@ -430,6 +514,7 @@ template <class T> int do_density(shsph_ctx* c, shsph_particles* p)
                           P<InstDev>(c->inst_d), c->prm.hfact, (T*)p->rho, st);
     TRY(check_launch(c, "density scatter"));
     HIPTRY(c, hipStreamSynchronize(st));
+    prof_collect(c);
     c->state = ST_DENSITY;
     return rc;
 }
@@ -448,9 +533,11 @@ template <class T> int do_force(shsph_ctx* c, shsph_particles* p)
                      P<vec4<T>>(c->thermo), st);
     launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
     const SphParams sp = sph_params(c->prm);
+    prof_begin(c, S_FORCE);
     launch_force<T>(sorted<T>(c, false), P<vec4<T>>(c->thermo), P<u64>(c->noff), P<u32>(c->nlist), n,
                     P<i64>(c->poff_d), c->ninst, P<InstDev>(c->inst_d), sp, P<vec4<T>>(c->acc),
                     P<T>(c->vsig), P<InstStat>(c->stat_d), st);
+    prof_end(c);
     TRY(check_launch(c, "force"));
     const vec4<T>* acc = P<vec4<T>>(c->acc);
     launch_scatter<T>(eps, n, acc, 0, nullptr, (T*)p->ax, st);
@@ -459,6 +546,7 @@ template <class T> int do_force(shsph_ctx* c, shsph_particles* p)
     launch_scatter<T>(eps, n, acc, 3, nullptr, (T*)p->dudt, st);
     TRY(check_launch(c, "force scatter"));
     HIPTRY(c, hipStreamSynchronize(st));
+    prof_collect(c);
     c->state = ST_FORCE;
     return SHSPH_OK;
 }
@@ -487,9 +575,11 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
     TRY(ensure(c, c->acc, n * sizeof(vec4<T>)));
     launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
     const SphParams sp = sph_params(c->prm);
+    prof_begin(c, S_FORCE);
     launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u64>(c->noff), P<u32>(c->nlist), n,
                     P<i64>(c->poff_d), c->ninst, P<InstDev>(c->inst_d), sp, P<vec4<T>>(c->acc),
                     nullptr, P<InstStat>(c->stat_d), st);
+    prof_end(c);
     TRY(check_launch(c, "force"));
     OutPtrs<T> o;
     o.x = (T*)p->x; o.y = (T*)p->y; o.z = (T*)p->z;
@@ -497,14 +587,17 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
     o.u = (T*)p->u; o.h = (T*)p->h;
     o.ax = (T*)p->ax; o.ay = (T*)p->ay; o.az = (T*)p->az; o.du = (T*)p->dudt;
     o.rho = (T*)p->rho; o.omega = (T*)p->omega; o.pid = p->pid;
+    prof_begin(c, S_CORRECT);
     launch_correct<T>(sorted<T>(c, true), P<vec4<T>>(c->acc), P<T>(c->omega), n, P<i64>(c->poff_d),
                       c->ninst, P<InstDev>(c->inst_d), dt_dev, c->prm.hfact, o,
                       P<InstStat>(c->stat_d), st);
+    prof_end(c);
     TRY(check_launch(c, "correct"));
     if (dt_used) {
         TRY(read_back(c, dt_dev, sizeof(double)));
         *dt_used = *(double*)c->pinned;
     }
+    prof_collect(c);
     c->state = ST_FORCE;
     return SHSPH_OK;
 }
@@ -572,6 +665,7 @@ int shsph_destroy(shsph_ctx* c)
     for (Buf* b : all)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);
+    for (hipEvent_t e : c->prof.ev) hipEventDestroy(e);
     delete c;
     return SHSPH_OK;
 }
@@ -626,6 +720,27 @@ int shsph_step(shsph_ctx* c, shsph_particles* p, double dt, double* dt_used)
     return p->dtype == SHSPH_F32 ? do_step<float>(c, p, dt, dt_used)
                                  : do_step<double>(c, p, dt, dt_used);
 }
+
+int shsph_set_profiling(shsph_ctx* c, int on)
+{
+    if (!c) return SHSPH_EINVAL;
+    c->prof.on = on != 0;
+    c->prof.used = 0;
+    for (int i = 0; i < S_NUM; ++i) { c->prof.ms[i] = 0; c->prof.launches[i] = 0; }
+    return SHSPH_OK;
+}
+
+int shsph_get_stage_times(shsph_ctx* c, double* ms, int64_t* launches, int32_t n)
+{
+    if (!c || n < 0) return SHSPH_EINVAL;
+    for (int i = 0; i < n && i < S_NUM; ++i) {
+        if (ms) ms[i] = c->prof.ms[i];
+        if (launches) launches[i] = c->prof.launches[i];
+    }
+    return SHSPH_OK;
+}
+
+const char* shsph_stage_name(int32_t i) { return (i >= 0 && i < S_NUM) ? STAGE_NAMES[i] : ""; }
 
 int shsph_get_info(shsph_ctx* c, shsph_info* o)
 {
