@@ -48,26 +48,26 @@ def make_input(name):
 
 
 def algorithmic_bytes(stage, n, info, T):
-    """HBM bytes the kernel's algorithm must move once per launch (each array
-    read or written once; neighbour fields re-read through L2 are not counted)."""
-    e1, e2, nl = info["n_leaf_neigh"], info["n_neigh"], info["n_leaf"]
+    """HBM bytes the kernel's algorithm must move once per launch: every array
+    it touches read or written once (neighbour data re-read through L2/LDS is
+    not counted).  E2 = particle-cache entries (2 B each), E1 = group-cache
+    leaves, L = leaves, G = groups."""
+    e1, e2, nl, G = info["n_leaf_neigh"], info["n_neigh"], info["n_leaf"], info["n_groups"]
     v4 = 4 * T
     if stage == "density":
-        # posh, hn, hcache, noff, u* in; h, omega, status, thermo out; + list
-        return n * (v4 + 2 * T + 8 + T + T + T + 1 + v4) + 4 * e2
+        # posh, h^n, h_cache, count, u* in; h, omega, status, thermo out; + slots
+        return n * (v4 + T + T + 4 + T + T + T + 1 + v4) + 2 * e2 + 8 * e1
     if stage == "force":
-        # posh, velu, thermo, noff in; acc out; + list
-        return n * (3 * v4 + 8 + v4) + 4 * e2
-    if stage == "particle_cache_fill":
-        # posh, leaf-of (scan), noff in; leaf lists and leaf ranges; list out
-        return n * (v4 + 4 + 8) + nl * (8 + 4) + 4 * e1 + 4 * e2
-    if stage == "particle_cache_count":
-        return n * (v4 + 4 + 4) + nl * (8 + 4) + 4 * e1
+        # posh, velu, thermo, count in; acc out; + slots
+        return n * (3 * v4 + 4 + v4) + 2 * e2 + 8 * e1
+    if stage == "particle_cache":
+        # posh in; counts and slots out; union leaves (id, slot start, box)
+        return n * (v4 + 4) + 2 * e2 + e1 * (8 + 8 + 2 * v4)
     if stage == "correct":
         # posh, velu, vhalf, acc, pid in; 12 state fields + pid out
         return n * (4 * v4 + 4 + 12 * T + 4)
     if stage == "gather":
-        # eps + 14 fields in (x3, v3, a3, u, du, h, pid); posh, velu, vhalf, hn, hcache, pid out
+        # eps + 13 fields in (x3, v3, a3, u, du, h) + pid; posh, velu, vhalf, h^n, h_cache, pid out
         return n * (4 + 13 * T + 4 + 3 * v4 + 2 * T + 4)
     return None
 

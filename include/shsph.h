@@ -91,7 +91,8 @@ typedef struct {
 typedef struct {
     int64_t n;
     int64_t n_leaf;          /* leaves after dedupe + reduction */
-    int64_t n_leaf_neigh;    /* stage-1 cache entries (leaf -> leaves) */
+    int64_t n_groups;        /* groups of 256 key-order particles */
+    int64_t n_leaf_neigh;    /* stage-1 cache entries (group -> leaves) */
     int64_t n_neigh;         /* stage-2 cache entries (particle -> particles) */
     int32_t n_red;
     int32_t restarts;        /* cache rebuilds caused by h > chi h_cache */
@@ -105,8 +106,11 @@ typedef struct {
 
 /* Host buffers receiving the tree of the last build (test and debug use).
  * Any pointer may be NULL.  Sizes: n = particles, L = n_leaf, I = L - 1,
- * NN = 2L - 1, E1 = n_leaf_neigh, E2 = n_neigh.  Node arrays are indexed by
- * node: internal nodes 0..I-1, then leaves I..NN-1.  T = the dtype. */
+ * NN = 2L - 1, G = n_groups, E1 = n_leaf_neigh, E2 = n_neigh.  Node arrays
+ * are indexed by node: internal nodes 0..I-1, then leaves I..NN-1.  The
+ * first stage of the cache is kept per group of 256 consecutive key-order
+ * particles (group g = slots [256 g, 256 g + 256)); the second stage is
+ * returned in the plain offsets + list form of Alg. 5.  T = the dtype. */
 typedef struct {
     uint64_t *keys;      /* n   Morton keys in the caller's order (App. C.1) */
     uint32_t *eps;       /* n   sort permutation: key slot i <- input eps[i] */
@@ -122,8 +126,8 @@ typedef struct {
     void *hmax;          /* NN  T   max h of the cell */
     uint32_t *pbox;      /* 6*NN  integer prefix box X0 Y0 Z0 X1 Y1 Z1 (App. C.6) */
     int32_t *plen;       /* NN    prefix length of the box */
-    uint64_t *leaf_off;  /* L+1  stage-1 offsets */
-    uint32_t *leaf_list; /* E1   neighbour leaves (ascending) */
+    uint64_t *group_off;    /* G+1  stage-1 offsets, G = n_groups */
+    uint32_t *group_leaves; /* E1   neighbour leaves of each group (ascending) */
     uint64_t *neigh_off; /* n+1  stage-2 offsets (Alg. 5) */
     uint32_t *neigh_list;/* E2   neighbours in key slots (ascending, self included) */
     void *h_sorted;      /* n T  h in key order (after a density call: converged h) */
@@ -189,7 +193,7 @@ int shsph_export_tree(shsph_ctx *ctx, const shsph_tree_export *out);
 /* Optional per-stage timing: with `on`, every stage of the calls above is
  * bracketed by HIP events on the context's stream and the calls wait for
  * them at their end.  Turning it on (or off) clears the totals. */
-#define SHSPH_NUM_STAGES 12
+#define SHSPH_NUM_STAGES 11
 int shsph_set_profiling(shsph_ctx *ctx, int on);
 
 /* Totals since profiling was turned on: ms[i] = summed event time of stage i,

@@ -25,7 +25,7 @@ SHSPH_ECAPACITY, SHSPH_EHIP, SHSPH_ESTATE = -4, -5, -6
 ERRORS = {SHSPH_EINVAL: "EINVAL", SHSPH_ENOMEM: "ENOMEM", SHSPH_ENOCONV: "ENOCONV",
           SHSPH_ECAPACITY: "ECAPACITY", SHSPH_EHIP: "EHIP", SHSPH_ESTATE: "ESTATE"}
 F32, F64 = 0, 1
-NUM_STAGES = 12
+NUM_STAGES = 11
 
 
 class ShsphError(RuntimeError):
@@ -50,7 +50,8 @@ class CParticles(C.Structure):
 
 
 class Info(C.Structure):
-    _fields_ = [("n", C.c_int64), ("n_leaf", C.c_int64), ("n_leaf_neigh", C.c_int64),
+    _fields_ = [("n", C.c_int64), ("n_leaf", C.c_int64), ("n_groups", C.c_int64),
+                ("n_leaf_neigh", C.c_int64),
                 ("n_neigh", C.c_int64), ("n_red", C.c_int32), ("restarts", C.c_int32),
                 ("max_iter_seen", C.c_int32), ("n_noconv", C.c_int32), ("dt_cfl", C.c_double),
                 ("dv_max", C.c_double), ("dv2_sum", C.c_double), ("v2_sum", C.c_double)]
@@ -60,8 +61,8 @@ class Info(C.Structure):
 
 
 _EXPORT_FIELDS = ["keys", "eps", "mu", "xi", "id", "mu_leaf", "lchild", "rchild", "endrange",
-                  "lflag", "rflag", "parent", "bmin", "bmax", "hmax", "pbox", "plen", "leaf_off",
-                  "leaf_list", "neigh_off", "neigh_list", "h_sorted"]
+                  "lflag", "rflag", "parent", "bmin", "bmax", "hmax", "pbox", "plen", "group_off",
+                  "group_leaves", "neigh_off", "neigh_list", "h_sorted"]
 
 
 class TreeExport(C.Structure):
@@ -220,7 +221,7 @@ class Context:
     def export_tree(self, dtype=np.float32, fields=None) -> dict:
         """Copy the last tree / caches to host numpy arrays."""
         info = self.get_info()
-        n, nl = info["n"], info["n_leaf"]
+        n, nl, G = info["n"], info["n_leaf"], info["n_groups"]
         ni, nn = nl - 1, 2 * nl - 1
         e1, e2 = info["n_leaf_neigh"], info["n_neigh"]
         T = np.dtype(dtype)
@@ -229,8 +230,8 @@ class Context:
                       rchild=(ni, np.uint32), endrange=(ni, np.uint32), lflag=(ni, np.uint8),
                       rflag=(ni, np.uint8), parent=(nn, np.uint32), bmin=((nn, 3), T),
                       bmax=((nn, 3), T), hmax=(nn, T), pbox=((nn, 6), np.uint32),
-                      plen=(nn, np.int32), leaf_off=(nl + 1, np.uint64),
-                      leaf_list=(e1, np.uint32), neigh_off=(n + 1, np.uint64),
+                      plen=(nn, np.int32), group_off=(G + 1, np.uint64),
+                      group_leaves=(e1, np.uint32), neigh_off=(n + 1, np.uint64),
                       neigh_list=(e2, np.uint32), h_sorted=(n, T))
         want = fields or list(shapes)
         out, ex = {}, TreeExport()

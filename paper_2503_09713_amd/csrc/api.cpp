@@ -25,12 +25,12 @@ enum State { ST_NONE = 0, ST_TREE = 1, ST_DENSITY = 2, ST_FORCE = 3 };
 
 // Stages timed by the optional HIP-event profiler (one entry per launch group).
 enum Stage {
-    S_MORTON, S_SORT, S_GATHER, S_LEAVES, S_KARRAS, S_BOXES, S_STAGE1, S_STAGE2_COUNT,
-    S_STAGE2_FILL, S_DENSITY, S_FORCE, S_CORRECT, S_NUM
+    S_MORTON, S_SORT, S_GATHER, S_LEAVES, S_KARRAS, S_BOXES, S_STAGE1, S_STAGE2, S_DENSITY,
+    S_FORCE, S_CORRECT, S_NUM
 };
 const char* const STAGE_NAMES[S_NUM] = {
-    "predict_morton", "radix_sort", "gather", "mask_reduce_compact", "karras", "boxes_up",
-    "leaf_cache", "particle_cache_count", "particle_cache_fill", "density", "force", "correct"
+    "predict_morton", "radix_sort", "gather", "mask_reduce_compact", "karras", "boxes",
+    "group_leaf_cache", "particle_cache", "density", "force", "correct"
 };
 
 struct Prof {
@@ -54,7 +54,8 @@ struct shsph_ctx {
     int dtype = 0;
     i64 n = 0;
     int ninst = 0;
-    i64 n_leaf = 0, n_internal = 0, n_lneigh = 0, n_neigh = 0;
+    i64 n_leaf = 0, n_internal = 0, n_groups = 0;
+    i64 cap_leaf = 256, cap_entry = 112;        // per-group leaves, per-particle entries
     int state = ST_NONE;
     int restarts = 0;
     int vals_sel = 0;       // which value buffer holds eps after the sort
@@ -65,15 +66,17 @@ struct shsph_ctx {
     Buf posh, velu, vhalf, hn, hcache, pid_s, thermo, omega, acc, vsig, status;
     Buf xi[2], xscan, id, mu_leaf;
     Buf lchild, rchild, endrange, lflag, rflag, child, parent, arrive, blo, bhi;
-    Buf lcnt, loff, llist, ncnt, noff, nlist, overflow;
-    Buf inst_d, poff_d, leaf_off_d, ioff_d, root_d, stat_d, dt_inst_d, dt_host_d;
-    Buf pbox, plen;
+    Buf rec, nrec, rscan;                       // bottom-up box records
+    Buf glo, ghi, uleaf, uslot, ucnt, ustot;    // stage 1, per group
+    Buf nlist, ncnt, flags;                     // stage 2, per particle (ELL)
+    Buf inst_d, poff_d, goff_d, leaf_off_d, ioff_d, root_d, stat_d, dt_inst_d, dt_host_d;
+    Buf pbox, plen, xoff, xlist;                // export only
 
     // pinned host staging for counters
     void* pinned = nullptr;
 
     std::vector<InstDev> inst_h;
-    std::vector<i64> poff_h;
+    std::vector<i64> poff_h, goff_h;
     Prof prof;
 };
 
@@ -254,11 +257,36 @@ int set_single_instance(shsph_ctx* c, const shsph_particles* p)
     TRY(ensure(c, c->ioff_d, 2 * sizeof(i64)));
     TRY(ensure(c, c->root_d, sizeof(u32)));
     TRY(ensure(c, c->bbox, 6 * sizeof(u64)));
+    TRY(ensure(c, c->goff_d, 2 * sizeof(i64)));
+    c->n_groups = (p->n + GROUP - 1) / GROUP;
+    c->goff_h = { 0, c->n_groups };
     HIPTRY(c, hipMemcpyAsync(c->inst_d.p, c->inst_h.data(), sizeof(InstDev), hipMemcpyHostToDevice,
                              c->stream));
     HIPTRY(c, hipMemcpyAsync(c->poff_d.p, c->poff_h.data(), 2 * sizeof(i64), hipMemcpyHostToDevice,
                              c->stream));
+    HIPTRY(c, hipMemcpyAsync(c->goff_d.p, c->goff_h.data(), 2 * sizeof(i64), hipMemcpyHostToDevice,
+                             c->stream));
     return SHSPH_OK;
+}
+
+GroupMap group_map(shsph_ctx* c)
+{
+    GroupMap g;
+    g.goff = P<i64>(c->goff_d);
+    g.p_off = P<i64>(c->poff_d);
+    g.ninst = c->ninst;
+    return g;
+}
+
+CacheView cache_view(shsph_ctx* c)
+{
+    CacheView v;
+    v.uleaf = P<u32>(c->uleaf); v.uslot = P<u32>(c->uslot);
+    v.ucnt = P<u32>(c->ucnt); v.ustot = P<u32>(c->ustot);
+    v.cap = c->cap_leaf;
+    v.nlist = P<u16>(c->nlist); v.ncnt = P<u32>(c->ncnt);
+    v.capj = c->cap_entry;
+    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -366,80 +394,86 @@ template <class T> int build(shsph_ctx* c, const shsph_particles* p, const doubl
 }
 
 // Boxes, stage-1 and stage-2 caches on the current tree, with h_cache = posh.w.
+// Capacities (leaves per group, entries per particle) grow and the stage is
+// redone when a build reports more than fits.
 template <class T> int build_caches(shsph_ctx* c)
 {
     hipStream_t st = c->stream;
-    const i64 n = c->n, nl = c->n_leaf, ni = c->n_internal;
+    const i64 n = c->n, nl = c->n_leaf, ni = c->n_internal, G = c->n_groups;
     const InstDev* inst = P<InstDev>(c->inst_d);
-    const i64* poff = P<i64>(c->poff_d);
     const int ninst = c->ninst;
     const vec4<T>* posh = P<vec4<T>>(c->posh);
+    const GroupMap gm = group_map(c);
+    const double rk = 2.0 * c->prm.chi;
     // bottom-up boxes and h_max
+    const size_t nrc = boxes_rec_count(nl);
+    const i64 nbb = (i64)(nrc / 128);
+    TRY(ensure(c, c->rec, nrc * sizeof(u32)));
+    TRY(ensure(c, c->nrec, (nbb + 1) * sizeof(u32)));
+    TRY(ensure(c, c->rscan, (nbb + 1) * sizeof(u32)));
+    TRY(ensure(c, c->flags, 4 * sizeof(u32)));
+    TRY(ensure(c, c->glo, G * sizeof(vec4<T>)));
+    TRY(ensure(c, c->ghi, G * sizeof(vec4<T>)));
+    TRY(ensure(c, c->ucnt, G * sizeof(u32)));
+    TRY(ensure(c, c->ustot, G * sizeof(u32)));
+    TRY(ensure(c, c->ncnt, n * sizeof(u32)));
     prof_begin(c, S_BOXES);
     launch_fill_u32(P<u32>(c->arrive), std::max<i64>(ni, 1), 0u, st);
+    launch_fill_u32(P<u32>(c->flags), 4, 0u, st);
     launch_boxes_up<T>(posh, P<u32>(c->id), nl, ni, P<u32>(c->child), P<u32>(c->parent),
-                       P<u32>(c->arrive), P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), st);
+                       P<u32>(c->endrange), P<i64>(c->ioff_d), P<i64>(c->leaf_off_d), ninst,
+                       P<u32>(c->arrive), P<u32>(c->rec), P<u32>(c->nrec), P<u32>(c->rscan),
+                       c->scan_tmp.p, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->flags), st);
+    launch_group_boxes<T>(posh, gm, G, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), st);
     prof_end(c);
     TRY(check_launch(c, "boxes"));
-    // stage 1, leaf -> leaves
-    const double rk = 2.0 * c->prm.chi;
-    TRY(ensure(c, c->lcnt, (nl + 1) * sizeof(u32)));
-    TRY(ensure(c, c->loff, (nl + 1) * sizeof(u64)));
-    TRY(ensure(c, c->overflow, sizeof(u32)));
-    TRY(ensure(c, c->scan_tmp, scan_tmp_bytes(n + 1)));
-    launch_fill_u32(P<u32>(c->overflow), 1, 0u, st);
-    prof_begin(c, S_STAGE1);
-    launch_leaf_neigh<T>(false, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child), ni, nl,
-                         P<i64>(c->leaf_off_d), ninst, P<u32>(c->root_d), inst, rk, nullptr,
-                         P<u32>(c->lcnt), nullptr, P<u32>(c->overflow), st);
-    scan_u32_u64(P<u32>(c->lcnt), P<u64>(c->loff), nl, c->scan_tmp.p, st);
-    prof_end(c);
-    TRY(check_launch(c, "stage1 count"));
-    HIPTRY(c, hipMemcpyAsync(c->pinned, P<u64>(c->loff) + nl, sizeof(u64), hipMemcpyDeviceToHost, st));
-    HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 8, c->overflow.p, sizeof(u32), hipMemcpyDeviceToHost, st));
-    HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 16, P<vec4<T>>(c->blo), sizeof(vec4<T>),
-                             hipMemcpyDeviceToHost, st));
-    HIPTRY(c, hipStreamSynchronize(st));
-    const i64 e1 = (i64)*(u64*)c->pinned;
-    if (*(u32*)((char*)c->pinned + 8)) return fail(c, SHSPH_ECAPACITY, "tree traversal stack overflow");
-    // periodic minimum image needs the cache radius below half the box
-    for (int k = 0; k < ninst; ++k) {
-        const InstDev& in = c->inst_h[k];
-        if (!in.periodic) continue;
-        // node 0 is the root of a single instance (internal node, or the only leaf)
-        const double hmax = (ninst == 1) ? (double)((vec4<T>*)((char*)c->pinned + 16))->w : 0.0;
-        for (int d = 0; d < 3; ++d)
-            if (rk * hmax >= 0.5 * (in.hi[d] - in.lo[d]))
-                return fail(c, SHSPH_EINVAL, "periodic box smaller than twice the cache radius");
+    for (int attempt = 0;; ++attempt) {
+        // stage 1: neighbour leaves of each group
+        TRY(ensure(c, c->uleaf, (size_t)G * c->cap_leaf * sizeof(u32)));
+        TRY(ensure(c, c->uslot, (size_t)G * c->cap_leaf * sizeof(u32)));
+        TRY(ensure(c, c->nlist, (size_t)G * c->cap_entry * GROUP * sizeof(u16)));
+        prof_begin(c, S_STAGE1);
+        launch_group_leaves<T>(P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child),
+                               P<u32>(c->id), ni, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), G, gm,
+                               P<u32>(c->root_d), inst, rk, c->cap_leaf, P<u32>(c->uleaf),
+                               P<u32>(c->uslot), P<u32>(c->ucnt), P<u32>(c->ustot),
+                               P<u32>(c->flags), st);
+        prof_end(c);
+        TRY(check_launch(c, "stage1"));
+        // stage 2: particle neighbours as union slots
+        prof_begin(c, S_STAGE2);
+        launch_group_cache<T>(posh, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->id), ni, gm, G,
+                              inst, rk, rk, c->cap_leaf, P<u32>(c->uleaf), P<u32>(c->uslot),
+                              P<u32>(c->ucnt), c->cap_entry, P<u16>(c->nlist), P<u32>(c->ncnt),
+                              P<u32>(c->flags), st);
+        prof_end(c);
+        TRY(check_launch(c, "stage2"));
+        HIPTRY(c, hipMemcpyAsync(c->pinned, c->flags.p, 4 * sizeof(u32), hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 16, P<vec4<T>>(c->blo), sizeof(vec4<T>),
+                                 hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipStreamSynchronize(st));
+        u32 fl[4];
+        memcpy(fl, c->pinned, sizeof(fl));
+        if (fl[0] & 1u) return fail(c, SHSPH_ECAPACITY, "tree traversal stack overflow");
+        if (fl[0] & 8u)
+            return fail(c, SHSPH_ECAPACITY, "a group's candidate union exceeds 65535 particles");
+        if (fl[0] & 16u) return fail(c, SHSPH_ECAPACITY, "bottom-up box records overflow");
+        // periodic minimum image needs the cache radius below half the box
+        for (int k = 0; k < ninst; ++k) {
+            const InstDev& in = c->inst_h[k];
+            if (!in.periodic || ninst != 1) continue;
+            // node 0 is the root of a single instance (internal node, or the only leaf)
+            const double hmax = (double)((vec4<T>*)((char*)c->pinned + 16))->w;
+            for (int d = 0; d < 3; ++d)
+                if (rk * hmax >= 0.5 * (in.hi[d] - in.lo[d]))
+                    return fail(c, SHSPH_EINVAL, "periodic box smaller than twice the cache radius");
+        }
+        if (!(fl[0] & 6u)) break;
+        if (attempt >= 4) return fail(c, SHSPH_ECAPACITY, "neighbour cache capacity");
+        if (fl[0] & 2u) c->cap_leaf = (i64)fl[1] + fl[1] / 4 + 16;
+        if (fl[0] & 4u) c->cap_entry = (i64)fl[2] + fl[2] / 4 + 8;
+        launch_fill_u32(P<u32>(c->flags), 4, 0u, st);
     }
-    c->n_lneigh = e1;
-    TRY(ensure(c, c->llist, std::max<i64>(e1, 1) * sizeof(u32)));
-    prof_begin(c, S_STAGE1);
-    launch_leaf_neigh<T>(true, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child), ni, nl,
-                         P<i64>(c->leaf_off_d), ninst, P<u32>(c->root_d), inst, rk, P<u64>(c->loff),
-                         nullptr, P<u32>(c->llist), P<u32>(c->overflow), st);
-    prof_end(c);
-    TRY(check_launch(c, "stage1 fill"));
-    // stage 2, particle -> particles (exact criterion in T)
-    TRY(ensure(c, c->ncnt, (n + 1) * sizeof(u32)));
-    TRY(ensure(c, c->noff, (n + 1) * sizeof(u64)));
-    prof_begin(c, S_STAGE2_COUNT);
-    launch_part_neigh<T>(false, posh, P<u32>(c->xscan), P<u32>(c->id), P<u64>(c->loff),
-                         P<u32>(c->llist), n, poff, ninst, inst, rk, P<u32>(c->ncnt), nullptr,
-                         nullptr, P<u32>(c->overflow), st);
-    scan_u32_u64(P<u32>(c->ncnt), P<u64>(c->noff), n, c->scan_tmp.p, st);
-    prof_end(c);
-    TRY(check_launch(c, "stage2 count"));
-    TRY(read_back(c, P<u64>(c->noff) + n, sizeof(u64)));
-    const i64 e2 = (i64)*(u64*)c->pinned;
-    c->n_neigh = e2;
-    TRY(ensure(c, c->nlist, std::max<i64>(e2, 1) * sizeof(u32)));
-    prof_begin(c, S_STAGE2_FILL);
-    launch_part_neigh<T>(true, posh, P<u32>(c->xscan), P<u32>(c->id), P<u64>(c->loff),
-                         P<u32>(c->llist), n, poff, ninst, inst, rk, nullptr, P<u64>(c->noff),
-                         P<u32>(c->nlist), P<u32>(c->overflow), st);
-    prof_end(c);
-    TRY(check_launch(c, "stage2 fill"));
     return SHSPH_OK;
 }
 
@@ -457,18 +491,16 @@ template <class T> int run_density(shsph_ctx* c, bool with_thermo)
     for (int attempt = 0;; ++attempt) {
         launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
         prof_begin(c, S_DENSITY);
-        launch_density<T>(s, P<u64>(c->noff), P<u32>(c->nlist), n, P<i64>(c->poff_d), c->ninst,
-                          P<InstDev>(c->inst_d), sp, P<T>(c->omega),
+        launch_density<T>(s, P<u32>(c->id), group_map(c), c->n_groups, P<InstDev>(c->inst_d), sp,
+                          cache_view(c), P<T>(c->omega),
                           with_thermo ? P<vec4<T>>(c->thermo) : nullptr, P<u8>(c->status),
                           P<InstStat>(c->stat_d), st);
         prof_end(c);
         TRY(check_launch(c, "density"));
         std::vector<InstStat> hs(c->ninst);
-        const size_t sb = std::min(c->ninst * sizeof(InstStat), PINNED_BYTES - 16);
-        HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 16, c->stat_d.p, sb, hipMemcpyDeviceToHost, st));
-        TRY(read_back(c, c->overflow.p, sizeof(u32)));
-        if (*(u32*)c->pinned) return fail(c, SHSPH_ECAPACITY, "neighbour cache fill exceeded its count");
-        memcpy(hs.data(), (char*)c->pinned + 16, sb);
+        const size_t sb = std::min(c->ninst * sizeof(InstStat), PINNED_BYTES);
+        TRY(read_back(c, c->stat_d.p, sb));
+        memcpy(hs.data(), c->pinned, sb);
         u32 ex = 0, nc = 0;
         for (const InstStat& q : hs) { ex += q.n_exceed; nc += q.n_noconv; }
         if (ex == 0) {
@@ -534,8 +566,8 @@ template <class T> int do_force(shsph_ctx* c, shsph_particles* p)
     launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
     const SphParams sp = sph_params(c->prm);
     prof_begin(c, S_FORCE);
-    launch_force<T>(sorted<T>(c, false), P<vec4<T>>(c->thermo), P<u64>(c->noff), P<u32>(c->nlist), n,
-                    P<i64>(c->poff_d), c->ninst, P<InstDev>(c->inst_d), sp, P<vec4<T>>(c->acc),
+    launch_force<T>(sorted<T>(c, false), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
+                    c->n_groups, P<InstDev>(c->inst_d), sp, cache_view(c), P<vec4<T>>(c->acc),
                     P<T>(c->vsig), P<InstStat>(c->stat_d), st);
     prof_end(c);
     TRY(check_launch(c, "force"));
@@ -576,8 +608,8 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
     launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
     const SphParams sp = sph_params(c->prm);
     prof_begin(c, S_FORCE);
-    launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u64>(c->noff), P<u32>(c->nlist), n,
-                    P<i64>(c->poff_d), c->ninst, P<InstDev>(c->inst_d), sp, P<vec4<T>>(c->acc),
+    launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
+                    c->n_groups, P<InstDev>(c->inst_d), sp, cache_view(c), P<vec4<T>>(c->acc),
                     nullptr, P<InstStat>(c->stat_d), st);
     prof_end(c);
     TRY(check_launch(c, "force"));
@@ -599,6 +631,19 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
     }
     prof_collect(c);
     c->state = ST_FORCE;
+    return SHSPH_OK;
+}
+
+// Sum of a device u32 array (through the exclusive scan; waits).
+int sum_u32(shsph_ctx* c, const u32* p, i64 count, u64* out)
+{
+    *out = 0;
+    if (count <= 0) return SHSPH_OK;
+    TRY(ensure(c, c->xoff, (count + 1) * sizeof(u64)));
+    TRY(ensure(c, c->scan_tmp, scan_tmp_bytes(count + 1)));
+    scan_u32_u64(p, P<u64>(c->xoff), count, c->scan_tmp.p, c->stream);
+    TRY(read_back(c, P<u64>(c->xoff) + count, 8));
+    *out = *(u64*)c->pinned;
     return SHSPH_OK;
 }
 
@@ -659,9 +704,10 @@ int shsph_destroy(shsph_ctx* c)
                    &c->pid_s, &c->thermo, &c->omega, &c->acc, &c->vsig, &c->status, &c->xi[0],
                    &c->xi[1], &c->xscan, &c->id, &c->mu_leaf, &c->lchild, &c->rchild, &c->endrange,
                    &c->lflag, &c->rflag, &c->child, &c->parent, &c->arrive, &c->blo, &c->bhi,
-                   &c->lcnt, &c->loff, &c->llist, &c->ncnt, &c->noff, &c->nlist, &c->overflow,
-                   &c->inst_d, &c->poff_d, &c->leaf_off_d, &c->ioff_d, &c->root_d, &c->stat_d,
-                   &c->dt_inst_d, &c->dt_host_d, &c->pbox, &c->plen };
+                   &c->rec, &c->nrec, &c->rscan, &c->glo, &c->ghi, &c->uleaf, &c->uslot,
+                   &c->ucnt, &c->ustot, &c->nlist, &c->ncnt, &c->flags, &c->inst_d, &c->poff_d,
+                   &c->goff_d, &c->leaf_off_d, &c->ioff_d, &c->root_d, &c->stat_d,
+                   &c->dt_inst_d, &c->dt_host_d, &c->pbox, &c->plen, &c->xoff, &c->xlist };
     for (Buf* b : all)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);
@@ -748,10 +794,17 @@ int shsph_get_info(shsph_ctx* c, shsph_info* o)
     memset(o, 0, sizeof(*o));
     o->n = c->n;
     o->n_leaf = c->n_leaf;
-    o->n_leaf_neigh = c->n_lneigh;
-    o->n_neigh = c->n_neigh;
+    o->n_groups = c->n_groups;
     o->n_red = c->prm.n_red;
     o->restarts = c->restarts;
+    HIPTRY(c, hipSetDevice(c->device));
+    if (c->state >= ST_TREE) {
+        u64 t1 = 0, t2 = 0;
+        TRY(sum_u32(c, P<u32>(c->ucnt), c->n_groups, &t1));
+        TRY(sum_u32(c, P<u32>(c->ncnt), c->n, &t2));
+        o->n_leaf_neigh = (int64_t)t1;
+        o->n_neigh = (int64_t)t2;
+    }
     if (c->stat_d.p && c->ninst >= 1) {
         InstStat s;
         HIPTRY(c, hipMemcpyAsync(c->pinned, c->stat_d.p, sizeof(InstStat), hipMemcpyDeviceToHost,
@@ -763,8 +816,7 @@ int shsph_get_info(shsph_ctx* c, shsph_info* o)
         memcpy(&dv, &s.dvmax_bits, 4);
         o->dt_cfl = dt;
         o->dv_max = dv;
-        o->dv2_sum = s.dv2_sum;
-        o->v2_sum = s.v2_sum;
+        for (int i = 0; i < STAT_SLOTS; ++i) { o->dv2_sum += s.dv2_part[i]; o->v2_sum += s.v2_part[i]; }
         o->max_iter_seen = (int32_t)s.max_iter_seen;
         o->n_noconv = (int32_t)s.n_noconv;
     }
@@ -777,15 +829,14 @@ int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
     if (c->state < ST_TREE) return fail(c, SHSPH_ESTATE, "no tree built");
     HIPTRY(c, hipSetDevice(c->device));
     hipStream_t st = c->stream;
-    const i64 n = c->n, nl = c->n_leaf, ni = c->n_internal, nn = ni + nl;
+    const i64 n = c->n, nl = c->n_leaf, ni = c->n_internal, nn = ni + nl, G = c->n_groups;
     const size_t T = c->dtype == SHSPH_F32 ? 4 : 8;
     auto cp = [&](void* dst, const void* src, size_t bytes) -> int {
         if (dst && bytes) HIPTRY(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
         return SHSPH_OK;
     };
-    // keys in caller order are not kept after the sort: recompute them
+    // keys in caller order are not kept after the sort: scatter back through eps
     if (o->keys) {
-        // scatter the sorted keys back through eps
         std::vector<u64> mu(n);
         std::vector<u32> eps(n);
         HIPTRY(c, hipMemcpyAsync(mu.data(), c->keys[c->vals_sel].p, n * 8, hipMemcpyDeviceToHost, st));
@@ -820,7 +871,7 @@ int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
         }
     }
     if (o->pbox || o->plen) {
-        TRY(ensure(c, c->pbox, std::max<size_t>(n * sizeof(u64), 6 * nn * sizeof(u32))));
+        TRY(ensure(c, c->pbox, 6 * nn * sizeof(u32)));
         TRY(ensure(c, c->plen, nn * sizeof(i32)));
         launch_prefix_boxes(P<u64>(c->mu_leaf), P<i64>(c->leaf_off_d), P<i64>(c->ioff_d), c->ninst,
                             ni, nl, P<u32>(c->endrange), P<u32>(c->parent), P<u32>(c->pbox),
@@ -829,10 +880,35 @@ int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
         TRY(cp(o->pbox, c->pbox.p, 6 * nn * 4));
         TRY(cp(o->plen, c->plen.p, nn * 4));
     }
-    TRY(cp(o->leaf_off, c->loff.p, (nl + 1) * 8));
-    TRY(cp(o->leaf_list, c->llist.p, c->n_lneigh * 4));
-    TRY(cp(o->neigh_off, c->noff.p, (n + 1) * 8));
-    TRY(cp(o->neigh_list, c->nlist.p, c->n_neigh * 4));
+    if (o->group_off || o->group_leaves) {
+        std::vector<u32> cnt(G), ul((size_t)G * c->cap_leaf);
+        HIPTRY(c, hipMemcpyAsync(cnt.data(), c->ucnt.p, G * 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipMemcpyAsync(ul.data(), c->uleaf.p, ul.size() * 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipStreamSynchronize(st));
+        u64 off = 0;
+        for (i64 g = 0; g < G; ++g) {
+            if (o->group_off) o->group_off[g] = off;
+            if (o->group_leaves)
+                memcpy(o->group_leaves + off, &ul[(size_t)g * c->cap_leaf], cnt[g] * 4);
+            off += cnt[g];
+        }
+        if (o->group_off) o->group_off[G] = off;
+    }
+    if (o->neigh_off || o->neigh_list) {
+        u64 total = 0;
+        TRY(ensure(c, c->xoff, (n + 1) * sizeof(u64)));
+        TRY(ensure(c, c->scan_tmp, scan_tmp_bytes(n + 1)));
+        scan_u32_u64(P<u32>(c->ncnt), P<u64>(c->xoff), n, c->scan_tmp.p, st);
+        TRY(read_back(c, P<u64>(c->xoff) + n, 8));
+        total = *(u64*)c->pinned;
+        TRY(ensure(c, c->xlist, std::max<u64>(total, 1) * sizeof(u32)));
+        launch_cache_to_global(P<u32>(c->id), group_map(c), G, c->cap_leaf, P<u32>(c->uleaf),
+                               P<u32>(c->uslot), P<u32>(c->ucnt), c->cap_entry, P<u16>(c->nlist),
+                               P<u32>(c->ncnt), P<u64>(c->xoff), P<u32>(c->xlist), st);
+        TRY(check_launch(c, "cache export"));
+        TRY(cp(o->neigh_off, c->xoff.p, (n + 1) * 8));
+        TRY(cp(o->neigh_list, c->xlist.p, total * 4));
+    }
     if (o->h_sorted) {
         std::vector<char> ph(n * 4 * T);
         HIPTRY(c, hipMemcpyAsync(ph.data(), c->posh.p, n * 4 * T, hipMemcpyDeviceToHost, st));

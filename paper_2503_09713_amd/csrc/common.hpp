@@ -6,6 +6,7 @@
 namespace shsph {
 
 typedef uint8_t u8;
+typedef uint16_t u16;
 typedef uint32_t u32;
 typedef uint64_t u64;
 typedef int32_t i32;
@@ -36,15 +37,21 @@ struct InstDev {
     i32 pad;
 };
 
-// Per-instance reductions written by the step kernels.
+// Per-instance reductions written by the step kernels.  Sums are spread
+// over STAT_SLOTS partial slots (slot = block index mod STAT_SLOTS) so that
+// no single address takes an atomic from every workgroup.
+constexpr int STAT_SLOTS = 16;
 struct InstStat {
     u32 dt_bits;             // CFL dt as the bit pattern of a positive float
     u32 dvmax_bits;          // max |dv| (positive float bits)
-    double dv2_sum;          // sum |dv|^2
-    double v2_sum;           // sum |v|^2
     u32 n_exceed, n_noconv;  // h iteration outcome counters
-    u32 max_iter_seen, pad;
+    u32 max_iter_seen;
+    u32 pad[3];
+    double dv2_part[STAT_SLOTS];   // sum |dv|^2
+    double v2_part[STAT_SLOTS];    // sum |v|^2
 };
+
+
 
 // Largest k with off[k] <= i, for a sorted table off[0..n] (binary search).
 __device__ inline int find_seg(const i64* off, int n, i64 i)
@@ -56,6 +63,22 @@ __device__ inline int find_seg(const i64* off, int n, i64 i)
     }
     return lo;
 }
+
+// Particles are processed in groups of GROUP consecutive key-order slots,
+// one workgroup per group; groups never straddle two instances.
+constexpr int GROUP = 256;
+struct GroupMap {
+    const i64* goff;    // ninst+1: first group of each instance
+    const i64* p_off;   // ninst+1: first particle of each instance
+    int ninst;
+    __device__ int inst_of(i64 g) const { return find_seg(goff, ninst, g); }
+    __device__ void range(i64 g, i64& beg, i64& end, int& k) const
+    {
+        k = inst_of(g);
+        beg = p_off[k] + (g - goff[k]) * GROUP;
+        end = beg + GROUP < p_off[k + 1] ? beg + GROUP : p_off[k + 1];
+    }
+};
 
 // ------------------------------------------------------ wave primitives ----
 __device__ inline u64 lanemask_lt() { return (1ull << __lane_id()) - 1ull; }

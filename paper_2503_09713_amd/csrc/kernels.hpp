@@ -36,6 +36,19 @@ template <class T> struct OutPtrs {
     u32* pid;
 };
 
+// The group neighbour cache: per group, its union of neighbour leaves
+// (uleaf, with the union slot where each leaf starts, uslot; ucnt leaves,
+// ustot slots; capacity cap per group), and per particle its neighbours as
+// 16-bit union slots in ELL layout nlist[(g * capj + j) * GROUP + lane],
+// ncnt[a] of them.
+struct CacheView {
+    const u32 *uleaf, *uslot, *ucnt, *ustot;
+    i64 cap;
+    const u16* nlist;
+    const u32* ncnt;
+    i64 capj;
+};
+
 struct SphParams {
     double hfact, gamma, alpha, beta, beta_u, chi, lambda, eps_h, c_cour, c_force, r_kern;
     int max_iter;
@@ -73,23 +86,35 @@ void launch_karras(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int
                    i64 n_internal, const TreePtrs& t, hipStream_t st);
 template <class T>
 void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 n_leaf, i64 n_internal,
-                     const u32* child, const u32* parent, u32* arrive, vec4<T>* blo, vec4<T>* bhi,
+                     const u32* child, const u32* parent, const u32* endrange, const i64* ioff,
+                     const i64* leaf_off, int ninst, u32* arrive, u32* rec, u32* nrec,
+                     u32* rscan, void* scan_tmp, vec4<T>* blo, vec4<T>* bhi, u32* flags,
                      hipStream_t st);
+size_t boxes_rec_count(i64 n_leaf);
 void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
                          i64 n_internal, i64 n_leaf, const u32* endrange, const u32* parent,
                          u32* pbox, i32* plen, hipStream_t st);
 
 // neigh.hip
 template <class T>
-void launch_leaf_neigh(bool fill, const vec4<T>* blo, const vec4<T>* bhi, const u32* child,
-                       i64 n_internal, i64 n_leaf, const i64* leaf_off, int ninst, const u32* root,
-                       const InstDev* inst, double rk, const u64* off, u32* cnt, u32* list,
-                       u32* overflow, hipStream_t st);
+void launch_group_boxes(const vec4<T>* posh, const GroupMap& gm, i64 ngroups, vec4<T>* glo,
+                        vec4<T>* ghi, hipStream_t st);
 template <class T>
-void launch_part_neigh(bool fill, const vec4<T>* posh, const u32* xscan, const u32* id,
-                       const u64* loff, const u32* llist, i64 n, const i64* p_off, int ninst,
-                       const InstDev* inst, double rkc, u32* cnt, const u64* noff, u32* nlist,
-                       u32* overflow, hipStream_t st);
+void launch_group_leaves(const vec4<T>* blo, const vec4<T>* bhi, const u32* child, const u32* id,
+                         i64 n_internal, const vec4<T>* glo, const vec4<T>* ghi, i64 ngroups,
+                         const GroupMap& gm, const u32* root, const InstDev* inst, double rk,
+                         i64 cap, u32* uleaf, u32* uslot, u32* ucnt, u32* ustot, u32* flags,
+                         hipStream_t st);
+template <class T>
+void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* bhi, const u32* id,
+                        i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
+                        double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
+                        const u32* ucnt, i64 capj, u16* nlist, u32* ncnt, u32* flags,
+                        hipStream_t st);
+void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
+                            const u32* uleaf, const u32* uslot, const u32* ucnt, i64 capj,
+                            const u16* nlist, const u32* ncnt, const u64* off, u32* list,
+                            hipStream_t st);
 
 // sph.hip
 void launch_fill_u32(u32* p, i64 n, u32 v, hipStream_t st);
@@ -98,12 +123,12 @@ void launch_dt_select(double* dt_inst, const InstStat* s, const double* dt_host,
                       hipStream_t st);
 template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStream_t st);
 template <class T>
-void launch_density(const SortedPtrs<T>& s, const u64* noff, const u32* nlist, i64 n,
-                    const i64* p_off, int ninst, const InstDev* inst, const SphParams& P,
-                    T* omega, vec4<T>* thermo, u8* status, InstStat* stat, hipStream_t st);
+void launch_density(const SortedPtrs<T>& s, const u32* id, const GroupMap& gm, i64 ngroups,
+                    const InstDev* inst, const SphParams& P, const CacheView& cv, T* omega,
+                    vec4<T>* thermo, u8* status, InstStat* stat, hipStream_t st);
 template <class T>
-void launch_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u64* noff, const u32* nlist,
-                  i64 n, const i64* p_off, int ninst, const InstDev* inst, const SphParams& P,
+void launch_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id, const GroupMap& gm,
+                  i64 ngroups, const InstDev* inst, const SphParams& P, const CacheView& cv,
                   vec4<T>* acc, T* vsig, InstStat* stat, hipStream_t st);
 template <class T>
 void launch_correct(const SortedPtrs<T>& s, const vec4<T>* acc, const T* omega, i64 n,

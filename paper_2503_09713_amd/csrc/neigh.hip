@@ -1,16 +1,20 @@
-// Two-stage neighbour cache (App. E.3-E.4, Alg. 4-6).
+// Two-stage neighbour cache (App. E.3-E.4, Alg. 4-6), laid out for gfx950.
 //
-// Stage 1: one thread per leaf walks its instance's tree with a 64-entry
-// stack kept in LDS (one column per lane, conflict free) and keeps the
-// leaves that pass the group-group criterion
-//     AABB_L  n  [AABB_C (+) R chi max(hmax_L, hmax_C)]  !=  0
-// (App. F), with periodic images and a small outward inflation so that the
-// prune is a superset of the exact particle test.  Children are pushed right
-// then left, so leaves come out in ascending order.
-// Stage 2: one thread per particle tests the particles of its leaf's
-// neighbour leaves with the exact object-object criterion in the storage
-// type, writing neighbours in ascending key order.  Both stages run a count
-// pass, an exclusive scan and a fill pass (Alg. 5).
+// Particles are taken in groups of GROUP = 256 consecutive key-order slots
+// (one workgroup).  Stage 1 runs once per group: one thread walks the tree
+// with a 64-entry stack in LDS (Alg. 4) and keeps the leaves that pass the
+// group-group criterion of App. F,
+//     box_G  n  [box_C (+) R chi max(hmax_G, hmax_C)]  !=  0,
+// with periodic images and a slight outward inflation so that the prune is a
+// superset of the exact particle test.  Children are pushed right then left,
+// so the kept leaves come out in ascending order; their particles, in that
+// order, form the group's candidate "union", numbered by 16-bit slots.
+// Stage 2 runs one workgroup per group: each particle prefilters the union's
+// leaves by box and tests their particles with the exact object-object
+// criterion in the storage type, writing the accepted slots (ascending)
+// into an ELL layout [group][entry][lane] so that reads and writes of the
+// cache are coalesced across a wave.  The derivative kernels stage the union's
+// particle data in LDS and resolve slots there.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -18,6 +22,7 @@ namespace shsph {
 
 constexpr int STACK = 64;   // tree depth is bounded by the 63 key bits
 constexpr int TRAV_BLOCK = 64;
+constexpr int LCHUNK = 512;  // union leaves staged in LDS at a time (stage 2)
 
 template <class T> struct Inflate;
 template <> struct Inflate<float> {
@@ -39,134 +44,264 @@ __device__ inline T gap1(T a0, T a1, T b0, T b1, T L, int periodic)
     return g;
 }
 
-template <class T, bool FILL>
+template <class T> __device__ inline T abs_inflation(const Box<T>& bx)
+{
+    T s = fmax(fmax(fabs(bx.lo[0]), fabs(bx.hi[0])), fmax(fabs(bx.lo[1]), fabs(bx.hi[1])));
+    s = fmax(s, fmax(fabs(bx.lo[2]), fabs(bx.hi[2])));
+    s = fmax(s, fmax(bx.L[0], fmax(bx.L[1], bx.L[2])));
+    return Inflate<T>::abs * s;
+}
+
+// Box-box prune with the inflated radius; explicit roundings keep it
+// identical wherever it is evaluated.
+template <class T>
+__device__ inline bool box_hit(const vec4<T>& al, const vec4<T>& ah, const vec4<T>& bl,
+                               const vec4<T>& bh, T rk, T eps_abs, const Box<T>& bx)
+{
+    const T r = add_rn(mul_rn(mul_rn(rk, fmax(al.w, bl.w)), T(1) + Inflate<T>::rel), eps_abs);
+    return gap1<T>(al.x, ah.x, bl.x, bh.x, bx.L[0], bx.periodic) <= r &&
+           gap1<T>(al.y, ah.y, bl.y, bh.y, bx.L[1], bx.periodic) <= r &&
+           gap1<T>(al.z, ah.z, bl.z, bh.z, bx.L[2], bx.periodic) <= r;
+}
+
+// Tight box and h_max of each group (one workgroup per group).
+template <class T>
+__global__ void __launch_bounds__(GROUP)
+k_group_boxes(const vec4<T>* __restrict__ posh, const GroupMap gm, vec4<T>* __restrict__ glo,
+              vec4<T>* __restrict__ ghi)
+{
+    __shared__ T red[GROUP / WAVE][7];
+    const i64 g = blockIdx.x;
+    i64 beg, end;
+    int k;
+    gm.range(g, beg, end, k);
+    const i64 a = beg + threadIdx.x;
+    const bool live = a < end;
+    const vec4<T> p = posh[live ? a : beg];
+    T v[7] = { p.x, p.y, p.z, -p.x, -p.y, -p.z, p.w };     // all reduced with min, h with max
+    v[6] = -p.w;
+    for (int c = 0; c < 7; ++c) {
+        T x = v[c];
+        for (int d = WAVE / 2; d > 0; d >>= 1) x = fmin(x, __shfl_xor(x, d, WAVE));
+        v[c] = x;
+    }
+    const int lane = __lane_id(), wid = threadIdx.x / WAVE;
+    if (lane == 0)
+        for (int c = 0; c < 7; ++c) red[wid][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < GROUP / WAVE; ++w)
+            for (int c = 0; c < 7; ++c) v[c] = fmin(v[c], red[w][c]);
+        glo[g] = mk4<T>(v[0], v[1], v[2], -v[6]);
+        ghi[g] = mk4<T>(-v[3], -v[4], -v[5], T(0));
+    }
+}
+
+// Stage 1: neighbour leaves of each group, ascending, with the slot where
+// each leaf's particles start in the group's union.  Writes at most `cap`
+// leaves per group; reports the largest count and union size.
+template <class T>
 __global__ void __launch_bounds__(TRAV_BLOCK)
-k_leaf_neigh(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
-             const u32* __restrict__ child, i64 n_internal, i64 n_leaf,
-             const i64* __restrict__ leaf_off, int ninst, const u32* __restrict__ root,
-             const InstDev* __restrict__ inst, T rk, const u64* __restrict__ off,
-             u32* __restrict__ cnt, u32* __restrict__ list, u32* __restrict__ overflow)
+k_group_leaves(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
+               const u32* __restrict__ child, const u32* __restrict__ id, i64 n_internal,
+               const vec4<T>* __restrict__ glo, const vec4<T>* __restrict__ ghi, i64 ngroups,
+               const GroupMap gm, const u32* __restrict__ root, const InstDev* __restrict__ inst,
+               T rk, i64 cap, u32* __restrict__ uleaf, u32* __restrict__ uslot,
+               u32* __restrict__ ucnt, u32* __restrict__ ustot, u32* __restrict__ flags)
 {
     __shared__ u32 stack[STACK][TRAV_BLOCK];
     const int lane = threadIdx.x;
-    const i64 g = (i64)blockIdx.x * TRAV_BLOCK + lane;
-    if (g >= n_leaf) return;
-    const int k = find_seg(leaf_off, ninst, g);
-    const InstDev in = inst[k];
-    const Box<T> bx = make_box<T>(in);
-    T scale = fmax(fmax(fabs(bx.lo[0]), fabs(bx.hi[0])), fmax(fabs(bx.lo[1]), fabs(bx.hi[1])));
-    scale = fmax(scale, fmax(fabs(bx.lo[2]), fabs(bx.hi[2])));
-    scale = fmax(scale, fmax(bx.L[0], fmax(bx.L[1], bx.L[2])));
-    const T eps_abs = Inflate<T>::abs * scale;
-    const vec4<T> ql = blo[n_internal + g], qh = bhi[n_internal + g];
-    u64 out = FILL ? off[g] : 0;
-    const u64 out_end = FILL ? off[g + 1] : 0;
-    const T onep = T(1) + Inflate<T>::rel;
-    u32 count = 0;
+    const i64 g0 = (i64)blockIdx.x * TRAV_BLOCK + lane;
+    const bool live = g0 < ngroups;
+    const i64 g = live ? g0 : ngroups - 1;
+    const int k = gm.inst_of(g);
+    const Box<T> bx = make_box<T>(inst[k]);
+    const T eps_abs = abs_inflation(bx);
+    const vec4<T> ql = glo[g], qh = ghi[g];
+    u32* ul = uleaf + g * cap;
+    u32* us = uslot + g * cap;
+    u32 count = 0, slots = 0;
     int sp = 0;
-    stack[sp++][lane] = root[k];
+    if (live) stack[sp++][lane] = root[k];
+    bool stack_over = false;
     while (sp > 0) {
         const u32 node = stack[--sp][lane];
-        const vec4<T> l = blo[node], h = bhi[node];
-        const T r = add_rn(mul_rn(mul_rn(rk, fmax(ql.w, l.w)), onep), eps_abs);
-        const bool hit = gap1<T>(ql.x, qh.x, l.x, h.x, bx.L[0], bx.periodic) <= r &&
-                         gap1<T>(ql.y, qh.y, l.y, h.y, bx.L[1], bx.periodic) <= r &&
-                         gap1<T>(ql.z, qh.z, l.z, h.z, bx.L[2], bx.periodic) <= r;
-        if (!hit) continue;
+        if (!box_hit<T>(ql, qh, blo[node], bhi[node], rk, eps_abs, bx)) continue;
         if (node >= n_internal) {
-            if (FILL) {
-                if (out < out_end) list[out++] = (u32)(node - n_internal);
-                else { atomicOr(overflow, 2u); break; }
-            } else {
-                ++count;
-            }
+            const u32 leaf = (u32)(node - n_internal);
+            if (count < cap) { ul[count] = leaf; us[count] = slots; }
+            ++count;
+            slots += id[leaf + 1] - id[leaf];
         } else {
-            if (sp + 2 > STACK) { atomicOr(overflow, 1u); break; }
+            if (sp + 2 > STACK) { stack_over = true; break; }
             stack[sp++][lane] = child[2 * node + 1];
             stack[sp++][lane] = child[2 * node];
         }
     }
-    if (!FILL) cnt[g] = count;
+    if (live) {
+        ucnt[g] = count;
+        ustot[g] = slots;
+    }
+    u32 f = stack_over ? 1u : 0u;
+    if (count > cap) f |= 2u;
+    if (slots > 0xffffu) f |= 8u;
+    if (f) atomicOr(&flags[0], f);
+    // largest leaf count (for the capacity of the next build)
+    const u32 wmax = wave_max(count);
+    if (__lane_id() == 0 && wmax > __hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(&flags[1], wmax);
 }
 
-template <class T, bool FILL>
-__global__ void __launch_bounds__(256)
-k_part_neigh(const vec4<T>* __restrict__ posh, const u32* __restrict__ xscan,
-             const u32* __restrict__ id, const u64* __restrict__ loff, const u32* __restrict__ llist,
-             i64 n, const i64* __restrict__ p_off, int ninst, const InstDev* __restrict__ inst,
-             T rkc, u32* __restrict__ cnt, const u64* __restrict__ noff, u32* __restrict__ nlist,
-             u32* __restrict__ overflow)
+// Stage 2: per particle, its neighbours among the group's union (Alg. 5 with
+// the object-object criterion), as ascending 16-bit slots in ELL layout
+// nlist[(g * capj + j) * GROUP + lane].  ncnt[a] = number of neighbours.
+template <class T>
+__global__ void __launch_bounds__(GROUP)
+k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
+              const vec4<T>* __restrict__ bhi, const u32* __restrict__ id, i64 n_internal,
+              const GroupMap gm, const InstDev* __restrict__ inst, T rk, T rkc, i64 cap,
+              const u32* __restrict__ uleaf, const u32* __restrict__ uslot,
+              const u32* __restrict__ ucnt, i64 capj, u16* __restrict__ nlist,
+              u32* __restrict__ ncnt, u32* __restrict__ flags)
 {
-    const i64 a = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= n) return;
-    const int k = find_seg(p_off, ninst, a);
+    __shared__ u32 s_b0[LCHUNK];
+    __shared__ u32 s_b1[LCHUNK];
+    __shared__ u32 s_slot[LCHUNK];
+    __shared__ vec4<T> s_lo[LCHUNK];
+    __shared__ vec4<T> s_hi[LCHUNK];
+    const i64 g = blockIdx.x;
+    i64 beg, end;
+    int k;
+    gm.range(g, beg, end, k);
     const Box<T> bx = make_box<T>(inst[k]);
-    const u32 L = xscan[a + 1] - 1u;
-    const vec4<T> pa = posh[a];
-    u64 out = FILL ? noff[a] : 0;
-    const u64 out_end = FILL ? noff[a + 1] : 0;
+    const T eps_abs = abs_inflation(bx);
+    const i64 a = beg + threadIdx.x;
+    const bool live = a < end;
+    const vec4<T> pa = posh[live ? a : beg];
+    const vec4<T> pl = mk4<T>(pa.x, pa.y, pa.z, pa.w);   // point box
+    const u32 nu = min((u32)cap, ucnt[g]);
+    u16* out = nlist + (u64)g * (u64)capj * GROUP + threadIdx.x;
     u32 c = 0;
-    const u64 j1 = loff[L + 1];
-    for (u64 j = loff[L]; j < j1; ++j) {
-        const u32 M = llist[j];
-        const u32 b1 = id[M + 1];
-        for (u32 b = id[M]; b < b1; ++b) {
-            const vec4<T> pb = posh[b];
-            if (cache_crit<T>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w, bx, rkc)) {
-                if (FILL) {
-                    if (out < out_end) nlist[out++] = b;
-                    else atomicOr(overflow, 4u);
-                } else {
+    for (u32 c0 = 0; c0 < nu; c0 += LCHUNK) {
+        const u32 c1 = min(nu, c0 + LCHUNK);
+        __syncthreads();
+        for (u32 j = c0 + threadIdx.x; j < c1; j += GROUP) {
+            const u32 leaf = uleaf[g * cap + j];
+            s_b0[j - c0] = id[leaf];
+            s_b1[j - c0] = id[leaf + 1];
+            s_slot[j - c0] = uslot[g * cap + j];
+            s_lo[j - c0] = blo[n_internal + leaf];
+            s_hi[j - c0] = bhi[n_internal + leaf];
+        }
+        __syncthreads();
+        if (!live) continue;
+        for (u32 j = 0; j < c1 - c0; ++j) {
+            if (!box_hit<T>(pl, pl, s_lo[j], s_hi[j], rk, eps_abs, bx)) continue;
+            const u32 b0 = s_b0[j], b1 = s_b1[j], sl = s_slot[j];
+            for (u32 b = b0; b < b1; ++b) {
+                const vec4<T> pb = posh[b];
+                if (cache_crit<T>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w, bx, rkc)) {
+                    if (c < capj) out[(u64)c * GROUP] = (u16)(sl + (b - b0));
                     ++c;
                 }
             }
         }
     }
-    if (!FILL) cnt[a] = c;
+    if (live) ncnt[a] = c;
+    const u32 wmax = wave_max(live ? c : 0u);
+    if (__lane_id() == 0) {
+        if (wmax > capj) atomicOr(&flags[0], 4u);
+        if (wmax > __hip_atomic_load(&flags[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&flags[2], wmax);
+    }
+}
+
+// Convert the cache to global key-order indices (export / tests only):
+// list[off[a] + j] = key slot of the j-th neighbour of a.
+__global__ void __launch_bounds__(GROUP)
+k_cache_to_global(const u32* __restrict__ id, const GroupMap gm, i64 cap,
+                  const u32* __restrict__ uleaf, const u32* __restrict__ uslot,
+                  const u32* __restrict__ ucnt, i64 capj, const u16* __restrict__ nlist,
+                  const u32* __restrict__ ncnt, const u64* __restrict__ off, u32* __restrict__ list)
+{
+    const i64 g = blockIdx.x;
+    i64 beg, end;
+    int k;
+    gm.range(g, beg, end, k);
+    const i64 a = beg + threadIdx.x;
+    if (a >= end) return;
+    const u32 nu = min((u32)cap, ucnt[g]);
+    const u32* sl = uslot + g * cap;
+    const u32* ul = uleaf + g * cap;
+    const u32 c = ncnt[a];
+    for (u32 j = 0; j < c; ++j) {
+        const u32 s = nlist[((u64)g * capj + j) * GROUP + threadIdx.x];
+        u32 lo = 0, hi = nu - 1;       // last leaf whose start slot <= s
+        while (lo < hi) {
+            const u32 mid = (lo + hi + 1) >> 1;
+            if (sl[mid] <= s) lo = mid; else hi = mid - 1;
+        }
+        list[off[a] + j] = id[ul[lo]] + (s - sl[lo]);
+    }
 }
 
 template <class T>
-void launch_leaf_neigh(bool fill, const vec4<T>* blo, const vec4<T>* bhi, const u32* child,
-                       i64 n_internal, i64 n_leaf, const i64* leaf_off, int ninst, const u32* root,
-                       const InstDev* inst, double rk, const u64* off, u32* cnt, u32* list,
-                       u32* overflow, hipStream_t st)
+void launch_group_boxes(const vec4<T>* posh, const GroupMap& gm, i64 ngroups, vec4<T>* glo,
+                        vec4<T>* ghi, hipStream_t st)
 {
-    if (n_leaf <= 0) return;
-    const dim3 grid((unsigned)((n_leaf + TRAV_BLOCK - 1) / TRAV_BLOCK));
-    if (fill)
-        hipLaunchKernelGGL((k_leaf_neigh<T, true>), grid, dim3(TRAV_BLOCK), 0, st, blo, bhi, child,
-                           n_internal, n_leaf, leaf_off, ninst, root, inst, (T)rk, off, cnt, list,
-                           overflow);
-    else
-        hipLaunchKernelGGL((k_leaf_neigh<T, false>), grid, dim3(TRAV_BLOCK), 0, st, blo, bhi, child,
-                           n_internal, n_leaf, leaf_off, ninst, root, inst, (T)rk, off, cnt, list,
-                           overflow);
+    if (ngroups <= 0) return;
+    hipLaunchKernelGGL((k_group_boxes<T>), dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, gm,
+                       glo, ghi);
 }
 
 template <class T>
-void launch_part_neigh(bool fill, const vec4<T>* posh, const u32* xscan, const u32* id,
-                       const u64* loff, const u32* llist, i64 n, const i64* p_off, int ninst,
-                       const InstDev* inst, double rkc, u32* cnt, const u64* noff, u32* nlist,
-                       u32* overflow, hipStream_t st)
+void launch_group_leaves(const vec4<T>* blo, const vec4<T>* bhi, const u32* child, const u32* id,
+                         i64 n_internal, const vec4<T>* glo, const vec4<T>* ghi, i64 ngroups,
+                         const GroupMap& gm, const u32* root, const InstDev* inst, double rk,
+                         i64 cap, u32* uleaf, u32* uslot, u32* ucnt, u32* ustot, u32* flags,
+                         hipStream_t st)
 {
-    if (n <= 0) return;
-    const dim3 grid((unsigned)((n + 255) / 256));
-    if (fill)
-        hipLaunchKernelGGL((k_part_neigh<T, true>), grid, dim3(256), 0, st, posh, xscan, id, loff,
-                           llist, n, p_off, ninst, inst, (T)rkc, cnt, noff, nlist, overflow);
-    else
-        hipLaunchKernelGGL((k_part_neigh<T, false>), grid, dim3(256), 0, st, posh, xscan, id, loff,
-                           llist, n, p_off, ninst, inst, (T)rkc, cnt, noff, nlist, overflow);
+    if (ngroups <= 0) return;
+    const dim3 grid((unsigned)((ngroups + TRAV_BLOCK - 1) / TRAV_BLOCK));
+    hipLaunchKernelGGL((k_group_leaves<T>), grid, dim3(TRAV_BLOCK), 0, st, blo, bhi, child, id,
+                       n_internal, glo, ghi, ngroups, gm, root, inst, (T)rk, cap, uleaf, uslot,
+                       ucnt, ustot, flags);
 }
 
-#define INST(T)                                                                                 \
-    template void launch_leaf_neigh<T>(bool, const vec4<T>*, const vec4<T>*, const u32*, i64,  \
-                                       i64, const i64*, int, const u32*, const InstDev*, double, \
-                                       const u64*, u32*, u32*, u32*, hipStream_t);              \
-    template void launch_part_neigh<T>(bool, const vec4<T>*, const u32*, const u32*,            \
-                                       const u64*, const u32*, i64, const i64*, int,            \
-                                       const InstDev*, double, u32*, const u64*, u32*, u32*,    \
-                                       hipStream_t);
+template <class T>
+void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* bhi, const u32* id,
+                        i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
+                        double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
+                        const u32* ucnt, i64 capj, u16* nlist, u32* ncnt, u32* flags,
+                        hipStream_t st)
+{
+    if (ngroups <= 0) return;
+    hipLaunchKernelGGL((k_group_cache<T>), dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, blo,
+                       bhi, id, n_internal, gm, inst, (T)rk, (T)rkc, cap, uleaf, uslot, ucnt, capj,
+                       nlist, ncnt, flags);
+}
+
+void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
+                            const u32* uleaf, const u32* uslot, const u32* ucnt, i64 capj,
+                            const u16* nlist, const u32* ncnt, const u64* off, u32* list,
+                            hipStream_t st)
+{
+    if (ngroups <= 0) return;
+    hipLaunchKernelGGL(k_cache_to_global, dim3((unsigned)ngroups), dim3(GROUP), 0, st, id, gm, cap,
+                       uleaf, uslot, ucnt, capj, nlist, ncnt, off, list);
+}
+
+#define INST(T)                                                                                   \
+    template void launch_group_boxes<T>(const vec4<T>*, const GroupMap&, i64, vec4<T>*, vec4<T>*, \
+                                        hipStream_t);                                             \
+    template void launch_group_leaves<T>(const vec4<T>*, const vec4<T>*, const u32*, const u32*,  \
+                                         i64, const vec4<T>*, const vec4<T>*, i64,                \
+                                         const GroupMap&, const u32*, const InstDev*, double,     \
+                                         i64, u32*, u32*, u32*, u32*, u32*, hipStream_t);         \
+    template void launch_group_cache<T>(const vec4<T>*, const vec4<T>*, const vec4<T>*,           \
+                                        const u32*, i64, const GroupMap&, i64, const InstDev*,    \
+                                        double, double, i64, const u32*, const u32*, const u32*,  \
+                                        i64, u16*, u32*, u32*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

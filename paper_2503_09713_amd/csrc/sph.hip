@@ -24,12 +24,11 @@ __global__ void k_stat_reset(InstStat* s, int ninst)
     InstStat z;
     z.dt_bits = 0x7f800000u;   // +inf
     z.dvmax_bits = 0u;
-    z.dv2_sum = 0.0;
-    z.v2_sum = 0.0;
     z.n_exceed = 0u;
     z.n_noconv = 0u;
     z.max_iter_seen = 0u;
-    z.pad = 0u;
+    z.pad[0] = z.pad[1] = z.pad[2] = 0u;
+    for (int i = 0; i < STAT_SLOTS; ++i) { z.dv2_part[i] = 0.0; z.v2_part[i] = 0.0; }
     s[k] = z;
 }
 
@@ -49,19 +48,60 @@ template <class T> __global__ void k_copy_h(const vec4<T>* __restrict__ posh, T*
     if (i < n) hc[i] = posh[i].w;
 }
 
-// Wave-aggregated per-instance counter increment.
-__device__ inline void wave_count(u32* dst_base_stride0, bool pred, int k, size_t stride_bytes)
+
+// ---------------------------------------------------------------------------
+// Staging of a group's candidate union into LDS: slots [c0, c1) of the union
+// (its leaves' particles in ascending key order) are copied from the
+// key-order arrays.  One thread per union leaf.
+// ---------------------------------------------------------------------------
+template <class T, int NF>
+__device__ inline void stage_union(const vec4<T>* const* src, vec4<T>* const* dst, const u32* id,
+                                   const u32* ul, const u32* us, u32 nu, u32 c0, u32 c1)
 {
-    const u64 m = __ballot(pred);
-    if (!m) return;
-    const int k0 = __shfl(k, __ffsll((unsigned long long)m) - 1, WAVE);
-    const bool uniform = __ballot(pred && k != k0) == 0;
-    if (uniform) {
-        if (__lane_id() == __ffsll((unsigned long long)m) - 1)
-            atomicAdd((u32*)((char*)dst_base_stride0 + stride_bytes * k0), (u32)__popcll(m));
-    } else if (pred) {
-        atomicAdd((u32*)((char*)dst_base_stride0 + stride_bytes * k), 1u);
+    for (u32 j = threadIdx.x; j < nu; j += GROUP) {
+        const u32 s0 = us[j];
+        const u32 leaf = ul[j];
+        const u32 b0 = id[leaf], sz = id[leaf + 1] - b0;
+        const u32 lo = s0 > c0 ? s0 : c0;
+        const u32 hi = (s0 + sz) < c1 ? (s0 + sz) : c1;
+        for (u32 s = lo; s < hi; ++s) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) dst[f][s - c0] = src[f][b0 + (s - s0)];
+        }
     }
+}
+
+// Block-wide reduction helpers for per-instance statistics: the block's
+// lanes usually share one instance, then a single atomic per block is done
+// (and min/max atomics only when they can change the stored value).
+__device__ inline bool block_uniform(int k, int* s_k)
+{
+    if (threadIdx.x == 0) *s_k = k;
+    __syncthreads();
+    const int k0 = *s_k;
+    return __syncthreads_and(k == k0) != 0;
+}
+
+template <class T> __device__ inline T block_max(T v, T* lds)
+{
+    return block_reduce<GROUP>(v, lds, [](T a, T b) { return a > b ? a : b; });
+}
+template <class T> __device__ inline T block_min(T v, T* lds)
+{
+    return block_reduce<GROUP>(v, lds, [](T a, T b) { return a < b ? a : b; });
+}
+template <class T> __device__ inline T block_sum(T v, T* lds)
+{
+    return block_reduce<GROUP>(v, lds, [](T a, T b) { return a + b; });
+}
+
+__device__ inline void atomic_max_if(u32* p, u32 v)
+{
+    if (v > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, v);
+}
+__device__ inline void atomic_min_if(u32* p, u32 v)
+{
+    if (v < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(p, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -76,75 +116,104 @@ __device__ inline void wave_count(u32* dst_base_stride0, bool pred, int k, size_
 // Final values: rho = m (hfact/h)^3 (App. G uses rho(h), not the sum) and
 // Omega = 1 + h/(3 rho) sum_b m dW/dh (Eq. sphomega with dh/drho = -h/(3 rho)),
 // both taken at the last h where the sums were evaluated.
+// One workgroup per group: the union's positions are staged in LDS once and
+// every Newton pass reads neighbours from there.
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void __launch_bounds__(256)
+template <class T, int CH>
+__global__ void __launch_bounds__(GROUP)
 k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restrict__ hc,
-          const vec4<T>* __restrict__ velu, const u64* __restrict__ noff,
-          const u32* __restrict__ nlist, i64 n, const i64* __restrict__ p_off, int ninst,
-          const InstDev* __restrict__ inst, SphParams P, T* __restrict__ omega,
+          const vec4<T>* __restrict__ velu, const u32* __restrict__ id, const GroupMap gm,
+          const InstDev* __restrict__ inst, SphParams P, CacheView cv, T* __restrict__ omega,
           vec4<T>* __restrict__ thermo, u8* __restrict__ status, InstStat* __restrict__ stat)
 {
-    const i64 a = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = a < n;
-    const i64 ai = live ? a : n - 1;
-    const int k = find_seg(p_off, ninst, ai);
+    __shared__ vec4<T> s_pos[CH];
+    __shared__ u32 s_red[GROUP / WAVE];
+    __shared__ int s_k;
+    const i64 g = blockIdx.x;
+    i64 beg, end;
+    int k;
+    gm.range(g, beg, end, k);
     const InstDev in = inst[k];
     const Box<T> bx = make_box<T>(in);
+    const i64 a = beg + threadIdx.x;
+    const bool live = a < end;
+    const i64 ai = live ? a : beg;
     const vec4<T> pa = posh[ai];
     const T m = (T)in.mass, hfact = (T)P.hfact, lam = (T)P.lambda, chi = (T)P.chi;
     const T h_n = hn[ai], h_c = hc[ai];
-    const u64 j0 = noff[ai], j1 = noff[ai + 1];
+    const u32 cnt = live ? cv.ncnt[a] : 0u;
+    const u32 nu = min((u32)cv.cap, cv.ucnt[g]);
+    const u32 S = cv.ustot[g];
+    const u32 nch = (S + CH - 1) / CH;
+    const u32* ul = cv.uleaf + g * cv.cap;
+    const u32* us = cv.uslot + g * cv.cap;
+    const u16* my = cv.nlist + (u64)g * (u64)cv.capj * GROUP + threadIdx.x;
+    const vec4<T>* src[1] = { posh };
+    vec4<T>* dst[1] = { s_pos };
     T h = pa.w, h_eval = pa.w, dsum = T(0);
     int st = 1;   // 0 converged, 1 not converged, 2 chi exceeded
-    int it = 0;
-    for (; it < P.max_iter; ++it) {
+    int iters = 0;
+    bool active = live;
+    for (int it = 0; it < P.max_iter; ++it) {
         const T hinv = T(1) / h;
         const T h2x4 = T(4) * h * h;
         T s = T(0), ds = T(0);
-        for (u64 j = j0; j < j1; ++j) {
-            const vec4<T> pb = posh[nlist[j]];
-            const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
-            const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
-            const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
-            const T r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < h2x4) {
-                const T q = sqrt(r2) * hinv;
-                T f, df;
-                m4<T>(q, f, df);
-                s += f;
-                ds -= T(3) * f + q * df;
+        u32 j = 0;
+        for (u32 ch = 0; ch < nch; ++ch) {
+            const u32 c0 = ch * CH, c1 = min(S, c0 + CH);
+            if (nch > 1 || it == 0) {
+                __syncthreads();
+                stage_union<T, 1>(src, dst, id, ul, us, nu, c0, c1);
+                __syncthreads();
+            }
+            if (!active) continue;
+            for (; j < cnt; ++j) {
+                const u32 slot = my[(u64)j * GROUP];
+                if (slot >= c1) break;
+                const vec4<T> pb = s_pos[slot - c0];
+                const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
+                const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
+                const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 < h2x4) {
+                    const T q = sqrt(r2) * hinv;
+                    T f, df;
+                    m4<T>(q, f, df);
+                    s += f;
+                    ds -= T(3) * f + q * df;
+                }
             }
         }
-        const T hinv3 = hinv * hinv * hinv;
-        const T rho_sum = m * s * hinv3 * inv_pi<T>();
-        const T dsum_h = m * ds * hinv3 * hinv * inv_pi<T>();
-        const T hf = hfact * hinv;
-        const T rho_h = m * hf * hf * hf;
-        const T ddrho = dsum_h + T(3) * rho_h * hinv;
-        T hnew = h - (rho_sum - rho_h) / ddrho;
-        if (hnew > h * lam) hnew = h * lam;
-        else if (hnew < h / lam) hnew = h / lam;
-        const T eps = fabs(hnew - h) / h_n;
-        h_eval = h;
-        dsum = dsum_h;
-        if (hnew > h_c * chi) { h = h_c * chi; st = 2; ++it; break; }
-        h = hnew;
-        if (eps < (T)P.eps_h) { st = 0; ++it; break; }
-    }
-    if (!live) st = 0;
-    // per-instance outcome counters
-    wave_count(&stat[0].n_exceed, live && st == 2, k, sizeof(InstStat));
-    wave_count(&stat[0].n_noconv, live && st == 1, k, sizeof(InstStat));
-    {
-        const int k0 = __shfl(k, 0, WAVE);
-        const u32 itw = live ? (u32)it : 0u;
-        if (__ballot(k != k0) == 0) {
-            const u32 mx = wave_max(itw);
-            if (__lane_id() == 0) atomicMax(&stat[k0].max_iter_seen, mx);
-        } else if (live) {
-            atomicMax(&stat[k].max_iter_seen, itw);
+        if (active) {
+            const T hinv3 = hinv * hinv * hinv;
+            const T rho_sum = m * s * hinv3 * inv_pi<T>();
+            const T dsum_h = m * ds * hinv3 * hinv * inv_pi<T>();
+            const T hf = hfact * hinv;
+            const T rho_h = m * hf * hf * hf;
+            const T ddrho = dsum_h + T(3) * rho_h * hinv;
+            T hnew = h - (rho_sum - rho_h) / ddrho;
+            if (hnew > h * lam) hnew = h * lam;
+            else if (hnew < h / lam) hnew = h / lam;
+            const T eps = fabs(hnew - h) / h_n;
+            h_eval = h;
+            dsum = dsum_h;
+            iters = it + 1;
+            if (hnew > h_c * chi) { h = h_c * chi; st = 2; active = false; }
+            else {
+                h = hnew;
+                if (eps < (T)P.eps_h) { st = 0; active = false; }
+            }
         }
+        if (!__syncthreads_or(active)) break;
+    }
+    // per-instance outcome counters (rare events: per-lane atomics)
+    if (live && st == 2) atomicAdd(&stat[k].n_exceed, 1u);
+    if (live && st == 1) atomicAdd(&stat[k].n_noconv, 1u);
+    if (block_uniform(k, &s_k)) {
+        const u32 mx = block_max<u32>(live ? (u32)iters : 0u, s_red);
+        if (threadIdx.x == 0) atomic_max_if(&stat[k].max_iter_seen, mx);
+    } else if (live) {
+        atomic_max_if(&stat[k].max_iter_seen, (u32)iters);
     }
     if (!live) return;
     const T hf = hfact / h_eval;
@@ -157,9 +226,9 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
     status[a] = (u8)st;
     if (thermo) {
         const T u = velu ? velu[a].w : T(0);
-        const T g = (T)P.gamma;
-        const T Pr = (g - T(1)) * rho * u;
-        const T cs = sqrt(g * (g - T(1)) * u);
+        const T gm1 = (T)P.gamma - T(1);
+        const T Pr = gm1 * rho * u;
+        const T cs = sqrt((T)P.gamma * gm1 * u);
         const T B = T(1) / (rho * om);
         thermo[a] = mk4<T>(Pr * B / rho, B, cs, Pr);
     }
@@ -176,21 +245,30 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
 // vsig_u = sqrt(|P_a - P_b| / ((rho_a+rho_b)/2)).
 // The timestep signal speed is the largest vsig_a over the pairs (floor c_a);
 // dt_a = min(C_cour h/vsig, C_force sqrt(h/|a|)) is min-reduced per instance.
+// One workgroup per group: the union's position, velocity and pressure terms
+// are staged in LDS.
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void __launch_bounds__(256)
+template <class T, int CH>
+__global__ void __launch_bounds__(GROUP)
 k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
-        const vec4<T>* __restrict__ thermo, const u64* __restrict__ noff,
-        const u32* __restrict__ nlist, i64 n, const i64* __restrict__ p_off, int ninst,
-        const InstDev* __restrict__ inst, SphParams P, vec4<T>* __restrict__ acc,
+        const vec4<T>* __restrict__ thermo, const u32* __restrict__ id, const GroupMap gm,
+        const InstDev* __restrict__ inst, SphParams P, CacheView cv, vec4<T>* __restrict__ acc,
         T* __restrict__ vsig_out, InstStat* __restrict__ stat)
 {
-    const i64 a = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = a < n;
-    const i64 ai = live ? a : n - 1;
-    const int k = find_seg(p_off, ninst, ai);
+    __shared__ vec4<T> s_pos[CH];
+    __shared__ vec4<T> s_vel[CH];
+    __shared__ vec4<T> s_thm[CH];
+    __shared__ float s_red[GROUP / WAVE];
+    __shared__ int s_k;
+    const i64 g = blockIdx.x;
+    i64 beg, end;
+    int k;
+    gm.range(g, beg, end, k);
     const InstDev in = inst[k];
     const Box<T> bx = make_box<T>(in);
+    const i64 a = beg + threadIdx.x;
+    const bool live = a < end;
+    const i64 ai = live ? a : beg;
     const T m = (T)in.mass, hfact = (T)P.hfact;
     const T alpha = (T)P.alpha, beta = (T)P.beta, beta_u = (T)P.beta_u;
     const vec4<T> pa = posh[ai], va = velu[ai], ta = thermo[ai];
@@ -199,41 +277,58 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     const T hfa = hfact * hia;
     const T rhoa = m * hfa * hfa * hfa;
     const T Aa = ta.x, Ba = ta.y, ca = ta.z, Pa = ta.w;
+    const u32 cnt = live ? cv.ncnt[a] : 0u;
+    const u32 nu = min((u32)cv.cap, cv.ucnt[g]);
+    const u32 S = cv.ustot[g];
+    const u32 nch = (S + CH - 1) / CH;
+    const u32* ul = cv.uleaf + g * cv.cap;
+    const u32* us = cv.uslot + g * cv.cap;
+    const u16* my = cv.nlist + (u64)g * (u64)cv.capj * GROUP + threadIdx.x;
+    const vec4<T>* src[3] = { posh, velu, thermo };
+    vec4<T>* dst[3] = { s_pos, s_vel, s_thm };
     T ax = T(0), ay = T(0), az = T(0), du = T(0), lam = T(0), vmax = ca;
-    const u64 j0 = noff[ai], j1 = noff[ai + 1];
-    for (u64 j = j0; j < j1; ++j) {
-        const u32 b = nlist[j];
-        const vec4<T> pb = posh[b];
-        const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
-        const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
-        const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        const T hb = pb.w;
-        const T hm = ha > hb ? ha : hb;
-        if (!(r2 > T(0)) || !(r2 < T(4) * hm * hm)) continue;
-        const vec4<T> vb = velu[b], tb = thermo[b];
-        const T r = sqrt(r2), rinv = T(1) / r;
-        const T ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-        const T w = (va.x - vb.x) * ex + (va.y - vb.y) * ey + (va.z - vb.z) * ez;
-        const T hib = T(1) / hb;
-        const T Fa = m4_df<T>(r * hia) * hia4;
-        const T Fb = m4_df<T>(r * hib) * (hib * hib * hib * hib * inv_pi<T>());
-        const T aw = fabs(w);
-        const T vsa = alpha * ca + beta * aw;
-        const T vsb = alpha * tb.z + beta * aw;
-        const T wn = w < T(0) ? w : T(0);
-        const T ka = (Aa - T(0.5) * vsa * wn * Ba) * Fa;
-        const T kb = (tb.x - T(0.5) * vsb * wn * tb.y) * Fb;
-        const T fab = m * (ka + kb);
-        ax -= fab * ex;
-        ay -= fab * ey;
-        az -= fab * ez;
-        du += m * ka * w;
-        const T hfb = hfact * hib;
-        const T rhob = m * hfb * hfb * hfb;
-        const T vsu = sqrt(fabs(Pa - tb.w) / (T(0.5) * (rhoa + rhob)));
-        lam += m * beta_u * vsu * (va.w - vb.w) * T(0.5) * (Fa * Ba + Fb * tb.y);
-        vmax = vsa > vmax ? vsa : vmax;
+    u32 j = 0;
+    for (u32 ch = 0; ch < nch; ++ch) {
+        const u32 c0 = ch * CH, c1 = min(S, c0 + CH);
+        __syncthreads();
+        stage_union<T, 3>(src, dst, id, ul, us, nu, c0, c1);
+        __syncthreads();
+        for (; j < cnt; ++j) {
+            const u32 slot = my[(u64)j * GROUP];
+            if (slot >= c1) break;
+            const u32 sl = slot - c0;
+            const vec4<T> pb = s_pos[sl];
+            const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
+            const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
+            const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            const T hb = pb.w;
+            const T hm = ha > hb ? ha : hb;
+            if (!(r2 > T(0)) || !(r2 < T(4) * hm * hm)) continue;
+            const vec4<T> vb = s_vel[sl], tb = s_thm[sl];
+            const T r = sqrt(r2), rinv = T(1) / r;
+            const T ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+            const T w = (va.x - vb.x) * ex + (va.y - vb.y) * ey + (va.z - vb.z) * ez;
+            const T hib = T(1) / hb;
+            const T Fa = m4_df<T>(r * hia) * hia4;
+            const T Fb = m4_df<T>(r * hib) * (hib * hib * hib * hib * inv_pi<T>());
+            const T aw = fabs(w);
+            const T vsa = alpha * ca + beta * aw;
+            const T vsb = alpha * tb.z + beta * aw;
+            const T wn = w < T(0) ? w : T(0);
+            const T ka = (Aa - T(0.5) * vsa * wn * Ba) * Fa;
+            const T kb = (tb.x - T(0.5) * vsb * wn * tb.y) * Fb;
+            const T fab = m * (ka + kb);
+            ax -= fab * ex;
+            ay -= fab * ey;
+            az -= fab * ez;
+            du += m * ka * w;
+            const T hfb = hfact * hib;
+            const T rhob = m * hfb * hfb * hfb;
+            const T vsu = sqrt(fabs(Pa - tb.w) / (T(0.5) * (rhoa + rhob)));
+            lam += m * beta_u * vsu * (va.w - vb.w) * T(0.5) * (Fa * Ba + Fb * tb.y);
+            vmax = vsa > vmax ? vsa : vmax;
+        }
     }
     float dta = __int_as_float(0x7f800000);
     if (live) {
@@ -244,14 +339,11 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         const T t2 = am > T(0) ? (T)P.c_force * sqrt(ha / am) : T(INFINITY);
         dta = (float)(t1 < t2 ? t1 : t2);
     }
-    // per-instance min of dt_a
-    const int k0 = __shfl(k, 0, WAVE);
-    if (__ballot(k != k0) == 0) {
-        const float wmin = wave_min(dta);
-        if (__lane_id() == 0 && wmin < __int_as_float(0x7f800000))
-            atomic_min_posf(&stat[k0].dt_bits, wmin);
+    if (block_uniform(k, &s_k)) {
+        const float bmin = block_min<float>(dta, s_red);
+        if (threadIdx.x == 0) atomic_min_if(&stat[k].dt_bits, __float_as_uint(bmin));
     } else if (live) {
-        atomic_min_posf(&stat[k].dt_bits, dta);
+        atomic_min_if(&stat[k].dt_bits, __float_as_uint(dta));
     }
 }
 
@@ -262,7 +354,7 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
 // max|dv|, sum|dv|^2 and sum|v|^2 per instance for the reversibility check.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(GROUP)
 k_correct(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
           const vec4<T>* __restrict__ vhalf, const vec4<T>* __restrict__ acc,
           const T* __restrict__ omega, const u32* __restrict__ pid, i64 n,
@@ -270,6 +362,9 @@ k_correct(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
           const double* __restrict__ dt_inst, double hfact, OutPtrs<T> o,
           InstStat* __restrict__ stat)
 {
+    __shared__ double s_red[GROUP / WAVE];
+    __shared__ float s_redf[GROUP / WAVE];
+    __shared__ int s_k;
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = i < n;
     const i64 ii = live ? i : n - 1;
@@ -295,19 +390,20 @@ k_correct(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         dv = (float)sqrt(dv2);
         v2 = (double)vx * vx + (double)vy * vy + (double)vz * vz;
     }
-    const int k0 = __shfl(k, 0, WAVE);
-    if (__ballot(k != k0) == 0) {
-        const float m = wave_max(dv);
-        const double s1 = wave_sum(dv2), s2 = wave_sum(v2);
-        if (__lane_id() == 0) {
-            atomic_max_posf(&stat[k0].dvmax_bits, m);
-            atomicAdd(&stat[k0].dv2_sum, s1);
-            atomicAdd(&stat[k0].v2_sum, s2);
+    const int slot = blockIdx.x % STAT_SLOTS;
+    if (block_uniform(k, &s_k)) {
+        const float mx = block_max<float>(dv, s_redf);
+        const double s1 = block_sum<double>(dv2, s_red);
+        const double s2 = block_sum<double>(v2, s_red);
+        if (threadIdx.x == 0) {
+            atomic_max_if(&stat[k].dvmax_bits, __float_as_uint(mx));
+            atomicAdd(&stat[k].dv2_part[slot], s1);
+            atomicAdd(&stat[k].v2_part[slot], s2);
         }
     } else if (live) {
-        atomic_max_posf(&stat[k].dvmax_bits, dv);
-        atomicAdd(&stat[k].dv2_sum, dv2);
-        atomicAdd(&stat[k].v2_sum, v2);
+        atomic_max_if(&stat[k].dvmax_bits, __float_as_uint(dv));
+        atomicAdd(&stat[k].dv2_part[slot], dv2);
+        atomicAdd(&stat[k].v2_part[slot], v2);
     }
 }
 
@@ -393,24 +489,37 @@ template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStre
     if (n > 0) hipLaunchKernelGGL((k_copy_h<T>), grid_for(n, 256), dim3(256), 0, st, posh, hc, n);
 }
 
+constexpr int DENS_CH_F = 2048, DENS_CH_D = 1024;
+constexpr int FORCE_CH_F = 1024, FORCE_CH_D = 512;
+
 template <class T>
-void launch_density(const SortedPtrs<T>& s, const u64* noff, const u32* nlist, i64 n,
-                    const i64* p_off, int ninst, const InstDev* inst, const SphParams& P,
-                    T* omega, vec4<T>* thermo, u8* status, InstStat* stat, hipStream_t st)
+void launch_density(const SortedPtrs<T>& s, const u32* id, const GroupMap& gm, i64 ngroups,
+                    const InstDev* inst, const SphParams& P, const CacheView& cv, T* omega,
+                    vec4<T>* thermo, u8* status, InstStat* stat, hipStream_t st)
 {
-    if (n <= 0) return;
-    hipLaunchKernelGGL((k_density<T>), grid_for(n, 256), dim3(256), 0, st, s.posh, s.hn, s.hcache,
-                       s.velu, noff, nlist, n, p_off, ninst, inst, P, omega, thermo, status, stat);
+    if (ngroups <= 0) return;
+    if (sizeof(T) == 4)
+        hipLaunchKernelGGL((k_density<T, DENS_CH_F>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
+                           s.posh, s.hn, s.hcache, s.velu, id, gm, inst, P, cv, omega, thermo,
+                           status, stat);
+    else
+        hipLaunchKernelGGL((k_density<T, DENS_CH_D>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
+                           s.posh, s.hn, s.hcache, s.velu, id, gm, inst, P, cv, omega, thermo,
+                           status, stat);
 }
 
 template <class T>
-void launch_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u64* noff, const u32* nlist,
-                  i64 n, const i64* p_off, int ninst, const InstDev* inst, const SphParams& P,
+void launch_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id, const GroupMap& gm,
+                  i64 ngroups, const InstDev* inst, const SphParams& P, const CacheView& cv,
                   vec4<T>* acc, T* vsig, InstStat* stat, hipStream_t st)
 {
-    if (n <= 0) return;
-    hipLaunchKernelGGL((k_force<T>), grid_for(n, 256), dim3(256), 0, st, s.posh, s.velu, thermo,
-                       noff, nlist, n, p_off, ninst, inst, P, acc, vsig, stat);
+    if (ngroups <= 0) return;
+    if (sizeof(T) == 4)
+        hipLaunchKernelGGL((k_force<T, FORCE_CH_F>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
+                           s.posh, s.velu, thermo, id, gm, inst, P, cv, acc, vsig, stat);
+    else
+        hipLaunchKernelGGL((k_force<T, FORCE_CH_D>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
+                           s.posh, s.velu, thermo, id, gm, inst, P, cv, acc, vsig, stat);
 }
 
 template <class T>
@@ -419,8 +528,8 @@ void launch_correct(const SortedPtrs<T>& s, const vec4<T>* acc, const T* omega, 
                     double hfact, const OutPtrs<T>& o, InstStat* stat, hipStream_t st)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL((k_correct<T>), grid_for(n, 256), dim3(256), 0, st, s.posh, s.velu, s.vhalf,
-                       acc, omega, s.pid, n, p_off, ninst, inst, dt_inst, hfact, o, stat);
+    hipLaunchKernelGGL((k_correct<T>), grid_for(n, GROUP), dim3(GROUP), 0, st, s.posh, s.velu,
+                       s.vhalf, acc, omega, s.pid, n, p_off, ninst, inst, dt_inst, hfact, o, stat);
 }
 
 template <class T>
@@ -462,12 +571,12 @@ void launch_scatter_rho(const u32* eps, i64 n, const vec4<T>* posh, const i64* p
 
 #define INST(T)                                                                                   \
     template void launch_copy_h<T>(const vec4<T>*, T*, i64, hipStream_t);                         \
-    template void launch_density<T>(const SortedPtrs<T>&, const u64*, const u32*, i64,            \
-                                    const i64*, int, const InstDev*, const SphParams&, T*,        \
+    template void launch_density<T>(const SortedPtrs<T>&, const u32*, const GroupMap&, i64,       \
+                                    const InstDev*, const SphParams&, const CacheView&, T*,       \
                                     vec4<T>*, u8*, InstStat*, hipStream_t);                        \
-    template void launch_force<T>(const SortedPtrs<T>&, const vec4<T>*, const u64*, const u32*,   \
-                                  i64, const i64*, int, const InstDev*, const SphParams&,         \
-                                  vec4<T>*, T*, InstStat*, hipStream_t);                           \
+    template void launch_force<T>(const SortedPtrs<T>&, const vec4<T>*, const u32*,               \
+                                  const GroupMap&, i64, const InstDev*, const SphParams&,         \
+                                  const CacheView&, vec4<T>*, T*, InstStat*, hipStream_t);         \
     template void launch_correct<T>(const SortedPtrs<T>&, const vec4<T>*, const T*, i64,          \
                                     const i64*, int, const InstDev*, const double*, double,       \
                                     const OutPtrs<T>&, InstStat*, hipStream_t);                    \

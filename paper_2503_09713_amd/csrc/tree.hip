@@ -262,46 +262,152 @@ __global__ void k_karras(const u64* __restrict__ mu_leaf, const i64* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Cell boxes, bottom-up: each leaf computes the tight AABB and h_max of its
-// particles (h = posh.w, the h the neighbour cache is built with), then climbs; the second thread to reach an internal node merges
-// the two children and continues (arrival counters, device-scope fences).
+// Cell boxes, bottom-up (tight AABB + h_max of every node).  Pass 1: each
+// workgroup owns BOX_BLK consecutive leaves; a thread computes its leaf's box
+// from the leaf's particles (h = posh.w, the h the cache is built with), then
+// climbs: at a parent whose whole leaf range lies in the block, the second of
+// the two arriving threads (LDS counters) merges the children's boxes (held
+// in LDS) and continues.  A climb that reaches a parent straddling two blocks
+// records its node and stops.  Pass 2 (one workgroup) finishes the nodes
+// above those records with workgroup-scope arrival counters in memory.  No
+// device-wide fence is needed anywhere.
 // Node layout: lo = (xmin, ymin, zmin, hmax), hi = (xmax, ymax, zmax, 0).
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void k_boxes_up(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 n_leaf, i64 n_internal,
-                           const u32* __restrict__ child, const u32* __restrict__ parent,
-                           u32* __restrict__ arrive, vec4<T>* blo, vec4<T>* bhi)
+constexpr int BOX_BLK = 256;
+constexpr int BOX_OUT = 128;     // records per block: at most 2 * depth <= 126
+constexpr int TOP_BLOCK = 1024;
+
+// Leaf range [f, l] (global leaf indices) of internal node p and its
+// Karras index in global leaf numbering.
+__device__ inline void node_span(u32 p, const i64* ioff, const i64* leaf_off, int ninst,
+                                 const u32* endrange, i64& f, i64& l, i64& kidx)
 {
-    const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_leaf) return;
-    const u32 b0 = id[g], b1 = id[g + 1];
-    vec4<T> p = posh[b0];
-    T lo0 = p.x, lo1 = p.y, lo2 = p.z, hi0 = p.x, hi1 = p.y, hi2 = p.z, hm = p.w;
-    for (u32 b = b0 + 1; b < b1; ++b) {
-        p = posh[b];
-        lo0 = fmin(lo0, p.x); lo1 = fmin(lo1, p.y); lo2 = fmin(lo2, p.z);
-        hi0 = fmax(hi0, p.x); hi1 = fmax(hi1, p.y); hi2 = fmax(hi2, p.z);
-        hm = fmax(hm, p.w);
+    const int k = find_seg(ioff, ninst, (i64)p);
+    const i64 L0 = leaf_off[k];
+    const i64 i = (i64)p - ioff[k], j = endrange[p];
+    f = L0 + (i < j ? i : j);
+    l = L0 + (i < j ? j : i);
+    kidx = L0 + i;
+}
+
+template <class T>
+__global__ void __launch_bounds__(BOX_BLK)
+k_boxes_local(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 n_leaf,
+              i64 n_internal, const u32* __restrict__ child, const u32* __restrict__ parent,
+              const u32* __restrict__ endrange, const i64* __restrict__ ioff,
+              const i64* __restrict__ leaf_off, int ninst, vec4<T>* __restrict__ blo,
+              vec4<T>* __restrict__ bhi, u32* __restrict__ rec, u32* __restrict__ nrec,
+              u32* __restrict__ flags)
+{
+    __shared__ vec4<T> s_llo[BOX_BLK], s_lhi[BOX_BLK];   // leaves of the block
+    __shared__ vec4<T> s_nlo[BOX_BLK], s_nhi[BOX_BLK];   // internal nodes, by Karras index
+    __shared__ u32 s_arr[BOX_BLK];
+    __shared__ u32 s_rec[BOX_OUT];
+    __shared__ u32 s_nrec;
+    const i64 B0 = (i64)blockIdx.x * BOX_BLK;
+    const i64 B1 = (B0 + BOX_BLK) < n_leaf ? (B0 + BOX_BLK) : n_leaf;
+    const int t = threadIdx.x;
+    s_arr[t] = 0;
+    if (t == 0) s_nrec = 0;
+    const i64 g = B0 + t;
+    const bool live = g < B1;
+    T lo0 = 0, lo1 = 0, lo2 = 0, hi0 = 0, hi1 = 0, hi2 = 0, hm = 0;
+    if (live) {
+        const u32 b0 = id[g], b1 = id[g + 1];
+        vec4<T> p = posh[b0];
+        lo0 = hi0 = p.x; lo1 = hi1 = p.y; lo2 = hi2 = p.z; hm = p.w;
+        for (u32 b = b0 + 1; b < b1; ++b) {
+            p = posh[b];
+            lo0 = fmin(lo0, p.x); lo1 = fmin(lo1, p.y); lo2 = fmin(lo2, p.z);
+            hi0 = fmax(hi0, p.x); hi1 = fmax(hi1, p.y); hi2 = fmax(hi2, p.z);
+            hm = fmax(hm, p.w);
+        }
+        const vec4<T> l = mk4<T>(lo0, lo1, lo2, hm), h = mk4<T>(hi0, hi1, hi2, T(0));
+        s_llo[t] = l;
+        s_lhi[t] = h;
+        blo[n_internal + g] = l;
+        bhi[n_internal + g] = h;
     }
-    u32 node = (u32)(n_internal + g);
-    blo[node] = mk4<T>(lo0, lo1, lo2, hm);
-    bhi[node] = mk4<T>(hi0, hi1, hi2, T(0));
-    while (true) {
-        const u32 par = parent[node];
-        if (par == 0xffffffffu) break;
-        __threadfence();
-        const u32 prev = atomicAdd(&arrive[par], 1u);
-        if (prev == 0) break;              // the sibling's thread will continue
-        __threadfence();
-        const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
-        const u32 other = (c0 == node) ? c1 : c0;
-        const vec4<T> ol = blo[other];
-        const vec4<T> oh = bhi[other];
-        lo0 = fmin(lo0, ol.x); lo1 = fmin(lo1, ol.y); lo2 = fmin(lo2, ol.z); hm = fmax(hm, ol.w);
-        hi0 = fmax(hi0, oh.x); hi1 = fmax(hi1, oh.y); hi2 = fmax(hi2, oh.z);
-        blo[par] = mk4<T>(lo0, lo1, lo2, hm);
-        bhi[par] = mk4<T>(hi0, hi1, hi2, T(0));
-        node = par;
+    __syncthreads();
+    if (live) {
+        u32 node = (u32)(n_internal + g);
+        while (true) {
+            const u32 par = parent[node];
+            if (par == 0xffffffffu) break;
+            i64 f, l, kidx;
+            node_span(par, ioff, leaf_off, ninst, endrange, f, l, kidx);
+            if (f < B0 || l >= B1) {               // parent straddles blocks
+                const u32 q = atomicAdd(&s_nrec, 1u);
+                if (q < BOX_OUT) s_rec[q] = node;
+                break;
+            }
+            const int ps = (int)(kidx - B0);
+            __threadfence_block();
+            if (atomicAdd(&s_arr[ps], 1u) == 0) break;   // the sibling's thread continues
+            __threadfence_block();
+            const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
+            const u32 other = (c0 == node) ? c1 : c0;
+            vec4<T> ol, oh;
+            if (other >= n_internal) {
+                ol = s_llo[other - n_internal - B0];
+                oh = s_lhi[other - n_internal - B0];
+            } else {
+                i64 f2, l2, k2;
+                node_span(other, ioff, leaf_off, ninst, endrange, f2, l2, k2);
+                ol = s_nlo[k2 - B0];
+                oh = s_nhi[k2 - B0];
+            }
+            lo0 = fmin(lo0, ol.x); lo1 = fmin(lo1, ol.y); lo2 = fmin(lo2, ol.z); hm = fmax(hm, ol.w);
+            hi0 = fmax(hi0, oh.x); hi1 = fmax(hi1, oh.y); hi2 = fmax(hi2, oh.z);
+            const vec4<T> nl = mk4<T>(lo0, lo1, lo2, hm), nh = mk4<T>(hi0, hi1, hi2, T(0));
+            s_nlo[ps] = nl;
+            s_nhi[ps] = nh;
+            blo[par] = nl;
+            bhi[par] = nh;
+            node = par;
+        }
+    }
+    __syncthreads();
+    const u32 nr = s_nrec < BOX_OUT ? s_nrec : BOX_OUT;
+    for (u32 q = t; q < nr; q += BOX_BLK) rec[(i64)blockIdx.x * BOX_OUT + q] = s_rec[q];
+    if (t == 0) {
+        nrec[blockIdx.x] = nr;
+        if (s_nrec > BOX_OUT) atomicOr(flags, 16u);
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(TOP_BLOCK)
+k_boxes_top(const u32* __restrict__ rec, const u32* __restrict__ rscan, i64 nblocks,
+            const u32* __restrict__ child, const u32* __restrict__ parent,
+            u32* __restrict__ arrive, vec4<T>* blo, vec4<T>* bhi)
+{
+    const u32 total = rscan[nblocks];
+    for (u32 r = threadIdx.x; r < total; r += TOP_BLOCK) {
+        i64 lo = 0, hi = nblocks - 1;       // block holding record r
+        while (lo < hi) {
+            const i64 mid = (lo + hi + 1) >> 1;
+            if (rscan[mid] <= r) lo = mid; else hi = mid - 1;
+        }
+        u32 node = rec[lo * BOX_OUT + (r - rscan[lo])];
+        vec4<T> ml = blo[node], mh = bhi[node];
+        while (true) {
+            const u32 par = parent[node];
+            if (par == 0xffffffffu) break;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            const u32 prev = __hip_atomic_fetch_add(&arrive[par], 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (prev == 0) break;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
+            const u32 other = (c0 == node) ? c1 : c0;
+            const vec4<T> ol = blo[other], oh = bhi[other];
+            ml = mk4<T>(fmin(ml.x, ol.x), fmin(ml.y, ol.y), fmin(ml.z, ol.z), fmax(ml.w, ol.w));
+            mh = mk4<T>(fmax(mh.x, oh.x), fmax(mh.y, oh.y), fmax(mh.z, oh.z), T(0));
+            blo[par] = ml;
+            bhi[par] = mh;
+            node = par;
+        }
     }
 }
 
@@ -517,13 +623,24 @@ void launch_karras(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int
 
 template <class T>
 void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 n_leaf, i64 n_internal,
-                     const u32* child, const u32* parent, u32* arrive, vec4<T>* blo, vec4<T>* bhi,
+                     const u32* child, const u32* parent, const u32* endrange, const i64* ioff,
+                     const i64* leaf_off, int ninst, u32* arrive, u32* rec, u32* nrec,
+                     u32* rscan, void* scan_tmp, vec4<T>* blo, vec4<T>* bhi, u32* flags,
                      hipStream_t st)
 {
     if (n_leaf <= 0) return;
-    hipLaunchKernelGGL((k_boxes_up<T>), grid_for(n_leaf, 256), dim3(256), 0, st, posh, id,
-                       n_leaf, n_internal, child, parent, arrive, blo, bhi);
+    const i64 nb = (n_leaf + BOX_BLK - 1) / BOX_BLK;
+    hipLaunchKernelGGL((k_boxes_local<T>), dim3((unsigned)nb), dim3(BOX_BLK), 0, st, posh, id, n_leaf,
+                       n_internal, child, parent, endrange, ioff, leaf_off, ninst, blo, bhi, rec,
+                       nrec, flags);
+    if (nb > 1) {
+        scan_u32_u32(nrec, rscan, nb, scan_tmp, st);
+        hipLaunchKernelGGL((k_boxes_top<T>), dim3(1), dim3(TOP_BLOCK), 0, st, rec, rscan, nb, child,
+                           parent, arrive, blo, bhi);
+    }
 }
+
+size_t boxes_rec_count(i64 n_leaf) { return (size_t)((n_leaf + BOX_BLK - 1) / BOX_BLK) * BOX_OUT; }
 
 void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
                          i64 n_internal, i64 n_leaf, const u32* endrange, const u32* parent,
@@ -543,7 +660,9 @@ void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* iof
     template void launch_bbox<T>(const FieldPtrs<T>&, i64, InstDev*, const i64*, int,            \
                                  const double*, u64*, hipStream_t);                               \
     template void launch_boxes_up<T>(const vec4<T>*, const u32*, i64, i64, const u32*,            \
-                                     const u32*, u32*, vec4<T>*, vec4<T>*, hipStream_t);
+                                     const u32*, const u32*, const i64*, const i64*, int, u32*,   \
+                                     u32*, u32*, u32*, void*, vec4<T>*, vec4<T>*, u32*,           \
+                                     hipStream_t);
 INST(float)
 INST(double)
 #undef INST

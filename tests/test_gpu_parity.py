@@ -73,12 +73,13 @@ def check_tree(ctx, p, n_red, chi=1.1):
     off, lst = oracle.neighbours(xs, ys, zs, hs, lo, hi, p.periodic, 2.0 * chi)
     assert np.array_equal(ex["neigh_off"], off), "neighbour counts"
     assert np.array_equal(ex["neigh_list"], lst), "neighbour sets / order"
-    # stage-1 lists are ascending and cover every neighbour's leaf
-    lo1, l1 = ex["leaf_off"], ex["leaf_list"]
+    # stage-1 lists (per group of 256 key-order slots) are ascending and
+    # cover the leaf of every neighbour of every particle of the group
+    go, gl = ex["group_off"], ex["group_leaves"]
     leaf_of = np.searchsorted(ids, np.arange(p.n), side="right") - 1
     for a in range(0, p.n, max(1, p.n // 300)):
-        L = leaf_of[a]
-        seg = l1[lo1[L]:lo1[L + 1]]
+        g = a // 256
+        seg = gl[go[g]:go[g + 1]]
         assert (np.diff(seg.astype(np.int64)) > 0).all()
         assert set(leaf_of[lst[off[a]:off[a + 1]]]) <= set(seg.tolist())
     return ex
