@@ -69,6 +69,7 @@ struct shsph_ctx {
     Buf rec, nrec, rscan;                       // bottom-up box records
     Buf glo, ghi, uleaf, uslot, ucnt, ustot;    // stage 1, per group
     Buf nlist, ncnt, flags;                     // stage 2, per particle (ELL)
+    Buf bpart;                                  // corrector partial sums
     Buf inst_d, poff_d, goff_d, leaf_off_d, ioff_d, root_d, stat_d, dt_inst_d, dt_host_d;
     Buf pbox, plen, xoff, xlist;                // export only
 
@@ -444,8 +445,8 @@ template <class T> int build_caches(shsph_ctx* c)
         prof_begin(c, S_STAGE2);
         launch_group_cache<T>(posh, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->id), ni, gm, G,
                               inst, rk, rk, c->cap_leaf, P<u32>(c->uleaf), P<u32>(c->uslot),
-                              P<u32>(c->ucnt), c->cap_entry, P<u16>(c->nlist), P<u32>(c->ncnt),
-                              P<u32>(c->flags), st);
+                              P<u32>(c->ucnt), P<u32>(c->ustot), c->cap_entry, P<u16>(c->nlist),
+                              P<u32>(c->ncnt), P<u32>(c->flags), st);
         prof_end(c);
         TRY(check_launch(c, "stage2"));
         HIPTRY(c, hipMemcpyAsync(c->pinned, c->flags.p, 4 * sizeof(u32), hipMemcpyDeviceToHost, st));
@@ -619,10 +620,11 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
     o.u = (T*)p->u; o.h = (T*)p->h;
     o.ax = (T*)p->ax; o.ay = (T*)p->ay; o.az = (T*)p->az; o.du = (T*)p->dudt;
     o.rho = (T*)p->rho; o.omega = (T*)p->omega; o.pid = p->pid;
+    TRY(ensure(c, c->bpart, ((n + GROUP - 1) / GROUP) * sizeof(BlockPart)));
     prof_begin(c, S_CORRECT);
     launch_correct<T>(sorted<T>(c, true), P<vec4<T>>(c->acc), P<T>(c->omega), n, P<i64>(c->poff_d),
                       c->ninst, P<InstDev>(c->inst_d), dt_dev, c->prm.hfact, o,
-                      P<InstStat>(c->stat_d), st);
+                      P<InstStat>(c->stat_d), P<BlockPart>(c->bpart), st);
     prof_end(c);
     TRY(check_launch(c, "correct"));
     if (dt_used) {
@@ -707,7 +709,8 @@ int shsph_destroy(shsph_ctx* c)
                    &c->rec, &c->nrec, &c->rscan, &c->glo, &c->ghi, &c->uleaf, &c->uslot,
                    &c->ucnt, &c->ustot, &c->nlist, &c->ncnt, &c->flags, &c->inst_d, &c->poff_d,
                    &c->goff_d, &c->leaf_off_d, &c->ioff_d, &c->root_d, &c->stat_d,
-                   &c->dt_inst_d, &c->dt_host_d, &c->pbox, &c->plen, &c->xoff, &c->xlist };
+                   &c->dt_inst_d, &c->dt_host_d, &c->pbox, &c->plen, &c->xoff, &c->xlist,
+                   &c->bpart };
     for (Buf* b : all)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);

@@ -231,6 +231,16 @@ template <class T> __device__ inline T m4_df(T q)
 
 template <class T> __device__ inline T inv_pi() { return T(0.318309886183790671537767526745); }
 
+// Reciprocal, reciprocal square root and square root for the derivative
+// sums: the hardware instructions (about 1 ulp) in FP32, IEEE operations in
+// FP64.  The neighbour decision never uses them.
+__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double fast_rcp(double x) { return 1.0 / x; }
+__device__ inline double fast_rsq(double x) { return 1.0 / sqrt(x); }
+__device__ inline double fast_sqrt(double x) { return sqrt(x); }
+
 // Positive-float atomic min/max through the integer order of the bit pattern.
 __device__ inline void atomic_min_posf(u32* addr, float v) { atomicMin(addr, __float_as_uint(v)); }
 __device__ inline void atomic_max_posf(u32* addr, float v) { atomicMax(addr, __float_as_uint(v)); }
@@ -248,6 +258,28 @@ template <int BLOCK, class T, class Op> __device__ inline T block_reduce(T v, T*
     for (int w = 1; w < BLOCK / WAVE; ++w) r = op(r, lds[w]);
     __syncthreads();
     return r;
+}
+
+// ---------------------------------------------------------------------------
+// Staging of a group's candidate union into LDS: slots [c0, c1) of the union
+// (its leaves' particles in ascending key order) are copied from the
+// key-order arrays.  One thread per union leaf.
+// ---------------------------------------------------------------------------
+template <class T, int NF>
+__device__ inline void stage_union(const vec4<T>* const* src, vec4<T>* const* dst, const u32* id,
+                                   const u32* ul, const u32* us, u32 nu, u32 c0, u32 c1)
+{
+    for (u32 j = threadIdx.x; j < nu; j += GROUP) {
+        const u32 s0 = us[j];
+        const u32 leaf = ul[j];
+        const u32 b0 = id[leaf], sz = id[leaf + 1] - b0;
+        const u32 lo = s0 > c0 ? s0 : c0;
+        const u32 hi = (s0 + sz) < c1 ? (s0 + sz) : c1;
+        for (u32 s = lo; s < hi; ++s) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) dst[f][s - c0] = src[f][b0 + (s - s0)];
+        }
+    }
 }
 
 }  // namespace shsph

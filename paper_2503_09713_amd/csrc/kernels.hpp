@@ -49,6 +49,14 @@ struct CacheView {
     i64 capj;
 };
 
+// Per-block partial sums of the corrector (instance id, or -1 if the block
+// spans two instances and added its lanes directly).
+struct BlockPart {
+    int inst;
+    int pad;
+    double dv2, v2;
+};
+
 struct SphParams {
     double hfact, gamma, alpha, beta, beta_u, chi, lambda, eps_h, c_cour, c_force, r_kern;
     int max_iter;
@@ -109,8 +117,8 @@ template <class T>
 void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* bhi, const u32* id,
                         i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
-                        const u32* ucnt, i64 capj, u16* nlist, u32* ncnt, u32* flags,
-                        hipStream_t st);
+                        const u32* ucnt, const u32* ustot, i64 capj, u16* nlist, u32* ncnt,
+                        u32* flags, hipStream_t st);
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
                             const u32* uleaf, const u32* uslot, const u32* ucnt, i64 capj,
                             const u16* nlist, const u32* ncnt, const u64* off, u32* list,
@@ -133,7 +141,8 @@ void launch_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id, 
 template <class T>
 void launch_correct(const SortedPtrs<T>& s, const vec4<T>* acc, const T* omega, i64 n,
                     const i64* p_off, int ninst, const InstDev* inst, const double* dt_inst,
-                    double hfact, const OutPtrs<T>& o, InstStat* stat, hipStream_t st);
+                    double hfact, const OutPtrs<T>& o, InstStat* stat, BlockPart* part,
+                    hipStream_t st);
 template <class T>
 void launch_gather_velu(const u32* eps, i64 n, const T* vx, const T* vy, const T* vz, const T* u,
                         vec4<T>* velu, hipStream_t st);

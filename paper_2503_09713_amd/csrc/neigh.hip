@@ -22,7 +22,8 @@ namespace shsph {
 
 constexpr int STACK = 64;   // tree depth is bounded by the 63 key bits
 constexpr int TRAV_BLOCK = 64;
-constexpr int LCHUNK = 512;  // union leaves staged in LDS at a time (stage 2)
+constexpr int LCHUNK = 256;  // union leaves staged in LDS at a time (stage 2)
+constexpr int UCH = 1536;    // union particles staged in LDS (larger unions read HBM/L2)
 
 template <class T> struct Inflate;
 template <> struct Inflate<float> {
@@ -161,14 +162,15 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
               const vec4<T>* __restrict__ bhi, const u32* __restrict__ id, i64 n_internal,
               const GroupMap gm, const InstDev* __restrict__ inst, T rk, T rkc, i64 cap,
               const u32* __restrict__ uleaf, const u32* __restrict__ uslot,
-              const u32* __restrict__ ucnt, i64 capj, u16* __restrict__ nlist,
-              u32* __restrict__ ncnt, u32* __restrict__ flags)
+              const u32* __restrict__ ucnt, const u32* __restrict__ ustot, i64 capj,
+              u16* __restrict__ nlist, u32* __restrict__ ncnt, u32* __restrict__ flags)
 {
     __shared__ u32 s_b0[LCHUNK];
     __shared__ u32 s_b1[LCHUNK];
     __shared__ u32 s_slot[LCHUNK];
     __shared__ vec4<T> s_lo[LCHUNK];
     __shared__ vec4<T> s_hi[LCHUNK];
+    __shared__ vec4<T> s_upos[UCH];
     const i64 g = blockIdx.x;
     i64 beg, end;
     int k;
@@ -180,6 +182,13 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     const vec4<T> pa = posh[live ? a : beg];
     const vec4<T> pl = mk4<T>(pa.x, pa.y, pa.z, pa.w);   // point box
     const u32 nu = min((u32)cap, ucnt[g]);
+    const u32 S = ustot[g];
+    const bool in_lds = S <= (u32)UCH;
+    if (in_lds) {
+        const vec4<T>* src[1] = { posh };
+        vec4<T>* dst[1] = { s_upos };
+        stage_union<T, 1>(src, dst, id, uleaf + g * cap, uslot + g * cap, nu, 0u, S);
+    }
     u16* out = nlist + (u64)g * (u64)capj * GROUP + threadIdx.x;
     u32 c = 0;
     for (u32 c0 = 0; c0 < nu; c0 += LCHUNK) {
@@ -199,7 +208,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
             if (!box_hit<T>(pl, pl, s_lo[j], s_hi[j], rk, eps_abs, bx)) continue;
             const u32 b0 = s_b0[j], b1 = s_b1[j], sl = s_slot[j];
             for (u32 b = b0; b < b1; ++b) {
-                const vec4<T> pb = posh[b];
+                const vec4<T> pb = in_lds ? s_upos[sl + (b - b0)] : posh[b];
                 if (cache_crit<T>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w, bx, rkc)) {
                     if (c < capj) out[(u64)c * GROUP] = (u16)(sl + (b - b0));
                     ++c;
@@ -272,13 +281,13 @@ template <class T>
 void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* bhi, const u32* id,
                         i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
-                        const u32* ucnt, i64 capj, u16* nlist, u32* ncnt, u32* flags,
-                        hipStream_t st)
+                        const u32* ucnt, const u32* ustot, i64 capj, u16* nlist, u32* ncnt,
+                        u32* flags, hipStream_t st)
 {
     if (ngroups <= 0) return;
     hipLaunchKernelGGL((k_group_cache<T>), dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, blo,
-                       bhi, id, n_internal, gm, inst, (T)rk, (T)rkc, cap, uleaf, uslot, ucnt, capj,
-                       nlist, ncnt, flags);
+                       bhi, id, n_internal, gm, inst, (T)rk, (T)rkc, cap, uleaf, uslot, ucnt, ustot,
+                       capj, nlist, ncnt, flags);
 }
 
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
@@ -301,7 +310,7 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
     template void launch_group_cache<T>(const vec4<T>*, const vec4<T>*, const vec4<T>*,           \
                                         const u32*, i64, const GroupMap&, i64, const InstDev*,    \
                                         double, double, i64, const u32*, const u32*, const u32*,  \
-                                        i64, u16*, u32*, u32*, hipStream_t);
+                                        const u32*, i64, u16*, u32*, u32*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -49,28 +49,6 @@ template <class T> __global__ void k_copy_h(const vec4<T>* __restrict__ posh, T*
 }
 
 
-// ---------------------------------------------------------------------------
-// Staging of a group's candidate union into LDS: slots [c0, c1) of the union
-// (its leaves' particles in ascending key order) are copied from the
-// key-order arrays.  One thread per union leaf.
-// ---------------------------------------------------------------------------
-template <class T, int NF>
-__device__ inline void stage_union(const vec4<T>* const* src, vec4<T>* const* dst, const u32* id,
-                                   const u32* ul, const u32* us, u32 nu, u32 c0, u32 c1)
-{
-    for (u32 j = threadIdx.x; j < nu; j += GROUP) {
-        const u32 s0 = us[j];
-        const u32 leaf = ul[j];
-        const u32 b0 = id[leaf], sz = id[leaf + 1] - b0;
-        const u32 lo = s0 > c0 ? s0 : c0;
-        const u32 hi = (s0 + sz) < c1 ? (s0 + sz) : c1;
-        for (u32 s = lo; s < hi; ++s) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) dst[f][s - c0] = src[f][b0 + (s - s0)];
-        }
-    }
-}
-
 // Block-wide reduction helpers for per-instance statistics: the block's
 // lanes usually share one instance, then a single atomic per block is done
 // (and min/max atomics only when they can change the stored value).
@@ -176,7 +154,7 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
                 const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 if (r2 < h2x4) {
-                    const T q = sqrt(r2) * hinv;
+                    const T q = fast_sqrt(r2) * hinv;
                     T f, df;
                     m4<T>(q, f, df);
                     s += f;
@@ -306,10 +284,10 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
             const T hm = ha > hb ? ha : hb;
             if (!(r2 > T(0)) || !(r2 < T(4) * hm * hm)) continue;
             const vec4<T> vb = s_vel[sl], tb = s_thm[sl];
-            const T r = sqrt(r2), rinv = T(1) / r;
+            const T rinv = fast_rsq(r2), r = r2 * rinv;
             const T ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
             const T w = (va.x - vb.x) * ex + (va.y - vb.y) * ey + (va.z - vb.z) * ez;
-            const T hib = T(1) / hb;
+            const T hib = fast_rcp(hb);
             const T Fa = m4_df<T>(r * hia) * hia4;
             const T Fb = m4_df<T>(r * hib) * (hib * hib * hib * hib * inv_pi<T>());
             const T aw = fabs(w);
@@ -325,7 +303,7 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
             du += m * ka * w;
             const T hfb = hfact * hib;
             const T rhob = m * hfb * hfb * hfb;
-            const T vsu = sqrt(fabs(Pa - tb.w) / (T(0.5) * (rhoa + rhob)));
+            const T vsu = fast_sqrt(fabs(Pa - tb.w)) * fast_rsq(T(0.5) * (rhoa + rhob));
             lam += m * beta_u * vsu * (va.w - vb.w) * T(0.5) * (Fa * Ba + Fb * tb.y);
             vmax = vsa > vmax ? vsa : vmax;
         }
@@ -360,7 +338,7 @@ k_correct(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
           const T* __restrict__ omega, const u32* __restrict__ pid, i64 n,
           const i64* __restrict__ p_off, int ninst, const InstDev* __restrict__ inst,
           const double* __restrict__ dt_inst, double hfact, OutPtrs<T> o,
-          InstStat* __restrict__ stat)
+          InstStat* __restrict__ stat, BlockPart* __restrict__ part)
 {
     __shared__ double s_red[GROUP / WAVE];
     __shared__ float s_redf[GROUP / WAVE];
@@ -390,6 +368,8 @@ k_correct(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         dv = (float)sqrt(dv2);
         v2 = (double)vx * vx + (double)vy * vy + (double)vz * vz;
     }
+    // one partial per block (no atomics); blocks spanning two instances add
+    // their lanes directly (rare: only at instance boundaries)
     const int slot = blockIdx.x % STAT_SLOTS;
     if (block_uniform(k, &s_k)) {
         const float mx = block_max<float>(dv, s_redf);
@@ -397,13 +377,45 @@ k_correct(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         const double s2 = block_sum<double>(v2, s_red);
         if (threadIdx.x == 0) {
             atomic_max_if(&stat[k].dvmax_bits, __float_as_uint(mx));
-            atomicAdd(&stat[k].dv2_part[slot], s1);
-            atomicAdd(&stat[k].v2_part[slot], s2);
+            BlockPart bp;
+            bp.inst = k;
+            bp.dv2 = s1;
+            bp.v2 = s2;
+            part[blockIdx.x] = bp;
         }
-    } else if (live) {
-        atomic_max_if(&stat[k].dvmax_bits, __float_as_uint(dv));
-        atomicAdd(&stat[k].dv2_part[slot], dv2);
-        atomicAdd(&stat[k].v2_part[slot], v2);
+    } else {
+        if (live) {
+            atomic_max_if(&stat[k].dvmax_bits, __float_as_uint(dv));
+            atomicAdd(&stat[k].dv2_part[slot], dv2);
+            atomicAdd(&stat[k].v2_part[slot], v2);
+        }
+        if (threadIdx.x == 0) {
+            BlockPart bp;
+            bp.inst = -1;
+            bp.dv2 = 0.0;
+            bp.v2 = 0.0;
+            part[blockIdx.x] = bp;
+        }
+    }
+}
+
+// Fold the per-block partials of the corrector into the instance stats
+// (one workgroup per instance).
+__global__ void __launch_bounds__(GROUP)
+k_fold_parts(const BlockPart* __restrict__ part, i64 nblocks, InstStat* __restrict__ stat)
+{
+    __shared__ double s_red[GROUP / WAVE];
+    const int k = blockIdx.x;
+    double a = 0.0, b = 0.0;
+    for (i64 i = threadIdx.x; i < nblocks; i += GROUP) {
+        const BlockPart p = part[i];
+        if (p.inst == k) { a += p.dv2; b += p.v2; }
+    }
+    a = block_sum<double>(a, s_red);
+    b = block_sum<double>(b, s_red);
+    if (threadIdx.x == 0) {
+        stat[k].dv2_part[0] += a;
+        stat[k].v2_part[0] += b;
     }
 }
 
@@ -525,11 +537,15 @@ void launch_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id, 
 template <class T>
 void launch_correct(const SortedPtrs<T>& s, const vec4<T>* acc, const T* omega, i64 n,
                     const i64* p_off, int ninst, const InstDev* inst, const double* dt_inst,
-                    double hfact, const OutPtrs<T>& o, InstStat* stat, hipStream_t st)
+                    double hfact, const OutPtrs<T>& o, InstStat* stat, BlockPart* part,
+                    hipStream_t st)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL((k_correct<T>), grid_for(n, GROUP), dim3(GROUP), 0, st, s.posh, s.velu,
-                       s.vhalf, acc, omega, s.pid, n, p_off, ninst, inst, dt_inst, hfact, o, stat);
+    const i64 nb = (n + GROUP - 1) / GROUP;
+    hipLaunchKernelGGL((k_correct<T>), dim3((unsigned)nb), dim3(GROUP), 0, st, s.posh, s.velu,
+                       s.vhalf, acc, omega, s.pid, n, p_off, ninst, inst, dt_inst, hfact, o, stat,
+                       part);
+    hipLaunchKernelGGL(k_fold_parts, dim3((unsigned)ninst), dim3(GROUP), 0, st, part, nb, stat);
 }
 
 template <class T>
@@ -579,7 +595,7 @@ void launch_scatter_rho(const u32* eps, i64 n, const vec4<T>* posh, const i64* p
                                   const CacheView&, vec4<T>*, T*, InstStat*, hipStream_t);         \
     template void launch_correct<T>(const SortedPtrs<T>&, const vec4<T>*, const T*, i64,          \
                                     const i64*, int, const InstDev*, const double*, double,       \
-                                    const OutPtrs<T>&, InstStat*, hipStream_t);                    \
+                                    const OutPtrs<T>&, InstStat*, BlockPart*, hipStream_t);        \
     template void launch_gather_velu<T>(const u32*, i64, const T*, const T*, const T*, const T*,  \
                                         vec4<T>*, hipStream_t);                                   \
     template void launch_thermo<T>(const vec4<T>*, const vec4<T>*, const T*, i64, const i64*,     \
