@@ -55,7 +55,7 @@ struct shsph_ctx {
     i64 n = 0;
     int ninst = 0;
     i64 n_leaf = 0, n_internal = 0, n_groups = 0;
-    i64 cap_leaf = 256, cap_entry = 112;        // per-group leaves, per-particle entries
+    i64 cap_leaf = 256, cap_words = 28;         // per-group leaves, per-particle cache words (4 entries)
     int state = ST_NONE;
     int restarts = 0;
     int vals_sel = 0;       // which value buffer holds eps after the sort
@@ -285,8 +285,8 @@ CacheView cache_view(shsph_ctx* c)
     v.uleaf = P<u32>(c->uleaf); v.uslot = P<u32>(c->uslot);
     v.ucnt = P<u32>(c->ucnt); v.ustot = P<u32>(c->ustot);
     v.cap = c->cap_leaf;
-    v.nlist = P<u16>(c->nlist); v.ncnt = P<u32>(c->ncnt);
-    v.capj = c->cap_entry;
+    v.nlist = P<u64>(c->nlist); v.ncnt = P<u32>(c->ncnt);
+    v.capq = (u32)c->cap_words;
     return v;
 }
 
@@ -432,7 +432,7 @@ template <class T> int build_caches(shsph_ctx* c)
         // stage 1: neighbour leaves of each group
         TRY(ensure(c, c->uleaf, (size_t)G * c->cap_leaf * sizeof(u32)));
         TRY(ensure(c, c->uslot, (size_t)G * c->cap_leaf * sizeof(u32)));
-        TRY(ensure(c, c->nlist, (size_t)G * c->cap_entry * GROUP * sizeof(u16)));
+        TRY(ensure(c, c->nlist, (size_t)G * c->cap_words * GROUP * sizeof(u64)));
         prof_begin(c, S_STAGE1);
         launch_group_leaves<T>(P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child),
                                P<u32>(c->id), ni, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), G, gm,
@@ -445,7 +445,7 @@ template <class T> int build_caches(shsph_ctx* c)
         prof_begin(c, S_STAGE2);
         launch_group_cache<T>(posh, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->id), ni, gm, G,
                               inst, rk, rk, c->cap_leaf, P<u32>(c->uleaf), P<u32>(c->uslot),
-                              P<u32>(c->ucnt), P<u32>(c->ustot), c->cap_entry, P<u16>(c->nlist),
+                              P<u32>(c->ucnt), P<u32>(c->ustot), (u32)c->cap_words, P<u64>(c->nlist),
                               P<u32>(c->ncnt), P<u32>(c->flags), st);
         prof_end(c);
         TRY(check_launch(c, "stage2"));
@@ -472,7 +472,7 @@ template <class T> int build_caches(shsph_ctx* c)
         if (!(fl[0] & 6u)) break;
         if (attempt >= 4) return fail(c, SHSPH_ECAPACITY, "neighbour cache capacity");
         if (fl[0] & 2u) c->cap_leaf = (i64)fl[1] + fl[1] / 4 + 16;
-        if (fl[0] & 4u) c->cap_entry = (i64)fl[2] + fl[2] / 4 + 8;
+        if (fl[0] & 4u) c->cap_words = ((i64)fl[2] + fl[2] / 4 + 8 + 3) / 4;
         launch_fill_u32(P<u32>(c->flags), 4, 0u, st);
     }
     return SHSPH_OK;
@@ -906,7 +906,7 @@ int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
         total = *(u64*)c->pinned;
         TRY(ensure(c, c->xlist, std::max<u64>(total, 1) * sizeof(u32)));
         launch_cache_to_global(P<u32>(c->id), group_map(c), G, c->cap_leaf, P<u32>(c->uleaf),
-                               P<u32>(c->uslot), P<u32>(c->ucnt), c->cap_entry, P<u16>(c->nlist),
+                               P<u32>(c->uslot), P<u32>(c->ucnt), (u32)c->cap_words, P<u64>(c->nlist),
                                P<u32>(c->ncnt), P<u64>(c->xoff), P<u32>(c->xlist), st);
         TRY(check_launch(c, "cache export"));
         TRY(cp(o->neigh_off, c->xoff.p, (n + 1) * 8));

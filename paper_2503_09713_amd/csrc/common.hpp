@@ -148,14 +148,9 @@ template <int BITS> __device__ inline u64 match_digit(u32 d, u64 active)
 }
 
 // ---------------------------------------------- exact float arithmetic ----
-// The neighbour decision must be bit-identical to the CPU definition, so it
-// is written with explicit round-to-nearest operations (no contraction).
-__device__ inline float add_rn(float a, float b) { return __fadd_rn(a, b); }
-__device__ inline float sub_rn(float a, float b) { return __fsub_rn(a, b); }
-__device__ inline float mul_rn(float a, float b) { return __fmul_rn(a, b); }
-__device__ inline double add_rn(double a, double b) { return __dadd_rn(a, b); }
-__device__ inline double sub_rn(double a, double b) { return __dsub_rn(a, b); }
-__device__ inline double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+// The neighbour decision and the predicted positions must be bit-identical
+// to their CPU definitions (and between kernels), so the code that computes
+// them sits in scopes with FMA contraction disabled.
 
 // Periodic box constants in the storage type: L = (T)(hi-lo),
 // halfL = (T)(0.5*(hi-lo)).
@@ -178,14 +173,14 @@ template <class T> __device__ inline Box<T> make_box(const InstDev& in)
     return b;
 }
 
-// Minimum image applied once: d -> d - L if d > L/2, d + L if d < -L/2.
+// Minimum image applied once: d -> d - L if d > L/2, d + L if d < -L/2
+// (written with selects: no divergent branches).
 template <class T> __device__ inline T min_image(T d, T L, T halfL, int periodic)
 {
-    if (periodic) {
-        if (d > halfL) d = sub_rn(d, L);
-        else if (d < -halfL) d = add_rn(d, L);
-    }
-    return d;
+#pragma clang fp contract(off)
+    const T dm = d - L, dp = d + L;
+    const T w = d > halfL ? dm : (d < -halfL ? dp : d);
+    return periodic ? w : d;
 }
 
 // Object-object criterion of the cache (App. F, chi-extended radius), in T:
@@ -195,14 +190,23 @@ template <class T>
 __device__ inline bool cache_crit(T xa, T ya, T za, T ha, T xb, T yb, T zb, T hb,
                                   const Box<T>& bx, T rkc)
 {
-    T dx = min_image(sub_rn(xb, xa), bx.L[0], bx.halfL[0], bx.periodic);
-    T dy = min_image(sub_rn(yb, ya), bx.L[1], bx.halfL[1], bx.periodic);
-    T dz = min_image(sub_rn(zb, za), bx.L[2], bx.halfL[2], bx.periodic);
-    T r2 = add_rn(add_rn(mul_rn(dx, dx), mul_rn(dy, dy)), mul_rn(dz, dz));
-    T hm = ha > hb ? ha : hb;
-    T rc = mul_rn(rkc, hm);
-    return r2 < mul_rn(rc, rc);
+#pragma clang fp contract(off)
+    const T dx = min_image(xb - xa, bx.L[0], bx.halfL[0], bx.periodic);
+    const T dy = min_image(yb - ya, bx.L[1], bx.halfL[1], bx.periodic);
+    const T dz = min_image(zb - za, bx.L[2], bx.halfL[2], bx.periodic);
+    const T xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    const T r2 = (xx + yy) + zz;
+    const T hm = ha > hb ? ha : hb;
+    const T rc = rkc * hm;
+    const T rc2 = rc * rc;
+    return r2 < rc2;
 }
+
+// The group cache stores four 16-bit union slots per 64-bit word, ELL
+// layout word[(g * capq + j / 4) * GROUP + lane], slot j at bits 16 (j % 4);
+// unused slots of the last word hold SLOT_NONE.
+constexpr u32 SLOT_NONE = 0xffffu;
+__device__ inline u32 slot_of(u64 w, u32 r) { return (u32)(w >> (16u * r)) & 0xffffu; }
 
 // ------------------------------------------------------------- M4 spline --
 // f(q) = 1 - 3/2 q^2 + 3/4 q^3 (q<1), (2-q)^3/4 (1<=q<2), 0 beyond;

@@ -39,14 +39,14 @@ template <class T> struct OutPtrs {
 // The group neighbour cache: per group, its union of neighbour leaves
 // (uleaf, with the union slot where each leaf starts, uslot; ucnt leaves,
 // ustot slots; capacity cap per group), and per particle its neighbours as
-// 16-bit union slots in ELL layout nlist[(g * capj + j) * GROUP + lane],
-// ncnt[a] of them.
+// 16-bit union slots, four per word, ELL layout
+// nlist[(g * capq + j / 4) * GROUP + lane]; ncnt[a] of them.
 struct CacheView {
     const u32 *uleaf, *uslot, *ucnt, *ustot;
     i64 cap;
-    const u16* nlist;
+    const u64* nlist;
     const u32* ncnt;
-    i64 capj;
+    u32 capq;
 };
 
 // Per-block partial sums of the corrector (instance id, or -1 if the block
@@ -117,11 +117,11 @@ template <class T>
 void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* bhi, const u32* id,
                         i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
-                        const u32* ucnt, const u32* ustot, i64 capj, u16* nlist, u32* ncnt,
+                        const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
                         u32* flags, hipStream_t st);
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
-                            const u32* uleaf, const u32* uslot, const u32* ucnt, i64 capj,
-                            const u16* nlist, const u32* ncnt, const u64* off, u32* list,
+                            const u32* uleaf, const u32* uslot, const u32* ucnt, u32 capq,
+                            const u64* nlist, const u32* ncnt, const u64* off, u32* list,
                             hipStream_t st);
 
 // sph.hip

@@ -59,7 +59,7 @@ template <class T>
 __device__ inline bool box_hit(const vec4<T>& al, const vec4<T>& ah, const vec4<T>& bl,
                                const vec4<T>& bh, T rk, T eps_abs, const Box<T>& bx)
 {
-    const T r = add_rn(mul_rn(mul_rn(rk, fmax(al.w, bl.w)), T(1) + Inflate<T>::rel), eps_abs);
+    const T r = rk * fmax(al.w, bl.w) * (T(1) + Inflate<T>::rel) + eps_abs;
     return gap1<T>(al.x, ah.x, bl.x, bh.x, bx.L[0], bx.periodic) <= r &&
            gap1<T>(al.y, ah.y, bl.y, bh.y, bx.L[1], bx.periodic) <= r &&
            gap1<T>(al.z, ah.z, bl.z, bh.z, bx.L[2], bx.periodic) <= r;
@@ -154,16 +154,54 @@ k_group_leaves(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
 }
 
 // Stage 2: per particle, its neighbours among the group's union (Alg. 5 with
-// the object-object criterion), as ascending 16-bit slots in ELL layout
-// nlist[(g * capj + j) * GROUP + lane].  ncnt[a] = number of neighbours.
+// the object-object criterion), as ascending 16-bit slots, four per 64-bit
+// word in ELL layout (see slot_of); ncnt[a] = number of neighbours.
+// Each lane first marks the union leaves whose box passes the point-box
+// prune (bitmask over an LDS tile of leaves), then walks only the particles
+// of its own marked leaves, reading positions from LDS.
+template <class T, bool LDS>
+__device__ inline void cache_leaves(const vec4<T>& pa, const Box<T>& bx, T rk, T rkc, T eps_abs,
+                                    u32 nl, const u32* s_b0, const u32* s_b1, const u32* s_slot,
+                                    const vec4<T>* s_lo, const vec4<T>* s_hi,
+                                    const vec4<T>* s_upos, const vec4<T>* posh, u64* out,
+                                    u32 capq, u32& c, u64& wbuf)
+{
+    u64 mk[LCHUNK / 64];
+#pragma unroll
+    for (int w = 0; w < LCHUNK / 64; ++w) mk[w] = 0;
+    for (u32 j = 0; j < nl; ++j)
+        if (box_hit<T>(pa, pa, s_lo[j], s_hi[j], rk, eps_abs, bx)) mk[j >> 6] |= 1ull << (j & 63);
+#pragma unroll
+    for (int w = 0; w < LCHUNK / 64; ++w) {
+        u64 cur = mk[w];
+        while (cur) {
+            const u32 j = (u32)(w * 64) + (u32)(__ffsll((unsigned long long)cur) - 1);
+            cur &= cur - 1;
+            const u32 b0 = s_b0[j], b1 = s_b1[j], sl = s_slot[j];
+            for (u32 b = b0; b < b1; ++b) {
+                const vec4<T> pb = LDS ? s_upos[sl + (b - b0)] : posh[b];
+                if (cache_crit<T>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w, bx, rkc)) {
+                    wbuf |= (u64)(sl + (b - b0)) << (16u * (c & 3u));
+                    ++c;
+                    if ((c & 3u) == 0) {
+                        const u32 q = (c >> 2) - 1u;
+                        if (q < capq) out[(u64)q * GROUP] = wbuf;
+                        wbuf = 0;
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <class T>
 __global__ void __launch_bounds__(GROUP)
 k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
               const vec4<T>* __restrict__ bhi, const u32* __restrict__ id, i64 n_internal,
               const GroupMap gm, const InstDev* __restrict__ inst, T rk, T rkc, i64 cap,
               const u32* __restrict__ uleaf, const u32* __restrict__ uslot,
-              const u32* __restrict__ ucnt, const u32* __restrict__ ustot, i64 capj,
-              u16* __restrict__ nlist, u32* __restrict__ ncnt, u32* __restrict__ flags)
+              const u32* __restrict__ ucnt, const u32* __restrict__ ustot, u32 capq,
+              u64* __restrict__ nlist, u32* __restrict__ ncnt, u32* __restrict__ flags)
 {
     __shared__ u32 s_b0[LCHUNK];
     __shared__ u32 s_b1[LCHUNK];
@@ -180,7 +218,6 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     const i64 a = beg + threadIdx.x;
     const bool live = a < end;
     const vec4<T> pa = posh[live ? a : beg];
-    const vec4<T> pl = mk4<T>(pa.x, pa.y, pa.z, pa.w);   // point box
     const u32 nu = min((u32)cap, ucnt[g]);
     const u32 S = ustot[g];
     const bool in_lds = S <= (u32)UCH;
@@ -189,8 +226,9 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         vec4<T>* dst[1] = { s_upos };
         stage_union<T, 1>(src, dst, id, uleaf + g * cap, uslot + g * cap, nu, 0u, S);
     }
-    u16* out = nlist + (u64)g * (u64)capj * GROUP + threadIdx.x;
+    u64* out = nlist + (u64)g * capq * GROUP + threadIdx.x;
     u32 c = 0;
+    u64 wbuf = 0;
     for (u32 c0 = 0; c0 < nu; c0 += LCHUNK) {
         const u32 c1 = min(nu, c0 + LCHUNK);
         __syncthreads();
@@ -204,22 +242,24 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         }
         __syncthreads();
         if (!live) continue;
-        for (u32 j = 0; j < c1 - c0; ++j) {
-            if (!box_hit<T>(pl, pl, s_lo[j], s_hi[j], rk, eps_abs, bx)) continue;
-            const u32 b0 = s_b0[j], b1 = s_b1[j], sl = s_slot[j];
-            for (u32 b = b0; b < b1; ++b) {
-                const vec4<T> pb = in_lds ? s_upos[sl + (b - b0)] : posh[b];
-                if (cache_crit<T>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w, bx, rkc)) {
-                    if (c < capj) out[(u64)c * GROUP] = (u16)(sl + (b - b0));
-                    ++c;
-                }
-            }
-        }
+        if (in_lds)
+            cache_leaves<T, true>(pa, bx, rk, rkc, eps_abs, c1 - c0, s_b0, s_b1, s_slot, s_lo, s_hi,
+                                  s_upos, posh, out, capq, c, wbuf);
+        else
+            cache_leaves<T, false>(pa, bx, rk, rkc, eps_abs, c1 - c0, s_b0, s_b1, s_slot, s_lo,
+                                   s_hi, s_upos, posh, out, capq, c, wbuf);
     }
-    if (live) ncnt[a] = c;
+    if (live) {
+        if (c & 3u) {
+            for (u32 r = c & 3u; r < 4u; ++r) wbuf |= (u64)SLOT_NONE << (16u * r);
+            const u32 q = c >> 2;
+            if (q < capq) out[(u64)q * GROUP] = wbuf;
+        }
+        ncnt[a] = c;
+    }
     const u32 wmax = wave_max(live ? c : 0u);
     if (__lane_id() == 0) {
-        if (wmax > capj) atomicOr(&flags[0], 4u);
+        if (wmax > 4u * capq) atomicOr(&flags[0], 4u);
         if (wmax > __hip_atomic_load(&flags[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(&flags[2], wmax);
     }
@@ -230,7 +270,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
 __global__ void __launch_bounds__(GROUP)
 k_cache_to_global(const u32* __restrict__ id, const GroupMap gm, i64 cap,
                   const u32* __restrict__ uleaf, const u32* __restrict__ uslot,
-                  const u32* __restrict__ ucnt, i64 capj, const u16* __restrict__ nlist,
+                  const u32* __restrict__ ucnt, u32 capq, const u64* __restrict__ nlist,
                   const u32* __restrict__ ncnt, const u64* __restrict__ off, u32* __restrict__ list)
 {
     const i64 g = blockIdx.x;
@@ -244,7 +284,8 @@ k_cache_to_global(const u32* __restrict__ id, const GroupMap gm, i64 cap,
     const u32* ul = uleaf + g * cap;
     const u32 c = ncnt[a];
     for (u32 j = 0; j < c; ++j) {
-        const u32 s = nlist[((u64)g * capj + j) * GROUP + threadIdx.x];
+        const u64 w = nlist[((u64)g * capq + (j >> 2)) * GROUP + threadIdx.x];
+        const u32 s = slot_of(w, j & 3u);
         u32 lo = 0, hi = nu - 1;       // last leaf whose start slot <= s
         while (lo < hi) {
             const u32 mid = (lo + hi + 1) >> 1;
@@ -281,23 +322,23 @@ template <class T>
 void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* bhi, const u32* id,
                         i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
-                        const u32* ucnt, const u32* ustot, i64 capj, u16* nlist, u32* ncnt,
+                        const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
                         u32* flags, hipStream_t st)
 {
     if (ngroups <= 0) return;
     hipLaunchKernelGGL((k_group_cache<T>), dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, blo,
                        bhi, id, n_internal, gm, inst, (T)rk, (T)rkc, cap, uleaf, uslot, ucnt, ustot,
-                       capj, nlist, ncnt, flags);
+                       capq, nlist, ncnt, flags);
 }
 
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
-                            const u32* uleaf, const u32* uslot, const u32* ucnt, i64 capj,
-                            const u16* nlist, const u32* ncnt, const u64* off, u32* list,
+                            const u32* uleaf, const u32* uslot, const u32* ucnt, u32 capq,
+                            const u64* nlist, const u32* ncnt, const u64* off, u32* list,
                             hipStream_t st)
 {
     if (ngroups <= 0) return;
     hipLaunchKernelGGL(k_cache_to_global, dim3((unsigned)ngroups), dim3(GROUP), 0, st, id, gm, cap,
-                       uleaf, uslot, ucnt, capj, nlist, ncnt, off, list);
+                       uleaf, uslot, ucnt, capq, nlist, ncnt, off, list);
 }
 
 #define INST(T)                                                                                   \
@@ -310,7 +351,7 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
     template void launch_group_cache<T>(const vec4<T>*, const vec4<T>*, const vec4<T>*,           \
                                         const u32*, i64, const GroupMap&, i64, const InstDev*,    \
                                         double, double, i64, const u32*, const u32*, const u32*,  \
-                                        const u32*, i64, u16*, u32*, u32*, hipStream_t);
+                                        const u32*, u32, u64*, u32*, u32*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -49,6 +49,34 @@ template <class T> __global__ void k_copy_h(const vec4<T>* __restrict__ posh, T*
 }
 
 
+// Visit the cache entries of one particle (ELL words `my`, cnt entries).
+// One LDS tile: all entries, four per word, padding skipped.  Several
+// tiles: entries with slots in [c0, c1), resuming at entry j.
+template <class F> __device__ inline void entries_all(const u64* my, u32 cnt, F&& f)
+{
+    const u32 nq = (cnt + 3u) >> 2;
+    for (u32 q = 0; q < nq; ++q) {
+        const u64 w = my[(u64)q * GROUP];
+#pragma unroll
+        for (u32 r = 0; r < 4u; ++r) {
+            const u32 sl = slot_of(w, r);
+            if (sl != SLOT_NONE) f(sl);
+        }
+    }
+}
+
+template <class F>
+__device__ inline void entries_tile(const u64* my, u32 cnt, u32& j, u32 c0, u32 c1, F&& f)
+{
+    while (j < cnt) {
+        const u64 w = my[(u64)(j >> 2) * GROUP];
+        const u32 sl = slot_of(w, j & 3u);
+        if (sl >= c1) break;
+        f(sl - c0);
+        ++j;
+    }
+}
+
 // Block-wide reduction helpers for per-instance statistics: the block's
 // lanes usually share one instance, then a single atomic per block is done
 // (and min/max atomics only when they can change the stored value).
@@ -125,7 +153,7 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
     const u32 nch = (S + CH - 1) / CH;
     const u32* ul = cv.uleaf + g * cv.cap;
     const u32* us = cv.uslot + g * cv.cap;
-    const u16* my = cv.nlist + (u64)g * (u64)cv.capj * GROUP + threadIdx.x;
+    const u64* my = cv.nlist + (u64)g * cv.capq * GROUP + threadIdx.x;
     const vec4<T>* src[1] = { posh };
     vec4<T>* dst[1] = { s_pos };
     T h = pa.w, h_eval = pa.w, dsum = T(0);
@@ -136,30 +164,34 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
         const T hinv = T(1) / h;
         const T h2x4 = T(4) * h * h;
         T s = T(0), ds = T(0);
-        u32 j = 0;
-        for (u32 ch = 0; ch < nch; ++ch) {
-            const u32 c0 = ch * CH, c1 = min(S, c0 + CH);
-            if (nch > 1 || it == 0) {
+        auto add = [&](u32 sl) {
+            const vec4<T> pb = s_pos[sl];
+            const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
+            const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
+            const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < h2x4) {
+                const T q = fast_sqrt(r2) * hinv;
+                T f, df;
+                m4<T>(q, f, df);
+                s += f;
+                ds -= T(3) * f + q * df;
+            }
+        };
+        if (nch == 1) {
+            if (it == 0) {
+                stage_union<T, 1>(src, dst, id, ul, us, nu, 0u, S);
+                __syncthreads();
+            }
+            if (active) entries_all(my, cnt, add);
+        } else {
+            u32 j = 0;
+            for (u32 ch = 0; ch < nch; ++ch) {
+                const u32 c0 = ch * CH, c1 = min(S, c0 + CH);
                 __syncthreads();
                 stage_union<T, 1>(src, dst, id, ul, us, nu, c0, c1);
                 __syncthreads();
-            }
-            if (!active) continue;
-            for (; j < cnt; ++j) {
-                const u32 slot = my[(u64)j * GROUP];
-                if (slot >= c1) break;
-                const vec4<T> pb = s_pos[slot - c0];
-                const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
-                const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
-                const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
-                const T r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < h2x4) {
-                    const T q = fast_sqrt(r2) * hinv;
-                    T f, df;
-                    m4<T>(q, f, df);
-                    s += f;
-                    ds -= T(3) * f + q * df;
-                }
+                if (active) entries_tile(my, cnt, j, c0, c1, add);
             }
         }
         if (active) {
@@ -261,51 +293,55 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     const u32 nch = (S + CH - 1) / CH;
     const u32* ul = cv.uleaf + g * cv.cap;
     const u32* us = cv.uslot + g * cv.cap;
-    const u16* my = cv.nlist + (u64)g * (u64)cv.capj * GROUP + threadIdx.x;
+    const u64* my = cv.nlist + (u64)g * cv.capq * GROUP + threadIdx.x;
     const vec4<T>* src[3] = { posh, velu, thermo };
     vec4<T>* dst[3] = { s_pos, s_vel, s_thm };
     T ax = T(0), ay = T(0), az = T(0), du = T(0), lam = T(0), vmax = ca;
-    u32 j = 0;
-    for (u32 ch = 0; ch < nch; ++ch) {
-        const u32 c0 = ch * CH, c1 = min(S, c0 + CH);
+    auto pair = [&](u32 sl) {
+        const vec4<T> pb = s_pos[sl];
+        const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
+        const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
+        const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const T hb = pb.w;
+        const T hm = ha > hb ? ha : hb;
+        if (!(r2 > T(0)) || !(r2 < T(4) * hm * hm)) return;
+        const vec4<T> vb = s_vel[sl], tb = s_thm[sl];
+        const T rinv = fast_rsq(r2), r = r2 * rinv;
+        const T ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+        const T w = (va.x - vb.x) * ex + (va.y - vb.y) * ey + (va.z - vb.z) * ez;
+        const T hib = fast_rcp(hb);
+        const T Fa = m4_df<T>(r * hia) * hia4;
+        const T Fb = m4_df<T>(r * hib) * (hib * hib * hib * hib * inv_pi<T>());
+        const T aw = fabs(w);
+        const T vsa = alpha * ca + beta * aw;
+        const T vsb = alpha * tb.z + beta * aw;
+        const T wn = w < T(0) ? w : T(0);
+        const T ka = (Aa - T(0.5) * vsa * wn * Ba) * Fa;
+        const T kb = (tb.x - T(0.5) * vsb * wn * tb.y) * Fb;
+        const T fab = m * (ka + kb);
+        ax -= fab * ex;
+        ay -= fab * ey;
+        az -= fab * ez;
+        du += m * ka * w;
+        const T hfb = hfact * hib;
+        const T rhob = m * hfb * hfb * hfb;
+        const T vsu = fast_sqrt(fabs(Pa - tb.w)) * fast_rsq(T(0.5) * (rhoa + rhob));
+        lam += m * beta_u * vsu * (va.w - vb.w) * T(0.5) * (Fa * Ba + Fb * tb.y);
+        vmax = vsa > vmax ? vsa : vmax;
+    };
+    if (nch == 1) {
+        stage_union<T, 3>(src, dst, id, ul, us, nu, 0u, S);
         __syncthreads();
-        stage_union<T, 3>(src, dst, id, ul, us, nu, c0, c1);
-        __syncthreads();
-        for (; j < cnt; ++j) {
-            const u32 slot = my[(u64)j * GROUP];
-            if (slot >= c1) break;
-            const u32 sl = slot - c0;
-            const vec4<T> pb = s_pos[sl];
-            const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
-            const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
-            const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
-            const T r2 = dx * dx + dy * dy + dz * dz;
-            const T hb = pb.w;
-            const T hm = ha > hb ? ha : hb;
-            if (!(r2 > T(0)) || !(r2 < T(4) * hm * hm)) continue;
-            const vec4<T> vb = s_vel[sl], tb = s_thm[sl];
-            const T rinv = fast_rsq(r2), r = r2 * rinv;
-            const T ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-            const T w = (va.x - vb.x) * ex + (va.y - vb.y) * ey + (va.z - vb.z) * ez;
-            const T hib = fast_rcp(hb);
-            const T Fa = m4_df<T>(r * hia) * hia4;
-            const T Fb = m4_df<T>(r * hib) * (hib * hib * hib * hib * inv_pi<T>());
-            const T aw = fabs(w);
-            const T vsa = alpha * ca + beta * aw;
-            const T vsb = alpha * tb.z + beta * aw;
-            const T wn = w < T(0) ? w : T(0);
-            const T ka = (Aa - T(0.5) * vsa * wn * Ba) * Fa;
-            const T kb = (tb.x - T(0.5) * vsb * wn * tb.y) * Fb;
-            const T fab = m * (ka + kb);
-            ax -= fab * ex;
-            ay -= fab * ey;
-            az -= fab * ez;
-            du += m * ka * w;
-            const T hfb = hfact * hib;
-            const T rhob = m * hfb * hfb * hfb;
-            const T vsu = fast_sqrt(fabs(Pa - tb.w)) * fast_rsq(T(0.5) * (rhoa + rhob));
-            lam += m * beta_u * vsu * (va.w - vb.w) * T(0.5) * (Fa * Ba + Fb * tb.y);
-            vmax = vsa > vmax ? vsa : vmax;
+        entries_all(my, cnt, pair);
+    } else {
+        u32 j = 0;
+        for (u32 ch = 0; ch < nch; ++ch) {
+            const u32 c0 = ch * CH, c1 = min(S, c0 + CH);
+            __syncthreads();
+            stage_union<T, 3>(src, dst, id, ul, us, nu, c0, c1);
+            __syncthreads();
+            entries_tile(my, cnt, j, c0, c1, pair);
         }
     }
     float dta = __int_as_float(0x7f800000);

@@ -24,26 +24,30 @@ __device__ inline void predict(const T* const* xp, const T* const* vp, const T* 
                                const T* u, const T* du, i64 j, T dt, const Box<T>& bx,
                                Pred<T>& o)
 {
-    const T hdt = mul_rn(T(0.5), dt);
+#pragma clang fp contract(off)
+    const T hdt = T(0.5) * dt;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const T a = ap ? ap[d][j] : T(0);
         const T v = vp ? vp[d][j] : T(0);
-        const T vh = add_rn(v, mul_rn(hdt, a));
-        T x = add_rn(xp[d][j], mul_rn(dt, vh));
+        const T ka = hdt * a;
+        const T vh = v + ka;
+        const T dx = dt * vh;
+        T x = xp[d][j] + dx;
         if (bx.periodic) {
-            if (x >= bx.hi[d]) x = sub_rn(x, bx.L[d]);
-            if (x < bx.lo[d]) x = add_rn(x, bx.L[d]);
+            if (x >= bx.hi[d]) x = x - bx.L[d];
+            if (x < bx.lo[d]) x = x + bx.L[d];
             if (x >= bx.hi[d]) x = bx.lo[d];
         }
         o.x[d] = x;
         o.vh[d] = vh;
-        o.vs[d] = add_rn(vh, mul_rn(hdt, a));
+        o.vs[d] = vh + ka;
     }
     const T uu = u ? u[j] : T(0);
     const T dd = du ? du[j] : T(0);
-    o.uh = add_rn(uu, mul_rn(hdt, dd));
-    o.us = add_rn(o.uh, mul_rn(hdt, dd));
+    const T kd = hdt * dd;
+    o.uh = uu + kd;
+    o.us = o.uh + kd;
 }
 
 // Morton key (App. C.1): X = min(2^21-1, max(0, floor((x - lo) * 2^21/(hi - lo))))
@@ -61,7 +65,9 @@ __device__ inline u64 spread3(u32 v)
 
 __device__ inline u32 quantize(double v, double lo, double scale)
 {
-    const double t = __dmul_rn(__dsub_rn(v, lo), scale);
+#pragma clang fp contract(off)
+    const double d = v - lo;
+    const double t = d * scale;
     const double f = floor(t);
     if (!(f >= 0.0)) return 0u;
     if (f > (double)MORTON_MAX) return MORTON_MAX;
