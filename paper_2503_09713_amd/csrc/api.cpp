@@ -70,6 +70,7 @@ struct shsph_ctx {
     Buf glo, ghi, uleaf, uslot, ucnt, ustot;    // stage 1, per group
     Buf nlist, ncnt, flags;                     // stage 2, per particle (ELL)
     Buf bpart;                                  // corrector partial sums
+    i64 parts_pending = 0;                      // corrector blocks not yet folded
     Buf inst_d, poff_d, goff_d, leaf_off_d, ioff_d, root_d, stat_d, dt_inst_d, dt_host_d;
     Buf pbox, plen, xoff, xlist;                // export only
 
@@ -287,6 +288,9 @@ CacheView cache_view(shsph_ctx* c)
     v.cap = c->cap_leaf;
     v.nlist = P<u64>(c->nlist); v.ncnt = P<u32>(c->ncnt);
     v.capq = (u32)c->cap_words;
+    v.glo = c->glo.p; v.ghi = c->ghi.p; v.blo = c->blo.p;
+    v.root = P<u32>(c->root_d);
+    v.rk = 2.0 * c->prm.chi;
     return v;
 }
 
@@ -408,7 +412,7 @@ template <class T> int build_caches(shsph_ctx* c)
     const double rk = 2.0 * c->prm.chi;
     // bottom-up boxes and h_max
     const size_t nrc = boxes_rec_count(nl);
-    const i64 nbb = (i64)(nrc / 128);
+    const i64 nbb = (i64)(nrc / 128) + 1;
     TRY(ensure(c, c->rec, nrc * sizeof(u32)));
     TRY(ensure(c, c->nrec, (nbb + 1) * sizeof(u32)));
     TRY(ensure(c, c->rscan, (nbb + 1) * sizeof(u32)));
@@ -446,7 +450,8 @@ template <class T> int build_caches(shsph_ctx* c)
         launch_group_cache<T>(posh, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->id), ni, gm, G,
                               inst, rk, rk, c->cap_leaf, P<u32>(c->uleaf), P<u32>(c->uslot),
                               P<u32>(c->ucnt), P<u32>(c->ustot), (u32)c->cap_words, P<u64>(c->nlist),
-                              P<u32>(c->ncnt), P<u32>(c->flags), st);
+                              P<u32>(c->ncnt), P<u32>(c->flags), P<vec4<T>>(c->glo),
+                              P<vec4<T>>(c->ghi), P<u32>(c->root_d), st);
         prof_end(c);
         TRY(check_launch(c, "stage2"));
         HIPTRY(c, hipMemcpyAsync(c->pinned, c->flags.p, 4 * sizeof(u32), hipMemcpyDeviceToHost, st));
@@ -491,6 +496,7 @@ template <class T> int run_density(shsph_ctx* c, bool with_thermo)
     if (!with_thermo) s.velu = nullptr;
     for (int attempt = 0;; ++attempt) {
         launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
+        c->parts_pending = 0;
         prof_begin(c, S_DENSITY);
         launch_density<T>(s, P<u32>(c->id), group_map(c), c->n_groups, P<InstDev>(c->inst_d), sp,
                           cache_view(c), P<T>(c->omega),
@@ -565,6 +571,7 @@ template <class T> int do_force(shsph_ctx* c, shsph_particles* p)
                      c->ninst, P<InstDev>(c->inst_d), c->prm.hfact, c->prm.gamma,
                      P<vec4<T>>(c->thermo), st);
     launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
+        c->parts_pending = 0;
     const SphParams sp = sph_params(c->prm);
     prof_begin(c, S_FORCE);
     launch_force<T>(sorted<T>(c, false), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
@@ -607,6 +614,7 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
     const i64 n = c->n;
     TRY(ensure(c, c->acc, n * sizeof(vec4<T>)));
     launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
+        c->parts_pending = 0;
     const SphParams sp = sph_params(c->prm);
     prof_begin(c, S_FORCE);
     launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
@@ -625,6 +633,7 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
     launch_correct<T>(sorted<T>(c, true), P<vec4<T>>(c->acc), P<T>(c->omega), n, P<i64>(c->poff_d),
                       c->ninst, P<InstDev>(c->inst_d), dt_dev, c->prm.hfact, o,
                       P<InstStat>(c->stat_d), P<BlockPart>(c->bpart), st);
+    c->parts_pending = (n + GROUP - 1) / GROUP;
     prof_end(c);
     TRY(check_launch(c, "correct"));
     if (dt_used) {
@@ -794,6 +803,7 @@ const char* shsph_stage_name(int32_t i) { return (i >= 0 && i < S_NUM) ? STAGE_N
 int shsph_get_info(shsph_ctx* c, shsph_info* o)
 {
     if (!c || !o) return SHSPH_EINVAL;
+    c->err.clear();
     memset(o, 0, sizeof(*o));
     o->n = c->n;
     o->n_leaf = c->n_leaf;
@@ -809,6 +819,11 @@ int shsph_get_info(shsph_ctx* c, shsph_info* o)
         o->n_neigh = (int64_t)t2;
     }
     if (c->stat_d.p && c->ninst >= 1) {
+        if (c->parts_pending > 0) {
+            launch_fold_parts(P<BlockPart>(c->bpart), c->parts_pending, c->ninst,
+                              P<InstStat>(c->stat_d), c->stream);
+            c->parts_pending = 0;
+        }
         InstStat s;
         HIPTRY(c, hipMemcpyAsync(c->pinned, c->stat_d.p, sizeof(InstStat), hipMemcpyDeviceToHost,
                                  c->stream));

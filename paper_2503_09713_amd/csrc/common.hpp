@@ -186,20 +186,35 @@ template <class T> __device__ inline T min_image(T d, T L, T halfL, int periodic
 // Object-object criterion of the cache (App. F, chi-extended radius), in T:
 //   dx = x_b - x_a (min image), r2 = (dx*dx + dy*dy) + dz*dz,
 //   rc = rkc * max(h_a, h_b), accept iff r2 < rc*rc.
-template <class T>
+template <class T, bool WRAP = true>
 __device__ inline bool cache_crit(T xa, T ya, T za, T ha, T xb, T yb, T zb, T hb,
                                   const Box<T>& bx, T rkc)
 {
 #pragma clang fp contract(off)
-    const T dx = min_image(xb - xa, bx.L[0], bx.halfL[0], bx.periodic);
-    const T dy = min_image(yb - ya, bx.L[1], bx.halfL[1], bx.periodic);
-    const T dz = min_image(zb - za, bx.L[2], bx.halfL[2], bx.periodic);
+    const int per = WRAP ? bx.periodic : 0;
+    const T dx = min_image(xb - xa, bx.L[0], bx.halfL[0], per);
+    const T dy = min_image(yb - ya, bx.L[1], bx.halfL[1], per);
+    const T dz = min_image(zb - za, bx.L[2], bx.halfL[2], per);
     const T xx = dx * dx, yy = dy * dy, zz = dz * dz;
     const T r2 = (xx + yy) + zz;
     const T hm = ha > hb ? ha : hb;
     const T rc = rkc * hm;
     const T rc2 = rc * rc;
     return r2 < rc2;
+}
+
+// A group is interior when its box grown by the largest cache radius
+// (rk * h_max of the whole tree, inflated) stays inside the periodic box: then
+// every cached pair is closer than half a period and the minimum image is the
+// identity, so it can be skipped exactly.
+template <class T>
+__device__ inline bool group_interior(const vec4<T>& gl, const vec4<T>& gh, T hmax_all, T rk,
+                                      const Box<T>& bx)
+{
+    if (!bx.periodic) return true;
+    const T r = rk * hmax_all * T(1.001) + T(1e-5) * (bx.L[0] + bx.L[1] + bx.L[2]);
+    return gl.x - r > bx.lo[0] && gl.y - r > bx.lo[1] && gl.z - r > bx.lo[2] &&
+           gh.x + r < bx.hi[0] && gh.y + r < bx.hi[1] && gh.z + r < bx.hi[2];
 }
 
 // The group cache stores four 16-bit union slots per 64-bit word, ELL

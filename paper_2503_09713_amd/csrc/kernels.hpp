@@ -47,6 +47,10 @@ struct CacheView {
     const u64* nlist;
     const u32* ncnt;
     u32 capq;
+    const void *glo, *ghi;    // group boxes (vec4<T>) for the interior test
+    const void* blo;          // node boxes: h_max of each instance's root
+    const u32* root;
+    double rk;                // R chi
 };
 
 // Per-block partial sums of the corrector (instance id, or -1 if the block
@@ -118,7 +122,8 @@ void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* 
                         i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
                         const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
-                        u32* flags, hipStream_t st);
+                        u32* flags, const vec4<T>* glo, const vec4<T>* ghi, const u32* root,
+                        hipStream_t st);
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
                             const u32* uleaf, const u32* uslot, const u32* ucnt, u32 capq,
                             const u64* nlist, const u32* ncnt, const u64* off, u32* list,
@@ -143,6 +148,7 @@ void launch_correct(const SortedPtrs<T>& s, const vec4<T>* acc, const T* omega, 
                     const i64* p_off, int ninst, const InstDev* inst, const double* dt_inst,
                     double hfact, const OutPtrs<T>& o, InstStat* stat, BlockPart* part,
                     hipStream_t st);
+void launch_fold_parts(const BlockPart* part, i64 nblocks, int ninst, InstStat* stat, hipStream_t st);
 template <class T>
 void launch_gather_velu(const u32* eps, i64 n, const T* vx, const T* vy, const T* vz, const T* u,
                         vec4<T>* velu, hipStream_t st);

@@ -159,7 +159,7 @@ k_group_leaves(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
 // Each lane first marks the union leaves whose box passes the point-box
 // prune (bitmask over an LDS tile of leaves), then walks only the particles
 // of its own marked leaves, reading positions from LDS.
-template <class T, bool LDS>
+template <class T, bool LDS, bool WRAP>
 __device__ inline void cache_leaves(const vec4<T>& pa, const Box<T>& bx, T rk, T rkc, T eps_abs,
                                     u32 nl, const u32* s_b0, const u32* s_b1, const u32* s_slot,
                                     const vec4<T>* s_lo, const vec4<T>* s_hi,
@@ -180,7 +180,7 @@ __device__ inline void cache_leaves(const vec4<T>& pa, const Box<T>& bx, T rk, T
             const u32 b0 = s_b0[j], b1 = s_b1[j], sl = s_slot[j];
             for (u32 b = b0; b < b1; ++b) {
                 const vec4<T> pb = LDS ? s_upos[sl + (b - b0)] : posh[b];
-                if (cache_crit<T>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w, bx, rkc)) {
+                if (cache_crit<T, WRAP>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w, bx, rkc)) {
                     wbuf |= (u64)(sl + (b - b0)) << (16u * (c & 3u));
                     ++c;
                     if ((c & 3u) == 0) {
@@ -201,7 +201,9 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
               const GroupMap gm, const InstDev* __restrict__ inst, T rk, T rkc, i64 cap,
               const u32* __restrict__ uleaf, const u32* __restrict__ uslot,
               const u32* __restrict__ ucnt, const u32* __restrict__ ustot, u32 capq,
-              u64* __restrict__ nlist, u32* __restrict__ ncnt, u32* __restrict__ flags)
+              u64* __restrict__ nlist, u32* __restrict__ ncnt, u32* __restrict__ flags,
+              const vec4<T>* __restrict__ glo, const vec4<T>* __restrict__ ghi,
+              const u32* __restrict__ root)
 {
     __shared__ u32 s_b0[LCHUNK];
     __shared__ u32 s_b1[LCHUNK];
@@ -221,6 +223,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     const u32 nu = min((u32)cap, ucnt[g]);
     const u32 S = ustot[g];
     const bool in_lds = S <= (u32)UCH;
+    const bool interior = group_interior<T>(glo[g], ghi[g], blo[root[k]].w, rk, bx);
     if (in_lds) {
         const vec4<T>* src[1] = { posh };
         vec4<T>* dst[1] = { s_upos };
@@ -242,12 +245,15 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         }
         __syncthreads();
         if (!live) continue;
-        if (in_lds)
-            cache_leaves<T, true>(pa, bx, rk, rkc, eps_abs, c1 - c0, s_b0, s_b1, s_slot, s_lo, s_hi,
-                                  s_upos, posh, out, capq, c, wbuf);
+        if (in_lds && interior)
+            cache_leaves<T, true, false>(pa, bx, rk, rkc, eps_abs, c1 - c0, s_b0, s_b1, s_slot,
+                                         s_lo, s_hi, s_upos, posh, out, capq, c, wbuf);
+        else if (in_lds)
+            cache_leaves<T, true, true>(pa, bx, rk, rkc, eps_abs, c1 - c0, s_b0, s_b1, s_slot,
+                                        s_lo, s_hi, s_upos, posh, out, capq, c, wbuf);
         else
-            cache_leaves<T, false>(pa, bx, rk, rkc, eps_abs, c1 - c0, s_b0, s_b1, s_slot, s_lo,
-                                   s_hi, s_upos, posh, out, capq, c, wbuf);
+            cache_leaves<T, false, true>(pa, bx, rk, rkc, eps_abs, c1 - c0, s_b0, s_b1, s_slot,
+                                         s_lo, s_hi, s_upos, posh, out, capq, c, wbuf);
     }
     if (live) {
         if (c & 3u) {
@@ -323,12 +329,13 @@ void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* 
                         i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
                         const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
-                        u32* flags, hipStream_t st)
+                        u32* flags, const vec4<T>* glo, const vec4<T>* ghi, const u32* root,
+                        hipStream_t st)
 {
     if (ngroups <= 0) return;
     hipLaunchKernelGGL((k_group_cache<T>), dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, blo,
                        bhi, id, n_internal, gm, inst, (T)rk, (T)rkc, cap, uleaf, uslot, ucnt, ustot,
-                       capq, nlist, ncnt, flags);
+                       capq, nlist, ncnt, flags, glo, ghi, root);
 }
 
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
@@ -351,7 +358,8 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
     template void launch_group_cache<T>(const vec4<T>*, const vec4<T>*, const vec4<T>*,           \
                                         const u32*, i64, const GroupMap&, i64, const InstDev*,    \
                                         double, double, i64, const u32*, const u32*, const u32*,  \
-                                        const u32*, u32, u64*, u32*, u32*, hipStream_t);
+                                        const u32*, u32, u64*, u32*, u32*, const vec4<T>*,        \
+                                        const vec4<T>*, const u32*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

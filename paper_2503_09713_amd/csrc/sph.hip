@@ -160,15 +160,18 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
     int st = 1;   // 0 converged, 1 not converged, 2 chi exceeded
     int iters = 0;
     bool active = live;
+    const int per = group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
+                                      ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx)
+                        ? 0 : bx.periodic;
     for (int it = 0; it < P.max_iter; ++it) {
         const T hinv = T(1) / h;
         const T h2x4 = T(4) * h * h;
         T s = T(0), ds = T(0);
         auto add = [&](u32 sl) {
             const vec4<T> pb = s_pos[sl];
-            const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
-            const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
-            const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
+            const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], per);
+            const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], per);
+            const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], per);
             const T r2 = dx * dx + dy * dy + dz * dz;
             if (r2 < h2x4) {
                 const T q = fast_sqrt(r2) * hinv;
@@ -297,11 +300,14 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     const vec4<T>* src[3] = { posh, velu, thermo };
     vec4<T>* dst[3] = { s_pos, s_vel, s_thm };
     T ax = T(0), ay = T(0), az = T(0), du = T(0), lam = T(0), vmax = ca;
+    const int per = group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
+                                      ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx)
+                        ? 0 : bx.periodic;
     auto pair = [&](u32 sl) {
         const vec4<T> pb = s_pos[sl];
-        const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
-        const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
-        const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
+        const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], per);
+        const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], per);
+        const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], per);
         const T r2 = dx * dx + dy * dy + dz * dz;
         const T hb = pb.w;
         const T hm = ha > hb ? ha : hb;
@@ -581,7 +587,12 @@ void launch_correct(const SortedPtrs<T>& s, const vec4<T>* acc, const T* omega, 
     hipLaunchKernelGGL((k_correct<T>), dim3((unsigned)nb), dim3(GROUP), 0, st, s.posh, s.velu,
                        s.vhalf, acc, omega, s.pid, n, p_off, ninst, inst, dt_inst, hfact, o, stat,
                        part);
-    hipLaunchKernelGGL(k_fold_parts, dim3((unsigned)ninst), dim3(GROUP), 0, st, part, nb, stat);
+}
+
+void launch_fold_parts(const BlockPart* part, i64 nblocks, int ninst, InstStat* stat, hipStream_t st)
+{
+    if (nblocks > 0)
+        hipLaunchKernelGGL(k_fold_parts, dim3((unsigned)ninst), dim3(GROUP), 0, st, part, nblocks, stat);
 }
 
 template <class T>

@@ -279,7 +279,7 @@ __global__ void k_karras(const u64* __restrict__ mu_leaf, const i64* __restrict_
 // device-wide fence is needed anywhere.
 // Node layout: lo = (xmin, ymin, zmin, hmax), hi = (xmax, ymax, zmax, 0).
 // ---------------------------------------------------------------------------
-constexpr int BOX_BLK = 256;
+constexpr int BOX_BLK = 1024;
 constexpr int BOX_OUT = 128;     // records per block: at most 2 * depth <= 126
 constexpr int TOP_BLOCK = 1024;
 
@@ -384,35 +384,33 @@ k_boxes_local(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 
 
 template <class T>
 __global__ void __launch_bounds__(TOP_BLOCK)
-k_boxes_top(const u32* __restrict__ rec, const u32* __restrict__ rscan, i64 nblocks,
+k_boxes_top(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nblocks,
             const u32* __restrict__ child, const u32* __restrict__ parent,
             u32* __restrict__ arrive, vec4<T>* blo, vec4<T>* bhi)
 {
-    const u32 total = rscan[nblocks];
-    for (u32 r = threadIdx.x; r < total; r += TOP_BLOCK) {
-        i64 lo = 0, hi = nblocks - 1;       // block holding record r
-        while (lo < hi) {
-            const i64 mid = (lo + hi + 1) >> 1;
-            if (rscan[mid] <= r) lo = mid; else hi = mid - 1;
-        }
-        u32 node = rec[lo * BOX_OUT + (r - rscan[lo])];
-        vec4<T> ml = blo[node], mh = bhi[node];
-        while (true) {
-            const u32 par = parent[node];
-            if (par == 0xffffffffu) break;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            const u32 prev = __hip_atomic_fetch_add(&arrive[par], 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (prev == 0) break;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
-            const u32 other = (c0 == node) ? c1 : c0;
-            const vec4<T> ol = blo[other], oh = bhi[other];
-            ml = mk4<T>(fmin(ml.x, ol.x), fmin(ml.y, ol.y), fmin(ml.z, ol.z), fmax(ml.w, ol.w));
-            mh = mk4<T>(fmax(mh.x, oh.x), fmax(mh.y, oh.y), fmax(mh.z, oh.z), T(0));
-            blo[par] = ml;
-            bhi[par] = mh;
-            node = par;
+    // thread t finishes the climbs recorded by blocks t, t + TOP_BLOCK, ...
+    for (i64 b = threadIdx.x; b < nblocks; b += TOP_BLOCK) {
+        const u32 nr = nrec[b];
+        for (u32 q = 0; q < nr; ++q) {
+            u32 node = rec[b * BOX_OUT + q];
+            vec4<T> ml = blo[node], mh = bhi[node];
+            while (true) {
+                const u32 par = parent[node];
+                if (par == 0xffffffffu) break;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                const u32 prev = __hip_atomic_fetch_add(&arrive[par], 1u, __ATOMIC_ACQ_REL,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (prev == 0) break;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
+                const u32 other = (c0 == node) ? c1 : c0;
+                const vec4<T> ol = blo[other], oh = bhi[other];
+                ml = mk4<T>(fmin(ml.x, ol.x), fmin(ml.y, ol.y), fmin(ml.z, ol.z), fmax(ml.w, ol.w));
+                mh = mk4<T>(fmax(mh.x, oh.x), fmax(mh.y, oh.y), fmax(mh.z, oh.z), T(0));
+                blo[par] = ml;
+                bhi[par] = mh;
+                node = par;
+            }
         }
     }
 }
@@ -639,11 +637,9 @@ void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 n_leaf, i64 n_inter
     hipLaunchKernelGGL((k_boxes_local<T>), dim3((unsigned)nb), dim3(BOX_BLK), 0, st, posh, id, n_leaf,
                        n_internal, child, parent, endrange, ioff, leaf_off, ninst, blo, bhi, rec,
                        nrec, flags);
-    if (nb > 1) {
-        scan_u32_u32(nrec, rscan, nb, scan_tmp, st);
-        hipLaunchKernelGGL((k_boxes_top<T>), dim3(1), dim3(TOP_BLOCK), 0, st, rec, rscan, nb, child,
+    if (nb > 1)
+        hipLaunchKernelGGL((k_boxes_top<T>), dim3(1), dim3(TOP_BLOCK), 0, st, rec, nrec, nb, child,
                            parent, arrive, blo, bhi);
-    }
 }
 
 size_t boxes_rec_count(i64 n_leaf) { return (size_t)((n_leaf + BOX_BLK - 1) / BOX_BLK) * BOX_OUT; }
