@@ -55,13 +55,15 @@ template <class T> __global__ void k_copy_h(const vec4<T>* __restrict__ posh, T*
 template <class F> __device__ inline void entries_all(const u64* my, u32 cnt, F&& f)
 {
     const u32 nq = (cnt + 3u) >> 2;
+    u64 w = nq ? my[0] : 0;
     for (u32 q = 0; q < nq; ++q) {
-        const u64 w = my[(u64)q * GROUP];
+        const u64 wn = (q + 1 < nq) ? my[(u64)(q + 1) * GROUP] : 0;   // prefetch
 #pragma unroll
         for (u32 r = 0; r < 4u; ++r) {
             const u32 sl = slot_of(w, r);
             if (sl != SLOT_NONE) f(sl);
         }
+        w = wn;
     }
 }
 
@@ -160,19 +162,13 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
     int st = 1;   // 0 converged, 1 not converged, 2 chi exceeded
     int iters = 0;
     bool active = live;
-    const int per = group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
-                                      ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx)
-                        ? 0 : bx.periodic;
+    const bool wrap = !group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
+                                         ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx);
     for (int it = 0; it < P.max_iter; ++it) {
         const T hinv = T(1) / h;
         const T h2x4 = T(4) * h * h;
         T s = T(0), ds = T(0);
-        auto add = [&](u32 sl) {
-            const vec4<T> pb = s_pos[sl];
-            const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], per);
-            const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], per);
-            const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], per);
-            const T r2 = dx * dx + dy * dy + dz * dz;
+        auto add_r2 = [&](T r2) {
             if (r2 < h2x4) {
                 const T q = fast_sqrt(r2) * hinv;
                 T f, df;
@@ -181,12 +177,27 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
                 ds -= T(3) * f + q * df;
             }
         };
+        auto add = [&](u32 sl) {          // any group: minimum image
+            const vec4<T> pb = s_pos[sl];
+            const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
+            const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
+            const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
+            add_r2(dx * dx + dy * dy + dz * dz);
+        };
+        auto add_in = [&](u32 sl) {       // interior group: no image can be closer
+            const vec4<T> pb = s_pos[sl];
+            const T dx = pa.x - pb.x, dy = pa.y - pb.y, dz = pa.z - pb.z;
+            add_r2(dx * dx + dy * dy + dz * dz);
+        };
         if (nch == 1) {
             if (it == 0) {
                 stage_union<T, 1>(src, dst, id, ul, us, nu, 0u, S);
                 __syncthreads();
             }
-            if (active) entries_all(my, cnt, add);
+            if (active) {
+                if (wrap) entries_all(my, cnt, add);
+                else entries_all(my, cnt, add_in);
+            }
         } else {
             u32 j = 0;
             for (u32 ch = 0; ch < nch; ++ch) {
@@ -300,14 +311,9 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     const vec4<T>* src[3] = { posh, velu, thermo };
     vec4<T>* dst[3] = { s_pos, s_vel, s_thm };
     T ax = T(0), ay = T(0), az = T(0), du = T(0), lam = T(0), vmax = ca;
-    const int per = group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
-                                      ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx)
-                        ? 0 : bx.periodic;
-    auto pair = [&](u32 sl) {
-        const vec4<T> pb = s_pos[sl];
-        const T dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], per);
-        const T dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], per);
-        const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], per);
+    const bool wrap = !group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
+                                         ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx);
+    auto pair_d = [&](u32 sl, T dx, T dy, T dz, const vec4<T>& pb) {
         const T r2 = dx * dx + dy * dy + dz * dz;
         const T hb = pb.w;
         const T hm = ha > hb ? ha : hb;
@@ -336,10 +342,21 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         lam += m * beta_u * vsu * (va.w - vb.w) * T(0.5) * (Fa * Ba + Fb * tb.y);
         vmax = vsa > vmax ? vsa : vmax;
     };
+    auto pair = [&](u32 sl) {             // any group: minimum image
+        const vec4<T> pb = s_pos[sl];
+        pair_d(sl, min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic),
+               min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic),
+               min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic), pb);
+    };
+    auto pair_in = [&](u32 sl) {          // interior group: no image can be closer
+        const vec4<T> pb = s_pos[sl];
+        pair_d(sl, pa.x - pb.x, pa.y - pb.y, pa.z - pb.z, pb);
+    };
     if (nch == 1) {
         stage_union<T, 3>(src, dst, id, ul, us, nu, 0u, S);
         __syncthreads();
-        entries_all(my, cnt, pair);
+        if (wrap) entries_all(my, cnt, pair);
+        else entries_all(my, cnt, pair_in);
     } else {
         u32 j = 0;
         for (u32 ch = 0; ch < nch; ++ch) {
