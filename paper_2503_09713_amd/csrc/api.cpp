@@ -447,7 +447,8 @@ template <class T> int build_caches(shsph_ctx* c)
         TRY(check_launch(c, "stage1"));
         // stage 2: particle neighbours as union slots
         prof_begin(c, S_STAGE2);
-        launch_group_cache<T>(posh, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->id), ni, gm, G,
+        launch_group_cache<T>(posh, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->id),
+                              P<u32>(c->xscan), ni, gm, G,
                               inst, rk, rk, c->cap_leaf, P<u32>(c->uleaf), P<u32>(c->uslot),
                               P<u32>(c->ucnt), P<u32>(c->ustot), (u32)c->cap_words, P<u64>(c->nlist),
                               P<u32>(c->ncnt), P<u32>(c->flags), P<vec4<T>>(c->glo),

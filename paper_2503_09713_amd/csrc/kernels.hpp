@@ -119,7 +119,7 @@ void launch_group_leaves(const vec4<T>* blo, const vec4<T>* bhi, const u32* chil
                          hipStream_t st);
 template <class T>
 void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* bhi, const u32* id,
-                        i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
+                        const u32* xscan, i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
                         const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
                         u32* flags, const vec4<T>* glo, const vec4<T>* ghi, const u32* root,

@@ -156,24 +156,22 @@ k_group_leaves(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
 // Stage 2: per particle, its neighbours among the group's union (Alg. 5 with
 // the object-object criterion), as ascending 16-bit slots, four per 64-bit
 // word in ELL layout (see slot_of); ncnt[a] = number of neighbours.
-// Each lane first marks the union leaves whose box passes the point-box
-// prune (bitmask over an LDS tile of leaves), then walks only the particles
-// of its own marked leaves, reading positions from LDS.
+// The workgroup first marks, for every leaf holding particles of the group
+// ("target leaf"), the union leaves that pass the group-group prune against
+// it (bitmasks in LDS, built cooperatively); each lane then walks only the
+// particles of its own leaf's marked union leaves, positions read from LDS.
+constexpr int TMAX = GROUP;      // target leaves of a group: at most one per particle
+constexpr int MW = LCHUNK / 64;  // mask words per target leaf
+
 template <class T, bool LDS, bool WRAP>
-__device__ inline void cache_leaves(const vec4<T>& pa, const Box<T>& bx, T rk, T rkc, T eps_abs,
-                                    u32 nl, const u32* s_b0, const u32* s_b1, const u32* s_slot,
-                                    const vec4<T>* s_lo, const vec4<T>* s_hi,
-                                    const vec4<T>* s_upos, const vec4<T>* posh, u64* out,
-                                    u32 capq, u32& c, u64& wbuf)
+__device__ inline void cache_walk(const vec4<T>& pa, const Box<T>& bx, T rkc, const u64* mask,
+                                  const u32* s_b0, const u32* s_b1, const u32* s_slot,
+                                  const vec4<T>* s_upos, const vec4<T>* posh, u64* out, u32 capq,
+                                  u32& c, u64& wbuf)
 {
-    u64 mk[LCHUNK / 64];
 #pragma unroll
-    for (int w = 0; w < LCHUNK / 64; ++w) mk[w] = 0;
-    for (u32 j = 0; j < nl; ++j)
-        if (box_hit<T>(pa, pa, s_lo[j], s_hi[j], rk, eps_abs, bx)) mk[j >> 6] |= 1ull << (j & 63);
-#pragma unroll
-    for (int w = 0; w < LCHUNK / 64; ++w) {
-        u64 cur = mk[w];
+    for (int w = 0; w < MW; ++w) {
+        u64 cur = mask[w];
         while (cur) {
             const u32 j = (u32)(w * 64) + (u32)(__ffsll((unsigned long long)cur) - 1);
             cur &= cur - 1;
@@ -197,8 +195,9 @@ __device__ inline void cache_leaves(const vec4<T>& pa, const Box<T>& bx, T rk, T
 template <class T>
 __global__ void __launch_bounds__(GROUP)
 k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
-              const vec4<T>* __restrict__ bhi, const u32* __restrict__ id, i64 n_internal,
-              const GroupMap gm, const InstDev* __restrict__ inst, T rk, T rkc, i64 cap,
+              const vec4<T>* __restrict__ bhi, const u32* __restrict__ id,
+              const u32* __restrict__ xscan, i64 n_internal, const GroupMap gm,
+              const InstDev* __restrict__ inst, T rk, T rkc, i64 cap,
               const u32* __restrict__ uleaf, const u32* __restrict__ uslot,
               const u32* __restrict__ ucnt, const u32* __restrict__ ustot, u32 capq,
               u64* __restrict__ nlist, u32* __restrict__ ncnt, u32* __restrict__ flags,
@@ -210,6 +209,9 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     __shared__ u32 s_slot[LCHUNK];
     __shared__ vec4<T> s_lo[LCHUNK];
     __shared__ vec4<T> s_hi[LCHUNK];
+    __shared__ vec4<T> s_tlo[TMAX];
+    __shared__ vec4<T> s_thi[TMAX];
+    __shared__ u64 s_mask[TMAX][MW];
     __shared__ vec4<T> s_upos[UCH];
     const i64 g = blockIdx.x;
     i64 beg, end;
@@ -219,11 +221,20 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     const T eps_abs = abs_inflation(bx);
     const i64 a = beg + threadIdx.x;
     const bool live = a < end;
-    const vec4<T> pa = posh[live ? a : beg];
+    const i64 ai = live ? a : beg;
+    const vec4<T> pa = posh[ai];
     const u32 nu = min((u32)cap, ucnt[g]);
     const u32 S = ustot[g];
     const bool in_lds = S <= (u32)UCH;
     const bool interior = group_interior<T>(glo[g], ghi[g], blo[root[k]].w, rk, bx);
+    // target leaves: the leaves holding slots beg .. end-1
+    const u32 t0 = xscan[beg + 1] - 1u;
+    const u32 nt = xscan[end] - t0;              // <= GROUP
+    const u32 ta = xscan[ai + 1] - 1u - t0;
+    for (u32 t = threadIdx.x; t < nt; t += GROUP) {
+        s_tlo[t] = blo[n_internal + t0 + t];
+        s_thi[t] = bhi[n_internal + t0 + t];
+    }
     if (in_lds) {
         const vec4<T>* src[1] = { posh };
         vec4<T>* dst[1] = { s_upos };
@@ -234,6 +245,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     u64 wbuf = 0;
     for (u32 c0 = 0; c0 < nu; c0 += LCHUNK) {
         const u32 c1 = min(nu, c0 + LCHUNK);
+        const u32 nl = c1 - c0;
         __syncthreads();
         for (u32 j = c0 + threadIdx.x; j < c1; j += GROUP) {
             const u32 leaf = uleaf[g * cap + j];
@@ -243,17 +255,28 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
             s_lo[j - c0] = blo[n_internal + leaf];
             s_hi[j - c0] = bhi[n_internal + leaf];
         }
+        for (u32 q = threadIdx.x; q < nt * MW; q += GROUP) (&s_mask[0][0])[q] = 0;
+        __syncthreads();
+        // target leaf x union leaf prune, shared by the lanes of each target leaf
+        for (u32 q = threadIdx.x; q < nt * nl; q += GROUP) {
+            const u32 t = q / nl, j = q - t * nl;
+            if (box_hit<T>(s_tlo[t], s_thi[t], s_lo[j], s_hi[j], rk, eps_abs, bx))
+                atomicOr((unsigned long long*)&s_mask[t][j >> 6], 1ull << (j & 63));
+        }
         __syncthreads();
         if (!live) continue;
+        u64 mk[MW];
+#pragma unroll
+        for (int w = 0; w < MW; ++w) mk[w] = s_mask[ta][w];
         if (in_lds && interior)
-            cache_leaves<T, true, false>(pa, bx, rk, rkc, eps_abs, c1 - c0, s_b0, s_b1, s_slot,
-                                         s_lo, s_hi, s_upos, posh, out, capq, c, wbuf);
+            cache_walk<T, true, false>(pa, bx, rkc, mk, s_b0, s_b1, s_slot, s_upos, posh, out, capq,
+                                       c, wbuf);
         else if (in_lds)
-            cache_leaves<T, true, true>(pa, bx, rk, rkc, eps_abs, c1 - c0, s_b0, s_b1, s_slot,
-                                        s_lo, s_hi, s_upos, posh, out, capq, c, wbuf);
+            cache_walk<T, true, true>(pa, bx, rkc, mk, s_b0, s_b1, s_slot, s_upos, posh, out, capq,
+                                      c, wbuf);
         else
-            cache_leaves<T, false, true>(pa, bx, rk, rkc, eps_abs, c1 - c0, s_b0, s_b1, s_slot,
-                                         s_lo, s_hi, s_upos, posh, out, capq, c, wbuf);
+            cache_walk<T, false, true>(pa, bx, rkc, mk, s_b0, s_b1, s_slot, s_upos, posh, out,
+                                       capq, c, wbuf);
     }
     if (live) {
         if (c & 3u) {
@@ -326,7 +349,7 @@ void launch_group_leaves(const vec4<T>* blo, const vec4<T>* bhi, const u32* chil
 
 template <class T>
 void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* bhi, const u32* id,
-                        i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
+                        const u32* xscan, i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
                         const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
                         u32* flags, const vec4<T>* glo, const vec4<T>* ghi, const u32* root,
@@ -334,7 +357,7 @@ void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* 
 {
     if (ngroups <= 0) return;
     hipLaunchKernelGGL((k_group_cache<T>), dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, blo,
-                       bhi, id, n_internal, gm, inst, (T)rk, (T)rkc, cap, uleaf, uslot, ucnt, ustot,
+                       bhi, id, xscan, n_internal, gm, inst, (T)rk, (T)rkc, cap, uleaf, uslot, ucnt, ustot,
                        capq, nlist, ncnt, flags, glo, ghi, root);
 }
 
@@ -356,7 +379,7 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
                                          const GroupMap&, const u32*, const InstDev*, double,     \
                                          i64, u32*, u32*, u32*, u32*, u32*, hipStream_t);         \
     template void launch_group_cache<T>(const vec4<T>*, const vec4<T>*, const vec4<T>*,           \
-                                        const u32*, i64, const GroupMap&, i64, const InstDev*,    \
+                                        const u32*, const u32*, i64, const GroupMap&, i64, const InstDev*,    \
                                         double, double, i64, const u32*, const u32*, const u32*,  \
                                         const u32*, u32, u64*, u32*, u32*, const vec4<T>*,        \
                                         const vec4<T>*, const u32*, hipStream_t);

@@ -561,7 +561,7 @@ template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStre
 }
 
 constexpr int DENS_CH_F = 2048, DENS_CH_D = 1024;
-constexpr int FORCE_CH_F = 1024, FORCE_CH_D = 512;
+constexpr int FORCE_CH_F = 1280, FORCE_CH_D = 640;
 
 template <class T>
 void launch_density(const SortedPtrs<T>& s, const u32* id, const GroupMap& gm, i64 ngroups,
