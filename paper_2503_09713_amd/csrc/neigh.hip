@@ -176,10 +176,9 @@ __device__ inline void cache_walk(const vec4<T>& pa, const Box<T>& bx, T rkc, co
             const u32 j = (u32)(w * 64) + (u32)(__ffsll((unsigned long long)cur) - 1);
             cur &= cur - 1;
             const u32 b0 = s_b0[j], b1 = s_b1[j], sl = s_slot[j];
-            for (u32 b = b0; b < b1; ++b) {
-                const vec4<T> pb = LDS ? s_upos[sl + (b - b0)] : posh[b];
+            auto take = [&](const vec4<T>& pb, u32 s) {
                 if (cache_crit<T, WRAP>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w, bx, rkc)) {
-                    wbuf |= (u64)(sl + (b - b0)) << (16u * (c & 3u));
+                    wbuf |= (u64)s << (16u * (c & 3u));
                     ++c;
                     if ((c & 3u) == 0) {
                         const u32 q = (c >> 2) - 1u;
@@ -187,7 +186,21 @@ __device__ inline void cache_walk(const vec4<T>& pa, const Box<T>& bx, T rkc, co
                         wbuf = 0;
                     }
                 }
+            };
+            u32 b = b0;
+            // four candidates in flight, tested in ascending order
+            for (; b + 4 <= b1; b += 4) {
+                const u32 s = sl + (b - b0);
+                const vec4<T> p0 = LDS ? s_upos[s] : posh[b];
+                const vec4<T> p1 = LDS ? s_upos[s + 1] : posh[b + 1];
+                const vec4<T> p2 = LDS ? s_upos[s + 2] : posh[b + 2];
+                const vec4<T> p3 = LDS ? s_upos[s + 3] : posh[b + 3];
+                take(p0, s);
+                take(p1, s + 1);
+                take(p2, s + 2);
+                take(p3, s + 3);
             }
+            for (; b < b1; ++b) take(LDS ? s_upos[sl + (b - b0)] : posh[b], sl + (b - b0));
         }
     }
 }

@@ -52,17 +52,24 @@ template <class T> __global__ void k_copy_h(const vec4<T>* __restrict__ posh, T*
 // Visit the cache entries of one particle (ELL words `my`, cnt entries).
 // One LDS tile: all entries, four per word, padding skipped.  Several
 // tiles: entries with slots in [c0, c1), resuming at entry j.
+// f(slot, valid): the four slots of a word are visited with slot 0 standing
+// in for padding, so that the callee can issue its LDS reads unconditionally
+// (all four in flight) and use `valid` only to discard the result.
 template <class F> __device__ inline void entries_all(const u64* my, u32 cnt, F&& f)
 {
     const u32 nq = (cnt + 3u) >> 2;
     u64 w = nq ? my[0] : 0;
     for (u32 q = 0; q < nq; ++q) {
         const u64 wn = (q + 1 < nq) ? my[(u64)(q + 1) * GROUP] : 0;   // prefetch
+        u32 sl[4];
+        bool ok[4];
 #pragma unroll
         for (u32 r = 0; r < 4u; ++r) {
-            const u32 sl = slot_of(w, r);
-            if (sl != SLOT_NONE) f(sl);
+            const u32 s = slot_of(w, r);
+            ok[r] = s != SLOT_NONE;
+            sl[r] = ok[r] ? s : 0u;
         }
+        f(sl, ok);
         w = wn;
     }
 }
@@ -184,20 +191,28 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
             const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
             add_r2(dx * dx + dy * dy + dz * dz);
         };
-        auto add_in = [&](u32 sl) {       // interior group: no image can be closer
-            const vec4<T> pb = s_pos[sl];
-            const T dx = pa.x - pb.x, dy = pa.y - pb.y, dz = pa.z - pb.z;
-            add_r2(dx * dx + dy * dy + dz * dz);
+        auto add4 = [&](const u32* sl, const bool* ok) {
+            vec4<T> pb[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pb[r] = s_pos[sl[r]];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T dx = pa.x - pb[r].x, dy = pa.y - pb[r].y, dz = pa.z - pb[r].z;
+                if (wrap) {
+                    dx = min_image(dx, bx.L[0], bx.halfL[0], bx.periodic);
+                    dy = min_image(dy, bx.L[1], bx.halfL[1], bx.periodic);
+                    dz = min_image(dz, bx.L[2], bx.halfL[2], bx.periodic);
+                }
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                add_r2(ok[r] ? r2 : T(INFINITY));
+            }
         };
         if (nch == 1) {
             if (it == 0) {
                 stage_union<T, 1>(src, dst, id, ul, us, nu, 0u, S);
                 __syncthreads();
             }
-            if (active) {
-                if (wrap) entries_all(my, cnt, add);
-                else entries_all(my, cnt, add_in);
-            }
+            if (active) entries_all(my, cnt, add4);
         } else {
             u32 j = 0;
             for (u32 ch = 0; ch < nch; ++ch) {
@@ -348,15 +363,26 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
                min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic),
                min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic), pb);
     };
-    auto pair_in = [&](u32 sl) {          // interior group: no image can be closer
-        const vec4<T> pb = s_pos[sl];
-        pair_d(sl, pa.x - pb.x, pa.y - pb.y, pa.z - pb.z, pb);
+    auto pair4 = [&](const u32* sl, const bool* ok) {
+        vec4<T> pb[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pb[r] = s_pos[sl[r]];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (!ok[r]) continue;
+            T dx = pa.x - pb[r].x, dy = pa.y - pb[r].y, dz = pa.z - pb[r].z;
+            if (wrap) {
+                dx = min_image(dx, bx.L[0], bx.halfL[0], bx.periodic);
+                dy = min_image(dy, bx.L[1], bx.halfL[1], bx.periodic);
+                dz = min_image(dz, bx.L[2], bx.halfL[2], bx.periodic);
+            }
+            pair_d(sl[r], dx, dy, dz, pb[r]);
+        }
     };
     if (nch == 1) {
         stage_union<T, 3>(src, dst, id, ul, us, nu, 0u, S);
         __syncthreads();
-        if (wrap) entries_all(my, cnt, pair);
-        else entries_all(my, cnt, pair_in);
+        entries_all(my, cnt, pair4);
     } else {
         u32 j = 0;
         for (u32 ch = 0; ch < nch; ++ch) {
