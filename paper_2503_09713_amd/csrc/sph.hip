@@ -74,6 +74,22 @@ template <class F> __device__ inline void entries_all(const u64* my, u32 cnt, F&
     }
 }
 
+// f(slot) for each stored slot (single visits; for heavy per-pair bodies).
+template <class F> __device__ inline void entries_each(const u64* my, u32 cnt, F&& f)
+{
+    const u32 nq = (cnt + 3u) >> 2;
+    u64 w = nq ? my[0] : 0;
+    for (u32 q = 0; q < nq; ++q) {
+        const u64 wn = (q + 1 < nq) ? my[(u64)(q + 1) * GROUP] : 0;   // prefetch
+#pragma unroll
+        for (u32 r = 0; r < 4u; ++r) {
+            const u32 sl = slot_of(w, r);
+            if (sl != SLOT_NONE) f(sl);
+        }
+        w = wn;
+    }
+}
+
 template <class F>
 __device__ inline void entries_tile(const u64* my, u32 cnt, u32& j, u32 c0, u32 c1, F&& f)
 {
@@ -191,18 +207,26 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
             const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
             add_r2(dx * dx + dy * dy + dz * dz);
         };
-        auto add4 = [&](const u32* sl, const bool* ok) {
+        auto add4_in = [&](const u32* sl, const bool* ok) {   // interior group
             vec4<T> pb[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) pb[r] = s_pos[sl[r]];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                T dx = pa.x - pb[r].x, dy = pa.y - pb[r].y, dz = pa.z - pb[r].z;
-                if (wrap) {
-                    dx = min_image(dx, bx.L[0], bx.halfL[0], bx.periodic);
-                    dy = min_image(dy, bx.L[1], bx.halfL[1], bx.periodic);
-                    dz = min_image(dz, bx.L[2], bx.halfL[2], bx.periodic);
-                }
+                const T dx = pa.x - pb[r].x, dy = pa.y - pb[r].y, dz = pa.z - pb[r].z;
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                add_r2(ok[r] ? r2 : T(INFINITY));
+            }
+        };
+        auto add4_wr = [&](const u32* sl, const bool* ok) {   // minimum image
+            vec4<T> pb[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pb[r] = s_pos[sl[r]];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const T dx = min_image(pa.x - pb[r].x, bx.L[0], bx.halfL[0], bx.periodic);
+                const T dy = min_image(pa.y - pb[r].y, bx.L[1], bx.halfL[1], bx.periodic);
+                const T dz = min_image(pa.z - pb[r].z, bx.L[2], bx.halfL[2], bx.periodic);
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 add_r2(ok[r] ? r2 : T(INFINITY));
             }
@@ -212,7 +236,10 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
                 stage_union<T, 1>(src, dst, id, ul, us, nu, 0u, S);
                 __syncthreads();
             }
-            if (active) entries_all(my, cnt, add4);
+            if (active) {
+                if (wrap) entries_all(my, cnt, add4_wr);
+                else entries_all(my, cnt, add4_in);
+            }
         } else {
             u32 j = 0;
             for (u32 ch = 0; ch < nch; ++ch) {
@@ -363,26 +390,15 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
                min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic),
                min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic), pb);
     };
-    auto pair4 = [&](const u32* sl, const bool* ok) {
-        vec4<T> pb[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) pb[r] = s_pos[sl[r]];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (!ok[r]) continue;
-            T dx = pa.x - pb[r].x, dy = pa.y - pb[r].y, dz = pa.z - pb[r].z;
-            if (wrap) {
-                dx = min_image(dx, bx.L[0], bx.halfL[0], bx.periodic);
-                dy = min_image(dy, bx.L[1], bx.halfL[1], bx.periodic);
-                dz = min_image(dz, bx.L[2], bx.halfL[2], bx.periodic);
-            }
-            pair_d(sl[r], dx, dy, dz, pb[r]);
-        }
+    auto pair_in = [&](u32 sl) {          // interior group: no image can be closer
+        const vec4<T> pb = s_pos[sl];
+        pair_d(sl, pa.x - pb.x, pa.y - pb.y, pa.z - pb.z, pb);
     };
     if (nch == 1) {
         stage_union<T, 3>(src, dst, id, ul, us, nu, 0u, S);
         __syncthreads();
-        entries_all(my, cnt, pair4);
+        if (wrap) entries_each(my, cnt, pair);
+        else entries_each(my, cnt, pair_in);
     } else {
         u32 j = 0;
         for (u32 ch = 0; ch < nch; ++ch) {
