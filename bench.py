@@ -24,6 +24,22 @@ if ROOT not in sys.path:
 
 METRIC = "particle-steps/s/GPU (tree+density+force), %HBM peak; batched/served vs plain, p99"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3           # published vector FP32 (packed); 78.6 without packed FP32
+FP32_PEAK_NONPACKED_TFLOPS = 78.6
+
+# FP32 operations per counted item (multiply-add counted as 2), from the
+# kernels' arithmetic:
+#   particle cache: a candidate test (3 sub, 3 mul, 2 add, max, 2 mul, compare)
+#                   = 12; a leaf-box prune test = 19
+#   density: a pair evaluation (3 sub, squares and sum, compare) = 9, plus 20
+#            for the kernel sums of pairs within 2h
+#   force: an entry visit (separation, r^2, max, range test) = 12, plus 82 for
+#          an interacting pair (unit vector, w, two spline gradients, AV,
+#          pressure terms, acceleration, du/dt, conductivity, signal speed)
+OPS = {"particle_cache": (12, 19), "density": (9, 20), "force": (12, 82)}
+WORK_KEYS = {"particle_cache": ("cache_tests", "cache_prune_tests"),
+             "density": ("density_pair_evals", "density_pairs_in_2h"),
+             "force": ("force_entries", "force_pairs")}
 
 WORKLOADS = {
     # name: (generator, lattice side, seed, dtype)
@@ -157,20 +173,36 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stages = ctx.stage_times()
+    work = ctx.work()
     ctx.set_profiling(False)
     info = ctx.get_info()
     ms_per_step = 1e3 * elapsed / args.steps
     value = p.n * args.steps / elapsed
 
-    # dominant single-kernel stage and its roofline against HBM
+    # dominant single-kernel stage and its roofline: the neighbour kernels
+    # are instruction bound (ALU, counted operations); streaming kernels HBM
     cand = {k: v for k, v in stages.items() if algorithmic_bytes(k, p.n, info, T) is not None and v[1] > 0}
     dom = max(cand, key=lambda k: cand[k][0])
     avg_ms = cand[dom][0] / cand[dom][1]
     by = algorithmic_bytes(dom, p.n, info, T)
-    achieved = by / (avg_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": int(by)}
+    hbm = by / (avg_ms * 1e-3) / 1e9
+    if dom in OPS:
+        k1, k2 = WORK_KEYS[dom]
+        ops = (OPS[dom][0] * work[k1] + OPS[dom][1] * work[k2]) / cand[dom][1]
+        tf = ops / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(tf, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "frac_of_nonpacked_peak": round(tf / FP32_PEAK_NONPACKED_TFLOPS, 4),
+                "avg_launch_ms": round(avg_ms, 4), "flop_per_launch": int(ops),
+                "hbm_algorithmic_GBs": round(hbm, 1), "bytes_per_launch": int(by)}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": int(by)}
+    # whole step against HBM: algorithmic bytes of all stages per step
+    step_bytes = sum(algorithmic_bytes(k, p.n, info, T) * (v[1] / args.steps)
+                     for k, v in stages.items() if algorithmic_bytes(k, p.n, info, T) is not None)
+    step_bytes += 8 * p.n * 32 + p.n * 48 + p.n * 34   # sort, predict/keys, mask/reduce/compact
 
     out = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
@@ -182,6 +214,10 @@ def main():
                    "neighbours_per_particle": info["n_neigh"] / p.n,
                    "leaves": info["n_leaf"]},
         "roofline": roof,
+        "step_hbm": {"algorithmic_bytes_per_step": int(step_bytes),
+                     "GBs": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+                     "frac_of_8TBs": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "work_per_step": {k: v / args.steps for k, v in work.items()},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
     }
     if not args.no_cpu_baseline:

@@ -203,6 +203,13 @@ int shsph_get_stage_times(shsph_ctx *ctx, double *ms, int64_t *launches, int32_t
 /* Name of stage i ("" when out of range); static storage. */
 const char *shsph_stage_name(int32_t i);
 
+/* Work counted by the neighbour kernels while profiling is on (totals since
+ * it was turned on), 6 doubles: particle cache {candidate pair tests, leaf
+ * box prune tests}, density {pair evaluations summed over Newton passes,
+ * force {cache entries visited, interacting pairs}; density's second entry
+ * counts the evaluations within 2h. */
+int shsph_get_work(shsph_ctx *ctx, double *out6);
+
 #ifdef __cplusplus
 }
 #endif

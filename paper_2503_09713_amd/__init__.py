@@ -92,11 +92,13 @@ def lib():
     L.shsph_export_tree.argtypes = [vp, C.POINTER(TreeExport)]
     L.shsph_set_profiling.argtypes = [vp, ip]
     L.shsph_get_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+    L.shsph_get_work.argtypes = [vp, C.POINTER(C.c_double)]
     L.shsph_stage_name.argtypes = [C.c_int32]
     L.shsph_stage_name.restype = C.c_char_p
     for fn in ("shsph_create", "shsph_destroy", "shsph_set_stream", "shsph_build_tree",
                "shsph_density", "shsph_force", "shsph_step", "shsph_get_info",
-               "shsph_export_tree", "shsph_set_profiling", "shsph_get_stage_times"):
+               "shsph_export_tree", "shsph_set_profiling", "shsph_get_stage_times",
+               "shsph_get_work"):
         getattr(L, fn).restype = ip
     _lib = L
     return L
@@ -253,6 +255,13 @@ class Context:
         cnt = (C.c_int64 * n)()
         self._check(self.L.shsph_get_stage_times(self.h, ms, cnt, n))
         return {self.L.shsph_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(n)}
+
+    def work(self) -> dict:
+        """Work counted by the neighbour kernels since profiling was turned on."""
+        w = (C.c_double * 6)()
+        self._check(self.L.shsph_get_work(self.h, w))
+        return dict(cache_tests=w[0], cache_prune_tests=w[1], density_pair_evals=w[2],
+                    density_pairs_in_2h=w[3], force_entries=w[4], force_pairs=w[5])
 
     def close(self) -> None:
         if getattr(self, "h", None):

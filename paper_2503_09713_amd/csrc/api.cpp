@@ -70,6 +70,7 @@ struct shsph_ctx {
     Buf glo, ghi, uleaf, uslot, ucnt, ustot;    // stage 1, per group
     Buf nlist, ncnt, flags;                     // stage 2, per particle (ELL)
     Buf bpart;                                  // corrector partial sums
+    Buf work[3];                                // work counters (profiling)
     i64 parts_pending = 0;                      // corrector blocks not yet folded
     Buf inst_d, poff_d, goff_d, leaf_off_d, ioff_d, root_d, stat_d, dt_inst_d, dt_host_d;
     Buf pbox, plen, xoff, xlist;                // export only
@@ -280,9 +281,18 @@ GroupMap group_map(shsph_ctx* c)
     return g;
 }
 
+// Work counters: kernel kind 0 = particle cache, 1 = density, 2 = force;
+// 64 slots x 2 u64 each, accumulated on the device while profiling is on.
+u64* work_ptr(shsph_ctx* c, int kind)
+{
+    if (!c->prof.on || !c->work[kind].p) return nullptr;
+    return P<u64>(c->work[kind]);
+}
+
 CacheView cache_view(shsph_ctx* c)
 {
     CacheView v;
+    v.work = nullptr;
     v.uleaf = P<u32>(c->uleaf); v.uslot = P<u32>(c->uslot);
     v.ucnt = P<u32>(c->ucnt); v.ustot = P<u32>(c->ustot);
     v.cap = c->cap_leaf;
@@ -452,7 +462,7 @@ template <class T> int build_caches(shsph_ctx* c)
                               inst, rk, rk, c->cap_leaf, P<u32>(c->uleaf), P<u32>(c->uslot),
                               P<u32>(c->ucnt), P<u32>(c->ustot), (u32)c->cap_words, P<u64>(c->nlist),
                               P<u32>(c->ncnt), P<u32>(c->flags), P<vec4<T>>(c->glo),
-                              P<vec4<T>>(c->ghi), P<u32>(c->root_d), st);
+                              P<vec4<T>>(c->ghi), P<u32>(c->root_d), work_ptr(c, 0), st);
         prof_end(c);
         TRY(check_launch(c, "stage2"));
         HIPTRY(c, hipMemcpyAsync(c->pinned, c->flags.p, 4 * sizeof(u32), hipMemcpyDeviceToHost, st));
@@ -499,8 +509,10 @@ template <class T> int run_density(shsph_ctx* c, bool with_thermo)
         launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
         c->parts_pending = 0;
         prof_begin(c, S_DENSITY);
+        CacheView cvd = cache_view(c);
+        cvd.work = work_ptr(c, 1);
         launch_density<T>(s, P<u32>(c->id), group_map(c), c->n_groups, P<InstDev>(c->inst_d), sp,
-                          cache_view(c), P<T>(c->omega),
+                          cvd, P<T>(c->omega),
                           with_thermo ? P<vec4<T>>(c->thermo) : nullptr, P<u8>(c->status),
                           P<InstStat>(c->stat_d), st);
         prof_end(c);
@@ -618,8 +630,10 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
         c->parts_pending = 0;
     const SphParams sp = sph_params(c->prm);
     prof_begin(c, S_FORCE);
+    CacheView cvf = cache_view(c);
+    cvf.work = work_ptr(c, 2);
     launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
-                    c->n_groups, P<InstDev>(c->inst_d), sp, cache_view(c), P<vec4<T>>(c->acc),
+                    c->n_groups, P<InstDev>(c->inst_d), sp, cvf, P<vec4<T>>(c->acc),
                     nullptr, P<InstStat>(c->stat_d), st);
     prof_end(c);
     TRY(check_launch(c, "force"));
@@ -720,7 +734,7 @@ int shsph_destroy(shsph_ctx* c)
                    &c->ucnt, &c->ustot, &c->nlist, &c->ncnt, &c->flags, &c->inst_d, &c->poff_d,
                    &c->goff_d, &c->leaf_off_d, &c->ioff_d, &c->root_d, &c->stat_d,
                    &c->dt_inst_d, &c->dt_host_d, &c->pbox, &c->plen, &c->xoff, &c->xlist,
-                   &c->bpart };
+                   &c->bpart, &c->work[0], &c->work[1], &c->work[2] };
     for (Buf* b : all)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);
@@ -785,7 +799,27 @@ int shsph_set_profiling(shsph_ctx* c, int on)
     if (!c) return SHSPH_EINVAL;
     c->prof.on = on != 0;
     c->prof.used = 0;
+    HIPTRY(c, hipSetDevice(c->device));
+    for (int k = 0; k < 3; ++k) {
+        TRY(ensure(c, c->work[k], 128 * sizeof(u64)));
+        launch_fill_u32(P<u32>(c->work[k]), 256, 0u, c->stream);
+    }
     for (int i = 0; i < S_NUM; ++i) { c->prof.ms[i] = 0; c->prof.launches[i] = 0; }
+    return SHSPH_OK;
+}
+
+int shsph_get_work(shsph_ctx* c, double* out6)
+{
+    if (!c || !out6) return SHSPH_EINVAL;
+    for (int k = 0; k < 6; ++k) out6[k] = 0.0;
+    HIPTRY(c, hipSetDevice(c->device));
+    for (int k = 0; k < 3; ++k) {
+        if (!c->work[k].p) continue;
+        u64 w[128];
+        HIPTRY(c, hipMemcpyAsync(w, c->work[k].p, sizeof(w), hipMemcpyDeviceToHost, c->stream));
+        HIPTRY(c, hipStreamSynchronize(c->stream));
+        for (int s = 0; s < 64; ++s) { out6[2 * k] += (double)w[2 * s]; out6[2 * k + 1] += (double)w[2 * s + 1]; }
+    }
     return SHSPH_OK;
 }
 

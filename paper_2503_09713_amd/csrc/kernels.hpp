@@ -51,6 +51,7 @@ struct CacheView {
     const void* blo;          // node boxes: h_max of each instance's root
     const u32* root;
     double rk;                // R chi
+    u64* work;                // work counters, 64 slots x 2 (profiling), or null
 };
 
 // Per-block partial sums of the corrector (instance id, or -1 if the block
@@ -123,7 +124,7 @@ void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* 
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
                         const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
                         u32* flags, const vec4<T>* glo, const vec4<T>* ghi, const u32* root,
-                        hipStream_t st);
+                        u64* work, hipStream_t st);
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
                             const u32* uleaf, const u32* uslot, const u32* ucnt, u32 capq,
                             const u64* nlist, const u32* ncnt, const u64* off, u32* list,

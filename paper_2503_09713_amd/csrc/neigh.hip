@@ -167,7 +167,7 @@ template <class T, bool LDS, bool WRAP>
 __device__ inline void cache_walk(const vec4<T>& pa, const Box<T>& bx, T rkc, const u64* mask,
                                   const u32* s_b0, const u32* s_b1, const u32* s_slot,
                                   const vec4<T>* s_upos, const vec4<T>* posh, u64* out, u32 capq,
-                                  u32& c, u64& wbuf)
+                                  u32& c, u64& wbuf, u32& tested)
 {
 #pragma unroll
     for (int w = 0; w < MW; ++w) {
@@ -176,6 +176,7 @@ __device__ inline void cache_walk(const vec4<T>& pa, const Box<T>& bx, T rkc, co
             const u32 j = (u32)(w * 64) + (u32)(__ffsll((unsigned long long)cur) - 1);
             cur &= cur - 1;
             const u32 b0 = s_b0[j], b1 = s_b1[j], sl = s_slot[j];
+            tested += b1 - b0;
             auto take = [&](const vec4<T>& pb, u32 s) {
                 if (cache_crit<T, WRAP>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w, bx, rkc)) {
                     wbuf |= (u64)s << (16u * (c & 3u));
@@ -215,8 +216,9 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
               const u32* __restrict__ ucnt, const u32* __restrict__ ustot, u32 capq,
               u64* __restrict__ nlist, u32* __restrict__ ncnt, u32* __restrict__ flags,
               const vec4<T>* __restrict__ glo, const vec4<T>* __restrict__ ghi,
-              const u32* __restrict__ root)
+              const u32* __restrict__ root, u64* __restrict__ work)
 {
+    __shared__ u64 s_w[GROUP / WAVE];
     __shared__ u32 s_b0[LCHUNK];
     __shared__ u32 s_b1[LCHUNK];
     __shared__ u32 s_slot[LCHUNK];
@@ -254,11 +256,12 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         stage_union<T, 1>(src, dst, id, uleaf + g * cap, uslot + g * cap, nu, 0u, S);
     }
     u64* out = nlist + (u64)g * capq * GROUP + threadIdx.x;
-    u32 c = 0;
-    u64 wbuf = 0;
+    u32 c = 0, tested = 0;
+    u64 wbuf = 0, boxtests = 0;
     for (u32 c0 = 0; c0 < nu; c0 += LCHUNK) {
         const u32 c1 = min(nu, c0 + LCHUNK);
         const u32 nl = c1 - c0;
+        boxtests += (u64)nt * nl;
         __syncthreads();
         for (u32 j = c0 + threadIdx.x; j < c1; j += GROUP) {
             const u32 leaf = uleaf[g * cap + j];
@@ -283,13 +286,13 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         for (int w = 0; w < MW; ++w) mk[w] = s_mask[ta][w];
         if (in_lds && interior)
             cache_walk<T, true, false>(pa, bx, rkc, mk, s_b0, s_b1, s_slot, s_upos, posh, out, capq,
-                                       c, wbuf);
+                                       c, wbuf, tested);
         else if (in_lds)
             cache_walk<T, true, true>(pa, bx, rkc, mk, s_b0, s_b1, s_slot, s_upos, posh, out, capq,
-                                      c, wbuf);
+                                      c, wbuf, tested);
         else
             cache_walk<T, false, true>(pa, bx, rkc, mk, s_b0, s_b1, s_slot, s_upos, posh, out,
-                                       capq, c, wbuf);
+                                       capq, c, wbuf, tested);
     }
     if (live) {
         if (c & 3u) {
@@ -298,6 +301,13 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
             if (q < capq) out[(u64)q * GROUP] = wbuf;
         }
         ncnt[a] = c;
+    }
+    if (work) {   // work counters (profiling): candidate tests, prune tests
+        const u64 t = block_reduce<GROUP>((u64)tested, s_w, [](u64 x, u64 y) { return x + y; });
+        if (threadIdx.x == 0) {
+            atomicAdd((unsigned long long*)&work[2 * (g & 63)], (unsigned long long)t);
+            atomicAdd((unsigned long long*)&work[2 * (g & 63) + 1], (unsigned long long)boxtests);
+        }
     }
     const u32 wmax = wave_max(live ? c : 0u);
     if (__lane_id() == 0) {
@@ -366,12 +376,12 @@ void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* 
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
                         const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
                         u32* flags, const vec4<T>* glo, const vec4<T>* ghi, const u32* root,
-                        hipStream_t st)
+                        u64* work, hipStream_t st)
 {
     if (ngroups <= 0) return;
     hipLaunchKernelGGL((k_group_cache<T>), dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, blo,
                        bhi, id, xscan, n_internal, gm, inst, (T)rk, (T)rkc, cap, uleaf, uslot, ucnt, ustot,
-                       capq, nlist, ncnt, flags, glo, ghi, root);
+                       capq, nlist, ncnt, flags, glo, ghi, root, work);
 }
 
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
@@ -395,7 +405,7 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
                                         const u32*, const u32*, i64, const GroupMap&, i64, const InstDev*,    \
                                         double, double, i64, const u32*, const u32*, const u32*,  \
                                         const u32*, u32, u64*, u32*, u32*, const vec4<T>*,        \
-                                        const vec4<T>*, const u32*, hipStream_t);
+                                        const vec4<T>*, const u32*, u64*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -52,28 +52,6 @@ template <class T> __global__ void k_copy_h(const vec4<T>* __restrict__ posh, T*
 // Visit the cache entries of one particle (ELL words `my`, cnt entries).
 // One LDS tile: all entries, four per word, padding skipped.  Several
 // tiles: entries with slots in [c0, c1), resuming at entry j.
-// f(slot, valid): the four slots of a word are visited with slot 0 standing
-// in for padding, so that the callee can issue its LDS reads unconditionally
-// (all four in flight) and use `valid` only to discard the result.
-template <class F> __device__ inline void entries_all(const u64* my, u32 cnt, F&& f)
-{
-    const u32 nq = (cnt + 3u) >> 2;
-    u64 w = nq ? my[0] : 0;
-    for (u32 q = 0; q < nq; ++q) {
-        const u64 wn = (q + 1 < nq) ? my[(u64)(q + 1) * GROUP] : 0;   // prefetch
-        u32 sl[4];
-        bool ok[4];
-#pragma unroll
-        for (u32 r = 0; r < 4u; ++r) {
-            const u32 s = slot_of(w, r);
-            ok[r] = s != SLOT_NONE;
-            sl[r] = ok[r] ? s : 0u;
-        }
-        f(sl, ok);
-        w = wn;
-    }
-}
-
 // f(slot) for each stored slot (single visits; for heavy per-pair bodies).
 template <class F> __device__ inline void entries_each(const u64* my, u32 cnt, F&& f)
 {
@@ -159,6 +137,7 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
 {
     __shared__ vec4<T> s_pos[CH];
     __shared__ u32 s_red[GROUP / WAVE];
+    __shared__ u64 s_w[GROUP / WAVE];
     __shared__ int s_k;
     const i64 g = blockIdx.x;
     i64 beg, end;
@@ -185,6 +164,7 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
     int st = 1;   // 0 converged, 1 not converged, 2 chi exceeded
     int iters = 0;
     bool active = live;
+    u64 evals = 0, inrange = 0;
     const bool wrap = !group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
                                          ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx);
     for (int it = 0; it < P.max_iter; ++it) {
@@ -192,7 +172,9 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
         const T h2x4 = T(4) * h * h;
         T s = T(0), ds = T(0);
         auto add_r2 = [&](T r2) {
+            ++evals;
             if (r2 < h2x4) {
+                ++inrange;
                 const T q = fast_sqrt(r2) * hinv;
                 T f, df;
                 m4<T>(q, f, df);
@@ -207,29 +189,10 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
             const T dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
             add_r2(dx * dx + dy * dy + dz * dz);
         };
-        auto add4_in = [&](const u32* sl, const bool* ok) {   // interior group
-            vec4<T> pb[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) pb[r] = s_pos[sl[r]];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const T dx = pa.x - pb[r].x, dy = pa.y - pb[r].y, dz = pa.z - pb[r].z;
-                const T r2 = dx * dx + dy * dy + dz * dz;
-                add_r2(ok[r] ? r2 : T(INFINITY));
-            }
-        };
-        auto add4_wr = [&](const u32* sl, const bool* ok) {   // minimum image
-            vec4<T> pb[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) pb[r] = s_pos[sl[r]];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const T dx = min_image(pa.x - pb[r].x, bx.L[0], bx.halfL[0], bx.periodic);
-                const T dy = min_image(pa.y - pb[r].y, bx.L[1], bx.halfL[1], bx.periodic);
-                const T dz = min_image(pa.z - pb[r].z, bx.L[2], bx.halfL[2], bx.periodic);
-                const T r2 = dx * dx + dy * dy + dz * dz;
-                add_r2(ok[r] ? r2 : T(INFINITY));
-            }
+        auto add_in = [&](u32 sl) {       // interior group: no image can be closer
+            const vec4<T> pb = s_pos[sl];
+            const T dx = pa.x - pb.x, dy = pa.y - pb.y, dz = pa.z - pb.z;
+            add_r2(dx * dx + dy * dy + dz * dz);
         };
         if (nch == 1) {
             if (it == 0) {
@@ -237,8 +200,8 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
                 __syncthreads();
             }
             if (active) {
-                if (wrap) entries_all(my, cnt, add4_wr);
-                else entries_all(my, cnt, add4_in);
+                if (wrap) entries_each(my, cnt, add);
+                else entries_each(my, cnt, add_in);
             }
         } else {
             u32 j = 0;
@@ -280,6 +243,14 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
         if (threadIdx.x == 0) atomic_max_if(&stat[k].max_iter_seen, mx);
     } else if (live) {
         atomic_max_if(&stat[k].max_iter_seen, (u32)iters);
+    }
+    if (cv.work) {   // work counters (profiling): pair evaluations, those within 2h
+        const u64 t1 = block_reduce<GROUP>(evals, s_w, [](u64 x, u64 y) { return x + y; });
+        const u64 t2 = block_reduce<GROUP>(inrange, s_w, [](u64 x, u64 y) { return x + y; });
+        if (threadIdx.x == 0) {
+            atomicAdd((unsigned long long*)&cv.work[2 * (g & 63)], (unsigned long long)t1);
+            atomicAdd((unsigned long long*)&cv.work[2 * (g & 63) + 1], (unsigned long long)t2);
+        }
     }
     if (!live) return;
     const T hf = hfact / h_eval;
@@ -325,6 +296,7 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     __shared__ vec4<T> s_vel[CH];
     __shared__ vec4<T> s_thm[CH];
     __shared__ float s_red[GROUP / WAVE];
+    __shared__ u64 s_w[GROUP / WAVE];
     __shared__ int s_k;
     const i64 g = blockIdx.x;
     i64 beg, end;
@@ -353,13 +325,16 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     const vec4<T>* src[3] = { posh, velu, thermo };
     vec4<T>* dst[3] = { s_pos, s_vel, s_thm };
     T ax = T(0), ay = T(0), az = T(0), du = T(0), lam = T(0), vmax = ca;
+    u64 visited = 0, inter = 0;
     const bool wrap = !group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
                                          ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx);
     auto pair_d = [&](u32 sl, T dx, T dy, T dz, const vec4<T>& pb) {
         const T r2 = dx * dx + dy * dy + dz * dz;
         const T hb = pb.w;
         const T hm = ha > hb ? ha : hb;
+        ++visited;
         if (!(r2 > T(0)) || !(r2 < T(4) * hm * hm)) return;
+        ++inter;
         const vec4<T> vb = s_vel[sl], tb = s_thm[sl];
         const T rinv = fast_rsq(r2), r = r2 * rinv;
         const T ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
@@ -407,6 +382,14 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
             stage_union<T, 3>(src, dst, id, ul, us, nu, c0, c1);
             __syncthreads();
             entries_tile(my, cnt, j, c0, c1, pair);
+        }
+    }
+    if (cv.work) {   // work counters (profiling): visited entries, interacting pairs
+        const u64 t1 = block_reduce<GROUP>(visited, s_w, [](u64 x, u64 y) { return x + y; });
+        const u64 t2 = block_reduce<GROUP>(inter, s_w, [](u64 x, u64 y) { return x + y; });
+        if (threadIdx.x == 0) {
+            atomicAdd((unsigned long long*)&cv.work[2 * (g & 63)], (unsigned long long)t1);
+            atomicAdd((unsigned long long*)&cv.work[2 * (g & 63) + 1], (unsigned long long)t2);
         }
     }
     float dta = __int_as_float(0x7f800000);

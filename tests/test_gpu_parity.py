@@ -210,6 +210,9 @@ def test_force_vs_oracle(torch_cuda, case):
                         p.periodic, p.mass)
     ea2, eu2 = _force_err(g, ref2)
     assert ea2 <= tol and eu2 <= tol, (ea2, eu2)
+    # CFL dt: min over particles of C_cour h/vsig, C_force sqrt(h/|a|)
+    dt_ref = oracle.cfl(g["h"], ref["vsig"], ref["ax"], ref["ay"], ref["az"])
+    assert abs(ctx.get_info()["dt_cfl"] / dt_ref - 1) < (1e-4 if T == np.float32 else 1e-6)
     # momentum conservation of the GPU result itself
     S = (p.mass * ref["scale_a"]).sum()
     for c in ("ax", "ay", "az"):

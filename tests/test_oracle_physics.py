@@ -191,6 +191,20 @@ def test_force_brute_force_small():
     assert np.abs(ref - a).max() < 1e-12 * np.abs(a).max()
 
 
+def test_cfl_closed_form_at_rest():
+    # unjittered lattice at rest, uniform u: a = 0 and the signal speed is the
+    # sound speed, so dt = C_cour h / c_s with c_s = sqrt(gamma (gamma-1) u)
+    p = gen.lattice(10, 1, dtype=np.float64, jitter=0.0)
+    p.u = np.full(p.n, 2.5)
+    h, rho, om, _ = oracle.density(p.x, p.y, p.z, p.h, p.lo, p.hi, True, p.mass)
+    f = oracle.force(p.x, p.y, p.z, p.vx, p.vy, p.vz, p.u, h, rho, om, p.lo, p.hi, True, p.mass)
+    g = 5.0 / 3.0
+    cs = math.sqrt(g * (g - 1) * 2.5)
+    assert np.allclose(f["vsig"], cs, rtol=1e-14)
+    dt = oracle.cfl(h, f["vsig"], f["ax"], f["ay"], f["az"])
+    assert abs(dt - 0.3 * h.min() / cs) < 1e-12 * dt
+
+
 # ---------------------------------------------------------------- step ----
 def test_kdk_step_conserves_momentum_and_is_reversible():
     rng = np.random.default_rng(9)
