@@ -129,6 +129,134 @@ def cpu_baseline(ps_host, p, args):
                        f"({t1:.1f}s, {t2:.1f}s measured)")}
 
 
+def run_batched(args, shsph, torch):
+    """64 uneven instances (half jittered lattices, half Plummer spheres,
+    N_i log-uniform in [2^12, 2^20]): K CFL steps as one batched pass per step,
+    against the same kernels run one instance per pass (plain launches)."""
+    import gen
+    log("[batched] generating 64 instances")
+    insts = gen.batch(seed=gen.SEEDS["batch"], n_inst=64)
+    ntot = sum(p.n for p in insts)
+    sets = [shsph.ParticleSet.from_particles(p) for p in insts]
+    K, W = args.batch_steps, args.batch_warmup
+    res = {"workload": "batched64", "instances": len(insts), "particles": ntot,
+           "n_min": min(p.n for p in insts), "n_max": max(p.n for p in insts), "steps": K}
+    ctx = shsph.Context(0, n_red=args.n_red)
+    hs = [ctx.instance_create(s) for s in sets]
+    for _ in range(W):
+        ctx.step_batch(hs)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        ctx.step_batch(hs)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    stages = ctx.stage_times()
+    ctx.set_profiling(False)
+    ctx.close()
+    log(f"[batched] batched {1e3 * tb / K:.2f} ms/step")
+    ctx = shsph.Context(0, n_red=args.n_red)
+    hs = [ctx.instance_create(s) for s in sets]
+    for _ in range(W):
+        for h in hs:
+            ctx.step_batch([h])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        for h in hs:
+            ctx.step_batch([h])
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    ctx.close()
+    log(f"[batched] plain {1e3 * tp / K:.2f} ms/step")
+    res.update({"value": ntot * K / tb, "unit": "particle-steps/s", "ms_per_step": 1e3 * tb / K,
+                "plain_value": ntot * K / tp, "plain_ms_per_step": 1e3 * tp / K,
+                "speedup_vs_plain": tp / tb,
+                "stages_ms_per_step": {k: round(v[0] / K, 4) for k, v in stages.items()}})
+    return res
+
+
+def serve_templates(seed):
+    """Seeded instance templates for the serving trace: per family, 16 sizes
+    evenly spaced in log N over [2^12, 2^22] (bin centres); a job takes the
+    template of its family nearest to its drawn size."""
+    import numpy as np
+    import gen
+    out = {"lattice": [], "plummer": []}
+    sizes = np.floor(2.0 ** (12 + 10 * (np.arange(16) + 0.5) / 16)).astype(int)
+    for fam in out:
+        for k, n in enumerate(sizes):
+            if fam == "lattice":
+                n1 = max(16, int(round(n ** (1.0 / 3.0))))
+                p = gen.lattice(n1, seed * 100 + k)
+            else:
+                p = gen.plummer(int(n), seed * 100 + 50 + k)
+            out[fam].append(p)
+    return out
+
+
+def run_served(args, shsph, torch, capacity):
+    """Poisson arrivals of STEP (1-10 CFL steps) and EVAL jobs, each bringing
+    its own instance, served under a 200 GB budget with continuous batching and,
+    on the same trace, one job at a time."""
+    import numpy as np
+    import gen
+    log("[served] generating templates")
+    tpl = serve_templates(gen.SEEDS["serve"])
+    sets = {f: [shsph.ParticleSet.from_particles(p) for p in ps] for f, ps in tpl.items()}
+    logn = {f: np.log([p.n for p in ps]) for f, ps in tpl.items()}
+    base = gen.serve_trace(1.0, args.serve_jobs, seed=gen.SEEDS["serve"])
+    jobs = []
+    for j in base:
+        k = int(np.argmin(np.abs(logn[j["family"]] - np.log(j["n"]))))
+        jobs.append(dict(j, tpl=k, n=tpl[j["family"]][k].n))
+    # passes per job: a STEP job's instance first gets its derivatives
+    work = np.array([j["n"] * (j["nsteps"] + 1 if j["kind"] == "step" else 1) for j in jobs], float)
+    rate = args.serve_load * capacity / work.mean()
+    res = {"workload": "served", "jobs": len(jobs), "rate_jobs_per_s": rate,
+           "offered_load_of_batched_capacity": args.serve_load, "budget_GB": 200,
+           "templates": 32, "eval_fraction": float(np.mean([j["kind"] == "eval" for j in jobs]))}
+    for name, policy in (("continuous", shsph.SERVE_CONTINUOUS),
+                         ("one_at_a_time", shsph.SERVE_ONE_AT_A_TIME)):
+        ctx = shsph.Context(0, n_red=args.n_red)
+        ctx.serve_start(200e9, max_batch=256, policy=policy)
+        log(f"[served] {name}: {len(jobs)} jobs at {rate:.1f}/s")
+        tk = []
+        t0 = time.perf_counter()
+        for j in jobs:
+            due = t0 + j["t"] / rate
+            while True:
+                d = due - time.perf_counter()
+                if d <= 0:
+                    break
+                time.sleep(d if d > 2e-3 else 0)
+            kind = shsph.JOB_EVAL if j["kind"] == "eval" else shsph.JOB_STEP
+            tk.append(ctx.submit(init=sets[j["family"]][j["tpl"]], kind=kind, nsteps=j["nsteps"],
+                                 release=True))
+        ctx.serve_drain(1800.0)
+        st = [ctx.poll(t) for t in tk]
+        stats = ctx.serve_stats()
+        ctx.serve_stop()
+        ctx.close()
+        lat = np.array([s["t_done"] - s["t_submit"] for s in st])
+        done = sum(s["state"] == "done" for s in st)
+        span = max(s["t_done"] for s in st) - min(s["t_submit"] for s in st)
+        steps = sum(j["n"] * (j["nsteps"] if j["kind"] == "step" else 1) for j in jobs)
+        res[name] = {"p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                     "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                     "mean_ms": 1e3 * float(lat.mean()), "jobs_done": int(done),
+                     "throughput_particle_steps_per_s": steps / span, "makespan_s": span,
+                     "passes": stats["passes"], "peak_jobs_per_pass": stats["peak_jobs"],
+                     "peak_GB": stats["peak_bytes"] / 1e9}
+        log(f"[served] {name}: p50 {res[name]['p50_ms']:.1f} ms, p99 {res[name]['p99_ms']:.1f} ms")
+    c, o = res["continuous"], res["one_at_a_time"]
+    res["throughput_vs_one_at_a_time"] = (c["throughput_particle_steps_per_s"] /
+                                          o["throughput_particle_steps_per_s"])
+    res["p99_vs_one_at_a_time"] = c["p99_ms"] / o["p99_ms"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +266,16 @@ def main():
     ap.add_argument("--n-red", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=240000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batch run")
+    ap.add_argument("--no-served", action="store_true", help="skip the serving run")
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--batch-warmup", type=int, default=2)
+    ap.add_argument("--serve-jobs", type=int, default=2000)
+    ap.add_argument("--serve-load", type=float, default=0.75,
+                    help="offered load as a fraction of the measured batched throughput")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters against known bytes) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the sharded design is described, "
@@ -146,6 +284,16 @@ def main():
 
     import numpy as np
     import torch
+    if args.calibrate_copy > 0:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb, "launches": 5}), flush=True)
+        return
     import paper_2503_09713_amd as shsph
 
     log(f"[bench] generating {args.workload}")
@@ -220,10 +368,18 @@ def main():
         "work_per_step": {k: v / args.steps for k, v in work.items()},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
     }
-    if not args.no_cpu_baseline:
-        host = ps.host("x", "y", "z", "vx", "vy", "vz", "u", "h")
-        out["cpu_baseline"] = cpu_baseline(host, p, args)
+    host = ps.host("x", "y", "z", "vx", "vy", "vz", "u", "h") if not args.no_cpu_baseline else None
     ctx.close()
+    del ps
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = run_batched(args, shsph, torch)
+        torch.cuda.empty_cache()
+    if not args.no_served:
+        cap = out["batched"]["value"] if "batched" in out else value
+        out["served"] = run_served(args, shsph, torch, cap)
+    if host is not None:
+        out["cpu_baseline"] = cpu_baseline(host, p, args)
     print(json.dumps(out), flush=True)
 
 

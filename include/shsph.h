@@ -17,7 +17,11 @@
  *   - Indices into the neighbour cache and the tree are positions in Morton
  *     (key) order; the permutation `eps` (sorted slot i <- input index
  *     eps[i]) maps them back to the caller's order.
- *   - A context is used by one host thread at a time.
+ *   - Calls on one context are serialised by a lock inside the context; the
+ *     serving loop (shsph_serve_start) is one more user of that lock.  The
+ *     plain calls (build / density / force / step) keep their tree and
+ *     caches in the context only until the next call that builds one,
+ *     pooled passes included.
  */
 #ifndef SHSPH_H
 #define SHSPH_H
@@ -209,6 +213,148 @@ const char *shsph_stage_name(int32_t i);
  * force {cache entries visited, interacting pairs}; density's second entry
  * counts the evaluations within 2h. */
 int shsph_get_work(shsph_ctx *ctx, double *out6);
+
+/* ------------------------------------------------------------------------
+ * Pooled instances and batched passes.
+ *
+ * Many independent instances (uneven sizes, periodic or isolated, one dtype
+ * per context) live in a device pool owned by the context.  A batched pass
+ * runs every stage of the step once over all the instances it names: the
+ * sort is segmented by instance, each instance gets its own tree, cache,
+ * h iteration, reductions and CFL dt, and each result is the same as the
+ * instance would get alone (the kernels never mix instances).  The pooled
+ * state is kept in Morton order after each pass; `pid` maps it back.
+ * ---------------------------------------------------------------------- */
+
+/* Copy an instance into the pool: reads x..h, vx..u (required) and ax..dudt,
+ * rho, omega, pid when non-NULL (zeros, and pid = 0..n-1, otherwise).  The
+ * pointers may be device or host memory; the call waits for the copy.
+ * *handle receives a positive id.  EINVAL on bad input or a dtype other
+ * than the pool's, ENOMEM when the pool cannot grow. */
+int shsph_instance_create(shsph_ctx *ctx, const shsph_particles *init, int64_t *handle);
+
+/* Return the instance's range to the pool.  ESTATE while a serving job
+ * holds it. */
+int shsph_instance_destroy(shsph_ctx *ctx, int64_t handle);
+
+/* Copy the instance's current state (Morton order) into the non-NULL
+ * arrays of `out` (device or host memory; out->n and out->dtype must match);
+ * waits for the copy. */
+int shsph_instance_read(shsph_ctx *ctx, int64_t handle, const shsph_particles *out);
+
+/* The instance's reductions from its last pass: n, dt_cfl, dv_max, dv2_sum,
+ * v2_sum, max_iter_seen, n_noconv (tree counters are 0). */
+int shsph_instance_info(shsph_ctx *ctx, int64_t handle, shsph_info *out);
+
+/* One kick-drift-kick step (App. H.1) of every listed instance in a single
+ * batched pass; dt[k] > 0 is a fixed step, dt[k] <= 0 (or dt NULL) the
+ * instance's CFL dt (App. H.2).  A CFL instance that has no derivatives yet
+ * first gets a derivative pass (as shsph_eval_batch).  dt_used (optional)
+ * receives the dt taken per instance.  1..2048 distinct handles.  ENOCONV
+ * when some instance's h iteration did not settle: the step is complete,
+ * shsph_instance_info tells which. */
+int shsph_step_batch(shsph_ctx *ctx, const int64_t *handles, int32_t count, const double *dt,
+                     double *dt_used);
+
+/* Derivatives at the current state of every listed instance in one batched
+ * pass: h (Newton iteration, App. G), rho, Omega, a, du/dt and the CFL dt;
+ * positions, velocities and u are unchanged (values; the order becomes the
+ * new Morton order). */
+int shsph_eval_batch(shsph_ctx *ctx, const int64_t *handles, int32_t count);
+
+/* Pool occupancy: particles held by instances, pool capacity, instances. */
+int shsph_pool_usage(shsph_ctx *ctx, int64_t *particles_used, int64_t *particles_cap,
+                     int64_t *n_instances);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop on a host thread of the context.
+ *
+ * Jobs (advance an instance by nsteps steps, or evaluate its derivatives)
+ * are queued in arrival order.  A job is admitted when the HBM it needs fits
+ * the budget (its instance, if the job brings one, plus the working memory
+ * of its particles while it runs) and the pass has room; admitted jobs run
+ * together: every pass is one batched pass over all running jobs, and jobs
+ * join and leave at pass boundaries (continuous batching).  The
+ * one-at-a-time policy runs the same queue with a single job on the device.
+ * ---------------------------------------------------------------------- */
+#define SHSPH_SERVE_CONTINUOUS 0
+#define SHSPH_SERVE_ONE_AT_A_TIME 1
+
+#define SHSPH_JOB_STEP 0
+#define SHSPH_JOB_EVAL 1
+
+#define SHSPH_JOB_PENDING 0
+#define SHSPH_JOB_RUNNING 1
+#define SHSPH_JOB_DONE 2
+#define SHSPH_JOB_FAILED 3
+
+typedef struct {
+    double budget_bytes;          /* HBM for resident instances + running work */
+    int64_t max_batch_particles;  /* particles in one pass (0: no limit) */
+    int32_t max_batch;            /* jobs in one pass (1..2048) */
+    int32_t policy;               /* SHSPH_SERVE_* */
+} shsph_serve_config;
+
+typedef struct {
+    int64_t handle;               /* pooled instance to work on, or 0 with init */
+    const shsph_particles *init;  /* if non-NULL: the job's instance is created from
+                                     these arrays when the job is admitted; the struct
+                                     is copied at submit, the arrays must stay valid
+                                     until the job has left PENDING */
+    int32_t kind;                 /* SHSPH_JOB_STEP or SHSPH_JOB_EVAL */
+    int32_t nsteps;               /* STEP: steps to take (>= 1) */
+    double dt;                    /* STEP: > 0 fixed dt, <= 0 CFL dt */
+    int32_t release;              /* 1: destroy the instance when the job ends */
+    int32_t reserved;
+} shsph_job;
+
+typedef struct {
+    int32_t state;                /* SHSPH_JOB_* */
+    int32_t error;                /* SHSPH_E* when FAILED */
+    int64_t handle;               /* the job's instance (0 before admission) */
+    int32_t steps_done;
+    int32_t passes;               /* batched passes the job took part in */
+    double t_submit, t_start, t_done;   /* shsph_clock() seconds */
+} shsph_job_status;
+
+typedef struct {
+    int64_t jobs_done;
+    int64_t jobs_failed;
+    int64_t passes;
+    int64_t peak_jobs;            /* most jobs in one pass */
+    double particle_passes;       /* sum over passes of the particles in them */
+    double busy_s;                /* time inside passes */
+    double peak_bytes;            /* largest accounted footprint */
+} shsph_serve_counters;
+
+/* Start the loop.  EINVAL for a bad config, ESTATE if already serving. */
+int shsph_serve_start(shsph_ctx *ctx, const shsph_serve_config *cfg);
+
+/* Queue a job; *ticket identifies it.  ENOMEM if the job can never fit the
+ * budget, EINVAL for a bad job (unknown handle, nsteps < 1, dtype other
+ * than the pool's), ESTATE if not serving. */
+int shsph_submit(shsph_ctx *ctx, const shsph_job *job, uint64_t *ticket);
+
+/* Status of a job (does not wait).  EINVAL for an unknown ticket. */
+int shsph_poll(shsph_ctx *ctx, uint64_t ticket, shsph_job_status *st);
+
+/* Wait until no job is pending or running, at most timeout_s seconds
+ * (ESTATE on time-out). */
+int shsph_serve_drain(shsph_ctx *ctx, double timeout_s);
+
+/* Counters of the loop since it started. */
+int shsph_serve_stats(shsph_ctx *ctx, shsph_serve_counters *out);
+
+/* Finish pending and running jobs, then stop the loop (shsph_destroy calls it). */
+int shsph_serve_stop(shsph_ctx *ctx);
+
+/* HBM the admission rule charges for an instance of n particles of the
+ * context's dtype: pooled state, and the working memory while it runs. */
+int shsph_footprint(shsph_ctx *ctx, int64_t n, int32_t dtype, double *state_bytes,
+                    double *work_bytes);
+
+/* Seconds on the steady clock used for job timestamps. */
+double shsph_clock(void);
 
 #ifdef __cplusplus
 }

@@ -7,7 +7,9 @@ library has not been built (``python -m paper_2503_09713_amd.build``).
 
 Entry points mirror ``include/shsph.h``: ``Context.build_tree``,
 ``Context.density``, ``Context.force``, ``Context.step``,
-``Context.get_info`` and ``Context.export_tree``.
+``Context.get_info`` and ``Context.export_tree``; pooled instances and
+batched passes (``instance_create``, ``step_batch``, ``eval_batch`` ...) and
+the serving loop (``serve_start``, ``submit``, ``poll``, ``serve_drain`` ...).
 """
 from __future__ import annotations
 
@@ -60,6 +62,42 @@ class Info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+SERVE_CONTINUOUS, SERVE_ONE_AT_A_TIME = 0, 1
+JOB_STEP, JOB_EVAL = 0, 1
+JOB_STATES = {0: "pending", 1: "running", 2: "done", 3: "failed"}
+
+
+class ServeConfig(C.Structure):
+    _fields_ = [("budget_bytes", C.c_double), ("max_batch_particles", C.c_int64),
+                ("max_batch", C.c_int32), ("policy", C.c_int32)]
+
+
+class Job(C.Structure):
+    _fields_ = [("handle", C.c_int64), ("init", C.c_void_p), ("kind", C.c_int32),
+                ("nsteps", C.c_int32), ("dt", C.c_double), ("release", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class JobStatus(C.Structure):
+    _fields_ = [("state", C.c_int32), ("error", C.c_int32), ("handle", C.c_int64),
+                ("steps_done", C.c_int32), ("passes", C.c_int32), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["state"] = JOB_STATES.get(d["state"], d["state"])
+        return d
+
+
+class ServeCounters(C.Structure):
+    _fields_ = [("jobs_done", C.c_int64), ("jobs_failed", C.c_int64), ("passes", C.c_int64),
+                ("peak_jobs", C.c_int64), ("particle_passes", C.c_double), ("busy_s", C.c_double),
+                ("peak_bytes", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _EXPORT_FIELDS = ["keys", "eps", "mu", "xi", "id", "mu_leaf", "lchild", "rchild", "endrange",
                   "lflag", "rflag", "parent", "bmin", "bmax", "hmax", "pbox", "plen", "group_off",
                   "group_leaves", "neigh_off", "neigh_list", "h_sorted"]
@@ -95,10 +133,31 @@ def lib():
     L.shsph_get_work.argtypes = [vp, C.POINTER(C.c_double)]
     L.shsph_stage_name.argtypes = [C.c_int32]
     L.shsph_stage_name.restype = C.c_char_p
+    i64p, dp = C.POINTER(C.c_int64), C.POINTER(C.c_double)
+    L.shsph_instance_create.argtypes = [vp, C.POINTER(CParticles), i64p]
+    L.shsph_instance_destroy.argtypes = [vp, C.c_int64]
+    L.shsph_instance_read.argtypes = [vp, C.c_int64, C.POINTER(CParticles)]
+    L.shsph_instance_info.argtypes = [vp, C.c_int64, C.POINTER(Info)]
+    L.shsph_step_batch.argtypes = [vp, i64p, C.c_int32, dp, dp]
+    L.shsph_eval_batch.argtypes = [vp, i64p, C.c_int32]
+    L.shsph_pool_usage.argtypes = [vp, i64p, i64p, i64p]
+    L.shsph_serve_start.argtypes = [vp, C.POINTER(ServeConfig)]
+    L.shsph_submit.argtypes = [vp, C.POINTER(Job), C.POINTER(C.c_uint64)]
+    L.shsph_poll.argtypes = [vp, C.c_uint64, C.POINTER(JobStatus)]
+    L.shsph_serve_drain.argtypes = [vp, C.c_double]
+    L.shsph_serve_stats.argtypes = [vp, C.POINTER(ServeCounters)]
+    L.shsph_serve_stop.argtypes = [vp]
+    L.shsph_footprint.argtypes = [vp, C.c_int64, C.c_int32, dp, dp]
+    L.shsph_clock.argtypes = []
+    L.shsph_clock.restype = C.c_double
     for fn in ("shsph_create", "shsph_destroy", "shsph_set_stream", "shsph_build_tree",
                "shsph_density", "shsph_force", "shsph_step", "shsph_get_info",
                "shsph_export_tree", "shsph_set_profiling", "shsph_get_stage_times",
-               "shsph_get_work"):
+               "shsph_get_work", "shsph_instance_create", "shsph_instance_destroy",
+               "shsph_instance_read", "shsph_instance_info", "shsph_step_batch",
+               "shsph_eval_batch", "shsph_pool_usage", "shsph_serve_start", "shsph_submit",
+               "shsph_poll", "shsph_serve_drain", "shsph_serve_stats", "shsph_serve_stop",
+               "shsph_footprint"):
         getattr(L, fn).restype = ip
     _lib = L
     return L
@@ -262,6 +321,101 @@ class Context:
         self._check(self.L.shsph_get_work(self.h, w))
         return dict(cache_tests=w[0], cache_prune_tests=w[1], density_pair_evals=w[2],
                     density_pairs_in_2h=w[3], force_entries=w[4], force_pairs=w[5])
+
+    # ---------------------------------------------- pooled instances, batches
+    def instance_create(self, ps: ParticleSet) -> int:
+        """Copy ``ps`` into the context's instance pool; returns the handle."""
+        cp = ps.cstruct()
+        h = C.c_int64(0)
+        self._check(self.L.shsph_instance_create(self.h, C.byref(cp), C.byref(h)))
+        return h.value
+
+    def instance_destroy(self, handle: int) -> None:
+        self._check(self.L.shsph_instance_destroy(self.h, int(handle)))
+
+    def instance_read(self, handle: int, out: ParticleSet) -> None:
+        """Copy the pooled state (Morton order, ``pid`` = particle ids) into ``out``."""
+        cp = out.cstruct()
+        self._check(self.L.shsph_instance_read(self.h, int(handle), C.byref(cp)))
+
+    def instance_info(self, handle: int) -> dict:
+        o = Info()
+        self._check(self.L.shsph_instance_info(self.h, int(handle), C.byref(o)))
+        return o.as_dict()
+
+    @staticmethod
+    def _handles(handles):
+        hs = list(int(h) for h in handles)
+        return hs, (C.c_int64 * len(hs))(*hs)
+
+    def step_batch(self, handles, dt=None, allow_noconv: bool = False):
+        """One step of every listed instance in one batched pass; returns dt used."""
+        hs, arr = self._handles(handles)
+        dts = (C.c_double * len(hs))(*([0.0] * len(hs) if dt is None else
+                                       [float(d) for d in (dt if hasattr(dt, "__len__") else [dt] * len(hs))]))
+        used = (C.c_double * len(hs))()
+        allow = (SHSPH_ENOCONV,) if allow_noconv else ()
+        self._check(self.L.shsph_step_batch(self.h, arr, len(hs), dts, used), allow)
+        return list(used)
+
+    def eval_batch(self, handles, allow_noconv: bool = False) -> None:
+        hs, arr = self._handles(handles)
+        allow = (SHSPH_ENOCONV,) if allow_noconv else ()
+        self._check(self.L.shsph_eval_batch(self.h, arr, len(hs)), allow)
+
+    def pool_usage(self) -> dict:
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(self.L.shsph_pool_usage(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(particles=a.value, capacity=b.value, instances=c.value)
+
+    # ------------------------------------------------------------- serving
+    def serve_start(self, budget_bytes: float, max_batch: int = 256, policy: int = SERVE_CONTINUOUS,
+                    max_batch_particles: int = 0) -> None:
+        cfg = ServeConfig(float(budget_bytes), int(max_batch_particles), int(max_batch), int(policy))
+        self._check(self.L.shsph_serve_start(self.h, C.byref(cfg)))
+        self._keep = {}
+
+    def submit(self, handle: int = 0, init: ParticleSet | None = None, kind: int = JOB_STEP,
+               nsteps: int = 1, dt: float = 0.0, release: bool = False) -> int:
+        """Queue a job; ``init`` (kept alive here until the job is admitted) brings a new instance."""
+        cp = init.cstruct() if init is not None else None
+        job = Job(int(handle), C.cast(C.pointer(cp), C.c_void_p) if cp is not None else None,
+                  int(kind), int(nsteps), float(dt), 1 if release else 0, 0)
+        t = C.c_uint64(0)
+        self._check(self.L.shsph_submit(self.h, C.byref(job), C.byref(t)))
+        if init is not None:
+            self._keep[t.value] = init
+        return t.value
+
+    def poll(self, ticket: int) -> dict:
+        st = JobStatus()
+        self._check(self.L.shsph_poll(self.h, int(ticket), C.byref(st)))
+        d = st.as_dict()
+        if d["state"] != "pending":
+            getattr(self, "_keep", {}).pop(int(ticket), None)
+        return d
+
+    def serve_drain(self, timeout_s: float = 600.0) -> None:
+        self._check(self.L.shsph_serve_drain(self.h, float(timeout_s)))
+        getattr(self, "_keep", {}).clear()
+
+    def serve_stats(self) -> dict:
+        o = ServeCounters()
+        self._check(self.L.shsph_serve_stats(self.h, C.byref(o)))
+        return o.as_dict()
+
+    def serve_stop(self) -> None:
+        self._check(self.L.shsph_serve_stop(self.h))
+        getattr(self, "_keep", {}).clear()
+
+    def footprint(self, n: int, dtype=np.float32):
+        s, w = C.c_double(), C.c_double()
+        self._check(self.L.shsph_footprint(self.h, int(n), F32 if np.dtype(dtype) == np.float32 else F64,
+                                           C.byref(s), C.byref(w)))
+        return s.value, w.value
+
+    def clock(self) -> float:
+        return self.L.shsph_clock()
 
     def close(self) -> None:
         if getattr(self, "h", None):

@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -31,6 +33,27 @@ enum Stage {
 const char* const STAGE_NAMES[S_NUM] = {
     "predict_morton", "radix_sort", "gather", "mask_reduce_compact", "karras", "boxes",
     "group_leaf_cache", "particle_cache", "density", "force", "correct"
+};
+
+// A pooled instance: its fields live at [off, off + n) of the pool arrays.
+struct Inst {
+    i64 off = 0, n = 0;
+    double mass = 0, lo[3] = { 0, 0, 0 }, hi[3] = { 0, 0, 0 };
+    int periodic = 0;
+    bool has_force = false;     // a derivative pass has run (CFL dt known)
+    InstStat stat;              // reductions of the last pass
+    int busy = 0;               // held by a running serving job
+};
+
+// Field pools of the context's instances (structure of arrays, one dtype).
+// The free list maps offset -> length; neighbouring free ranges are merged.
+enum PoolField { PF_X, PF_Y, PF_Z, PF_VX, PF_VY, PF_VZ, PF_U, PF_H, PF_AX, PF_AY, PF_AZ, PF_DU,
+                 PF_RHO, PF_OMEGA, PF_PID, PF_NUM };
+struct Pool {
+    int dtype = -1;
+    i64 cap = 0, used = 0;
+    void* fld[PF_NUM] = {};
+    std::map<i64, i64> free_;
 };
 
 struct Prof {
@@ -75,17 +98,29 @@ struct shsph_ctx {
     Buf inst_d, poff_d, goff_d, leaf_off_d, ioff_d, root_d, stat_d, dt_inst_d, dt_host_d;
     Buf pbox, plen, xoff, xlist;                // export only
 
+    Buf redo_d, rhmax_d;                        // per-instance density redo flags, root h_max
+
     // pinned host staging for counters
-    void* pinned = nullptr;
+    void* pinned = nullptr;                     // PINNED_BYTES read-back + UPLOAD_BYTES upload
+    hipEvent_t up_done = nullptr;               // last upload from the pinned area
 
     std::vector<InstDev> inst_h;
     std::vector<i64> poff_h, goff_h;
     Prof prof;
+
+    // pooled instances (batched passes and serving)
+    Pool pool;
+    std::map<int64_t, Inst> insts;
+    int64_t next_handle = 1;
+    std::recursive_mutex mu;                    // one API call at a time on this context
+    void* server = nullptr;                     // serving loop (serve.cpp), if started
 };
 
 namespace {
 
-const size_t PINNED_BYTES = 4096;
+const size_t PINNED_BYTES = 1 << 20;      // read-back staging
+const size_t UPLOAD_BYTES = 1 << 20;      // upload staging (instance tables), after it
+const int MAX_BATCH = 2048;           // instances per batched pass (stats fit the staging)
 
 int fail(shsph_ctx* c, int code, const std::string& msg)
 {
@@ -238,6 +273,52 @@ template <class T> SortedPtrs<T> sorted(shsph_ctx* c, bool with_step)
     return s;
 }
 
+// Size the per-instance device tables for c->ninst and upload the instance
+// table and the particle / group offsets.
+int upload_instances(shsph_ctx* c)
+{
+    const int k = c->ninst;
+    TRY(ensure(c, c->inst_d, k * sizeof(InstDev)));
+    TRY(ensure(c, c->poff_d, (k + 1) * sizeof(i64)));
+    TRY(ensure(c, c->goff_d, (k + 1) * sizeof(i64)));
+    TRY(ensure(c, c->stat_d, k * sizeof(InstStat)));
+    TRY(ensure(c, c->dt_inst_d, k * sizeof(double)));
+    TRY(ensure(c, c->dt_host_d, k * sizeof(double)));
+    TRY(ensure(c, c->leaf_off_d, (k + 1) * sizeof(i64)));
+    TRY(ensure(c, c->ioff_d, (k + 1) * sizeof(i64)));
+    TRY(ensure(c, c->root_d, k * sizeof(u32)));
+    TRY(ensure(c, c->bbox, 6 * k * sizeof(u64)));
+    TRY(ensure(c, c->redo_d, k));
+    TRY(ensure(c, c->rhmax_d, k * sizeof(double)));
+    // stage through the pinned upload area (the previous upload must have left it)
+    if (c->up_done) HIPTRY(c, hipEventSynchronize(c->up_done));
+    char* up = (char*)c->pinned + PINNED_BYTES;
+    const size_t b0 = k * sizeof(InstDev), b1 = (k + 1) * sizeof(i64);
+    memcpy(up, c->inst_h.data(), b0);
+    memcpy(up + b0, c->poff_h.data(), b1);
+    memcpy(up + b0 + b1, c->goff_h.data(), b1);
+    HIPTRY(c, hipMemcpyAsync(c->inst_d.p, up, b0, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(c, hipMemcpyAsync(c->poff_d.p, up + b0, b1, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(c, hipMemcpyAsync(c->goff_d.p, up + b0 + b1, b1, hipMemcpyHostToDevice, c->stream));
+    if (!c->up_done) HIPTRY(c, hipEventCreateWithFlags(&c->up_done, hipEventDisableTiming));
+    HIPTRY(c, hipEventRecord(c->up_done, c->stream));
+    return SHSPH_OK;
+}
+
+// Upload `bytes` from host memory to device through the pinned upload area,
+// after the instance tables (same wait rule).
+int upload_extra(shsph_ctx* c, void* dst, const void* src, size_t bytes)
+{
+    const int k = c->ninst;
+    const size_t off = k * sizeof(InstDev) + 2 * (k + 1) * sizeof(i64);
+    if (off + bytes > UPLOAD_BYTES) return fail(c, SHSPH_EINVAL, "upload area too small");
+    char* up = (char*)c->pinned + PINNED_BYTES + off;
+    memcpy(up, src, bytes);
+    HIPTRY(c, hipMemcpyAsync(dst, up, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(c, hipEventRecord(c->up_done, c->stream));
+    return SHSPH_OK;
+}
+
 // Instance table for a single instance.
 int set_single_instance(shsph_ctx* c, const shsph_particles* p)
 {
@@ -246,30 +327,15 @@ int set_single_instance(shsph_ctx* c, const shsph_particles* p)
     InstDev& in = c->inst_h[0];
     in.p_off = 0;
     in.p_cnt = p->n;
+    in.shift = 0;
     for (int d = 0; d < 3; ++d) { in.lo[d] = p->lo[d]; in.hi[d] = p->hi[d]; }
     in.mass = p->mass;
     in.periodic = p->periodic ? 1 : 0;
     in.pad = 0;
     c->poff_h = { 0, p->n };
-    TRY(ensure(c, c->inst_d, sizeof(InstDev)));
-    TRY(ensure(c, c->poff_d, 2 * sizeof(i64)));
-    TRY(ensure(c, c->stat_d, sizeof(InstStat)));
-    TRY(ensure(c, c->dt_inst_d, sizeof(double)));
-    TRY(ensure(c, c->dt_host_d, sizeof(double)));
-    TRY(ensure(c, c->leaf_off_d, 2 * sizeof(i64)));
-    TRY(ensure(c, c->ioff_d, 2 * sizeof(i64)));
-    TRY(ensure(c, c->root_d, sizeof(u32)));
-    TRY(ensure(c, c->bbox, 6 * sizeof(u64)));
-    TRY(ensure(c, c->goff_d, 2 * sizeof(i64)));
     c->n_groups = (p->n + GROUP - 1) / GROUP;
     c->goff_h = { 0, c->n_groups };
-    HIPTRY(c, hipMemcpyAsync(c->inst_d.p, c->inst_h.data(), sizeof(InstDev), hipMemcpyHostToDevice,
-                             c->stream));
-    HIPTRY(c, hipMemcpyAsync(c->poff_d.p, c->poff_h.data(), 2 * sizeof(i64), hipMemcpyHostToDevice,
-                             c->stream));
-    HIPTRY(c, hipMemcpyAsync(c->goff_d.p, c->goff_h.data(), 2 * sizeof(i64), hipMemcpyHostToDevice,
-                             c->stream));
-    return SHSPH_OK;
+    return upload_instances(c);
 }
 
 GroupMap group_map(shsph_ctx* c)
@@ -311,12 +377,10 @@ CacheView cache_view(shsph_ctx* c)
 // ---------------------------------------------------------------------------
 template <class T> int build_caches(shsph_ctx* c);
 
-template <class T> int build(shsph_ctx* c, const shsph_particles* p, const double* dt_dev, bool step)
+template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const double* dt_dev, bool step)
 {
-    const i64 n = p->n;
     hipStream_t st = c->stream;
     const int nred = c->prm.n_red < 0 ? 3 : c->prm.n_red;
-    const FieldPtrs<T> f = fields<T>(p);
 
     TRY(ensure(c, c->keys[0], n * sizeof(u64)));
     TRY(ensure(c, c->keys[1], n * sizeof(u64)));
@@ -465,8 +529,9 @@ template <class T> int build_caches(shsph_ctx* c)
                               P<vec4<T>>(c->ghi), P<u32>(c->root_d), work_ptr(c, 0), st);
         prof_end(c);
         TRY(check_launch(c, "stage2"));
+        launch_root_hmax<T>(P<vec4<T>>(c->blo), P<u32>(c->root_d), ninst, P<double>(c->rhmax_d), st);
         HIPTRY(c, hipMemcpyAsync(c->pinned, c->flags.p, 4 * sizeof(u32), hipMemcpyDeviceToHost, st));
-        HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 16, P<vec4<T>>(c->blo), sizeof(vec4<T>),
+        HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 16, c->rhmax_d.p, ninst * sizeof(double),
                                  hipMemcpyDeviceToHost, st));
         HIPTRY(c, hipStreamSynchronize(st));
         u32 fl[4];
@@ -476,14 +541,14 @@ template <class T> int build_caches(shsph_ctx* c)
             return fail(c, SHSPH_ECAPACITY, "a group's candidate union exceeds 65535 particles");
         if (fl[0] & 16u) return fail(c, SHSPH_ECAPACITY, "bottom-up box records overflow");
         // periodic minimum image needs the cache radius below half the box
+        const double* rh = (const double*)((char*)c->pinned + 16);
         for (int k = 0; k < ninst; ++k) {
             const InstDev& in = c->inst_h[k];
-            if (!in.periodic || ninst != 1) continue;
-            // node 0 is the root of a single instance (internal node, or the only leaf)
-            const double hmax = (double)((vec4<T>*)((char*)c->pinned + 16))->w;
+            if (!in.periodic) continue;
             for (int d = 0; d < 3; ++d)
-                if (rk * hmax >= 0.5 * (in.hi[d] - in.lo[d]))
-                    return fail(c, SHSPH_EINVAL, "periodic box smaller than twice the cache radius");
+                if (rk * rh[k] >= 0.5 * (in.hi[d] - in.lo[d]))
+                    return fail(c, SHSPH_EINVAL, "periodic box smaller than twice the cache radius" +
+                                (ninst > 1 ? " (batch instance " + std::to_string(k) + ")" : std::string()));
         }
         if (!(fl[0] & 6u)) break;
         if (attempt >= 4) return fail(c, SHSPH_ECAPACITY, "neighbour cache capacity");
@@ -505,24 +570,31 @@ template <class T> int run_density(shsph_ctx* c, bool with_thermo)
     const SphParams sp = sph_params(c->prm);
     SortedPtrs<T> s = sorted<T>(c, false);
     if (!with_thermo) s.velu = nullptr;
+    // Instances whose h all settled keep their result; only those with a
+    // particle past chi h_cache iterate again on the rebuilt caches, so an
+    // instance gets the same h whatever else shares the pass.
+    const int ninst = c->ninst;
+    std::vector<u8> redo(ninst, 1);
     for (int attempt = 0;; ++attempt) {
-        launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
-        c->parts_pending = 0;
+        const u8* rd = attempt ? P<u8>(c->redo_d) : nullptr;
+        launch_stat_reset(P<InstStat>(c->stat_d), ninst, 1, rd, st);
         prof_begin(c, S_DENSITY);
         CacheView cvd = cache_view(c);
         cvd.work = work_ptr(c, 1);
         launch_density<T>(s, P<u32>(c->id), group_map(c), c->n_groups, P<InstDev>(c->inst_d), sp,
                           cvd, P<T>(c->omega),
                           with_thermo ? P<vec4<T>>(c->thermo) : nullptr, P<u8>(c->status),
-                          P<InstStat>(c->stat_d), st);
+                          P<InstStat>(c->stat_d), rd, st);
         prof_end(c);
         TRY(check_launch(c, "density"));
-        std::vector<InstStat> hs(c->ninst);
-        const size_t sb = std::min(c->ninst * sizeof(InstStat), PINNED_BYTES);
-        TRY(read_back(c, c->stat_d.p, sb));
-        memcpy(hs.data(), c->pinned, sb);
+        TRY(read_back(c, c->stat_d.p, ninst * sizeof(InstStat)));
+        const InstStat* hs = (const InstStat*)c->pinned;
         u32 ex = 0, nc = 0;
-        for (const InstStat& q : hs) { ex += q.n_exceed; nc += q.n_noconv; }
+        for (int k = 0; k < ninst; ++k) {
+            redo[k] = hs[k].n_exceed ? 1 : 0;
+            ex += hs[k].n_exceed;
+            nc += hs[k].n_noconv;
+        }
         if (ex == 0) {
             if (nc) return fail(c, SHSPH_ENOCONV, "h iteration did not converge for " + std::to_string(nc) + " particles");
             return SHSPH_OK;
@@ -531,6 +603,7 @@ template <class T> int run_density(shsph_ctx* c, bool with_thermo)
             return fail(c, SHSPH_ENOCONV, "h kept exceeding the cache tolerance after rebuilds");
         // rebuild the caches with the current h as the cache h
         ++c->restarts;
+        TRY(upload_extra(c, c->redo_d.p, redo.data(), ninst));
         launch_copy_h<T>(s.posh, s.hcache, n, st);
         TRY(build_caches<T>(c));
     }
@@ -542,7 +615,8 @@ template <class T> int do_build(shsph_ctx* c, const shsph_particles* p)
     c->n = p->n;
     c->dtype = p->dtype;
     c->state = ST_NONE;
-    TRY(build<T>(c, p, nullptr, false));
+    launch_stat_reset(P<InstStat>(c->stat_d), 1, 3, nullptr, c->stream);
+    TRY(build<T>(c, fields<T>(p), p->n, nullptr, false));
     prof_collect(c);
     c->state = ST_TREE;
     return SHSPH_OK;
@@ -583,8 +657,8 @@ template <class T> int do_force(shsph_ctx* c, shsph_particles* p)
     launch_thermo<T>(P<vec4<T>>(c->posh), P<vec4<T>>(c->velu), P<T>(c->omega), n, P<i64>(c->poff_d),
                      c->ninst, P<InstDev>(c->inst_d), c->prm.hfact, c->prm.gamma,
                      P<vec4<T>>(c->thermo), st);
-    launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
-        c->parts_pending = 0;
+    launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, 2, nullptr, st);
+    c->parts_pending = 0;
     const SphParams sp = sph_params(c->prm);
     prof_begin(c, S_FORCE);
     launch_force<T>(sorted<T>(c, false), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
@@ -613,21 +687,20 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
     const bool keep_stat = c->stat_d.p && c->ninst == 1;
     TRY(set_single_instance(c, p));
     if (!keep_stat && !(dt > 0)) return fail(c, SHSPH_ESTATE, "no CFL dt available");
-    *(double*)c->pinned = dt;
-    HIPTRY(c, hipMemcpyAsync(c->dt_host_d.p, c->pinned, sizeof(double), hipMemcpyHostToDevice, st));
+    TRY(upload_extra(c, c->dt_host_d.p, &dt, sizeof(double)));
     launch_dt_select(P<double>(c->dt_inst_d), P<InstStat>(c->stat_d), P<double>(c->dt_host_d), 1, st);
     c->n = p->n;
     c->dtype = p->dtype;
     c->state = ST_NONE;
     const double* dt_dev = P<double>(c->dt_inst_d);
-    TRY(build<T>(c, p, dt_dev, true));
+    TRY(build<T>(c, fields<T>(p), p->n, dt_dev, true));
     c->state = ST_TREE;
     int rc = run_density<T>(c, true);
     if (rc != SHSPH_OK) return rc;
     const i64 n = c->n;
     TRY(ensure(c, c->acc, n * sizeof(vec4<T>)));
-    launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, st);
-        c->parts_pending = 0;
+    launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, 2, nullptr, st);
+    c->parts_pending = 0;
     const SphParams sp = sph_params(c->prm);
     prof_begin(c, S_FORCE);
     CacheView cvf = cache_view(c);
@@ -673,7 +746,241 @@ int sum_u32(shsph_ctx* c, const u32* p, i64 count, u64* out)
     return SHSPH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Instance pool: one array per field for all pooled instances; an instance
+// is a contiguous range [off, off + n).  Ranges are handed out first-fit and
+// merged on release; the arrays grow (copy + free) when no range fits.
+// ---------------------------------------------------------------------------
+size_t pool_elem(int f, int dtype) { return f == PF_PID ? 4 : (dtype == SHSPH_F32 ? 4 : 8); }
+
+void pool_release(shsph_ctx* c)
+{
+    Pool& q = c->pool;
+    for (int f = 0; f < PF_NUM; ++f)
+        if (q.fld[f]) { (void)hipFree(q.fld[f]); q.fld[f] = nullptr; }
+    q.cap = 0;
+    q.used = 0;
+    q.free_.clear();
+}
+
+void pool_put(Pool& q, i64 off, i64 len)
+{
+    auto it = q.free_.emplace(off, len).first;
+    if (it != q.free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) { pv->second += it->second; q.free_.erase(it); it = pv; }
+    }
+    auto nx = std::next(it);
+    if (nx != q.free_.end() && it->first + it->second == nx->first) { it->second += nx->second; q.free_.erase(nx); }
+}
+
+int pool_grow(shsph_ctx* c, i64 need)
+{
+    Pool& q = c->pool;
+    const i64 ncap = std::max<i64>(q.cap + std::max<i64>(need, q.cap / 2), (i64)1 << 16);
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    void* nf[PF_NUM] = {};
+    for (int f = 0; f < PF_NUM; ++f) {
+        if (hipMalloc(&nf[f], ncap * pool_elem(f, q.dtype)) != hipSuccess) {
+            for (int g = 0; g < PF_NUM; ++g) if (nf[g]) hipFree(nf[g]);
+            (void)hipGetLastError();
+            return fail(c, SHSPH_ENOMEM, "instance pool: device memory exhausted");
+        }
+    }
+    for (int f = 0; f < PF_NUM; ++f) {
+        if (q.cap)
+            HIPTRY(c, hipMemcpyAsync(nf[f], q.fld[f], q.cap * pool_elem(f, q.dtype),
+                                     hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    for (int f = 0; f < PF_NUM; ++f) {
+        if (q.fld[f]) hipFree(q.fld[f]);
+        q.fld[f] = nf[f];
+    }
+    pool_put(q, q.cap, ncap - q.cap);
+    q.cap = ncap;
+    return SHSPH_OK;
+}
+
+int pool_alloc(shsph_ctx* c, i64 n, i64* off)
+{
+    Pool& q = c->pool;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (auto it = q.free_.begin(); it != q.free_.end(); ++it) {
+            if (it->second < n) continue;
+            *off = it->first;
+            const i64 rest = it->second - n, roff = it->first + n;
+            q.free_.erase(it);
+            if (rest) q.free_.emplace(roff, rest);
+            q.used += n;
+            return SHSPH_OK;
+        }
+        if (pass == 0) TRY(pool_grow(c, n));
+    }
+    return fail(c, SHSPH_ENOMEM, "instance pool: no range fits");
+}
+
+template <class T> FieldPtrs<T> pool_fields(shsph_ctx* c)
+{
+    void* const* f = c->pool.fld;
+    FieldPtrs<T> r;
+    r.x = (const T*)f[PF_X]; r.y = (const T*)f[PF_Y]; r.z = (const T*)f[PF_Z];
+    r.vx = (const T*)f[PF_VX]; r.vy = (const T*)f[PF_VY]; r.vz = (const T*)f[PF_VZ];
+    r.u = (const T*)f[PF_U]; r.h = (const T*)f[PF_H];
+    r.ax = (const T*)f[PF_AX]; r.ay = (const T*)f[PF_AY]; r.az = (const T*)f[PF_AZ];
+    r.du = (const T*)f[PF_DU];
+    r.pid = (const u32*)f[PF_PID];
+    return r;
+}
+
+template <class T> OutPtrs<T> pool_out(shsph_ctx* c)
+{
+    void* const* f = c->pool.fld;
+    OutPtrs<T> o;
+    o.x = (T*)f[PF_X]; o.y = (T*)f[PF_Y]; o.z = (T*)f[PF_Z];
+    o.vx = (T*)f[PF_VX]; o.vy = (T*)f[PF_VY]; o.vz = (T*)f[PF_VZ];
+    o.u = (T*)f[PF_U]; o.h = (T*)f[PF_H];
+    o.ax = (T*)f[PF_AX]; o.ay = (T*)f[PF_AY]; o.az = (T*)f[PF_AZ]; o.du = (T*)f[PF_DU];
+    o.rho = (T*)f[PF_RHO]; o.omega = (T*)f[PF_OMEGA]; o.pid = (u32*)f[PF_PID];
+    return o;
+}
+
+// One pass of the whole step over pooled instances b with per-instance dt
+// (dt = 0: derivatives at the current state, the state itself unchanged).
+// Every stage is one launch over all of them.  Instances whose h iteration
+// does not settle are reported through their stats (SHSPH_ENOCONV); the
+// others are complete.
+template <class T> int batch_pass(shsph_ctx* c, const std::vector<Inst*>& b, const std::vector<double>& dt)
+{
+    hipStream_t st = c->stream;
+    const int ninst = (int)b.size();
+    c->state = ST_NONE;
+    c->ninst = ninst;
+    c->inst_h.assign(ninst, InstDev());
+    c->poff_h.assign(ninst + 1, 0);
+    c->goff_h.assign(ninst + 1, 0);
+    i64 off = 0, g = 0;
+    for (int k = 0; k < ninst; ++k) {
+        InstDev& in = c->inst_h[k];
+        in.p_off = off;
+        in.p_cnt = b[k]->n;
+        in.shift = b[k]->off - off;
+        for (int d = 0; d < 3; ++d) { in.lo[d] = b[k]->lo[d]; in.hi[d] = b[k]->hi[d]; }
+        in.mass = b[k]->mass;
+        in.periodic = b[k]->periodic;
+        in.pad = 0;
+        c->poff_h[k] = off;
+        c->goff_h[k] = g;
+        off += b[k]->n;
+        g += (b[k]->n + GROUP - 1) / GROUP;
+    }
+    c->poff_h[ninst] = off;
+    c->goff_h[ninst] = g;
+    c->n = off;
+    c->n_groups = g;
+    c->dtype = c->pool.dtype;
+    TRY(upload_instances(c));
+    TRY(upload_extra(c, c->dt_inst_d.p, dt.data(), ninst * sizeof(double)));
+    launch_stat_reset(P<InstStat>(c->stat_d), ninst, 3, nullptr, st);
+    const double* dt_dev = P<double>(c->dt_inst_d);
+    TRY(build<T>(c, pool_fields<T>(c), off, dt_dev, true));
+    const int rc = run_density<T>(c, true);
+    if (rc != SHSPH_OK && rc != SHSPH_ENOCONV) return rc;
+    const i64 n = c->n;
+    TRY(ensure(c, c->acc, n * sizeof(vec4<T>)));
+    launch_stat_reset(P<InstStat>(c->stat_d), ninst, 2, nullptr, st);
+    const SphParams sp = sph_params(c->prm);
+    prof_begin(c, S_FORCE);
+    CacheView cvf = cache_view(c);
+    cvf.work = work_ptr(c, 2);
+    launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
+                    c->n_groups, P<InstDev>(c->inst_d), sp, cvf, P<vec4<T>>(c->acc), nullptr,
+                    P<InstStat>(c->stat_d), st);
+    prof_end(c);
+    TRY(check_launch(c, "force"));
+    const i64 nb = (n + GROUP - 1) / GROUP;
+    TRY(ensure(c, c->bpart, nb * sizeof(BlockPart)));
+    prof_begin(c, S_CORRECT);
+    launch_correct<T>(sorted<T>(c, true), P<vec4<T>>(c->acc), P<T>(c->omega), n, P<i64>(c->poff_d),
+                      ninst, P<InstDev>(c->inst_d), dt_dev, c->prm.hfact, pool_out<T>(c),
+                      P<InstStat>(c->stat_d), P<BlockPart>(c->bpart), st);
+    prof_end(c);
+    launch_fold_parts(P<BlockPart>(c->bpart), nb, ninst, P<InstStat>(c->stat_d), st);
+    c->parts_pending = 0;
+    TRY(check_launch(c, "correct"));
+    TRY(read_back(c, c->stat_d.p, ninst * sizeof(InstStat)));
+    prof_collect(c);
+    const InstStat* hs = (const InstStat*)c->pinned;
+    for (int k = 0; k < ninst; ++k) {
+        b[k]->stat = hs[k];
+        b[k]->has_force = true;
+    }
+    return rc;
+}
+
+Inst* find_inst(shsph_ctx* c, int64_t h)
+{
+    auto it = c->insts.find(h);
+    return it == c->insts.end() ? nullptr : &it->second;
+}
+
+double inst_dt_cfl(const Inst& in)
+{
+    float f;
+    memcpy(&f, &in.stat.dt_bits, 4);
+    return (double)f;
+}
+
+// Resolve handles and the dt of each instance for a stepping pass; CFL
+// instances without a derivative pass get one first (dt = 0).
+int gather_batch(shsph_ctx* c, const int64_t* handles, int32_t count, std::vector<Inst*>& b)
+{
+    if (!handles || count < 1 || count > MAX_BATCH)
+        return fail(c, SHSPH_EINVAL, "batch needs 1.." + std::to_string(MAX_BATCH) + " handles");
+    b.clear();
+    for (int k = 0; k < count; ++k) {
+        Inst* in = find_inst(c, handles[k]);
+        if (!in) return fail(c, SHSPH_EINVAL, "unknown instance handle " + std::to_string(handles[k]));
+        if (in->busy) return fail(c, SHSPH_ESTATE, "instance is held by a serving job");
+        for (Inst* o : b)
+            if (o == in) return fail(c, SHSPH_EINVAL, "a handle appears twice in the batch");
+        b.push_back(in);
+    }
+    return SHSPH_OK;
+}
+
+int run_pass(shsph_ctx* c, const std::vector<Inst*>& b, const std::vector<double>& dt)
+{
+    return c->pool.dtype == SHSPH_F32 ? batch_pass<float>(c, b, dt) : batch_pass<double>(c, b, dt);
+}
+
 }  // namespace
+
+// Internal entry points of the serving loop (serve.cpp): a pass over pooled
+// instances, their sizes, and the context lock.
+int shsph_internal_pass(shsph_ctx* c, const int64_t* handles, const double* dt, int32_t count)
+{
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    std::vector<Inst*> b;
+    TRY(gather_batch(c, handles, count, b));
+    HIPTRY(c, hipSetDevice(c->device));
+    return run_pass(c, b, std::vector<double>(dt, dt + count));
+}
+
+int shsph_internal_inst_state(shsph_ctx* c, int64_t h, int64_t* n, int* has_force, double* dt_cfl, int busy_delta)
+{
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    Inst* in = find_inst(c, h);
+    if (!in) return SHSPH_EINVAL;
+    if (n) *n = in->n;
+    if (has_force) *has_force = in->has_force ? 1 : 0;
+    if (dt_cfl) *dt_cfl = inst_dt_cfl(*in);
+    in->busy += busy_delta;
+    return SHSPH_OK;
+}
+
+void*& shsph_internal_server(shsph_ctx* c) { return c->server; }
+int shsph_internal_dtype(shsph_ctx* c) { return c->pool.dtype; }
 
 // =========================================================== C interface ===
 extern "C" {
@@ -711,7 +1018,7 @@ int shsph_create(int device, const shsph_params* p, shsph_ctx** out)
         delete c;
         return SHSPH_EINVAL;
     }
-    if (hipSetDevice(device) != hipSuccess || hipHostMalloc(&c->pinned, PINNED_BYTES) != hipSuccess) {
+    if (hipSetDevice(device) != hipSuccess || hipHostMalloc(&c->pinned, PINNED_BYTES + UPLOAD_BYTES) != hipSuccess) {
         delete c;
         return SHSPH_EHIP;
     }
@@ -723,8 +1030,11 @@ int shsph_create(int device, const shsph_params* p, shsph_ctx** out)
 int shsph_destroy(shsph_ctx* c)
 {
     if (!c) return SHSPH_EINVAL;
+    if (c->server) shsph_serve_stop(c);
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
+    pool_release(c);
+    if (c->up_done) hipEventDestroy(c->up_done);
     Buf* all[] = { &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->hist, &c->hist_scan,
                    &c->scan_tmp, &c->bbox, &c->posh, &c->velu, &c->vhalf, &c->hn, &c->hcache,
                    &c->pid_s, &c->thermo, &c->omega, &c->acc, &c->vsig, &c->status, &c->xi[0],
@@ -734,7 +1044,7 @@ int shsph_destroy(shsph_ctx* c)
                    &c->ucnt, &c->ustot, &c->nlist, &c->ncnt, &c->flags, &c->inst_d, &c->poff_d,
                    &c->goff_d, &c->leaf_off_d, &c->ioff_d, &c->root_d, &c->stat_d,
                    &c->dt_inst_d, &c->dt_host_d, &c->pbox, &c->plen, &c->xoff, &c->xlist,
-                   &c->bpart, &c->work[0], &c->work[1], &c->work[2] };
+                   &c->bpart, &c->work[0], &c->work[1], &c->work[2], &c->redo_d, &c->rhmax_d };
     for (Buf* b : all)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);
@@ -746,6 +1056,7 @@ int shsph_destroy(shsph_ctx* c)
 int shsph_set_stream(shsph_ctx* c, void* stream)
 {
     if (!c) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     c->stream = (hipStream_t)stream;
     return SHSPH_OK;
 }
@@ -755,6 +1066,7 @@ const char* shsph_last_error(const shsph_ctx* c) { return c ? c->err.c_str() : "
 int shsph_build_tree(shsph_ctx* c, const shsph_particles* p)
 {
     if (!c) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     c->err.clear();
     TRY(validate(c, p, false, false));
     HIPTRY(c, hipSetDevice(c->device));
@@ -764,6 +1076,7 @@ int shsph_build_tree(shsph_ctx* c, const shsph_particles* p)
 int shsph_density(shsph_ctx* c, shsph_particles* p)
 {
     if (!c) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     c->err.clear();
     TRY(validate(c, p, false, false));
     if (c->state < ST_TREE || p->n != c->n || p->dtype != c->dtype)
@@ -775,6 +1088,7 @@ int shsph_density(shsph_ctx* c, shsph_particles* p)
 int shsph_force(shsph_ctx* c, shsph_particles* p)
 {
     if (!c) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     c->err.clear();
     TRY(validate(c, p, true, true));
     if (c->state < ST_DENSITY || p->n != c->n || p->dtype != c->dtype)
@@ -786,6 +1100,7 @@ int shsph_force(shsph_ctx* c, shsph_particles* p)
 int shsph_step(shsph_ctx* c, shsph_particles* p, double dt, double* dt_used)
 {
     if (!c) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     c->err.clear();
     TRY(validate(c, p, true, true));
     if (!std::isfinite(dt)) return fail(c, SHSPH_EINVAL, "dt must be finite");
@@ -797,6 +1112,7 @@ int shsph_step(shsph_ctx* c, shsph_particles* p, double dt, double* dt_used)
 int shsph_set_profiling(shsph_ctx* c, int on)
 {
     if (!c) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     c->prof.on = on != 0;
     c->prof.used = 0;
     HIPTRY(c, hipSetDevice(c->device));
@@ -811,6 +1127,7 @@ int shsph_set_profiling(shsph_ctx* c, int on)
 int shsph_get_work(shsph_ctx* c, double* out6)
 {
     if (!c || !out6) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     for (int k = 0; k < 6; ++k) out6[k] = 0.0;
     HIPTRY(c, hipSetDevice(c->device));
     for (int k = 0; k < 3; ++k) {
@@ -826,6 +1143,7 @@ int shsph_get_work(shsph_ctx* c, double* out6)
 int shsph_get_stage_times(shsph_ctx* c, double* ms, int64_t* launches, int32_t n)
 {
     if (!c || n < 0) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     for (int i = 0; i < n && i < S_NUM; ++i) {
         if (ms) ms[i] = c->prof.ms[i];
         if (launches) launches[i] = c->prof.launches[i];
@@ -838,6 +1156,7 @@ const char* shsph_stage_name(int32_t i) { return (i >= 0 && i < S_NUM) ? STAGE_N
 int shsph_get_info(shsph_ctx* c, shsph_info* o)
 {
     if (!c || !o) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     c->err.clear();
     memset(o, 0, sizeof(*o));
     o->n = c->n;
@@ -879,6 +1198,7 @@ int shsph_get_info(shsph_ctx* c, shsph_info* o)
 int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
 {
     if (!c || !o) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     if (c->state < ST_TREE) return fail(c, SHSPH_ESTATE, "no tree built");
     HIPTRY(c, hipSetDevice(c->device));
     hipStream_t st = c->stream;
@@ -969,6 +1289,169 @@ int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
         for (i64 i = 0; i < n; ++i) memcpy((char*)o->h_sorted + i * T, &ph[(4 * i + 3) * T], T);
     }
     HIPTRY(c, hipStreamSynchronize(st));
+    return SHSPH_OK;
+}
+
+
+// ----------------------------------------------- pooled instances, batches ---
+int shsph_instance_create(shsph_ctx* c, const shsph_particles* p, int64_t* handle)
+{
+    if (!c || !handle) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->err.clear();
+    TRY(validate(c, p, true, false));
+    HIPTRY(c, hipSetDevice(c->device));
+    Pool& q = c->pool;
+    if (q.used == 0 && q.dtype != p->dtype) {
+        HIPTRY(c, hipStreamSynchronize(c->stream));
+        pool_release(c);
+        q.dtype = p->dtype;
+    }
+    if (q.dtype != p->dtype)
+        return fail(c, SHSPH_EINVAL, "all pooled instances of a context share one dtype");
+    const i64 n = p->n;
+    i64 off = 0;
+    TRY(pool_alloc(c, n, &off));
+    const size_t es = pool_elem(PF_X, q.dtype);
+    const void* src[PF_NUM] = { p->x, p->y, p->z, p->vx, p->vy, p->vz, p->u, p->h,
+                                p->ax, p->ay, p->az, p->dudt, p->rho, p->omega, p->pid };
+    int rc = SHSPH_OK;
+    for (int f = 0; f < PF_NUM && rc == SHSPH_OK; ++f) {
+        char* dst = (char*)q.fld[f] + off * pool_elem(f, q.dtype);
+        hipError_t e;
+        if (src[f]) e = hipMemcpyAsync(dst, src[f], n * pool_elem(f, q.dtype), hipMemcpyDefault, c->stream);
+        else if (f == PF_PID) { launch_iota_u32((u32*)dst, n, c->stream); e = hipGetLastError(); }
+        else e = hipMemsetAsync(dst, 0, n * es, c->stream);
+        if (e != hipSuccess) rc = fail(c, SHSPH_EHIP, std::string("instance copy: ") + hipGetErrorString(e));
+    }
+    if (rc == SHSPH_OK && hipStreamSynchronize(c->stream) != hipSuccess)
+        rc = fail(c, SHSPH_EHIP, "instance copy failed");
+    if (rc != SHSPH_OK) {
+        pool_put(q, off, n);
+        q.used -= n;
+        return rc;
+    }
+    Inst in;
+    in.off = off;
+    in.n = n;
+    in.mass = p->mass;
+    for (int d = 0; d < 3; ++d) { in.lo[d] = p->lo[d]; in.hi[d] = p->hi[d]; }
+    in.periodic = p->periodic ? 1 : 0;
+    memset(&in.stat, 0, sizeof(in.stat));
+    in.stat.dt_bits = 0x7f800000u;
+    *handle = c->next_handle++;
+    c->insts[*handle] = in;
+    return SHSPH_OK;
+}
+
+int shsph_instance_destroy(shsph_ctx* c, int64_t handle)
+{
+    if (!c) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->err.clear();
+    Inst* in = find_inst(c, handle);
+    if (!in) return fail(c, SHSPH_EINVAL, "unknown instance handle");
+    if (in->busy) return fail(c, SHSPH_ESTATE, "instance is held by a serving job");
+    pool_put(c->pool, in->off, in->n);
+    c->pool.used -= in->n;
+    c->insts.erase(handle);
+    return SHSPH_OK;
+}
+
+int shsph_instance_read(shsph_ctx* c, int64_t handle, const shsph_particles* out)
+{
+    if (!c || !out) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->err.clear();
+    Inst* in = find_inst(c, handle);
+    if (!in) return fail(c, SHSPH_EINVAL, "unknown instance handle");
+    if (out->n != in->n || out->dtype != c->pool.dtype)
+        return fail(c, SHSPH_EINVAL, "output size or dtype differs from the instance");
+    HIPTRY(c, hipSetDevice(c->device));
+    Pool& q = c->pool;
+    void* dst[PF_NUM] = { out->x, out->y, out->z, out->vx, out->vy, out->vz, out->u, out->h,
+                          out->ax, out->ay, out->az, out->dudt, out->rho, out->omega, out->pid };
+    for (int f = 0; f < PF_NUM; ++f) {
+        if (!dst[f]) continue;
+        const size_t es = pool_elem(f, q.dtype);
+        HIPTRY(c, hipMemcpyAsync(dst[f], (char*)q.fld[f] + in->off * es, in->n * es,
+                                 hipMemcpyDefault, c->stream));
+    }
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    return SHSPH_OK;
+}
+
+int shsph_instance_info(shsph_ctx* c, int64_t handle, shsph_info* o)
+{
+    if (!c || !o) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->err.clear();
+    Inst* in = find_inst(c, handle);
+    if (!in) return fail(c, SHSPH_EINVAL, "unknown instance handle");
+    memset(o, 0, sizeof(*o));
+    o->n = in->n;
+    o->n_red = c->prm.n_red;
+    const InstStat& s = in->stat;
+    float dv;
+    memcpy(&dv, &s.dvmax_bits, 4);
+    o->dt_cfl = inst_dt_cfl(*in);
+    o->dv_max = dv;
+    for (int i = 0; i < STAT_SLOTS; ++i) { o->dv2_sum += s.dv2_part[i]; o->v2_sum += s.v2_part[i]; }
+    o->max_iter_seen = (int32_t)s.max_iter_seen;
+    o->n_noconv = (int32_t)s.n_noconv;
+    return SHSPH_OK;
+}
+
+int shsph_step_batch(shsph_ctx* c, const int64_t* handles, int32_t count, const double* dt,
+                     double* dt_used)
+{
+    if (!c) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->err.clear();
+    std::vector<Inst*> b;
+    TRY(gather_batch(c, handles, count, b));
+    HIPTRY(c, hipSetDevice(c->device));
+    std::vector<Inst*> pre;
+    for (int k = 0; k < count; ++k) {
+        const double d = dt ? dt[k] : 0.0;
+        if (!std::isfinite(d)) return fail(c, SHSPH_EINVAL, "dt must be finite");
+        if (!(d > 0) && !b[k]->has_force) pre.push_back(b[k]);
+    }
+    int rc = SHSPH_OK;
+    if (!pre.empty()) {
+        rc = run_pass(c, pre, std::vector<double>(pre.size(), 0.0));
+        if (rc != SHSPH_OK) return rc;
+    }
+    std::vector<double> d(count);
+    for (int k = 0; k < count; ++k) {
+        d[k] = (dt && dt[k] > 0) ? dt[k] : inst_dt_cfl(*b[k]);
+        if (!(d[k] > 0) || !std::isfinite(d[k]))
+            return fail(c, SHSPH_ESTATE, "no finite CFL dt for instance " + std::to_string(handles[k]));
+    }
+    rc = run_pass(c, b, d);
+    if (dt_used && (rc == SHSPH_OK || rc == SHSPH_ENOCONV))
+        for (int k = 0; k < count; ++k) dt_used[k] = d[k];
+    return rc;
+}
+
+int shsph_eval_batch(shsph_ctx* c, const int64_t* handles, int32_t count)
+{
+    if (!c) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->err.clear();
+    std::vector<Inst*> b;
+    TRY(gather_batch(c, handles, count, b));
+    HIPTRY(c, hipSetDevice(c->device));
+    return run_pass(c, b, std::vector<double>(count, 0.0));
+}
+
+int shsph_pool_usage(shsph_ctx* c, int64_t* particles_used, int64_t* particles_cap, int64_t* n_instances)
+{
+    if (!c) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (particles_used) *particles_used = c->pool.used;
+    if (particles_cap) *particles_cap = c->pool.cap;
+    if (n_instances) *n_instances = (int64_t)c->insts.size();
     return SHSPH_OK;
 }
 

@@ -31,6 +31,9 @@ template <class T> __host__ __device__ inline vec4<T> mk4(T a, T b, T c, T d)
 // One row per independent SPH instance; the plain API is a table of one.
 struct InstDev {
     i64 p_off, p_cnt;        // particle range in the (batched) arrays
+    i64 shift;               // caller-array index = batch index + shift (0 for
+                             // caller arrays; pool offset - p_off for pooled
+                             // instances, which live anywhere in the pool)
     double lo[3], hi[3];     // box; isolated instances get the data extent
     double mass;
     i32 periodic;

@@ -132,14 +132,17 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
 
 // sph.hip
 void launch_fill_u32(u32* p, i64 n, u32 v, hipStream_t st);
-void launch_stat_reset(InstStat* s, int ninst, hipStream_t st);
+void launch_iota_u32(u32* p, i64 n, hipStream_t st);
+void launch_stat_reset(InstStat* s, int ninst, int what, const u8* redo, hipStream_t st);
+template <class T>
+void launch_root_hmax(const vec4<T>* blo, const u32* root, int ninst, double* out, hipStream_t st);
 void launch_dt_select(double* dt_inst, const InstStat* s, const double* dt_host, int ninst,
                       hipStream_t st);
 template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStream_t st);
 template <class T>
 void launch_density(const SortedPtrs<T>& s, const u32* id, const GroupMap& gm, i64 ngroups,
                     const InstDev* inst, const SphParams& P, const CacheView& cv, T* omega,
-                    vec4<T>* thermo, u8* status, InstStat* stat, hipStream_t st);
+                    vec4<T>* thermo, u8* status, InstStat* stat, const u8* redo, hipStream_t st);
 template <class T>
 void launch_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id, const GroupMap& gm,
                   i64 ngroups, const InstDev* inst, const SphParams& P, const CacheView& cv,

@@ -17,19 +17,40 @@ __global__ void k_fill_u32(u32* p, i64 n, u32 v)
     if (i < n) p[i] = v;
 }
 
-__global__ void k_stat_reset(InstStat* s, int ninst)
+__global__ void k_iota_u32(u32* p, i64 n)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (u32)i;
+}
+
+// Reset per-instance reductions: what & 1 the h-iteration counters (only for
+// instances with redo[k] != 0 when redo is given), what & 2 the timestep and
+// corrector reductions.
+__global__ void k_stat_reset(InstStat* s, int ninst, int what, const u8* redo)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ninst) return;
-    InstStat z;
-    z.dt_bits = 0x7f800000u;   // +inf
-    z.dvmax_bits = 0u;
-    z.n_exceed = 0u;
-    z.n_noconv = 0u;
-    z.max_iter_seen = 0u;
+    InstStat& z = s[k];
+    if ((what & 1) && (!redo || redo[k])) {
+        z.n_exceed = 0u;
+        z.n_noconv = 0u;
+        z.max_iter_seen = 0u;
+    }
+    if (what & 2) {
+        z.dt_bits = 0x7f800000u;   // +inf
+        z.dvmax_bits = 0u;
+        for (int i = 0; i < STAT_SLOTS; ++i) { z.dv2_part[i] = 0.0; z.v2_part[i] = 0.0; }
+    }
     z.pad[0] = z.pad[1] = z.pad[2] = 0u;
-    for (int i = 0; i < STAT_SLOTS; ++i) { z.dv2_part[i] = 0.0; z.v2_part[i] = 0.0; }
-    s[k] = z;
+}
+
+// h_max of each instance's root cell (for the periodic radius check).
+template <class T>
+__global__ void k_root_hmax(const vec4<T>* __restrict__ blo, const u32* __restrict__ root,
+                            int ninst, double* __restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < ninst) out[k] = (double)blo[root[k]].w;
 }
 
 // dt for the coming step: the caller's value when positive, else the CFL dt
@@ -133,7 +154,8 @@ __global__ void __launch_bounds__(GROUP)
 k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restrict__ hc,
           const vec4<T>* __restrict__ velu, const u32* __restrict__ id, const GroupMap gm,
           const InstDev* __restrict__ inst, SphParams P, CacheView cv, T* __restrict__ omega,
-          vec4<T>* __restrict__ thermo, u8* __restrict__ status, InstStat* __restrict__ stat)
+          vec4<T>* __restrict__ thermo, u8* __restrict__ status, InstStat* __restrict__ stat,
+          const u8* __restrict__ redo)
 {
     __shared__ vec4<T> s_pos[CH];
     __shared__ u32 s_red[GROUP / WAVE];
@@ -143,6 +165,7 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
     i64 beg, end;
     int k;
     gm.range(g, beg, end, k);
+    if (redo && !redo[k]) return;     // this instance's h is final (uniform per group)
     const InstDev in = inst[k];
     const Box<T> bx = make_box<T>(in);
     const i64 a = beg + threadIdx.x;
@@ -439,14 +462,15 @@ k_correct(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     float dv = 0.f;
     double dv2 = 0.0, v2 = 0.0;
     if (live) {
-        o.x[i] = p.x; o.y[i] = p.y; o.z[i] = p.z; o.h[i] = p.w;
-        o.vx[i] = vx; o.vy[i] = vy; o.vz[i] = vz; o.u[i] = u;
-        o.ax[i] = a.x; o.ay[i] = a.y; o.az[i] = a.z; o.du[i] = a.w;
-        if (o.pid) o.pid[i] = pid[i];
-        if (o.omega) o.omega[i] = omega[i];
+        const i64 c = i + inst[k].shift;
+        o.x[c] = p.x; o.y[c] = p.y; o.z[c] = p.z; o.h[c] = p.w;
+        o.vx[c] = vx; o.vy[c] = vy; o.vz[c] = vz; o.u[c] = u;
+        o.ax[c] = a.x; o.ay[c] = a.y; o.az[c] = a.z; o.du[c] = a.w;
+        if (o.pid) o.pid[c] = pid[i];
+        if (o.omega) o.omega[c] = omega[i];
         if (o.rho) {
             const double hf = hfact / (double)p.w;
-            o.rho[i] = (T)(inst[k].mass * hf * hf * hf);
+            o.rho[c] = (T)(inst[k].mass * hf * hf * hf);
         }
         dv2 = (double)dvx * dvx + (double)dvy * dvy + (double)dvz * dvz;
         dv = (float)sqrt(dv2);
@@ -569,9 +593,20 @@ void launch_fill_u32(u32* p, i64 n, u32 v, hipStream_t st)
     if (n > 0) hipLaunchKernelGGL(k_fill_u32, grid_for(n, 256), dim3(256), 0, st, p, n, v);
 }
 
-void launch_stat_reset(InstStat* s, int ninst, hipStream_t st)
+void launch_iota_u32(u32* p, i64 n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_stat_reset, grid_for(ninst, 64), dim3(64), 0, st, s, ninst);
+    if (n > 0) hipLaunchKernelGGL(k_iota_u32, grid_for(n, 256), dim3(256), 0, st, p, n);
+}
+
+void launch_stat_reset(InstStat* s, int ninst, int what, const u8* redo, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stat_reset, grid_for(ninst, 64), dim3(64), 0, st, s, ninst, what, redo);
+}
+
+template <class T>
+void launch_root_hmax(const vec4<T>* blo, const u32* root, int ninst, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_root_hmax<T>), grid_for(ninst, 64), dim3(64), 0, st, blo, root, ninst, out);
 }
 
 void launch_dt_select(double* dt_inst, const InstStat* s, const double* dt_host, int ninst,
@@ -591,17 +626,17 @@ constexpr int FORCE_CH_F = 1280, FORCE_CH_D = 640;
 template <class T>
 void launch_density(const SortedPtrs<T>& s, const u32* id, const GroupMap& gm, i64 ngroups,
                     const InstDev* inst, const SphParams& P, const CacheView& cv, T* omega,
-                    vec4<T>* thermo, u8* status, InstStat* stat, hipStream_t st)
+                    vec4<T>* thermo, u8* status, InstStat* stat, const u8* redo, hipStream_t st)
 {
     if (ngroups <= 0) return;
     if (sizeof(T) == 4)
         hipLaunchKernelGGL((k_density<T, DENS_CH_F>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
                            s.posh, s.hn, s.hcache, s.velu, id, gm, inst, P, cv, omega, thermo,
-                           status, stat);
+                           status, stat, redo);
     else
         hipLaunchKernelGGL((k_density<T, DENS_CH_D>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
                            s.posh, s.hn, s.hcache, s.velu, id, gm, inst, P, cv, omega, thermo,
-                           status, stat);
+                           status, stat, redo);
 }
 
 template <class T>
@@ -678,7 +713,8 @@ void launch_scatter_rho(const u32* eps, i64 n, const vec4<T>* posh, const i64* p
     template void launch_copy_h<T>(const vec4<T>*, T*, i64, hipStream_t);                         \
     template void launch_density<T>(const SortedPtrs<T>&, const u32*, const GroupMap&, i64,       \
                                     const InstDev*, const SphParams&, const CacheView&, T*,       \
-                                    vec4<T>*, u8*, InstStat*, hipStream_t);                        \
+                                    vec4<T>*, u8*, InstStat*, const u8*, hipStream_t);             \
+    template void launch_root_hmax<T>(const vec4<T>*, const u32*, int, double*, hipStream_t);     \
     template void launch_force<T>(const SortedPtrs<T>&, const vec4<T>*, const u32*,               \
                                   const GroupMap&, i64, const InstDev*, const SphParams&,         \
                                   const CacheView&, vec4<T>*, T*, InstStat*, hipStream_t);         \

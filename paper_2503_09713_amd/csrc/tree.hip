@@ -93,6 +93,7 @@ __global__ void k_predict_morton(FieldPtrs<T> f, i64 n, const InstDev* __restric
     if (i >= n) return;
     const int k = find_seg(p_off, ninst, i);
     const InstDev in = inst[k];
+    const i64 ic = i + in.shift;
     double x, y, z;
     if (dt_inst) {
         const Box<T> bx = make_box<T>(in);
@@ -100,10 +101,10 @@ __global__ void k_predict_morton(FieldPtrs<T> f, i64 n, const InstDev* __restric
         const T* vp[3] = { f.vx, f.vy, f.vz };
         const T* ap[3] = { f.ax, f.ay, f.az };
         Pred<T> o;
-        predict<T>(xp, vp, f.ax ? ap : nullptr, f.u, f.du, i, (T)dt_inst[k], bx, o);
+        predict<T>(xp, vp, f.ax ? ap : nullptr, f.u, f.du, ic, (T)dt_inst[k], bx, o);
         x = o.x[0]; y = o.x[1]; z = o.x[2];
     } else {
-        x = f.x[i]; y = f.y[i]; z = f.z[i];
+        x = f.x[ic]; y = f.y[ic]; z = f.z[ic];
     }
     keys[i] = morton_key(x, y, z, in);
     vals[i] = (u32)i;
@@ -117,10 +118,11 @@ __global__ void k_gather(FieldPtrs<T> f, i64 n, const InstDev* __restrict__ inst
 {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const i64 j = eps[i];
+    const i64 j0 = eps[i];
+    const int k = find_seg(p_off, ninst, i);     // the sort keeps instances apart
+    const i64 j = j0 + inst[k].shift;
     const T h = f.h[j];
     if (dt_inst) {
-        const int k = find_seg(p_off, ninst, i);
         const Box<T> bx = make_box<T>(inst[k]);
         const T* xp[3] = { f.x, f.y, f.z };
         const T* vp[3] = { f.vx, f.vy, f.vz };
@@ -137,7 +139,7 @@ __global__ void k_gather(FieldPtrs<T> f, i64 n, const InstDev* __restrict__ inst
     }
     s.hn[i] = h;
     s.hcache[i] = h;
-    if (s.pid) s.pid[i] = f.pid ? f.pid[j] : (u32)j;
+    if (s.pid) s.pid[i] = f.pid ? f.pid[j] : (u32)j0;
 }
 
 // ---------------------------------------------------------------------------
@@ -517,10 +519,11 @@ __global__ void k_bbox_reduce(FieldPtrs<T> f, i64 n, const InstDev* __restrict__
                 const T* vp[3] = { f.vx, f.vy, f.vz };
                 const T* ap[3] = { f.ax, f.ay, f.az };
                 Pred<T> o;
-                predict<T>(xp, vp, f.ax ? ap : nullptr, f.u, f.du, i, (T)dt_inst[k], bx, o);
+                predict<T>(xp, vp, f.ax ? ap : nullptr, f.u, f.du, i + in.shift, (T)dt_inst[k], bx, o);
                 p[0] = o.x[0]; p[1] = o.x[1]; p[2] = o.x[2];
             } else {
-                p[0] = f.x[i]; p[1] = f.y[i]; p[2] = f.z[i];
+                const i64 ic = i + in.shift;
+                p[0] = f.x[ic]; p[1] = f.y[ic]; p[2] = f.z[ic];
             }
             for (int d = 0; d < 3; ++d) {
                 const u64 o = ord64(p[d]);
