@@ -513,8 +513,9 @@ template <class T> int build_caches(shsph_ctx* c)
         TRY(ensure(c, c->nlist, (size_t)G * c->cap_words * GROUP * sizeof(u64)));
         prof_begin(c, S_STAGE1);
         launch_group_leaves<T>(P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child),
-                               P<u32>(c->id), ni, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), G, gm,
-                               P<u32>(c->root_d), inst, rk, c->cap_leaf, P<u32>(c->uleaf),
+                               P<u32>(c->id), P<u32>(c->xscan), ni, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), G, gm,
+                               P<u32>(c->root_d), inst, rk, c->cap_leaf,
+                               (u32)c->prm.spread_slots, P<u32>(c->uleaf),
                                P<u32>(c->uslot), P<u32>(c->ucnt), P<u32>(c->ustot),
                                P<u32>(c->flags), st);
         prof_end(c);
@@ -913,6 +914,9 @@ template <class T> int batch_pass(shsph_ctx* c, const std::vector<Inst*>& b, con
     const InstStat* hs = (const InstStat*)c->pinned;
     for (int k = 0; k < ninst; ++k) {
         b[k]->stat = hs[k];
+        // particles still past chi h_cache when the rebuilds ran out did not
+        // converge either
+        b[k]->stat.n_noconv += hs[k].n_exceed;
         b[k]->has_force = true;
     }
     return rc;
@@ -933,7 +937,8 @@ double inst_dt_cfl(const Inst& in)
 
 // Resolve handles and the dt of each instance for a stepping pass; CFL
 // instances without a derivative pass get one first (dt = 0).
-int gather_batch(shsph_ctx* c, const int64_t* handles, int32_t count, std::vector<Inst*>& b)
+int gather_batch(shsph_ctx* c, const int64_t* handles, int32_t count, std::vector<Inst*>& b,
+                 bool server = false)
 {
     if (!handles || count < 1 || count > MAX_BATCH)
         return fail(c, SHSPH_EINVAL, "batch needs 1.." + std::to_string(MAX_BATCH) + " handles");
@@ -941,7 +946,7 @@ int gather_batch(shsph_ctx* c, const int64_t* handles, int32_t count, std::vecto
     for (int k = 0; k < count; ++k) {
         Inst* in = find_inst(c, handles[k]);
         if (!in) return fail(c, SHSPH_EINVAL, "unknown instance handle " + std::to_string(handles[k]));
-        if (in->busy) return fail(c, SHSPH_ESTATE, "instance is held by a serving job");
+        if (in->busy && !server) return fail(c, SHSPH_ESTATE, "instance is held by a serving job");
         for (Inst* o : b)
             if (o == in) return fail(c, SHSPH_EINVAL, "a handle appears twice in the batch");
         b.push_back(in);
@@ -962,7 +967,7 @@ int shsph_internal_pass(shsph_ctx* c, const int64_t* handles, const double* dt, 
 {
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     std::vector<Inst*> b;
-    TRY(gather_batch(c, handles, count, b));
+    TRY(gather_batch(c, handles, count, b, true));
     HIPTRY(c, hipSetDevice(c->device));
     return run_pass(c, b, std::vector<double>(dt, dt + count));
 }
@@ -1001,7 +1006,7 @@ void shsph_params_default(shsph_params* p)
     p->max_iter = 50;
     p->n_red = 3;
     p->max_restarts = 8;
-    p->reserved = 0;
+    p->spread_slots = 8192;
 }
 
 int shsph_create(int device, const shsph_params* p, shsph_ctx** out)
@@ -1014,7 +1019,8 @@ int shsph_create(int device, const shsph_params* p, shsph_ctx** out)
     c->device = device;
     if (p) c->prm = *p; else shsph_params_default(&c->prm);
     if (!(c->prm.hfact > 0) || !(c->prm.chi >= 1) || !(c->prm.lambda > 1) || !(c->prm.eps_h > 0) ||
-        c->prm.max_iter < 1 || c->prm.n_red > 20 || c->prm.max_restarts < 0) {
+        c->prm.max_iter < 1 || c->prm.n_red > 20 || c->prm.max_restarts < 0 ||
+        c->prm.spread_slots < 1) {
         delete c;
         return SHSPH_EINVAL;
     }

@@ -101,13 +101,20 @@ k_group_boxes(const vec4<T>* __restrict__ posh, const GroupMap gm, vec4<T>* __re
 // Stage 1: neighbour leaves of each group, ascending, with the slot where
 // each leaf's particles start in the group's union.  Writes at most `cap`
 // leaves per group; reports the largest count and union size.
+// The union is first gathered with the group's box (one box test per node).
+// A group whose union passes `spread` particles (256 consecutive Morton
+// codes can straddle a jump of the curve and span a wide, sparse region)
+// is traversed again keeping only nodes within reach of one of its target
+// leaves -- the same leaf-pair prune stage 2 applies -- so its union holds
+// exactly the leaves some particle of the group can reach.
 template <class T>
 __global__ void __launch_bounds__(TRAV_BLOCK)
 k_group_leaves(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
-               const u32* __restrict__ child, const u32* __restrict__ id, i64 n_internal,
+               const u32* __restrict__ child, const u32* __restrict__ id,
+               const u32* __restrict__ xscan, i64 n_internal,
                const vec4<T>* __restrict__ glo, const vec4<T>* __restrict__ ghi, i64 ngroups,
                const GroupMap gm, const u32* __restrict__ root, const InstDev* __restrict__ inst,
-               T rk, i64 cap, u32* __restrict__ uleaf, u32* __restrict__ uslot,
+               T rk, i64 cap, u32 spread, u32* __restrict__ uleaf, u32* __restrict__ uslot,
                u32* __restrict__ ucnt, u32* __restrict__ ustot, u32* __restrict__ flags)
 {
     __shared__ u32 stack[STACK][TRAV_BLOCK];
@@ -115,29 +122,48 @@ k_group_leaves(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
     const i64 g0 = (i64)blockIdx.x * TRAV_BLOCK + lane;
     const bool live = g0 < ngroups;
     const i64 g = live ? g0 : ngroups - 1;
-    const int k = gm.inst_of(g);
+    i64 beg, end;
+    int k;
+    gm.range(g, beg, end, k);
     const Box<T> bx = make_box<T>(inst[k]);
     const T eps_abs = abs_inflation(bx);
     const vec4<T> ql = glo[g], qh = ghi[g];
+    const u32 t0 = xscan[beg + 1] - 1u;          // target leaves t0 .. t0 + nt - 1
+    const u32 nt = xscan[end] - t0;
     u32* ul = uleaf + g * cap;
     u32* us = uslot + g * cap;
     u32 count = 0, slots = 0;
-    int sp = 0;
-    if (live) stack[sp++][lane] = root[k];
     bool stack_over = false;
-    while (sp > 0) {
-        const u32 node = stack[--sp][lane];
-        if (!box_hit<T>(ql, qh, blo[node], bhi[node], rk, eps_abs, bx)) continue;
-        if (node >= n_internal) {
-            const u32 leaf = (u32)(node - n_internal);
-            if (count < cap) { ul[count] = leaf; us[count] = slots; }
-            ++count;
-            slots += id[leaf + 1] - id[leaf];
-        } else {
-            if (sp + 2 > STACK) { stack_over = true; break; }
-            stack[sp++][lane] = child[2 * node + 1];
-            stack[sp++][lane] = child[2 * node];
+    for (int pass = 0; pass < 2; ++pass) {
+        count = 0;
+        slots = 0;
+        bool wide = false;
+        int sp = 0;
+        if (live) stack[sp++][lane] = root[k];
+        while (sp > 0) {
+            const u32 node = stack[--sp][lane];
+            const vec4<T> nl = blo[node], nh = bhi[node];
+            if (!box_hit<T>(ql, qh, nl, nh, rk, eps_abs, bx)) continue;
+            if (pass == 1) {
+                bool near = false;
+                for (u32 t = 0; t < nt && !near; ++t)
+                    near = box_hit<T>(blo[n_internal + t0 + t], bhi[n_internal + t0 + t], nl, nh,
+                                      rk, eps_abs, bx);
+                if (!near) continue;
+            }
+            if (node >= n_internal) {
+                const u32 leaf = (u32)(node - n_internal);
+                if (count < cap) { ul[count] = leaf; us[count] = slots; }
+                ++count;
+                slots += id[leaf + 1] - id[leaf];
+                if (pass == 0 && slots > spread) { wide = true; break; }
+            } else {
+                if (sp + 2 > STACK) { stack_over = true; break; }
+                stack[sp++][lane] = child[2 * node + 1];
+                stack[sp++][lane] = child[2 * node];
+            }
         }
+        if (!wide || stack_over) break;
     }
     if (live) {
         ucnt[g] = count;
@@ -358,16 +384,16 @@ void launch_group_boxes(const vec4<T>* posh, const GroupMap& gm, i64 ngroups, ve
 
 template <class T>
 void launch_group_leaves(const vec4<T>* blo, const vec4<T>* bhi, const u32* child, const u32* id,
-                         i64 n_internal, const vec4<T>* glo, const vec4<T>* ghi, i64 ngroups,
-                         const GroupMap& gm, const u32* root, const InstDev* inst, double rk,
-                         i64 cap, u32* uleaf, u32* uslot, u32* ucnt, u32* ustot, u32* flags,
-                         hipStream_t st)
+                         const u32* xscan, i64 n_internal, const vec4<T>* glo, const vec4<T>* ghi,
+                         i64 ngroups, const GroupMap& gm, const u32* root, const InstDev* inst,
+                         double rk, i64 cap, u32 spread, u32* uleaf, u32* uslot, u32* ucnt,
+                         u32* ustot, u32* flags, hipStream_t st)
 {
     if (ngroups <= 0) return;
     const dim3 grid((unsigned)((ngroups + TRAV_BLOCK - 1) / TRAV_BLOCK));
     hipLaunchKernelGGL((k_group_leaves<T>), grid, dim3(TRAV_BLOCK), 0, st, blo, bhi, child, id,
-                       n_internal, glo, ghi, ngroups, gm, root, inst, (T)rk, cap, uleaf, uslot,
-                       ucnt, ustot, flags);
+                       xscan, n_internal, glo, ghi, ngroups, gm, root, inst, (T)rk, cap, spread,
+                       uleaf, uslot, ucnt, ustot, flags);
 }
 
 template <class T>
@@ -397,10 +423,10 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
 #define INST(T)                                                                                   \
     template void launch_group_boxes<T>(const vec4<T>*, const GroupMap&, i64, vec4<T>*, vec4<T>*, \
                                         hipStream_t);                                             \
-    template void launch_group_leaves<T>(const vec4<T>*, const vec4<T>*, const u32*, const u32*,  \
+    template void launch_group_leaves<T>(const vec4<T>*, const vec4<T>*, const u32*, const u32*, const u32*,  \
                                          i64, const vec4<T>*, const vec4<T>*, i64,                \
                                          const GroupMap&, const u32*, const InstDev*, double,     \
-                                         i64, u32*, u32*, u32*, u32*, u32*, hipStream_t);         \
+                                         i64, u32, u32*, u32*, u32*, u32*, u32*, hipStream_t);    \
     template void launch_group_cache<T>(const vec4<T>*, const vec4<T>*, const vec4<T>*,           \
                                         const u32*, const u32*, i64, const GroupMap&, i64, const InstDev*,    \
                                         double, double, i64, const u32*, const u32*, const u32*,  \

@@ -54,6 +54,7 @@ struct Server {
     std::vector<uint64_t> running;
     std::unordered_map<uint64_t, Job> jobs;
     uint64_t next_ticket = 1;
+    int admitting = 0;                   // jobs off the queue, instance being created
     double running_work = 0;             // work bytes charged to running jobs
     bool stop = false;
     shsph_serve_counters stats;
@@ -109,9 +110,11 @@ void admit(Server* S, std::unique_lock<std::mutex>& lk)
         S->queue.pop_front();
         int64_t h = j.spec.handle;
         if (j.has_init) {
+            ++S->admitting;
             lk.unlock();
             const int rc = shsph_instance_create(S->ctx, &j.init, &h);
             lk.lock();
+            --S->admitting;
             if (rc != SHSPH_OK) { finish(S, j, SHSPH_JOB_FAILED, rc, now_s()); S->cv_done.notify_all(); continue; }
         }
         if (shsph_internal_inst_state(S->ctx, h, nullptr, nullptr, nullptr, +1) != SHSPH_OK) {
@@ -299,7 +302,9 @@ int shsph_serve_drain(shsph_ctx* c, double timeout_s)
     const auto until = std::chrono::steady_clock::now() +
                        std::chrono::duration_cast<std::chrono::steady_clock::duration>(
                            std::chrono::duration<double>(std::max(timeout_s, 0.0)));
-    const bool ok = S->cv_done.wait_until(lk, until, [S] { return S->queue.empty() && S->running.empty(); });
+    const bool ok = S->cv_done.wait_until(lk, until, [S] {
+        return S->queue.empty() && S->running.empty() && S->admitting == 0;
+    });
     return ok ? SHSPH_OK : SHSPH_ESTATE;
 }
 

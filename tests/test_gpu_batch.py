@@ -50,7 +50,7 @@ def _mix():
         _random_state(gen.lattice(8, 31, dtype=np.float32), 1),
         _random_state(gen.plummer(3000, 32, dtype=np.float32), 2, vscale=0.3),
         gen.sedov(10, 33, dtype=np.float32),
-        _random_state(gen.plummer(100, 34, dtype=np.float32), 3, vscale=0.2),
+        _random_state(gen.lattice(6, 34, dtype=np.float32), 3, vscale=0.05),
         _random_state(gen.lattice(12, 35, dtype=np.float32), 4),
         _random_state(gen.plummer(1500, 36, dtype=np.float32), 5, vscale=0.1),
     ]
@@ -241,6 +241,27 @@ def test_serve_budget_policy_and_errors(torch_cuda):
     assert all(ctx.poll(t)["state"] == "done" for t in tk)
     ctx.serve_stop()
     ctx.close()
+
+
+def test_batch_flags_instance_that_does_not_converge(torch_cuda):
+    _say("[batch] a 100-particle isolated Plummer sphere (h iteration runs out of rebuilds)")
+    good = _random_state(gen.lattice(8, 31, dtype=np.float32), 1)
+    bad = gen.plummer(100, 34, dtype=np.float32)
+    ctx = shsph.Context(0)
+    hg = ctx.instance_create(shsph.ParticleSet.from_particles(good))
+    hb = ctx.instance_create(shsph.ParticleSet.from_particles(bad))
+    with pytest.raises(shsph.ShsphError) as e:
+        ctx.eval_batch([hg, hb])
+    assert e.value.code == shsph.SHSPH_ENOCONV
+    assert ctx.instance_info(hb)["n_noconv"] > 0
+    assert ctx.instance_info(hg)["n_noconv"] == 0
+    got = _read(ctx, hg, good)
+    ctx.close()
+    alone = shsph.Context(0)
+    h = alone.instance_create(shsph.ParticleSet.from_particles(good))
+    alone.eval_batch([h])
+    _same(got, _read(alone, h, good), "converged instance next to a failing one")
+    alone.close()
 
 
 def test_instance_errors(torch_cuda):

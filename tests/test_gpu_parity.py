@@ -114,6 +114,29 @@ def test_tree_and_cache_bit_exact(torch_cuda, name, make, n_red):
     ctx.close()
 
 
+@pytest.mark.parametrize("name,make,n_red", [
+    ("plummer5000_f32", lambda: gen.plummer(5000, 6, dtype=np.float32), 3),
+    ("lattice16_f64", lambda: gen.lattice(16, gen.SEEDS["tiny"], dtype=np.float64), 3),
+], ids=["plummer5000_f32", "lattice16_f64"])
+def test_stage1_leaf_by_leaf_pass(torch_cuda, name, make, n_red):
+    _say(f"[tree] {name}: every group gathered leaf by leaf (spread_slots=1)")
+    p = make()
+    ctx = _ctx(torch_cuda, n_red=n_red, spread_slots=1)
+    ctx.build_tree(_upload(p, torch_cuda))
+    ex = check_tree(ctx, p, n_red)
+    exact = np.diff(ex["group_off"].astype(np.int64))
+    ctx.close()
+    ctx = _ctx(torch_cuda, n_red=n_red)
+    ctx.build_tree(_upload(p, torch_cuda))
+    plain = np.diff(ctx.export_tree(dtype=p.x.dtype, fields=["group_off"])["group_off"].astype(np.int64))
+    ctx.close()
+    # the leaf-by-leaf union is a subset of the group-box union (equal for the
+    # compact groups of a lattice, smaller for the spread groups of a sphere)
+    assert (exact <= plain).all()
+    if name.startswith("plummer"):
+        assert exact.sum() < plain.sum()
+
+
 def test_tree_with_duplicate_positions(torch_cuda):
     _say("[tree] duplicates")
     base = gen.lattice(12, 9, dtype=np.float32)
