@@ -137,7 +137,12 @@ __device__ inline void atomic_min_if(u32* p, u32 v)
 // ---------------------------------------------------------------------------
 // h iteration (App. G, Alg. 7), per particle, over the cached neighbours:
 //   rho_sum = sum_b m W(r_ab, h),   W = f(r/h)/(pi h^3)
-//   drho = rho_sum - m (hfact/h)^3,  d(drho)/dh = sum_b m dW/dh + 3 rho(h)/h
+//   drho = rho_sum - m (hfact/h)^3,  d(drho)/dh = sum_b m dW/dh + 3 rho_sum/h
+//   (the derivative term as Alg. 7 prints it, with the SPH sum: it equals the
+//   exact derivative at the root, and since every M4 term has
+//   dW/dh >= -3 W / h it never goes negative, so the step always points
+//   towards smaller |drho|; only the particle itself within 2h gives 0,
+//   and then the step is the clamp in the direction that lowers |drho|);
 //   Newton step, clamped to [h/lambda, h lambda]; eps = |h' - h| / h^n.
 // The particle stops when eps < eps_h.  If h' exceeds chi times the h the
 // cache was built with, h' is clamped there and the particle is flagged: the
@@ -193,7 +198,7 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
     for (int it = 0; it < P.max_iter; ++it) {
         const T hinv = T(1) / h;
         const T h2x4 = T(4) * h * h;
-        T s = T(0), ds = T(0);
+        T s = T(0), dq = T(0);          // sum f, sum -q f' (>= 0: f is non-increasing)
         auto add_r2 = [&](T r2) {
             ++evals;
             if (r2 < h2x4) {
@@ -202,7 +207,7 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
                 T f, df;
                 m4<T>(q, f, df);
                 s += f;
-                ds -= T(3) * f + q * df;
+                dq -= q * df;
             }
         };
         auto add = [&](u32 sl) {          // any group: minimum image
@@ -239,11 +244,13 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
         if (active) {
             const T hinv3 = hinv * hinv * hinv;
             const T rho_sum = m * s * hinv3 * inv_pi<T>();
-            const T dsum_h = m * ds * hinv3 * hinv * inv_pi<T>();
+            const T mh4 = m * hinv3 * hinv * inv_pi<T>();
+            const T dsum_h = mh4 * (dq - T(3) * s);      // sum_b m dW/dh
             const T hf = hfact * hinv;
             const T rho_h = m * hf * hf * hf;
-            const T ddrho = dsum_h + T(3) * rho_h * hinv;
-            T hnew = h - (rho_sum - rho_h) / ddrho;
+            const T ddrho = mh4 * dq;                     // = dsum_h + 3 rho_sum / h
+            const T drho = rho_sum - rho_h;
+            T hnew = ddrho > T(0) ? h - drho / ddrho : (drho < T(0) ? h * lam : h / lam);
             if (hnew > h * lam) hnew = h * lam;
             else if (hnew < h / lam) hnew = h / lam;
             const T eps = fabs(hnew - h) / h_n;
