@@ -224,7 +224,10 @@ def run_served(args, shsph, torch, capacity):
         log(f"[served] {name}: {len(jobs)} jobs at {rate:.1f}/s")
         tk = []
         t0 = time.perf_counter()
-        for j in jobs:
+        for i, j in enumerate(jobs):
+            if i and i % 250 == 0:
+                st = ctx.serve_stats()
+                log(f"[served] {name}: {i} submitted, {st['jobs_done']} done, {st['passes']} passes")
             due = t0 + j["t"] / rate
             while True:
                 d = due - time.perf_counter()
@@ -234,7 +237,12 @@ def run_served(args, shsph, torch, capacity):
             kind = shsph.JOB_EVAL if j["kind"] == "eval" else shsph.JOB_STEP
             tk.append(ctx.submit(init=sets[j["family"]][j["tpl"]], kind=kind, nsteps=j["nsteps"],
                                  release=True))
-        ctx.serve_drain(1800.0)
+        t_end = time.perf_counter() + args.serve_timeout
+        while not ctx.serve_wait(5.0):
+            st = ctx.serve_stats()
+            log(f"[served] {name}: draining, {st['jobs_done']} of {len(jobs)} done")
+            if time.perf_counter() > t_end:
+                raise RuntimeError(f"serving run ({name}) did not finish in {args.serve_timeout} s")
         st = [ctx.poll(t) for t in tk]
         stats = ctx.serve_stats()
         ctx.serve_stop()
@@ -271,6 +279,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--serve-jobs", type=int, default=2000)
+    ap.add_argument("--serve-timeout", type=float, default=300.0,
+                    help="give up a serving run that has not drained after this many seconds")
     ap.add_argument("--serve-load", type=float, default=0.75,
                     help="offered load as a fraction of the measured batched throughput")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

@@ -399,6 +399,15 @@ class Context:
         self._check(self.L.shsph_serve_drain(self.h, float(timeout_s)))
         getattr(self, "_keep", {}).clear()
 
+    def serve_wait(self, timeout_s: float) -> bool:
+        """True when no job is pending or running (waits at most timeout_s)."""
+        rc = self.L.shsph_serve_drain(self.h, float(timeout_s))
+        if rc == SHSPH_ESTATE:
+            return False
+        self._check(rc)
+        getattr(self, "_keep", {}).clear()
+        return True
+
     def serve_stats(self) -> dict:
         o = ServeCounters()
         self._check(self.L.shsph_serve_stats(self.h, C.byref(o)))

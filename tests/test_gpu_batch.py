@@ -244,10 +244,11 @@ def test_serve_budget_policy_and_errors(torch_cuda):
 
 
 def test_batch_flags_instance_that_does_not_converge(torch_cuda):
-    _say("[batch] a 100-particle isolated Plummer sphere (h iteration runs out of rebuilds)")
+    _say("[batch] no cache rebuilds allowed; one instance starts with h at half its root")
     good = _random_state(gen.lattice(8, 31, dtype=np.float32), 1)
-    bad = gen.plummer(100, 34, dtype=np.float32)
-    ctx = shsph.Context(0)
+    bad = gen.plummer(3000, 34, dtype=np.float32)
+    bad.h = (bad.h * 0.5).astype(np.float32)       # must grow past chi h_cache
+    ctx = shsph.Context(0, max_restarts=0)
     hg = ctx.instance_create(shsph.ParticleSet.from_particles(good))
     hb = ctx.instance_create(shsph.ParticleSet.from_particles(bad))
     with pytest.raises(shsph.ShsphError) as e:
@@ -257,7 +258,7 @@ def test_batch_flags_instance_that_does_not_converge(torch_cuda):
     assert ctx.instance_info(hg)["n_noconv"] == 0
     got = _read(ctx, hg, good)
     ctx.close()
-    alone = shsph.Context(0)
+    alone = shsph.Context(0, max_restarts=0)
     h = alone.instance_create(shsph.ParticleSet.from_particles(good))
     alone.eval_batch([h])
     _same(got, _read(alone, h, good), "converged instance next to a failing one")

@@ -184,6 +184,22 @@ def test_density_plummer_with_cache_rebuilds(torch_cuda):
     ctx.close()
 
 
+def test_density_clustered_plummer_core(torch_cuda):
+    _say("[density] plummer 40000 (random cores: sums dominated by close neighbours)")
+    p = gen.plummer(40000, 4001, dtype=np.float32)
+    ctx = _ctx(torch_cuda)
+    ps = _upload(p, torch_cuda)
+    ctx.build_tree(ps)
+    ctx.density(ps)                       # converges: no ENOCONV
+    assert ctx.get_info()["restarts"] <= 4
+    g = ps.host("h")
+    h, _, _, fl = oracle.density(p.x, p.y, p.z, p.h, *_box_for_oracle(p), False, p.mass)
+    ok = fl == 0
+    assert ok.mean() > 0.99
+    assert np.abs(g["h"][ok] / h[ok] - 1).max() <= 1e-5
+    ctx.close()
+
+
 def _random_state(p, seed, vscale=0.1, uvar=0.3):
     rng = np.random.default_rng(seed)
     T = p.x.dtype
