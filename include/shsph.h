@@ -65,10 +65,13 @@ typedef struct {
     int32_t max_iter;
     int32_t n_red;
     int32_t max_restarts;   /* cache rebuilds allowed when h exceeds chi h (default 8) */
-    int32_t spread_slots;   /* a group (256 consecutive Morton slots) whose candidate
-                               union, gathered with the group's box, passes this many
-                               particles is gathered again leaf by leaf (default 8192;
-                               1 = always leaf by leaf).  Changes work, not results. */
+    int32_t spread_slots;   /* serial stage-1 walk only: a group whose union, gathered
+                               with the group's box, passes this many particles is
+                               gathered again leaf by leaf (default 8192; 1 = always) */
+    int32_t stage1_serial;  /* 1: stage 1 by the serial per-group walk for every group
+                               (default 0: one wave per group, serial walk only for
+                               groups that outgrow its buffers).  Work, not results. */
+    int32_t reserved;
 } shsph_params;
 
 /* One SPH instance.  x..h are read; h, rho, omega, ax..dudt are written as

@@ -515,7 +515,8 @@ template <class T> int build_caches(shsph_ctx* c)
         launch_group_leaves<T>(P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child),
                                P<u32>(c->id), P<u32>(c->xscan), ni, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), G, gm,
                                P<u32>(c->root_d), inst, rk, c->cap_leaf,
-                               (u32)c->prm.spread_slots, P<u32>(c->uleaf),
+                               (u32)c->prm.spread_slots, c->prm.stage1_serial != 0,
+                               P<u32>(c->uleaf),
                                P<u32>(c->uslot), P<u32>(c->ucnt), P<u32>(c->ustot),
                                P<u32>(c->flags), st);
         prof_end(c);
@@ -1007,6 +1008,8 @@ void shsph_params_default(shsph_params* p)
     p->n_red = 3;
     p->max_restarts = 8;
     p->spread_slots = 8192;
+    p->stage1_serial = 0;
+    p->reserved = 0;
 }
 
 int shsph_create(int device, const shsph_params* p, shsph_ctx** out)

@@ -117,8 +117,8 @@ void launch_group_leaves(const vec4<T>* blo, const vec4<T>* bhi, const u32* chil
                          const u32* xscan, i64 n_internal, const vec4<T>* glo, const vec4<T>* ghi,
                          i64 ngroups,
                          const GroupMap& gm, const u32* root, const InstDev* inst, double rk,
-                         i64 cap, u32 spread, u32* uleaf, u32* uslot, u32* ucnt, u32* ustot,
-                         u32* flags, hipStream_t st);
+                         i64 cap, u32 spread, bool serial, u32* uleaf, u32* uslot, u32* ucnt,
+                         u32* ustot, u32* flags, hipStream_t st);
 template <class T>
 void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* bhi, const u32* id,
                         const u32* xscan, i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,

@@ -1,14 +1,14 @@
 // Two-stage neighbour cache (App. E.3-E.4, Alg. 4-6), laid out for gfx950.
 //
 // Particles are taken in groups of GROUP = 256 consecutive key-order slots
-// (one workgroup).  Stage 1 runs once per group: one thread walks the tree
-// with a 64-entry stack in LDS (Alg. 4) and keeps the leaves that pass the
-// group-group criterion of App. F,
-//     box_G  n  [box_C (+) R chi max(hmax_G, hmax_C)]  !=  0,
-// with periodic images and a slight outward inflation so that the prune is a
-// superset of the exact particle test.  Children are pushed right then left,
-// so the kept leaves come out in ascending order; their particles, in that
-// order, form the group's candidate "union", numbered by 16-bit slots.
+// (one workgroup).  Stage 1 runs once per group (Alg. 4 walked for all the
+// group's leaves at once): one wave walks the tree level by level and keeps
+// the leaves that pass the group-group criterion of App. F,
+//     box_A  n  [box_C (+) R chi max(hmax_A, hmax_C)]  !=  0,
+// for some target leaf A of the group, with periodic images and a slight
+// outward inflation so that the prune is a superset of the exact particle
+// test.  The kept leaves, in ascending order, form the group's candidate
+// "union"; their particles are numbered by 16-bit slots.
 // Stage 2 runs one workgroup per group: each particle prefilters the union's
 // leaves by box and tests their particles with the exact object-object
 // criterion in the storage type, writing the accepted slots (ascending)
@@ -107,9 +107,11 @@ k_group_boxes(const vec4<T>* __restrict__ posh, const GroupMap gm, vec4<T>* __re
 // is traversed again keeping only nodes within reach of one of its target
 // leaves -- the same leaf-pair prune stage 2 applies -- so its union holds
 // exactly the leaves some particle of the group can reach.
+constexpr u32 S1_SERIAL = 0xffffffffu;   // ucnt marker: group left to the serial walk
+
 template <class T>
 __global__ void __launch_bounds__(TRAV_BLOCK)
-k_group_leaves(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
+k_group_leaves_serial(bool only_marked, const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
                const u32* __restrict__ child, const u32* __restrict__ id,
                const u32* __restrict__ xscan, i64 n_internal,
                const vec4<T>* __restrict__ glo, const vec4<T>* __restrict__ ghi, i64 ngroups,
@@ -120,8 +122,9 @@ k_group_leaves(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
     __shared__ u32 stack[STACK][TRAV_BLOCK];
     const int lane = threadIdx.x;
     const i64 g0 = (i64)blockIdx.x * TRAV_BLOCK + lane;
-    const bool live = g0 < ngroups;
-    const i64 g = live ? g0 : ngroups - 1;
+    const i64 g = g0 < ngroups ? g0 : ngroups - 1;
+    const bool live = g0 < ngroups && (!only_marked || ucnt[g] == S1_SERIAL);
+    if (only_marked && __ballot(live) == 0) return;
     i64 beg, end;
     int k;
     gm.range(g, beg, end, k);
@@ -177,6 +180,163 @@ k_group_leaves(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
     const u32 wmax = wave_max(count);
     if (__lane_id() == 0 && wmax > __hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         atomicMax(&flags[1], wmax);
+}
+
+// Stage 1, one wave per group.  A stack in LDS holds the pending nodes in
+// left-to-right order (the top is the leftmost) and each iteration the 64
+// lanes take the 64 leftmost.  A node is kept when it passes the group's box
+// and, more tightly, the box of at least one of the group's target leaves;
+// each entry carries the set of targets that reached its parent, so a node
+// is tested only against those (as a mask over S1_TS runs of consecutive
+// targets: a run's bit stays set while any of its targets reaches the node;
+// every target is still tested on its own, so the prune is exact).  A kept leaf is written out at once when no
+// kept internal node lies to its left in the batch, otherwise it goes back on
+// the stack marked final; kept internal nodes go back as their two children.
+// Everything pushed back keeps the order, so the union comes out ascending
+// with its slot starts (a running wave scan of the leaf sizes).  The union is
+// the set of leaves within reach of some target leaf: the same leaf-pair
+// prune stage 2 applies.  A group whose stack outgrows the LDS buffer is
+// marked and left to the serial walk.
+constexpr int S1_WAVES = 2;
+constexpr int S1_SMAX = 1536;
+constexpr int S1_TS = 32;               // target runs (mask bits)
+constexpr u32 S1_FINAL = 0x80000000u;      // stack entry: an accepted leaf
+
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <class T>
+__global__ void __launch_bounds__(S1_WAVES * WAVE)
+k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
+                    const u32* __restrict__ child, const u32* __restrict__ id,
+                    const u32* __restrict__ xscan, i64 n_internal,
+                    const vec4<T>* __restrict__ glo, const vec4<T>* __restrict__ ghi, i64 ngroups,
+                    const GroupMap gm, const u32* __restrict__ root,
+                    const InstDev* __restrict__ inst, T rk, i64 cap, u32* __restrict__ uleaf,
+                    u32* __restrict__ uslot, u32* __restrict__ ucnt, u32* __restrict__ ustot,
+                    u32* __restrict__ flags)
+{
+    __shared__ u32 s_sn[S1_WAVES][S1_SMAX];
+    __shared__ u32 s_sm[S1_WAVES][S1_SMAX];
+    __shared__ vec4<T> s_tl[S1_WAVES][GROUP];      // target leaf boxes (at most one per particle)
+    __shared__ vec4<T> s_th[S1_WAVES][GROUP];
+    const int w = threadIdx.x / WAVE;
+    const u32 lane = (u32)__lane_id();
+    const i64 g = (i64)blockIdx.x * S1_WAVES + w;
+    if (g >= ngroups) return;                 // per wave; no workgroup barrier below
+    i64 beg, end;
+    int k;
+    gm.range(g, beg, end, k);
+    const Box<T> bx = make_box<T>(inst[k]);
+    const T eps_abs = abs_inflation(bx);
+    const vec4<T> ql = glo[g], qh = ghi[g];
+    const u32 t0 = xscan[beg + 1] - 1u;       // target leaves t0 .. t0 + nt - 1
+    const u32 nt = xscan[end] - t0;
+    const u32 ns = nt < (u32)S1_TS ? nt : (u32)S1_TS;     // runs; run r = targets
+    const u32 rl = (nt + ns - 1u) / ns;                     // [r rl, min(nt, r rl + rl))
+    for (u32 a = lane; a < nt; a += WAVE) {
+        s_tl[w][a] = blo[n_internal + t0 + a];
+        s_th[w][a] = bhi[n_internal + t0 + a];
+    }
+    if (lane == 0) {
+        s_sn[w][0] = root[k];
+        s_sm[w][0] = ns == 32u ? 0xffffffffu : ((1u << ns) - 1u);
+    }
+    wave_lds_sync();
+    u32* ul = uleaf + g * cap;
+    u32* us = uslot + g * cap;
+    u32 sp = 1, count = 0, slots = 0;
+    bool over = false;
+    while (sp > 0) {
+        const u32 take_n = sp < (u32)WAVE ? sp : (u32)WAVE;
+        const u32 base = sp - take_n;
+        u32 e = 0, m = 0;
+        if (lane < take_n) {                  // lane 0 takes the top (leftmost)
+            e = s_sn[w][sp - 1u - lane];
+            m = s_sm[w][sp - 1u - lane];
+        }
+        wave_lds_sync();                       // popped before anything is pushed over them
+        const u32 v = e & ~S1_FINAL;
+        bool keep = false, leaf = false;
+        u32 cm = 0;
+        if (lane < take_n) {
+            if (e & S1_FINAL) {
+                keep = true;
+                leaf = true;
+            } else {
+                const vec4<T> nl = blo[v], nh = bhi[v];
+                if (box_hit<T>(ql, qh, nl, nh, rk, eps_abs, bx)) {
+                    while (m) {
+                        const u32 r = (u32)(__ffs(m) - 1);
+                        m &= m - 1u;
+                        const u32 a1 = min(nt, r * rl + rl);
+                        for (u32 a = r * rl; a < a1; ++a)
+                            if (box_hit<T>(s_tl[w][a], s_th[w][a], nl, nh, rk, eps_abs, bx)) {
+                                cm |= 1u << r;
+                                break;
+                            }
+                    }
+                    keep = cm != 0u;
+                    leaf = v >= (u32)n_internal;
+                }
+            }
+        }
+        // leaves left of the first kept internal node are final in order
+        const u64 bint = __ballot(keep && !leaf);
+        const u32 first_int = bint ? (u32)(__ffsll((unsigned long long)bint) - 1) : (u32)WAVE;
+        const bool emit = keep && leaf && lane < first_int;
+        const bool defer = keep && leaf && lane > first_int;
+        const u32 nres = (keep && !leaf) ? 2u : (defer ? 1u : 0u);
+        const u32 rincl = wave_incl_scan(nres);
+        const u32 rtot = __shfl(rincl, WAVE - 1, WAVE);
+        if (base + rtot > (u32)S1_SMAX) { over = true; break; }
+        // emitted leaves: ascending, with their slot starts
+        const u64 bem = __ballot(emit);
+        const u32 sz = emit ? id[v - (u32)n_internal + 1] - id[v - (u32)n_internal] : 0u;
+        const u32 sincl = wave_incl_scan(sz);
+        if (emit) {
+            const u32 q = count + (u32)__popcll(bem & lanemask_lt());
+            if ((i64)q < cap) {
+                ul[q] = v - (u32)n_internal;
+                us[q] = slots + sincl - sz;
+            }
+        }
+        count += (u32)__popcll(bem);
+        slots += __shfl(sincl, WAVE - 1, WAVE);
+        // push back: result r (0 = leftmost) goes to base + rtot - 1 - r
+        const u32 r0 = rincl - nres;
+        if (keep && !leaf) {
+            s_sn[w][base + rtot - 1u - r0] = child[2 * (u64)v];
+            s_sn[w][base + rtot - 2u - r0] = child[2 * (u64)v + 1];
+            s_sm[w][base + rtot - 1u - r0] = cm;
+            s_sm[w][base + rtot - 2u - r0] = cm;
+        } else if (defer) {
+            s_sn[w][base + rtot - 1u - r0] = v | S1_FINAL;
+            s_sm[w][base + rtot - 1u - r0] = 0u;
+        }
+        sp = base + rtot;
+        wave_lds_sync();
+    }
+    if (over) {
+        if (lane == 0) {
+            ucnt[g] = S1_SERIAL;
+            ustot[g] = 0;
+        }
+        return;
+    }
+    if (lane == 0) {
+        ucnt[g] = count;
+        ustot[g] = slots;
+        u32 f = 0;
+        if ((i64)count > cap) f |= 2u;
+        if (slots > 0xffffu) f |= 8u;
+        if (f) atomicOr(&flags[0], f);
+        if (count > __hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&flags[1], count);
+    }
 }
 
 // Stage 2: per particle, its neighbours among the group's union (Alg. 5 with
@@ -386,14 +546,21 @@ template <class T>
 void launch_group_leaves(const vec4<T>* blo, const vec4<T>* bhi, const u32* child, const u32* id,
                          const u32* xscan, i64 n_internal, const vec4<T>* glo, const vec4<T>* ghi,
                          i64 ngroups, const GroupMap& gm, const u32* root, const InstDev* inst,
-                         double rk, i64 cap, u32 spread, u32* uleaf, u32* uslot, u32* ucnt,
-                         u32* ustot, u32* flags, hipStream_t st)
+                         double rk, i64 cap, u32 spread, bool serial, u32* uleaf, u32* uslot,
+                         u32* ucnt, u32* ustot, u32* flags, hipStream_t st)
 {
     if (ngroups <= 0) return;
+    if (!serial) {
+        const dim3 gw((unsigned)((ngroups + S1_WAVES - 1) / S1_WAVES));
+        hipLaunchKernelGGL((k_group_leaves_wave<T>), gw, dim3(S1_WAVES * WAVE), 0, st, blo, bhi,
+                           child, id, xscan, n_internal, glo, ghi, ngroups, gm, root, inst, (T)rk,
+                           cap, uleaf, uslot, ucnt, ustot, flags);
+    }
+    // the serial walk takes every group (serial) or the marked ones
     const dim3 grid((unsigned)((ngroups + TRAV_BLOCK - 1) / TRAV_BLOCK));
-    hipLaunchKernelGGL((k_group_leaves<T>), grid, dim3(TRAV_BLOCK), 0, st, blo, bhi, child, id,
-                       xscan, n_internal, glo, ghi, ngroups, gm, root, inst, (T)rk, cap, spread,
-                       uleaf, uslot, ucnt, ustot, flags);
+    hipLaunchKernelGGL((k_group_leaves_serial<T>), grid, dim3(TRAV_BLOCK), 0, st, !serial, blo,
+                       bhi, child, id, xscan, n_internal, glo, ghi, ngroups, gm, root, inst, (T)rk,
+                       cap, spread, uleaf, uslot, ucnt, ustot, flags);
 }
 
 template <class T>
@@ -426,7 +593,8 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
     template void launch_group_leaves<T>(const vec4<T>*, const vec4<T>*, const u32*, const u32*, const u32*,  \
                                          i64, const vec4<T>*, const vec4<T>*, i64,                \
                                          const GroupMap&, const u32*, const InstDev*, double,     \
-                                         i64, u32, u32*, u32*, u32*, u32*, u32*, hipStream_t);    \
+                                         i64, u32, bool, u32*, u32*, u32*, u32*, u32*,            \
+                                         hipStream_t);                                            \
     template void launch_group_cache<T>(const vec4<T>*, const vec4<T>*, const vec4<T>*,           \
                                         const u32*, const u32*, i64, const GroupMap&, i64, const InstDev*,    \
                                         double, double, i64, const u32*, const u32*, const u32*,  \

@@ -117,24 +117,25 @@ def test_tree_and_cache_bit_exact(torch_cuda, name, make, n_red):
 @pytest.mark.parametrize("name,make,n_red", [
     ("plummer5000_f32", lambda: gen.plummer(5000, 6, dtype=np.float32), 3),
     ("lattice16_f64", lambda: gen.lattice(16, gen.SEEDS["tiny"], dtype=np.float64), 3),
-], ids=["plummer5000_f32", "lattice16_f64"])
-def test_stage1_leaf_by_leaf_pass(torch_cuda, name, make, n_red):
-    _say(f"[tree] {name}: every group gathered leaf by leaf (spread_slots=1)")
+    ("lattice21_f32_nred0", lambda: gen.lattice(21, 5, dtype=np.float32), 0),
+], ids=["plummer5000_f32", "lattice16_f64", "lattice21_f32_nred0"])
+def test_stage1_paths(torch_cuda, name, make, n_red):
+    """Stage 1 by the wave walk (default), and by the serial walk gathering
+    with the group's box or leaf by leaf: identical neighbour sets, and
+    unions nested leaf-by-leaf <= wave (targets merged beyond 32) <= box."""
+    _say(f"[tree] {name}: stage-1 paths")
     p = make()
-    ctx = _ctx(torch_cuda, n_red=n_red, spread_slots=1)
-    ctx.build_tree(_upload(p, torch_cuda))
-    ex = check_tree(ctx, p, n_red)
-    exact = np.diff(ex["group_off"].astype(np.int64))
-    ctx.close()
-    ctx = _ctx(torch_cuda, n_red=n_red)
-    ctx.build_tree(_upload(p, torch_cuda))
-    plain = np.diff(ctx.export_tree(dtype=p.x.dtype, fields=["group_off"])["group_off"].astype(np.int64))
-    ctx.close()
-    # the leaf-by-leaf union is a subset of the group-box union (equal for the
-    # compact groups of a lattice, smaller for the spread groups of a sphere)
-    assert (exact <= plain).all()
+    unions = {}
+    for mode, kw in (("wave", {}), ("box", dict(stage1_serial=1)),
+                     ("leaf", dict(stage1_serial=1, spread_slots=1))):
+        ctx = _ctx(torch_cuda, n_red=n_red, **kw)
+        ctx.build_tree(_upload(p, torch_cuda))
+        ex = check_tree(ctx, p, n_red)
+        unions[mode] = np.diff(ex["group_off"].astype(np.int64))
+        ctx.close()
+    assert (unions["leaf"] <= unions["wave"]).all() and (unions["wave"] <= unions["box"]).all()
     if name.startswith("plummer"):
-        assert exact.sum() < plain.sum()
+        assert unions["wave"].sum() < unions["box"].sum()
 
 
 def test_tree_with_duplicate_positions(torch_cuda):
