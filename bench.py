@@ -216,11 +216,13 @@ def run_served(args, shsph, torch, capacity):
     rate = args.serve_load * capacity / work.mean()
     res = {"workload": "served", "jobs": len(jobs), "rate_jobs_per_s": rate,
            "offered_load_of_batched_capacity": args.serve_load, "budget_GB": 200,
+           "pass_particles_max": args.serve_pass_particles,
            "templates": 32, "eval_fraction": float(np.mean([j["kind"] == "eval" for j in jobs]))}
     for name, policy in (("continuous", shsph.SERVE_CONTINUOUS),
                          ("one_at_a_time", shsph.SERVE_ONE_AT_A_TIME)):
         ctx = shsph.Context(0, n_red=args.n_red)
-        ctx.serve_start(200e9, max_batch=256, policy=policy)
+        ctx.serve_start(200e9, max_batch=256, policy=policy,
+                        max_batch_particles=args.serve_pass_particles)
         log(f"[served] {name}: {len(jobs)} jobs at {rate:.1f}/s")
         tk = []
         t0 = time.perf_counter()
@@ -247,6 +249,12 @@ def run_served(args, shsph, torch, capacity):
         stats = ctx.serve_stats()
         ctx.serve_stop()
         ctx.close()
+        errs = {}
+        for s in st:
+            if s["state"] != "done":
+                errs[str(s["error"])] = errs.get(str(s["error"]), 0) + 1
+        if errs:
+            log(f"[served] {name}: failed jobs by error code {errs}")
         lat = np.array([s["t_done"] - s["t_submit"] for s in st])
         done = sum(s["state"] == "done" for s in st)
         span = max(s["t_done"] for s in st) - min(s["t_submit"] for s in st)
@@ -255,6 +263,7 @@ def run_served(args, shsph, torch, capacity):
                      "p99_ms": 1e3 * float(np.percentile(lat, 99)),
                      "mean_ms": 1e3 * float(lat.mean()), "jobs_done": int(done),
                      "throughput_particle_steps_per_s": steps / span, "makespan_s": span,
+                     "failed_by_error": errs,
                      "passes": stats["passes"], "peak_jobs_per_pass": stats["peak_jobs"],
                      "peak_GB": stats["peak_bytes"] / 1e9}
         log(f"[served] {name}: p50 {res[name]['p50_ms']:.1f} ms, p99 {res[name]['p99_ms']:.1f} ms")
@@ -279,6 +288,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--serve-jobs", type=int, default=2000)
+    ap.add_argument("--serve-pass-particles", type=int, default=1 << 25,
+                    help="particles in one serving pass (bounds working memory and pass time)")
     ap.add_argument("--serve-timeout", type=float, default=300.0,
                     help="give up a serving run that has not drained after this many seconds")
     ap.add_argument("--serve-load", type=float, default=0.75,

@@ -195,8 +195,11 @@ k_group_leaves_serial(bool only_marked, const vec4<T>* __restrict__ blo, const v
 // Everything pushed back keeps the order, so the union comes out ascending
 // with its slot starts (a running wave scan of the leaf sizes).  The union is
 // the set of leaves within reach of some target leaf: the same leaf-pair
-// prune stage 2 applies.  A group whose stack outgrows the LDS buffer is
-// marked and left to the serial walk.
+// prune stage 2 applies.  A compact group (box at most four cache radii of
+// its smallest target wide, h within 1.5x, the common case) uses the
+// group's box alone, which is then nearly as tight.
+// A group whose stack outgrows the LDS buffer is marked and left to the
+// serial walk.
 constexpr int S1_WAVES = 2;
 constexpr int S1_SMAX = 1536;
 constexpr int S1_TS = 32;               // target runs (mask bits)
@@ -237,10 +240,20 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
     const u32 nt = xscan[end] - t0;
     const u32 ns = nt < (u32)S1_TS ? nt : (u32)S1_TS;     // runs; run r = targets
     const u32 rl = (nt + ns - 1u) / ns;                     // [r rl, min(nt, r rl + rl))
+    T hmin = ql.w;                            // smallest target h_max
     for (u32 a = lane; a < nt; a += WAVE) {
-        s_tl[w][a] = blo[n_internal + t0 + a];
+        const vec4<T> tl = blo[n_internal + t0 + a];
+        s_tl[w][a] = tl;
         s_th[w][a] = bhi[n_internal + t0 + a];
+        hmin = fmin(hmin, tl.w);
     }
+    hmin = wave_min(hmin);
+    // a compact group (box no wider than a few cache radii of its smallest
+    // target, h nearly uniform) keeps the plain group-box test: per-target
+    // tests would prune little and cost up to nt box tests per node
+    const T reach = rk * hmin;
+    const bool compact = ql.w <= T(1.5) * hmin && (qh.x - ql.x) <= T(4) * reach &&
+                         (qh.y - ql.y) <= T(4) * reach && (qh.z - ql.z) <= T(4) * reach;
     if (lane == 0) {
         s_sn[w][0] = root[k];
         s_sm[w][0] = ns == 32u ? 0xffffffffu : ((1u << ns) - 1u);
@@ -269,7 +282,8 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
             } else {
                 const vec4<T> nl = blo[v], nh = bhi[v];
                 if (box_hit<T>(ql, qh, nl, nh, rk, eps_abs, bx)) {
-                    while (m) {
+                    if (compact) cm = m;
+                    else while (m) {
                         const u32 r = (u32)(__ffs(m) - 1);
                         m &= m - 1u;
                         const u32 a1 = min(nt, r * rl + rl);
