@@ -157,7 +157,11 @@ int ensure(shsph_ctx* c, Buf& b, size_t bytes)
     }
     size_t want = bytes + bytes / 4;
     want = (want + 255) & ~(size_t)255;
-    HIPTRY(c, hipMalloc(&b.p, want));
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();                 // do not leave the failure to later launches
+        return fail(c, SHSPH_ENOMEM, "device memory exhausted (" + std::to_string(want >> 20) + " MiB)");
+    }
     b.cap = want;
     return SHSPH_OK;
 }

@@ -56,6 +56,8 @@ struct Server {
     uint64_t next_ticket = 1;
     int admitting = 0;                   // jobs off the queue, instance being created
     double running_work = 0;             // work bytes charged to running jobs
+    size_t pass_cap = 0;                 // jobs per pass (halved when a pass runs out of memory)
+    size_t rot = 0;                      // first running job of the next capped pass
     bool stop = false;
     shsph_serve_counters stats;
     std::thread th;
@@ -143,13 +145,17 @@ void loop(Server* S)
             S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
             continue;
         }
-        // one pass over every running job: 0 = first derivatives of a CFL
+        // one pass over the running jobs (all of them unless a pass ran out
+        // of memory; then a rotating share): 0 = first derivatives of a CFL
         // job, 1 = evaluation, 2 = a step
-        const size_t m = S->running.size();
+        const size_t nr = S->running.size();
+        const size_t m = std::min(nr, S->pass_cap ? S->pass_cap : nr);
         std::vector<int64_t> hs(m);
         std::vector<double> dts(m);
         std::vector<int> kind(m);
-        std::vector<uint64_t> tk(S->running);
+        std::vector<uint64_t> tk(m);
+        for (size_t i = 0; i < m; ++i) tk[i] = S->running[(S->rot + i) % nr];
+        S->rot = (S->rot + m) % nr;
         double np = 0;
         for (size_t i = 0; i < m; ++i) {
             Job& j = S->jobs[tk[i]];
@@ -176,7 +182,11 @@ void loop(Server* S)
         S->stats.particle_passes += np;
         S->stats.busy_s += t1 - t0;
         S->stats.peak_jobs = std::max<int64_t>(S->stats.peak_jobs, (int64_t)m);
-        std::vector<uint64_t> keep;
+        if (rc == SHSPH_ENOMEM && m > 1) {     // retry with half the jobs per pass
+            S->pass_cap = m / 2;
+            continue;
+        }
+        std::vector<uint64_t> done_now;
         for (size_t i = 0; i < m; ++i) {
             Job& j = S->jobs[tk[i]];
             ++j.st.passes;
@@ -193,7 +203,8 @@ void loop(Server* S)
                     end = SHSPH_JOB_DONE;
                 }
             }
-            if (!end) { keep.push_back(tk[i]); continue; }
+            if (!end) continue;
+            done_now.push_back(tk[i]);
             finish(S, j, end, err, t1);
             shsph_internal_inst_state(S->ctx, j.st.handle, nullptr, nullptr, nullptr, -1);
             S->running_work -= j.need_work;
@@ -202,8 +213,16 @@ void loop(Server* S)
                 j.st.handle = 0;
             }
         }
+        std::vector<uint64_t> keep;
+        for (uint64_t t : S->running)
+            if (std::find(done_now.begin(), done_now.end(), t) == done_now.end()) keep.push_back(t);
         S->running.swap(keep);
-        if (S->running.empty()) S->running_work = 0;   // no drift from rounding
+        if (S->running.empty()) {
+            S->running_work = 0;                       // no drift from rounding
+            S->rot = 0;
+        } else {
+            S->rot %= S->running.size();
+        }
         S->cv_done.notify_all();
     }
     S->cv_done.notify_all();
