@@ -71,7 +71,10 @@ typedef struct {
     int32_t stage1_serial;  /* 1: stage 1 by the serial per-group walk for every group
                                (default 0: one wave per group, serial walk only for
                                groups that outgrow its buffers).  Work, not results. */
-    int32_t reserved;
+    int32_t stage2_mode;    /* stage-2 walk: 1 = per lane (default), 2 = per wave (all
+                               lanes take the wave's joint candidates; pays off when h is
+                               large against the wave's extent), 0 = chosen per wave by
+                               its estimated cost.  Work, not results. */
 } shsph_params;
 
 /* One SPH instance.  x..h are read; h, rho, omega, ax..dudt are written as

@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("lambda_", C.c_double), ("eps_h", C.c_double), ("c_cour", C.c_double),
                 ("c_force", C.c_double), ("max_iter", C.c_int32), ("n_red", C.c_int32),
                 ("max_restarts", C.c_int32), ("spread_slots", C.c_int32),
-                ("stage1_serial", C.c_int32), ("reserved", C.c_int32)]
+                ("stage1_serial", C.c_int32), ("stage2_mode", C.c_int32)]
 
 
 class CParticles(C.Structure):

@@ -532,7 +532,8 @@ template <class T> int build_caches(shsph_ctx* c)
                               inst, rk, rk, c->cap_leaf, P<u32>(c->uleaf), P<u32>(c->uslot),
                               P<u32>(c->ucnt), P<u32>(c->ustot), (u32)c->cap_words, P<u64>(c->nlist),
                               P<u32>(c->ncnt), P<u32>(c->flags), P<vec4<T>>(c->glo),
-                              P<vec4<T>>(c->ghi), P<u32>(c->root_d), work_ptr(c, 0), st);
+                              P<vec4<T>>(c->ghi), P<u32>(c->root_d), work_ptr(c, 0),
+                              c->prm.stage2_mode, st);
         prof_end(c);
         TRY(check_launch(c, "stage2"));
         launch_root_hmax<T>(P<vec4<T>>(c->blo), P<u32>(c->root_d), ninst, P<double>(c->rhmax_d), st);
@@ -1013,7 +1014,7 @@ void shsph_params_default(shsph_params* p)
     p->max_restarts = 8;
     p->spread_slots = 8192;
     p->stage1_serial = 0;
-    p->reserved = 0;
+    p->stage2_mode = 1;
 }
 
 int shsph_create(int device, const shsph_params* p, shsph_ctx** out)
@@ -1027,7 +1028,7 @@ int shsph_create(int device, const shsph_params* p, shsph_ctx** out)
     if (p) c->prm = *p; else shsph_params_default(&c->prm);
     if (!(c->prm.hfact > 0) || !(c->prm.chi >= 1) || !(c->prm.lambda > 1) || !(c->prm.eps_h > 0) ||
         c->prm.max_iter < 1 || c->prm.n_red > 20 || c->prm.max_restarts < 0 ||
-        c->prm.spread_slots < 1) {
+        c->prm.spread_slots < 1 || c->prm.stage2_mode < 0 || c->prm.stage2_mode > 2) {
         delete c;
         return SHSPH_EINVAL;
     }

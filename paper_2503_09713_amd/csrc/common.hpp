@@ -186,26 +186,6 @@ template <class T> __device__ inline T min_image(T d, T L, T halfL, int periodic
     return periodic ? w : d;
 }
 
-// Object-object criterion of the cache (App. F, chi-extended radius), in T:
-//   dx = x_b - x_a (min image), r2 = (dx*dx + dy*dy) + dz*dz,
-//   rc = rkc * max(h_a, h_b), accept iff r2 < rc*rc.
-template <class T, bool WRAP = true>
-__device__ inline bool cache_crit(T xa, T ya, T za, T ha, T xb, T yb, T zb, T hb,
-                                  const Box<T>& bx, T rkc)
-{
-#pragma clang fp contract(off)
-    const int per = WRAP ? bx.periodic : 0;
-    const T dx = min_image(xb - xa, bx.L[0], bx.halfL[0], per);
-    const T dy = min_image(yb - ya, bx.L[1], bx.halfL[1], per);
-    const T dz = min_image(zb - za, bx.L[2], bx.halfL[2], per);
-    const T xx = dx * dx, yy = dy * dy, zz = dz * dz;
-    const T r2 = (xx + yy) + zz;
-    const T hm = ha > hb ? ha : hb;
-    const T rc = rkc * hm;
-    const T rc2 = rc * rc;
-    return r2 < rc2;
-}
-
 // A group is interior when its box grown by the largest cache radius
 // (rk * h_max of the whole tree, inflated) stays inside the periodic box: then
 // every cached pair is closer than half a period and the minimum image is the

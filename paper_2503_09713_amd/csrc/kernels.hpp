@@ -125,7 +125,7 @@ void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* 
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
                         const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
                         u32* flags, const vec4<T>* glo, const vec4<T>* ghi, const u32* root,
-                        u64* work, hipStream_t st);
+                        u64* work, int mode, hipStream_t st);
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
                             const u32* uleaf, const u32* uslot, const u32* ucnt, u32 capq,
                             const u64* nlist, const u32* ncnt, const u64* off, u32* list,

@@ -363,12 +363,54 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
 constexpr int TMAX = GROUP;      // target leaves of a group: at most one per particle
 constexpr int MW = LCHUNK / 64;  // mask words per target leaf
 
-template <class T, bool LDS, bool WRAP>
-__device__ inline void cache_walk(const vec4<T>& pa, const Box<T>& bx, T rkc, const u64* mask,
-                                  const u32* s_b0, const u32* s_b1, const u32* s_slot,
-                                  const vec4<T>* s_upos, const vec4<T>* posh, u64* out, u32 capq,
-                                  u32& c, u64& wbuf, u32& tested)
+// Accept step of the stage-2 walks, without branches around the packing:
+// slot s goes into the lane's current ELL word, which is written out when
+// full.  The criterion compares r^2 with max(qa, qb), q = (rkc h)^2 rounded
+// as (rkc h)(rkc h): rounding is monotone, so this equals (rkc max(h_a,
+// h_b))^2 exactly.
+template <class T, bool WRAP>
+__device__ inline void cache_take(const vec4<T>& pa, T qa, bool live, const Box<T>& bx,
+                                  const vec4<T>& pb, T qb, u32 s, u64* out, u32 capq, u32& c,
+                                  u64& wbuf)
 {
+#pragma clang fp contract(off)
+    const int per = WRAP ? bx.periodic : 0;
+    const T dx = min_image(pb.x - pa.x, bx.L[0], bx.halfL[0], per);
+    const T dy = min_image(pb.y - pa.y, bx.L[1], bx.halfL[1], per);
+    const T dz = min_image(pb.z - pa.z, bx.L[2], bx.halfL[2], per);
+    const T xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    const T r2 = (xx + yy) + zz;
+    const bool acc = live && r2 < fmax(qa, qb);
+    const u64 ins = (u64)s << (16u * (c & 3u));
+    wbuf = acc ? (wbuf | ins) : wbuf;
+    c += acc ? 1u : 0u;
+    const bool full = acc && (c & 3u) == 0u;
+    if (full) {
+        const u32 q = (c >> 2) - 1u;
+        if (q < capq) out[(u64)q * GROUP] = wbuf;
+    }
+    wbuf = full ? 0ull : wbuf;
+}
+
+template <class T, bool LDS>
+__device__ inline T cand_q(const vec4<T>& pb, T rkc)
+{
+#pragma clang fp contract(off)
+    if (LDS) return pb.w;                         // staged as (rkc h_b)^2
+    const T r = rkc * pb.w;
+    return r * r;
+}
+
+// Stage-2 walk, per lane: each lane takes the union leaves of its own
+// target leaf's mask (lanes diverge; every issued test is one the lane needs).
+template <class T, bool LDS, bool WRAP>
+__device__ inline void cache_walk_lane(const vec4<T>& pa, T qa, bool live, const Box<T>& bx,
+                                       T rkc, const u64* mask, const u32* s_b0, const u32* s_b1,
+                                       const u32* s_slot, const vec4<T>* s_upos,
+                                       const vec4<T>* posh, u64* out, u32 capq, u32& c, u64& wbuf,
+                                       u32& tested)
+{
+    if (!live) return;
 #pragma unroll
     for (int w = 0; w < MW; ++w) {
         u64 cur = mask[w];
@@ -377,33 +419,82 @@ __device__ inline void cache_walk(const vec4<T>& pa, const Box<T>& bx, T rkc, co
             cur &= cur - 1;
             const u32 b0 = s_b0[j], b1 = s_b1[j], sl = s_slot[j];
             tested += b1 - b0;
-            auto take = [&](const vec4<T>& pb, u32 s) {
-                if (cache_crit<T, WRAP>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w, bx, rkc)) {
-                    wbuf |= (u64)s << (16u * (c & 3u));
-                    ++c;
-                    if ((c & 3u) == 0) {
-                        const u32 q = (c >> 2) - 1u;
-                        if (q < capq) out[(u64)q * GROUP] = wbuf;
-                        wbuf = 0;
-                    }
-                }
-            };
             u32 b = b0;
-            // four candidates in flight, tested in ascending order
             for (; b + 4 <= b1; b += 4) {
                 const u32 s = sl + (b - b0);
                 const vec4<T> p0 = LDS ? s_upos[s] : posh[b];
                 const vec4<T> p1 = LDS ? s_upos[s + 1] : posh[b + 1];
                 const vec4<T> p2 = LDS ? s_upos[s + 2] : posh[b + 2];
                 const vec4<T> p3 = LDS ? s_upos[s + 3] : posh[b + 3];
-                take(p0, s);
-                take(p1, s + 1);
-                take(p2, s + 2);
-                take(p3, s + 3);
+                cache_take<T, WRAP>(pa, qa, true, bx, p0, cand_q<T, LDS>(p0, rkc), s, out, capq, c, wbuf);
+                cache_take<T, WRAP>(pa, qa, true, bx, p1, cand_q<T, LDS>(p1, rkc), s + 1, out, capq, c, wbuf);
+                cache_take<T, WRAP>(pa, qa, true, bx, p2, cand_q<T, LDS>(p2, rkc), s + 2, out, capq, c, wbuf);
+                cache_take<T, WRAP>(pa, qa, true, bx, p3, cand_q<T, LDS>(p3, rkc), s + 3, out, capq, c, wbuf);
             }
-            for (; b < b1; ++b) take(LDS ? s_upos[sl + (b - b0)] : posh[b], sl + (b - b0));
+            for (; b < b1; ++b) {
+                const vec4<T> p = LDS ? s_upos[sl + (b - b0)] : posh[b];
+                cache_take<T, WRAP>(pa, qa, true, bx, p, cand_q<T, LDS>(p, rkc), sl + (b - b0), out,
+                                    capq, c, wbuf);
+            }
         }
     }
+}
+
+// Stage-2 walk, per wave: the wave takes the union leaves marked for any of
+// its lanes (the OR of their masks), in ascending order, and every lane tests
+// every particle of them: the criterion is exact, so a lane never accepts a
+// particle its own mask would have skipped, and its slots stay ascending.
+// Uniform control and broadcast LDS reads; worth it when the lanes' candidate
+// sets overlap (the wave's union is not much larger than one lane's).
+template <class T, bool LDS, bool WRAP>
+__device__ inline void cache_walk_wave(const vec4<T>& pa, T qa, bool live, const Box<T>& bx, T rkc,
+                                       const u64* wmask, const u32* s_b0, const u32* s_b1,
+                                       const u32* s_slot, const vec4<T>* s_upos,
+                                       const vec4<T>* posh, u64* out, u32 capq, u32& c, u64& wbuf,
+                                       u32& tested)
+{
+#pragma unroll
+    for (int w = 0; w < MW; ++w) {
+        u64 cur = wmask[w];
+        while (cur) {
+            const u32 j = (u32)(w * 64) + (u32)(__ffsll((unsigned long long)cur) - 1);
+            cur &= cur - 1;
+            const u32 b0 = __builtin_amdgcn_readfirstlane(s_b0[j]);
+            const u32 b1 = __builtin_amdgcn_readfirstlane(s_b1[j]);
+            const u32 sl = __builtin_amdgcn_readfirstlane(s_slot[j]);
+            if (live) tested += b1 - b0;
+            u32 b = b0;
+            for (; b + 4 <= b1; b += 4) {
+                const u32 s = sl + (b - b0);
+                const vec4<T> p0 = LDS ? s_upos[s] : posh[b];
+                const vec4<T> p1 = LDS ? s_upos[s + 1] : posh[b + 1];
+                const vec4<T> p2 = LDS ? s_upos[s + 2] : posh[b + 2];
+                const vec4<T> p3 = LDS ? s_upos[s + 3] : posh[b + 3];
+                cache_take<T, WRAP>(pa, qa, live, bx, p0, cand_q<T, LDS>(p0, rkc), s, out, capq, c, wbuf);
+                cache_take<T, WRAP>(pa, qa, live, bx, p1, cand_q<T, LDS>(p1, rkc), s + 1, out, capq, c, wbuf);
+                cache_take<T, WRAP>(pa, qa, live, bx, p2, cand_q<T, LDS>(p2, rkc), s + 2, out, capq, c, wbuf);
+                cache_take<T, WRAP>(pa, qa, live, bx, p3, cand_q<T, LDS>(p3, rkc), s + 3, out, capq, c, wbuf);
+            }
+            for (; b < b1; ++b) {
+                const vec4<T> p = LDS ? s_upos[sl + (b - b0)] : posh[b];
+                cache_take<T, WRAP>(pa, qa, live, bx, p, cand_q<T, LDS>(p, rkc), sl + (b - b0), out,
+                                    capq, c, wbuf);
+            }
+        }
+    }
+}
+
+__device__ inline u64 wave_or64(u64 x)
+{
+    u32 lo = (u32)x, hi = (u32)(x >> 32);
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+        lo |= __shfl_xor(lo, d, WAVE);
+        hi |= __shfl_xor(hi, d, WAVE);
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    hi = __builtin_amdgcn_readfirstlane(hi);
+    return ((u64)hi << 32) | lo;
 }
 
 template <class T>
@@ -416,7 +507,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
               const u32* __restrict__ ucnt, const u32* __restrict__ ustot, u32 capq,
               u64* __restrict__ nlist, u32* __restrict__ ncnt, u32* __restrict__ flags,
               const vec4<T>* __restrict__ glo, const vec4<T>* __restrict__ ghi,
-              const u32* __restrict__ root, u64* __restrict__ work)
+              const u32* __restrict__ root, u64* __restrict__ work, int mode)
 {
     __shared__ u64 s_w[GROUP / WAVE];
     __shared__ u32 s_b0[LCHUNK];
@@ -454,6 +545,18 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         const vec4<T>* src[1] = { posh };
         vec4<T>* dst[1] = { s_upos };
         stage_union<T, 1>(src, dst, id, uleaf + g * cap, uslot + g * cap, nu, 0u, S);
+        __syncthreads();
+        for (u32 t = threadIdx.x; t < S; t += GROUP) {   // h -> (rkc h)^2
+#pragma clang fp contract(off)
+            const T r = rkc * s_upos[t].w;
+            s_upos[t].w = r * r;
+        }
+    }
+    T qa;
+    {
+#pragma clang fp contract(off)
+        const T r = rkc * pa.w;
+        qa = r * r;
     }
     u64* out = nlist + (u64)g * capq * GROUP + threadIdx.x;
     u32 c = 0, tested = 0;
@@ -480,19 +583,46 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
                 atomicOr((unsigned long long*)&s_mask[t][j >> 6], 1ull << (j & 63));
         }
         __syncthreads();
-        if (!live) continue;
-        u64 mk[MW];
+        u64 mk[MW], wm[MW];
 #pragma unroll
-        for (int w = 0; w < MW; ++w) mk[w] = s_mask[ta][w];
-        if (in_lds && interior)
-            cache_walk<T, true, false>(pa, bx, rkc, mk, s_b0, s_b1, s_slot, s_upos, posh, out, capq,
-                                       c, wbuf, tested);
-        else if (in_lds)
-            cache_walk<T, true, true>(pa, bx, rkc, mk, s_b0, s_b1, s_slot, s_upos, posh, out, capq,
-                                      c, wbuf, tested);
-        else
-            cache_walk<T, false, true>(pa, bx, rkc, mk, s_b0, s_b1, s_slot, s_upos, posh, out,
-                                       capq, c, wbuf, tested);
+        for (int w = 0; w < MW; ++w) {
+            mk[w] = live ? s_mask[ta][w] : 0ull;
+            wm[w] = wave_or64(mk[w]);
+        }
+        // walk per wave or per lane: the wave issues about (leaves of the
+        // wave's mask) uniform leaf visits or (leaves of the busiest lane's
+        // mask) divergent ones, the latter ~1.4x as dear per candidate
+        bool uniform = mode == 2;
+        if (mode == 0) {
+            u32 mine = 0, all = 0;
+#pragma unroll
+            for (int w = 0; w < MW; ++w) {
+                mine += (u32)__popcll(mk[w]);
+                all += (u32)__popcll(wm[w]);
+            }
+            uniform = 10u * all < 14u * wave_max(mine);
+        }
+        if (uniform) {
+            if (in_lds && interior)
+                cache_walk_wave<T, true, false>(pa, qa, live, bx, rkc, wm, s_b0, s_b1, s_slot,
+                                                s_upos, posh, out, capq, c, wbuf, tested);
+            else if (in_lds)
+                cache_walk_wave<T, true, true>(pa, qa, live, bx, rkc, wm, s_b0, s_b1, s_slot,
+                                               s_upos, posh, out, capq, c, wbuf, tested);
+            else
+                cache_walk_wave<T, false, true>(pa, qa, live, bx, rkc, wm, s_b0, s_b1, s_slot,
+                                                s_upos, posh, out, capq, c, wbuf, tested);
+        } else {
+            if (in_lds && interior)
+                cache_walk_lane<T, true, false>(pa, qa, live, bx, rkc, mk, s_b0, s_b1, s_slot,
+                                                s_upos, posh, out, capq, c, wbuf, tested);
+            else if (in_lds)
+                cache_walk_lane<T, true, true>(pa, qa, live, bx, rkc, mk, s_b0, s_b1, s_slot,
+                                               s_upos, posh, out, capq, c, wbuf, tested);
+            else
+                cache_walk_lane<T, false, true>(pa, qa, live, bx, rkc, mk, s_b0, s_b1, s_slot,
+                                                s_upos, posh, out, capq, c, wbuf, tested);
+        }
     }
     if (live) {
         if (c & 3u) {
@@ -583,12 +713,12 @@ void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* 
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
                         const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
                         u32* flags, const vec4<T>* glo, const vec4<T>* ghi, const u32* root,
-                        u64* work, hipStream_t st)
+                        u64* work, int mode, hipStream_t st)
 {
     if (ngroups <= 0) return;
     hipLaunchKernelGGL((k_group_cache<T>), dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, blo,
                        bhi, id, xscan, n_internal, gm, inst, (T)rk, (T)rkc, cap, uleaf, uslot, ucnt, ustot,
-                       capq, nlist, ncnt, flags, glo, ghi, root, work);
+                       capq, nlist, ncnt, flags, glo, ghi, root, work, mode);
 }
 
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
@@ -613,7 +743,7 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
                                         const u32*, const u32*, i64, const GroupMap&, i64, const InstDev*,    \
                                         double, double, i64, const u32*, const u32*, const u32*,  \
                                         const u32*, u32, u64*, u32*, u32*, const vec4<T>*,        \
-                                        const vec4<T>*, const u32*, u64*, hipStream_t);
+                                        const vec4<T>*, const u32*, u64*, int, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -138,6 +138,21 @@ def test_stage1_paths(torch_cuda, name, make, n_red):
     assert (unions["leaf"] <= unions["wave"]).all() and (unions["leaf"] <= unions["box"]).all()
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("name,make", [
+    ("lattice16_f32", lambda: gen.lattice(16, gen.SEEDS["tiny"], dtype=np.float32)),
+    ("plummer5000_f32", lambda: gen.plummer(5000, 6, dtype=np.float32)),
+], ids=["lattice16_f32", "plummer5000_f32"])
+def test_stage2_walks(torch_cuda, name, make, mode):
+    """Stage 2 forced to the per-lane (1) or per-wave (2) walk: same cache."""
+    _say(f"[tree] {name}: stage-2 walk {mode}")
+    p = make()
+    ctx = _ctx(torch_cuda, n_red=3, stage2_mode=mode)
+    ctx.build_tree(_upload(p, torch_cuda))
+    check_tree(ctx, p, 3)
+    ctx.close()
+
+
 def test_tree_with_duplicate_positions(torch_cuda):
     _say("[tree] duplicates")
     base = gen.lattice(12, 9, dtype=np.float32)
