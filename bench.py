@@ -41,6 +41,30 @@ WORK_KEYS = {"particle_cache": ("cache_tests", "cache_prune_tests"),
              "density": ("density_pair_evals", "density_pairs_in_2h"),
              "force": ("force_entries", "force_pairs")}
 
+# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a plain
+# 1 GiB device copy (FETCH x2.0000, WRITE x1.0000), with the sha256 of the
+# kernel's sources at the time: the figure is reported only while they match.
+TRAFFIC = {}
+KERNEL_SOURCES = {"particle_cache": ("neigh.hip", "common.hpp", "kernels.hpp")}
+
+
+def sources_sha(stage):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(stage, ()):
+        with open(os.path.join(ROOT, "paper_2503_09713_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_for(stage, workload):
+    t = TRAFFIC.get((stage, workload))
+    if not t or t["sources_sha256"] != sources_sha(stage):
+        return None
+    return t["bytes_per_launch"]
+
+
 WORKLOADS = {
     # name: (generator, lattice side, seed, dtype)
     "sedov256": ("sedov", 256, 3, "f32"),
@@ -196,7 +220,7 @@ def serve_templates(seed):
     return out
 
 
-def run_served(args, shsph, torch, capacity):
+def run_served(args, shsph, torch):
     """Poisson arrivals of STEP (1-10 CFL steps) and EVAL jobs, each bringing
     its own instance, served under a 200 GB budget with continuous batching and,
     on the same trace, one job at a time."""
@@ -205,6 +229,15 @@ def run_served(args, shsph, torch, capacity):
     log("[served] generating templates")
     tpl = serve_templates(gen.SEEDS["serve"])
     sets = {f: [shsph.ParticleSet.from_particles(p) for p in ps] for f, ps in tpl.items()}
+    # instances come from running simulations: settle each template's h once
+    pre = shsph.Context(0, n_red=args.n_red)
+    for f in sets:
+        for ps in sets[f]:
+            h = pre.instance_create(ps)
+            pre.eval_batch([h])
+            pre.instance_read(h, ps)
+            pre.instance_destroy(h)
+    pre.close()
     logn = {f: np.log([p.n for p in ps]) for f, ps in tpl.items()}
     base = gen.serve_trace(1.0, args.serve_jobs, seed=gen.SEEDS["serve"])
     jobs = []
@@ -213,9 +246,29 @@ def run_served(args, shsph, torch, capacity):
         jobs.append(dict(j, tpl=k, n=tpl[j["family"]][k].n))
     # passes per job: a STEP job's instance first gets its derivatives
     work = np.array([j["n"] * (j["nsteps"] + 1 if j["kind"] == "step" else 1) for j in jobs], float)
-    rate = args.serve_load * capacity / work.mean()
+
+    def submit(ctx, j):
+        kind = shsph.JOB_EVAL if j["kind"] == "eval" else shsph.JOB_STEP
+        return ctx.submit(init=sets[j["family"]][j["tpl"]], kind=kind, nsteps=j["nsteps"],
+                          release=True)
+
+    # capacity of the served mix: a burst of the trace's first jobs, all at once
+    nb = min(300, len(jobs))
+    ctx = shsph.Context(0, n_red=args.n_red)
+    ctx.serve_start(200e9, max_batch=256, max_batch_particles=args.serve_pass_particles)
+    log(f"[served] capacity probe: {nb} jobs at once")
+    t0 = time.perf_counter()
+    for j in jobs[:nb]:
+        submit(ctx, j)
+    while not ctx.serve_wait(5.0):
+        log(f"[served] capacity probe: {ctx.serve_stats()['jobs_done']} of {nb} done")
+    cap_served = work[:nb].sum() / (time.perf_counter() - t0)
+    ctx.serve_stop()
+    ctx.close()
+    rate = args.serve_load * cap_served / work.mean()
     res = {"workload": "served", "jobs": len(jobs), "rate_jobs_per_s": rate,
-           "offered_load_of_batched_capacity": args.serve_load, "budget_GB": 200,
+           "capacity_particle_passes_per_s": cap_served,
+           "offered_load_of_capacity": args.serve_load, "budget_GB": 200,
            "pass_particles_max": args.serve_pass_particles,
            "templates": 32, "eval_fraction": float(np.mean([j["kind"] == "eval" for j in jobs]))}
     for name, policy in (("continuous", shsph.SERVE_CONTINUOUS),
@@ -236,9 +289,7 @@ def run_served(args, shsph, torch, capacity):
                 if d <= 0:
                     break
                 time.sleep(d if d > 2e-3 else 0)
-            kind = shsph.JOB_EVAL if j["kind"] == "eval" else shsph.JOB_STEP
-            tk.append(ctx.submit(init=sets[j["family"]][j["tpl"]], kind=kind, nsteps=j["nsteps"],
-                                 release=True))
+            tk.append(submit(ctx, j))
         t_end = time.perf_counter() + args.serve_timeout
         while not ctx.serve_wait(5.0):
             st = ctx.serve_stats()
@@ -293,7 +344,7 @@ def main():
     ap.add_argument("--serve-timeout", type=float, default=300.0,
                     help="give up a serving run that has not drained after this many seconds")
     ap.add_argument("--serve-load", type=float, default=0.75,
-                    help="offered load as a fraction of the measured batched throughput")
+                    help="offered load as a fraction of the served mix's measured capacity")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against known bytes) and exit")
@@ -360,13 +411,15 @@ def main():
         ops = (OPS[dom][0] * work[k1] + OPS[dom][1] * work[k2]) / cand[dom][1]
         tf = ops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": round(tf, 3), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4),
+                "traffic": traffic_for(dom, args.workload),
                 "frac_of_nonpacked_peak": round(tf / FP32_PEAK_NONPACKED_TFLOPS, 4),
                 "avg_launch_ms": round(avg_ms, 4), "flop_per_launch": int(ops),
                 "hbm_algorithmic_GBs": round(hbm, 1), "bytes_per_launch": int(by)}
     else:
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4),
+                "traffic": traffic_for(dom, args.workload),
                 "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": int(by)}
     # whole step against HBM: algorithmic bytes of all stages per step
     step_bytes = sum(algorithmic_bytes(k, p.n, info, T) * (v[1] / args.steps)
@@ -397,8 +450,7 @@ def main():
         out["batched"] = run_batched(args, shsph, torch)
         torch.cuda.empty_cache()
     if not args.no_served:
-        cap = out["batched"]["value"] if "batched" in out else value
-        out["served"] = run_served(args, shsph, torch, cap)
+        out["served"] = run_served(args, shsph, torch)
     if host is not None:
         out["cpu_baseline"] = cpu_baseline(host, p, args)
     print(json.dumps(out), flush=True)
