@@ -45,7 +45,11 @@ WORK_KEYS = {"particle_cache": ("cache_tests", "cache_prune_tests"),
 # (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a plain
 # 1 GiB device copy (FETCH x2.0000, WRITE x1.0000), with the sha256 of the
 # kernel's sources at the time: the figure is reported only while they match.
-TRAFFIC = {}
+TRAFFIC = {
+    ("particle_cache", "sedov256"): {
+        "bytes_per_launch": 5.320e9,      # FETCH 2.144 GB + WRITE 3.176 GB (k_group_cache)
+        "sources_sha256": "ce1a8b035bd4e7c036d209d36ff0fc78dd599d1949a11b0278d1ec8f96188371"},
+}
 KERNEL_SOURCES = {"particle_cache": ("neigh.hip", "common.hpp", "kernels.hpp")}
 
 
