@@ -171,6 +171,9 @@ def run_batched(args, shsph, torch):
            "n_min": min(p.n for p in insts), "n_max": max(p.n for p in insts), "steps": K}
     ctx = shsph.Context(0, n_red=args.n_red)
     hs = [ctx.instance_create(s) for s in sets]
+    tune = ctx.autotune(hs)
+    log(f"[batched] autotuned: n_red {tune['n_red']}, stage-2 walk {tune['stage2_mode']}")
+    res["autotuned"] = tune
     for _ in range(W):
         ctx.step_batch(hs)
     torch.cuda.synchronize()
@@ -184,7 +187,7 @@ def run_batched(args, shsph, torch):
     ctx.set_profiling(False)
     ctx.close()
     log(f"[batched] batched {1e3 * tb / K:.2f} ms/step")
-    ctx = shsph.Context(0, n_red=args.n_red)
+    ctx = shsph.Context(0, n_red=tune["n_red"], stage2_mode=tune["stage2_mode"])
     hs = [ctx.instance_create(s) for s in sets]
     for _ in range(W):
         for h in hs:
@@ -224,17 +227,19 @@ def serve_templates(seed):
     return out
 
 
-def run_served(args, shsph, torch):
+def run_served(args, shsph, torch, tune=None):
     """Poisson arrivals of STEP (1-10 CFL steps) and EVAL jobs, each bringing
     its own instance, served under a 200 GB budget with continuous batching and,
     on the same trace, one job at a time."""
     import numpy as np
     import gen
+    kw = dict(n_red=args.n_red) if not tune else dict(n_red=tune["n_red"],
+                                                      stage2_mode=tune["stage2_mode"])
     log("[served] generating templates")
     tpl = serve_templates(gen.SEEDS["serve"])
     sets = {f: [shsph.ParticleSet.from_particles(p) for p in ps] for f, ps in tpl.items()}
     # instances come from running simulations: settle each template's h once
-    pre = shsph.Context(0, n_red=args.n_red)
+    pre = shsph.Context(0, **kw)
     for f in sets:
         for ps in sets[f]:
             h = pre.instance_create(ps)
@@ -258,7 +263,7 @@ def run_served(args, shsph, torch):
 
     # capacity of the served mix: a burst of the trace's first jobs, all at once
     nb = min(300, len(jobs))
-    ctx = shsph.Context(0, n_red=args.n_red)
+    ctx = shsph.Context(0, **kw)
     ctx.serve_start(200e9, max_batch=256, max_batch_particles=args.serve_pass_particles)
     log(f"[served] capacity probe: {nb} jobs at once")
     t0 = time.perf_counter()
@@ -277,7 +282,7 @@ def run_served(args, shsph, torch):
            "templates": 32, "eval_fraction": float(np.mean([j["kind"] == "eval" for j in jobs]))}
     for name, policy in (("continuous", shsph.SERVE_CONTINUOUS),
                          ("one_at_a_time", shsph.SERVE_ONE_AT_A_TIME)):
-        ctx = shsph.Context(0, n_red=args.n_red)
+        ctx = shsph.Context(0, **kw)
         ctx.serve_start(200e9, max_batch=256, policy=policy,
                         max_batch_particles=args.serve_pass_particles)
         log(f"[served] {name}: {len(jobs)} jobs at {rate:.1f}/s")
@@ -454,7 +459,7 @@ def main():
         out["batched"] = run_batched(args, shsph, torch)
         torch.cuda.empty_cache()
     if not args.no_served:
-        out["served"] = run_served(args, shsph, torch)
+        out["served"] = run_served(args, shsph, torch, out.get("batched", {}).get("autotuned"))
     if host is not None:
         out["cpu_baseline"] = cpu_baseline(host, p, args)
     print(json.dumps(out), flush=True)

@@ -271,6 +271,14 @@ int shsph_step_batch(shsph_ctx *ctx, const int64_t *handles, int32_t count, cons
  * new Morton order). */
 int shsph_eval_batch(shsph_ctx *ctx, const int64_t *handles, int32_t count);
 
+/* Autotuner for batched passes: times evaluation passes of the listed
+ * instances (as shsph_eval_batch: positions, velocities and u unchanged) for
+ * leaf sizes n_red = 2, 3, 4 and both stage-2 walks, and keeps the fastest
+ * in the context's parameters for later passes.  Neither changes results.
+ * Outputs (optional): the chosen n_red and walk, and its pass time in ms. */
+int shsph_autotune(shsph_ctx *ctx, const int64_t *handles, int32_t count, int32_t *n_red,
+                   int32_t *stage2_mode, double *pass_ms);
+
 /* Pool occupancy: particles held by instances, pool capacity, instances. */
 int shsph_pool_usage(shsph_ctx *ctx, int64_t *particles_used, int64_t *particles_cap,
                      int64_t *n_instances);

@@ -142,6 +142,7 @@ def lib():
     L.shsph_step_batch.argtypes = [vp, i64p, C.c_int32, dp, dp]
     L.shsph_eval_batch.argtypes = [vp, i64p, C.c_int32]
     L.shsph_pool_usage.argtypes = [vp, i64p, i64p, i64p]
+    L.shsph_autotune.argtypes = [vp, i64p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
     L.shsph_serve_start.argtypes = [vp, C.POINTER(ServeConfig)]
     L.shsph_submit.argtypes = [vp, C.POINTER(Job), C.POINTER(C.c_uint64)]
     L.shsph_poll.argtypes = [vp, C.c_uint64, C.POINTER(JobStatus)]
@@ -158,7 +159,7 @@ def lib():
                "shsph_instance_read", "shsph_instance_info", "shsph_step_batch",
                "shsph_eval_batch", "shsph_pool_usage", "shsph_serve_start", "shsph_submit",
                "shsph_poll", "shsph_serve_drain", "shsph_serve_stats", "shsph_serve_stop",
-               "shsph_footprint"):
+               "shsph_footprint", "shsph_autotune"):
         getattr(L, fn).restype = ip
     _lib = L
     return L
@@ -363,6 +364,14 @@ class Context:
         hs, arr = self._handles(handles)
         allow = (SHSPH_ENOCONV,) if allow_noconv else ()
         self._check(self.L.shsph_eval_batch(self.h, arr, len(hs)), allow)
+
+    def autotune(self, handles) -> dict:
+        """Pick leaf size (n_red) and stage-2 walk for batched passes of these instances."""
+        hs, arr = self._handles(handles)
+        nr, md, ms = C.c_int32(), C.c_int32(), C.c_double()
+        self._check(self.L.shsph_autotune(self.h, arr, len(hs), C.byref(nr), C.byref(md), C.byref(ms)))
+        self.params.n_red, self.params.stage2_mode = nr.value, md.value
+        return dict(n_red=nr.value, stage2_mode=md.value, pass_ms=ms.value)
 
     def pool_usage(self) -> dict:
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1466,6 +1467,45 @@ int shsph_pool_usage(shsph_ctx* c, int64_t* particles_used, int64_t* particles_c
     if (particles_used) *particles_used = c->pool.used;
     if (particles_cap) *particles_cap = c->pool.cap;
     if (n_instances) *n_instances = (int64_t)c->insts.size();
+    return SHSPH_OK;
+}
+
+
+// Autotuner for batched passes: leaf size (n_red) x stage-2 walk, timed on
+// evaluation passes of the given instances; the fastest is kept.
+int shsph_autotune(shsph_ctx* c, const int64_t* handles, int32_t count, int32_t* n_red_out,
+                   int32_t* mode_out, double* ms_out)
+{
+    if (!c) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->err.clear();
+    std::vector<Inst*> b;
+    TRY(gather_batch(c, handles, count, b));
+    HIPTRY(c, hipSetDevice(c->device));
+    const std::vector<double> zero(count, 0.0);
+    const shsph_params keep = c->prm;
+    double best = 1e300;
+    int best_nr = keep.n_red, best_md = keep.stage2_mode;
+    for (int nr = 2; nr <= 4; ++nr) {
+        for (int md = 1; md <= 2; ++md) {
+            c->prm.n_red = nr;
+            c->prm.stage2_mode = md;
+            double t = 0;
+            for (int rep = 0; rep < 2; ++rep) {          // the first pass sizes buffers
+                const auto t0 = std::chrono::steady_clock::now();
+                const int rc = run_pass(c, b, zero);
+                if (rc != SHSPH_OK && rc != SHSPH_ENOCONV) { c->prm = keep; return rc; }
+                t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            }
+            if (t < best) { best = t; best_nr = nr; best_md = md; }
+        }
+    }
+    c->prm = keep;
+    c->prm.n_red = best_nr;
+    c->prm.stage2_mode = best_md;
+    if (n_red_out) *n_red_out = best_nr;
+    if (mode_out) *mode_out = best_md;
+    if (ms_out) *ms_out = best;
     return SHSPH_OK;
 }
 

@@ -363,15 +363,12 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
 constexpr int TMAX = GROUP;      // target leaves of a group: at most one per particle
 constexpr int MW = LCHUNK / 64;  // mask words per target leaf
 
-// Accept step of the stage-2 walks, without branches around the packing:
-// slot s goes into the lane's current ELL word, which is written out when
-// full.  The criterion compares r^2 with max(qa, qb), q = (rkc h)^2 rounded
-// as (rkc h)(rkc h): rounding is monotone, so this equals (rkc max(h_a,
-// h_b))^2 exactly.
+// Stage-2 candidate test in the storage type, without FMA:
+//   dx = x_b - x_a (minimum image), r2 = (dx*dx + dy*dy) + dz*dz, accept iff
+//   r2 < max(qa, qb), q = (rkc h)^2 rounded as (rkc h)(rkc h); rounding is
+//   monotone, so max(qa, qb) equals (rkc max(h_a, h_b))^2 exactly.
 template <class T, bool WRAP>
-__device__ inline void cache_take(const vec4<T>& pa, T qa, bool live, const Box<T>& bx,
-                                  const vec4<T>& pb, T qb, u32 s, u64* out, u32 capq, u32& c,
-                                  u64& wbuf)
+__device__ inline bool cache_test(const vec4<T>& pa, T qa, const Box<T>& bx, const vec4<T>& pb, T qb)
 {
 #pragma clang fp contract(off)
     const int per = WRAP ? bx.periodic : 0;
@@ -380,7 +377,25 @@ __device__ inline void cache_take(const vec4<T>& pa, T qa, bool live, const Box<
     const T dz = min_image(pb.z - pa.z, bx.L[2], bx.halfL[2], per);
     const T xx = dx * dx, yy = dy * dy, zz = dz * dz;
     const T r2 = (xx + yy) + zz;
-    const bool acc = live && r2 < fmax(qa, qb);
+    return r2 < fmax(qa, qb);
+}
+
+template <class T, bool LDS>
+__device__ inline T cand_q(const vec4<T>& pb, T rkc)
+{
+#pragma clang fp contract(off)
+    if (LDS) return pb.w;                         // staged as (rkc h_b)^2
+    const T r = rkc * pb.w;
+    return r * r;
+}
+
+// Test candidate slot s and, if accepted, pack it at once (branch-free around
+// the packing; the per-lane walk, where leaves are short).
+template <class T, bool LDS, bool WRAP>
+__device__ inline void cache_take(const vec4<T>& pa, T qa, const Box<T>& bx, const vec4<T>& pb,
+                                  T rkc, u32 s, u64* out, u32 capq, u32& c, u64& wbuf)
+{
+    const bool acc = cache_test<T, WRAP>(pa, qa, bx, pb, cand_q<T, LDS>(pb, rkc));
     const u64 ins = (u64)s << (16u * (c & 3u));
     wbuf = acc ? (wbuf | ins) : wbuf;
     c += acc ? 1u : 0u;
@@ -392,13 +407,54 @@ __device__ inline void cache_take(const vec4<T>& pa, T qa, bool live, const Box<
     wbuf = full ? 0ull : wbuf;
 }
 
-template <class T, bool LDS>
-__device__ inline T cand_q(const vec4<T>& pb, T rkc)
+// Append slot s to the lane's ELL words (written out when a word is full).
+__device__ inline void cache_append(u32 s, u64* out, u32 capq, u32& c, u64& wbuf)
 {
-#pragma clang fp contract(off)
-    if (LDS) return pb.w;                         // staged as (rkc h_b)^2
-    const T r = rkc * pb.w;
-    return r * r;
+    wbuf |= (u64)s << (16u * (c & 3u));
+    ++c;
+    if ((c & 3u) == 0u) {
+        const u32 q = (c >> 2) - 1u;
+        if (q < capq) out[(u64)q * GROUP] = wbuf;
+        wbuf = 0;
+    }
+}
+
+// One union leaf's particles [b0, b1) (union slots from sl) for the per-wave
+// walk: the tests set bits of a 32-candidate mask, then only the accepted
+// slots are appended, in ascending order (the packing runs only where a lane
+// accepted, not for every candidate the wave tests).
+template <class T, bool LDS, bool WRAP>
+__device__ inline void cache_leaf(const vec4<T>& pa, T qa, bool live, const Box<T>& bx, T rkc,
+                                  u32 b0, u32 b1, u32 sl, const vec4<T>* s_upos,
+                                  const vec4<T>* posh, u64* out, u32 capq, u32& c, u64& wbuf)
+{
+    for (u32 bc = b0; bc < b1; bc += 32u) {
+        const u32 e = min(b1, bc + 32u);
+        const u32 s0 = sl + (bc - b0);
+        u32 bits = 0, k = 0;
+        u32 b = bc;
+        for (; b + 4 <= e; b += 4, k += 4) {
+            const u32 s = s0 + k;
+            const vec4<T> p0 = LDS ? s_upos[s] : posh[b];
+            const vec4<T> p1 = LDS ? s_upos[s + 1] : posh[b + 1];
+            const vec4<T> p2 = LDS ? s_upos[s + 2] : posh[b + 2];
+            const vec4<T> p3 = LDS ? s_upos[s + 3] : posh[b + 3];
+            bits |= (cache_test<T, WRAP>(pa, qa, bx, p0, cand_q<T, LDS>(p0, rkc)) ? 1u : 0u) << k;
+            bits |= (cache_test<T, WRAP>(pa, qa, bx, p1, cand_q<T, LDS>(p1, rkc)) ? 2u : 0u) << k;
+            bits |= (cache_test<T, WRAP>(pa, qa, bx, p2, cand_q<T, LDS>(p2, rkc)) ? 4u : 0u) << k;
+            bits |= (cache_test<T, WRAP>(pa, qa, bx, p3, cand_q<T, LDS>(p3, rkc)) ? 8u : 0u) << k;
+        }
+        for (; b < e; ++b, ++k) {
+            const vec4<T> p = LDS ? s_upos[s0 + k] : posh[b];
+            bits |= (cache_test<T, WRAP>(pa, qa, bx, p, cand_q<T, LDS>(p, rkc)) ? 1u : 0u) << k;
+        }
+        if (!live) bits = 0;
+        while (bits) {
+            const u32 t = (u32)(__ffs(bits) - 1);
+            bits &= bits - 1u;
+            cache_append(s0 + t, out, capq, c, wbuf);
+        }
+    }
 }
 
 // Stage-2 walk, per lane: each lane takes the union leaves of its own
@@ -426,16 +482,14 @@ __device__ inline void cache_walk_lane(const vec4<T>& pa, T qa, bool live, const
                 const vec4<T> p1 = LDS ? s_upos[s + 1] : posh[b + 1];
                 const vec4<T> p2 = LDS ? s_upos[s + 2] : posh[b + 2];
                 const vec4<T> p3 = LDS ? s_upos[s + 3] : posh[b + 3];
-                cache_take<T, WRAP>(pa, qa, true, bx, p0, cand_q<T, LDS>(p0, rkc), s, out, capq, c, wbuf);
-                cache_take<T, WRAP>(pa, qa, true, bx, p1, cand_q<T, LDS>(p1, rkc), s + 1, out, capq, c, wbuf);
-                cache_take<T, WRAP>(pa, qa, true, bx, p2, cand_q<T, LDS>(p2, rkc), s + 2, out, capq, c, wbuf);
-                cache_take<T, WRAP>(pa, qa, true, bx, p3, cand_q<T, LDS>(p3, rkc), s + 3, out, capq, c, wbuf);
+                cache_take<T, LDS, WRAP>(pa, qa, bx, p0, rkc, s, out, capq, c, wbuf);
+                cache_take<T, LDS, WRAP>(pa, qa, bx, p1, rkc, s + 1, out, capq, c, wbuf);
+                cache_take<T, LDS, WRAP>(pa, qa, bx, p2, rkc, s + 2, out, capq, c, wbuf);
+                cache_take<T, LDS, WRAP>(pa, qa, bx, p3, rkc, s + 3, out, capq, c, wbuf);
             }
-            for (; b < b1; ++b) {
-                const vec4<T> p = LDS ? s_upos[sl + (b - b0)] : posh[b];
-                cache_take<T, WRAP>(pa, qa, true, bx, p, cand_q<T, LDS>(p, rkc), sl + (b - b0), out,
-                                    capq, c, wbuf);
-            }
+            for (; b < b1; ++b)
+                cache_take<T, LDS, WRAP>(pa, qa, bx, LDS ? s_upos[sl + (b - b0)] : posh[b], rkc,
+                                         sl + (b - b0), out, capq, c, wbuf);
         }
     }
 }
@@ -463,23 +517,8 @@ __device__ inline void cache_walk_wave(const vec4<T>& pa, T qa, bool live, const
             const u32 b1 = __builtin_amdgcn_readfirstlane(s_b1[j]);
             const u32 sl = __builtin_amdgcn_readfirstlane(s_slot[j]);
             if (live) tested += b1 - b0;
-            u32 b = b0;
-            for (; b + 4 <= b1; b += 4) {
-                const u32 s = sl + (b - b0);
-                const vec4<T> p0 = LDS ? s_upos[s] : posh[b];
-                const vec4<T> p1 = LDS ? s_upos[s + 1] : posh[b + 1];
-                const vec4<T> p2 = LDS ? s_upos[s + 2] : posh[b + 2];
-                const vec4<T> p3 = LDS ? s_upos[s + 3] : posh[b + 3];
-                cache_take<T, WRAP>(pa, qa, live, bx, p0, cand_q<T, LDS>(p0, rkc), s, out, capq, c, wbuf);
-                cache_take<T, WRAP>(pa, qa, live, bx, p1, cand_q<T, LDS>(p1, rkc), s + 1, out, capq, c, wbuf);
-                cache_take<T, WRAP>(pa, qa, live, bx, p2, cand_q<T, LDS>(p2, rkc), s + 2, out, capq, c, wbuf);
-                cache_take<T, WRAP>(pa, qa, live, bx, p3, cand_q<T, LDS>(p3, rkc), s + 3, out, capq, c, wbuf);
-            }
-            for (; b < b1; ++b) {
-                const vec4<T> p = LDS ? s_upos[sl + (b - b0)] : posh[b];
-                cache_take<T, WRAP>(pa, qa, live, bx, p, cand_q<T, LDS>(p, rkc), sl + (b - b0), out,
-                                    capq, c, wbuf);
-            }
+            cache_leaf<T, LDS, WRAP>(pa, qa, live, bx, rkc, b0, b1, sl, s_upos, posh, out, capq, c,
+                                     wbuf);
         }
     }
 }
@@ -497,7 +536,7 @@ __device__ inline u64 wave_or64(u64 x)
     return ((u64)hi << 32) | lo;
 }
 
-template <class T>
+template <class T, int MODE>
 __global__ void __launch_bounds__(GROUP)
 k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
               const vec4<T>* __restrict__ bhi, const u32* __restrict__ id,
@@ -507,8 +546,9 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
               const u32* __restrict__ ucnt, const u32* __restrict__ ustot, u32 capq,
               u64* __restrict__ nlist, u32* __restrict__ ncnt, u32* __restrict__ flags,
               const vec4<T>* __restrict__ glo, const vec4<T>* __restrict__ ghi,
-              const u32* __restrict__ root, u64* __restrict__ work, int mode)
+              const u32* __restrict__ root, u64* __restrict__ work)
 {
+    constexpr int mode = MODE;
     __shared__ u64 s_w[GROUP / WAVE];
     __shared__ u32 s_b0[LCHUNK];
     __shared__ u32 s_b1[LCHUNK];
@@ -587,13 +627,13 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
 #pragma unroll
         for (int w = 0; w < MW; ++w) {
             mk[w] = live ? s_mask[ta][w] : 0ull;
-            wm[w] = wave_or64(mk[w]);
+            wm[w] = mode != 1 ? wave_or64(mk[w]) : 0ull;
         }
         // walk per wave or per lane: the wave issues about (leaves of the
         // wave's mask) uniform leaf visits or (leaves of the busiest lane's
         // mask) divergent ones, the latter ~1.4x as dear per candidate
         bool uniform = mode == 2;
-        if (mode == 0) {
+        if constexpr (mode == 0) {
             u32 mine = 0, all = 0;
 #pragma unroll
             for (int w = 0; w < MW; ++w) {
@@ -602,7 +642,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
             }
             uniform = 10u * all < 14u * wave_max(mine);
         }
-        if (uniform) {
+        if (mode != 1 && uniform) {
             if (in_lds && interior)
                 cache_walk_wave<T, true, false>(pa, qa, live, bx, rkc, wm, s_b0, s_b1, s_slot,
                                                 s_upos, posh, out, capq, c, wbuf, tested);
@@ -612,7 +652,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
             else
                 cache_walk_wave<T, false, true>(pa, qa, live, bx, rkc, wm, s_b0, s_b1, s_slot,
                                                 s_upos, posh, out, capq, c, wbuf, tested);
-        } else {
+        } else if (mode != 2) {
             if (in_lds && interior)
                 cache_walk_lane<T, true, false>(pa, qa, live, bx, rkc, mk, s_b0, s_b1, s_slot,
                                                 s_upos, posh, out, capq, c, wbuf, tested);
@@ -716,9 +756,10 @@ void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* 
                         u64* work, int mode, hipStream_t st)
 {
     if (ngroups <= 0) return;
-    hipLaunchKernelGGL((k_group_cache<T>), dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, blo,
+    auto kern = mode == 2 ? k_group_cache<T, 2> : mode == 0 ? k_group_cache<T, 0> : k_group_cache<T, 1>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, blo,
                        bhi, id, xscan, n_internal, gm, inst, (T)rk, (T)rkc, cap, uleaf, uslot, ucnt, ustot,
-                       capq, nlist, ncnt, flags, glo, ghi, root, work, mode);
+                       capq, nlist, ncnt, flags, glo, ghi, root, work);
 }
 
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
