@@ -267,11 +267,11 @@ template <int BLOCK, class T, class Op> __device__ inline T block_reduce(T v, T*
 // (its leaves' particles in ascending key order) are copied from the
 // key-order arrays.  One thread per union leaf.
 // ---------------------------------------------------------------------------
-template <class T, int NF>
+template <class T, int NF, int NT = GROUP>
 __device__ inline void stage_union(const vec4<T>* const* src, vec4<T>* const* dst, const u32* id,
                                    const u32* ul, const u32* us, u32 nu, u32 c0, u32 c1)
 {
-    for (u32 j = threadIdx.x; j < nu; j += GROUP) {
+    for (u32 j = threadIdx.x; j < nu; j += NT) {
         const u32 s0 = us[j];
         const u32 leaf = ul[j];
         const u32 b0 = id[leaf], sz = id[leaf + 1] - b0;

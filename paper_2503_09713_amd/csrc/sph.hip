@@ -89,6 +89,22 @@ template <class F> __device__ inline void entries_each(const u64* my, u32 cnt, F
     }
 }
 
+// Entries [4 q0, min(cnt, 4 q1)) only (words q0 .. q1-1), single visits.
+template <class F> __device__ inline void entries_words(const u64* my, u32 cnt, u32 q0, u32 q1, F&& f)
+{
+    const u32 nq = min((cnt + 3u) >> 2, q1);
+    u64 w = q0 < nq ? my[(u64)q0 * GROUP] : 0;
+    for (u32 q = q0; q < nq; ++q) {
+        const u64 wn = (q + 1 < nq) ? my[(u64)(q + 1) * GROUP] : 0;   // prefetch
+#pragma unroll
+        for (u32 r = 0; r < 4u; ++r) {
+            const u32 sl = slot_of(w, r);
+            if (sl != SLOT_NONE) f(sl);
+        }
+        w = wn;
+    }
+}
+
 template <class F>
 __device__ inline void entries_tile(const u64* my, u32 cnt, u32& j, u32 c0, u32 c1, F&& f)
 {
@@ -315,8 +331,10 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
 // One workgroup per group: the union's position, velocity and pressure terms
 // are staged in LDS.
 // ---------------------------------------------------------------------------
+constexpr int FT = 2 * GROUP;   // force: two threads per particle, each half of its list
+
 template <class T, int CH>
-__global__ void __launch_bounds__(GROUP)
+__global__ void __launch_bounds__(FT)
 k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         const vec4<T>* __restrict__ thermo, const u32* __restrict__ id, const GroupMap gm,
         const InstDev* __restrict__ inst, SphParams P, CacheView cv, vec4<T>* __restrict__ acc,
@@ -325,8 +343,9 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     __shared__ vec4<T> s_pos[CH];
     __shared__ vec4<T> s_vel[CH];
     __shared__ vec4<T> s_thm[CH];
-    __shared__ float s_red[GROUP / WAVE];
-    __shared__ u64 s_w[GROUP / WAVE];
+    __shared__ T s_half[6][GROUP];          // second-half sums, added by the first half
+    __shared__ float s_red[FT / WAVE];
+    __shared__ u64 s_w[FT / WAVE];
     __shared__ int s_k;
     const i64 g = blockIdx.x;
     i64 beg, end;
@@ -334,7 +353,8 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     gm.range(g, beg, end, k);
     const InstDev in = inst[k];
     const Box<T> bx = make_box<T>(in);
-    const i64 a = beg + threadIdx.x;
+    const u32 lt = threadIdx.x & (GROUP - 1), half = threadIdx.x / GROUP;
+    const i64 a = beg + lt;
     const bool live = a < end;
     const i64 ai = live ? a : beg;
     const T m = (T)in.mass, hfact = (T)P.hfact;
@@ -351,9 +371,14 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     const u32 nch = (S + CH - 1) / CH;
     const u32* ul = cv.uleaf + g * cv.cap;
     const u32* us = cv.uslot + g * cv.cap;
-    const u64* my = cv.nlist + (u64)g * cv.capq * GROUP + threadIdx.x;
+    const u64* my = cv.nlist + (u64)g * cv.capq * GROUP + lt;
     const vec4<T>* src[3] = { posh, velu, thermo };
     vec4<T>* dst[3] = { s_pos, s_vel, s_thm };
+    // this thread's share of the list: words [q0, q1) (first half: the first
+    // ceil(nq/2) words), entries [e0, e1) for the tiled path
+    const u32 nq = (cnt + 3u) >> 2, qh = (nq + 1u) >> 1;
+    const u32 q0 = half ? qh : 0u, q1 = half ? nq : qh;
+    const u32 e0 = min(cnt, 4u * q0), e1 = min(cnt, 4u * q1);
     T ax = T(0), ay = T(0), az = T(0), du = T(0), lam = T(0), vmax = ca;
     u64 visited = 0, inter = 0;
     const bool wrap = !group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
@@ -400,30 +425,41 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         pair_d(sl, pa.x - pb.x, pa.y - pb.y, pa.z - pb.z, pb);
     };
     if (nch == 1) {
-        stage_union<T, 3>(src, dst, id, ul, us, nu, 0u, S);
+        stage_union<T, 3, FT>(src, dst, id, ul, us, nu, 0u, S);
         __syncthreads();
-        if (wrap) entries_each(my, cnt, pair);
-        else entries_each(my, cnt, pair_in);
+        if (wrap) entries_words(my, cnt, q0, q1, pair);
+        else entries_words(my, cnt, q0, q1, pair_in);
     } else {
-        u32 j = 0;
+        u32 j = e0;
         for (u32 ch = 0; ch < nch; ++ch) {
             const u32 c0 = ch * CH, c1 = min(S, c0 + CH);
             __syncthreads();
-            stage_union<T, 3>(src, dst, id, ul, us, nu, c0, c1);
+            stage_union<T, 3, FT>(src, dst, id, ul, us, nu, c0, c1);
             __syncthreads();
-            entries_tile(my, cnt, j, c0, c1, pair);
+            entries_tile(my, e1, j, c0, c1, pair);
         }
     }
+    // first half + second half, in that order
+    if (half) {
+        s_half[0][lt] = ax; s_half[1][lt] = ay; s_half[2][lt] = az;
+        s_half[3][lt] = du; s_half[4][lt] = lam; s_half[5][lt] = vmax;
+    }
+    __syncthreads();
+    if (!half) {
+        ax += s_half[0][lt]; ay += s_half[1][lt]; az += s_half[2][lt];
+        du += s_half[3][lt]; lam += s_half[4][lt];
+        vmax = vmax > s_half[5][lt] ? vmax : s_half[5][lt];
+    }
     if (cv.work) {   // work counters (profiling): visited entries, interacting pairs
-        const u64 t1 = block_reduce<GROUP>(visited, s_w, [](u64 x, u64 y) { return x + y; });
-        const u64 t2 = block_reduce<GROUP>(inter, s_w, [](u64 x, u64 y) { return x + y; });
+        const u64 t1 = block_reduce<FT>(visited, s_w, [](u64 x, u64 y) { return x + y; });
+        const u64 t2 = block_reduce<FT>(inter, s_w, [](u64 x, u64 y) { return x + y; });
         if (threadIdx.x == 0) {
             atomicAdd((unsigned long long*)&cv.work[2 * (g & 63)], (unsigned long long)t1);
             atomicAdd((unsigned long long*)&cv.work[2 * (g & 63) + 1], (unsigned long long)t2);
         }
     }
     float dta = __int_as_float(0x7f800000);
-    if (live) {
+    if (live && !half) {
         acc[a] = mk4<T>(ax, ay, az, du + lam);
         if (vsig_out) vsig_out[a] = vmax;
         const T am = sqrt(ax * ax + ay * ay + az * az);
@@ -432,9 +468,9 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         dta = (float)(t1 < t2 ? t1 : t2);
     }
     if (block_uniform(k, &s_k)) {
-        const float bmin = block_min<float>(dta, s_red);
+        const float bmin = block_reduce<FT>(dta, s_red, [](float x, float y) { return x < y ? x : y; });
         if (threadIdx.x == 0) atomic_min_if(&stat[k].dt_bits, __float_as_uint(bmin));
-    } else if (live) {
+    } else if (live && !half) {
         atomic_min_if(&stat[k].dt_bits, __float_as_uint(dta));
     }
 }
@@ -653,10 +689,10 @@ void launch_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id, 
 {
     if (ngroups <= 0) return;
     if (sizeof(T) == 4)
-        hipLaunchKernelGGL((k_force<T, FORCE_CH_F>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
+        hipLaunchKernelGGL((k_force<T, FORCE_CH_F>), dim3((unsigned)ngroups), dim3(FT), 0, st,
                            s.posh, s.velu, thermo, id, gm, inst, P, cv, acc, vsig, stat);
     else
-        hipLaunchKernelGGL((k_force<T, FORCE_CH_D>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
+        hipLaunchKernelGGL((k_force<T, FORCE_CH_D>), dim3((unsigned)ngroups), dim3(FT), 0, st,
                            s.posh, s.velu, thermo, id, gm, inst, P, cv, acc, vsig, stat);
 }
 
