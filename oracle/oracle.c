@@ -423,12 +423,13 @@ static void sep64(const double *L, int periodic, double xa, double ya, double za
 /* Neighbour sets in the storage precision T (App. F, object-object     */
 /* criterion with the chi-extended cache radius):                      */
 /*   dx = x_b - x_a;  periodic: once, dx -= L if dx > L/2, += L if     */
-/*   dx < -L/2;  r2 = (dx*dx + dy*dy) + dz*dz;                          */
+/*   dx < -L/2;  r2 = fma(dz, dz, fma(dy, dy, dx*dx)) (fused, each      */
+/*   rounded once: the paper fixes no rounding for this sum);           */
 /*   rc = (T)(R*chi) * max(h_a, h_b);  accept iff r2 < rc*rc.           */
 /* Indices are positions in the given arrays, listed in ascending      */
 /* order; the particle itself is included.                              */
 /* ------------------------------------------------------------------ */
-#define DEFINE_NEIGH(T, SUF)                                                    \
+#define DEFINE_NEIGH(T, SUF, FMA)                                               \
 static int crit_##SUF(const T *x, const T *y, const T *z, const T *h,          \
                       int periodic, const T *Lt, const T *Ht, T rkc,           \
                       int64_t a, int64_t b)                                    \
@@ -439,8 +440,7 @@ static int crit_##SUF(const T *x, const T *y, const T *z, const T *h,          \
         if (dy > Ht[1]) dy = dy - Lt[1]; else if (dy < -Ht[1]) dy = dy + Lt[1];\
         if (dz > Ht[2]) dz = dz - Lt[2]; else if (dz < -Ht[2]) dz = dz + Lt[2];\
     }                                                                          \
-    T xx = dx * dx, yy = dy * dy, zz = dz * dz;                                \
-    T r2 = (xx + yy) + zz;                                                     \
+    T r2 = FMA(dz, dz, FMA(dy, dy, dx * dx));                                  \
     T hm = h[a] > h[b] ? h[a] : h[b];                                          \
     T rc = rkc * hm;                                                           \
     T rc2 = rc * rc;                                                           \
@@ -511,8 +511,8 @@ int64_t orc_neigh_##SUF(int64_t n, const T *x, const T *y, const T *z,         \
     return total <= cap ? total : -total;                                      \
 }
 
-DEFINE_NEIGH(float, f32)
-DEFINE_NEIGH(double, f64)
+DEFINE_NEIGH(float, f32, fmaf)
+DEFINE_NEIGH(double, f64, fma)
 
 /* ------------------------------------------------------------------ */
 /* M4 cubic spline (Schoenberg B-spline), C_norm = 1/pi in 3D, support  */

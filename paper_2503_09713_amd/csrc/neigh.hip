@@ -363,10 +363,10 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
 constexpr int TMAX = GROUP;      // target leaves of a group: at most one per particle
 constexpr int MW = LCHUNK / 64;  // mask words per target leaf
 
-// Stage-2 candidate test in the storage type, without FMA:
-//   dx = x_b - x_a (minimum image), r2 = (dx*dx + dy*dy) + dz*dz, accept iff
-//   r2 < max(qa, qb), q = (rkc h)^2 rounded as (rkc h)(rkc h); rounding is
-//   monotone, so max(qa, qb) equals (rkc max(h_a, h_b))^2 exactly.
+// Stage-2 candidate test in the storage type:
+//   dx = x_b - x_a (minimum image), r2 = fma(dz, dz, fma(dy, dy, dx*dx)),
+//   accept iff r2 < max(qa, qb), q = (rkc h)^2 rounded as (rkc h)(rkc h);
+//   rounding is monotone, so max(qa, qb) equals (rkc max(h_a, h_b))^2 exactly.
 template <class T, bool WRAP>
 __device__ inline bool cache_test(const vec4<T>& pa, T qa, const Box<T>& bx, const vec4<T>& pb, T qb)
 {
@@ -375,8 +375,7 @@ __device__ inline bool cache_test(const vec4<T>& pa, T qa, const Box<T>& bx, con
     const T dx = min_image(pb.x - pa.x, bx.L[0], bx.halfL[0], per);
     const T dy = min_image(pb.y - pa.y, bx.L[1], bx.halfL[1], per);
     const T dz = min_image(pb.z - pa.z, bx.L[2], bx.halfL[2], per);
-    const T xx = dx * dx, yy = dy * dy, zz = dz * dz;
-    const T r2 = (xx + yy) + zz;
+    const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     return r2 < fmax(qa, qb);
 }
 
