@@ -273,7 +273,7 @@ int shsph_eval_batch(shsph_ctx *ctx, const int64_t *handles, int32_t count);
 
 /* Autotuner for batched passes: times evaluation passes of the listed
  * instances (as shsph_eval_batch: positions, velocities and u unchanged) for
- * leaf sizes n_red = 2, 3, 4 and both stage-2 walks, and keeps the fastest
+ * leaf sizes n_red = 2, 3, 4 and stage-2 walks 0, 1, 2, and keeps the fastest
  * in the context's parameters for later passes.  Neither changes results.
  * Outputs (optional): the chosen n_red and walk, and its pass time in ms. */
 int shsph_autotune(shsph_ctx *ctx, const int64_t *handles, int32_t count, int32_t *n_red,

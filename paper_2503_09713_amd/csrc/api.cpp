@@ -1487,7 +1487,7 @@ int shsph_autotune(shsph_ctx* c, const int64_t* handles, int32_t count, int32_t*
     double best = 1e300;
     int best_nr = keep.n_red, best_md = keep.stage2_mode;
     for (int nr = 2; nr <= 4; ++nr) {
-        for (int md = 1; md <= 2; ++md) {
+        for (int md = 0; md <= 2; ++md) {
             c->prm.n_red = nr;
             c->prm.stage2_mode = md;
             double t = 0;

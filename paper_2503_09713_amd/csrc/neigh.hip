@@ -367,17 +367,12 @@ constexpr int MW = LCHUNK / 64;  // mask words per target leaf
 //   dx = x_b - x_a (minimum image), r2 = fma(dz, dz, fma(dy, dy, dx*dx)),
 //   accept iff r2 < max(qa, qb), q = (rkc h)^2 rounded as (rkc h)(rkc h);
 //   rounding is monotone, so max(qa, qb) equals (rkc max(h_a, h_b))^2 exactly.
-template <class T, bool WRAP>
-__device__ inline bool cache_test(const vec4<T>& pa, T qa, const Box<T>& bx, const vec4<T>& pb, T qb)
-{
-#pragma clang fp contract(off)
-    const int per = WRAP ? bx.periodic : 0;
-    const T dx = min_image(pb.x - pa.x, bx.L[0], bx.halfL[0], per);
-    const T dy = min_image(pb.y - pa.y, bx.L[1], bx.halfL[1], per);
-    const T dz = min_image(pb.z - pa.z, bx.L[2], bx.halfL[2], per);
-    const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    return r2 < fmax(qa, qb);
-}
+// Squared radii staged in LDS (and qa) have a NaN replaced by +0: that
+// changes no decision (max(q, +0) = max(q, NaN) = q for q >= 0, and both
+// reject everything when the other operand is NaN too), and lets the FP32
+// test compare bit patterns: for r2 >= +0 or NaN and q in [+0, inf] the
+// unsigned order of the bits is the float order, a NaN r2 is rejected.
+template <class T> __device__ inline T q_clean(T q) { return q == q ? q : T(0); }
 
 template <class T, bool LDS>
 __device__ inline T cand_q(const vec4<T>& pb, T rkc)
@@ -388,71 +383,84 @@ __device__ inline T cand_q(const vec4<T>& pb, T rkc)
     return r * r;
 }
 
-// Test candidate slot s and, if accepted, pack it at once (branch-free around
-// the packing; the per-lane walk, where leaves are short).
 template <class T, bool LDS, bool WRAP>
-__device__ inline void cache_take(const vec4<T>& pa, T qa, const Box<T>& bx, const vec4<T>& pb,
-                                  T rkc, u32 s, u64* out, u32 capq, u32& c, u64& wbuf)
+__device__ inline bool cache_acc(const vec4<T>& pa, T qa, const Box<T>& bx, const vec4<T>& pb,
+                                 T rkc)
 {
-    const bool acc = cache_test<T, WRAP>(pa, qa, bx, pb, cand_q<T, LDS>(pb, rkc));
-    const u64 ins = (u64)s << (16u * (c & 3u));
-    wbuf = acc ? (wbuf | ins) : wbuf;
-    c += acc ? 1u : 0u;
-    const bool full = acc && (c & 3u) == 0u;
-    if (full) {
-        const u32 q = (c >> 2) - 1u;
-        if (q < capq) out[(u64)q * GROUP] = wbuf;
-    }
-    wbuf = full ? 0ull : wbuf;
-}
-
-// Append slot s to the lane's ELL words (written out when a word is full).
-__device__ inline void cache_append(u32 s, u64* out, u32 capq, u32& c, u64& wbuf)
-{
-    wbuf |= (u64)s << (16u * (c & 3u));
-    ++c;
-    if ((c & 3u) == 0u) {
-        const u32 q = (c >> 2) - 1u;
-        if (q < capq) out[(u64)q * GROUP] = wbuf;
-        wbuf = 0;
+#pragma clang fp contract(off)
+    const int per = WRAP ? bx.periodic : 0;
+    const T dx = min_image(pb.x - pa.x, bx.L[0], bx.halfL[0], per);
+    const T dy = min_image(pb.y - pa.y, bx.L[1], bx.halfL[1], per);
+    const T dz = min_image(pb.z - pa.z, bx.L[2], bx.halfL[2], per);
+    const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    if constexpr (LDS && sizeof(T) == 4) {
+        const u32 qa_b = __float_as_uint(qa), qb_b = __float_as_uint(pb.w);
+        return __float_as_uint(r2) < (qa_b > qb_b ? qa_b : qb_b);
+    } else {
+        return r2 < fmax(qa, cand_q<T, LDS>(pb, rkc));
     }
 }
 
-// One union leaf's particles [b0, b1) (union slots from sl) for the per-wave
-// walk: the tests set bits of a 32-candidate mask, then only the accepted
-// slots are appended, in ascending order (the packing runs only where a lane
-// accepted, not for every candidate the wave tests).
+// Accepted slots are queued per lane in LDS: each lane owns QLEN 16-bit
+// entries; every tested slot is written at the queue's fill position and the
+// position advances by the accept flag, so the packing costs no branch and no
+// variable shift per candidate.  After every group of up to four candidates
+// a completed ELL word (the first four entries) is copied to the cache and
+// the rest moves to the front.  At most 3 entries are pending before a group
+// and 7 after it.
+constexpr u32 QLEN = 8;
+constexpr u32 QSTRIDE = 12;   // u16 per lane: 8 entries + pad (24 B, 8-byte aligned)
+
+struct LaneQueue {
+    u16* e;       // this lane's entries in LDS
+    u32 pos;      // pending entries
+    u32 q;        // ELL words completed so far
+    u64* out;     // where word q goes
+};
+
+__device__ inline void queue_put(LaneQueue& lq, u32 s, bool acc)
+{
+    lq.e[lq.pos] = (u16)s;
+    lq.pos += acc ? 1u : 0u;
+}
+
+__device__ inline void queue_flush(LaneQueue& lq, u32 capq)
+{
+    if (lq.pos >= 4u) {
+        const u64 w = *(const u64*)lq.e;
+        if (lq.q < capq) *lq.out = w;
+        lq.out += GROUP;
+        ++lq.q;
+        *(u64*)lq.e = *(const u64*)(lq.e + 4);
+        lq.pos -= 4u;
+    }
+}
+
+// Tests the particles [b0, b1) of one union leaf (union slots from sl) and
+// queues the accepted ones (the per-lane walk).
 template <class T, bool LDS, bool WRAP>
-__device__ inline void cache_leaf(const vec4<T>& pa, T qa, bool live, const Box<T>& bx, T rkc,
+__device__ inline void cache_leaf(const vec4<T>& pa, T qa, const Box<T>& bx, T rkc,
                                   u32 b0, u32 b1, u32 sl, const vec4<T>* s_upos,
-                                  const vec4<T>* posh, u64* out, u32 capq, u32& c, u64& wbuf)
+                                  const vec4<T>* posh, LaneQueue& lq, u32 capq)
 {
-    for (u32 bc = b0; bc < b1; bc += 32u) {
-        const u32 e = min(b1, bc + 32u);
-        const u32 s0 = sl + (bc - b0);
-        u32 bits = 0, k = 0;
-        u32 b = bc;
-        for (; b + 4 <= e; b += 4, k += 4) {
-            const u32 s = s0 + k;
-            const vec4<T> p0 = LDS ? s_upos[s] : posh[b];
-            const vec4<T> p1 = LDS ? s_upos[s + 1] : posh[b + 1];
-            const vec4<T> p2 = LDS ? s_upos[s + 2] : posh[b + 2];
-            const vec4<T> p3 = LDS ? s_upos[s + 3] : posh[b + 3];
-            bits |= (cache_test<T, WRAP>(pa, qa, bx, p0, cand_q<T, LDS>(p0, rkc)) ? 1u : 0u) << k;
-            bits |= (cache_test<T, WRAP>(pa, qa, bx, p1, cand_q<T, LDS>(p1, rkc)) ? 2u : 0u) << k;
-            bits |= (cache_test<T, WRAP>(pa, qa, bx, p2, cand_q<T, LDS>(p2, rkc)) ? 4u : 0u) << k;
-            bits |= (cache_test<T, WRAP>(pa, qa, bx, p3, cand_q<T, LDS>(p3, rkc)) ? 8u : 0u) << k;
-        }
-        for (; b < e; ++b, ++k) {
-            const vec4<T> p = LDS ? s_upos[s0 + k] : posh[b];
-            bits |= (cache_test<T, WRAP>(pa, qa, bx, p, cand_q<T, LDS>(p, rkc)) ? 1u : 0u) << k;
-        }
-        if (!live) bits = 0;
-        while (bits) {
-            const u32 t = (u32)(__ffs(bits) - 1);
-            bits &= bits - 1u;
-            cache_append(s0 + t, out, capq, c, wbuf);
-        }
+    u32 b = b0;
+    for (; b + 4 <= b1; b += 4) {
+        const u32 s = sl + (b - b0);
+        const vec4<T> p0 = LDS ? s_upos[s] : posh[b];
+        const vec4<T> p1 = LDS ? s_upos[s + 1] : posh[b + 1];
+        const vec4<T> p2 = LDS ? s_upos[s + 2] : posh[b + 2];
+        const vec4<T> p3 = LDS ? s_upos[s + 3] : posh[b + 3];
+        queue_put(lq, s, cache_acc<T, LDS, WRAP>(pa, qa, bx, p0, rkc));
+        queue_put(lq, s + 1, cache_acc<T, LDS, WRAP>(pa, qa, bx, p1, rkc));
+        queue_put(lq, s + 2, cache_acc<T, LDS, WRAP>(pa, qa, bx, p2, rkc));
+        queue_put(lq, s + 3, cache_acc<T, LDS, WRAP>(pa, qa, bx, p3, rkc));
+        queue_flush(lq, capq);
+    }
+    for (; b < b1; ++b) {
+        const u32 s = sl + (b - b0);
+        const vec4<T> p = LDS ? s_upos[s] : posh[b];
+        queue_put(lq, s, cache_acc<T, LDS, WRAP>(pa, qa, bx, p, rkc));
+        queue_flush(lq, capq);
     }
 }
 
@@ -462,8 +470,7 @@ template <class T, bool LDS, bool WRAP>
 __device__ inline void cache_walk_lane(const vec4<T>& pa, T qa, bool live, const Box<T>& bx,
                                        T rkc, const u64* mask, const u32* s_b0, const u32* s_b1,
                                        const u32* s_slot, const vec4<T>* s_upos,
-                                       const vec4<T>* posh, u64* out, u32 capq, u32& c, u64& wbuf,
-                                       u32& tested)
+                                       const vec4<T>* posh, LaneQueue& lq, u32 capq, u32& tested)
 {
     if (!live) return;
 #pragma unroll
@@ -472,24 +479,24 @@ __device__ inline void cache_walk_lane(const vec4<T>& pa, T qa, bool live, const
         while (cur) {
             const u32 j = (u32)(w * 64) + (u32)(__ffsll((unsigned long long)cur) - 1);
             cur &= cur - 1;
-            const u32 b0 = s_b0[j], b1 = s_b1[j], sl = s_slot[j];
+            const u32 b0 = s_b0[j], b1 = s_b1[j];
             tested += b1 - b0;
-            u32 b = b0;
-            for (; b + 4 <= b1; b += 4) {
-                const u32 s = sl + (b - b0);
-                const vec4<T> p0 = LDS ? s_upos[s] : posh[b];
-                const vec4<T> p1 = LDS ? s_upos[s + 1] : posh[b + 1];
-                const vec4<T> p2 = LDS ? s_upos[s + 2] : posh[b + 2];
-                const vec4<T> p3 = LDS ? s_upos[s + 3] : posh[b + 3];
-                cache_take<T, LDS, WRAP>(pa, qa, bx, p0, rkc, s, out, capq, c, wbuf);
-                cache_take<T, LDS, WRAP>(pa, qa, bx, p1, rkc, s + 1, out, capq, c, wbuf);
-                cache_take<T, LDS, WRAP>(pa, qa, bx, p2, rkc, s + 2, out, capq, c, wbuf);
-                cache_take<T, LDS, WRAP>(pa, qa, bx, p3, rkc, s + 3, out, capq, c, wbuf);
-            }
-            for (; b < b1; ++b)
-                cache_take<T, LDS, WRAP>(pa, qa, bx, LDS ? s_upos[sl + (b - b0)] : posh[b], rkc,
-                                         sl + (b - b0), out, capq, c, wbuf);
+            cache_leaf<T, LDS, WRAP>(pa, qa, bx, rkc, b0, b1, s_slot[j], s_upos, posh, lq, capq);
         }
+    }
+}
+
+// Appends one accepted slot (the per-wave walk's accept path, taken only for
+// accepted candidates): at most 3 entries are pending between calls.
+__device__ inline void queue_append(LaneQueue& lq, u32 s, u32 capq)
+{
+    lq.e[lq.pos] = (u16)s;
+    if (++lq.pos == 4u) {
+        const u64 w = *(const u64*)lq.e;
+        if (lq.q < capq) *lq.out = w;
+        lq.out += GROUP;
+        ++lq.q;
+        lq.pos = 0u;
     }
 }
 
@@ -498,13 +505,14 @@ __device__ inline void cache_walk_lane(const vec4<T>& pa, T qa, bool live, const
 // every particle of them: the criterion is exact, so a lane never accepts a
 // particle its own mask would have skipped, and its slots stay ascending.
 // Uniform control and broadcast LDS reads; worth it when the lanes' candidate
-// sets overlap (the wave's union is not much larger than one lane's).
+// sets overlap (the wave's union is not much larger than one lane's).  Most
+// of a lane's tests here are rejections, so a leaf's tests set bits of a
+// 32-candidate mask first and only the accepted slots are queued.
 template <class T, bool LDS, bool WRAP>
 __device__ inline void cache_walk_wave(const vec4<T>& pa, T qa, bool live, const Box<T>& bx, T rkc,
                                        const u64* wmask, const u32* s_b0, const u32* s_b1,
                                        const u32* s_slot, const vec4<T>* s_upos,
-                                       const vec4<T>* posh, u64* out, u32 capq, u32& c, u64& wbuf,
-                                       u32& tested)
+                                       const vec4<T>* posh, LaneQueue& lq, u32 capq, u32& tested)
 {
 #pragma unroll
     for (int w = 0; w < MW; ++w) {
@@ -516,8 +524,33 @@ __device__ inline void cache_walk_wave(const vec4<T>& pa, T qa, bool live, const
             const u32 b1 = __builtin_amdgcn_readfirstlane(s_b1[j]);
             const u32 sl = __builtin_amdgcn_readfirstlane(s_slot[j]);
             if (live) tested += b1 - b0;
-            cache_leaf<T, LDS, WRAP>(pa, qa, live, bx, rkc, b0, b1, sl, s_upos, posh, out, capq, c,
-                                     wbuf);
+            for (u32 bc = b0; bc < b1; bc += 32u) {
+                const u32 e = min(b1, bc + 32u);
+                const u32 s0 = sl + (bc - b0);
+                u32 bits = 0, k = 0;
+                u32 b = bc;
+                for (; b + 4 <= e; b += 4, k += 4) {
+                    const u32 s = s0 + k;
+                    const vec4<T> p0 = LDS ? s_upos[s] : posh[b];
+                    const vec4<T> p1 = LDS ? s_upos[s + 1] : posh[b + 1];
+                    const vec4<T> p2 = LDS ? s_upos[s + 2] : posh[b + 2];
+                    const vec4<T> p3 = LDS ? s_upos[s + 3] : posh[b + 3];
+                    bits |= (cache_acc<T, LDS, WRAP>(pa, qa, bx, p0, rkc) ? 1u : 0u) << k;
+                    bits |= (cache_acc<T, LDS, WRAP>(pa, qa, bx, p1, rkc) ? 2u : 0u) << k;
+                    bits |= (cache_acc<T, LDS, WRAP>(pa, qa, bx, p2, rkc) ? 4u : 0u) << k;
+                    bits |= (cache_acc<T, LDS, WRAP>(pa, qa, bx, p3, rkc) ? 8u : 0u) << k;
+                }
+                for (; b < e; ++b, ++k) {
+                    const vec4<T> p = LDS ? s_upos[s0 + k] : posh[b];
+                    bits |= (cache_acc<T, LDS, WRAP>(pa, qa, bx, p, rkc) ? 1u : 0u) << k;
+                }
+                if (!live) bits = 0;
+                while (bits) {
+                    const u32 t = (u32)(__ffs(bits) - 1);
+                    bits &= bits - 1u;
+                    queue_append(lq, s0 + t, capq);
+                }
+            }
         }
     }
 }
@@ -552,8 +585,13 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     __shared__ u32 s_b0[LCHUNK];
     __shared__ u32 s_b1[LCHUNK];
     __shared__ u32 s_slot[LCHUNK];
-    __shared__ vec4<T> s_lo[LCHUNK];
-    __shared__ vec4<T> s_hi[LCHUNK];
+    // union-leaf boxes of the chunk (prune only); the queued walk reuses the
+    // space for the lanes' queues (pending entries carried over chunks in a
+    // register)
+    __shared__ vec4<T> s_box[2 * LCHUNK];
+    vec4<T>* const s_lo = s_box;
+    vec4<T>* const s_hi = s_box + LCHUNK;
+    static_assert(GROUP * QSTRIDE * sizeof(u16) <= sizeof(s_box), "queues do not fit");
     __shared__ vec4<T> s_tlo[TMAX];
     __shared__ vec4<T> s_thi[TMAX];
     __shared__ u64 s_mask[TMAX][MW];
@@ -588,18 +626,19 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         for (u32 t = threadIdx.x; t < S; t += GROUP) {   // h -> (rkc h)^2
 #pragma clang fp contract(off)
             const T r = rkc * s_upos[t].w;
-            s_upos[t].w = r * r;
+            s_upos[t].w = q_clean(r * r);
         }
     }
     T qa;
     {
 #pragma clang fp contract(off)
         const T r = rkc * pa.w;
-        qa = r * r;
+        qa = q_clean(r * r);
     }
     u64* out = nlist + (u64)g * capq * GROUP + threadIdx.x;
-    u32 c = 0, tested = 0;
-    u64 wbuf = 0, boxtests = 0;
+    u32 tested = 0;
+    u64 wbuf = 0, boxtests = 0;   // wbuf: the queue's pending entries between chunks
+    LaneQueue lq{(u16*)s_box + threadIdx.x * QSTRIDE, 0u, 0u, out};
     for (u32 c0 = 0; c0 < nu; c0 += LCHUNK) {
         const u32 c1 = min(nu, c0 + LCHUNK);
         const u32 nl = c1 - c0;
@@ -630,7 +669,8 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         }
         // walk per wave or per lane: the wave issues about (leaves of the
         // wave's mask) uniform leaf visits or (leaves of the busiest lane's
-        // mask) divergent ones, the latter ~1.4x as dear per candidate
+        // mask) divergent ones; weighted 1 : 1.4 this picks the faster walk
+        // on lattices (per lane) and on clustered instances (per wave)
         bool uniform = mode == 2;
         if constexpr (mode == 0) {
             u32 mine = 0, all = 0;
@@ -641,28 +681,31 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
             }
             uniform = 10u * all < 14u * wave_max(mine);
         }
+        if (lq.pos) *(u64*)lq.e = wbuf;   // pending entries
         if (mode != 1 && uniform) {
             if (in_lds && interior)
                 cache_walk_wave<T, true, false>(pa, qa, live, bx, rkc, wm, s_b0, s_b1, s_slot,
-                                                s_upos, posh, out, capq, c, wbuf, tested);
+                                                s_upos, posh, lq, capq, tested);
             else if (in_lds)
                 cache_walk_wave<T, true, true>(pa, qa, live, bx, rkc, wm, s_b0, s_b1, s_slot,
-                                               s_upos, posh, out, capq, c, wbuf, tested);
+                                               s_upos, posh, lq, capq, tested);
             else
                 cache_walk_wave<T, false, true>(pa, qa, live, bx, rkc, wm, s_b0, s_b1, s_slot,
-                                                s_upos, posh, out, capq, c, wbuf, tested);
+                                                s_upos, posh, lq, capq, tested);
         } else if (mode != 2) {
             if (in_lds && interior)
                 cache_walk_lane<T, true, false>(pa, qa, live, bx, rkc, mk, s_b0, s_b1, s_slot,
-                                                s_upos, posh, out, capq, c, wbuf, tested);
+                                                s_upos, posh, lq, capq, tested);
             else if (in_lds)
                 cache_walk_lane<T, true, true>(pa, qa, live, bx, rkc, mk, s_b0, s_b1, s_slot,
-                                               s_upos, posh, out, capq, c, wbuf, tested);
+                                               s_upos, posh, lq, capq, tested);
             else
                 cache_walk_lane<T, false, true>(pa, qa, live, bx, rkc, mk, s_b0, s_b1, s_slot,
-                                                s_upos, posh, out, capq, c, wbuf, tested);
+                                                s_upos, posh, lq, capq, tested);
         }
+        wbuf = lq.pos ? *(const u64*)lq.e : 0ull;
     }
+    const u32 c = 4u * lq.q + lq.pos;
     if (live) {
         if (c & 3u) {
             for (u32 r = c & 3u; r < 4u; ++r) wbuf |= (u64)SLOT_NONE << (16u * r);

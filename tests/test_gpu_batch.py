@@ -266,10 +266,11 @@ def test_batch_flags_instance_that_does_not_converge(torch_cuda):
 
 
 def test_leaf_size_and_walk_do_not_change_results(torch_cuda):
-    _say("[batch] n_red 2 / per-lane walk vs n_red 4 / per-wave walk: bit-exact; autotuner")
+    _say("[batch] leaf size and stage-2 walk: bit-exact; autotuner")
     ps = _mix()
     got = []
-    for kw in (dict(n_red=2, stage2_mode=1), dict(n_red=4, stage2_mode=2)):
+    for kw in (dict(n_red=2, stage2_mode=1), dict(n_red=4, stage2_mode=2),
+               dict(n_red=3, stage2_mode=0)):
         ctx = shsph.Context(0, **kw)
         hs = [ctx.instance_create(shsph.ParticleSet.from_particles(p)) for p in ps]
         ctx.step_batch(hs)
@@ -278,10 +279,11 @@ def test_leaf_size_and_walk_do_not_change_results(torch_cuda):
         ctx.close()
     for k in range(len(ps)):
         _same(got[0][k], got[1][k], f"instance {k}")
+        _same(got[0][k], got[2][k], f"instance {k}")
     ctx = shsph.Context(0)
     hs = [ctx.instance_create(shsph.ParticleSet.from_particles(p)) for p in ps]
     t = ctx.autotune(hs)
-    assert t["n_red"] in (2, 3, 4) and t["stage2_mode"] in (1, 2) and t["pass_ms"] > 0
+    assert t["n_red"] in (2, 3, 4) and t["stage2_mode"] in (0, 1, 2) and t["pass_ms"] > 0
     ctx.step_batch(hs)
     ctx.close()
 

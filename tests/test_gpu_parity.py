@@ -138,19 +138,32 @@ def test_stage1_paths(torch_cuda, name, make, n_red):
     assert (unions["leaf"] <= unions["wave"]).all() and (unions["leaf"] <= unions["box"]).all()
 
 
-@pytest.mark.parametrize("mode", [1, 2])
-@pytest.mark.parametrize("name,make", [
-    ("lattice16_f32", lambda: gen.lattice(16, gen.SEEDS["tiny"], dtype=np.float32)),
-    ("plummer5000_f32", lambda: gen.plummer(5000, 6, dtype=np.float32)),
-], ids=["lattice16_f32", "plummer5000_f32"])
-def test_stage2_walks(torch_cuda, name, make, mode):
-    """Stage 2 forced to the per-lane (1) or per-wave (2) walk: same cache."""
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("name,make,n_red", [
+    ("lattice16_f32", lambda: gen.lattice(16, gen.SEEDS["tiny"], dtype=np.float32), 3),
+    ("lattice16_f64", lambda: gen.lattice(16, gen.SEEDS["tiny"], dtype=np.float64), 3),
+    ("plummer5000_f32", lambda: gen.plummer(5000, 6, dtype=np.float32), 3),
+    ("lattice21_f32_nred0", lambda: gen.lattice(21, 5, dtype=np.float32), 0),
+], ids=["lattice16_f32", "lattice16_f64", "plummer5000_f32", "lattice21_f32_nred0"])
+def test_stage2_walks(torch_cuda, name, make, n_red, mode):
+    """Stage 2 forced to each walk: per lane (1), per wave (2) or chosen per
+    wave (0): the same cache.  One-particle
+    leaves (n_red 0) give unions of more than one LDS chunk of leaves, the
+    sphere's core unions too large to stage in LDS, and the periodic
+    lattices groups on the box faces (minimum image)."""
     _say(f"[tree] {name}: stage-2 walk {mode}")
     p = make()
-    ctx = _ctx(torch_cuda, n_red=3, stage2_mode=mode)
+    ctx = _ctx(torch_cuda, n_red=n_red, stage2_mode=mode)
     ctx.build_tree(_upload(p, torch_cuda))
-    check_tree(ctx, p, 3)
+    ex = check_tree(ctx, p, n_red)
     ctx.close()
+    go, gl, sizes = ex["group_off"].astype(np.int64), ex["group_leaves"], np.diff(ex["id"])
+    leaves = np.diff(go)
+    parts = np.array([sizes[gl[go[g]:go[g + 1]]].sum() for g in range(len(leaves))])
+    if name == "plummer5000_f32":
+        assert parts.max() > 1536 and leaves.max() > 256   # HBM-read and multi-chunk unions
+    if name == "lattice21_f32_nred0":
+        assert leaves.max() > 256
 
 
 def test_tree_with_duplicate_positions(torch_cuda):
