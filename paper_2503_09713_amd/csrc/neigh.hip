@@ -54,15 +54,32 @@ template <class T> __device__ inline T abs_inflation(const Box<T>& bx)
 }
 
 // Box-box prune with the inflated radius; explicit roundings keep it
-// identical wherever it is evaluated.
-template <class T>
+// identical wherever it is evaluated.  WRAP = false drops the periodic images
+// (exact for boxes far enough from the faces, see prune_interior).
+template <class T, bool WRAP = true>
 __device__ inline bool box_hit(const vec4<T>& al, const vec4<T>& ah, const vec4<T>& bl,
                                const vec4<T>& bh, T rk, T eps_abs, const Box<T>& bx)
 {
     const T r = rk * fmax(al.w, bl.w) * (T(1) + Inflate<T>::rel) + eps_abs;
-    return gap1<T>(al.x, ah.x, bl.x, bh.x, bx.L[0], bx.periodic) <= r &&
-           gap1<T>(al.y, ah.y, bl.y, bh.y, bx.L[1], bx.periodic) <= r &&
-           gap1<T>(al.z, ah.z, bl.z, bh.z, bx.L[2], bx.periodic) <= r;
+    const int per = WRAP ? bx.periodic : 0;
+    return gap1<T>(al.x, ah.x, bl.x, bh.x, bx.L[0], per) <= r &&
+           gap1<T>(al.y, ah.y, bl.y, bh.y, bx.L[1], per) <= r &&
+           gap1<T>(al.z, ah.z, bl.z, bh.z, bx.L[2], per) <= r;
+}
+
+// A box at least r_all = rk h_max(all) 1.001 + 2 eps_abs + 1e-5 (Lx+Ly+Lz)
+// inside every face: any periodic image of any box of the domain lies at a
+// gap of at least r_all from it along the shifted axis, more than the prune
+// radius of any pair, so per axis the image gaps never decide box_hit and it
+// equals its version without images.
+template <class T>
+__device__ inline bool prune_interior(const vec4<T>& l, const vec4<T>& h, T hmax_all, T rk,
+                                      T eps_abs, const Box<T>& bx)
+{
+    if (!bx.periodic) return true;
+    const T r = rk * hmax_all * T(1.001) + T(2) * eps_abs + T(1e-5) * (bx.L[0] + bx.L[1] + bx.L[2]);
+    return l.x - r > bx.lo[0] && l.y - r > bx.lo[1] && l.z - r > bx.lo[2] &&
+           h.x + r < bx.hi[0] && h.y + r < bx.hi[1] && h.z + r < bx.hi[2];
 }
 
 // Tight box and h_max of each group (one workgroup per group).
@@ -465,24 +482,29 @@ __device__ inline void cache_leaf(const vec4<T>& pa, T qa, const Box<T>& bx, T r
 }
 
 // Stage-2 walk, per lane: each lane takes the union leaves of its own
-// target leaf's mask (lanes diverge; every issued test is one the lane needs).
+// target leaf's mask row (in LDS), one leaf per iteration across all the
+// row's words, so lanes whose marked leaves fall in different words still
+// visit in step (lanes diverge only in where their leaves are).
 template <class T, bool LDS, bool WRAP>
 __device__ inline void cache_walk_lane(const vec4<T>& pa, T qa, bool live, const Box<T>& bx,
-                                       T rkc, const u64* mask, const u32* s_b0, const u32* s_b1,
+                                       T rkc, const u64* mrow, const u32* s_b0, const u32* s_b1,
                                        const u32* s_slot, const vec4<T>* s_upos,
                                        const vec4<T>* posh, LaneQueue& lq, u32 capq, u32& tested)
 {
     if (!live) return;
-#pragma unroll
-    for (int w = 0; w < MW; ++w) {
-        u64 cur = mask[w];
-        while (cur) {
-            const u32 j = (u32)(w * 64) + (u32)(__ffsll((unsigned long long)cur) - 1);
-            cur &= cur - 1;
-            const u32 b0 = s_b0[j], b1 = s_b1[j];
-            tested += b1 - b0;
-            cache_leaf<T, LDS, WRAP>(pa, qa, bx, rkc, b0, b1, s_slot[j], s_upos, posh, lq, capq);
+    u32 wb = 0;                 // 64 x (current word)
+    u64 cur = mrow[0];
+    for (;;) {
+        while (cur == 0ull && wb < (u32)(MW - 1) * 64u) {
+            wb += 64u;
+            cur = mrow[wb >> 6];
         }
+        if (cur == 0ull) break;
+        const u32 j = wb + (u32)(__ffsll((unsigned long long)cur) - 1);
+        cur &= cur - 1;
+        const u32 b0 = s_b0[j], b1 = s_b1[j];
+        tested += b1 - b0;
+        cache_leaf<T, LDS, WRAP>(pa, qa, bx, rkc, b0, b1, s_slot[j], s_upos, posh, lq, capq);
     }
 }
 
@@ -610,14 +632,20 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     const u32 S = ustot[g];
     const bool in_lds = S <= (u32)UCH;
     const bool interior = group_interior<T>(glo[g], ghi[g], blo[root[k]].w, rk, bx);
+    static_assert(LCHUNK == GROUP && MW == GROUP / WAVE, "prune: one mask word per wave");
     // target leaves: the leaves holding slots beg .. end-1
     const u32 t0 = xscan[beg + 1] - 1u;
     const u32 nt = xscan[end] - t0;              // <= GROUP
     const u32 ta = xscan[ai + 1] - 1u - t0;
+    const T hmax_all = blo[root[k]].w;
+    bool t_in = true;
     for (u32 t = threadIdx.x; t < nt; t += GROUP) {
-        s_tlo[t] = blo[n_internal + t0 + t];
-        s_thi[t] = bhi[n_internal + t0 + t];
+        const vec4<T> l = blo[n_internal + t0 + t], h = bhi[n_internal + t0 + t];
+        s_tlo[t] = l;
+        s_thi[t] = h;
+        t_in = t_in && prune_interior<T>(l, h, hmax_all, rk, eps_abs, bx);
     }
+    const bool prune_wrap = __syncthreads_or(!t_in);
     if (in_lds) {
         const vec4<T>* src[1] = { posh };
         vec4<T>* dst[1] = { s_upos };
@@ -652,19 +680,30 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
             s_lo[j - c0] = blo[n_internal + leaf];
             s_hi[j - c0] = bhi[n_internal + leaf];
         }
-        for (u32 q = threadIdx.x; q < nt * MW; q += GROUP) (&s_mask[0][0])[q] = 0;
         __syncthreads();
-        // target leaf x union leaf prune, shared by the lanes of each target leaf
-        for (u32 q = threadIdx.x; q < nt * nl; q += GROUP) {
-            const u32 t = q / nl, j = q - t * nl;
-            if (box_hit<T>(s_tlo[t], s_thi[t], s_lo[j], s_hi[j], rk, eps_abs, bx))
-                atomicOr((unsigned long long*)&s_mask[t][j >> 6], 1ull << (j & 63));
+        // target leaf x union leaf prune, shared by the lanes of each target
+        // leaf: wave w owns mask word w (union leaves 64w .. 64w+63 of the
+        // chunk, one per lane) and sweeps the target leaves
+        {
+            const u32 wv = threadIdx.x / WAVE, j = threadIdx.x;
+            if (wv * WAVE >= nl) {
+                for (u32 t = __lane_id(); t < nt; t += WAVE) s_mask[t][wv] = 0ull;
+            } else {
+                const bool jv = j < nl;
+                const vec4<T> bl = s_lo[jv ? j : 0], bh = s_hi[jv ? j : 0];
+                for (u32 t = 0; t < nt; ++t) {
+                    const bool hit = jv && (prune_wrap ? box_hit<T, true>(s_tlo[t], s_thi[t], bl, bh, rk, eps_abs, bx)
+                                                       : box_hit<T, false>(s_tlo[t], s_thi[t], bl, bh, rk, eps_abs, bx));
+                    const u64 word = __ballot(hit);
+                    if (__lane_id() == 0) s_mask[t][wv] = word;
+                }
+            }
         }
         __syncthreads();
         u64 mk[MW], wm[MW];
 #pragma unroll
         for (int w = 0; w < MW; ++w) {
-            mk[w] = live ? s_mask[ta][w] : 0ull;
+            mk[w] = live && mode != 1 ? s_mask[ta][w] : 0ull;
             wm[w] = mode != 1 ? wave_or64(mk[w]) : 0ull;
         }
         // walk per wave or per lane: the wave issues about (leaves of the
@@ -694,14 +733,14 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
                                                 s_upos, posh, lq, capq, tested);
         } else if (mode != 2) {
             if (in_lds && interior)
-                cache_walk_lane<T, true, false>(pa, qa, live, bx, rkc, mk, s_b0, s_b1, s_slot,
-                                                s_upos, posh, lq, capq, tested);
+                cache_walk_lane<T, true, false>(pa, qa, live, bx, rkc, s_mask[ta], s_b0, s_b1,
+                                                s_slot, s_upos, posh, lq, capq, tested);
             else if (in_lds)
-                cache_walk_lane<T, true, true>(pa, qa, live, bx, rkc, mk, s_b0, s_b1, s_slot,
-                                               s_upos, posh, lq, capq, tested);
+                cache_walk_lane<T, true, true>(pa, qa, live, bx, rkc, s_mask[ta], s_b0, s_b1,
+                                               s_slot, s_upos, posh, lq, capq, tested);
             else
-                cache_walk_lane<T, false, true>(pa, qa, live, bx, rkc, mk, s_b0, s_b1, s_slot,
-                                                s_upos, posh, lq, capq, tested);
+                cache_walk_lane<T, false, true>(pa, qa, live, bx, rkc, s_mask[ta], s_b0, s_b1,
+                                                s_slot, s_upos, posh, lq, capq, tested);
         }
         wbuf = lq.pos ? *(const u64*)lq.e : 0ull;
     }
