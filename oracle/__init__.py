@@ -66,7 +66,7 @@ def lib():
     for suf, fp in (("f32", f32p), ("f64", f64p)):
         fn = getattr(L, "orc_neigh_" + suf)
         fn.restype = i64
-        fn.argtypes = [i64, fp, fp, fp, fp, f64p, f64p, i32, f64, i32, u64p, u32p, i64]
+        fn.argtypes = [i64, fp, fp, fp, fp, f64p, f64p, i32, f64, i32, i64, vp, u64p, u32p, i64]
     L.orc_m4_f.restype = f64
     L.orc_m4_f.argtypes = [f64]
     L.orc_m4_df.restype = f64
@@ -193,9 +193,11 @@ def tight_boxes(ids, tree, xs, ys, zs, hs):
     return bmin, bmax, hmax
 
 
-def neighbours(x, y, z, h, lo, hi, periodic: bool, r_kern_chi: float, brute=False):
+def neighbours(x, y, z, h, lo, hi, periodic: bool, r_kern_chi: float, brute=False,
+               targets=None):
     """Neighbour sets decided in the storage precision of x (App. F):
-    returns (offsets[n+1] uint64, list uint32), ascending, self included."""
+    returns (offsets[nt+1] uint64, list uint32), ascending, self included,
+    for the targets (default: every particle)."""
     x = np.ascontiguousarray(x)
     T = x.dtype
     if T not in (np.float32, np.float64):
@@ -204,12 +206,15 @@ def neighbours(x, y, z, h, lo, hi, periodic: bool, r_kern_chi: float, brute=Fals
     arrs = [np.ascontiguousarray(a, dtype=T) for a in (x, y, z, h)]
     lo, hi = _box(lo, hi)
     n = x.shape[0]
-    off = np.zeros(n + 1, np.uint64)
-    cap = max(n * 64, 1)
+    t, tp = _targets(targets)
+    nt = n if t is None else t.shape[0]
+    off = np.zeros(nt + 1, np.uint64)
+    cap = max(nt * 64, 1)
     fn = getattr(lib(), "orc_neigh_" + suf)
     while True:
         lst = np.zeros(cap, np.uint32)
-        tot = fn(n, *arrs, lo, hi, int(bool(periodic)), float(r_kern_chi), int(brute), off, lst, cap)
+        tot = fn(n, *arrs, lo, hi, int(bool(periodic)), float(r_kern_chi), int(brute), nt, tp,
+                 off, lst, cap)
         if tot >= 0:
             return off, lst[:tot].copy()
         cap = -tot

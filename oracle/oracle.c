@@ -463,8 +463,11 @@ static void visit_##SUF(void *u, int64_t b)                                    \
 int64_t orc_neigh_##SUF(int64_t n, const T *x, const T *y, const T *z,         \
                         const T *h, const double *lo, const double *hi,        \
                         int periodic, double r_kern_chi, int brute,            \
+                        int64_t nt, const int64_t *targets,                    \
                         uint64_t *offsets, uint32_t *list, int64_t cap)        \
 {                                                                              \
+    /* targets == NULL: every particle (nt = n); else the listed ones */       \
+    if (!targets) nt = n;                                                      \
     T Lt[3], Ht[3];                                                            \
     double lo_d[3], hi_d[3];                                                   \
     for (int d = 0; d < 3; ++d) {                                              \
@@ -483,10 +486,11 @@ int64_t orc_neigh_##SUF(int64_t n, const T *x, const T *y, const T *z,         \
     double rsearch = r_kern_chi * hmax * 1.001 + 1e-12;                        \
     grid_t g;                                                                  \
     grid_build(&g, n, xd, yd, zd, lo_d, hi_d, periodic, brute ? 1e300 : rsearch);\
-    int64_t *cnt = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));\
-    int64_t **lists = (int64_t **)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t *));\
+    int64_t *cnt = (int64_t *)calloc((size_t)(nt > 0 ? nt : 1), sizeof(int64_t));\
+    int64_t **lists = (int64_t **)calloc((size_t)(nt > 0 ? nt : 1), sizeof(int64_t *));\
     _Pragma("omp parallel for schedule(dynamic, 256)")                         \
-    for (int64_t a = 0; a < n; ++a) {                                          \
+    for (int64_t t = 0; t < nt; ++t) {                                         \
+        const int64_t a = targets ? targets[t] : t;                            \
         nctx_##SUF c = { NULL, 0, 0, x, y, z, h, periodic, Lt, Ht, rkc, a };   \
         if (brute) { for (int64_t b = 0; b < n; ++b) visit_##SUF(&c, b); }     \
         else grid_visit(&g, xd[a], yd[a], zd[a], rsearch, visit_##SUF, &c);    \
@@ -496,17 +500,17 @@ int64_t orc_neigh_##SUF(int64_t n, const T *x, const T *y, const T *z,         \
             while (j >= 0 && c.buf[j] > v) { c.buf[j + 1] = c.buf[j]; --j; }   \
             c.buf[j + 1] = v;                                                  \
         }                                                                      \
-        cnt[a] = c.cnt; lists[a] = c.buf;                                      \
+        cnt[t] = c.cnt; lists[t] = c.buf;                                      \
     }                                                                          \
     int64_t total = 0;                                                         \
-    for (int64_t a = 0; a < n; ++a) { offsets[a] = (uint64_t)total; total += cnt[a]; }\
-    offsets[n] = (uint64_t)total;                                              \
+    for (int64_t t = 0; t < nt; ++t) { offsets[t] = (uint64_t)total; total += cnt[t]; }\
+    offsets[nt] = (uint64_t)total;                                             \
     if (total <= cap) {                                                        \
-        for (int64_t a = 0; a < n; ++a)                                        \
-            for (int64_t k = 0; k < cnt[a]; ++k)                               \
-                list[offsets[a] + k] = (uint32_t)lists[a][k];                  \
+        for (int64_t t = 0; t < nt; ++t)                                       \
+            for (int64_t k = 0; k < cnt[t]; ++k)                               \
+                list[offsets[t] + k] = (uint32_t)lists[t][k];                  \
     }                                                                          \
-    for (int64_t a = 0; a < n; ++a) free(lists[a]);                            \
+    for (int64_t t = 0; t < nt; ++t) free(lists[t]);                           \
     free(lists); free(cnt); free(xd); free(yd); free(zd); grid_free(&g);       \
     return total <= cap ? total : -total;                                      \
 }

@@ -86,7 +86,7 @@ struct shsph_ctx {
     int xi_sel = 0;         // which mask buffer holds the final keep mask
 
     // device buffers (grown on demand, never shrunk)
-    Buf keys[2], vals[2], hist, hist_scan, scan_tmp, bbox;
+    Buf keys[2], vals[2], hist, scan_tmp, bbox;          // hist: radix sort state
     Buf posh, velu, vhalf, hn, hcache, pid_s, thermo, omega, acc, vsig, status;
     Buf xi[2], xscan, id, mu_leaf;
     Buf lchild, rchild, endrange, lflag, rflag, child, parent, arrive, blo, bhi;
@@ -120,6 +120,9 @@ struct shsph_ctx {
 namespace {
 
 const size_t PINNED_BYTES = 1 << 20;      // read-back staging
+// device flag words: 0..3 tree traversal / cache capacity (reset per cache
+// build), FLAG_SORT = radix sort look-back overrun
+constexpr int FLAG_WORDS = 8, FLAG_SORT = 4;
 const size_t UPLOAD_BYTES = 1 << 20;      // upload staging (instance tables), after it
 const int MAX_BATCH = 2048;           // instances per batched pass (stats fit the staging)
 
@@ -391,10 +394,12 @@ template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const d
     TRY(ensure(c, c->keys[1], n * sizeof(u64)));
     TRY(ensure(c, c->vals[0], n * sizeof(u32)));
     TRY(ensure(c, c->vals[1], n * sizeof(u32)));
-    const size_t nh = radix_hist_count(n);
-    TRY(ensure(c, c->hist, nh * sizeof(u32)));
-    TRY(ensure(c, c->hist_scan, (nh + 1) * sizeof(u32)));
-    TRY(ensure(c, c->scan_tmp, scan_tmp_bytes(std::max<i64>(n + 1, (i64)nh + 1))));
+    TRY(ensure(c, c->hist, radix_state_words(n, c->ninst) * sizeof(u32)));
+    TRY(ensure(c, c->scan_tmp, scan_tmp_bytes(n + 1)));
+    if (!c->flags.p) {
+        TRY(ensure(c, c->flags, FLAG_WORDS * sizeof(u32)));
+        launch_fill_u32(P<u32>(c->flags), FLAG_WORDS, 0u, st);
+    }
     TRY(ensure(c, c->posh, n * sizeof(vec4<T>)));
     TRY(ensure(c, c->velu, n * sizeof(vec4<T>)));
     if (step) TRY(ensure(c, c->vhalf, n * sizeof(vec4<T>)));
@@ -423,8 +428,9 @@ template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const d
     prof_begin(c, S_SORT);
     const int sel = radix_sort_pairs(P<u64>(c->keys[0]), P<u32>(c->vals[0]), P<u64>(c->keys[1]),
                                      P<u32>(c->vals[1]), n, 63, poff, ninst, P<u32>(c->hist),
-                                     P<u32>(c->hist_scan), c->scan_tmp.p, st);
+                                     P<u32>(c->flags) + FLAG_SORT, st);
     prof_end(c);
+    if (sel < 0) return fail(c, SHSPH_ECAPACITY, "more than 2^30 - 2 particles in one pass");
     c->vals_sel = sel;
     const u64* mu = P<u64>(c->keys[sel]);
     const u32* eps = P<u32>(c->vals[sel]);
@@ -495,7 +501,6 @@ template <class T> int build_caches(shsph_ctx* c)
     TRY(ensure(c, c->rec, nrc * sizeof(u32)));
     TRY(ensure(c, c->nrec, (nbb + 1) * sizeof(u32)));
     TRY(ensure(c, c->rscan, (nbb + 1) * sizeof(u32)));
-    TRY(ensure(c, c->flags, 4 * sizeof(u32)));
     TRY(ensure(c, c->glo, G * sizeof(vec4<T>)));
     TRY(ensure(c, c->ghi, G * sizeof(vec4<T>)));
     TRY(ensure(c, c->ucnt, G * sizeof(u32)));
@@ -538,18 +543,23 @@ template <class T> int build_caches(shsph_ctx* c)
         prof_end(c);
         TRY(check_launch(c, "stage2"));
         launch_root_hmax<T>(P<vec4<T>>(c->blo), P<u32>(c->root_d), ninst, P<double>(c->rhmax_d), st);
-        HIPTRY(c, hipMemcpyAsync(c->pinned, c->flags.p, 4 * sizeof(u32), hipMemcpyDeviceToHost, st));
-        HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 16, c->rhmax_d.p, ninst * sizeof(double),
+        HIPTRY(c, hipMemcpyAsync(c->pinned, c->flags.p, FLAG_WORDS * sizeof(u32),
                                  hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipMemcpyAsync((char*)c->pinned + FLAG_WORDS * sizeof(u32), c->rhmax_d.p,
+                                 ninst * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPTRY(c, hipStreamSynchronize(st));
-        u32 fl[4];
+        u32 fl[FLAG_WORDS];
         memcpy(fl, c->pinned, sizeof(fl));
+        if (fl[FLAG_SORT]) {
+            launch_fill_u32(P<u32>(c->flags) + FLAG_SORT, 1, 0u, st);
+            return fail(c, SHSPH_EHIP, "radix sort: a look-back wait ran past its bound");
+        }
         if (fl[0] & 1u) return fail(c, SHSPH_ECAPACITY, "tree traversal stack overflow");
         if (fl[0] & 8u)
             return fail(c, SHSPH_ECAPACITY, "a group's candidate union exceeds 65535 particles");
         if (fl[0] & 16u) return fail(c, SHSPH_ECAPACITY, "bottom-up box records overflow");
         // periodic minimum image needs the cache radius below half the box
-        const double* rh = (const double*)((char*)c->pinned + 16);
+        const double* rh = (const double*)((char*)c->pinned + FLAG_WORDS * sizeof(u32));
         for (int k = 0; k < ninst; ++k) {
             const InstDev& in = c->inst_h[k];
             if (!in.periodic) continue;
@@ -1050,7 +1060,7 @@ int shsph_destroy(shsph_ctx* c)
     hipStreamSynchronize(c->stream);
     pool_release(c);
     if (c->up_done) hipEventDestroy(c->up_done);
-    Buf* all[] = { &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->hist, &c->hist_scan,
+    Buf* all[] = { &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->hist,
                    &c->scan_tmp, &c->bbox, &c->posh, &c->velu, &c->vhalf, &c->hn, &c->hcache,
                    &c->pid_s, &c->thermo, &c->omega, &c->acc, &c->vsig, &c->status, &c->xi[0],
                    &c->xi[1], &c->xscan, &c->id, &c->mu_leaf, &c->lchild, &c->rchild, &c->endrange,

@@ -74,9 +74,9 @@ void scan_u32_u32(const u32* in, u32* out, i64 n, void* tmp, hipStream_t st);
 void scan_u32_u64(const u32* in, u64* out, i64 n, void* tmp, hipStream_t st);
 
 // sort.hip
-size_t radix_hist_count(i64 n);
+size_t radix_state_words(i64 n, int nseg);
 int radix_sort_pairs(u64* k0, u32* v0, u64* k1, u32* v1, i64 n, int key_bits, const i64* seg_off,
-                     int nseg, u32* hist, u32* hist_scan, void* scan_tmp, hipStream_t st);
+                     int nseg, u32* state, u32* err, hipStream_t st);
 
 // tree.hip
 template <class T>

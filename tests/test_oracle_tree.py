@@ -308,6 +308,11 @@ def test_neighbours_grid_equals_brute_force(family):
         assert (np.diff(seg.astype(np.int64)) > 0).all() and i in seg
         for j in seg[:5]:
             assert i in lst[off[j]:off[j + 1]]
+    # a target subset gives exactly those rows
+    t = np.array([p.n - 1, 0, 5, 5, 1234 % p.n])
+    to, tl = oracle.neighbours(p.x, p.y, p.z, p.h, p.lo, p.hi, p.periodic, 2.2, targets=t)
+    for r, i in enumerate(t):
+        assert np.array_equal(tl[to[r]:to[r + 1]], lst[off[i]:off[i + 1]])
 
 
 def test_neighbours_float_decision_in_float():
