@@ -217,8 +217,14 @@ k_group_leaves_serial(bool only_marked, const vec4<T>* __restrict__ blo, const v
 // group's box alone, which is then nearly as tight.
 // A group whose stack outgrows the LDS buffer is marked and left to the
 // serial walk.
-constexpr int S1_WAVES = 2;
+// The walk is compiled twice: FULL = false keeps only the node stack in LDS
+// (6 KB per wave, so many more waves hide the tree's load latency) and takes
+// the compact groups, marking the others; FULL = true, with the per-entry
+// target masks and the target boxes, then takes the marked groups.
+constexpr int S1_WAVES = 2;             // waves per workgroup, full walk
+constexpr int S1_CWAVES = 4;            // waves per workgroup, compact walk
 constexpr int S1_SMAX = 1536;
+constexpr u32 S1_WIDE = 0xfffffffeu;    // ucnt marker: group left to the full walk
 constexpr int S1_TS = 32;               // target runs (mask bits)
 constexpr u32 S1_FINAL = 0x80000000u;      // stack entry: an accepted leaf
 
@@ -228,8 +234,8 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-template <class T>
-__global__ void __launch_bounds__(S1_WAVES * WAVE)
+template <class T, bool FULL>
+__global__ void __launch_bounds__((FULL ? S1_WAVES : S1_CWAVES) * WAVE)
 k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__ bhi,
                     const u32* __restrict__ child, const u32* __restrict__ id,
                     const u32* __restrict__ xscan, i64 n_internal,
@@ -239,14 +245,16 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
                     u32* __restrict__ uslot, u32* __restrict__ ucnt, u32* __restrict__ ustot,
                     u32* __restrict__ flags)
 {
-    __shared__ u32 s_sn[S1_WAVES][S1_SMAX];
-    __shared__ u32 s_sm[S1_WAVES][S1_SMAX];
-    __shared__ vec4<T> s_tl[S1_WAVES][GROUP];      // target leaf boxes (at most one per particle)
-    __shared__ vec4<T> s_th[S1_WAVES][GROUP];
+    constexpr int NW = FULL ? S1_WAVES : S1_CWAVES;
+    __shared__ u32 s_sn[NW][S1_SMAX];
+    __shared__ u32 s_sm[FULL ? NW : 1][FULL ? S1_SMAX : 1];
+    __shared__ vec4<T> s_tl[FULL ? NW : 1][FULL ? GROUP : 1];   // target leaf boxes
+    __shared__ vec4<T> s_th[FULL ? NW : 1][FULL ? GROUP : 1];   // (at most one per particle)
     const int w = threadIdx.x / WAVE;
     const u32 lane = (u32)__lane_id();
-    const i64 g = (i64)blockIdx.x * S1_WAVES + w;
+    const i64 g = (i64)blockIdx.x * NW + w;
     if (g >= ngroups) return;                 // per wave; no workgroup barrier below
+    if (FULL && ucnt[g] != S1_WIDE) return;   // the compact walk took this group
     i64 beg, end;
     int k;
     gm.range(g, beg, end, k);
@@ -260,8 +268,10 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
     T hmin = ql.w;                            // smallest target h_max
     for (u32 a = lane; a < nt; a += WAVE) {
         const vec4<T> tl = blo[n_internal + t0 + a];
-        s_tl[w][a] = tl;
-        s_th[w][a] = bhi[n_internal + t0 + a];
+        if (FULL) {
+            s_tl[w][a] = tl;
+            s_th[w][a] = bhi[n_internal + t0 + a];
+        }
         hmin = fmin(hmin, tl.w);
     }
     hmin = wave_min(hmin);
@@ -271,9 +281,13 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
     const T reach = rk * hmin;
     const bool compact = ql.w <= T(1.5) * hmin && (qh.x - ql.x) <= T(4) * reach &&
                          (qh.y - ql.y) <= T(4) * reach && (qh.z - ql.z) <= T(4) * reach;
+    if (!FULL && !compact) {
+        if (lane == 0) ucnt[g] = S1_WIDE;
+        return;
+    }
     if (lane == 0) {
         s_sn[w][0] = root[k];
-        s_sm[w][0] = ns == 32u ? 0xffffffffu : ((1u << ns) - 1u);
+        if (FULL) s_sm[w][0] = ns == 32u ? 0xffffffffu : ((1u << ns) - 1u);
     }
     wave_lds_sync();
     u32* ul = uleaf + g * cap;
@@ -286,7 +300,7 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
         u32 e = 0, m = 0;
         if (lane < take_n) {                  // lane 0 takes the top (leftmost)
             e = s_sn[w][sp - 1u - lane];
-            m = s_sm[w][sp - 1u - lane];
+            m = FULL ? s_sm[w][sp - 1u - lane] : 1u;
         }
         wave_lds_sync();                       // popped before anything is pushed over them
         const u32 v = e & ~S1_FINAL;
@@ -299,7 +313,7 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
             } else {
                 const vec4<T> nl = blo[v], nh = bhi[v];
                 if (box_hit<T>(ql, qh, nl, nh, rk, eps_abs, bx)) {
-                    if (compact) cm = m;
+                    if (!FULL || compact) cm = m;
                     else while (m) {
                         const u32 r = (u32)(__ffs(m) - 1);
                         m &= m - 1u;
@@ -342,11 +356,13 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
         if (keep && !leaf) {
             s_sn[w][base + rtot - 1u - r0] = child[2 * (u64)v];
             s_sn[w][base + rtot - 2u - r0] = child[2 * (u64)v + 1];
-            s_sm[w][base + rtot - 1u - r0] = cm;
-            s_sm[w][base + rtot - 2u - r0] = cm;
+            if (FULL) {
+                s_sm[w][base + rtot - 1u - r0] = cm;
+                s_sm[w][base + rtot - 2u - r0] = cm;
+            }
         } else if (defer) {
             s_sn[w][base + rtot - 1u - r0] = v | S1_FINAL;
-            s_sm[w][base + rtot - 1u - r0] = 0u;
+            if (FULL) s_sm[w][base + rtot - 1u - r0] = 0u;
         }
         sp = base + rtot;
         wave_lds_sync();
@@ -816,10 +832,14 @@ void launch_group_leaves(const vec4<T>* blo, const vec4<T>* bhi, const u32* chil
 {
     if (ngroups <= 0) return;
     if (!serial) {
+        const dim3 gc((unsigned)((ngroups + S1_CWAVES - 1) / S1_CWAVES));
+        hipLaunchKernelGGL((k_group_leaves_wave<T, false>), gc, dim3(S1_CWAVES * WAVE), 0, st, blo,
+                           bhi, child, id, xscan, n_internal, glo, ghi, ngroups, gm, root, inst,
+                           (T)rk, cap, uleaf, uslot, ucnt, ustot, flags);
         const dim3 gw((unsigned)((ngroups + S1_WAVES - 1) / S1_WAVES));
-        hipLaunchKernelGGL((k_group_leaves_wave<T>), gw, dim3(S1_WAVES * WAVE), 0, st, blo, bhi,
-                           child, id, xscan, n_internal, glo, ghi, ngroups, gm, root, inst, (T)rk,
-                           cap, uleaf, uslot, ucnt, ustot, flags);
+        hipLaunchKernelGGL((k_group_leaves_wave<T, true>), gw, dim3(S1_WAVES * WAVE), 0, st, blo,
+                           bhi, child, id, xscan, n_internal, glo, ghi, ngroups, gm, root, inst,
+                           (T)rk, cap, uleaf, uslot, ucnt, ustot, flags);
     }
     // the serial walk takes every group (serial) or the marked ones
     const dim3 grid((unsigned)((ngroups + TRAV_BLOCK - 1) / TRAV_BLOCK));
