@@ -142,19 +142,53 @@ def cpu_baseline(ps_host, p, args):
                      targets=t)
         return time.perf_counter() - t0
 
+    def rate(s1, s2):
+        log(f"[cpu] oracle sample {s1} ({oracle.threads()} threads) ...")
+        t1 = run(s1)
+        log(f"[cpu] oracle sample {s2} ({oracle.threads()} threads) ...")
+        t2 = run(s2)
+        slope = max((t2 - t1) / (s2 - s1), 1e-12)
+        overhead = max(t1 - slope * s1, 0.0)
+        return n / (slope * n + overhead), t1, t2
+
+    cores = oracle.threads()
     s1, s2 = args.cpu_sample // 8, args.cpu_sample
-    log(f"[cpu] oracle sample {s1} ...")
-    t1 = run(s1)
-    log(f"[cpu] oracle sample {s2} ...")
-    t2 = run(s2)
-    slope = max((t2 - t1) / (s2 - s1), 1e-12)
-    overhead = max(t1 - slope * s1, 0.0)
-    t_full = slope * n + overhead
-    return {"value": n / t_full, "unit": "particle-steps/s", "cores": oracle.threads(),
-            "kind": "oracle",
+    v, t1, t2 = rate(s1, s2)
+    # one thread: a sample a quarter the size (the same extrapolation)
+    oracle.set_threads(1)
+    v1, u1, u2 = rate(s1 // 4, s2 // 4)
+    oracle.set_threads(cores)
+    return {"value": v, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "value_one_thread": v1,
             "sample": (f"{s2} and {s1} random particles of the {args.workload} state, FP64 "
                        f"density (h root) + force against all {n}; full step extrapolated "
-                       f"({t1:.1f}s, {t2:.1f}s measured)")}
+                       f"({t1:.1f}s, {t2:.1f}s measured; one thread: {s2 // 4} and {s1 // 4} "
+                       f"particles, {u1:.1f}s, {u2:.1f}s)")}
+
+
+def run_lattice(args, shsph, torch, name="uniform128", steps=20, warmup=3):
+    """The jittered-lattice workload (128^3, FP32, CFL steps) with the same
+    kernels and defaults: particle-steps/s beside the Sedov line."""
+    p = make_input(name)
+    log(f"[{name}] {p.n} particles")
+    ps = shsph.ParticleSet.from_particles(p)
+    ctx = shsph.Context(0, n_red=args.n_red)
+    ctx.build_tree(ps)
+    ctx.density(ps)
+    ctx.force(ps)
+    for _ in range(warmup):
+        ctx.step(ps, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(ps, 0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.close()
+    log(f"[{name}] {1e3 * el / steps:.2f} ms/step")
+    return {"workload": name, "particles": p.n, "steps": steps, "warmup": warmup,
+            "ms_per_step": 1e3 * el / steps, "value": p.n * steps / el,
+            "unit": "particle-steps/s"}
 
 
 def run_batched(args, shsph, torch):
@@ -344,6 +378,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=240000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batch run")
+    ap.add_argument("--no-lattice", action="store_true", help="skip the 128^3 lattice run")
     ap.add_argument("--no-served", action="store_true", help="skip the serving run")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-warmup", type=int, default=2)
@@ -449,12 +484,19 @@ def main():
                      "GBs": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
                      "frac_of_8TBs": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "work_per_step": {k: v / args.steps for k, v in work.items()},
+        # density passes over the cache per step (Newton evaluations, cache
+        # rebuild re-runs included) and the largest per-particle iteration count
+        "newton": {"passes_per_step": round(work["density_pair_evals"] / args.steps / max(info["n_neigh"], 1), 3),
+                   "max_iterations_last_step": info["max_iter_seen"]},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
     }
     host = ps.host("x", "y", "z", "vx", "vy", "vz", "u", "h") if not args.no_cpu_baseline else None
     ctx.close()
     del ps
     torch.cuda.empty_cache()
+    if not args.no_lattice:
+        out["uniform128"] = run_lattice(args, shsph, torch)
+        torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = run_batched(args, shsph, torch)
         torch.cuda.empty_cache()
