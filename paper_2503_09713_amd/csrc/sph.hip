@@ -208,15 +208,16 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
     int st = 1;   // 0 converged, 1 not converged, 2 chi exceeded
     int iters = 0;
     bool active = live;
-    u64 evals = 0, inrange = 0;
+    u64 evals = 0;                       // entries evaluated (profiling)
+    u32 inrange = 0;                     // of them within 2h (profiling)
     const bool wrap = !group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
                                          ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx);
     for (int it = 0; it < P.max_iter; ++it) {
         const T hinv = T(1) / h;
         const T h2x4 = T(4) * h * h;
         T s = T(0), dq = T(0);          // sum f, sum -q f' (>= 0: f is non-increasing)
+        if (active) evals += cnt;
         auto add_r2 = [&](T r2) {
-            ++evals;
             if (r2 < h2x4) {
                 ++inrange;
                 const T q = fast_sqrt(r2) * hinv;
@@ -292,7 +293,7 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
     }
     if (cv.work) {   // work counters (profiling): pair evaluations, those within 2h
         const u64 t1 = block_reduce<GROUP>(evals, s_w, [](u64 x, u64 y) { return x + y; });
-        const u64 t2 = block_reduce<GROUP>(inrange, s_w, [](u64 x, u64 y) { return x + y; });
+        const u64 t2 = block_reduce<GROUP>((u64)inrange, s_w, [](u64 x, u64 y) { return x + y; });
         if (threadIdx.x == 0) {
             atomicAdd((unsigned long long*)&cv.work[2 * (g & 63)], (unsigned long long)t1);
             atomicAdd((unsigned long long*)&cv.work[2 * (g & 63) + 1], (unsigned long long)t2);
@@ -380,21 +381,23 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     const u32 q0 = half ? qh : 0u, q1 = half ? nq : qh;
     const u32 e0 = min(cnt, 4u * q0), e1 = min(cnt, 4u * q1);
     T ax = T(0), ay = T(0), az = T(0), du = T(0), lam = T(0), vmax = ca;
-    u64 visited = 0, inter = 0;
+    u32 inter = 0;                      // interacting pairs (profiling)
     const bool wrap = !group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
                                          ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx);
+    // s_pos[].w holds 1/h of the staged particles (one reciprocal per
+    // staged particle instead of one per pair); r < 2 max(h_a, h_b) is
+    // tested as r^2 min(1/h_a, 1/h_b)^2 < 4 (the kernel gradient vanishes
+    // at q = 2, so the rounding of that boundary changes no sum)
     auto pair_d = [&](u32 sl, T dx, T dy, T dz, const vec4<T>& pb) {
         const T r2 = dx * dx + dy * dy + dz * dz;
-        const T hb = pb.w;
-        const T hm = ha > hb ? ha : hb;
-        ++visited;
-        if (!(r2 > T(0)) || !(r2 < T(4) * hm * hm)) return;
+        const T hib = pb.w;
+        const T hmi = hia < hib ? hia : hib;
+        if (!(r2 > T(0)) || !(r2 * hmi * hmi < T(4))) return;
         ++inter;
         const vec4<T> vb = s_vel[sl], tb = s_thm[sl];
         const T rinv = fast_rsq(r2), r = r2 * rinv;
         const T ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
         const T w = (va.x - vb.x) * ex + (va.y - vb.y) * ey + (va.z - vb.z) * ez;
-        const T hib = fast_rcp(hb);
         const T Fa = m4_df<T>(r * hia) * hia4;
         const T Fb = m4_df<T>(r * hib) * (hib * hib * hib * hib * inv_pi<T>());
         const T aw = fabs(w);
@@ -424,8 +427,13 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         const vec4<T> pb = s_pos[sl];
         pair_d(sl, pa.x - pb.x, pa.y - pb.y, pa.z - pb.z, pb);
     };
+    auto invert_h = [&](u32 n_st) {
+        for (u32 t = threadIdx.x; t < n_st; t += FT) s_pos[t].w = fast_rcp(s_pos[t].w);
+    };
     if (nch == 1) {
         stage_union<T, 3, FT>(src, dst, id, ul, us, nu, 0u, S);
+        __syncthreads();
+        invert_h(S);
         __syncthreads();
         if (wrap) entries_words(my, cnt, q0, q1, pair);
         else entries_words(my, cnt, q0, q1, pair_in);
@@ -435,6 +443,8 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
             const u32 c0 = ch * CH, c1 = min(S, c0 + CH);
             __syncthreads();
             stage_union<T, 3, FT>(src, dst, id, ul, us, nu, c0, c1);
+            __syncthreads();
+            invert_h(c1 - c0);
             __syncthreads();
             entries_tile(my, e1, j, c0, c1, pair);
         }
@@ -451,8 +461,8 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         vmax = vmax > s_half[5][lt] ? vmax : s_half[5][lt];
     }
     if (cv.work) {   // work counters (profiling): visited entries, interacting pairs
-        const u64 t1 = block_reduce<FT>(visited, s_w, [](u64 x, u64 y) { return x + y; });
-        const u64 t2 = block_reduce<FT>(inter, s_w, [](u64 x, u64 y) { return x + y; });
+        const u64 t1 = block_reduce<FT>((u64)(e1 - e0), s_w, [](u64 x, u64 y) { return x + y; });
+        const u64 t2 = block_reduce<FT>((u64)inter, s_w, [](u64 x, u64 y) { return x + y; });
         if (threadIdx.x == 0) {
             atomicAdd((unsigned long long*)&cv.work[2 * (g & 63)], (unsigned long long)t1);
             atomicAdd((unsigned long long*)&cv.work[2 * (g & 63) + 1], (unsigned long long)t2);
