@@ -384,6 +384,69 @@ k_boxes_local(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 
     }
 }
 
+// Middle level: workgroup c takes the climbs recorded by local blocks
+// c*BOX_MID .. c*BOX_MID + BOX_MID - 1 (one thread per block) and finishes
+// every parent whose leaf range lies inside those blocks' leaves, with
+// workgroup-scope arrival counters (both children of such a parent are
+// climbed by threads of this workgroup); climbs whose parent leaves that
+// range are recorded again for the top pass.
+constexpr int BOX_MID = 64;
+
+template <class T>
+__global__ void __launch_bounds__(BOX_MID)
+k_boxes_mid(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nblocks, i64 n_leaf,
+            const u32* __restrict__ child, const u32* __restrict__ parent,
+            const u32* __restrict__ endrange, const i64* __restrict__ ioff,
+            const i64* __restrict__ leaf_off, int ninst, u32* __restrict__ arrive, vec4<T>* blo,
+            vec4<T>* bhi, u32* __restrict__ rec2, u32* __restrict__ nrec2, u32* __restrict__ flags)
+{
+    __shared__ u32 s_rec[BOX_OUT];
+    __shared__ u32 s_nrec;
+    if (threadIdx.x == 0) s_nrec = 0;
+    __syncthreads();
+    const i64 b = (i64)blockIdx.x * BOX_MID + threadIdx.x;
+    const i64 C0 = (i64)blockIdx.x * BOX_MID * BOX_BLK;
+    const i64 C1 = (C0 + (i64)BOX_MID * BOX_BLK) < n_leaf ? (C0 + (i64)BOX_MID * BOX_BLK) : n_leaf;
+    if (b < nblocks) {
+        const u32 nr = nrec[b];
+        for (u32 q = 0; q < nr; ++q) {
+            u32 node = rec[b * BOX_OUT + q];
+            vec4<T> ml = blo[node], mh = bhi[node];
+            while (true) {
+                const u32 par = parent[node];
+                if (par == 0xffffffffu) break;
+                i64 f, l, kidx;
+                node_span(par, ioff, leaf_off, ninst, endrange, f, l, kidx);
+                if (f < C0 || l >= C1) {               // parent straddles this range
+                    const u32 r = atomicAdd(&s_nrec, 1u);
+                    if (r < BOX_OUT) s_rec[r] = node;
+                    break;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                const u32 prev = __hip_atomic_fetch_add(&arrive[par], 1u, __ATOMIC_ACQ_REL,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (prev == 0) break;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
+                const u32 other = (c0 == node) ? c1 : c0;
+                const vec4<T> ol = blo[other], oh = bhi[other];
+                ml = mk4<T>(fmin(ml.x, ol.x), fmin(ml.y, ol.y), fmin(ml.z, ol.z), fmax(ml.w, ol.w));
+                mh = mk4<T>(fmax(mh.x, oh.x), fmax(mh.y, oh.y), fmax(mh.z, oh.z), T(0));
+                blo[par] = ml;
+                bhi[par] = mh;
+                node = par;
+            }
+        }
+    }
+    __syncthreads();
+    const u32 nr = s_nrec < BOX_OUT ? s_nrec : BOX_OUT;
+    for (u32 q = threadIdx.x; q < nr; q += BOX_MID) rec2[(i64)blockIdx.x * BOX_OUT + q] = s_rec[q];
+    if (threadIdx.x == 0) {
+        nrec2[blockIdx.x] = nr;
+        if (s_nrec > BOX_OUT) atomicOr(flags, 16u);
+    }
+}
+
 template <class T>
 __global__ void __launch_bounds__(TOP_BLOCK)
 k_boxes_top(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nblocks,
@@ -640,12 +703,27 @@ void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 n_leaf, i64 n_inter
     hipLaunchKernelGGL((k_boxes_local<T>), dim3((unsigned)nb), dim3(BOX_BLK), 0, st, posh, id, n_leaf,
                        n_internal, child, parent, endrange, ioff, leaf_off, ninst, blo, bhi, rec,
                        nrec, flags);
-    if (nb > 1)
-        hipLaunchKernelGGL((k_boxes_top<T>), dim3(1), dim3(TOP_BLOCK), 0, st, rec, nrec, nb, child,
-                           parent, arrive, blo, bhi);
+    if (nb > 1) {
+        // middle level (ranges of BOX_MID local blocks), then one workgroup
+        // for the climbs that cross those ranges
+        const i64 nb2 = (nb + BOX_MID - 1) / BOX_MID;
+        u32* rec2 = rec + nb * BOX_OUT;
+        u32* nrec2 = nrec + nb;
+        hipLaunchKernelGGL((k_boxes_mid<T>), dim3((unsigned)nb2), dim3(BOX_MID), 0, st, rec, nrec,
+                           nb, n_leaf, child, parent, endrange, ioff, leaf_off, ninst, arrive, blo,
+                           bhi, rec2, nrec2, flags);
+        if (nb2 > 1)
+            hipLaunchKernelGGL((k_boxes_top<T>), dim3(1), dim3(TOP_BLOCK), 0, st, rec2, nrec2, nb2,
+                               child, parent, arrive, blo, bhi);
+    }
 }
 
-size_t boxes_rec_count(i64 n_leaf) { return (size_t)((n_leaf + BOX_BLK - 1) / BOX_BLK) * BOX_OUT; }
+// Record space: BOX_OUT per local block, then BOX_OUT per middle range.
+size_t boxes_rec_count(i64 n_leaf)
+{
+    const i64 nb = (n_leaf + BOX_BLK - 1) / BOX_BLK;
+    return (size_t)(nb + (nb + BOX_MID - 1) / BOX_MID) * BOX_OUT;
+}
 
 void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
                          i64 n_internal, i64 n_leaf, const u32* endrange, const u32* parent,

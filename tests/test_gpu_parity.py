@@ -96,6 +96,12 @@ CASES_TREE = [
     ("lattice21_f32_nred4", lambda: gen.lattice(21, 5, dtype=np.float32), 4),
     ("plummer5000_f32", lambda: gen.plummer(5000, 6, dtype=np.float32), 3),
     ("plummer4097_f64", lambda: gen.plummer(4097, 7, dtype=np.float64), 2),
+    # more than 64 blocks of 1024 leaves: the box climbs cross the middle
+    # level's ranges and reach the top pass (the strong jitter makes the
+    # tree irregular, so subtrees straddle the blocks)
+    ("lattice48_f32_nred0", lambda: gen.lattice(48, 8, dtype=np.float32), 0),
+    ("lattice48_f32_jitter_nred0",
+     lambda: gen.lattice(48, 9, dtype=np.float32, jitter=0.35), 0),
 ]
 
 
