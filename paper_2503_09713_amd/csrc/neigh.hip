@@ -395,6 +395,7 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
 // particles of its own leaf's marked union leaves, positions read from LDS.
 constexpr int TMAX = GROUP;      // target leaves of a group: at most one per particle
 constexpr int MW = LCHUNK / 64;  // mask words per target leaf
+static_assert(MW == 4, "the per-lane walk selects among four mask words");
 
 // Stage-2 candidate test in the storage type:
 //   dx = x_b - x_a (minimum image), r2 = fma(dz, dz, fma(dy, dy, dx*dx)),
@@ -469,6 +470,29 @@ __device__ inline void queue_flush(LaneQueue& lq, u32 capq)
     }
 }
 
+// Per-particle leaf test (groups that need no minimum image): the gaps from
+// the particle to the leaf's tight box, g = max(lo - x_a, x_a - hi, 0) per
+// axis, give d2 = fma(gz, gz, fma(gy, gy, gx gx)).  For any particle b of the
+// leaf, |x_b - x_a| >= g and the roundings are monotone, so its r2 >= d2;
+// and its staged q_b <= q_leaf = (rkc h_max)^2 rounded the same way.  So
+// d2 >= max(q_a, q_leaf) rejects every particle of the leaf exactly, and
+// only leaves that pass are walked.  q_leaf is staged in the box's .w.
+template <class T>
+__device__ inline bool leaf_reach(const vec4<T>& pa, T qa, const vec4<T>& bl, const vec4<T>& bh)
+{
+#pragma clang fp contract(off)
+    const T gx = fmax(fmax(bl.x - pa.x, pa.x - bh.x), T(0));
+    const T gy = fmax(fmax(bl.y - pa.y, pa.y - bh.y), T(0));
+    const T gz = fmax(fmax(bl.z - pa.z, pa.z - bh.z), T(0));
+    const T d2 = fma(gz, gz, fma(gy, gy, gx * gx));
+    if constexpr (sizeof(T) == 4) {
+        const u32 qa_b = __float_as_uint(qa), ql_b = __float_as_uint(bh.w);
+        return __float_as_uint(d2) < (qa_b > ql_b ? qa_b : ql_b);
+    } else {
+        return d2 < fmax(qa, bh.w);
+    }
+}
+
 // Tests the particles [b0, b1) of one union leaf (union slots from sl) and
 // queues the accepted ones (the per-lane walk).
 template <class T, bool LDS, bool WRAP>
@@ -497,23 +521,54 @@ __device__ inline void cache_leaf(const vec4<T>& pa, T qa, const Box<T>& bx, T r
     }
 }
 
-// Stage-2 walk, per lane: each lane takes the union leaves of its own
-// target leaf's mask row (in LDS), one leaf per iteration across all the
-// row's words, so lanes whose marked leaves fall in different words still
-// visit in step (lanes diverge only in where their leaves are).
+// Stage-2 walk, per lane: each lane takes the union leaves of its target
+// leaf's mask, one leaf per iteration across all the mask's words, so lanes
+// whose marked leaves fall in different words still visit in step.  For
+// groups that need no minimum image, when some lane of the wave has many
+// candidates (marked leaves x the union's mean leaf size >= 300: then the
+// rejected leaves save more tests than the pass costs), a first pass clears
+// the leaves that fail the particle's own leaf test (leaf_reach) from the
+// lane's copy of the mask, so the walk's iterations follow the leaves the
+// lane really visits (a skip inside the walk would cost the wave the test
+// and the visit).
 template <class T, bool LDS, bool WRAP>
-__device__ inline void cache_walk_lane(const vec4<T>& pa, T qa, bool live, const Box<T>& bx,
+__device__ inline void cache_walk_lane(const vec4<T>& pa, T qa, bool live, u32 S, u32 nu,
+                                       const Box<T>& bx,
                                        T rkc, const u64* mrow, const u32* s_b0, const u32* s_b1,
-                                       const u32* s_slot, const vec4<T>* s_upos,
+                                       const u32* s_slot, const vec4<T>* s_lo,
+                                       const vec4<T>* s_hi, const vec4<T>* s_upos,
                                        const vec4<T>* posh, LaneQueue& lq, u32 capq, u32& tested)
 {
+    bool refine = false;
+    if (!WRAP) {
+        u32 marked = 0;
+        if (live)
+#pragma unroll
+            for (int w = 0; w < MW; ++w) marked += (u32)__popcll(mrow[w]);
+        refine = __ballot((u64)marked * S >= 300ull * nu) != 0ull;
+    }
     if (!live) return;
+    u64 mk[MW];
+#pragma unroll
+    for (int w = 0; w < MW; ++w) {
+        u64 m = mrow[w];
+        if (!WRAP && refine) {
+            u64 cur = m;
+            while (cur) {
+                const u32 b = (u32)(__ffsll((unsigned long long)cur) - 1);
+                cur &= cur - 1;
+                const u32 j = (u32)(w * 64) + b;
+                if (!leaf_reach<T>(pa, qa, s_lo[j], s_hi[j])) m &= ~(1ull << b);
+            }
+        }
+        mk[w] = m;
+    }
     u32 wb = 0;                 // 64 x (current word)
-    u64 cur = mrow[0];
+    u64 cur = mk[0];
     for (;;) {
         while (cur == 0ull && wb < (u32)(MW - 1) * 64u) {
             wb += 64u;
-            cur = mrow[wb >> 6];
+            cur = wb == 64u ? mk[1] : (wb == 128u ? mk[2] : mk[3]);
         }
         if (cur == 0ull) break;
         const u32 j = wb + (u32)(__ffsll((unsigned long long)cur) - 1);
@@ -623,15 +678,17 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     __shared__ u32 s_b0[LCHUNK];
     __shared__ u32 s_b1[LCHUNK];
     __shared__ u32 s_slot[LCHUNK];
-    // union-leaf boxes of the chunk (prune only); the queued walk reuses the
+    // union-leaf boxes of the chunk (.w of the high corner: q of the leaf's
+    // h_max), for the prune and the per-particle leaf test
+    __shared__ vec4<T> s_lo[LCHUNK];
+    __shared__ vec4<T> s_hi[LCHUNK];
+    // target-leaf boxes (prune only, loaded per chunk); the walk reuses the
     // space for the lanes' queues (pending entries carried over chunks in a
     // register)
-    __shared__ vec4<T> s_box[2 * LCHUNK];
-    vec4<T>* const s_lo = s_box;
-    vec4<T>* const s_hi = s_box + LCHUNK;
-    static_assert(GROUP * QSTRIDE * sizeof(u16) <= sizeof(s_box), "queues do not fit");
-    __shared__ vec4<T> s_tlo[TMAX];
-    __shared__ vec4<T> s_thi[TMAX];
+    __shared__ vec4<T> s_tbox[2 * TMAX];
+    vec4<T>* const s_tlo = s_tbox;
+    vec4<T>* const s_thi = s_tbox + TMAX;
+    static_assert(GROUP * QSTRIDE * sizeof(u16) <= sizeof(s_tbox), "queues do not fit");
     __shared__ u64 s_mask[TMAX][MW];
     __shared__ vec4<T> s_upos[UCH];
     const i64 g = blockIdx.x;
@@ -655,12 +712,9 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     const u32 ta = xscan[ai + 1] - 1u - t0;
     const T hmax_all = blo[root[k]].w;
     bool t_in = true;
-    for (u32 t = threadIdx.x; t < nt; t += GROUP) {
-        const vec4<T> l = blo[n_internal + t0 + t], h = bhi[n_internal + t0 + t];
-        s_tlo[t] = l;
-        s_thi[t] = h;
-        t_in = t_in && prune_interior<T>(l, h, hmax_all, rk, eps_abs, bx);
-    }
+    for (u32 t = threadIdx.x; t < nt; t += GROUP)
+        t_in = t_in && prune_interior<T>(blo[n_internal + t0 + t], bhi[n_internal + t0 + t], hmax_all,
+                                         rk, eps_abs, bx);
     const bool prune_wrap = __syncthreads_or(!t_in);
     if (in_lds) {
         const vec4<T>* src[1] = { posh };
@@ -682,7 +736,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     u64* out = nlist + (u64)g * capq * GROUP + threadIdx.x;
     u32 tested = 0;
     u64 wbuf = 0, boxtests = 0;   // wbuf: the queue's pending entries between chunks
-    LaneQueue lq{(u16*)s_box + threadIdx.x * QSTRIDE, 0u, 0u, out};
+    LaneQueue lq{(u16*)s_tbox + threadIdx.x * QSTRIDE, 0u, 0u, out};
     for (u32 c0 = 0; c0 < nu; c0 += LCHUNK) {
         const u32 c1 = min(nu, c0 + LCHUNK);
         const u32 nl = c1 - c0;
@@ -693,8 +747,19 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
             s_b0[j - c0] = id[leaf];
             s_b1[j - c0] = id[leaf + 1];
             s_slot[j - c0] = uslot[g * cap + j];
-            s_lo[j - c0] = blo[n_internal + leaf];
-            s_hi[j - c0] = bhi[n_internal + leaf];
+            const vec4<T> ul = blo[n_internal + leaf];
+            vec4<T> uh = bhi[n_internal + leaf];
+            {
+#pragma clang fp contract(off)
+                const T r = rkc * ul.w;
+                uh.w = q_clean(r * r);            // q of the leaf's h_max
+            }
+            s_lo[j - c0] = ul;
+            s_hi[j - c0] = uh;
+        }
+        for (u32 t = threadIdx.x; t < nt; t += GROUP) {
+            s_tlo[t] = blo[n_internal + t0 + t];
+            s_thi[t] = bhi[n_internal + t0 + t];
         }
         __syncthreads();
         // target leaf x union leaf prune, shared by the lanes of each target
@@ -749,14 +814,18 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
                                                 s_upos, posh, lq, capq, tested);
         } else if (mode != 2) {
             if (in_lds && interior)
-                cache_walk_lane<T, true, false>(pa, qa, live, bx, rkc, s_mask[ta], s_b0, s_b1,
-                                                s_slot, s_upos, posh, lq, capq, tested);
+                cache_walk_lane<T, true, false>(pa, qa, live, S, nu, bx, rkc, s_mask[ta], s_b0, s_b1,
+                                                s_slot, s_lo, s_hi, s_upos, posh, lq, capq, tested);
             else if (in_lds)
-                cache_walk_lane<T, true, true>(pa, qa, live, bx, rkc, s_mask[ta], s_b0, s_b1,
-                                               s_slot, s_upos, posh, lq, capq, tested);
+                cache_walk_lane<T, true, true>(pa, qa, live, S, nu, bx, rkc, s_mask[ta], s_b0, s_b1,
+                                               s_slot, s_lo, s_hi, s_upos, posh, lq, capq, tested);
+            else if (interior)
+                cache_walk_lane<T, false, false>(pa, qa, live, S, nu, bx, rkc, s_mask[ta], s_b0, s_b1,
+                                                 s_slot, s_lo, s_hi, s_upos, posh, lq, capq,
+                                                 tested);
             else
-                cache_walk_lane<T, false, true>(pa, qa, live, bx, rkc, s_mask[ta], s_b0, s_b1,
-                                                s_slot, s_upos, posh, lq, capq, tested);
+                cache_walk_lane<T, false, true>(pa, qa, live, S, nu, bx, rkc, s_mask[ta], s_b0, s_b1,
+                                                s_slot, s_lo, s_hi, s_upos, posh, lq, capq, tested);
         }
         wbuf = lq.pos ? *(const u64*)lq.e : 0ull;
     }
