@@ -383,7 +383,7 @@ CacheView cache_view(shsph_ctx* c)
 // boxes -> caches.  `dt_dev` non-NULL: positions are the leapfrog-predicted
 // ones (stepping); the gather then also forms v*, u*, v^{n+1/2}, u^{n+1/2}.
 // ---------------------------------------------------------------------------
-template <class T> int build_caches(shsph_ctx* c);
+template <class T> int build_caches(shsph_ctx* c, const u8* redo = nullptr);
 
 template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const double* dt_dev, bool step)
 {
@@ -486,7 +486,11 @@ template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const d
 // Boxes, stage-1 and stage-2 caches on the current tree, with h_cache = posh.w.
 // Capacities (leaves per group, entries per particle) grow and the stage is
 // redone when a build reports more than fits.
-template <class T> int build_caches(shsph_ctx* c)
+// `redo` (device, per instance, optional): only instances flagged 1 get new
+// caches; the others keep the ones of the previous build (valid: their h
+// stayed within chi h_cache).  A capacity regrow changes the layout, so the
+// retry rebuilds every group.
+template <class T> int build_caches(shsph_ctx* c, const u8* redo)
 {
     hipStream_t st = c->stream;
     const i64 n = c->n, nl = c->n_leaf, ni = c->n_internal, G = c->n_groups;
@@ -528,7 +532,7 @@ template <class T> int build_caches(shsph_ctx* c)
                                (u32)c->prm.spread_slots, c->prm.stage1_serial != 0,
                                P<u32>(c->uleaf),
                                P<u32>(c->uslot), P<u32>(c->ucnt), P<u32>(c->ustot),
-                               P<u32>(c->flags), st);
+                               P<u32>(c->flags), attempt ? nullptr : redo, st);
         prof_end(c);
         TRY(check_launch(c, "stage1"));
         // stage 2: particle neighbours as union slots
@@ -539,7 +543,7 @@ template <class T> int build_caches(shsph_ctx* c)
                               P<u32>(c->ucnt), P<u32>(c->ustot), (u32)c->cap_words, P<u64>(c->nlist),
                               P<u32>(c->ncnt), P<u32>(c->flags), P<vec4<T>>(c->glo),
                               P<vec4<T>>(c->ghi), P<u32>(c->root_d), work_ptr(c, 0),
-                              c->prm.stage2_mode, st);
+                              c->prm.stage2_mode, attempt ? nullptr : redo, st);
         prof_end(c);
         TRY(check_launch(c, "stage2"));
         launch_root_hmax<T>(P<vec4<T>>(c->blo), P<u32>(c->root_d), ninst, P<double>(c->rhmax_d), st);
@@ -623,7 +627,7 @@ template <class T> int run_density(shsph_ctx* c, bool with_thermo)
         ++c->restarts;
         TRY(upload_extra(c, c->redo_d.p, redo.data(), ninst));
         launch_copy_h<T>(s.posh, s.hcache, n, st);
-        TRY(build_caches<T>(c));
+        TRY(build_caches<T>(c, ninst > 1 ? P<u8>(c->redo_d) : nullptr));
     }
 }
 

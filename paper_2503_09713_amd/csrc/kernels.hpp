@@ -118,14 +118,14 @@ void launch_group_leaves(const vec4<T>* blo, const vec4<T>* bhi, const u32* chil
                          i64 ngroups,
                          const GroupMap& gm, const u32* root, const InstDev* inst, double rk,
                          i64 cap, u32 spread, bool serial, u32* uleaf, u32* uslot, u32* ucnt,
-                         u32* ustot, u32* flags, hipStream_t st);
+                         u32* ustot, u32* flags, const u8* redo, hipStream_t st);
 template <class T>
 void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* bhi, const u32* id,
                         const u32* xscan, i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
                         const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
                         u32* flags, const vec4<T>* glo, const vec4<T>* ghi, const u32* root,
-                        u64* work, int mode, hipStream_t st);
+                        u64* work, int mode, const u8* redo, hipStream_t st);
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
                             const u32* uleaf, const u32* uslot, const u32* ucnt, u32 capq,
                             const u64* nlist, const u32* ncnt, const u64* off, u32* list,

@@ -134,17 +134,20 @@ k_group_leaves_serial(bool only_marked, const vec4<T>* __restrict__ blo, const v
                const vec4<T>* __restrict__ glo, const vec4<T>* __restrict__ ghi, i64 ngroups,
                const GroupMap gm, const u32* __restrict__ root, const InstDev* __restrict__ inst,
                T rk, i64 cap, u32 spread, u32* __restrict__ uleaf, u32* __restrict__ uslot,
-               u32* __restrict__ ucnt, u32* __restrict__ ustot, u32* __restrict__ flags)
+               u32* __restrict__ ucnt, u32* __restrict__ ustot, u32* __restrict__ flags,
+               const u8* __restrict__ redo)
 {
     __shared__ u32 stack[STACK][TRAV_BLOCK];
     const int lane = threadIdx.x;
     const i64 g0 = (i64)blockIdx.x * TRAV_BLOCK + lane;
     const i64 g = g0 < ngroups ? g0 : ngroups - 1;
-    const bool live = g0 < ngroups && (!only_marked || ucnt[g] == S1_SERIAL);
-    if (only_marked && __ballot(live) == 0) return;
+    bool live0 = g0 < ngroups && (!only_marked || ucnt[g] == S1_SERIAL);
+    if (only_marked && __ballot(live0) == 0) return;
     i64 beg, end;
     int k;
     gm.range(g, beg, end, k);
+    if (redo && !redo[k]) live0 = false;      // this instance keeps its caches
+    const bool live = live0;
     const Box<T> bx = make_box<T>(inst[k]);
     const T eps_abs = abs_inflation(bx);
     const vec4<T> ql = glo[g], qh = ghi[g];
@@ -243,7 +246,7 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
                     const GroupMap gm, const u32* __restrict__ root,
                     const InstDev* __restrict__ inst, T rk, i64 cap, u32* __restrict__ uleaf,
                     u32* __restrict__ uslot, u32* __restrict__ ucnt, u32* __restrict__ ustot,
-                    u32* __restrict__ flags)
+                    u32* __restrict__ flags, const u8* __restrict__ redo)
 {
     constexpr int NW = FULL ? S1_WAVES : S1_CWAVES;
     __shared__ u32 s_sn[NW][S1_SMAX];
@@ -258,6 +261,7 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
     i64 beg, end;
     int k;
     gm.range(g, beg, end, k);
+    if (redo && !redo[k]) return;             // this instance keeps its caches
     const Box<T> bx = make_box<T>(inst[k]);
     const T eps_abs = abs_inflation(bx);
     const vec4<T> ql = glo[g], qh = ghi[g];
@@ -671,7 +675,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
               const u32* __restrict__ ucnt, const u32* __restrict__ ustot, u32 capq,
               u64* __restrict__ nlist, u32* __restrict__ ncnt, u32* __restrict__ flags,
               const vec4<T>* __restrict__ glo, const vec4<T>* __restrict__ ghi,
-              const u32* __restrict__ root, u64* __restrict__ work)
+              const u32* __restrict__ root, u64* __restrict__ work, const u8* __restrict__ redo)
 {
     constexpr int mode = MODE;
     __shared__ u64 s_w[GROUP / WAVE];
@@ -695,6 +699,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     i64 beg, end;
     int k;
     gm.range(g, beg, end, k);
+    if (redo && !redo[k]) return;             // this instance keeps its caches (block-uniform)
     const Box<T> bx = make_box<T>(inst[k]);
     const T eps_abs = abs_inflation(bx);
     const i64 a = beg + threadIdx.x;
@@ -897,24 +902,24 @@ void launch_group_leaves(const vec4<T>* blo, const vec4<T>* bhi, const u32* chil
                          const u32* xscan, i64 n_internal, const vec4<T>* glo, const vec4<T>* ghi,
                          i64 ngroups, const GroupMap& gm, const u32* root, const InstDev* inst,
                          double rk, i64 cap, u32 spread, bool serial, u32* uleaf, u32* uslot,
-                         u32* ucnt, u32* ustot, u32* flags, hipStream_t st)
+                         u32* ucnt, u32* ustot, u32* flags, const u8* redo, hipStream_t st)
 {
     if (ngroups <= 0) return;
     if (!serial) {
         const dim3 gc((unsigned)((ngroups + S1_CWAVES - 1) / S1_CWAVES));
         hipLaunchKernelGGL((k_group_leaves_wave<T, false>), gc, dim3(S1_CWAVES * WAVE), 0, st, blo,
                            bhi, child, id, xscan, n_internal, glo, ghi, ngroups, gm, root, inst,
-                           (T)rk, cap, uleaf, uslot, ucnt, ustot, flags);
+                           (T)rk, cap, uleaf, uslot, ucnt, ustot, flags, redo);
         const dim3 gw((unsigned)((ngroups + S1_WAVES - 1) / S1_WAVES));
         hipLaunchKernelGGL((k_group_leaves_wave<T, true>), gw, dim3(S1_WAVES * WAVE), 0, st, blo,
                            bhi, child, id, xscan, n_internal, glo, ghi, ngroups, gm, root, inst,
-                           (T)rk, cap, uleaf, uslot, ucnt, ustot, flags);
+                           (T)rk, cap, uleaf, uslot, ucnt, ustot, flags, redo);
     }
     // the serial walk takes every group (serial) or the marked ones
     const dim3 grid((unsigned)((ngroups + TRAV_BLOCK - 1) / TRAV_BLOCK));
     hipLaunchKernelGGL((k_group_leaves_serial<T>), grid, dim3(TRAV_BLOCK), 0, st, !serial, blo,
                        bhi, child, id, xscan, n_internal, glo, ghi, ngroups, gm, root, inst, (T)rk,
-                       cap, spread, uleaf, uslot, ucnt, ustot, flags);
+                       cap, spread, uleaf, uslot, ucnt, ustot, flags, redo);
 }
 
 template <class T>
@@ -923,13 +928,13 @@ void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* 
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
                         const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
                         u32* flags, const vec4<T>* glo, const vec4<T>* ghi, const u32* root,
-                        u64* work, int mode, hipStream_t st)
+                        u64* work, int mode, const u8* redo, hipStream_t st)
 {
     if (ngroups <= 0) return;
     auto kern = mode == 2 ? k_group_cache<T, 2> : mode == 0 ? k_group_cache<T, 0> : k_group_cache<T, 1>;
     hipLaunchKernelGGL(kern, dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, blo,
                        bhi, id, xscan, n_internal, gm, inst, (T)rk, (T)rkc, cap, uleaf, uslot, ucnt, ustot,
-                       capq, nlist, ncnt, flags, glo, ghi, root, work);
+                       capq, nlist, ncnt, flags, glo, ghi, root, work, redo);
 }
 
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
@@ -949,12 +954,13 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
                                          i64, const vec4<T>*, const vec4<T>*, i64,                \
                                          const GroupMap&, const u32*, const InstDev*, double,     \
                                          i64, u32, bool, u32*, u32*, u32*, u32*, u32*,            \
-                                         hipStream_t);                                            \
+                                         const u8*, hipStream_t);                                 \
     template void launch_group_cache<T>(const vec4<T>*, const vec4<T>*, const vec4<T>*,           \
                                         const u32*, const u32*, i64, const GroupMap&, i64, const InstDev*,    \
                                         double, double, i64, const u32*, const u32*, const u32*,  \
                                         const u32*, u32, u64*, u32*, u32*, const vec4<T>*,        \
-                                        const vec4<T>*, const u32*, u64*, int, hipStream_t);
+                                        const vec4<T>*, const u32*, u64*, int, const u8*,         \
+                                        hipStream_t);
 INST(float)
 INST(double)
 #undef INST
