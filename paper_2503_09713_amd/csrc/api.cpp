@@ -428,8 +428,9 @@ template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const d
     prof_begin(c, S_SORT);
     const int sel = radix_sort_pairs(P<u64>(c->keys[0]), P<u32>(c->vals[0]), P<u64>(c->keys[1]),
                                      P<u32>(c->vals[1]), n, 63, poff, ninst, P<u32>(c->hist),
-                                     P<u32>(c->flags) + FLAG_SORT, st);
+                                     P<u32>(c->flags) + FLAG_SORT, (u32*)c->pinned, st);
     prof_end(c);
+    if (sel == -2) return fail(c, SHSPH_EHIP, "radix sort: reading the out-of-place count failed");
     if (sel < 0) return fail(c, SHSPH_ECAPACITY, "more than 2^30 - 2 particles in one pass");
     c->vals_sel = sel;
     const u64* mu = P<u64>(c->keys[sel]);

@@ -76,7 +76,7 @@ void scan_u32_u64(const u32* in, u64* out, i64 n, void* tmp, hipStream_t st);
 // sort.hip
 size_t radix_state_words(i64 n, int nseg);
 int radix_sort_pairs(u64* k0, u32* v0, u64* k1, u32* v1, i64 n, int key_bits, const i64* seg_off,
-                     int nseg, u32* state, u32* err, hipStream_t st);
+                     int nseg, u32* state, u32* err, u32* host_word, hipStream_t st);
 
 // tree.hip
 template <class T>

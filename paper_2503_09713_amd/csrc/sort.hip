@@ -258,24 +258,300 @@ k_rs_pass(const u64* __restrict__ kin, const u32* __restrict__ vin, u64* __restr
     }
 }
 
-size_t radix_state_words(i64 n, int nseg)
+// ---------------------------------------------------------------------------
+// Nearly sorted input.  Between steps the particles keep their previous key
+// order and few of them change place.  Element i is "in place" when no
+// earlier key is larger and no later key smaller; the in-place elements (R)
+// form a sorted sequence in index order.  The others (O) are sorted by the
+// radix passes and merged into R, both by (key, value).  With values that
+// increase with the index (the iota of the key kernel) ties keep the index
+// order on both sides, so the result is the stable sort.  Used when O holds
+// at most n/8 elements; otherwise the full radix sort runs.
+// ---------------------------------------------------------------------------
+constexpr int AD_TILE = RS_TILE;                  // 4096 keys, RS_BLOCK threads x RS_ITEMS
+constexpr int AD_SCAN = 1024;                     // threads of the one-block scans
+
+__device__ inline u64 shfl_up_u64(u64 x, int d)
 {
-    (void)nseg;
-    const i64 ntiles = std::max<i64>(1, (n + RS_TILE - 1) / RS_TILE);
-    return (size_t)(2 * RS_MAXP * RS_BINS + RS_MAXP + (i64)RS_MAXP * ntiles * RS_BINS);
+    const u32 lo = __shfl_up((u32)x, d, WAVE), hi = __shfl_up((u32)(x >> 32), d, WAVE);
+    return ((u64)hi << 32) | lo;
+}
+__device__ inline u64 shfl_down_u64(u64 x, int d)
+{
+    const u32 lo = __shfl_down((u32)x, d, WAVE), hi = __shfl_down((u32)(x >> 32), d, WAVE);
+    return ((u64)hi << 32) | lo;
 }
 
-// Sorts (keys, vals) over key bits [0, key_bits) and then, when nseg > 1,
-// stably by the instance id of the original index.  Buffers ping-pong between
-// (k0,v0) and (k1,v1); the return value says which pair holds the result
-// (0 -> k0/v0, 1 -> k1/v1), or -1 for n >= 2^30 (not supported).  `state`
-// holds radix_state_words(n) words; `err` (device) gets bit 0 set if a
-// look-back wait ran past its bound.
-int radix_sort_pairs(u64* k0, u32* v0, u64* k1, u32* v1, i64 n, int key_bits,
-                     const i64* seg_off, int nseg, u32* state, u32* err, hipStream_t st)
+// Exclusive prefix max and exclusive suffix min over the block's threads.
+template <int BLOCK>
+__device__ inline void block_pmax_smin(u64 vmax, u64 vmin, u64* lmax, u64* lmin, u64& pm, u64& sm)
 {
-    if (n <= 1) return 0;
-    if (n >= (i64)ST_VAL) return -1;
+    const int lane = __lane_id(), wid = threadIdx.x / WAVE;
+    u64 a = vmax, b = vmin;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {          // inclusive scans within the wave
+        const u64 ua = shfl_up_u64(a, d), db = shfl_down_u64(b, d);
+        if (lane >= d) a = ua > a ? ua : a;
+        if (lane + d < WAVE) b = db < b ? db : b;
+    }
+    if (lane == WAVE - 1) lmax[wid] = a;
+    if (lane == 0) lmin[wid] = b;
+    __syncthreads();
+    u64 pw = 0, sw = ~0ull;
+    for (int w = 0; w < BLOCK / WAVE; ++w) {
+        if (w < wid) pw = lmax[w] > pw ? lmax[w] : pw;
+        if (w > wid) sw = lmin[w] < sw ? lmin[w] : sw;
+    }
+    __syncthreads();
+    const u64 ea = shfl_up_u64(a, 1), eb = shfl_down_u64(b, 1);
+    pm = lane > 0 ? (ea > pw ? ea : pw) : pw;
+    sm = lane < WAVE - 1 ? (eb < sw ? eb : sw) : sw;
+}
+
+// Per tile: the smallest and the largest key.
+__global__ void __launch_bounds__(RS_BLOCK)
+k_ad_minmax(const u64* __restrict__ keys, i64 n, u64* __restrict__ tmin, u64* __restrict__ tmax)
+{
+    __shared__ u64 lmax[RS_WAVES], lmin[RS_WAVES];
+    const i64 t0 = (i64)blockIdx.x * AD_TILE;
+    u64 mx = 0, mn = ~0ull;
+    for (int j = threadIdx.x; j < AD_TILE; j += RS_BLOCK) {
+        const i64 i = t0 + j;
+        if (i < n) {
+            const u64 k = keys[i];
+            mx = k > mx ? k : mx;
+            mn = k < mn ? k : mn;
+        }
+    }
+    u64 pm, sm;
+    block_pmax_smin<RS_BLOCK>(mx, mn, lmax, lmin, pm, sm);
+    // the last thread's exclusive prefix max plus its own is the tile max
+    if (threadIdx.x == RS_BLOCK - 1) tmax[blockIdx.x] = mx > pm ? mx : pm;
+    if (threadIdx.x == 0) tmin[blockIdx.x] = mn < sm ? mn : sm;
+}
+
+// One block: pmax[t] = max of the tile maxima before t (0 for t = 0),
+// smin[t] = min of the tile minima after t (all ones for the last tile).
+__global__ void __launch_bounds__(AD_SCAN)
+k_ad_tilescan(const u64* __restrict__ tmin, const u64* __restrict__ tmax, i64 ntiles,
+              u64* __restrict__ pmax, u64* __restrict__ smin)
+{
+    __shared__ u64 lmax[AD_SCAN / WAVE], lmin[AD_SCAN / WAVE];
+    const i64 per = (ntiles + AD_SCAN - 1) / AD_SCAN;
+    const i64 a0 = (i64)threadIdx.x * per, a1 = (a0 + per) < ntiles ? (a0 + per) : ntiles;
+    u64 mx = 0, mn = ~0ull;
+    for (i64 t = a0; t < a1; ++t) {
+        mx = tmax[t] > mx ? tmax[t] : mx;
+        mn = tmin[t] < mn ? tmin[t] : mn;
+    }
+    u64 pm, sm;
+    block_pmax_smin<AD_SCAN>(mx, mn, lmax, lmin, pm, sm);
+    for (i64 t = a0; t < a1; ++t) {
+        pmax[t] = pm;
+        pm = tmax[t] > pm ? tmax[t] : pm;
+    }
+    for (i64 t = a1 - 1; t >= a0; --t) {
+        smin[t] = sm;
+        sm = tmin[t] < sm ? tmin[t] : sm;
+    }
+}
+
+// Classifies a tile's elements (out of place: a larger key before or a
+// smaller one after).  COMPACT = false: writes the tile's count of out-of-
+// place elements.  COMPACT = true: writes the in-place ones to R (at their
+// index minus the out-of-place ones before them) and the others to O (at the
+// tile's offset toff plus their rank), both in index order.
+template <bool COMPACT>
+__global__ void __launch_bounds__(RS_BLOCK)
+k_ad_classify(const u64* __restrict__ keys, const u32* __restrict__ vals, i64 n,
+              const u64* __restrict__ pmax, const u64* __restrict__ smin, u32* __restrict__ tcnt,
+              const u32* __restrict__ toff, u64* __restrict__ rk, u32* __restrict__ rv,
+              u64* __restrict__ ok, u32* __restrict__ ov)
+{
+    __shared__ u64 s_k[AD_TILE];
+    __shared__ u16 s_rank[AD_TILE];              // out-of-place elements before j; bit 15: j is one
+    __shared__ u64 lmax[RS_WAVES], lmin[RS_WAVES];
+    __shared__ u32 s_cnt[RS_WAVES];
+    const i64 tile = blockIdx.x, t0 = tile * AD_TILE;
+    const i64 cnt = (n - t0) < AD_TILE ? (n - t0) : AD_TILE;
+    for (int j = threadIdx.x; j < AD_TILE; j += RS_BLOCK) s_k[j] = j < cnt ? keys[t0 + j] : ~0ull;
+    __syncthreads();
+    // blocked: thread t holds elements RS_ITEMS t .. RS_ITEMS t + RS_ITEMS - 1
+    const int b0 = threadIdx.x * RS_ITEMS;
+    u64 mx = 0, mn = ~0ull;
+#pragma unroll
+    for (int q = 0; q < RS_ITEMS; ++q) {
+        const u64 k = s_k[b0 + q];
+        mx = k > mx ? k : mx;
+        mn = k < mn ? k : mn;
+    }
+    u64 pm, sm;
+    block_pmax_smin<RS_BLOCK>(mx, mn, lmax, lmin, pm, sm);
+    const u64 tp = pmax[tile], ts = smin[tile];
+    pm = tp > pm ? tp : pm;
+    sm = ts < sm ? ts : sm;
+    // suffix minima of the thread's own items, then a forward pass
+    u64 suf[RS_ITEMS];
+    {
+        u64 r = sm;
+#pragma unroll
+        for (int q = RS_ITEMS - 1; q >= 0; --q) {
+            suf[q] = r;
+            const u64 k = s_k[b0 + q];
+            r = k < r ? k : r;
+        }
+    }
+    u32 flags = 0, nown = 0;
+    {
+        u64 r = pm;
+#pragma unroll
+        for (int q = 0; q < RS_ITEMS; ++q) {
+            const u64 k = s_k[b0 + q];
+            const bool out = (b0 + q < cnt) && (k < r || k > suf[q]);
+            flags |= (out ? 1u : 0u) << q;
+            r = k > r ? k : r;
+        }
+        nown = (u32)__popc(flags);
+    }
+    // rank of each out-of-place element within the tile
+    u32 total;
+    {
+        const int lane = __lane_id(), wid = threadIdx.x / WAVE;
+        const u32 incl = wave_incl_scan(nown);
+        if (lane == WAVE - 1) s_cnt[wid] = incl;
+        __syncthreads();
+        u32 before = 0;
+        total = 0;
+        for (int w = 0; w < RS_WAVES; ++w) {
+            before += w < wid ? s_cnt[w] : 0u;
+            total += s_cnt[w];
+        }
+        u32 r = before + incl - nown;
+#pragma unroll
+        for (int q = 0; q < RS_ITEMS; ++q) {
+            const bool out = (flags >> q) & 1u;
+            s_rank[b0 + q] = (u16)(r | (out ? 0x8000u : 0u));
+            r += out ? 1u : 0u;
+        }
+    }
+    if (!COMPACT) {
+        if (threadIdx.x == 0) tcnt[tile] = total;
+        return;
+    }
+    __syncthreads();
+    const u32 base = toff[tile];
+    for (int j = threadIdx.x; j < cnt; j += RS_BLOCK) {
+        const u32 r = s_rank[j];
+        const i64 i = t0 + j;
+        const u64 k = s_k[j];
+        const u32 v = vals[i];
+        if (r & 0x8000u) {
+            const u32 o = base + (r & 0x7fffu);
+            ok[o] = k;
+            ov[o] = v;
+        } else {
+            const i64 ri = i - (i64)(base + r);
+            rk[ri] = k;
+            rv[ri] = v;
+        }
+    }
+}
+
+// One block: exclusive scan of the tile counts, total in toff[ntiles].
+__global__ void __launch_bounds__(AD_SCAN)
+k_ad_cntscan(const u32* __restrict__ tcnt, i64 ntiles, u32* __restrict__ toff)
+{
+    __shared__ u32 scr[AD_SCAN / WAVE];
+    const i64 per = (ntiles + AD_SCAN - 1) / AD_SCAN;
+    const i64 a0 = (i64)threadIdx.x * per, a1 = (a0 + per) < ntiles ? (a0 + per) : ntiles;
+    u32 s = 0;
+    for (i64 t = a0; t < a1; ++t) s += tcnt[t];
+    u32 tot;
+    u32 r = block_excl_scan<AD_SCAN>(s, scr, tot);
+    for (i64 t = a0; t < a1; ++t) {
+        toff[t] = r;
+        r += tcnt[t];
+    }
+    if (threadIdx.x == 0) toff[ntiles] = tot;
+}
+
+// Number of O elements ordered before (key, val) (lower bound by (key, val)).
+__device__ inline i64 o_before(const u64* ok, const u32* ov, i64 no, u64 k, u32 v)
+{
+    i64 lo = 0, hi = no;
+    while (lo < hi) {
+        const i64 mid = (lo + hi) >> 1;
+        const u64 km = ok[mid];
+        if (km < k || (km == k && ov[mid] < v)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Merge: R element j goes to j + (O elements before it); the O elements
+// ranked between R elements j-1 and j go right before it, and those after
+// the last R element follow it.
+__global__ void __launch_bounds__(RS_BLOCK)
+k_ad_merge(const u64* __restrict__ rk, const u32* __restrict__ rv, i64 nr,
+           const u64* __restrict__ ok, const u32* __restrict__ ov, i64 no, u64* __restrict__ outk,
+           u32* __restrict__ outv)
+{
+    const i64 j = (i64)blockIdx.x * RS_BLOCK + threadIdx.x;
+    if (j >= nr) return;
+    const u64 k = rk[j];
+    const u32 v = rv[j];
+    const i64 c = o_before(ok, ov, no, k, v);
+    const i64 cp = j > 0 ? o_before(ok, ov, no, rk[j - 1], rv[j - 1]) : 0;
+    outk[j + c] = k;
+    outv[j + c] = v;
+    for (i64 q = cp; q < c; ++q) {
+        outk[j + q] = ok[q];
+        outv[j + q] = ov[q];
+    }
+    if (j == nr - 1)
+        for (i64 q = c; q < no; ++q) {
+            outk[nr + q] = ok[q];
+            outv[nr + q] = ov[q];
+        }
+}
+
+__global__ void k_ad_copy(const u64* __restrict__ ok, const u32* __restrict__ ov, i64 no,
+                          u64* __restrict__ outk, u32* __restrict__ outv)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < no) {
+        outk[i] = ok[i];
+        outv[i] = ov[i];
+    }
+}
+
+static i64 radix_base_words(i64 n)
+{
+    const i64 ntiles = std::max<i64>(1, (n + RS_TILE - 1) / RS_TILE);
+    return 2 * RS_MAXP * RS_BINS + RS_MAXP + (i64)RS_MAXP * ntiles * RS_BINS;
+}
+
+// Adaptive part of the state (single-instance sorts): tile min/max and their
+// scans (4 x ntiles u64), tile counts and offsets, O keys and values twice
+// (ping-pong of the radix passes), n/8 each.
+static i64 adaptive_words(i64 n)
+{
+    const i64 ntiles = std::max<i64>(1, (n + AD_TILE - 1) / AD_TILE);
+    const i64 omax = n / 8 + 1;
+    return 8 * ntiles + 2 * ntiles + 2 + 4 * omax + 2 * omax + 8;
+}
+
+size_t radix_state_words(i64 n, int nseg)
+{
+    i64 w = radix_base_words(n);
+    if (nseg <= 1) w += (w & 1) + adaptive_words(n);
+    return (size_t)w;
+}
+
+// The radix passes (full sort) into the ping-pong pair; returns the side.
+static int radix_passes(u64* k0, u32* v0, u64* k1, u32* v1, i64 n, int key_bits,
+                        const i64* seg_off, int nseg, u32* state, u32* err, hipStream_t st)
+{
     const i64 ntiles = (n + RS_TILE - 1) / RS_TILE;
     const int pk = (key_bits + RS_BITS - 1) / RS_BITS;
     int ps = 0;
@@ -309,6 +585,70 @@ int radix_sort_pairs(u64* k0, u32* v0, u64* k1, u32* v1, i64 n, int key_bits,
         cur ^= 1;
     }
     return cur;
+}
+
+// Sorts (keys, vals) over key bits [0, key_bits) and then, when nseg > 1,
+// stably by the instance id of the original index.  Buffers ping-pong between
+// (k0,v0) and (k1,v1); the return value says which pair holds the result
+// (0 -> k0/v0, 1 -> k1/v1), or -1 for n >= 2^30 (not supported).  `state`
+// holds radix_state_words(n, nseg) words; `err` (device) gets bit 0 set if a
+// look-back wait ran past its bound.  With nseg <= 1 and `host_word`
+// (pinned host memory) given, nearly sorted input takes the adaptive path
+// (one host synchronisation to read the out-of-place count); it needs the
+// values to increase with the index (the key kernel's iota).
+int radix_sort_pairs(u64* k0, u32* v0, u64* k1, u32* v1, i64 n, int key_bits,
+                     const i64* seg_off, int nseg, u32* state, u32* err, u32* host_word,
+                     hipStream_t st)
+{
+    if (n <= 1) return 0;
+    if (n >= (i64)ST_VAL) return -1;
+    if (nseg <= 1 && host_word && n >= 2 * AD_TILE) {
+        const i64 ntiles = (n + AD_TILE - 1) / AD_TILE;
+        const i64 omax = n / 8;
+        i64 off = radix_base_words(n);
+        off += off & 1;                                   // u64 alignment
+        u64* tmin = (u64*)(state + off);
+        u64* tmax = tmin + ntiles;
+        u64* pmax = tmax + ntiles;
+        u64* smin = pmax + ntiles;
+        u32* tcnt = (u32*)(smin + ntiles);
+        u32* toff = tcnt + ntiles;                        // ntiles + 1
+        u64* oka = (u64*)(toff + ntiles + 2);            // 2 ntiles + 2 words past tcnt: aligned
+        u64* okb = oka + omax + 1;
+        u32* ova = (u32*)(okb + omax + 1);
+        u32* ovb = ova + omax + 1;
+        hipLaunchKernelGGL(k_ad_minmax, dim3((unsigned)ntiles), dim3(RS_BLOCK), 0, st, k0, n, tmin,
+                           tmax);
+        hipLaunchKernelGGL(k_ad_tilescan, dim3(1), dim3(AD_SCAN), 0, st, tmin, tmax, ntiles, pmax,
+                           smin);
+        hipLaunchKernelGGL((k_ad_classify<false>), dim3((unsigned)ntiles), dim3(RS_BLOCK), 0, st,
+                           k0, v0, n, pmax, smin, tcnt, nullptr, nullptr, nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL(k_ad_cntscan, dim3(1), dim3(AD_SCAN), 0, st, tcnt, ntiles, toff);
+        if (hipMemcpyAsync(host_word, toff + ntiles, sizeof(u32), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return -2;
+        const i64 no = *host_word;
+        if (no == 0) return 0;                            // already in order
+        if (no <= omax) {
+            const i64 nr = n - no;
+            hipLaunchKernelGGL((k_ad_classify<true>), dim3((unsigned)ntiles), dim3(RS_BLOCK), 0,
+                               st, k0, v0, n, pmax, smin, nullptr, toff, k1, v1, oka, ova);
+            int so = 0;
+            if (no > 1) so = radix_passes(oka, ova, okb, ovb, no, key_bits, nullptr, 1, state, err, st);
+            if (so < 0) return so;
+            const u64* osk = so ? okb : oka;
+            const u32* osv = so ? ovb : ova;
+            if (nr > 0)
+                hipLaunchKernelGGL(k_ad_merge, dim3((unsigned)((nr + RS_BLOCK - 1) / RS_BLOCK)),
+                                   dim3(RS_BLOCK), 0, st, k1, v1, nr, osk, osv, no, k0, v0);
+            else
+                hipLaunchKernelGGL(k_ad_copy, dim3((unsigned)((no + 255) / 256)), dim3(256), 0, st,
+                                   osk, osv, no, k0, v0);
+            return 0;
+        }
+    }
+    return radix_passes(k0, v0, k1, v1, n, key_bits, seg_off, nseg, state, err, st);
 }
 
 }  // namespace shsph

@@ -172,6 +172,44 @@ def test_stage2_walks(torch_cuda, name, make, n_red, mode):
         assert leaves.max() > 256
 
 
+@pytest.mark.parametrize("variant", ["sorted", "swaps", "far", "block", "dups", "many"])
+def test_sort_of_nearly_sorted_input(torch_cuda, variant):
+    """Keys in (nearly) the previous key order, as between steps: the sort's
+    in-place / out-of-place split and merge must give the stable sort, for an
+    already sorted input, local swaps, far jumps of single particles, a block
+    moved across the box, duplicated positions (ties), and a perturbation too
+    large for it (the full radix sort then runs)."""
+    _say(f"[sort] nearly sorted: {variant}")
+    p = gen.lattice(24, 13, dtype=np.float32)
+    keys = oracle.morton(p.x, p.y, p.z, p.lo, p.hi)
+    eps, _ = oracle.sort(keys)
+    q = p.subset(eps.astype(np.int64))
+    rng = np.random.default_rng(17)
+    n = q.n
+    if variant == "swaps":
+        for i in rng.choice(n - 1, size=150, replace=False):
+            for a in (q.x, q.y, q.z):
+                a[i], a[i + 1] = a[i + 1], a[i]
+    elif variant == "far":
+        for i, j in zip(rng.choice(n, 40, replace=False), rng.choice(n, 40, replace=False)):
+            q.x[i], q.y[i], q.z[i] = q.x[j], q.y[j], np.float32((float(q.z[j]) + 0.37) % 1.0)
+    elif variant == "block":
+        b = int(rng.integers(0, n - 64))
+        q.x[b:b + 64] = ((q.x[b:b + 64].astype(np.float64) + 0.25) % 1.0).astype(np.float32)
+    elif variant == "dups":
+        for i in rng.choice(n - 1, size=200, replace=False):
+            q.x[i + 1], q.y[i + 1], q.z[i + 1] = q.x[i], q.y[i], q.z[i]
+    elif variant == "many":
+        sel = rng.choice(n, size=n * 3 // 10, replace=False)
+        perm = rng.permutation(sel)
+        for a in (q.x, q.y, q.z):
+            a[sel] = a[perm]
+    ctx = _ctx(torch_cuda, n_red=3)
+    ctx.build_tree(_upload(q, torch_cuda))
+    check_tree(ctx, q, 3)
+    ctx.close()
+
+
 def test_tree_with_duplicate_positions(torch_cuda):
     _say("[tree] duplicates")
     base = gen.lattice(12, 9, dtype=np.float32)
