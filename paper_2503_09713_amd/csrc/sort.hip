@@ -260,9 +260,13 @@ k_rs_pass(const u64* __restrict__ kin, const u32* __restrict__ vin, u64* __restr
 
 // ---------------------------------------------------------------------------
 // Nearly sorted input.  Between steps the particles keep their previous key
-// order and few of them change place.  Element i is "in place" when no
-// earlier key is larger and no later key smaller; the in-place elements (R)
-// form a sorted sequence in index order.  The others (O) are sorted by the
+// order and few of them change place.  An isolated spike (a key out of order
+// with its neighbours while the neighbours are in order with each other: one
+// particle that jumped) is set aside first; of the other elements, one is
+// "in place" when no earlier non-spike key is larger and no later one
+// smaller.  The in-place elements (R) form a sorted sequence in index order,
+// and a single far jump costs one out-of-place element, not the run it
+// jumped over.  The others (O) are sorted by the
 // radix passes and merged into R, both by (key, value).  With values that
 // increase with the index (the iota of the key kernel) ties keep the index
 // order on both sides, so the result is the stable sort.  Used when O holds
@@ -308,7 +312,12 @@ __device__ inline void block_pmax_smin(u64 vmax, u64 vmin, u64* lmax, u64* lmin,
     sm = lane < WAVE - 1 ? (eb < sw ? eb : sw) : sw;
 }
 
-// Per tile: the smallest and the largest key.
+__device__ inline int ad_sw(int j) { return j + (j >> 4); }
+
+// Isolated spike: key k between neighbours a <= b but out of order with them.
+__device__ inline bool ad_spike(u64 a, u64 k, u64 b) { return a <= b && (k < a || k > b); }
+
+// Per tile: the smallest and the largest key among the non-spikes.
 __global__ void __launch_bounds__(RS_BLOCK)
 k_ad_minmax(const u64* __restrict__ keys, i64 n, u64* __restrict__ tmin, u64* __restrict__ tmax)
 {
@@ -319,8 +328,11 @@ k_ad_minmax(const u64* __restrict__ keys, i64 n, u64* __restrict__ tmin, u64* __
         const i64 i = t0 + j;
         if (i < n) {
             const u64 k = keys[i];
-            mx = k > mx ? k : mx;
-            mn = k < mn ? k : mn;
+            const u64 a = i > 0 ? keys[i - 1] : 0ull, b = i + 1 < n ? keys[i + 1] : ~0ull;
+            if (!ad_spike(a, k, b)) {
+                mx = k > mx ? k : mx;
+                mn = k < mn ? k : mn;
+            }
         }
     }
     u64 pm, sm;
@@ -368,20 +380,33 @@ k_ad_classify(const u64* __restrict__ keys, const u32* __restrict__ vals, i64 n,
               const u32* __restrict__ toff, u64* __restrict__ rk, u32* __restrict__ rv,
               u64* __restrict__ ok, u32* __restrict__ ov)
 {
-    __shared__ u64 s_k[AD_TILE];
-    __shared__ u16 s_rank[AD_TILE];              // out-of-place elements before j; bit 15: j is one
+    // element j at j + j/16: the blocked reads (16 consecutive elements per
+    // thread) then fall on different banks
+    __shared__ u64 s_k[AD_TILE + AD_TILE / 16];
+    __shared__ u16 s_rank[AD_TILE + AD_TILE / 16];  // out-of-place elements before j; bit 15: j is one
     __shared__ u64 lmax[RS_WAVES], lmin[RS_WAVES];
     __shared__ u32 s_cnt[RS_WAVES];
     const i64 tile = blockIdx.x, t0 = tile * AD_TILE;
     const i64 cnt = (n - t0) < AD_TILE ? (n - t0) : AD_TILE;
-    for (int j = threadIdx.x; j < AD_TILE; j += RS_BLOCK) s_k[j] = j < cnt ? keys[t0 + j] : ~0ull;
+    for (int j = threadIdx.x; j < AD_TILE; j += RS_BLOCK) s_k[ad_sw(j)] = j < cnt ? keys[t0 + j] : ~0ull;
+    const u64 kprev = t0 > 0 ? keys[t0 - 1] : 0ull;            // neighbours across the tile
+    const u64 knext = t0 + cnt < n ? keys[t0 + cnt] : ~0ull;
     __syncthreads();
     // blocked: thread t holds elements RS_ITEMS t .. RS_ITEMS t + RS_ITEMS - 1
     const int b0 = threadIdx.x * RS_ITEMS;
+    u32 spikes = 0;
+#pragma unroll
+    for (int q = 0; q < RS_ITEMS; ++q) {
+        const int j = b0 + q;
+        const u64 a = j > 0 ? s_k[ad_sw(j - 1)] : kprev;
+        const u64 b = j + 1 < AD_TILE ? (j + 1 < cnt ? s_k[ad_sw(j + 1)] : knext) : knext;
+        spikes |= (j < cnt && ad_spike(a, s_k[ad_sw(j)], b) ? 1u : 0u) << q;
+    }
     u64 mx = 0, mn = ~0ull;
 #pragma unroll
     for (int q = 0; q < RS_ITEMS; ++q) {
-        const u64 k = s_k[b0 + q];
+        if ((spikes >> q) & 1u) continue;
+        const u64 k = s_k[ad_sw(b0 + q)];
         mx = k > mx ? k : mx;
         mn = k < mn ? k : mn;
     }
@@ -397,8 +422,8 @@ k_ad_classify(const u64* __restrict__ keys, const u32* __restrict__ vals, i64 n,
 #pragma unroll
         for (int q = RS_ITEMS - 1; q >= 0; --q) {
             suf[q] = r;
-            const u64 k = s_k[b0 + q];
-            r = k < r ? k : r;
+            const u64 k = s_k[ad_sw(b0 + q)];
+            if (!((spikes >> q) & 1u)) r = k < r ? k : r;
         }
     }
     u32 flags = 0, nown = 0;
@@ -406,10 +431,11 @@ k_ad_classify(const u64* __restrict__ keys, const u32* __restrict__ vals, i64 n,
         u64 r = pm;
 #pragma unroll
         for (int q = 0; q < RS_ITEMS; ++q) {
-            const u64 k = s_k[b0 + q];
-            const bool out = (b0 + q < cnt) && (k < r || k > suf[q]);
+            const u64 k = s_k[ad_sw(b0 + q)];
+            const bool sp = (spikes >> q) & 1u;
+            const bool out = (b0 + q < cnt) && (sp || k < r || k > suf[q]);
             flags |= (out ? 1u : 0u) << q;
-            r = k > r ? k : r;
+            if (!sp) r = k > r ? k : r;
         }
         nown = (u32)__popc(flags);
     }
@@ -430,7 +456,7 @@ k_ad_classify(const u64* __restrict__ keys, const u32* __restrict__ vals, i64 n,
 #pragma unroll
         for (int q = 0; q < RS_ITEMS; ++q) {
             const bool out = (flags >> q) & 1u;
-            s_rank[b0 + q] = (u16)(r | (out ? 0x8000u : 0u));
+            s_rank[ad_sw(b0 + q)] = (u16)(r | (out ? 0x8000u : 0u));
             r += out ? 1u : 0u;
         }
     }
@@ -441,9 +467,9 @@ k_ad_classify(const u64* __restrict__ keys, const u32* __restrict__ vals, i64 n,
     __syncthreads();
     const u32 base = toff[tile];
     for (int j = threadIdx.x; j < cnt; j += RS_BLOCK) {
-        const u32 r = s_rank[j];
+        const u32 r = s_rank[ad_sw(j)];
         const i64 i = t0 + j;
-        const u64 k = s_k[j];
+        const u64 k = s_k[ad_sw(j)];
         const u32 v = vals[i];
         if (r & 0x8000u) {
             const u32 o = base + (r & 0x7fffu);
@@ -488,31 +514,92 @@ __device__ inline i64 o_before(const u64* ok, const u32* ov, i64 no, u64 k, u32 
     return lo;
 }
 
-// Merge: R element j goes to j + (O elements before it); the O elements
-// ranked between R elements j-1 and j go right before it, and those after
-// the last R element follow it.
+// Merge, R side, one tile of R per workgroup: R element j goes to j + c_j,
+// c_j = the O elements before it.  c is monotone, so the tile's first and
+// last elements bound the O range its elements search (usually empty).
+// Per R tile: c of its first and of its last element (one thread each).
+__global__ void k_ad_bounds(const u64* __restrict__ rk, const u32* __restrict__ rv, i64 nr,
+                            const u64* __restrict__ ok, const u32* __restrict__ ov, i64 no,
+                            u32* __restrict__ cfirst, u32* __restrict__ clast)
+{
+    const i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const i64 t = u >> 1;
+    const i64 j0 = t * AD_TILE;
+    if (j0 >= nr) return;
+    const i64 j = (u & 1) ? ((j0 + AD_TILE) < nr ? (j0 + AD_TILE) : nr) - 1 : j0;
+    const u32 c = (u32)o_before(ok, ov, no, rk[j], rv[j]);
+    if (u & 1) clast[t] = c;
+    else cfirst[t] = c;
+}
+
 __global__ void __launch_bounds__(RS_BLOCK)
 k_ad_merge(const u64* __restrict__ rk, const u32* __restrict__ rv, i64 nr,
-           const u64* __restrict__ ok, const u32* __restrict__ ov, i64 no, u64* __restrict__ outk,
+           const u64* __restrict__ ok, const u32* __restrict__ ov, i64 no,
+           const u32* __restrict__ cfirst, const u32* __restrict__ clast, u64* __restrict__ outk,
            u32* __restrict__ outv)
 {
-    const i64 j = (i64)blockIdx.x * RS_BLOCK + threadIdx.x;
-    if (j >= nr) return;
-    const u64 k = rk[j];
-    const u32 v = rv[j];
-    const i64 c = o_before(ok, ov, no, k, v);
-    const i64 cp = j > 0 ? o_before(ok, ov, no, rk[j - 1], rv[j - 1]) : 0;
-    outk[j + c] = k;
-    outv[j + c] = v;
-    for (i64 q = cp; q < c; ++q) {
-        outk[j + q] = ok[q];
-        outv[j + q] = ov[q];
+    constexpr int OL = 1024;                     // O range staged in LDS up to this size
+    __shared__ u64 s_ok[OL];
+    __shared__ u32 s_ov[OL];
+    const i64 j0 = (i64)blockIdx.x * AD_TILE;
+    const i64 cnt = (nr - j0) < AD_TILE ? (nr - j0) : AD_TILE;
+    const i64 lo = cfirst[blockIdx.x], hi = clast[blockIdx.x];
+    // the tile's R elements, all loads issued first
+    u64 kk[RS_ITEMS];
+    u32 vv[RS_ITEMS];
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const int j = threadIdx.x + it * RS_BLOCK;
+        kk[it] = j < cnt ? rk[j0 + j] : 0ull;
+        vv[it] = j < cnt ? rv[j0 + j] : 0u;
     }
-    if (j == nr - 1)
-        for (i64 q = c; q < no; ++q) {
-            outk[nr + q] = ok[q];
-            outv[nr + q] = ov[q];
+    u32 cc[RS_ITEMS];
+    if (lo == hi) {                              // no O element falls inside this tile
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) cc[it] = (u32)lo;
+    } else {
+        const bool staged = hi - lo <= OL;
+        if (staged) {
+            for (i64 q = threadIdx.x; q < hi - lo; q += RS_BLOCK) {
+                s_ok[q] = ok[lo + q];
+                s_ov[q] = ov[lo + q];
+            }
         }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it)
+            cc[it] = (u32)(lo + (staged ? o_before(s_ok, s_ov, hi - lo, kk[it], vv[it])
+                                        : o_before(ok + lo, ov + lo, hi - lo, kk[it], vv[it])));
+    }
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const int j = threadIdx.x + it * RS_BLOCK;
+        if (j < cnt) {
+            outk[j0 + j + cc[it]] = kk[it];
+            outv[j0 + j + cc[it]] = vv[it];
+        }
+    }
+}
+
+// O element q goes to q + (R elements before it): a binary search over R by
+// (key, value), one thread per O element.
+__global__ void k_ad_place_o(const u64* __restrict__ rk, const u32* __restrict__ rv, i64 nr,
+                             const u64* __restrict__ ok, const u32* __restrict__ ov, i64 no,
+                             u64* __restrict__ outk, u32* __restrict__ outv)
+{
+    const i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= no) return;
+    const u64 k = ok[q];
+    const u32 v = ov[q];
+    i64 lo = 0, hi = nr;
+    while (lo < hi) {
+        const i64 mid = (lo + hi) >> 1;
+        const u64 km = rk[mid];
+        if (km < k || (km == k && rv[mid] < v)) lo = mid + 1;
+        else hi = mid;
+    }
+    outk[q + lo] = k;
+    outv[q + lo] = v;
 }
 
 __global__ void k_ad_copy(const u64* __restrict__ ok, const u32* __restrict__ ov, i64 no,
@@ -639,9 +726,17 @@ int radix_sort_pairs(u64* k0, u32* v0, u64* k1, u32* v1, i64 n, int key_bits,
             if (so < 0) return so;
             const u64* osk = so ? okb : oka;
             const u32* osv = so ? ovb : ova;
-            if (nr > 0)
-                hipLaunchKernelGGL(k_ad_merge, dim3((unsigned)((nr + RS_BLOCK - 1) / RS_BLOCK)),
-                                   dim3(RS_BLOCK), 0, st, k1, v1, nr, osk, osv, no, k0, v0);
+            if (nr > 0) {
+                const i64 rt = (nr + AD_TILE - 1) / AD_TILE;
+                u32* cfirst = tcnt;                       // the tile counts are no longer needed
+                u32* clast = (u32*)pmax;                  // nor the prefix maxima
+                hipLaunchKernelGGL(k_ad_bounds, dim3((unsigned)((2 * rt + 255) / 256)), dim3(256), 0,
+                                   st, k1, v1, nr, osk, osv, no, cfirst, clast);
+                hipLaunchKernelGGL(k_ad_merge, dim3((unsigned)rt), dim3(RS_BLOCK), 0, st, k1, v1,
+                                   nr, osk, osv, no, cfirst, clast, k0, v0);
+                hipLaunchKernelGGL(k_ad_place_o, dim3((unsigned)((no + 255) / 256)), dim3(256), 0,
+                                   st, k1, v1, nr, osk, osv, no, k0, v0);
+            }
             else
                 hipLaunchKernelGGL(k_ad_copy, dim3((unsigned)((no + 255) / 256)), dim3(256), 0, st,
                                    osk, osv, no, k0, v0);
