@@ -97,6 +97,23 @@ template <class T> __device__ inline T wave_incl_scan(T x)
     return x;
 }
 
+// The same inclusive sum for 32-bit integers with DPP lane moves (no LDS
+// round trips): shifts by 1, 2, 4, 8 within each row of 16 lanes, then the
+// total of row 0 added into row 1 and of row 2 into row 3 (row_bcast:15),
+// then the total of rows 0-1 into rows 2-3 (row_bcast:31).  Lanes a move
+// does not write, or whose source lies outside the row, receive 0.
+__device__ inline u32 wave_incl_scan_dpp(u32 x)
+{
+    int v = (int)x;
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);    // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);    // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);    // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);    // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return (u32)v;
+}
+
 template <class T> __device__ inline T wave_sum(T x)
 {
 #pragma unroll

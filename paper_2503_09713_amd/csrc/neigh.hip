@@ -62,9 +62,10 @@ __device__ inline bool box_hit(const vec4<T>& al, const vec4<T>& ah, const vec4<
 {
     const T r = rk * fmax(al.w, bl.w) * (T(1) + Inflate<T>::rel) + eps_abs;
     const int per = WRAP ? bx.periodic : 0;
-    return gap1<T>(al.x, ah.x, bl.x, bh.x, bx.L[0], per) <= r &&
-           gap1<T>(al.y, ah.y, bl.y, bh.y, bx.L[1], per) <= r &&
-           gap1<T>(al.z, ah.z, bl.z, bh.z, bx.L[2], per) <= r;
+    // all three axes evaluated (no short circuit): one branch-free test
+    return (gap1<T>(al.x, ah.x, bl.x, bh.x, bx.L[0], per) <= r) &
+           (gap1<T>(al.y, ah.y, bl.y, bh.y, bx.L[1], per) <= r) &
+           (gap1<T>(al.z, ah.z, bl.z, bh.z, bx.L[2], per) <= r);
 }
 
 // A box at least r_all = rk h_max(all) 1.001 + 2 eps_abs + 1e-5 (Lx+Ly+Lz)
@@ -231,9 +232,13 @@ constexpr u32 S1_WIDE = 0xfffffffeu;    // ucnt marker: group left to the full w
 constexpr int S1_TS = 32;               // target runs (mask bits)
 constexpr u32 S1_FINAL = 0x80000000u;      // stack entry: an accepted leaf
 
+// Orders one wave's LDS accesses across its lanes.  A wave's LDS
+// instructions are performed in issue order, so only the compiler must keep
+// them in place: a wavefront-scope fence (no wait on the wave's outstanding
+// global stores) and a wave barrier.
 __device__ inline void wave_lds_sync()
 {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -308,14 +313,28 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
         }
         wave_lds_sync();                       // popped before anything is pushed over them
         const u32 v = e & ~S1_FINAL;
+        // one round of loads per iteration: the node's box and its pair of
+        // pointers (children of an internal node, particle range of a leaf)
+        const bool act = lane < take_n, fin = (e & S1_FINAL) != 0u;
+        const bool is_leaf = v >= (u32)n_internal;
+        u32 p0 = 0, p1 = 0;
+        vec4<T> nl{}, nh{};
+        if (act) {
+            const u32* pp = is_leaf ? id + (v - (u32)n_internal) : child + 2 * (u64)v;
+            p0 = pp[0];
+            p1 = pp[1];
+            if (!fin) {
+                nl = blo[v];
+                nh = bhi[v];
+            }
+        }
         bool keep = false, leaf = false;
         u32 cm = 0;
-        if (lane < take_n) {
-            if (e & S1_FINAL) {
+        if (act) {
+            if (fin) {
                 keep = true;
                 leaf = true;
             } else {
-                const vec4<T> nl = blo[v], nh = bhi[v];
                 if (box_hit<T>(ql, qh, nl, nh, rk, eps_abs, bx)) {
                     if (!FULL || compact) cm = m;
                     else while (m) {
@@ -329,7 +348,7 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
                             }
                     }
                     keep = cm != 0u;
-                    leaf = v >= (u32)n_internal;
+                    leaf = is_leaf;
                 }
             }
         }
@@ -339,13 +358,15 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
         const bool emit = keep && leaf && lane < first_int;
         const bool defer = keep && leaf && lane > first_int;
         const u32 nres = (keep && !leaf) ? 2u : (defer ? 1u : 0u);
-        const u32 rincl = wave_incl_scan(nres);
-        const u32 rtot = __shfl(rincl, WAVE - 1, WAVE);
+        // nres is 0, 1 or 2: its prefix sum is two masked population counts
+        const u64 b1 = __ballot(nres >= 1u), b2 = __ballot(nres == 2u);
+        const u32 rincl = (u32)__popcll(b1 & lanemask_lt()) + (u32)__popcll(b2 & lanemask_lt()) + nres;
+        const u32 rtot = (u32)__popcll(b1) + (u32)__popcll(b2);
         if (base + rtot > (u32)S1_SMAX) { over = true; break; }
         // emitted leaves: ascending, with their slot starts
         const u64 bem = __ballot(emit);
-        const u32 sz = emit ? id[v - (u32)n_internal + 1] - id[v - (u32)n_internal] : 0u;
-        const u32 sincl = wave_incl_scan(sz);
+        const u32 sz = emit ? p1 - p0 : 0u;
+        const u32 sincl = wave_incl_scan_dpp(sz);
         if (emit) {
             const u32 q = count + (u32)__popcll(bem & lanemask_lt());
             if ((i64)q < cap) {
@@ -354,12 +375,12 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
             }
         }
         count += (u32)__popcll(bem);
-        slots += __shfl(sincl, WAVE - 1, WAVE);
+        slots += (u32)__builtin_amdgcn_readlane((int)sincl, WAVE - 1);
         // push back: result r (0 = leftmost) goes to base + rtot - 1 - r
         const u32 r0 = rincl - nres;
         if (keep && !leaf) {
-            s_sn[w][base + rtot - 1u - r0] = child[2 * (u64)v];
-            s_sn[w][base + rtot - 2u - r0] = child[2 * (u64)v + 1];
+            s_sn[w][base + rtot - 1u - r0] = p0;
+            s_sn[w][base + rtot - 2u - r0] = p1;
             if (FULL) {
                 s_sm[w][base + rtot - 1u - r0] = cm;
                 s_sm[w][base + rtot - 2u - r0] = cm;
