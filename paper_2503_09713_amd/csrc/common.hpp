@@ -226,26 +226,29 @@ __device__ inline u32 slot_of(u64 w, u32 r) { return (u32)(w >> (16u * r)) & 0xf
 // ------------------------------------------------------------- M4 spline --
 // f(q) = 1 - 3/2 q^2 + 3/4 q^3 (q<1), (2-q)^3/4 (1<=q<2), 0 beyond;
 // C_norm = 1/pi in 3D; the support radius is 2h (Sect. 2.1).
-// Both pieces are evaluated and selected (no divergent branches).
+// Both pieces are evaluated and selected (no divergent branches); the outer
+// piece uses t = max(2 - q, 0), so it is zero from q = 2 on by itself and a
+// single select remains.
+
 template <class T> __device__ inline void m4(T q, T& f, T& df)
 {
-    const T t = T(2) - q;
+    const T t = fmax(T(2) - q, T(0));
     const T t2 = t * t;
     const T fi = T(1) + q * q * (T(0.75) * q - T(1.5));
     const T dfi = q * (T(2.25) * q - T(3));
     const T fo = T(0.25) * t2 * t;
     const T dfo = T(-0.75) * t2;
-    const bool in1 = q < T(1), in2 = q < T(2);
-    f = in1 ? fi : (in2 ? fo : T(0));
-    df = in1 ? dfi : (in2 ? dfo : T(0));
+    const bool in1 = q < T(1);
+    f = in1 ? fi : fo;
+    df = in1 ? dfi : dfo;
 }
 
 template <class T> __device__ inline T m4_df(T q)
 {
-    const T t = T(2) - q;
+    const T t = fmax(T(2) - q, T(0));
     const T dfi = q * (T(2.25) * q - T(3));
     const T dfo = T(-0.75) * t * t;
-    return q < T(1) ? dfi : (q < T(2) ? dfo : T(0));
+    return q < T(1) ? dfi : dfo;
 }
 
 template <class T> __device__ inline T inv_pi() { return T(0.318309886183790671537767526745); }
