@@ -47,10 +47,32 @@ WORK_KEYS = {"particle_cache": ("cache_tests", "cache_prune_tests"),
 # kernel's sources at the time: the figure is reported only while they match.
 TRAFFIC = {
     ("particle_cache", "sedov256"): {
-        "bytes_per_launch": 5.1157e9,     # FETCH 2.140 GB + WRITE 2.976 GB (k_group_cache<float, 1>)
-        "sources_sha256": "5221ade567f311866e2389ca6c5e014f4c0ec07a484cc6eefc51df221c7caca9"},
+        "bytes_per_launch": 5.1495e9,     # FETCH + WRITE of k_group_cache<float, 1>
+        "sources_sha256": "19f8e8399aa4daf37a3daa5d4c0e240db387fa812863e53b89be85e489eb195a"},
 }
 KERNEL_SOURCES = {"particle_cache": ("neigh.hip", "common.hpp", "kernels.hpp")}
+
+# Vector instructions the dominant kernel issues per launch (rocprofv3 --pmc
+# SQ_INSTS_VALU, wave instructions summed over the chip), with the sha256 of
+# its sources at the time.  Against the issue ceiling of one wave64 VALU
+# instruction per compute unit per clock (256 CUs at 2.4 GHz; a 64-lane FP32
+# operation occupies a SIMD for four clocks) it gives the fraction of the
+# launch the vector units were issuing.
+VALU_INSTS = {
+    ("particle_cache", "sedov256"): {
+        "valu_insts_per_launch": 1.3756e9,   # k_group_cache<float, 1>
+        "sources_sha256": "19f8e8399aa4daf37a3daa5d4c0e240db387fa812863e53b89be85e489eb195a"},
+}
+CU_COUNT, CLOCK_HZ = 256, 2.4e9
+
+
+def valu_issue_for(stage, workload, avg_ms):
+    t = VALU_INSTS.get((stage, workload))
+    if not t or t["sources_sha256"] != sources_sha(stage):
+        return None
+    n = t["valu_insts_per_launch"]
+    return {"valu_insts_per_launch": n,
+            "frac_of_issue_ceiling": round(n / (CU_COUNT * CLOCK_HZ * avg_ms * 1e-3), 4)}
 
 
 def sources_sha(stage):
@@ -459,7 +481,8 @@ def main():
                 "traffic": traffic_for(dom, args.workload),
                 "frac_of_nonpacked_peak": round(tf / FP32_PEAK_NONPACKED_TFLOPS, 4),
                 "avg_launch_ms": round(avg_ms, 4), "flop_per_launch": int(ops),
-                "hbm_algorithmic_GBs": round(hbm, 1), "bytes_per_launch": int(by)}
+                "hbm_algorithmic_GBs": round(hbm, 1), "bytes_per_launch": int(by),
+                "valu_issue": valu_issue_for(dom, args.workload, avg_ms)}
     else:
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4),

@@ -324,11 +324,18 @@ k_boxes_local(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 
         const u32 b0 = id[g], b1 = id[g + 1];
         vec4<T> p = posh[b0];
         lo0 = hi0 = p.x; lo1 = hi1 = p.y; lo2 = hi2 = p.z; hm = p.w;
-        for (u32 b = b0 + 1; b < b1; ++b) {
-            p = posh[b];
-            lo0 = fmin(lo0, p.x); lo1 = fmin(lo1, p.y); lo2 = fmin(lo2, p.z);
-            hi0 = fmax(hi0, p.x); hi1 = fmax(hi1, p.y); hi2 = fmax(hi2, p.z);
-            hm = fmax(hm, p.w);
+        // four independent loads in flight per round (a slot past the leaf
+        // repeats its first particle, which changes no min or max)
+        for (u32 b = b0 + 1; b < b1; b += 4) {
+            vec4<T> q[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[k] = posh[b + k < b1 ? b + k : b0];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                lo0 = fmin(lo0, q[k].x); lo1 = fmin(lo1, q[k].y); lo2 = fmin(lo2, q[k].z);
+                hi0 = fmax(hi0, q[k].x); hi1 = fmax(hi1, q[k].y); hi2 = fmax(hi2, q[k].z);
+                hm = fmax(hm, q[k].w);
+            }
         }
         const vec4<T> l = mk4<T>(lo0, lo1, lo2, hm), h = mk4<T>(hi0, hi1, hi2, T(0));
         s_llo[t] = l;
