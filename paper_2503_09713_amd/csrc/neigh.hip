@@ -465,10 +465,10 @@ __device__ inline bool cache_acc(const vec4<T>& pa, T qa, const Box<T>& bx, cons
 // position advances by the accept flag, so the packing costs no branch and no
 // variable shift per candidate.  After every group of up to four candidates
 // a completed ELL word (the first four entries) is copied to the cache and
-// the rest moves to the front.  At most 3 entries are pending before a group
-// and 7 after it.
-constexpr u32 QLEN = 8;
-constexpr u32 QSTRIDE = 12;   // u16 per lane: 8 entries + pad (24 B, 8-byte aligned)
+// the rest moves to the front; groups of eight candidates complete up to two
+// words.  At most 3 entries are pending before a group and 11 after it.
+constexpr u32 QLEN = 12;
+constexpr u32 QSTRIDE = QLEN; // u16 per lane (24 B, 8-byte aligned)
 
 struct LaneQueue {
     u16* e;       // this lane's entries in LDS
@@ -492,6 +492,20 @@ __device__ inline void queue_flush(LaneQueue& lq, u32 capq)
         ++lq.q;
         *(u64*)lq.e = *(const u64*)(lq.e + 4);
         lq.pos -= 4u;
+    }
+}
+
+// After a group of eight candidates: up to two completed words.
+__device__ inline void queue_flush2(LaneQueue& lq, u32 capq)
+{
+    if (lq.pos >= 4u) {
+        if (lq.q < capq) *lq.out = *(const u64*)lq.e;
+        lq.out += GROUP;
+        ++lq.q;
+        *(u64*)lq.e = *(const u64*)(lq.e + 4);
+        *(u64*)(lq.e + 4) = *(const u64*)(lq.e + 8);
+        lq.pos -= 4u;
+        queue_flush(lq, capq);
     }
 }
 
@@ -526,6 +540,15 @@ __device__ inline void cache_leaf(const vec4<T>& pa, T qa, const Box<T>& bx, T r
                                   const vec4<T>* posh, LaneQueue& lq, u32 capq)
 {
     u32 b = b0;
+    for (; b + 8 <= b1; b += 8) {         // eight candidate loads in flight
+        const u32 s = sl + (b - b0);
+        vec4<T> p[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) p[k] = LDS ? s_upos[s + k] : posh[b + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) queue_put(lq, s + k, cache_acc<T, LDS, WRAP>(pa, qa, bx, p[k], rkc));
+        queue_flush2(lq, capq);
+    }
     for (; b + 4 <= b1; b += 4) {
         const u32 s = sl + (b - b0);
         const vec4<T> p0 = LDS ? s_upos[s] : posh[b];
