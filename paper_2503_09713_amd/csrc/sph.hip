@@ -365,6 +365,7 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     const T hia4 = hia * hia * hia * hia * inv_pi<T>();
     const T hfa = hfact * hia;
     const T rhoa = m * hfa * hfa * hfa;
+    const T mhf3 = m * hfact * hfact * hfact;    // rho_b = mhf3 / h_b^3
     const T Aa = ta.x, Ba = ta.y, ca = ta.z, Pa = ta.w;
     const u32 cnt = live ? cv.ncnt[a] : 0u;
     const u32 nu = min((u32)cv.cap, cv.ucnt[g]);
@@ -399,7 +400,8 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         const T ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
         const T w = (va.x - vb.x) * ex + (va.y - vb.y) * ey + (va.z - vb.z) * ez;
         const T Fa = m4_df<T>(r * hia) * hia4;
-        const T Fb = m4_df<T>(r * hib) * (hib * hib * hib * hib * inv_pi<T>());
+        const T hib3 = hib * hib * hib;           // shared by F_b and rho_b
+        const T Fb = m4_df<T>(r * hib) * (hib3 * hib * inv_pi<T>());
         const T aw = fabs(w);
         const T vsa = alpha * ca + beta * aw;
         const T vsb = alpha * tb.z + beta * aw;
@@ -411,8 +413,7 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         ay -= fab * ey;
         az -= fab * ez;
         du += m * ka * w;
-        const T hfb = hfact * hib;
-        const T rhob = m * hfb * hfb * hfb;
+        const T rhob = mhf3 * hib3;
         const T vsu = fast_sqrt(fabs(Pa - tb.w)) * fast_rsq(T(0.5) * (rhoa + rhob));
         lam += m * beta_u * vsu * (va.w - vb.w) * T(0.5) * (Fa * Ba + Fb * tb.y);
         vmax = vsa > vmax ? vsa : vmax;
