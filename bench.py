@@ -47,8 +47,8 @@ WORK_KEYS = {"particle_cache": ("cache_tests", "cache_prune_tests"),
 # kernel's sources at the time: the figure is reported only while they match.
 TRAFFIC = {
     ("particle_cache", "sedov256"): {
-        "bytes_per_launch": 5.1495e9,     # FETCH + WRITE of k_group_cache<float, 1>
-        "sources_sha256": "19f8e8399aa4daf37a3daa5d4c0e240db387fa812863e53b89be85e489eb195a"},
+        "bytes_per_launch": 5.1340e9,     # FETCH + WRITE of k_group_cache<float, 1>
+        "sources_sha256": "549528224ef4679497ce9cff433dd8669a5ba207f57fbf809ee58bb37e8aa12e"},
 }
 KERNEL_SOURCES = {"particle_cache": ("neigh.hip", "common.hpp", "kernels.hpp")}
 
@@ -60,8 +60,8 @@ KERNEL_SOURCES = {"particle_cache": ("neigh.hip", "common.hpp", "kernels.hpp")}
 # launch the vector units were issuing.
 VALU_INSTS = {
     ("particle_cache", "sedov256"): {
-        "valu_insts_per_launch": 1.3756e9,   # k_group_cache<float, 1>
-        "sources_sha256": "19f8e8399aa4daf37a3daa5d4c0e240db387fa812863e53b89be85e489eb195a"},
+        "valu_insts_per_launch": 1.3808e9,   # k_group_cache<float, 1>
+        "sources_sha256": "549528224ef4679497ce9cff433dd8669a5ba207f57fbf809ee58bb37e8aa12e"},
 }
 CU_COUNT, CLOCK_HZ = 256, 2.4e9
 
