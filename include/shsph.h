@@ -45,12 +45,12 @@ typedef enum { SHSPH_F32 = 0, SHSPH_F64 = 1 } shsph_dtype;
 typedef struct shsph_ctx shsph_ctx;
 
 /* Method parameters.  Defaults (shsph_params_default) follow the paper:
- *   hfact = 1.2 for the M4 kernel and rho(h) = m (hfact/h)^3 (App. G, Eq. rhoh);
- *   chi = 1.1 ghost/cache tolerance and lambda = 1.2 Newton clamp (App. G);
+ *   hfact = 1.2 for the M4 kernel and rho(h) = m (hfact/h)^3 (App. F, Eq. rhoh);
+ *   chi = 1.1 ghost/cache tolerance and lambda = 1.2 Newton clamp (App. F);
  *   alpha_av = 1, beta_av = 2 artificial viscosity, beta_u = 1 conductivity
- *   (Sect. 2.1 and Sect. 4.2); c_cour = 0.3, c_force = 0.25 (App. H.2);
+ *   (Sect. 2.1 and Sect. 4.2); c_cour = 0.3, c_force = 0.25 (App. G.2);
  *   gamma = 5/3 adiabatic EOS; eps_h = 1e-6 Newton tolerance (the paper
- *   leaves it open), max_iter = 50; n_red = 3 reduction passes (App. D.2). */
+ *   leaves it open), max_iter = 50; n_red = 3 reduction passes (App. C.2). */
 typedef struct {
     double hfact;
     double gamma;
@@ -125,19 +125,19 @@ typedef struct {
  * particles (group g = slots [256 g, 256 g + 256)); the second stage is
  * returned in the plain offsets + list form of Alg. 5.  T = the dtype. */
 typedef struct {
-    uint64_t *keys;      /* n   Morton keys in the caller's order (App. C.1) */
+    uint64_t *keys;      /* n   Morton keys in the caller's order (App. B.1) */
     uint32_t *eps;       /* n   sort permutation: key slot i <- input eps[i] */
     uint64_t *mu;        /* n   sorted keys */
-    uint8_t *xi;         /* n   keep mask after reduction (App. D, Alg. 1) */
+    uint8_t *xi;         /* n   keep mask after reduction (App. C, Alg. 1) */
     uint32_t *id;        /* L+1 first key slot of each leaf, id[L] = n */
     uint64_t *mu_leaf;   /* L   leaf codes */
-    uint32_t *lchild, *rchild, *endrange;  /* I  Karras tables (App. C.7) */
+    uint32_t *lchild, *rchild, *endrange;  /* I  Karras tables (App. B.7) */
     uint8_t *lflag, *rflag;                /* I */
     uint32_t *parent;    /* NN  (root: 0xffffffff) */
     void *bmin;          /* 3*NN T  tight box lower corner */
     void *bmax;          /* 3*NN T  tight box upper corner */
     void *hmax;          /* NN  T   max h of the cell */
-    uint32_t *pbox;      /* 6*NN  integer prefix box X0 Y0 Z0 X1 Y1 Z1 (App. C.6) */
+    uint32_t *pbox;      /* 6*NN  integer prefix box X0 Y0 Z0 X1 Y1 Z1 (App. B.6) */
     int32_t *plen;       /* NN    prefix length of the box */
     uint64_t *group_off;    /* G+1  stage-1 offsets, G = n_groups */
     uint32_t *group_leaves; /* E1   neighbour leaves of each group (ascending) */
@@ -163,17 +163,17 @@ int shsph_set_stream(shsph_ctx *ctx, void *stream);
  * next call on the context. */
 const char *shsph_last_error(const shsph_ctx *ctx);
 
-/* The tree half of the hot path, on the particles as given (App. C-F):
- * Morton keys (App. C.1) -> stable radix sort -> keep mask + n_red reduction
- * passes (App. D, Alg. 1) -> compaction -> Karras radix tree (App. C.7) ->
+/* The tree half of the hot path, on the particles as given (App. B-E):
+ * Morton keys (App. B.1) -> stable radix sort -> keep mask + n_red reduction
+ * passes (App. C, Alg. 1) -> compaction -> Karras radix tree (App. B.7) ->
  * bottom-up tight cell boxes with h_max -> two-stage neighbour cache with the
- * chi-extended object-object criterion (App. E.4, Alg. 5, App. F).
+ * chi-extended object-object criterion (App. D.4, Alg. 5, App. E).
  * Reads x, y, z, h.  The tree and caches stay in the context until the next
  * build or step.  EINVAL on bad input, ECAPACITY if the traversal stack
  * overflows. */
 int shsph_build_tree(shsph_ctx *ctx, const shsph_particles *p);
 
-/* Smoothing length and density (App. G, Alg. 7; Sect. 2.1 Eq. sphomega): h and
+/* Smoothing length and density (App. F, Alg. 7; Sect. 2.1 Eq. sphomega): h and
  * rho = m (hfact/h)^3 by per-particle Newton iteration over the cache, with
  * cache rebuilds when h leaves chi times its cache h; then Omega.  Needs a
  * build on the same particles.  Writes h (in place), rho and omega (if
@@ -185,11 +185,11 @@ int shsph_density(shsph_ctx *ctx, shsph_particles *p);
 /* Derivatives (Sect. 2.1 Eqs. sphvel, sphuint, with artificial viscosity and
  * conductivity): writes ax, ay, az, dudt in the caller's order from the h,
  * rho, Omega of the preceding shsph_density and the caller's v and u.  Also
- * reduces the CFL dt (App. H.2), readable with shsph_get_info.  ESTATE if no
+ * reduces the CFL dt (App. G.2), readable with shsph_get_info.  ESTATE if no
  * density result is held. */
 int shsph_force(shsph_ctx *ctx, shsph_particles *p);
 
-/* The whole hot path: one kick-drift-kick step (App. H.1) of dt (dt <= 0: the CFL
+/* The whole hot path: one kick-drift-kick step (App. G.1) of dt (dt <= 0: the CFL
  * dt of the previous force evaluation).  Reads the state at t^n and
  * ax..dudt = derivatives at t^n; writes the state at t^{n+1} with its
  * derivatives, h, and rho/omega/pid when non-NULL.  The particles come back
@@ -255,9 +255,9 @@ int shsph_instance_read(shsph_ctx *ctx, int64_t handle, const shsph_particles *o
  * v2_sum, max_iter_seen, n_noconv (tree counters are 0). */
 int shsph_instance_info(shsph_ctx *ctx, int64_t handle, shsph_info *out);
 
-/* One kick-drift-kick step (App. H.1) of every listed instance in a single
+/* One kick-drift-kick step (App. G.1) of every listed instance in a single
  * batched pass; dt[k] > 0 is a fixed step, dt[k] <= 0 (or dt NULL) the
- * instance's CFL dt (App. H.2).  A CFL instance that has no derivatives yet
+ * instance's CFL dt (App. G.2).  A CFL instance that has no derivatives yet
  * first gets a derivative pass (as shsph_eval_batch).  dt_used (optional)
  * receives the dt taken per instance.  1..2048 distinct handles.  ENOCONV
  * when some instance's h iteration did not settle: the step is complete,
@@ -266,7 +266,7 @@ int shsph_step_batch(shsph_ctx *ctx, const int64_t *handles, int32_t count, cons
                      double *dt_used);
 
 /* Derivatives at the current state of every listed instance in one batched
- * pass: h (Newton iteration, App. G), rho, Omega, a, du/dt and the CFL dt;
+ * pass: h (Newton iteration, App. F), rho, Omega, a, du/dt and the CFL dt;
  * positions, velocities and u are unchanged (values; the order becomes the
  * new Morton order). */
 int shsph_eval_batch(shsph_ctx *ctx, const int64_t *handles, int32_t count);

@@ -101,7 +101,7 @@ def _targets(targets):
 
 # ----------------------------------------------------------------- tree --
 def interleave(X, Y, Z) -> int:
-    """Morton interleave X0 Y0 Z0 X1 ... of 21-bit integers (App. C.1)."""
+    """Morton interleave X0 Y0 Z0 X1 ... of 21-bit integers (App. B.1)."""
     return int(lib().orc_interleave(int(X), int(Y), int(Z)))
 
 
@@ -117,7 +117,7 @@ def delta(a: int, b: int) -> int:
 
 
 def morton(x, y, z, lo, hi) -> np.ndarray:
-    """64-bit Morton keys, 21 bits per axis, quantised in FP64 (App. C.1)."""
+    """64-bit Morton keys, 21 bits per axis, quantised in FP64 (App. B.1)."""
     x, y, z = _d(x), _d(y), _d(z)
     lo, hi = _box(lo, hi)
     key = np.empty(x.shape[0], np.uint64)
@@ -137,7 +137,7 @@ def sort(key):
 
 def leaves(mu, n_red: int):
     """Keep mask after dedupe + n_red reduction passes, and its compaction
-    (App. D, Alg. 1 and Fig. mortonlistbuild).  Returns (xi, id, mu_leaf)."""
+    (App. C, Alg. 1 and Fig. mortonlistbuild).  Returns (xi, id, mu_leaf)."""
     mu = np.ascontiguousarray(mu, dtype=np.uint64)
     n = mu.shape[0]
     xi = np.zeros(max(n, 1), np.uint8)
@@ -149,7 +149,7 @@ def leaves(mu, n_red: int):
 
 def radix_tree(mu_leaf):
     """Karras tables of the binary radix tree over distinct sorted codes
-    (App. C.7 and its Table).  parent[] covers internal nodes then leaves."""
+    (App. B.7 and its Table).  parent[] covers internal nodes then leaves."""
     ml = np.ascontiguousarray(mu_leaf, dtype=np.uint64)
     nl = ml.shape[0]
     ni = max(nl - 1, 0)
@@ -166,7 +166,7 @@ def radix_tree(mu_leaf):
 
 
 def prefix_boxes(mu_leaf, tree):
-    """Integer prefix-class box of every node (App. C.6): (box[nn,6], len[nn])."""
+    """Integer prefix-class box of every node (App. B.6): (box[nn,6], len[nn])."""
     ml = np.ascontiguousarray(mu_leaf, dtype=np.uint64)
     nl = ml.shape[0]
     nn = 2 * nl - 1
@@ -195,7 +195,7 @@ def tight_boxes(ids, tree, xs, ys, zs, hs):
 
 def neighbours(x, y, z, h, lo, hi, periodic: bool, r_kern_chi: float, brute=False,
                targets=None):
-    """Neighbour sets decided in the storage precision of x (App. F):
+    """Neighbour sets decided in the storage precision of x (App. E):
     returns (offsets[nt+1] uint64, list uint32), ascending, self included,
     for the targets (default: every particle)."""
     x = np.ascontiguousarray(x)
@@ -230,7 +230,7 @@ def m4_df(q: float) -> float:
 
 
 def density(x, y, z, h0, lo, hi, periodic, mass, hfact=1.2, targets=None):
-    """Self-consistent h, rho = m (hfact/h)^3 and Omega (App. G, Eq. sphomega).
+    """Self-consistent h, rho = m (hfact/h)^3 and Omega (App. F, Eq. sphomega).
     Returns (h, rho, omega, flags) for the targets (default: all)."""
     x, y, z, h0 = _d(x), _d(y), _d(z), _d(h0)
     lo, hi = _box(lo, hi)
@@ -279,7 +279,7 @@ def cfl(h, vsig, ax, ay, az, c_cour=0.3, c_force=0.25) -> float:
 
 def step(state: dict, lo, hi, periodic, mass, dt, hfact=1.2, gamma=5.0 / 3.0,
          alpha=1.0, beta=2.0, beta_u=1.0, c_cour=0.3, c_force=0.25):
-    """One fixed-dt KDK step (App. H.1).  ``state`` holds x,y,z,vx,vy,vz,u,h,
+    """One fixed-dt KDK step (App. G.1).  ``state`` holds x,y,z,vx,vy,vz,u,h,
     ax,ay,az,dudt (FP64 copies are made); returns the new state dict with
     rho, omega and diag = (max|dv|, sum|dv|^2, sum|v|^2, cfl dt)."""
     keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay", "az", "dudt")

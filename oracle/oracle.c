@@ -6,23 +6,23 @@
  * benchmark do.  It shares no code, header or table with the HIP library.
  *
  * Floating point is FP64 except where a decision must be taken in the storage
- * precision (the neighbour criterion, App. F), which is then evaluated in
+ * precision (the neighbour criterion, App. E), which is then evaluated in
  * float or double exactly as written, with FMA contraction disabled (the file
  * is built with -ffp-contract=off).
  *
  * Parity pins are the test-suite's job; every function below is written as
  * the plain definition of what the paper's algorithms compute:
- *   Morton encoding ........ App. C.1 (interleave X0 Y0 Z0 X1 ...)
- *   delta operator ......... App. C, Eq. delta_ab (clz of XOR)
- *   stable sort ............ App. E.1 "Sort by key" (ties by original index)
- *   keep mask + reduction .. App. D, Alg. 1 (Jacobi passes) + compaction
- *   radix tree ............. App. C.7 and its Table (recursive top-down split)
- *   cell boxes ............. App. C.6 Eqs. lowboundbox/highboundbox, App. F h_max
- *   neighbour sets ......... App. F, object-object criterion, chi-extended
- *   h / rho root ........... App. G Eq. rhoh, Sect. 2.1 Eqs. SPHmass/rhosphsum
+ *   Morton encoding ........ App. B.1 (interleave X0 Y0 Z0 X1 ...)
+ *   delta operator ......... App. B, Eq. delta_ab (clz of XOR)
+ *   stable sort ............ App. D.1 "Sort by key" (ties by original index)
+ *   keep mask + reduction .. App. C, Alg. 1 (Jacobi passes) + compaction
+ *   radix tree ............. App. B.7 and its Table (recursive top-down split)
+ *   cell boxes ............. App. B.6 Eqs. lowboundbox/highboundbox, App. E h_max
+ *   neighbour sets ......... App. E, object-object criterion, chi-extended
+ *   h / rho root ........... App. F Eq. rhoh, Sect. 2.1 Eqs. SPHmass/rhosphsum
  *   Omega .................. Sect. 2.1 Eq. sphomega
  *   force, du/dt ........... Sect. 2.1 Eqs. sphvel, sphuint (+ AV, conductivity)
- *   leapfrog, CFL .......... App. H.1 (KDK) and H.2 (timestep)
+ *   leapfrog, CFL .......... App. G.1 (KDK) and H.2 (timestep)
  */
 #include <math.h>
 #include <stdint.h>
@@ -57,7 +57,7 @@ void orc_set_threads(int n)
 }
 
 /* ------------------------------------------------------------------ */
-/* Morton codes (App. C.1): map to [0,1), sample a 2^21 grid per axis,  */
+/* Morton codes (App. B.1): map to [0,1), sample a 2^21 grid per axis,  */
 /* interleave bit by bit with X as the most significant of each triple. */
 /* ------------------------------------------------------------------ */
 static uint32_t quantize(double v, double lo, double scale)
@@ -145,7 +145,7 @@ void orc_sort(int64_t n, const uint64_t *key, uint32_t *eps, uint64_t *mu)
 }
 
 /* ------------------------------------------------------------------ */
-/* Keep mask, reduction passes and compaction (App. D, Alg. 1).        */
+/* Keep mask, reduction passes and compaction (App. C, Alg. 1).        */
 /* Each pass reads the previous mask and writes a new one.  A missing   */
 /* neighbour (outside [0,n)) contributes a prefix length of -1.         */
 /* ------------------------------------------------------------------ */
@@ -182,7 +182,7 @@ int64_t orc_leaves(int64_t n, const uint64_t *mu, int n_red,
 }
 
 /* ------------------------------------------------------------------ */
-/* Binary radix tree, plain top-down definition (App. C.7, its Table):  */
+/* Binary radix tree, plain top-down definition (App. B.7, its Table):  */
 /* a leaf range [f,l] is split after the last code whose bit at the     */
 /* first differing position (counted from the MSB) is 0.  The node of   */
 /* a range is numbered by its end that touches the split of its parent: */
@@ -238,7 +238,7 @@ static void node_ranges(int64_t nl, const uint32_t *er, int64_t *first, int64_t 
 }
 
 /* ------------------------------------------------------------------ */
-/* Integer prefix boxes (App. C.6): the prefix class of a node is all   */
+/* Integer prefix boxes (App. B.6): the prefix class of a node is all   */
 /* codes sharing its first `len` bits; p0 = code & mask, p1 = p0 | ~mask */
 /* decoded into inclusive integer corners.  For an internal node len is */
 /* delta(first, last); a leaf takes its parent's length + 1 (the whole  */
@@ -420,7 +420,7 @@ static void sep64(const double *L, int periodic, double xa, double ya, double za
 }
 
 /* ------------------------------------------------------------------ */
-/* Neighbour sets in the storage precision T (App. F, object-object     */
+/* Neighbour sets in the storage precision T (App. E, object-object     */
 /* criterion with the chi-extended cache radius):                      */
 /*   dx = x_b - x_a;  periodic: once, dx -= L if dx > L/2, += L if     */
 /*   dx < -L/2;  r2 = fma(dz, dz, fma(dy, dy, dx*dx)) (fused, each      */
@@ -551,7 +551,7 @@ static double dWdh(double r, double h)
 static double Fgrad(double r, double h) { return m4_df(r / h) / (M_PI * h * h * h * h); }
 
 /* ------------------------------------------------------------------ */
-/* Smoothing length (App. G): h_a is the root of                       */
+/* Smoothing length (App. F): h_a is the root of                       */
 /*    g(h) = sum_b m W(r_ab, h) - m (hfact/h)^3                          */
 /* over all b within 2h.  Bracket by geometric expansion from the       */
 /* initial h, then safeguarded Newton/bisection to 1e-13 relative.      */
@@ -801,7 +801,7 @@ void orc_force(int64_t n, const double *x, const double *y, const double *z,
 }
 
 /* ------------------------------------------------------------------ */
-/* CFL timestep (App. H.2): min over a of                               */
+/* CFL timestep (App. G.2): min over a of                               */
 /*   min(C_cour h_a / vsig_a, C_force sqrt(h_a / |a_a|)).               */
 /* ------------------------------------------------------------------ */
 double orc_cfl(int64_t n, const double *h, const double *vsig, const double *ax,
@@ -819,7 +819,7 @@ double orc_cfl(int64_t n, const double *h, const double *vsig, const double *ax,
 }
 
 /* ------------------------------------------------------------------ */
-/* One kick-drift-kick step with a fixed dt (App. H.1), u integrated    */
+/* One kick-drift-kick step with a fixed dt (App. G.1), u integrated    */
 /* like v.  In: state at t^n (x,v,u,h) and the derivatives a^n, du^n.   */
 /* Out (in place): state at t^{n+1}, h^{n+1}, rho, Omega, a^{n+1},       */
 /* du^{n+1}.  diag[0] = max |dv|, diag[1] = sum |dv|^2, diag[2] =        */

@@ -13,7 +13,7 @@ typedef int32_t i32;
 typedef int64_t i64;
 
 constexpr int WAVE = 64;
-constexpr int MORTON_BITS = 21;             // per axis, 63-bit keys (App. C.1)
+constexpr int MORTON_BITS = 21;             // per axis, 63-bit keys (App. B.1)
 constexpr u32 MORTON_MAX = (1u << MORTON_BITS) - 1u;
 
 // ---------------------------------------------------------------- vectors --

@@ -22,7 +22,7 @@ template <class T> struct SortedPtrs {
     u32* pid;          // particle ids carried through the reordering
 };
 
-// Karras tables (App. C.7) plus node-indexed links for the traversals.
+// Karras tables (App. B.7) plus node-indexed links for the traversals.
 struct TreePtrs {
     u32 *lchild, *rchild, *endrange;   // local leaf/internal ids per instance
     u8 *lflag, *rflag;

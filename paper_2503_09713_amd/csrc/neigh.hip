@@ -1,9 +1,9 @@
-// Two-stage neighbour cache (App. E.3-E.4, Alg. 4-6), laid out for gfx950.
+// Two-stage neighbour cache (App. D.3-E.4, Alg. 4-6), laid out for gfx950.
 //
 // Particles are taken in groups of GROUP = 256 consecutive key-order slots
 // (one workgroup).  Stage 1 runs once per group (Alg. 4 walked for all the
 // group's leaves at once): one wave walks the tree level by level and keeps
-// the leaves that pass the group-group criterion of App. F,
+// the leaves that pass the group-group criterion of App. E,
 //     box_A  n  [box_C (+) R chi max(hmax_A, hmax_C)]  !=  0,
 // for some target leaf A of the group, with periodic images and a slight
 // outward inflation so that the prune is a superset of the exact particle

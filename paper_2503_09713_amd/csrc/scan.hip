@@ -1,5 +1,5 @@
 // Device-wide exclusive scan (reduce, scan of block sums, downsweep).
-// Used for the stream compaction of the keep mask (App. E.1), the offsets of
+// Used for the stream compaction of the keep mask (App. D.1), the offsets of
 // the leaf and particle neighbour caches (Alg. 5) and the radix-sort digit
 // offsets.  out has n+1 entries; out[n] is the total.
 #include "common.hpp"

@@ -1,6 +1,6 @@
 // Stable LSD radix sort of (64-bit Morton key, 32-bit index) pairs.
 //
-// The paper sorts with a bitonic network (App. E.1) and names onesweep-style
+// The paper sorts with a bitonic network (App. D.1) and names onesweep-style
 // radix sorting as the faster alternative; this is such a sort built for
 // wave64, 8-bit digits:
 //   1. one read of all keys computes the digit histograms of every pass

@@ -1,8 +1,8 @@
 // SPH loops over the neighbour cache: the smoothing-length / density
-// iteration with Omega (App. G, Alg. 7; Sect. 2.1 Eq. sphomega), the force and
+// iteration with Omega (App. F, Alg. 7; Sect. 2.1 Eq. sphomega), the force and
 // energy equations with artificial viscosity and conductivity (Sect. 2.1
 // Eqs. sphvel, sphuint), the leapfrog corrector and the timestep reductions
-// (App. H).  One thread per particle in key order; arithmetic and
+// (App. G).  One thread per particle in key order; arithmetic and
 // accumulation in the storage type.
 #include "common.hpp"
 #include "kernels.hpp"
@@ -151,7 +151,7 @@ __device__ inline void atomic_min_if(u32* p, u32 v)
 }
 
 // ---------------------------------------------------------------------------
-// h iteration (App. G, Alg. 7), per particle, over the cached neighbours:
+// h iteration (App. F, Alg. 7), per particle, over the cached neighbours:
 //   rho_sum = sum_b m W(r_ab, h),   W = f(r/h)/(pi h^3)
 //   drho = rho_sum - m (hfact/h)^3,  d(drho)/dh = sum_b m dW/dh + 3 rho_sum/h
 //   (the derivative term as Alg. 7 prints it, with the SPH sum: it equals the
@@ -164,7 +164,7 @@ __device__ inline void atomic_min_if(u32* p, u32 v)
 // cache was built with, h' is clamped there and the particle is flagged: the
 // caller rebuilds the cache with the new h and iterates again (the
 // single-device form of the ghost re-exchange).
-// Final values: rho = m (hfact/h)^3 (App. G uses rho(h), not the sum) and
+// Final values: rho = m (hfact/h)^3 (App. F uses rho(h), not the sum) and
 // Omega = 1 + h/(3 rho) sum_b m dW/dh (Eq. sphomega with dh/drho = -h/(3 rho)),
 // both taken at the last h where the sums were evaluated.
 // One workgroup per group: the union's positions are staged in LDS once and
@@ -487,7 +487,7 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
 }
 
 // ---------------------------------------------------------------------------
-// Leapfrog corrector (App. H.1): v^{n+1} = v^{n+1/2} + dt/2 a^{n+1}
+// Leapfrog corrector (App. G.1): v^{n+1} = v^{n+1/2} + dt/2 a^{n+1}
 // (= v* + dt/2 (a^{n+1} - a^n)), same for u.  Writes the new state into the
 // caller's arrays at the particle's key-order position and reduces
 // max|dv|, sum|dv|^2 and sum|v|^2 per instance for the reversibility check.

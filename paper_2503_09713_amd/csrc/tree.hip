@@ -10,7 +10,7 @@ namespace shsph {
 static inline dim3 grid_for(i64 n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
 
 // ---------------------------------------------------------------------------
-// Leapfrog predictor (App. H.1): v^{n+1/2} = v + dt/2 a, r^{n+1} = r + dt v^{n+1/2},
+// Leapfrog predictor (App. G.1): v^{n+1/2} = v + dt/2 a, r^{n+1} = r + dt v^{n+1/2},
 // v* = v^{n+1/2} + dt/2 a, and the same for u; periodic positions are wrapped
 // into [lo, hi).  Written with explicit roundings so that every kernel that
 // evaluates it obtains bit-identical positions.
@@ -50,7 +50,7 @@ __device__ inline void predict(const T* const* xp, const T* const* vp, const T* 
     o.us = o.uh + kd;
 }
 
-// Morton key (App. C.1): X = min(2^21-1, max(0, floor((x - lo) * 2^21/(hi - lo))))
+// Morton key (App. B.1): X = min(2^21-1, max(0, floor((x - lo) * 2^21/(hi - lo))))
 // in FP64, interleaved X0 Y0 Z0 X1 Y1 Z1 ... (bit 63 unused).
 __device__ inline u64 spread3(u32 v)
 {
@@ -143,7 +143,7 @@ __global__ void k_gather(FieldPtrs<T> f, i64 n, const InstDev* __restrict__ inst
 }
 
 // ---------------------------------------------------------------------------
-// Keep mask and reduction (App. D, Alg. 1).  Duplicates are dropped, then
+// Keep mask and reduction (App. C, Alg. 1).  Duplicates are dropped, then
 // each pass removes code i when delta(i-2,i-1) < delta(i-1,i) > delta(i,i+1)
 // over the currently kept codes, i.e. when i is the second leaf of a pair of
 // sibling leaves.  Passes read the old mask and write a new one; neighbours
@@ -182,7 +182,7 @@ __global__ void k_reduce_pass(const u64* __restrict__ mu, i64 n, const i64* __re
 }
 
 // Compaction: id[k] = index of the k-th kept code, mu_leaf[k] its code,
-// id[n_leaf] = n (App. E.1, Fig. mortonlistbuild).
+// id[n_leaf] = n (App. D.1, Fig. mortonlistbuild).
 __global__ void k_compact(const u64* __restrict__ mu, const u8* __restrict__ xi,
                           const u32* __restrict__ xscan, i64 n, u32* __restrict__ id,
                           u64* __restrict__ mu_leaf)
@@ -217,7 +217,7 @@ __global__ void k_inst_leaves(const i64* __restrict__ p_off, int ninst, const u3
 }
 
 // ---------------------------------------------------------------------------
-// Karras radix tree (App. C.7): one thread per internal node, no ordering
+// Karras radix tree (App. B.7): one thread per internal node, no ordering
 // between nodes.  Direction from the larger of the neighbouring prefix
 // lengths, range end by exponential + binary search, split by binary search
 // for the last code sharing more than delta_node bits with node i.
@@ -487,7 +487,7 @@ k_boxes_top(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nbloc
     }
 }
 
-// Integer prefix boxes (App. C.6, Eqs. lowboundbox/highboundbox): internal
+// Integer prefix boxes (App. B.6, Eqs. lowboundbox/highboundbox): internal
 // nodes use delta(first, last) bits of their codes, leaves their parent's
 // length + 1; corners p0 = code & mask, p1 = p0 | ~mask, de-interleaved.
 __device__ inline u32 compact3(u64 x)

@@ -19,7 +19,7 @@ def _load(name):
 
 # ------------------------------------------------------------- Morton ----
 def test_interleave_x_is_msb_of_each_triple():
-    # App. C.1: m = X0 Y0 Z0 X1 Y1 Z1 ..., X0 the most significant bit of X.
+    # App. B.1: m = X0 Y0 Z0 X1 Y1 Z1 ..., X0 the most significant bit of X.
     assert oracle.interleave(1 << 20, 0, 0) == 1 << 62
     assert oracle.interleave(0, 1 << 20, 0) == 1 << 61
     assert oracle.interleave(0, 0, 1 << 20) == 1 << 60
@@ -92,7 +92,7 @@ def _tree_from_codes(codes):
 
 
 def _sibling_reduction(mu, n_red):
-    """The reduction as the paper states it in words (App. D.2): in the tree
+    """The reduction as the paper states it in words (App. C.2): in the tree
     of the currently kept codes, a code that is the second leaf of an
     internal node whose two children are both leaves is removed."""
     n = len(mu)
@@ -271,7 +271,7 @@ def test_aabb_extension_permutation_theorem():
 
 # --------------------------------------------------------- neighbours ----
 def _lattice_shell_counts(eta, radius_factor):
-    """Number of integer offsets n with |n| < radius_factor * eta (App. C,
+    """Number of integer offsets n with |n| < radius_factor * eta (App. B,
     cubic lattice, unit spacing): the neighbour count of every particle."""
     R = int(np.ceil(radius_factor * eta)) + 1
     r = np.arange(-R, R + 1)
@@ -327,3 +327,89 @@ def test_neighbours_float_decision_in_float():
     rc = np.float32(2.2) * h[0]
     want = 2 if dx * dx < rc * rc else 1
     assert int(off[1] - off[0]) == want
+
+
+# Pairs (float32 positions, common h) on which r^2 formed with fused
+# multiply-adds and r^2 formed as (dx*dx + dy*dy) + dz*dz fall on opposite
+# sides of the squared cache radius.  Found by a seeded search; the decision
+# the criterion of App. E asks for is the real-valued one.
+_STRADDLE_F32 = [
+    # h, particle b (particle a sits at (0.25, 0.375, 0.3125))
+    (0.012568564154207706, (0.2501320242881775, 0.34750130772590637, 0.30960628390312195)),
+    (0.013240364380180836, (0.25197258591651917, 0.39744433760643005, 0.33096206188201904)),
+]
+
+
+def _round_f32(v):
+    """Round an exact rational to the nearest float32 (ties to even)."""
+    from fractions import Fraction
+    if v == 0:
+        return Fraction(0)
+    s, a = (-1 if v < 0 else 1), abs(v)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    while Fraction(2) ** e > a:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= a:
+        e += 1
+    sc = Fraction(2) ** (e - 23)
+    m = a / sc
+    fl = m.numerator // m.denominator
+    rem = m - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    return s * fl * sc
+
+
+@pytest.mark.parametrize("case", range(len(_STRADDLE_F32)))
+def test_neighbour_r2_rounding_takes_the_exact_side(case):
+    """The storage-type r^2 is formed with fused multiply-adds (each partial
+    sum rounded once).  On these pairs the unfused sum rounds to the other
+    side of rc^2; the oracle must take the side of the exact real-valued
+    comparison of the (exactly representable) differences with rc^2."""
+    from fractions import Fraction as Fr
+    h, pb = _STRADDLE_F32[case]
+    pa = (0.25, 0.375, 0.3125)
+    x = np.array([pa[0], pb[0]], np.float32)
+    y = np.array([pa[1], pb[1]], np.float32)
+    z = np.array([pa[2], pb[2]], np.float32)
+    hh = np.full(2, h, np.float32)
+    d = [Fr(float(c[1])) - Fr(float(c[0])) for c in (x, y, z)]
+    for k, c in enumerate((x, y, z)):   # the float differences are exact
+        assert Fr(float(np.float32(c[1] - c[0]))) == d[k]
+    rc = _round_f32(_round_f32(Fr(11, 5)) * Fr(float(hh[0])))
+    rc2 = _round_f32(rc * rc)
+    exact = d[0] ** 2 + d[1] ** 2 + d[2] ** 2 < rc2
+    unfused = _round_f32(_round_f32(_round_f32(d[0] ** 2) + _round_f32(d[1] ** 2))
+                         + _round_f32(d[2] ** 2)) < rc2
+    assert exact != unfused            # the case does separate the two forms
+    off, lst = oracle.neighbours(x, y, z, hh, (0, 0, 0), (1, 1, 1), False, 2.2)
+    assert int(off[1] - off[0]) == (2 if exact else 1)
+    assert int(off[2] - off[1]) == (2 if exact else 1)
+
+
+def test_leaf_prefix_boxes_are_the_leaf_blocks():
+    """16^3 lattice, three reduction passes: every leaf is one 2x2x2 block of
+    lattice cells (each pass merges sibling leaves), so its prefix box
+    (parent's prefix length + 1) is exactly that block: 2^18 grid cells per
+    side, aligned to 2^18.  A leaf given its parent's length would be twice
+    as long on one axis.  The root's box is the whole grid."""
+    p = gen.lattice(16, 1, dtype=np.float64)
+    k = oracle.morton(p.x, p.y, p.z, p.lo, p.hi)
+    eps, mu = oracle.sort(k)
+    _, ids, ml = oracle.leaves(mu, 3)
+    assert len(ml) == 512
+    t = oracle.radix_tree(ml)
+    box, plen = oracle.prefix_boxes(ml, t)
+    ni = len(ml) - 1
+    side = 1 << 18
+    leaf = box[ni:].astype(np.int64)
+    assert (leaf[:, 3:] - leaf[:, :3] == side - 1).all()
+    assert (leaf[:, :3] % side == 0).all()
+    # the block holds exactly the leaf's particles
+    g = (np.stack([p.x, p.y, p.z], 1)[eps] * (1 << 21)).astype(np.int64)
+    for j in range(0, 512, 37):
+        sl = slice(ids[j], ids[j + 1])
+        assert ids[j + 1] - ids[j] == 8
+        assert (g[sl] >= leaf[j, :3]).all() and (g[sl] <= leaf[j, 3:]).all()
+    assert box[0].tolist() == [0, 0, 0, (1 << 21) - 1, (1 << 21) - 1, (1 << 21) - 1]
+    assert plen[0] == 1            # only the unused top bit is common to all codes
