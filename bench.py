@@ -24,22 +24,30 @@ if ROOT not in sys.path:
 
 METRIC = "particle-steps/s/GPU (tree+density+force), %HBM peak; batched/served vs plain, p99"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3           # published vector FP32 (packed); 78.6 without packed FP32
-FP32_PEAK_NONPACKED_TFLOPS = 78.6
 
-# FP32 operations per counted item (multiply-add counted as 2), from the
-# kernels' arithmetic:
-#   particle cache: a candidate test (3 sub, 3 mul, 2 add, max, 2 mul, compare)
-#                   = 12; a leaf-box prune test = 19
-#   density: a pair evaluation (3 sub, squares and sum, compare) = 9, plus 20
-#            for the kernel sums of pairs within 2h
-#   force: an entry visit (separation, r^2, max, range test) = 12, plus 82 for
-#          an interacting pair (unit vector, w, two spline gradients, AV,
-#          pressure terms, acceleration, du/dt, conductivity, signal speed)
-OPS = {"particle_cache": (12, 19), "density": (9, 20), "force": (12, 82)}
-WORK_KEYS = {"particle_cache": ("cache_tests", "cache_prune_tests"),
-             "density": ("density_pair_evals", "density_pairs_in_2h"),
-             "force": ("force_entries", "force_pairs")}
+# Algorithmic HBM bytes per particle of one launch of each stage, FP32: every
+# array the stage must touch crosses HBM once, neighbour data re-read through
+# LDS / L2 is not counted, 81 cache entries of 4 B, two Newton passes over the
+# cache per density launch, 8 radix passes.  Split as (integer bytes,
+# floating-point bytes); the floating part doubles in FP64.
+STAGE_BYTES = {
+    "predict_morton": (12, 100),        # x, v, a, u, du/dt in; x, v^{n+1/2}, v*, u's out; key, iota
+    "radix_sort": (192, 0),
+    "gather": (4, 126),
+    "mask_reduce_compact": (45, 0),
+    "karras": (3, 0),
+    "boxes": (0, 23),
+    "group_leaf_cache": (25, 0),
+    "particle_cache": (324, 46),        # 81 indices out; positions, h in
+    "density": (648, 62),               # the cache read twice (two Newton passes); x, h in; h, rho, Omega out
+    "force": (324, 56),                 # the cache; own fields in; a, du/dt out
+    "correct": (0, 64),
+}
+
+
+def stage_bytes_pp(stage, T):
+    ib, fb = STAGE_BYTES[stage]
+    return ib + fb * T // 4
 
 # HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a plain
@@ -54,10 +62,10 @@ KERNEL_SOURCES = {"particle_cache": ("neigh.hip", "common.hpp", "kernels.hpp")}
 
 # Vector instructions the dominant kernel issues per launch (rocprofv3 --pmc
 # SQ_INSTS_VALU, wave instructions summed over the chip), with the sha256 of
-# its sources at the time.  Against the issue ceiling of one wave64 VALU
-# instruction per compute unit per clock (256 CUs at 2.4 GHz; a 64-lane FP32
-# operation occupies a SIMD for four clocks) it gives the fraction of the
-# launch the vector units were issuing.
+# its sources at the time, set against the nominal rate of one wave64 VALU
+# instruction per compute unit per clock at 2.4 GHz (a 64-lane FP32 operation
+# occupies a 16-lane SIMD for four clocks, four SIMDs per CU).  A secondary
+# figure beside the HBM roofline; the clock under load is not measured here.
 VALU_INSTS = {
     ("particle_cache", "sedov256"): {
         "valu_insts_per_launch": 1.3808e9,   # k_group_cache<float, 1>
@@ -72,7 +80,7 @@ def valu_issue_for(stage, workload, avg_ms):
         return None
     n = t["valu_insts_per_launch"]
     return {"valu_insts_per_launch": n,
-            "frac_of_issue_ceiling": round(n / (CU_COUNT * CLOCK_HZ * avg_ms * 1e-3), 4)}
+            "frac_of_nominal_issue": round(n / (CU_COUNT * CLOCK_HZ * avg_ms * 1e-3), 4)}
 
 
 def sources_sha(stage):
@@ -113,31 +121,6 @@ def make_input(name):
     return gen.lattice(n1, seed, dtype=T)
 
 
-def algorithmic_bytes(stage, n, info, T):
-    """HBM bytes the kernel's algorithm must move once per launch: every array
-    it touches read or written once (neighbour data re-read through L2/LDS is
-    not counted).  E2 = particle-cache entries (2 B each), E1 = group-cache
-    leaves, L = leaves, G = groups."""
-    e1, e2, nl, G = info["n_leaf_neigh"], info["n_neigh"], info["n_leaf"], info["n_groups"]
-    v4 = 4 * T
-    if stage == "density":
-        # posh, h^n, h_cache, count, u* in; h, omega, status, thermo out; + slots
-        return n * (v4 + T + T + 4 + T + T + T + 1 + v4) + 2 * e2 + 8 * e1
-    if stage == "force":
-        # posh, velu, thermo, count in; acc out; + slots
-        return n * (3 * v4 + 4 + v4) + 2 * e2 + 8 * e1
-    if stage == "particle_cache":
-        # posh in; counts and slots out; union leaves (id, slot start, box)
-        return n * (v4 + 4) + 2 * e2 + e1 * (8 + 8 + 2 * v4)
-    if stage == "correct":
-        # posh, velu, vhalf, acc, pid in; 12 state fields + pid out
-        return n * (4 * v4 + 4 + 12 * T + 4)
-    if stage == "gather":
-        # eps + 13 fields in (x3, v3, a3, u, du, h) + pid; posh, velu, vhalf, h^n, h_cache, pid out
-        return n * (4 + 13 * T + 4 + 3 * v4 + 2 * T + 4)
-    return None
-
-
 def cpu_baseline(ps_host, p, args):
     """The CPU oracle (FP64, OpenMP) on a bounded sample of the same workload:
     density (h root) + force for S random target particles against all N,
@@ -174,6 +157,15 @@ def cpu_baseline(ps_host, p, args):
         return n / (slope * n + overhead), t1, t2
 
     cores = oracle.threads()
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     s1, s2 = args.cpu_sample // 8, args.cpu_sample
     v, t1, t2 = rate(s1, s2)
     # one thread: a sample a quarter the size (the same extrapolation)
@@ -181,7 +173,7 @@ def cpu_baseline(ps_host, p, args):
     v1, u1, u2 = rate(s1 // 4, s2 // 4)
     oracle.set_threads(cores)
     return {"value": v, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
-            "value_one_thread": v1,
+            "value_one_thread": v1, "cpu_model": cpu_model, "host_cpus": os.cpu_count(),
             "sample": (f"{s2} and {s1} random particles of the {args.workload} state, FP64 "
                        f"density (h root) + force against all {n}; full step extrapolated "
                        f"({t1:.1f}s, {t2:.1f}s measured; one thread: {s2 // 4} and {s1 // 4} "
@@ -465,33 +457,25 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = p.n * args.steps / elapsed
 
-    # dominant single-kernel stage and its roofline: the neighbour kernels
-    # are instruction bound (ALU, counted operations); streaming kernels HBM
-    cand = {k: v for k, v in stages.items() if algorithmic_bytes(k, p.n, info, T) is not None and v[1] > 0}
+    # dominant stage (largest time per step) and its roofline.  The bound is
+    # HBM bandwidth: achieved = the stage's algorithmic bytes per particle
+    # (STAGE_BYTES) times the particles one launch processes, over the live
+    # average launch time (HIP events on the library's stream)
+    cand = {k: v for k, v in stages.items() if k in STAGE_BYTES and v[1] > 0}
     dom = max(cand, key=lambda k: cand[k][0])
     avg_ms = cand[dom][0] / cand[dom][1]
-    by = algorithmic_bytes(dom, p.n, info, T)
+    bpp = stage_bytes_pp(dom, T)
+    by = bpp * p.n
     hbm = by / (avg_ms * 1e-3) / 1e9
-    if dom in OPS:
-        k1, k2 = WORK_KEYS[dom]
-        ops = (OPS[dom][0] * work[k1] + OPS[dom][1] * work[k2]) / cand[dom][1]
-        tf = ops / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": round(tf, 3), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4),
-                "traffic": traffic_for(dom, args.workload),
-                "frac_of_nonpacked_peak": round(tf / FP32_PEAK_NONPACKED_TFLOPS, 4),
-                "avg_launch_ms": round(avg_ms, 4), "flop_per_launch": int(ops),
-                "hbm_algorithmic_GBs": round(hbm, 1), "bytes_per_launch": int(by),
-                "valu_issue": valu_issue_for(dom, args.workload, avg_ms)}
-    else:
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4),
-                "traffic": traffic_for(dom, args.workload),
-                "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": int(by)}
-    # whole step against HBM: algorithmic bytes of all stages per step
-    step_bytes = sum(algorithmic_bytes(k, p.n, info, T) * (v[1] / args.steps)
-                     for k, v in stages.items() if algorithmic_bytes(k, p.n, info, T) is not None)
-    step_bytes += 8 * p.n * 32 + p.n * 48 + p.n * 34   # sort, predict/keys, mask/reduce/compact
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(dom, args.workload),
+            "avg_launch_ms": round(avg_ms, 4), "bytes_per_particle": bpp,
+            "particles_per_launch": p.n, "bytes_per_launch": int(by),
+            "launches_per_step": round(cand[dom][1] / args.steps, 3),
+            "valu_issue": valu_issue_for(dom, args.workload, avg_ms)}
+    # whole step: one launch of every stage per step at its algorithmic bytes
+    step_bytes = sum(stage_bytes_pp(k, T) for k in STAGE_BYTES) * p.n
 
     out = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,

@@ -144,6 +144,8 @@ typedef struct {
     uint64_t *neigh_off; /* n+1  stage-2 offsets (Alg. 5) */
     uint32_t *neigh_list;/* E2   neighbours in key slots (ascending, self included) */
     void *h_sorted;      /* n T  h in key order (after a density call: converged h) */
+    void *h_cache;       /* n T  h the neighbour cache was built with (key order): the
+                            step-start h, or the h of the last cache rebuild */
 } shsph_tree_export;
 
 /* Fill *p with the defaults listed above. */

@@ -101,7 +101,7 @@ class ServeCounters(C.Structure):
 
 _EXPORT_FIELDS = ["keys", "eps", "mu", "xi", "id", "mu_leaf", "lchild", "rchild", "endrange",
                   "lflag", "rflag", "parent", "bmin", "bmax", "hmax", "pbox", "plen", "group_off",
-                  "group_leaves", "neigh_off", "neigh_list", "h_sorted"]
+                  "group_leaves", "neigh_off", "neigh_list", "h_sorted", "h_cache"]
 
 
 class TreeExport(C.Structure):
@@ -295,7 +295,7 @@ class Context:
                       bmax=((nn, 3), T), hmax=(nn, T), pbox=((nn, 6), np.uint32),
                       plen=(nn, np.int32), group_off=(G + 1, np.uint64),
                       group_leaves=(e1, np.uint32), neigh_off=(n + 1, np.uint64),
-                      neigh_list=(e2, np.uint32), h_sorted=(n, T))
+                      neigh_list=(e2, np.uint32), h_sorted=(n, T), h_cache=(n, T))
         want = fields or list(shapes)
         out, ex = {}, TreeExport()
         for k in want:

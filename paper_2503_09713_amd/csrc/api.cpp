@@ -521,11 +521,13 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
     launch_group_boxes<T>(posh, gm, G, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), st);
     prof_end(c);
     TRY(check_launch(c, "boxes"));
+    bool run_stage1 = true;
     for (int attempt = 0;; ++attempt) {
         // stage 1: neighbour leaves of each group
         TRY(ensure(c, c->uleaf, (size_t)G * c->cap_leaf * sizeof(u32)));
         TRY(ensure(c, c->uslot, (size_t)G * c->cap_leaf * sizeof(u32)));
         TRY(ensure(c, c->nlist, (size_t)G * c->cap_words * GROUP * sizeof(u64)));
+        if (run_stage1) {
         prof_begin(c, S_STAGE1);
         launch_group_leaves<T>(P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child),
                                P<u32>(c->id), P<u32>(c->xscan), ni, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), G, gm,
@@ -536,6 +538,7 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
                                P<u32>(c->flags), attempt ? nullptr : redo, st);
         prof_end(c);
         TRY(check_launch(c, "stage1"));
+        }
         // stage 2: particle neighbours as union slots
         prof_begin(c, S_STAGE2);
         launch_group_cache<T>(posh, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->id),
@@ -575,8 +578,12 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
         }
         if (!(fl[0] & 6u)) break;
         if (attempt >= 4) return fail(c, SHSPH_ECAPACITY, "neighbour cache capacity");
-        if (fl[0] & 2u) c->cap_leaf = (i64)fl[1] + fl[1] / 4 + 16;
-        if (fl[0] & 4u) c->cap_words = ((i64)fl[2] + fl[2] / 4 + 8 + 3) / 4;
+        // capacities only grow, with half again as much room as the largest
+        // request seen, so that a run settles after few regrows; when only the
+        // particle cache overflowed, stage 1's lists are still valid
+        run_stage1 = (fl[0] & 2u) != 0;
+        if (fl[0] & 2u) c->cap_leaf = std::max<i64>(c->cap_leaf, (i64)fl[1] + fl[1] / 2 + 16);
+        if (fl[0] & 4u) c->cap_words = std::max<i64>(c->cap_words, ((i64)fl[2] + fl[2] / 2 + 8 + 3) / 4);
         launch_fill_u32(P<u32>(c->flags), 4, 0u, st);
     }
     return SHSPH_OK;
@@ -1318,6 +1325,7 @@ int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
         HIPTRY(c, hipStreamSynchronize(st));
         for (i64 i = 0; i < n; ++i) memcpy((char*)o->h_sorted + i * T, &ph[(4 * i + 3) * T], T);
     }
+    TRY(cp(o->h_cache, c->hcache.p, n * T));
     HIPTRY(c, hipStreamSynchronize(st));
     return SHSPH_OK;
 }

@@ -12,6 +12,7 @@ import pytest
 
 import gen
 import oracle
+import parity_util
 
 pytestmark = pytest.mark.gpu
 
@@ -139,30 +140,19 @@ def test_step_batch_vs_oracle(torch_cuda):
     _say("[batch] one fixed-dt step of 2 instances vs oracle step")
     ps = [_random_state(gen.lattice(12, 21, dtype=np.float32), 5, vscale=0.05, uvar=0.2),
           _random_state(gen.lattice(10, 22, dtype=np.float32), 6, vscale=0.05, uvar=0.2)]
+    ps[1].vy = (ps[1].vy - 0.5).astype(np.float32)      # a drift across the periodic faces
     ctx = shsph.Context(0)
     hs = [ctx.instance_create(shsph.ParticleSet.from_particles(p)) for p in ps]
     ctx.eval_batch(hs)
     s0 = [_read(ctx, h, p) for h, p in zip(hs, ps)]
-    dt = 0.2 * min(ctx.instance_info(h)["dt_cfl"] for h in hs)
+    dt = 0.5 * min(ctx.instance_info(h)["dt_cfl"] for h in hs)
     used = ctx.step_batch(hs, dt)
     assert used == [dt, dt]
     for p, h, a in zip(ps, hs, s0):
         st = {k: a[k] for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay", "az", "dudt")}
         ref = oracle.step(st, p.lo, p.hi, True, p.mass, dt)
         b = _read(ctx, h, p)
-        pos = np.empty(p.n, np.int64)
-        pos[a["pid"].astype(np.int64)] = np.arange(p.n)
-        j = pos[b["pid"].astype(np.int64)]
-        dx = np.abs(b["x"] - ref["x"][j])
-        assert np.minimum(dx, 1 - dx).max() <= 2e-6
-        assert np.abs(b["h"] / ref["h"][j] - 1).max() <= 1e-5
-        f = oracle.force(ref["x"], ref["y"], ref["z"], ref["vx"], ref["vy"], ref["vz"], ref["u"],
-                         ref["h"], ref["rho"], ref["omega"], p.lo, p.hi, True, p.mass)
-        sa = f["scale_a"][j]
-        ea = np.max(np.sqrt((b["ax"] - ref["ax"][j]) ** 2 + (b["ay"] - ref["ay"][j]) ** 2 +
-                            (b["az"] - ref["az"][j]) ** 2) / sa)
-        eu = np.max(np.abs(b["dudt"] - ref["dudt"][j]) / f["scale_u"][j])
-        assert ea <= 2e-4 and eu <= 2e-4, (ea, eu)
+        parity_util.check_step_vs_oracle(a, b, ref, ctx.instance_info(h), p, dt, np.float32)
     ctx.close()
 
 
@@ -188,11 +178,22 @@ def test_serve_mix_equals_alone(torch_cuda):
     ctx = shsph.Context(0)
     ctx.serve_start(budget_bytes=8e9, max_batch=16)
     sets = [shsph.ParticleSet.from_particles(p) for p in ps]
-    tk = [ctx.submit(init=s, kind=k, nsteps=n) for s, (k, n) in zip(sets, jobs)]
+    # half the jobs first; the rest arrive once the loop has run a pass, so
+    # they are admitted between passes while the first ones are running
+    tk = [ctx.submit(init=s, kind=k, nsteps=n) for s, (k, n) in zip(sets[:4], jobs[:4])]
+    import time
+    t_end = time.time() + 60.0
+    while ctx.serve_stats()["passes"] < 1 and time.time() < t_end:
+        time.sleep(1e-4)
+    passes_before = ctx.serve_stats()["passes"]
+    assert passes_before >= 1
+    tk += [ctx.submit(init=s, kind=k, nsteps=n) for s, (k, n) in zip(sets[4:], jobs[4:])]
     ctx.serve_drain(120.0)
     st = [ctx.poll(t) for t in tk]
     stats = ctx.serve_stats()
     got = [_read(ctx, s["handle"], p) for s, p in zip(st, ps)]
+    overlap = sum(1 for a in st[4:] for b in st[:4] if a["t_start"] < b["t_done"])
+    _say(f"[serve] late jobs admitted while an early one ran: {overlap} pairs")
     ctx.serve_stop()
     ctx.close()
     assert stats["jobs_done"] == len(jobs) and stats["jobs_failed"] == 0
