@@ -30,6 +30,30 @@ f32p = np.ctypeslib.ndpointer(np.float32, flags="C")
 f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
 
 
+KERNELS = {"M4": 0, "M5": 1, "M6": 2, "C2": 3, "C4": 4, "C6": 5}
+
+
+class OrcParams(C.Structure):
+    """Parameters of the oracle's step (mirrors orc_params in oracle.c)."""
+    _fields_ = [("hfact", C.c_double), ("gamma", C.c_double), ("alpha", C.c_double),
+                ("beta", C.c_double), ("beta_u", C.c_double), ("c_cour", C.c_double),
+                ("c_force", C.c_double), ("kernel", C.c_int), ("eps_v", C.c_double),
+                ("max_rerun", C.c_int), ("alpha_switch", C.c_int), ("alpha_min", C.c_double),
+                ("alpha_max", C.c_double), ("sigma_decay", C.c_double)]
+
+
+def _kid(kernel) -> int:
+    return KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+
+
+def make_params(hfact=1.2, gamma=5.0 / 3.0, alpha=1.0, beta=2.0, beta_u=1.0, c_cour=0.3,
+                c_force=0.25, kernel="M4", eps_v=0.0, max_rerun=0, alpha_switch=False,
+                alpha_min=0.0, alpha_max=1.0, sigma_decay=0.1) -> OrcParams:
+    return OrcParams(hfact, gamma, alpha, beta, beta_u, c_cour, c_force, _kid(kernel),
+                     eps_v, max_rerun, int(bool(alpha_switch)), alpha_min, alpha_max,
+                     sigma_decay)
+
+
 def build() -> str:
     """Compile oracle.c into liboracle.so (gcc, no GPU code)."""
     cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fPIC",
@@ -71,15 +95,28 @@ def lib():
     L.orc_m4_f.argtypes = [f64]
     L.orc_m4_df.restype = f64
     L.orc_m4_df.argtypes = [f64]
-    L.orc_density.argtypes = [i64, f64p, f64p, f64p, f64p, f64p, f64p, i32, f64, f64,
+    L.orc_kernel_count.restype = i32
+    for fn in ("orc_kernel_support", "orc_kernel_norm"):
+        getattr(L, fn).restype = f64
+        getattr(L, fn).argtypes = [i32]
+    for fn in ("orc_kernel_f", "orc_kernel_df"):
+        getattr(L, fn).restype = f64
+        getattr(L, fn).argtypes = [i32, f64]
+    L.orc_density.argtypes = [i64, f64p, f64p, f64p, f64p, f64p, f64p, i32, f64, f64, i32,
                               i64, vp, f64p, f64p, f64p, i32p]
-    L.orc_density_sum.argtypes = [i64, f64p, f64p, f64p, f64p, f64p, f64p, i32, f64,
+    L.orc_density_sum.argtypes = [i64, f64p, f64p, f64p, f64p, f64p, f64p, i32, f64, i32,
                                   i64, vp, f64p, f64p]
-    L.orc_force.argtypes = [i64] + [f64p] * 10 + [f64p, f64p, i32, f64, f64, f64, f64, f64,
-                                                   i64, vp] + [f64p] * 7
+    L.orc_force.argtypes = [i64] + [f64p] * 10 + [f64p, f64p, i32, f64, f64, f64, vp, f64, f64,
+                                                   i32, i64, vp] + [f64p] * 7
+    L.orc_gradient.argtypes = [i64] + [f64p] * 9 + [f64p, f64p, i32, f64, i32, i64, vp, f64p]
+    L.orc_alpha_switch.argtypes = [i64] + [f64p] * 14 + [f64p, f64p, i32, f64,
+                                                          C.POINTER(OrcParams), f64, f64p, vp, vp, vp]
+    L.orc_cfl_multiplier.restype = f64
+    L.orc_cfl_multiplier.argtypes = [f64, i32, f64]
     L.orc_cfl.restype = f64
     L.orc_cfl.argtypes = [i64, f64p, f64p, f64p, f64p, f64p, f64, f64]
-    L.orc_step.argtypes = [i64] + [f64p] * 14 + [f64p, f64p, i32] + [f64] * 9 + [f64p]
+    L.orc_step.argtypes = [i64] + [f64p] * 14 + [vp, f64p, f64p, i32, f64,
+                                                  C.POINTER(OrcParams), f64, f64p]
     _lib = L
     return L
 
@@ -229,7 +266,26 @@ def m4_df(q: float) -> float:
     return float(lib().orc_m4_df(float(q)))
 
 
-def density(x, y, z, h0, lo, hi, periodic, mass, hfact=1.2, targets=None):
+def kernel_f(kernel, q: float) -> float:
+    """f(q) of the named kernel (Sect. 2.1.1: M4, M5, M6, C2, C4, C6)."""
+    return float(lib().orc_kernel_f(_kid(kernel), float(q)))
+
+
+def kernel_df(kernel, q: float) -> float:
+    return float(lib().orc_kernel_df(_kid(kernel), float(q)))
+
+
+def kernel_support(kernel) -> float:
+    """Support radius R in units of h."""
+    return float(lib().orc_kernel_support(_kid(kernel)))
+
+
+def kernel_norm(kernel) -> float:
+    """3-D normalisation C_norm."""
+    return float(lib().orc_kernel_norm(_kid(kernel)))
+
+
+def density(x, y, z, h0, lo, hi, periodic, mass, hfact=1.2, targets=None, kernel="M4"):
     """Self-consistent h, rho = m (hfact/h)^3 and Omega (App. F, Eq. sphomega).
     Returns (h, rho, omega, flags) for the targets (default: all)."""
     x, y, z, h0 = _d(x), _d(y), _d(z), _d(h0)
@@ -239,11 +295,11 @@ def density(x, y, z, h0, lo, hi, periodic, mass, hfact=1.2, targets=None):
     h = np.zeros(nt); rho = np.zeros(nt); om = np.zeros(nt)
     fl = np.zeros(nt, np.int32)
     lib().orc_density(x.shape[0], x, y, z, h0, lo, hi, int(bool(periodic)), float(mass),
-                      float(hfact), nt, tp, h, rho, om, fl)
+                      float(hfact), _kid(kernel), nt, tp, h, rho, om, fl)
     return h, rho, om, fl
 
 
-def density_sum(x, y, z, h, lo, hi, periodic, mass, targets=None):
+def density_sum(x, y, z, h, lo, hi, periodic, mass, targets=None, kernel="M4"):
     """Plain SPH sum rho_a = sum_b m W_ab(h_a) (Eq. SPHmass) and sum m dW/dh."""
     x, y, z, h = _d(x), _d(y), _d(z), _d(h)
     lo, hi = _box(lo, hi)
@@ -251,24 +307,62 @@ def density_sum(x, y, z, h, lo, hi, periodic, mass, targets=None):
     nt = x.shape[0] if t is None else t.shape[0]
     s = np.zeros(nt); ds = np.zeros(nt)
     lib().orc_density_sum(x.shape[0], x, y, z, h, lo, hi, int(bool(periodic)),
-                          float(mass), nt, tp, s, ds)
+                          float(mass), _kid(kernel), nt, tp, s, ds)
     return s, ds
 
 
 def force(x, y, z, vx, vy, vz, u, h, rho, omega, lo, hi, periodic, mass,
-          gamma=5.0 / 3.0, alpha=1.0, beta=2.0, beta_u=1.0, targets=None):
+          gamma=5.0 / 3.0, alpha=1.0, beta=2.0, beta_u=1.0, targets=None, kernel="M4",
+          alpha_arr=None):
     """dv/dt, du/dt (Eqs. sphvel, sphuint with AV and conductivity), the
-    signal speed for the timestep and the per-particle error scales."""
+    signal speed for the timestep and the per-particle error scales.
+    alpha_arr: per-particle viscosity alpha (default: the constant alpha)."""
     arrs = [_d(a) for a in (x, y, z, vx, vy, vz, u, h, rho, omega)]
     lo, hi = _box(lo, hi)
     t, tp = _targets(targets)
     n = arrs[0].shape[0]
     nt = n if t is None else t.shape[0]
     out = [np.zeros(nt) for _ in range(7)]
+    al = None if alpha_arr is None else _d(alpha_arr)
     lib().orc_force(n, *arrs, lo, hi, int(bool(periodic)), float(mass), float(gamma),
-                    float(alpha), float(beta), float(beta_u), nt, tp, *out)
+                    float(alpha), None if al is None else al.ctypes.data_as(C.c_void_p),
+                    float(beta), float(beta_u), _kid(kernel), nt, tp, *out)
     keys = ("ax", "ay", "az", "dudt", "vsig", "scale_a", "scale_u")
     return dict(zip(keys, out))
+
+
+def gradient(x, y, z, fx, fy, fz, h, rho, omega, lo, hi, periodic, mass, kernel="M4",
+             targets=None):
+    """SPH gradient of a vector field, (nt, 3, 3) with [i][j] = d_j f_i."""
+    arrs = [_d(a) for a in (x, y, z, fx, fy, fz, h, rho, omega)]
+    lo, hi = _box(lo, hi)
+    t, tp = _targets(targets)
+    n = arrs[0].shape[0]
+    nt = n if t is None else t.shape[0]
+    out = np.zeros(9 * nt)
+    lib().orc_gradient(n, *arrs, lo, hi, int(bool(periodic)), float(mass), _kid(kernel),
+                       nt, tp, out)
+    return out.reshape(nt, 3, 3)
+
+
+def alpha_switch(x, y, z, vx, vy, vz, ax, ay, az, u, h, rho, omega, alpha_n, lo, hi,
+                 periodic, mass, dt, **params):
+    """Shock detector and implicit alpha update (App. G, Shock detection):
+    returns dict(alpha, alpha_loc, divv, ddivv_dt)."""
+    arrs = [_d(a) for a in (x, y, z, vx, vy, vz, ax, ay, az, u, h, rho, omega, alpha_n)]
+    lo, hi = _box(lo, hi)
+    n = arrs[0].shape[0]
+    P = make_params(**params)
+    out = [np.zeros(n) for _ in range(4)]
+    lib().orc_alpha_switch(n, *arrs, lo, hi, int(bool(periodic)), float(mass), C.byref(P),
+                           float(dt), out[0], out[1].ctypes.data_as(C.c_void_p),
+                           out[2].ctypes.data_as(C.c_void_p), out[3].ctypes.data_as(C.c_void_p))
+    return dict(alpha=out[0], alpha_loc=out[1], divv=out[2], ddivv_dt=out[3])
+
+
+def cfl_multiplier(lam: float, rerun: bool, lambda_stiff: float) -> float:
+    """Next CFL multiplier (App. G, CFL multiplier)."""
+    return float(lib().orc_cfl_multiplier(float(lam), int(bool(rerun)), float(lambda_stiff)))
 
 
 def cfl(h, vsig, ax, ay, az, c_cour=0.3, c_force=0.25) -> float:
@@ -277,21 +371,26 @@ def cfl(h, vsig, ax, ay, az, c_cour=0.3, c_force=0.25) -> float:
                                float(c_cour), float(c_force)))
 
 
-def step(state: dict, lo, hi, periodic, mass, dt, hfact=1.2, gamma=5.0 / 3.0,
-         alpha=1.0, beta=2.0, beta_u=1.0, c_cour=0.3, c_force=0.25):
+def step(state: dict, lo, hi, periodic, mass, dt, **params):
     """One fixed-dt KDK step (App. G.1).  ``state`` holds x,y,z,vx,vy,vz,u,h,
-    ax,ay,az,dudt (FP64 copies are made); returns the new state dict with
-    rho, omega and diag = (max|dv|, sum|dv|^2, sum|v|^2, cfl dt)."""
+    ax,ay,az,dudt (and alpha with alpha_switch=True); FP64 copies are made.
+    params: see make_params (hfact, kernel, eps_v / max_rerun for corrector
+    re-runs, the alpha switch ...).  Returns the new state dict with rho,
+    omega and diag = (max|dv|, sum|dv|^2, sum|v|^2, cfl dt, re-runs)."""
     keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay", "az", "dudt")
     s = {k: _d(state[k]).copy() for k in keys}
     n = s["x"].shape[0]
     s["rho"] = np.zeros(n); s["omega"] = np.zeros(n)
-    diag = np.zeros(4)
+    P = make_params(**params)
+    al = None
+    if P.alpha_switch:
+        al = _d(state["alpha"]).copy() if "alpha" in state else np.full(n, P.alpha)
+        s["alpha"] = al
+    diag = np.zeros(5)
     lo, hi = _box(lo, hi)
-    lib().orc_step(n, *[s[k] for k in keys], s["rho"], s["omega"], lo, hi,
-                   int(bool(periodic)), float(mass), float(hfact), float(gamma),
-                   float(alpha), float(beta), float(beta_u), float(c_cour),
-                   float(c_force), float(dt), diag)
+    lib().orc_step(n, *[s[k] for k in keys], s["rho"], s["omega"],
+                   None if al is None else al.ctypes.data_as(C.c_void_p), lo, hi,
+                   int(bool(periodic)), float(mass), C.byref(P), float(dt), diag)
     s["diag"] = diag
     return s
 

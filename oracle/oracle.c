@@ -519,36 +519,121 @@ DEFINE_NEIGH(float, f32, fmaf)
 DEFINE_NEIGH(double, f64, fma)
 
 /* ------------------------------------------------------------------ */
-/* M4 cubic spline (Schoenberg B-spline), C_norm = 1/pi in 3D, support  */
-/* radius 2h.  f(q), f'(q).                                             */
+/* Kernel functions f(q) of Sect. 2.1.1 (Eq. rhosphsum): the Schoenberg  */
+/* B-splines M4, M5, M6 and the Wendland functions C2, C4, C6, in their  */
+/* textbook forms with support radius R (q in units of h) and the 3-D    */
+/* normalisation C_norm such that int W dV = 1:                         */
+/*   M4: R = 2,   C = 1/pi,       f = 1 - 3/2 q^2 + 3/4 q^3 (q<1),     */
+/*                                    (2-q)^3/4 (1<=q<2)                */
+/*   M5: R = 5/2, C = 1/(20 pi),  f = (5/2-q)^4 - 5 (3/2-q)^4           */
+/*                                    + 10 (1/2-q)^4, each term only    */
+/*                                    while its bracket is positive     */
+/*   M6: R = 3,   C = 1/(120 pi), f = (3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5, */
+/*                                    same rule                         */
+/*   C2: R = 2,   C = 21/(16 pi),   f = (1-q/2)^4 (1 + 2q)              */
+/*   C4: R = 2,   C = 495/(256 pi), f = (1-q/2)^6 (1 + 3q + 35/12 q^2)  */
+/*   C6: R = 2,   C = 1365/(512 pi),f = (1-q/2)^8 (1 + 4q + 25/4 q^2    */
+/*                                    + 4 q^3)                          */
+/* f'(q) is the derivative of each piece, written out by the product    */
+/* and chain rules.                                                     */
 /* ------------------------------------------------------------------ */
-static double m4_f(double q)
+enum { K_M4 = 0, K_M5 = 1, K_M6 = 2, K_C2 = 3, K_C4 = 4, K_C6 = 5, K_NUM = 6 };
+
+static double pos(double t) { return t > 0.0 ? t : 0.0; }
+
+static double kern_R(int k)
 {
-    if (q < 1.0) return 1.0 - 1.5 * q * q + 0.75 * q * q * q;
-    if (q < 2.0) { double t = 2.0 - q; return 0.25 * t * t * t; }
-    return 0.0;
+    switch (k) {
+    case K_M5: return 2.5;
+    case K_M6: return 3.0;
+    default: return 2.0;
+    }
 }
 
-static double m4_df(double q)
+static double kern_C(int k)
 {
-    if (q < 1.0) return -3.0 * q + 2.25 * q * q;
-    if (q < 2.0) { double t = 2.0 - q; return -0.75 * t * t; }
-    return 0.0;
+    switch (k) {
+    case K_M4: return 1.0 / M_PI;
+    case K_M5: return 1.0 / (20.0 * M_PI);
+    case K_M6: return 1.0 / (120.0 * M_PI);
+    case K_C2: return 21.0 / (16.0 * M_PI);
+    case K_C4: return 495.0 / (256.0 * M_PI);
+    default:   return 1365.0 / (512.0 * M_PI);
+    }
 }
 
-double orc_m4_f(double q) { return m4_f(q); }
-double orc_m4_df(double q) { return m4_df(q); }
+static double kern_f(int k, double q)
+{
+    if (!(q < kern_R(k))) return 0.0;
+    switch (k) {
+    case K_M4:
+        if (q < 1.0) return 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+        { double t = 2.0 - q; return 0.25 * t * t * t; }
+    case K_M5: {
+        double a = pos(2.5 - q), b = pos(1.5 - q), c = pos(0.5 - q);
+        return pow(a, 4) - 5.0 * pow(b, 4) + 10.0 * pow(c, 4);
+    }
+    case K_M6: {
+        double a = pos(3.0 - q), b = pos(2.0 - q), c = pos(1.0 - q);
+        return pow(a, 5) - 6.0 * pow(b, 5) + 15.0 * pow(c, 5);
+    }
+    case K_C2: { double t = 1.0 - 0.5 * q; return pow(t, 4) * (1.0 + 2.0 * q); }
+    case K_C4: { double t = 1.0 - 0.5 * q; return pow(t, 6) * (1.0 + 3.0 * q + 35.0 / 12.0 * q * q); }
+    default:   { double t = 1.0 - 0.5 * q;
+                 return pow(t, 8) * (1.0 + 4.0 * q + 6.25 * q * q + 4.0 * q * q * q); }
+    }
+}
+
+static double kern_df(int k, double q)
+{
+    if (!(q < kern_R(k))) return 0.0;
+    switch (k) {
+    case K_M4:
+        if (q < 1.0) return -3.0 * q + 2.25 * q * q;
+        { double t = 2.0 - q; return -0.75 * t * t; }
+    case K_M5: {
+        double a = pos(2.5 - q), b = pos(1.5 - q), c = pos(0.5 - q);
+        return -4.0 * pow(a, 3) + 20.0 * pow(b, 3) - 40.0 * pow(c, 3);
+    }
+    case K_M6: {
+        double a = pos(3.0 - q), b = pos(2.0 - q), c = pos(1.0 - q);
+        return -5.0 * pow(a, 4) + 30.0 * pow(b, 4) - 75.0 * pow(c, 4);
+    }
+    case K_C2: {   /* d/dq [t^4 (1+2q)], dt/dq = -1/2 */
+        double t = 1.0 - 0.5 * q;
+        return 4.0 * pow(t, 3) * (-0.5) * (1.0 + 2.0 * q) + pow(t, 4) * 2.0;
+    }
+    case K_C4: {
+        double t = 1.0 - 0.5 * q;
+        return 6.0 * pow(t, 5) * (-0.5) * (1.0 + 3.0 * q + 35.0 / 12.0 * q * q)
+               + pow(t, 6) * (3.0 + 35.0 / 6.0 * q);
+    }
+    default: {
+        double t = 1.0 - 0.5 * q;
+        return 8.0 * pow(t, 7) * (-0.5) * (1.0 + 4.0 * q + 6.25 * q * q + 4.0 * q * q * q)
+               + pow(t, 8) * (4.0 + 12.5 * q + 12.0 * q * q);
+    }
+    }
+}
+
+int orc_kernel_count(void) { return K_NUM; }
+double orc_kernel_support(int k) { return kern_R(k); }
+double orc_kernel_norm(int k) { return kern_C(k); }
+double orc_kernel_f(int k, double q) { return kern_f(k, q); }
+double orc_kernel_df(int k, double q) { return kern_df(k, q); }
+double orc_m4_f(double q) { return kern_f(K_M4, q); }
+double orc_m4_df(double q) { return kern_df(K_M4, q); }
 
 /* W(r,h) = C_norm f(r/h) / h^3 (Eq. rhosphsum). */
-static double W(double r, double h) { return m4_f(r / h) / (M_PI * h * h * h); }
-/* dW/dh at fixed r = -(3 f + q f') / (pi h^4). */
-static double dWdh(double r, double h)
+static double W(int k, double r, double h) { return kern_C(k) * kern_f(k, r / h) / (h * h * h); }
+/* dW/dh at fixed r = -C_norm (3 f + q f') / h^4. */
+static double dWdh(int k, double r, double h)
 {
     double q = r / h;
-    return -(3.0 * m4_f(q) + q * m4_df(q)) / (M_PI * h * h * h * h);
+    return -kern_C(k) * (3.0 * kern_f(k, q) + q * kern_df(k, q)) / (h * h * h * h);
 }
-/* F(r,h) = rhat . grad_a W = f'(q) / (pi h^4). */
-static double Fgrad(double r, double h) { return m4_df(r / h) / (M_PI * h * h * h * h); }
+/* F(r,h) = rhat . grad_a W = C_norm f'(q) / h^4. */
+static double Fgrad(int k, double r, double h) { return kern_C(k) * kern_df(k, r / h) / (h * h * h * h); }
 
 /* ------------------------------------------------------------------ */
 /* Smoothing length (App. F): h_a is the root of                       */
@@ -578,11 +663,11 @@ static void visit_r(void *u, int64_t b)
     }
 }
 
-static void g_eval(const double *r, int64_t n, double h, double m, double hfact,
+static void g_eval(int kern, const double *r, int64_t n, double h, double m, double hfact,
                    double *g, double *dg)
 {
     double s = 0, ds = 0;
-    for (int64_t k = 0; k < n; ++k) { s += W(r[k], h); ds += dWdh(r[k], h); }
+    for (int64_t k = 0; k < n; ++k) { s += W(kern, r[k], h); ds += dWdh(kern, r[k], h); }
     double hf3 = hfact * hfact * hfact;
     *g = m * s - m * hf3 / (h * h * h);
     *dg = m * ds + 3.0 * m * hf3 / (h * h * h * h);
@@ -590,43 +675,44 @@ static void g_eval(const double *r, int64_t n, double h, double m, double hfact,
 
 void orc_density(int64_t n, const double *x, const double *y, const double *z,
                  const double *h0, const double *lo, const double *hi, int periodic,
-                 double m, double hfact, int64_t nt, const int64_t *targets,
+                 double m, double hfact, int kern, int64_t nt, const int64_t *targets,
                  double *h_out, double *rho_out, double *omega_out, int32_t *flags)
 {
+    const double R = kern_R(kern);
     double L[3];
     for (int d = 0; d < 3; ++d) L[d] = hi[d] - lo[d];
     double hmax = 0;
     for (int64_t i = 0; i < n; ++i) if (h0[i] > hmax) hmax = h0[i];
     grid_t g;
-    grid_build(&g, n, x, y, z, lo, hi, periodic, 2.0 * hmax);
+    grid_build(&g, n, x, y, z, lo, hi, periodic, R * hmax);
     #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t t = 0; t < nt; ++t) {
         int64_t a = targets ? targets[t] : t;
         int32_t flag = 0;
-        double reach = 4.0 * h0[a];
+        double reach = 2.0 * R * h0[a];
         rctx_t c = { NULL, 0, 0, x, y, z, L, periodic, a, 0 };
         double hroot = h0[a];
         for (int attempt = 0; attempt < 8; ++attempt) {
             c.cnt = 0; c.rmax = reach;
             grid_visit(&g, x[a], y[a], z[a], reach, visit_r, &c);
-            /* bracket: g(lo) < 0 < g(hi), both with 2h <= reach */
+            /* bracket: g(lo) < 0 < g(hi), both with R h <= reach */
             double hlo = h0[a], hhi = h0[a], glo, ghi, dg;
-            double hcap = 0.5 * reach;
-            g_eval(c.r, c.cnt, hlo, m, hfact, &glo, &dg);
+            double hcap = reach / R;
+            g_eval(kern, c.r, c.cnt, hlo, m, hfact, &glo, &dg);
             int ok = 1;
             if (glo > 0) {                   /* root below: shrink */
                 ghi = glo; hhi = hlo;
                 while (glo > 0) {
                     hhi = hlo; ghi = glo; hlo /= 1.2;
-                    g_eval(c.r, c.cnt, hlo, m, hfact, &glo, &dg);
+                    g_eval(kern, c.r, c.cnt, hlo, m, hfact, &glo, &dg);
                     if (hlo < 1e-12 * h0[a]) { ok = 0; break; }
                 }
             } else {                         /* root above: grow */
-                g_eval(c.r, c.cnt, hhi, m, hfact, &ghi, &dg);
+                g_eval(kern, c.r, c.cnt, hhi, m, hfact, &ghi, &dg);
                 while (ghi <= 0) {
                     hlo = hhi; glo = ghi; hhi *= 1.2;
                     if (hhi > hcap) { ok = -1; break; }
-                    g_eval(c.r, c.cnt, hhi, m, hfact, &ghi, &dg);
+                    g_eval(kern, c.r, c.cnt, hhi, m, hfact, &ghi, &dg);
                 }
             }
             if (ok == -1) { reach *= 2.0; continue; }
@@ -636,7 +722,7 @@ void orc_density(int64_t n, const double *x, const double *y, const double *z,
                 int changes = 0; double gp = glo;
                 for (int k = 1; k <= 16; ++k) {
                     double hk = hlo + (hhi - hlo) * k / 16.0, gk, dk;
-                    g_eval(c.r, c.cnt, hk, m, hfact, &gk, &dk);
+                    g_eval(kern, c.r, c.cnt, hk, m, hfact, &gk, &dk);
                     if ((gk > 0) != (gp > 0)) ++changes;
                     gp = gk;
                 }
@@ -646,7 +732,7 @@ void orc_density(int64_t n, const double *x, const double *y, const double *z,
             int conv = 0;
             for (int it = 0; it < 200; ++it) {
                 double gv, dv;
-                g_eval(c.r, c.cnt, hcur, m, hfact, &gv, &dv);
+                g_eval(kern, c.r, c.cnt, hcur, m, hfact, &gv, &dv);
                 if (gv > 0) hhi = hcur; else hlo = hcur;
                 double hn = (dv != 0) ? hcur - gv / dv : 0.5 * (hlo + hhi);
                 if (!(hn > hlo && hn < hhi)) hn = 0.5 * (hlo + hhi);
@@ -661,9 +747,9 @@ void orc_density(int64_t n, const double *x, const double *y, const double *z,
         }
         double rho = m * (hfact / hroot) * (hfact / hroot) * (hfact / hroot);
         double ds = 0;
-        c.cnt = 0; c.rmax = 2.0 * hroot;
-        grid_visit(&g, x[a], y[a], z[a], 2.0 * hroot, visit_r, &c);
-        for (int64_t k = 0; k < c.cnt; ++k) ds += dWdh(c.r[k], hroot);
+        c.cnt = 0; c.rmax = R * hroot;
+        grid_visit(&g, x[a], y[a], z[a], R * hroot, visit_r, &c);
+        for (int64_t k = 0; k < c.cnt; ++k) ds += dWdh(kern, c.r[k], hroot);
         h_out[t] = hroot;
         rho_out[t] = rho;
         omega_out[t] = 1.0 + hroot / (3.0 * rho) * m * ds;
@@ -676,22 +762,23 @@ void orc_density(int64_t n, const double *x, const double *y, const double *z,
 /* Plain SPH density sum at a given h (Eq. SPHmass), for the pins. */
 void orc_density_sum(int64_t n, const double *x, const double *y, const double *z,
                      const double *h, const double *lo, const double *hi, int periodic,
-                     double m, int64_t nt, const int64_t *targets, double *rho_sum,
+                     double m, int kern, int64_t nt, const int64_t *targets, double *rho_sum,
                      double *dsum_dh)
 {
+    const double R = kern_R(kern);
     double L[3];
     for (int d = 0; d < 3; ++d) L[d] = hi[d] - lo[d];
     double hmax = 0;
     for (int64_t i = 0; i < n; ++i) if (h[i] > hmax) hmax = h[i];
     grid_t g;
-    grid_build(&g, n, x, y, z, lo, hi, periodic, 2.0 * hmax);
+    grid_build(&g, n, x, y, z, lo, hi, periodic, R * hmax);
     #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t t = 0; t < nt; ++t) {
         int64_t a = targets ? targets[t] : t;
-        rctx_t c = { NULL, 0, 0, x, y, z, L, periodic, a, 2.0 * h[a] };
-        grid_visit(&g, x[a], y[a], z[a], 2.0 * h[a], visit_r, &c);
+        rctx_t c = { NULL, 0, 0, x, y, z, L, periodic, a, R * h[a] };
+        grid_visit(&g, x[a], y[a], z[a], R * h[a], visit_r, &c);
         double s = 0, ds = 0;
-        for (int64_t k = 0; k < c.cnt; ++k) { s += W(c.r[k], h[a]); ds += dWdh(c.r[k], h[a]); }
+        for (int64_t k = 0; k < c.cnt; ++k) { s += W(kern, c.r[k], h[a]); ds += dWdh(kern, c.r[k], h[a]); }
         rho_sum[t] = m * s;
         if (dsum_dh) dsum_dh[t] = m * ds;
         free(c.r);
@@ -708,7 +795,8 @@ void orc_density_sum(int64_t n, const double *x, const double *y, const double *
 /*   du_a/dt =  sum_b m (P_a+q^a)/(rho_a^2 Om_a) w F(h_a) + Lambda_a    */
 /*   Lambda_a = sum_b m beta_u vsig_u (u_a-u_b) (F(h_a)/(Om_a rho_a)     */
 /*                                            + F(h_b)/(Om_b rho_b))/2  */
-/* with w = v_ab . rhat_ab, vsig = alpha c_s + beta |w|,                 */
+/* with w = v_ab . rhat_ab, vsig = alpha c_s + beta |w| (alpha per      */
+/* particle when an array is given, Sect. 2.1.1 alpha_a^AV),            */
 /* q = -rho vsig w / 2 when w < 0, vsig_u = sqrt(|P_a-P_b|/((rho_a+rho_b)/2)),*/
 /* P = (gamma-1) rho u, c_s = sqrt(gamma P / rho).                      */
 /* Also returned: vsig_dt (max signal speed, floor c_s) and the scales  */
@@ -737,21 +825,22 @@ void orc_force(int64_t n, const double *x, const double *y, const double *z,
                const double *vx, const double *vy, const double *vz, const double *u,
                const double *h, const double *rho, const double *omega,
                const double *lo, const double *hi, int periodic, double m,
-               double gamma, double alpha, double beta, double beta_u,
-               int64_t nt, const int64_t *targets,
+               double gamma, double alpha, const double *alpha_arr, double beta, double beta_u,
+               int kern, int64_t nt, const int64_t *targets,
                double *ax, double *ay, double *az, double *dudt, double *vsig_dt,
                double *scale_a, double *scale_u)
 {
+    const double R = kern_R(kern);
     double L[3];
     for (int d = 0; d < 3; ++d) L[d] = hi[d] - lo[d];
     double hmax = 0;
     for (int64_t i = 0; i < n; ++i) if (h[i] > hmax) hmax = h[i];
     grid_t g;
-    grid_build(&g, n, x, y, z, lo, hi, periodic, 2.0 * hmax);
+    grid_build(&g, n, x, y, z, lo, hi, periodic, R * hmax);
     #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t t = 0; t < nt; ++t) {
         int64_t a = targets ? targets[t] : t;
-        double reach = 2.0 * (h[a] > hmax ? h[a] : hmax);
+        double reach = R * (h[a] > hmax ? h[a] : hmax);
         bctx_t c = { NULL, 0, 0, x, y, z, L, periodic, a, reach };
         grid_visit(&g, x[a], y[a], z[a], reach, visit_b, &c);
         double Pa = (gamma - 1.0) * rho[a] * u[a];
@@ -765,17 +854,18 @@ void orc_force(int64_t n, const double *x, const double *y, const double *z,
             sep64(L, periodic, x[a], y[a], z[a], x[b], y[b], z[b], d);
             double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             double hm = h[a] > h[b] ? h[a] : h[b];
-            if (!(r > 0.0) || !(r < 2.0 * hm)) continue;
+            if (!(r > 0.0) || !(r < R * hm)) continue;
             double rh[3] = { d[0] / r, d[1] / r, d[2] / r };
             double vab[3] = { vx[a] - vx[b], vy[a] - vy[b], vz[a] - vz[b] };
             double w = vab[0] * rh[0] + vab[1] * rh[1] + vab[2] * rh[2];
             double Pb = (gamma - 1.0) * rho[b] * u[b];
             double cb = sqrt(gamma * Pb / rho[b]);
-            double vsa = alpha * ca + beta * fabs(w);
-            double vsb = alpha * cb + beta * fabs(w);
+            double al_a = alpha_arr ? alpha_arr[a] : alpha, al_b = alpha_arr ? alpha_arr[b] : alpha;
+            double vsa = al_a * ca + beta * fabs(w);
+            double vsb = al_b * cb + beta * fabs(w);
             double qa = (w < 0) ? -0.5 * rho[a] * vsa * w : 0.0;
             double qb = (w < 0) ? -0.5 * rho[b] * vsb * w : 0.0;
-            double Fa = Fgrad(r, h[a]), Fb = Fgrad(r, h[b]);
+            double Fa = Fgrad(kern, r, h[a]), Fb = Fgrad(kern, r, h[b]);
             double ta = (Pa + qa) / (rho[a] * rho[a] * omega[a]) * Fa;
             double tb = (Pb + qb) / (rho[b] * rho[b] * omega[b]) * Fb;
             double f = m * (ta + tb);
@@ -819,18 +909,154 @@ double orc_cfl(int64_t n, const double *h, const double *vsig, const double *ax,
 }
 
 /* ------------------------------------------------------------------ */
+/* SPH gradient of a vector field (the estimate used by the shock       */
+/* detector, with the same kernel gradient and Omega as the force):     */
+/*   (d_j f_i)_a = -1/(rho_a Omega_a) sum_b m (f_a - f_b)_i              */
+/*                 (rhat_ab)_j F_ab(h_a)                                 */
+/* over b within R h_a.  out: 9 per target, row-major [i][j] = d_j f_i.  */
+/* ------------------------------------------------------------------ */
+void orc_gradient(int64_t n, const double *x, const double *y, const double *z,
+                  const double *fx, const double *fy, const double *fz, const double *h,
+                  const double *rho, const double *omega, const double *lo, const double *hi,
+                  int periodic, double m, int kern, int64_t nt, const int64_t *targets,
+                  double *out)
+{
+    const double R = kern_R(kern);
+    double L[3];
+    for (int d = 0; d < 3; ++d) L[d] = hi[d] - lo[d];
+    double hmax = 0;
+    for (int64_t i = 0; i < n; ++i) if (h[i] > hmax) hmax = h[i];
+    grid_t g;
+    grid_build(&g, n, x, y, z, lo, hi, periodic, R * hmax);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t a = targets ? targets[t] : t;
+        bctx_t c = { NULL, 0, 0, x, y, z, L, periodic, a, R * h[a] };
+        grid_visit(&g, x[a], y[a], z[a], R * h[a], visit_b, &c);
+        double G[3][3] = { { 0 } };
+        const double *F[3] = { fx, fy, fz };
+        for (int64_t k = 0; k < c.cnt; ++k) {
+            int64_t b = c.b[k];
+            double d[3];
+            sep64(L, periodic, x[a], y[a], z[a], x[b], y[b], z[b], d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!(r > 0.0)) continue;
+            double Fa = Fgrad(kern, r, h[a]);
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    G[i][j] += m * (F[i][a] - F[i][b]) * (d[j] / r) * Fa;
+        }
+        double s = -1.0 / (rho[a] * omega[a]);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) out[9 * t + 3 * i + j] = s * G[i][j];
+        free(c.b);
+    }
+    grid_free(&g);
+}
+
+/* ------------------------------------------------------------------ */
+/* Parameters of the step.                                              */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    double hfact, gamma, alpha, beta, beta_u, c_cour, c_force;
+    int kernel;
+    /* corrector re-runs (App. G.1): while max_a |dv_a| > eps_v v_rms and  */
+    /* fewer than max_rerun re-runs were made, the force is evaluated       */
+    /* again with v* <- v^{n+1} (u* <- u^{n+1}) and the corrector re-applied */
+    double eps_v;
+    int max_rerun;
+    /* shock-detection switch (App. G, Shock detection)                     */
+    int alpha_switch;
+    double alpha_min, alpha_max, sigma_decay;
+} orc_params;
+
+/* ------------------------------------------------------------------ */
+/* Shock detector and the implicit alpha update (App. G, Eq.             */
+/* evolalphaanalytic and the two lines after it), for every particle,    */
+/* at the new positions with h, rho, Omega of the density pass:          */
+/*   grad v* and grad a^n by orc_gradient, div v = tr(grad v),           */
+/*   curl v from its antisymmetric part,                                  */
+/*   d(div v)/dt = div a - sum_ij (d_j v_i)(d_i v_j),                      */
+/*   xi = (div v)^2 / ((div v)^2 + |curl v|^2) (0 when both vanish),      */
+/*   A = xi max(-d(div v)/dt, 0),                                         */
+/*   alpha_loc = max(alpha_min, alpha_max 10 h^2 A / (10 h^2 A + c_s^2)), */
+/*   tau = h / (sigma_decay c_s),                                         */
+/*   alpha^{n+1} = max((alpha^n + alpha_loc dt/tau) / (1 + dt/tau),      */
+/*                     alpha_loc).                                        */
+/* c_s = sqrt(gamma (gamma-1) u*).  The paper gives the update and      */
+/* refers to Phantom for alpha_loc and tau; the forms above are this     */
+/* implementation's reading (Cullen-Dehnen switch with a Balsara-type    */
+/* limiter).  Outputs (optional): alpha_loc, div v, d(div v)/dt.         */
+/* ------------------------------------------------------------------ */
+void orc_alpha_switch(int64_t n, const double *x, const double *y, const double *z,
+                      const double *vx, const double *vy, const double *vz,
+                      const double *ax, const double *ay, const double *az, const double *u,
+                      const double *h, const double *rho, const double *omega,
+                      const double *alpha_n, const double *lo, const double *hi, int periodic,
+                      double m, const orc_params *P, double dt, double *alpha_out,
+                      double *aloc_out, double *divv_out, double *ddiv_out)
+{
+    size_t sz = sizeof(double) * 9 * (size_t)(n > 0 ? n : 1);
+    double *gv = malloc(sz), *ga = malloc(sz);
+    orc_gradient(n, x, y, z, vx, vy, vz, h, rho, omega, lo, hi, periodic, m, P->kernel, n, NULL, gv);
+    orc_gradient(n, x, y, z, ax, ay, az, h, rho, omega, lo, hi, periodic, m, P->kernel, n, NULL, ga);
+    for (int64_t a = 0; a < n; ++a) {
+        const double *V = gv + 9 * a, *A = ga + 9 * a;   /* [i][j] = d_j f_i */
+        double divv = V[0] + V[4] + V[8];
+        double diva = A[0] + A[4] + A[8];
+        double cx = V[3 * 2 + 1] - V[3 * 1 + 2];          /* d_y v_z - d_z v_y */
+        double cy = V[3 * 0 + 2] - V[3 * 2 + 0];          /* d_z v_x - d_x v_z */
+        double cz = V[3 * 1 + 0] - V[3 * 0 + 1];          /* d_x v_y - d_y v_x */
+        double vv = 0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) vv += V[3 * i + j] * V[3 * j + i];
+        double ddiv = diva - vv;
+        double d2 = divv * divv, c2 = cx * cx + cy * cy + cz * cz;
+        double xi = (d2 + c2 > 0) ? d2 / (d2 + c2) : 0.0;
+        double Ash = xi * (ddiv < 0 ? -ddiv : 0.0);
+        double cs = sqrt(P->gamma * (P->gamma - 1.0) * u[a]);
+        double hh = 10.0 * h[a] * h[a] * Ash;
+        double aloc = (hh + cs * cs > 0) ? P->alpha_max * hh / (hh + cs * cs) : 0.0;
+        if (aloc < P->alpha_min) aloc = P->alpha_min;
+        double al = aloc;
+        if (cs > 0) {
+            double x_ = dt * P->sigma_decay * cs / h[a];   /* dt / tau */
+            al = (alpha_n[a] + aloc * x_) / (1.0 + x_);
+            if (al < aloc) al = aloc;
+        } else if (alpha_n[a] > aloc) {
+            al = alpha_n[a];                               /* tau infinite: no decay */
+        }
+        alpha_out[a] = al;
+        if (aloc_out) aloc_out[a] = aloc;
+        if (divv_out) divv_out[a] = divv;
+        if (ddiv_out) ddiv_out[a] = ddiv;
+    }
+    free(gv); free(ga);
+}
+
+/* CFL multiplier (App. G, CFL multiplier): halved after a step whose     */
+/* corrector had to be re-run, else relaxed towards 1:                    */
+/*   lambda^{n+1} = (1 + lambda_stiff lambda^n) / (1 + lambda_stiff).     */
+double orc_cfl_multiplier(double lam, int rerun, double lambda_stiff)
+{
+    if (rerun) return 0.5 * lam;
+    return (1.0 + lambda_stiff * lam) / (1.0 + lambda_stiff);
+}
+
+/* ------------------------------------------------------------------ */
 /* One kick-drift-kick step with a fixed dt (App. G.1), u integrated    */
-/* like v.  In: state at t^n (x,v,u,h) and the derivatives a^n, du^n.   */
-/* Out (in place): state at t^{n+1}, h^{n+1}, rho, Omega, a^{n+1},       */
-/* du^{n+1}.  diag[0] = max |dv|, diag[1] = sum |dv|^2, diag[2] =        */
-/* sum |v^{n+1}|^2, diag[3] = CFL dt of the new state.                   */
+/* like v.  In: state at t^n (x,v,u,h, alpha if the switch is on) and    */
+/* the derivatives a^n, du^n.  Out (in place): state at t^{n+1}, h^{n+1}, */
+/* rho, Omega, a^{n+1}, du^{n+1}, alpha^{n+1}.  diag[0] = max |dv|,       */
+/* diag[1] = sum |dv|^2, diag[2] = sum |v^{n+1}|^2, diag[3] = CFL dt of    */
+/* the new state, diag[4] = corrector re-runs made (of the last           */
+/* corrector: dv = v^{n+1} - v*).                                         */
 /* ------------------------------------------------------------------ */
 void orc_step(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
               double *vz, double *u, double *h, double *ax, double *ay, double *az,
-              double *dudt, double *rho, double *omega,
+              double *dudt, double *rho, double *omega, double *alpha,
               const double *lo, const double *hi, int periodic, double m,
-              double hfact, double gamma, double alpha, double beta, double beta_u,
-              double c_cour, double c_force, double dt, double *diag)
+              const orc_params *P, double dt, double *diag)
 {
     double L[3];
     for (int d = 0; d < 3; ++d) L[d] = hi[d] - lo[d];
@@ -838,8 +1064,8 @@ void orc_step(int64_t n, double *x, double *y, double *z, double *vx, double *vy
     double *vhx = malloc(sz), *vhy = malloc(sz), *vhz = malloc(sz), *uh = malloc(sz);
     double *vsx = malloc(sz), *vsy = malloc(sz), *vsz = malloc(sz), *us = malloc(sz);
     double *nax = malloc(sz), *nay = malloc(sz), *naz = malloc(sz), *ndu = malloc(sz);
-    double *hn = malloc(sz), *vs = malloc(sz);
-    double *P[3] = { x, y, z };
+    double *hn = malloc(sz), *vs = malloc(sz), *al = malloc(sz);
+    double *P3[3] = { x, y, z };
     for (int64_t i = 0; i < n; ++i) {
         vhx[i] = vx[i] + 0.5 * dt * ax[i];
         vhy[i] = vy[i] + 0.5 * dt * ay[i];
@@ -848,8 +1074,8 @@ void orc_step(int64_t n, double *x, double *y, double *z, double *vx, double *vy
         x[i] += dt * vhx[i]; y[i] += dt * vhy[i]; z[i] += dt * vhz[i];
         if (periodic) {
             for (int d = 0; d < 3; ++d) {
-                if (P[d][i] >= hi[d]) P[d][i] -= L[d];
-                if (P[d][i] < lo[d]) P[d][i] += L[d];
+                if (P3[d][i] >= hi[d]) P3[d][i] -= L[d];
+                if (P3[d][i] < lo[d]) P3[d][i] += L[d];
             }
         }
         vsx[i] = vhx[i] + 0.5 * dt * ax[i];
@@ -857,27 +1083,53 @@ void orc_step(int64_t n, double *x, double *y, double *z, double *vx, double *vy
         vsz[i] = vhz[i] + 0.5 * dt * az[i];
         us[i] = uh[i] + 0.5 * dt * dudt[i];
     }
-    orc_density(n, x, y, z, h, lo, hi, periodic, m, hfact, n, NULL, hn, rho, omega, NULL);
-    orc_force(n, x, y, z, vsx, vsy, vsz, us, hn, rho, omega, lo, hi, periodic, m,
-              gamma, alpha, beta, beta_u, n, NULL, nax, nay, naz, ndu, vs, NULL, NULL);
+    orc_density(n, x, y, z, h, lo, hi, periodic, m, P->hfact, P->kernel, n, NULL, hn, rho, omega,
+                NULL);
+    const double *alpha_use = NULL;
+    if (P->alpha_switch && alpha) {
+        /* alpha^{n+1} from v*, grad v*, grad a^n at the new positions */
+        orc_alpha_switch(n, x, y, z, vsx, vsy, vsz, ax, ay, az, us, hn, rho, omega, alpha, lo, hi,
+                         periodic, m, P, dt, al, NULL, NULL, NULL);
+        for (int64_t i = 0; i < n; ++i) alpha[i] = al[i];
+        alpha_use = alpha;
+    }
     double dvmax = 0, dvsum = 0, vsum = 0;
+    int rerun = 0;
+    for (;;) {
+        orc_force(n, x, y, z, vsx, vsy, vsz, us, hn, rho, omega, lo, hi, periodic, m,
+                  P->gamma, P->alpha, alpha_use, P->beta, P->beta_u, P->kernel, n, NULL,
+                  nax, nay, naz, ndu, vs, NULL, NULL);
+        dvmax = 0; dvsum = 0; vsum = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            /* v^{n+1} = v^{n+1/2} + dt/2 a^{n+1};  dv = v^{n+1} - v* */
+            double nvx = vhx[i] + 0.5 * dt * nax[i];
+            double nvy = vhy[i] + 0.5 * dt * nay[i];
+            double nvz = vhz[i] + 0.5 * dt * naz[i];
+            double dvx = nvx - vsx[i], dvy = nvy - vsy[i], dvz = nvz - vsz[i];
+            vx[i] = nvx; vy[i] = nvy; vz[i] = nvz;
+            u[i] = uh[i] + 0.5 * dt * ndu[i];
+            double dv = sqrt(dvx * dvx + dvy * dvy + dvz * dvz);
+            if (dv > dvmax) dvmax = dv;
+            dvsum += dv * dv;
+            vsum += vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
+        }
+        /* reversibility check: max |dv| against eps_v times the rms velocity */
+        int ok = !(P->eps_v > 0) || dvmax <= P->eps_v * sqrt(vsum / (double)(n > 0 ? n : 1));
+        if (ok || rerun >= P->max_rerun) break;
+        ++rerun;
+        for (int64_t i = 0; i < n; ++i) {   /* v* <- v^{n+1}, u* <- u^{n+1} */
+            vsx[i] = vx[i]; vsy[i] = vy[i]; vsz[i] = vz[i]; us[i] = u[i];
+        }
+    }
     for (int64_t i = 0; i < n; ++i) {
-        double dvx = 0.5 * dt * (nax[i] - ax[i]);
-        double dvy = 0.5 * dt * (nay[i] - ay[i]);
-        double dvz = 0.5 * dt * (naz[i] - az[i]);
-        vx[i] = vsx[i] + dvx; vy[i] = vsy[i] + dvy; vz[i] = vsz[i] + dvz;
-        u[i] = us[i] + 0.5 * dt * (ndu[i] - dudt[i]);
-        double dv = sqrt(dvx * dvx + dvy * dvy + dvz * dvz);
-        if (dv > dvmax) dvmax = dv;
-        dvsum += dv * dv;
-        vsum += vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
         ax[i] = nax[i]; ay[i] = nay[i]; az[i] = naz[i]; dudt[i] = ndu[i];
         h[i] = hn[i];
     }
     if (diag) {
         diag[0] = dvmax; diag[1] = dvsum; diag[2] = vsum;
-        diag[3] = orc_cfl(n, h, vs, ax, ay, az, c_cour, c_force);
+        diag[3] = orc_cfl(n, h, vs, ax, ay, az, P->c_cour, P->c_force);
+        diag[4] = rerun;
     }
     free(vhx); free(vhy); free(vhz); free(uh); free(vsx); free(vsy); free(vsz); free(us);
-    free(nax); free(nay); free(naz); free(ndu); free(hn); free(vs);
+    free(nax); free(nay); free(naz); free(ndu); free(hn); free(vs); free(al);
 }
