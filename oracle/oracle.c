@@ -22,7 +22,10 @@
  *   h / rho root ........... App. F Eq. rhoh, Sect. 2.1 Eqs. SPHmass/rhosphsum
  *   Omega .................. Sect. 2.1 Eq. sphomega
  *   force, du/dt ........... Sect. 2.1 Eqs. sphvel, sphuint (+ AV, conductivity)
- *   leapfrog, CFL .......... App. G.1 (KDK) and H.2 (timestep)
+ *   leapfrog, CFL .......... App. G.1 (KDK) and G.2 (timestep)
+ *   kernel family .......... Sect. 2.1.1: M4, M5, M6 B-splines, Wendland C2, C4, C6
+ *   corrector re-run ....... App. G.1 (Eqs. deltavi, cvleapfrog), CFL multiplier
+ *   shock detection ........ App. G (Eq. evolalphaanalytic and the implicit update)
  */
 #include <math.h>
 #include <stdint.h>
