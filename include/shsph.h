@@ -26,6 +26,7 @@
 #ifndef SHSPH_H
 #define SHSPH_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -75,7 +76,35 @@ typedef struct {
                                lanes take the wave's joint candidates; pays off when h is
                                large against the wave's extent), 0 = chosen per wave by
                                its estimated cost.  Work, not results. */
+    int32_t kernel;         /* smoothing kernel f (Sect. 2.1.1), SHSPH_KERNEL_*: support
+                               radius R h; the cache radius is R chi h.  Default M4.
+                               The paper's physics tests use M6 with hfact = 1.0. */
+    int32_t key_bits;       /* Morton code width (App. B.1, Sect. 5.2.1): 63 = 21 bits per
+                               axis in a 64-bit code (default), 30 = 10 bits per axis in
+                               a 32-bit code (faster tree build, coarser cells) */
+    double eps_v;           /* corrector re-run tolerance (App. G.1): after the
+                               corrector, if max |dv| > eps_v times the rms velocity the
+                               force is evaluated again with v* <- v^{n+1} and the
+                               corrector re-applied; 0 (default) = never */
+    int32_t max_reruns;     /* corrector re-runs allowed per step (default 3) */
+    int32_t alpha_switch;   /* 1: per-particle viscosity alpha evolved by the shock
+                               detector (App. G, Shock detection) in shsph_step, read
+                               from and written to shsph_particles.alpha; 0 (default):
+                               the constant alpha_av */
+    double lambda_stiff;    /* CFL multiplier stiffness (App. G, CFL multiplier): the
+                               multiplier halves after a re-run and relaxes as
+                               (1 + s l) / (1 + s) otherwise (default 1; only with
+                               eps_v > 0 and a CFL dt) */
+    double alpha_min, alpha_max;  /* bounds of the switch (0, 1) */
+    double sigma_decay;     /* decay time tau = h / (sigma_decay c_s) (0.1) */
 } shsph_params;
+
+#define SHSPH_KERNEL_M4 0
+#define SHSPH_KERNEL_M5 1
+#define SHSPH_KERNEL_M6 2
+#define SHSPH_KERNEL_C2 3
+#define SHSPH_KERNEL_C4 4
+#define SHSPH_KERNEL_C6 5
 
 /* One SPH instance.  x..h are read; h, rho, omega, ax..dudt are written as
  * documented per call.  `pid` (optional) is a per-particle id carried
@@ -98,6 +127,9 @@ typedef struct {
     void *dudt;             /* du/dt */
     void *rho, *omega;      /* optional outputs */
     uint32_t *pid;          /* optional */
+    void *alpha;            /* per-particle viscosity alpha (optional): read by the
+                               force and, with params.alpha_switch, evolved by
+                               shsph_step; NULL = the constant alpha_av */
 } shsph_particles;
 
 /* Counters of the last build / evaluation / step. */
@@ -115,6 +147,9 @@ typedef struct {
     double dv_max;           /* max |dv| of the last corrector */
     double dv2_sum;          /* sum |dv|^2 */
     double v2_sum;           /* sum |v^{n+1}|^2 */
+    int32_t reruns;          /* corrector re-runs of the last step (App. G.1) */
+    int32_t pad;
+    double cfl_multiplier;   /* CFL multiplier for the next CFL step (App. G) */
 } shsph_info;
 
 /* Host buffers receiving the tree of the last build (test and debug use).
@@ -157,6 +192,15 @@ int shsph_create(int device, const shsph_params *p, shsph_ctx **out);
 
 /* Release the context and all its device memory (waits for its stream). */
 int shsph_destroy(shsph_ctx *ctx);
+
+/* Replace the context's parameters (checked as at create; not while
+ * serving).  Later calls use them; the tree and caches of an earlier build
+ * stay valid only if kernel, chi, n_red and key_bits are unchanged.
+ * EINVAL for a parameter out of range, ESTATE while serving. */
+int shsph_set_params(shsph_ctx *ctx, const shsph_params *p);
+
+/* Copy the context's current parameters into *out. */
+int shsph_get_params(shsph_ctx *ctx, shsph_params *out);
 
 /* Use `stream` (a hipStream_t, NULL = the null stream) for all later work. */
 int shsph_set_stream(shsph_ctx *ctx, void *stream);

@@ -42,14 +42,22 @@ class Params(C.Structure):
                 ("lambda_", C.c_double), ("eps_h", C.c_double), ("c_cour", C.c_double),
                 ("c_force", C.c_double), ("max_iter", C.c_int32), ("n_red", C.c_int32),
                 ("max_restarts", C.c_int32), ("spread_slots", C.c_int32),
-                ("stage1_serial", C.c_int32), ("stage2_mode", C.c_int32)]
+                ("stage1_serial", C.c_int32), ("stage2_mode", C.c_int32),
+                ("kernel", C.c_int32), ("key_bits", C.c_int32), ("eps_v", C.c_double),
+                ("max_reruns", C.c_int32), ("alpha_switch", C.c_int32),
+                ("lambda_stiff", C.c_double), ("alpha_min", C.c_double),
+                ("alpha_max", C.c_double), ("sigma_decay", C.c_double)]
+
+
+KERNELS = {"M4": 0, "M5": 1, "M6": 2, "C2": 3, "C4": 4, "C6": 5}
 
 
 class CParticles(C.Structure):
     _fields_ = [("n", C.c_int64), ("dtype", C.c_int32), ("periodic", C.c_int32),
                 ("mass", C.c_double), ("lo", C.c_double * 3), ("hi", C.c_double * 3)] + \
                [(k, C.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay",
-                                          "az", "dudt", "rho", "omega")] + [("pid", C.c_void_p)]
+                                          "az", "dudt", "rho", "omega")] + [("pid", C.c_void_p),
+                                                                            ("alpha", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -57,7 +65,8 @@ class Info(C.Structure):
                 ("n_leaf_neigh", C.c_int64),
                 ("n_neigh", C.c_int64), ("n_red", C.c_int32), ("restarts", C.c_int32),
                 ("max_iter_seen", C.c_int32), ("n_noconv", C.c_int32), ("dt_cfl", C.c_double),
-                ("dv_max", C.c_double), ("dv2_sum", C.c_double), ("v2_sum", C.c_double)]
+                ("dv_max", C.c_double), ("dv2_sum", C.c_double), ("v2_sum", C.c_double),
+                ("reruns", C.c_int32), ("pad", C.c_int32), ("cfl_multiplier", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -122,6 +131,8 @@ def lib():
     L.shsph_create.argtypes = [ip, C.POINTER(Params), C.POINTER(vp)]
     L.shsph_destroy.argtypes = [vp]
     L.shsph_set_stream.argtypes = [vp, vp]
+    L.shsph_set_params.argtypes = [vp, C.POINTER(Params)]
+    L.shsph_get_params.argtypes = [vp, C.POINTER(Params)]
     L.shsph_last_error.argtypes = [vp]
     L.shsph_last_error.restype = C.c_char_p
     for fn in ("shsph_build_tree", "shsph_density", "shsph_force"):
@@ -152,8 +163,10 @@ def lib():
     L.shsph_footprint.argtypes = [vp, C.c_int64, C.c_int32, dp, dp]
     L.shsph_clock.argtypes = []
     L.shsph_clock.restype = C.c_double
-    for fn in ("shsph_create", "shsph_destroy", "shsph_set_stream", "shsph_build_tree",
-               "shsph_density", "shsph_force", "shsph_step", "shsph_get_info",
+    for fn in ("shsph_create", "shsph_destroy", "shsph_set_stream", "shsph_set_params",
+               "shsph_get_params", "shsph_build_tree",
+               "shsph_density", "shsph_force", "shsph_step",
+               "shsph_get_info",
                "shsph_export_tree", "shsph_set_profiling", "shsph_get_stage_times",
                "shsph_get_work", "shsph_instance_create", "shsph_instance_destroy",
                "shsph_instance_read", "shsph_instance_info", "shsph_step_batch",
@@ -196,15 +209,23 @@ class ParticleSet:
         if pid is None:
             pid = np.arange(self.n, dtype=np.int32)
         self.t["pid"] = torch.from_numpy(np.ascontiguousarray(np.asarray(pid).astype(np.int32))).to(device)
+        al = arrays.get("alpha")
+        if al is not None:      # per-particle viscosity alpha (a scalar fills every particle)
+            a = np.broadcast_to(np.asarray(al, dtype=self.dtype), (self.n,))
+            self.t["alpha"] = torch.from_numpy(np.ascontiguousarray(a)).to(device)
         self.mass = float(mass)
         self.lo = tuple(float(v) for v in lo)
         self.hi = tuple(float(v) for v in hi)
         self.periodic = bool(periodic)
 
     @classmethod
-    def from_particles(cls, p, device="cuda"):
-        """From a ``gen.Particles``-like object (numpy fields, mass, box)."""
-        return cls(p.fields(), p.mass, p.lo, p.hi, p.periodic, device=device)
+    def from_particles(cls, p, device="cuda", alpha=None):
+        """From a ``gen.Particles``-like object (numpy fields, mass, box);
+        alpha: optional per-particle viscosity alpha (array or scalar)."""
+        f = dict(p.fields())
+        if alpha is not None:
+            f["alpha"] = alpha
+        return cls(f, p.mass, p.lo, p.hi, p.periodic, device=device)
 
     def cstruct(self) -> CParticles:
         c = CParticles()
@@ -217,10 +238,11 @@ class ParticleSet:
         for k in self.FIELDS:
             setattr(c, k, self.t[k].data_ptr())
         c.pid = self.t["pid"].data_ptr()
+        c.alpha = self.t["alpha"].data_ptr() if "alpha" in self.t else None
         return c
 
     def host(self, *keys) -> dict:
-        keys = keys or (self.FIELDS + ("pid",))
+        keys = keys or (self.FIELDS + ("pid",) + (("alpha",) if "alpha" in self.t else ()))
         out = {k: self.t[k].cpu().numpy() for k in keys}
         if "pid" in out:
             out["pid"] = out["pid"].view(np.uint32)
@@ -235,6 +257,8 @@ class Context:
         if params is None:
             params = default_params()
         for k, v in kw.items():
+            if k == "kernel" and isinstance(v, str):
+                v = KERNELS[v]
             setattr(params, "lambda_" if k == "lambda" else k, v)
         self.params = params
         h = C.c_void_p()
@@ -252,6 +276,17 @@ class Context:
         if rc != SHSPH_OK and rc not in allow:
             raise ShsphError(rc, self.L.shsph_last_error(self.h).decode())
         return rc
+
+    def set_params(self, **kw) -> None:
+        """Change parameters of the context (shsph_set_params)."""
+        p = Params()
+        self._check(self.L.shsph_get_params(self.h, C.byref(p)))
+        for k, v in kw.items():
+            if k == "kernel" and isinstance(v, str):
+                v = KERNELS[v]
+            setattr(p, "lambda_" if k == "lambda" else k, v)
+        self._check(self.L.shsph_set_params(self.h, C.byref(p)))
+        self.params = p
 
     def set_stream(self, stream) -> None:
         self._check(self.L.shsph_set_stream(self.h, C.c_void_p(int(stream) if stream else 0)))

@@ -43,6 +43,8 @@ struct Inst {
     int periodic = 0;
     bool has_force = false;     // a derivative pass has run (CFL dt known)
     InstStat stat;              // reductions of the last pass
+    double lambda_cfl = 1.0;    // CFL multiplier (App. G)
+    int reruns = 0;             // corrector re-runs of the last pass
     int busy = 0;               // held by a running serving job
 };
 
@@ -83,11 +85,14 @@ struct shsph_ctx {
     int state = ST_NONE;
     int restarts = 0;
     int vals_sel = 0;       // which value buffer holds eps after the sort
+    double lambda_cfl = 1.0;  // CFL multiplier of the plain step (App. G)
+    int reruns_last = 0;      // corrector re-runs of the last plain step
     int xi_sel = 0;         // which mask buffer holds the final keep mask
 
     // device buffers (grown on demand, never shrunk)
     Buf keys[2], vals[2], hist, scan_tmp, bbox;          // hist: radix sort state
     Buf posh, velu, vhalf, hn, hcache, pid_s, thermo, omega, acc, vsig, status;
+    Buf alpha_s;                                // viscosity alpha in key order (switch)
     Buf xi[2], xscan, id, mu_leaf;
     Buf lchild, rchild, endrange, lflag, rflag, child, parent, arrive, blo, bhi;
     Buf rec, nrec, rscan;                       // bottom-up box records
@@ -253,7 +258,10 @@ SphParams sph_params(const shsph_params& q)
     SphParams s;
     s.hfact = q.hfact; s.gamma = q.gamma; s.alpha = q.alpha_av; s.beta = q.beta_av;
     s.beta_u = q.beta_u; s.chi = q.chi; s.lambda = q.lambda; s.eps_h = q.eps_h;
-    s.c_cour = q.c_cour; s.c_force = q.c_force; s.r_kern = 2.0; s.max_iter = q.max_iter;
+    s.c_cour = q.c_cour; s.c_force = q.c_force; s.max_iter = q.max_iter;
+    s.kernel = q.kernel;
+    s.r_kern = kernel_support(q.kernel);
+    s.alpha_min = q.alpha_min; s.alpha_max = q.alpha_max; s.sigma_decay = q.sigma_decay;
     return s;
 }
 
@@ -374,7 +382,7 @@ CacheView cache_view(shsph_ctx* c)
     v.capq = (u32)c->cap_words;
     v.glo = c->glo.p; v.ghi = c->ghi.p; v.blo = c->blo.p;
     v.root = P<u32>(c->root_d);
-    v.rk = 2.0 * c->prm.chi;
+    v.rk = kernel_support(c->prm.kernel) * c->prm.chi;
     return v;
 }
 
@@ -499,7 +507,7 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
     const int ninst = c->ninst;
     const vec4<T>* posh = P<vec4<T>>(c->posh);
     const GroupMap gm = group_map(c);
-    const double rk = 2.0 * c->prm.chi;
+    const double rk = kernel_support(c->prm.kernel) * c->prm.chi;
     // bottom-up boxes and h_max
     const size_t nrc = boxes_rec_count(nl);
     const i64 nbb = (i64)(nrc / 128) + 1;
@@ -684,9 +692,15 @@ template <class T> int do_force(shsph_ctx* c, shsph_particles* p)
     TRY(ensure(c, c->vsig, n * sizeof(T)));
     launch_gather_velu<T>(eps, n, (const T*)p->vx, (const T*)p->vy, (const T*)p->vz, (const T*)p->u,
                           P<vec4<T>>(c->velu), st);
+    const T* al = nullptr;
+    if (p->alpha) {           // per-particle viscosity alpha, gathered into key order
+        TRY(ensure(c, c->alpha_s, n * sizeof(T)));
+        launch_gather1<T>(eps, n, (const T*)p->alpha, P<T>(c->alpha_s), st);
+        al = P<T>(c->alpha_s);
+    }
     launch_thermo<T>(P<vec4<T>>(c->posh), P<vec4<T>>(c->velu), P<T>(c->omega), n, P<i64>(c->poff_d),
-                     c->ninst, P<InstDev>(c->inst_d), c->prm.hfact, c->prm.gamma,
-                     P<vec4<T>>(c->thermo), st);
+                     c->ninst, P<InstDev>(c->inst_d), c->prm.hfact, c->prm.gamma, c->prm.alpha_av,
+                     al, P<vec4<T>>(c->thermo), st);
     launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, 2, nullptr, st);
     c->parts_pending = 0;
     const SphParams sp = sph_params(c->prm);
@@ -708,6 +722,74 @@ template <class T> int do_force(shsph_ctx* c, shsph_particles* p)
     return SHSPH_OK;
 }
 
+// Corrector re-runs (App. G.1): an instance whose max |dv| exceeds eps_v
+// times its rms velocity gets v* <- v^{n+1}, u* <- u^{n+1} and the force and
+// corrector again, at most max_reruns times.  The derivative kernels run
+// over the whole pass; instances that passed keep v*, so they recompute
+// exactly what they had.  Leaves the folded reductions in stat_d and the
+// re-run count of each instance in `reruns`.
+template <class T>
+int corrector_reruns(shsph_ctx* c, const OutPtrs<T>& o, const double* dt_dev, std::vector<int>& reruns,
+                     const T* alpha_s = nullptr)
+{
+    hipStream_t st = c->stream;
+    const int ninst = c->ninst;
+    const i64 n = c->n, nb = (n + GROUP - 1) / GROUP;
+    reruns.assign(ninst, 0);
+    if (!(c->prm.eps_v > 0)) return SHSPH_OK;
+    std::vector<u8> redo(ninst, 0);
+    for (;;) {
+        if (c->parts_pending > 0) {
+            launch_fold_parts(P<BlockPart>(c->bpart), c->parts_pending, ninst,
+                              P<InstStat>(c->stat_d), st);
+            c->parts_pending = 0;
+        }
+        TRY(read_back(c, c->stat_d.p, ninst * sizeof(InstStat)));
+        const InstStat* hs = (const InstStat*)c->pinned;
+        bool any = false;
+        for (int k = 0; k < ninst; ++k) {
+            float dv;
+            memcpy(&dv, &hs[k].dvmax_bits, 4);
+            double v2 = 0;
+            for (int i = 0; i < STAT_SLOTS; ++i) v2 += hs[k].v2_part[i];
+            const double cnt = (double)std::max<i64>(c->poff_h[k + 1] - c->poff_h[k], 1);
+            const bool fail_k = (double)dv > c->prm.eps_v * std::sqrt(v2 / cnt);
+            redo[k] = (fail_k && reruns[k] < c->prm.max_reruns) ? 1 : 0;
+            if (redo[k]) { ++reruns[k]; any = true; }
+        }
+        if (!any) return SHSPH_OK;
+        TRY(upload_extra(c, c->redo_d.p, redo.data(), ninst));
+        launch_velu_from_out<T>(o, n, P<i64>(c->poff_d), ninst, P<InstDev>(c->inst_d),
+                                P<u8>(c->redo_d), P<vec4<T>>(c->velu), st);
+        launch_thermo<T>(P<vec4<T>>(c->posh), P<vec4<T>>(c->velu), P<T>(c->omega), n,
+                         P<i64>(c->poff_d), ninst, P<InstDev>(c->inst_d), c->prm.hfact,
+                         c->prm.gamma, c->prm.alpha_av, alpha_s, P<vec4<T>>(c->thermo), st);
+        launch_stat_reset(P<InstStat>(c->stat_d), ninst, 2, nullptr, st);
+        const SphParams sp = sph_params(c->prm);
+        prof_begin(c, S_FORCE);
+        launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
+                        c->n_groups, P<InstDev>(c->inst_d), sp, cache_view(c), P<vec4<T>>(c->acc),
+                        nullptr, P<InstStat>(c->stat_d), st);
+        prof_end(c);
+        TRY(check_launch(c, "force (corrector re-run)"));
+        prof_begin(c, S_CORRECT);
+        launch_correct<T>(sorted<T>(c, true), P<vec4<T>>(c->acc), P<T>(c->omega), n,
+                          P<i64>(c->poff_d), ninst, P<InstDev>(c->inst_d), dt_dev, c->prm.hfact,
+                          o, P<InstStat>(c->stat_d), P<BlockPart>(c->bpart), st);
+        c->parts_pending = nb;
+        prof_end(c);
+        TRY(check_launch(c, "correct (re-run)"));
+    }
+}
+
+// CFL multiplier (App. G): halved after a step that re-ran its corrector,
+// else relaxed towards 1 as (1 + s lambda) / (1 + s).
+double next_multiplier(const shsph_params& q, double lam, int reruns)
+{
+    if (!(q.eps_v > 0)) return 1.0;
+    return reruns ? 0.5 * lam : (1.0 + q.lambda_stiff * lam) / (1.0 + q.lambda_stiff);
+}
+
 template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, double* dt_used)
 {
     hipStream_t st = c->stream;
@@ -717,7 +799,9 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
     const bool keep_stat = c->stat_d.p && c->ninst == 1;
     TRY(set_single_instance(c, p));
     if (!keep_stat && !(dt > 0)) return fail(c, SHSPH_ESTATE, "no CFL dt available");
-    TRY(upload_extra(c, c->dt_host_d.p, &dt, sizeof(double)));
+    // a CFL step takes the CFL multiplier (encoded as -lambda)
+    const double dt_req = dt > 0 ? dt : -c->lambda_cfl;
+    TRY(upload_extra(c, c->dt_host_d.p, &dt_req, sizeof(double)));
     launch_dt_select(P<double>(c->dt_inst_d), P<InstStat>(c->stat_d), P<double>(c->dt_host_d), 1, st);
     c->n = p->n;
     c->dtype = p->dtype;
@@ -725,10 +809,24 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
     const double* dt_dev = P<double>(c->dt_inst_d);
     TRY(build<T>(c, fields<T>(p), p->n, dt_dev, true));
     c->state = ST_TREE;
-    int rc = run_density<T>(c, true);
-    if (rc != SHSPH_OK) return rc;
     const i64 n = c->n;
     TRY(ensure(c, c->acc, n * sizeof(vec4<T>)));
+    const bool sw = c->prm.alpha_switch && p->alpha;
+    if (sw) {   // alpha^n and a^n into key order for the shock detector
+        const u32* eps = P<u32>(c->vals[c->vals_sel]);
+        TRY(ensure(c, c->alpha_s, n * sizeof(T)));
+        launch_gather1<T>(eps, n, (const T*)p->alpha, P<T>(c->alpha_s), st);
+        launch_gather_velu<T>(eps, n, (const T*)p->ax, (const T*)p->ay, (const T*)p->az,
+                              (const T*)p->dudt, P<vec4<T>>(c->acc), st);
+    }
+    int rc = run_density<T>(c, true);
+    if (rc != SHSPH_OK) return rc;
+    if (sw) {   // alpha^{n+1} from v*, grad v*, grad a^n; alpha c staged for the force
+        launch_alpha<T>(sorted<T>(c, true), P<vec4<T>>(c->acc), P<T>(c->omega), P<u32>(c->id),
+                        group_map(c), c->n_groups, P<InstDev>(c->inst_d), sph_params(c->prm),
+                        cache_view(c), dt_dev, P<T>(c->alpha_s), P<vec4<T>>(c->thermo), st);
+        TRY(check_launch(c, "alpha switch"));
+    }
     launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, 2, nullptr, st);
     c->parts_pending = 0;
     const SphParams sp = sph_params(c->prm);
@@ -754,6 +852,12 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
     c->parts_pending = (n + GROUP - 1) / GROUP;
     prof_end(c);
     TRY(check_launch(c, "correct"));
+    std::vector<int> rr;
+    TRY(corrector_reruns<T>(c, o, dt_dev, rr, sw ? P<T>(c->alpha_s) : nullptr));
+    c->reruns_last = rr.empty() ? 0 : rr[0];
+    if (sw)   // alpha^{n+1} back to the caller, in the new key order like every field
+        HIPTRY(c, hipMemcpyAsync(p->alpha, c->alpha_s.p, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    c->lambda_cfl = next_multiplier(c->prm, c->lambda_cfl, c->reruns_last);
     if (dt_used) {
         TRY(read_back(c, dt_dev, sizeof(double)));
         *dt_used = *(double*)c->pinned;
@@ -935,9 +1039,14 @@ template <class T> int batch_pass(shsph_ctx* c, const std::vector<Inst*>& b, con
                       ninst, P<InstDev>(c->inst_d), dt_dev, c->prm.hfact, pool_out<T>(c),
                       P<InstStat>(c->stat_d), P<BlockPart>(c->bpart), st);
     prof_end(c);
-    launch_fold_parts(P<BlockPart>(c->bpart), nb, ninst, P<InstStat>(c->stat_d), st);
-    c->parts_pending = 0;
+    c->parts_pending = nb;
     TRY(check_launch(c, "correct"));
+    std::vector<int> rr;
+    TRY(corrector_reruns<T>(c, pool_out<T>(c), dt_dev, rr));
+    if (c->parts_pending > 0) {
+        launch_fold_parts(P<BlockPart>(c->bpart), c->parts_pending, ninst, P<InstStat>(c->stat_d), st);
+        c->parts_pending = 0;
+    }
     TRY(read_back(c, c->stat_d.p, ninst * sizeof(InstStat)));
     prof_collect(c);
     const InstStat* hs = (const InstStat*)c->pinned;
@@ -947,6 +1056,11 @@ template <class T> int batch_pass(shsph_ctx* c, const std::vector<Inst*>& b, con
         // converge either
         b[k]->stat.n_noconv += hs[k].n_exceed;
         b[k]->has_force = true;
+        // an evaluation pass (dt 0) is not a step: the multiplier stays
+        if (dt[k] > 0) {
+            b[k]->reruns = rr[k];
+            b[k]->lambda_cfl = next_multiplier(c->prm, b[k]->lambda_cfl, rr[k]);
+        }
     }
     return rc;
 }
@@ -963,6 +1077,9 @@ double inst_dt_cfl(const Inst& in)
     memcpy(&f, &in.stat.dt_bits, 4);
     return (double)f;
 }
+
+// dt of an instance's next CFL step: the CFL dt times its multiplier.
+double inst_dt_step(const Inst& in) { return in.lambda_cfl * inst_dt_cfl(in); }
 
 // Resolve handles and the dt of each instance for a stepping pass; CFL
 // instances without a derivative pass get one first (dt = 0).
@@ -1008,7 +1125,7 @@ int shsph_internal_inst_state(shsph_ctx* c, int64_t h, int64_t* n, int* has_forc
     if (!in) return SHSPH_EINVAL;
     if (n) *n = in->n;
     if (has_force) *has_force = in->has_force ? 1 : 0;
-    if (dt_cfl) *dt_cfl = inst_dt_cfl(*in);
+    if (dt_cfl) *dt_cfl = inst_dt_step(*in);
     in->busy += busy_delta;
     return SHSPH_OK;
 }
@@ -1038,6 +1155,43 @@ void shsph_params_default(shsph_params* p)
     p->spread_slots = 8192;
     p->stage1_serial = 0;
     p->stage2_mode = 1;
+    p->kernel = SHSPH_KERNEL_M4;
+    p->key_bits = 63;
+    p->eps_v = 0.0;
+    p->max_reruns = 3;
+    p->alpha_switch = 0;
+    p->lambda_stiff = 1.0;
+    p->alpha_min = 0.0;
+    p->alpha_max = 1.0;
+    p->sigma_decay = 0.1;
+}
+
+// Every device buffer of a context.
+static std::vector<Buf*> all_bufs(shsph_ctx* c)
+{
+    return { &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->hist,
+             &c->scan_tmp, &c->bbox, &c->posh, &c->velu, &c->vhalf, &c->hn, &c->hcache,
+             &c->pid_s, &c->thermo, &c->omega, &c->acc, &c->vsig, &c->status, &c->xi[0],
+             &c->xi[1], &c->xscan, &c->id, &c->mu_leaf, &c->lchild, &c->rchild, &c->endrange,
+             &c->lflag, &c->rflag, &c->child, &c->parent, &c->arrive, &c->blo, &c->bhi,
+             &c->rec, &c->nrec, &c->rscan, &c->glo, &c->ghi, &c->uleaf, &c->uslot,
+             &c->ucnt, &c->ustot, &c->nlist, &c->ncnt, &c->flags, &c->inst_d, &c->poff_d,
+             &c->goff_d, &c->leaf_off_d, &c->ioff_d, &c->root_d, &c->stat_d,
+             &c->dt_inst_d, &c->dt_host_d, &c->pbox, &c->plen, &c->xoff, &c->xlist,
+             &c->bpart, &c->work[0], &c->work[1], &c->work[2], &c->redo_d, &c->rhmax_d,
+             &c->alpha_s };
+}
+
+// Parameter ranges accepted by shsph_create and shsph_set_params.
+static bool params_valid(const shsph_params& q)
+{
+    return (q.hfact > 0) && (q.chi >= 1) && (q.lambda > 1) && (q.eps_h > 0) &&
+           !(q.max_iter < 1 || q.n_red > 20 || q.max_restarts < 0 ||
+             q.spread_slots < 1 || q.stage2_mode < 0 || q.stage2_mode > 2 ||
+             q.kernel < 0 || q.kernel >= KERNEL_COUNT ||
+             (q.key_bits != 63 && q.key_bits != 30) || !(q.eps_v >= 0) ||
+             q.max_reruns < 0 || !(q.lambda_stiff >= 0) || !(q.sigma_decay > 0) ||
+             !(q.alpha_min >= 0) || !(q.alpha_max >= q.alpha_min));
 }
 
 int shsph_create(int device, const shsph_params* p, shsph_ctx** out)
@@ -1049,13 +1203,18 @@ int shsph_create(int device, const shsph_params* p, shsph_ctx** out)
     shsph_ctx* c = new shsph_ctx();
     c->device = device;
     if (p) c->prm = *p; else shsph_params_default(&c->prm);
-    if (!(c->prm.hfact > 0) || !(c->prm.chi >= 1) || !(c->prm.lambda > 1) || !(c->prm.eps_h > 0) ||
-        c->prm.max_iter < 1 || c->prm.n_red > 20 || c->prm.max_restarts < 0 ||
-        c->prm.spread_slots < 1 || c->prm.stage2_mode < 0 || c->prm.stage2_mode > 2) {
+    if (!params_valid(c->prm)) {
         delete c;
         return SHSPH_EINVAL;
     }
+
     if (hipSetDevice(device) != hipSuccess || hipHostMalloc(&c->pinned, PINNED_BYTES + UPLOAD_BYTES) != hipSuccess) {
+        delete c;
+        return SHSPH_EHIP;
+    }
+    if (hipEventCreateWithFlags(&c->up_done, hipEventDisableTiming) != hipSuccess) {
+        if (c->up_done) hipEventDestroy(c->up_done);
+        hipHostFree(c->pinned);
         delete c;
         return SHSPH_EHIP;
     }
@@ -1072,21 +1231,30 @@ int shsph_destroy(shsph_ctx* c)
     hipStreamSynchronize(c->stream);
     pool_release(c);
     if (c->up_done) hipEventDestroy(c->up_done);
-    Buf* all[] = { &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->hist,
-                   &c->scan_tmp, &c->bbox, &c->posh, &c->velu, &c->vhalf, &c->hn, &c->hcache,
-                   &c->pid_s, &c->thermo, &c->omega, &c->acc, &c->vsig, &c->status, &c->xi[0],
-                   &c->xi[1], &c->xscan, &c->id, &c->mu_leaf, &c->lchild, &c->rchild, &c->endrange,
-                   &c->lflag, &c->rflag, &c->child, &c->parent, &c->arrive, &c->blo, &c->bhi,
-                   &c->rec, &c->nrec, &c->rscan, &c->glo, &c->ghi, &c->uleaf, &c->uslot,
-                   &c->ucnt, &c->ustot, &c->nlist, &c->ncnt, &c->flags, &c->inst_d, &c->poff_d,
-                   &c->goff_d, &c->leaf_off_d, &c->ioff_d, &c->root_d, &c->stat_d,
-                   &c->dt_inst_d, &c->dt_host_d, &c->pbox, &c->plen, &c->xoff, &c->xlist,
-                   &c->bpart, &c->work[0], &c->work[1], &c->work[2], &c->redo_d, &c->rhmax_d };
-    for (Buf* b : all)
+    for (Buf* b : all_bufs(c))
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);
     for (hipEvent_t e : c->prof.ev) hipEventDestroy(e);
     delete c;
+    return SHSPH_OK;
+}
+
+int shsph_set_params(shsph_ctx* c, const shsph_params* p)
+{
+    if (!c || !p) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->err.clear();
+    if (c->server) return fail(c, SHSPH_ESTATE, "parameters cannot change while serving");
+    if (!params_valid(*p)) return fail(c, SHSPH_EINVAL, "parameter out of range");
+    c->prm = *p;
+    return SHSPH_OK;
+}
+
+int shsph_get_params(shsph_ctx* c, shsph_params* out)
+{
+    if (!c || !out) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    *out = c->prm;
     return SHSPH_OK;
 }
 
@@ -1201,6 +1369,8 @@ int shsph_get_info(shsph_ctx* c, shsph_info* o)
     o->n_groups = c->n_groups;
     o->n_red = c->prm.n_red;
     o->restarts = c->restarts;
+    o->reruns = c->reruns_last;
+    o->cfl_multiplier = c->lambda_cfl;
     HIPTRY(c, hipSetDevice(c->device));
     if (c->state >= ST_TREE) {
         u64 t1 = 0, t2 = 0;
@@ -1437,6 +1607,8 @@ int shsph_instance_info(shsph_ctx* c, int64_t handle, shsph_info* o)
     for (int i = 0; i < STAT_SLOTS; ++i) { o->dv2_sum += s.dv2_part[i]; o->v2_sum += s.v2_part[i]; }
     o->max_iter_seen = (int32_t)s.max_iter_seen;
     o->n_noconv = (int32_t)s.n_noconv;
+    o->reruns = in->reruns;
+    o->cfl_multiplier = in->lambda_cfl;
     return SHSPH_OK;
 }
 
@@ -1462,7 +1634,7 @@ int shsph_step_batch(shsph_ctx* c, const int64_t* handles, int32_t count, const 
     }
     std::vector<double> d(count);
     for (int k = 0; k < count; ++k) {
-        d[k] = (dt && dt[k] > 0) ? dt[k] : inst_dt_cfl(*b[k]);
+        d[k] = (dt && dt[k] > 0) ? dt[k] : inst_dt_step(*b[k]);
         if (!(d[k] > 0) || !std::isfinite(d[k]))
             return fail(c, SHSPH_ESTATE, "no finite CFL dt for instance " + std::to_string(handles[k]));
     }

@@ -253,6 +253,113 @@ template <class T> __device__ inline T m4_df(T q)
 
 template <class T> __device__ inline T inv_pi() { return T(0.318309886183790671537767526745); }
 
+// ------------------------------------------------- kernel family (Sect. 2.1.1) --
+// f(q) and f'(q) of the B-splines M4, M5, M6 and the Wendland functions C2,
+// C4, C6, with support radius R (in units of h) and 3-D normalisation C:
+//   M4  R 2    C 1/pi       (the spline above)
+//   M5  R 5/2  C 1/(20 pi)  f = t1^4 - 5 t2^4 + 10 t3^4, t_i = max(5/2, 3/2, 1/2 - q, 0)
+//   M6  R 3    C 1/(120 pi) f = t1^5 - 6 t2^5 + 15 t3^5, t_i = max(3, 2, 1 - q, 0)
+//   C2  R 2    C 21/(16 pi)   f = t^4 (1 + 2q),                 t = max(1 - q/2, 0)
+//   C4  R 2    C 495/(256 pi) f = t^6 (1 + 3q + 35/12 q^2)
+//   C6  R 2    C 1365/(512 pi) f = t^8 (1 + 4q + 25/4 q^2 + 4q^3)
+// Every piece is clamped at its own breakpoint, so no branch remains.  The
+// Wendland derivatives are the simplified products
+//   C2: -5 q t^3,  C4: -14/3 q (1 + 5/2 q) t^5,  C6: -11/2 q (1 + 7/2 q + 4 q^2) t^7.
+enum KernelId { KM4 = 0, KM5 = 1, KM6 = 2, KC2 = 3, KC4 = 4, KC6 = 5, KERNEL_COUNT = 6 };
+
+inline double kernel_support(int k) { return k == KM5 ? 2.5 : (k == KM6 ? 3.0 : 2.0); }
+
+template <int K> struct Kern;
+
+template <> struct Kern<KM4> {
+    template <class T> __device__ static T R() { return T(2); }
+    template <class T> __device__ static T C() { return inv_pi<T>(); }
+    template <class T> __device__ static void fdf(T q, T& f, T& df) { m4<T>(q, f, df); }
+    template <class T> __device__ static T df(T q) { return m4_df<T>(q); }
+};
+
+template <> struct Kern<KM5> {
+    template <class T> __device__ static T R() { return T(2.5); }
+    template <class T> __device__ static T C() { return T(0.05) * inv_pi<T>(); }
+    template <class T> __device__ static void fdf(T q, T& f, T& d)
+    {
+        const T a = fmax(T(2.5) - q, T(0)), b = fmax(T(1.5) - q, T(0)), c = fmax(T(0.5) - q, T(0));
+        const T a3 = a * a * a, b3 = b * b * b, c3 = c * c * c;
+        f = a3 * a - T(5) * b3 * b + T(10) * c3 * c;
+        d = T(-4) * a3 + T(20) * b3 - T(40) * c3;
+    }
+    template <class T> __device__ static T df(T q)
+    {
+        const T a = fmax(T(2.5) - q, T(0)), b = fmax(T(1.5) - q, T(0)), c = fmax(T(0.5) - q, T(0));
+        return T(-4) * a * a * a + T(20) * b * b * b - T(40) * c * c * c;
+    }
+};
+
+template <> struct Kern<KM6> {
+    template <class T> __device__ static T R() { return T(3); }
+    template <class T> __device__ static T C() { return inv_pi<T>() / T(120); }
+    template <class T> __device__ static void fdf(T q, T& f, T& d)
+    {
+        const T a = fmax(T(3) - q, T(0)), b = fmax(T(2) - q, T(0)), c = fmax(T(1) - q, T(0));
+        const T a4 = (a * a) * (a * a), b4 = (b * b) * (b * b), c4 = (c * c) * (c * c);
+        f = a4 * a - T(6) * b4 * b + T(15) * c4 * c;
+        d = T(-5) * a4 + T(30) * b4 - T(75) * c4;
+    }
+    template <class T> __device__ static T df(T q)
+    {
+        const T a = fmax(T(3) - q, T(0)), b = fmax(T(2) - q, T(0)), c = fmax(T(1) - q, T(0));
+        return T(-5) * (a * a) * (a * a) + T(30) * (b * b) * (b * b) - T(75) * (c * c) * (c * c);
+    }
+};
+
+template <> struct Kern<KC2> {
+    template <class T> __device__ static T R() { return T(2); }
+    template <class T> __device__ static T C() { return T(21.0 / 16.0) * inv_pi<T>(); }
+    template <class T> __device__ static void fdf(T q, T& f, T& d)
+    {
+        const T t = fmax(T(1) - T(0.5) * q, T(0)), t3 = t * t * t;
+        f = t3 * t * (T(1) + T(2) * q);
+        d = T(-5) * q * t3;
+    }
+    template <class T> __device__ static T df(T q)
+    {
+        const T t = fmax(T(1) - T(0.5) * q, T(0));
+        return T(-5) * q * t * t * t;
+    }
+};
+
+template <> struct Kern<KC4> {
+    template <class T> __device__ static T R() { return T(2); }
+    template <class T> __device__ static T C() { return T(495.0 / 256.0) * inv_pi<T>(); }
+    template <class T> __device__ static void fdf(T q, T& f, T& d)
+    {
+        const T t = fmax(T(1) - T(0.5) * q, T(0)), t2 = t * t, t5 = t2 * t2 * t;
+        f = t5 * t * (T(1) + q * (T(3) + T(35.0 / 12.0) * q));
+        d = T(-14.0 / 3.0) * q * (T(1) + T(2.5) * q) * t5;
+    }
+    template <class T> __device__ static T df(T q)
+    {
+        const T t = fmax(T(1) - T(0.5) * q, T(0)), t2 = t * t;
+        return T(-14.0 / 3.0) * q * (T(1) + T(2.5) * q) * (t2 * t2 * t);
+    }
+};
+
+template <> struct Kern<KC6> {
+    template <class T> __device__ static T R() { return T(2); }
+    template <class T> __device__ static T C() { return T(1365.0 / 512.0) * inv_pi<T>(); }
+    template <class T> __device__ static void fdf(T q, T& f, T& d)
+    {
+        const T t = fmax(T(1) - T(0.5) * q, T(0)), t2 = t * t, t4 = t2 * t2, t7 = t4 * t2 * t;
+        f = t7 * t * (T(1) + q * (T(4) + q * (T(6.25) + T(4) * q)));
+        d = T(-5.5) * q * (T(1) + q * (T(3.5) + T(4) * q)) * t7;
+    }
+    template <class T> __device__ static T df(T q)
+    {
+        const T t = fmax(T(1) - T(0.5) * q, T(0)), t2 = t * t, t4 = t2 * t2;
+        return T(-5.5) * q * (T(1) + q * (T(3.5) + T(4) * q)) * (t4 * t2 * t);
+    }
+};
+
 // Reciprocal, reciprocal square root and square root for the derivative
 // sums: the hardware instructions (about 1 ulp) in FP32, IEEE operations in
 // FP64.  The neighbour decision never uses them.

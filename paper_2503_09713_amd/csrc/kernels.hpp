@@ -65,6 +65,8 @@ struct BlockPart {
 struct SphParams {
     double hfact, gamma, alpha, beta, beta_u, chi, lambda, eps_h, c_cour, c_force, r_kern;
     int max_iter;
+    int kernel;             // KernelId (Sect. 2.1.1)
+    double alpha_min, alpha_max, sigma_decay;   // shock-detection switch (App. G)
 };
 
 // scan.hip
@@ -158,9 +160,18 @@ template <class T>
 void launch_gather_velu(const u32* eps, i64 n, const T* vx, const T* vy, const T* vz, const T* u,
                         vec4<T>* velu, hipStream_t st);
 template <class T>
+void launch_alpha(const SortedPtrs<T>& s, const vec4<T>* acc_n, const T* omega, const u32* id,
+                  const GroupMap& gm, i64 ngroups, const InstDev* inst, const SphParams& P,
+                  const CacheView& cv, const double* dt_inst, T* alpha, vec4<T>* thermo,
+                  hipStream_t st);
+template <class T> void launch_gather1(const u32* eps, i64 n, const T* src, T* dst, hipStream_t st);
+template <class T>
+void launch_velu_from_out(const OutPtrs<T>& o, i64 n, const i64* p_off, int ninst,
+                          const InstDev* inst, const u8* redo, vec4<T>* velu, hipStream_t st);
+template <class T>
 void launch_thermo(const vec4<T>* posh, const vec4<T>* velu, const T* omega, i64 n,
                    const i64* p_off, int ninst, const InstDev* inst, double hfact, double gamma,
-                   vec4<T>* thermo, hipStream_t st);
+                   double alpha, const T* alpha_s, vec4<T>* thermo, hipStream_t st);
 template <class T>
 void launch_scatter(const u32* eps, i64 n, const vec4<T>* src4, int comp, const T* src1,
                     T* dst, hipStream_t st);

@@ -55,12 +55,16 @@ __global__ void k_root_hmax(const vec4<T>* __restrict__ blo, const u32* __restri
 
 // dt for the coming step: the caller's value when positive, else the CFL dt
 // left by the previous force evaluation.
+// dt of each instance: dt_host > 0 is a fixed dt; otherwise the CFL dt of
+// the last force evaluation, times -dt_host when dt_host < 0 (the CFL
+// multiplier of App. G; 0 means a multiplier of 1).
 __global__ void k_dt_select(double* dt_inst, const InstStat* s, const double* dt_host, int ninst)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ninst) return;
     const double h = dt_host[k];
-    dt_inst[k] = (h > 0.0) ? h : (double)__uint_as_float(s[k].dt_bits);
+    const double lam = h < 0.0 ? -h : 1.0;
+    dt_inst[k] = (h > 0.0) ? h : lam * (double)__uint_as_float(s[k].dt_bits);
 }
 
 template <class T> __global__ void k_copy_h(const vec4<T>* __restrict__ posh, T* __restrict__ hc, i64 n)
@@ -170,7 +174,7 @@ __device__ inline void atomic_min_if(u32* p, u32 v)
 // One workgroup per group: the union's positions are staged in LDS once and
 // every Newton pass reads neighbours from there.
 // ---------------------------------------------------------------------------
-template <class T, int CH>
+template <class T, int CH, int K>
 __global__ void __launch_bounds__(GROUP)
 k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restrict__ hc,
           const vec4<T>* __restrict__ velu, const u32* __restrict__ id, const GroupMap gm,
@@ -212,17 +216,18 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
     u32 inrange = 0;                     // of them within 2h (profiling)
     const bool wrap = !group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
                                          ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx);
+    const T RK = Kern<K>::template R<T>(), CK = Kern<K>::template C<T>();
     for (int it = 0; it < P.max_iter; ++it) {
         const T hinv = T(1) / h;
-        const T h2x4 = T(4) * h * h;
+        const T hR2 = RK * RK * h * h;
         T s = T(0), dq = T(0);          // sum f, sum -q f' (>= 0: f is non-increasing)
         if (active) evals += cnt;
         auto add_r2 = [&](T r2) {
-            if (r2 < h2x4) {
+            if (r2 < hR2) {
                 ++inrange;
                 const T q = fast_sqrt(r2) * hinv;
                 T f, df;
-                m4<T>(q, f, df);
+                Kern<K>::template fdf<T>(q, f, df);
                 s += f;
                 dq -= q * df;
             }
@@ -260,8 +265,8 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
         }
         if (active) {
             const T hinv3 = hinv * hinv * hinv;
-            const T rho_sum = m * s * hinv3 * inv_pi<T>();
-            const T mh4 = m * hinv3 * hinv * inv_pi<T>();
+            const T rho_sum = m * s * hinv3 * CK;
+            const T mh4 = m * hinv3 * hinv * CK;
             const T dsum_h = mh4 * (dq - T(3) * s);      // sum_b m dW/dh
             const T hf = hfact * hinv;
             const T rho_h = m * hf * hf * hf;
@@ -314,7 +319,7 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
         const T Pr = gm1 * rho * u;
         const T cs = sqrt((T)P.gamma * gm1 * u);
         const T B = T(1) / (rho * om);
-        thermo[a] = mk4<T>(Pr * B / rho, B, cs, Pr);
+        thermo[a] = mk4<T>(Pr * B / rho, B, (T)P.alpha * cs, Pr);
     }
 }
 
@@ -323,7 +328,8 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
 //   dv_a/dt = -sum_b m [(P_a+q^a)/(rho_a^2 Om_a) F_a + (P_b+q^b)/(rho_b^2 Om_b) F_b] rhat_ab
 //   du_a/dt =  sum_b m (P_a+q^a)/(rho_a^2 Om_a) (v_ab . rhat_ab) F_a + Lambda_cond
 // F_x = f'(r/h_x)/(pi h_x^4) (= rhat . grad W), q^x = -rho_x vsig_x w / 2 for
-// w = v_ab . rhat_ab < 0, vsig_x = alpha c_x + beta |w|.  With
+// w = v_ab . rhat_ab < 0, vsig_x = alpha_x c_x + beta |w| (alpha_x c_x staged
+// per particle: the constant alpha, or the shock detector's alpha_x).  With
 // A = P/(rho^2 Om) and B = 1/(rho Om): (P+q)/(rho^2 Om) = A - vsig w B / 2.
 // Conductivity: m beta_u vsig_u (u_a-u_b) (F_a B_a + F_b B_b)/2 with
 // vsig_u = sqrt(|P_a - P_b| / ((rho_a+rho_b)/2)).
@@ -334,7 +340,7 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
 // ---------------------------------------------------------------------------
 constexpr int FT = 2 * GROUP;   // force: two threads per particle, each half of its list
 
-template <class T, int CH>
+template <class T, int CH, int K>
 __global__ void __launch_bounds__(FT)
 k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         const vec4<T>* __restrict__ thermo, const u32* __restrict__ id, const GroupMap gm,
@@ -359,14 +365,16 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     const bool live = a < end;
     const i64 ai = live ? a : beg;
     const T m = (T)in.mass, hfact = (T)P.hfact;
-    const T alpha = (T)P.alpha, beta = (T)P.beta, beta_u = (T)P.beta_u;
+    const T beta = (T)P.beta, beta_u = (T)P.beta_u;
     const vec4<T> pa = posh[ai], va = velu[ai], ta = thermo[ai];
     const T ha = pa.w, hia = T(1) / ha;
-    const T hia4 = hia * hia * hia * hia * inv_pi<T>();
+    const T RK = Kern<K>::template R<T>(), CK = Kern<K>::template C<T>();
+    const T hia4 = hia * hia * hia * hia * CK;
     const T hfa = hfact * hia;
     const T rhoa = m * hfa * hfa * hfa;
     const T mhf3 = m * hfact * hfact * hfact;    // rho_b = mhf3 / h_b^3
-    const T Aa = ta.x, Ba = ta.y, ca = ta.z, Pa = ta.w;
+    const T Aa = ta.x, Ba = ta.y, aca = ta.z, Pa = ta.w;     // aca = alpha_a c_a
+    const T ca = sqrt((T)P.gamma * ((T)P.gamma - T(1)) * va.w);   // c_a: floor of the signal speed
     const u32 cnt = live ? cv.ncnt[a] : 0u;
     const u32 nu = min((u32)cv.cap, cv.ucnt[g]);
     const u32 S = cv.ustot[g];
@@ -393,18 +401,18 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         const T r2 = dx * dx + dy * dy + dz * dz;
         const T hib = pb.w;
         const T hmi = hia < hib ? hia : hib;
-        if (!(r2 > T(0)) || !(r2 * hmi * hmi < T(4))) return;
+        if (!(r2 > T(0)) || !(r2 * hmi * hmi < RK * RK)) return;
         ++inter;
         const vec4<T> vb = s_vel[sl], tb = s_thm[sl];
         const T rinv = fast_rsq(r2), r = r2 * rinv;
         const T ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
         const T w = (va.x - vb.x) * ex + (va.y - vb.y) * ey + (va.z - vb.z) * ez;
-        const T Fa = m4_df<T>(r * hia) * hia4;
+        const T Fa = Kern<K>::template df<T>(r * hia) * hia4;
         const T hib3 = hib * hib * hib;           // shared by F_b and rho_b
-        const T Fb = m4_df<T>(r * hib) * (hib3 * hib * inv_pi<T>());
+        const T Fb = Kern<K>::template df<T>(r * hib) * (hib3 * hib * CK);
         const T aw = fabs(w);
-        const T vsa = alpha * ca + beta * aw;
-        const T vsb = alpha * tb.z + beta * aw;
+        const T vsa = aca + beta * aw;
+        const T vsb = tb.z + beta * aw;
         const T wn = w < T(0) ? w : T(0);
         const T ka = (Aa - T(0.5) * vsa * wn * Ba) * Fa;
         const T kb = (tb.x - T(0.5) * vsb * wn * tb.y) * Fb;
@@ -484,6 +492,137 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     } else if (live && !half) {
         atomic_min_if(&stat[k].dt_bits, __float_as_uint(dta));
     }
+}
+
+// ---------------------------------------------------------------------------
+// Shock detector and viscosity switch (App. G, Shock detection), after the
+// density pass of a step, before the force:
+//   grad v* and grad a^n by the SPH estimate
+//     (d_j f_i)_a = -m/(rho_a Omega_a) sum_b (f_a - f_b)_i rhat_j F_ab(h_a),
+//   div v, curl v, d(div v)/dt = div a - sum_ij (d_j v_i)(d_i v_j),
+//   xi = (div v)^2 / ((div v)^2 + |curl v|^2), A = xi max(-d(div v)/dt, 0),
+//   alpha_loc = max(alpha_min, alpha_max 10 h^2 A / (10 h^2 A + c^2)),
+//   tau = h / (sigma_decay c), and the implicit update
+//   alpha^{n+1} = max((alpha^n + alpha_loc dt/tau) / (1 + dt/tau), alpha_loc).
+// alpha (key order) is updated in place and alpha c staged in thermo.z for
+// the force.  One workgroup per group, the union's positions, v* and a^n
+// staged in LDS.
+// ---------------------------------------------------------------------------
+template <class T, int CH, int K>
+__global__ void __launch_bounds__(GROUP)
+k_alpha(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
+        const vec4<T>* __restrict__ acc_n, const T* __restrict__ omega,
+        const u32* __restrict__ id, const GroupMap gm, const InstDev* __restrict__ inst,
+        SphParams P, CacheView cv, const double* __restrict__ dt_inst, T* __restrict__ alpha,
+        vec4<T>* __restrict__ thermo)
+{
+    __shared__ vec4<T> s_pos[CH];
+    __shared__ vec4<T> s_vel[CH];
+    __shared__ vec4<T> s_acc[CH];
+    const i64 g = blockIdx.x;
+    i64 beg, end;
+    int k;
+    gm.range(g, beg, end, k);
+    const InstDev in = inst[k];
+    const Box<T> bx = make_box<T>(in);
+    const i64 a = beg + threadIdx.x;
+    const bool live = a < end;
+    const i64 ai = live ? a : beg;
+    const vec4<T> pa = posh[ai], va = velu[ai], aa = acc_n[ai];
+    const T RK = Kern<K>::template R<T>(), CK = Kern<K>::template C<T>();
+    const T ha = pa.w, hia = T(1) / ha;
+    const T hia4 = hia * hia * hia * hia * CK;
+    const u32 cnt = live ? cv.ncnt[a] : 0u;
+    const u32 nu = min((u32)cv.cap, cv.ucnt[g]);
+    const u32 S = cv.ustot[g];
+    const u32 nch = (S + CH - 1) / CH;
+    const u32* ul = cv.uleaf + g * cv.cap;
+    const u32* us = cv.uslot + g * cv.cap;
+    const u64* my = cv.nlist + (u64)g * cv.capq * GROUP + threadIdx.x;
+    const vec4<T>* src[3] = { posh, velu, acc_n };
+    vec4<T>* dst[3] = { s_pos, s_vel, s_acc };
+    T gv[9], ga[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) { gv[t] = T(0); ga[t] = T(0); }
+    const bool wrap = !group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
+                                         ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx);
+    auto pair_d = [&](u32 sl, T dx, T dy, T dz) {
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        if (!(r2 > T(0)) || !(r2 * hia * hia < RK * RK)) return;
+        const T rinv = fast_rsq(r2);
+        const T Fr = Kern<K>::template df<T>(r2 * rinv * hia) * hia4 * rinv;   // F / r
+        const T ex = dx * Fr, ey = dy * Fr, ez = dz * Fr;                    // rhat F
+        const vec4<T> vb = s_vel[sl], ab = s_acc[sl];
+        const T d[3] = { va.x - vb.x, va.y - vb.y, va.z - vb.z };
+        const T e[3] = { aa.x - ab.x, aa.y - ab.y, aa.z - ab.z };
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            gv[3 * i + 0] += d[i] * ex; gv[3 * i + 1] += d[i] * ey; gv[3 * i + 2] += d[i] * ez;
+            ga[3 * i + 0] += e[i] * ex; ga[3 * i + 1] += e[i] * ey; ga[3 * i + 2] += e[i] * ez;
+        }
+    };
+    auto pair = [&](u32 sl) {
+        const vec4<T> pb = s_pos[sl];
+        pair_d(sl, min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic),
+               min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic),
+               min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic));
+    };
+    auto pair_in = [&](u32 sl) {
+        const vec4<T> pb = s_pos[sl];
+        pair_d(sl, pa.x - pb.x, pa.y - pb.y, pa.z - pb.z);
+    };
+    if (nch == 1) {
+        stage_union<T, 3>(src, dst, id, ul, us, nu, 0u, S);
+        __syncthreads();
+        if (live) {
+            if (wrap) entries_each(my, cnt, pair);
+            else entries_each(my, cnt, pair_in);
+        }
+    } else {
+        u32 j = 0;
+        for (u32 ch = 0; ch < nch; ++ch) {
+            const u32 c0 = ch * CH, c1 = min(S, c0 + CH);
+            __syncthreads();
+            stage_union<T, 3>(src, dst, id, ul, us, nu, c0, c1);
+            __syncthreads();
+            if (live) entries_tile(my, cnt, j, c0, c1, pair);
+        }
+    }
+    if (!live) return;
+    const T m = (T)in.mass;
+    const T hf = (T)P.hfact * hia;
+    const T rho = m * hf * hf * hf;
+    const T sc = -m / (rho * omega[a]);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) { gv[t] *= sc; ga[t] *= sc; }
+    const T divv = gv[0] + gv[4] + gv[8];
+    const T diva = ga[0] + ga[4] + ga[8];
+    const T cx = gv[7] - gv[5], cy = gv[2] - gv[6], cz = gv[3] - gv[1];
+    T vv = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) vv += gv[3 * i + j] * gv[3 * j + i];
+    const T ddiv = diva - vv;
+    const T d2 = divv * divv, c2 = cx * cx + cy * cy + cz * cz;
+    const T xi = (d2 + c2 > T(0)) ? d2 / (d2 + c2) : T(0);
+    const T Ash = xi * (ddiv < T(0) ? -ddiv : T(0));
+    const T gam = (T)P.gamma;
+    const T cs = sqrt(gam * (gam - T(1)) * va.w);
+    const T hh = T(10) * ha * ha * Ash;
+    T aloc = (hh + cs * cs > T(0)) ? (T)P.alpha_max * hh / (hh + cs * cs) : T(0);
+    aloc = aloc < (T)P.alpha_min ? (T)P.alpha_min : aloc;
+    const T an = alpha[a];
+    T al;
+    if (cs > T(0)) {
+        const T x = (T)dt_inst[k] * (T)P.sigma_decay * cs * hia;     // dt / tau
+        al = (an + aloc * x) / (T(1) + x);
+        al = al < aloc ? aloc : al;
+    } else {
+        al = an > aloc ? an : aloc;
+    }
+    alpha[a] = al;
+    thermo[a].z = al * cs;
 }
 
 // ---------------------------------------------------------------------------
@@ -588,7 +727,7 @@ template <class T>
 __global__ void k_thermo(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
                          const T* __restrict__ omega, i64 n, const i64* __restrict__ p_off,
                          int ninst, const InstDev* __restrict__ inst, double hfact, double gamma,
-                         vec4<T>* __restrict__ thermo)
+                         double alpha, const T* __restrict__ alpha_s, vec4<T>* __restrict__ thermo)
 {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -598,7 +737,24 @@ __global__ void k_thermo(const vec4<T>* __restrict__ posh, const vec4<T>* __rest
     const T om = omega[i], u = velu[i].w, g = (T)gamma;
     const T Pr = (g - T(1)) * rho * u;
     const T B = T(1) / (rho * om);
-    thermo[i] = mk4<T>(Pr * B / rho, B, sqrt(g * (g - T(1)) * u), Pr);
+    const T al = alpha_s ? alpha_s[i] : (T)alpha;
+    thermo[i] = mk4<T>(Pr * B / rho, B, al * sqrt(g * (g - T(1)) * u), Pr);
+}
+
+// Corrector re-run (App. G.1): v* <- v^{n+1}, u* <- u^{n+1} for the particles
+// of the instances flagged in `redo`, read back from the step's outputs
+// (key order, at i + shift).
+template <class T>
+__global__ void k_velu_from_out(OutPtrs<T> o, i64 n, const i64* __restrict__ p_off, int ninst,
+                                const InstDev* __restrict__ inst, const u8* __restrict__ redo,
+                                vec4<T>* __restrict__ velu)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = find_seg(p_off, ninst, i);
+    if (!redo[k]) return;
+    const i64 c = i + inst[k].shift;
+    velu[i] = mk4<T>(o.vx[c], o.vy[c], o.vz[c], o.u[c]);
 }
 
 // Gather v, u into key order for a derivative evaluation outside a step.
@@ -677,20 +833,48 @@ template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStre
 constexpr int DENS_CH_F = 2048, DENS_CH_D = 1024;
 constexpr int FORCE_CH_F = 1280, FORCE_CH_D = 640;
 
+template <class T, int K>
+void launch_density_k(const SortedPtrs<T>& s, const u32* id, const GroupMap& gm, i64 ngroups,
+                      const InstDev* inst, const SphParams& P, const CacheView& cv, T* omega,
+                      vec4<T>* thermo, u8* status, InstStat* stat, const u8* redo, hipStream_t st)
+{
+    if (sizeof(T) == 4)
+        hipLaunchKernelGGL((k_density<T, DENS_CH_F, K>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
+                           s.posh, s.hn, s.hcache, s.velu, id, gm, inst, P, cv, omega, thermo,
+                           status, stat, redo);
+    else
+        hipLaunchKernelGGL((k_density<T, DENS_CH_D, K>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
+                           s.posh, s.hn, s.hcache, s.velu, id, gm, inst, P, cv, omega, thermo,
+                           status, stat, redo);
+}
+
 template <class T>
 void launch_density(const SortedPtrs<T>& s, const u32* id, const GroupMap& gm, i64 ngroups,
                     const InstDev* inst, const SphParams& P, const CacheView& cv, T* omega,
                     vec4<T>* thermo, u8* status, InstStat* stat, const u8* redo, hipStream_t st)
 {
     if (ngroups <= 0) return;
+    switch (P.kernel) {
+    case KM5: launch_density_k<T, KM5>(s, id, gm, ngroups, inst, P, cv, omega, thermo, status, stat, redo, st); break;
+    case KM6: launch_density_k<T, KM6>(s, id, gm, ngroups, inst, P, cv, omega, thermo, status, stat, redo, st); break;
+    case KC2: launch_density_k<T, KC2>(s, id, gm, ngroups, inst, P, cv, omega, thermo, status, stat, redo, st); break;
+    case KC4: launch_density_k<T, KC4>(s, id, gm, ngroups, inst, P, cv, omega, thermo, status, stat, redo, st); break;
+    case KC6: launch_density_k<T, KC6>(s, id, gm, ngroups, inst, P, cv, omega, thermo, status, stat, redo, st); break;
+    default:  launch_density_k<T, KM4>(s, id, gm, ngroups, inst, P, cv, omega, thermo, status, stat, redo, st); break;
+    }
+}
+
+template <class T, int K>
+void launch_force_k(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id, const GroupMap& gm,
+                    i64 ngroups, const InstDev* inst, const SphParams& P, const CacheView& cv,
+                    vec4<T>* acc, T* vsig, InstStat* stat, hipStream_t st)
+{
     if (sizeof(T) == 4)
-        hipLaunchKernelGGL((k_density<T, DENS_CH_F>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
-                           s.posh, s.hn, s.hcache, s.velu, id, gm, inst, P, cv, omega, thermo,
-                           status, stat, redo);
+        hipLaunchKernelGGL((k_force<T, FORCE_CH_F, K>), dim3((unsigned)ngroups), dim3(FT), 0, st,
+                           s.posh, s.velu, thermo, id, gm, inst, P, cv, acc, vsig, stat);
     else
-        hipLaunchKernelGGL((k_density<T, DENS_CH_D>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
-                           s.posh, s.hn, s.hcache, s.velu, id, gm, inst, P, cv, omega, thermo,
-                           status, stat, redo);
+        hipLaunchKernelGGL((k_force<T, FORCE_CH_D, K>), dim3((unsigned)ngroups), dim3(FT), 0, st,
+                           s.posh, s.velu, thermo, id, gm, inst, P, cv, acc, vsig, stat);
 }
 
 template <class T>
@@ -699,12 +883,61 @@ void launch_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id, 
                   vec4<T>* acc, T* vsig, InstStat* stat, hipStream_t st)
 {
     if (ngroups <= 0) return;
+    switch (P.kernel) {
+    case KM5: launch_force_k<T, KM5>(s, thermo, id, gm, ngroups, inst, P, cv, acc, vsig, stat, st); break;
+    case KM6: launch_force_k<T, KM6>(s, thermo, id, gm, ngroups, inst, P, cv, acc, vsig, stat, st); break;
+    case KC2: launch_force_k<T, KC2>(s, thermo, id, gm, ngroups, inst, P, cv, acc, vsig, stat, st); break;
+    case KC4: launch_force_k<T, KC4>(s, thermo, id, gm, ngroups, inst, P, cv, acc, vsig, stat, st); break;
+    case KC6: launch_force_k<T, KC6>(s, thermo, id, gm, ngroups, inst, P, cv, acc, vsig, stat, st); break;
+    default:  launch_force_k<T, KM4>(s, thermo, id, gm, ngroups, inst, P, cv, acc, vsig, stat, st); break;
+    }
+}
+
+constexpr int ALPHA_CH_F = 1280, ALPHA_CH_D = 640;
+
+template <class T, int K>
+void launch_alpha_k(const SortedPtrs<T>& s, const vec4<T>* acc_n, const T* omega, const u32* id,
+                    const GroupMap& gm, i64 ngroups, const InstDev* inst, const SphParams& P,
+                    const CacheView& cv, const double* dt_inst, T* alpha, vec4<T>* thermo,
+                    hipStream_t st)
+{
     if (sizeof(T) == 4)
-        hipLaunchKernelGGL((k_force<T, FORCE_CH_F>), dim3((unsigned)ngroups), dim3(FT), 0, st,
-                           s.posh, s.velu, thermo, id, gm, inst, P, cv, acc, vsig, stat);
+        hipLaunchKernelGGL((k_alpha<T, ALPHA_CH_F, K>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
+                           s.posh, s.velu, acc_n, omega, id, gm, inst, P, cv, dt_inst, alpha, thermo);
     else
-        hipLaunchKernelGGL((k_force<T, FORCE_CH_D>), dim3((unsigned)ngroups), dim3(FT), 0, st,
-                           s.posh, s.velu, thermo, id, gm, inst, P, cv, acc, vsig, stat);
+        hipLaunchKernelGGL((k_alpha<T, ALPHA_CH_D, K>), dim3((unsigned)ngroups), dim3(GROUP), 0, st,
+                           s.posh, s.velu, acc_n, omega, id, gm, inst, P, cv, dt_inst, alpha, thermo);
+}
+
+template <class T>
+void launch_alpha(const SortedPtrs<T>& s, const vec4<T>* acc_n, const T* omega, const u32* id,
+                  const GroupMap& gm, i64 ngroups, const InstDev* inst, const SphParams& P,
+                  const CacheView& cv, const double* dt_inst, T* alpha, vec4<T>* thermo,
+                  hipStream_t st)
+{
+    if (ngroups <= 0) return;
+    switch (P.kernel) {
+    case KM5: launch_alpha_k<T, KM5>(s, acc_n, omega, id, gm, ngroups, inst, P, cv, dt_inst, alpha, thermo, st); break;
+    case KM6: launch_alpha_k<T, KM6>(s, acc_n, omega, id, gm, ngroups, inst, P, cv, dt_inst, alpha, thermo, st); break;
+    case KC2: launch_alpha_k<T, KC2>(s, acc_n, omega, id, gm, ngroups, inst, P, cv, dt_inst, alpha, thermo, st); break;
+    case KC4: launch_alpha_k<T, KC4>(s, acc_n, omega, id, gm, ngroups, inst, P, cv, dt_inst, alpha, thermo, st); break;
+    case KC6: launch_alpha_k<T, KC6>(s, acc_n, omega, id, gm, ngroups, inst, P, cv, dt_inst, alpha, thermo, st); break;
+    default:  launch_alpha_k<T, KM4>(s, acc_n, omega, id, gm, ngroups, inst, P, cv, dt_inst, alpha, thermo, st); break;
+    }
+}
+
+// Gather a key-order copy of one caller array: dst[i] = src[eps[i]].
+template <class T>
+__global__ void k_gather1(const u32* __restrict__ eps, i64 n, const T* __restrict__ src,
+                          T* __restrict__ dst)
+{
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[eps[i]];
+}
+
+template <class T> void launch_gather1(const u32* eps, i64 n, const T* src, T* dst, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL((k_gather1<T>), grid_for(n, 256), dim3(256), 0, st, eps, n, src, dst);
 }
 
 template <class T>
@@ -736,13 +969,22 @@ void launch_gather_velu(const u32* eps, i64 n, const T* vx, const T* vy, const T
 }
 
 template <class T>
+void launch_velu_from_out(const OutPtrs<T>& o, i64 n, const i64* p_off, int ninst,
+                          const InstDev* inst, const u8* redo, vec4<T>* velu, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL((k_velu_from_out<T>), grid_for(n, 256), dim3(256), 0, st, o, n, p_off,
+                           ninst, inst, redo, velu);
+}
+
+template <class T>
 void launch_thermo(const vec4<T>* posh, const vec4<T>* velu, const T* omega, i64 n,
                    const i64* p_off, int ninst, const InstDev* inst, double hfact, double gamma,
-                   vec4<T>* thermo, hipStream_t st)
+                   double alpha, const T* alpha_s, vec4<T>* thermo, hipStream_t st)
 {
     if (n > 0)
         hipLaunchKernelGGL((k_thermo<T>), grid_for(n, 256), dim3(256), 0, st, posh, velu, omega, n,
-                           p_off, ninst, inst, hfact, gamma, thermo);
+                           p_off, ninst, inst, hfact, gamma, alpha, alpha_s, thermo);
 }
 
 template <class T>
@@ -777,8 +1019,15 @@ void launch_scatter_rho(const u32* eps, i64 n, const vec4<T>* posh, const i64* p
                                     const OutPtrs<T>&, InstStat*, BlockPart*, hipStream_t);        \
     template void launch_gather_velu<T>(const u32*, i64, const T*, const T*, const T*, const T*,  \
                                         vec4<T>*, hipStream_t);                                   \
+    template void launch_alpha<T>(const SortedPtrs<T>&, const vec4<T>*, const T*, const u32*,     \
+                                  const GroupMap&, i64, const InstDev*, const SphParams&,         \
+                                  const CacheView&, const double*, T*, vec4<T>*, hipStream_t);    \
+    template void launch_gather1<T>(const u32*, i64, const T*, T*, hipStream_t);                  \
+    template void launch_velu_from_out<T>(const OutPtrs<T>&, i64, const i64*, int,                \
+                                          const InstDev*, const u8*, vec4<T>*, hipStream_t);      \
     template void launch_thermo<T>(const vec4<T>*, const vec4<T>*, const T*, i64, const i64*,     \
-                                   int, const InstDev*, double, double, vec4<T>*, hipStream_t);   \
+                                   int, const InstDev*, double, double, double, const T*,         \
+                                   vec4<T>*, hipStream_t);                                        \
     template void launch_scatter<T>(const u32*, i64, const vec4<T>*, int, const T*, T*,           \
                                     hipStream_t);                                                 \
     template void launch_scatter_rho<T>(const u32*, i64, const vec4<T>*, const i64*, int,         \

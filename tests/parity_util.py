@@ -8,6 +8,61 @@ import oracle
 F32_ULP = 2.0 ** -23
 
 
+def box_for_oracle(p):
+    """The oracle's box: the periodic box, or the data extent (isolated)."""
+    if p.periodic:
+        return p.lo, p.hi
+    return ((float(p.x.min()), float(p.y.min()), float(p.z.min())),
+            (float(p.x.max()), float(p.y.max()), float(p.z.max())))
+
+
+def _oracle_tree(p, n_red):
+    lo, hi = box_for_oracle(p)
+    keys = oracle.morton(p.x, p.y, p.z, lo, hi)
+    eps, mu = oracle.sort(keys)
+    xi, ids, ml = oracle.leaves(mu, n_red)
+    t = oracle.radix_tree(ml)
+    return keys, eps, mu, xi, ids, ml, t
+
+
+def check_tree(ctx, p, n_red, chi=1.1, r_kern=2.0):
+    """Every table of the GPU's last build against the oracle, bit for bit;
+    the cache radius is r_kern chi max(h_a, h_b)."""
+    T = p.x.dtype
+    ex = ctx.export_tree(dtype=T)
+    keys, eps, mu, xi, ids, ml, t = _oracle_tree(p, n_red)
+    assert np.array_equal(ex["keys"], keys), "Morton keys"
+    assert np.array_equal(ex["eps"], eps), "sort permutation"
+    assert np.array_equal(ex["mu"], mu)
+    assert np.array_equal(ex["xi"], xi), "keep mask"
+    assert np.array_equal(ex["id"], ids)
+    assert np.array_equal(ex["mu_leaf"], ml)
+    for k in ("lchild", "rchild", "lflag", "rflag", "endrange"):
+        assert np.array_equal(ex[k], t[k]), k
+    assert np.array_equal(ex["parent"], t["parent"]), "parent"
+    xs, ys, zs, hs = p.x[eps], p.y[eps], p.z[eps], p.h[eps]
+    bmin, bmax, hmax = oracle.tight_boxes(ids, t, xs, ys, zs, hs)
+    assert np.array_equal(ex["bmin"].astype(np.float64), bmin), "tight box min"
+    assert np.array_equal(ex["bmax"].astype(np.float64), bmax), "tight box max"
+    assert np.array_equal(ex["hmax"].astype(np.float64), hmax), "h_max"
+    box, plen = oracle.prefix_boxes(ml, t)
+    assert np.array_equal(ex["pbox"], box) and np.array_equal(ex["plen"], plen), "prefix boxes"
+    lo, hi = box_for_oracle(p)
+    off, lst = oracle.neighbours(xs, ys, zs, hs, lo, hi, p.periodic, r_kern * chi)
+    assert np.array_equal(ex["neigh_off"], off), "neighbour counts"
+    assert np.array_equal(ex["neigh_list"], lst), "neighbour sets / order"
+    # stage-1 lists (per group of 256 key-order slots) are ascending and
+    # cover the leaf of every neighbour of every particle of the group
+    go, gl = ex["group_off"], ex["group_leaves"]
+    leaf_of = np.searchsorted(ids, np.arange(p.n), side="right") - 1
+    for a in range(0, p.n, max(1, p.n // 300)):
+        g = a // 256
+        seg = gl[go[g]:go[g + 1]]
+        assert (np.diff(seg.astype(np.int64)) > 0).all()
+        assert set(leaf_of[lst[off[a]:off[a + 1]]]) <= set(seg.tolist())
+    return ex
+
+
 def map_to_start(pid_start, pid_after):
     """Index into the start-of-step arrays for every particle of the output
     (the step returns the particles in the new key order, ids carried)."""
@@ -91,7 +146,7 @@ def check_corrector_forms(s0, s1, j, dt, T, lo, hi, periodic, info=None):
     return amb
 
 
-def check_step_vs_oracle(s0, s1, ref, info, p, dt, T):
+def check_step_vs_oracle(s0, s1, ref, info, p, dt, T, **params):
     """A GPU step (s0 -> s1, FP32 or FP64) against oracle.step on the same
     start state (ref): raw positions, h, a, du/dt (scaled), v, u, and the
     corrector reductions max|dv|, sum|dv|^2, sum|v|^2 against the oracle's."""
@@ -102,8 +157,11 @@ def check_step_vs_oracle(s0, s1, ref, info, p, dt, T):
                     p.lo, p.hi, tolx)
     hr = np.abs(s1["h"] / ref["h"][j] - 1).max()
     assert hr <= (1e-5 if f32 else 1e-10), hr
+    fp = {k: params[k] for k in ("kernel", "gamma", "alpha", "beta", "beta_u") if k in params}
+    if "alpha" in ref:
+        fp["alpha_arr"] = ref["alpha"]
     fr = oracle.force(ref["x"], ref["y"], ref["z"], ref["vx"], ref["vy"], ref["vz"], ref["u"],
-                      ref["h"], ref["rho"], ref["omega"], p.lo, p.hi, p.periodic, p.mass)
+                      ref["h"], ref["rho"], ref["omega"], p.lo, p.hi, p.periodic, p.mass, **fp)
     g = {k: s1[k].astype(np.float64) for k in ("ax", "ay", "az", "dudt")}
     r = {k: ref[k][j] for k in ("ax", "ay", "az", "dudt")}
     r["scale_a"], r["scale_u"] = fr["scale_a"][j], fr["scale_u"][j]

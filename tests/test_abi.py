@@ -50,7 +50,11 @@ def test_params_default_matches_paper_values(lib_path):
     assert p.alpha_av == 1.0 and p.beta_av == 2.0 and p.beta_u == 1.0
     assert p.c_cour == 0.3 and p.c_force == 0.25
     assert abs(p.gamma - 5.0 / 3.0) < 1e-15
-    assert ctypes.sizeof(shsph.CParticles) == 8 + 4 + 4 + 8 + 48 + 15 * 8
+    assert ctypes.sizeof(shsph.CParticles) == 8 + 4 + 4 + 8 + 48 + 16 * 8
+    # extensions: M4 kernel, 64-bit Morton codes, no corrector re-runs, constant alpha
+    assert p.kernel == 0 and p.key_bits == 63 and p.eps_v == 0.0 and p.max_reruns == 3
+    assert p.alpha_switch == 0 and p.alpha_min == 0.0 and p.alpha_max == 1.0
+    assert p.sigma_decay == 0.1 and p.lambda_stiff == 1.0
 
 
 def test_binding_has_no_fallback(monkeypatch, tmp_path):

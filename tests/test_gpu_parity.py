@@ -34,56 +34,8 @@ def _ctx(torch_cuda, **kw):
     return shsph.Context(0, **kw)
 
 
-def _box_for_oracle(p):
-    if p.periodic:
-        return p.lo, p.hi
-    return ((float(p.x.min()), float(p.y.min()), float(p.z.min())),
-            (float(p.x.max()), float(p.y.max()), float(p.z.max())))
-
-
-def _oracle_tree(p, n_red):
-    lo, hi = _box_for_oracle(p)
-    keys = oracle.morton(p.x, p.y, p.z, lo, hi)
-    eps, mu = oracle.sort(keys)
-    xi, ids, ml = oracle.leaves(mu, n_red)
-    t = oracle.radix_tree(ml)
-    return keys, eps, mu, xi, ids, ml, t
-
-
-def check_tree(ctx, p, n_red, chi=1.1):
-    T = p.x.dtype
-    ex = ctx.export_tree(dtype=T)
-    keys, eps, mu, xi, ids, ml, t = _oracle_tree(p, n_red)
-    assert np.array_equal(ex["keys"], keys), "Morton keys"
-    assert np.array_equal(ex["eps"], eps), "sort permutation"
-    assert np.array_equal(ex["mu"], mu)
-    assert np.array_equal(ex["xi"], xi), "keep mask"
-    assert np.array_equal(ex["id"], ids)
-    assert np.array_equal(ex["mu_leaf"], ml)
-    for k in ("lchild", "rchild", "lflag", "rflag", "endrange"):
-        assert np.array_equal(ex[k], t[k]), k
-    assert np.array_equal(ex["parent"], t["parent"]), "parent"
-    xs, ys, zs, hs = p.x[eps], p.y[eps], p.z[eps], p.h[eps]
-    bmin, bmax, hmax = oracle.tight_boxes(ids, t, xs, ys, zs, hs)
-    assert np.array_equal(ex["bmin"].astype(np.float64), bmin), "tight box min"
-    assert np.array_equal(ex["bmax"].astype(np.float64), bmax), "tight box max"
-    assert np.array_equal(ex["hmax"].astype(np.float64), hmax), "h_max"
-    box, plen = oracle.prefix_boxes(ml, t)
-    assert np.array_equal(ex["pbox"], box) and np.array_equal(ex["plen"], plen), "prefix boxes"
-    lo, hi = _box_for_oracle(p)
-    off, lst = oracle.neighbours(xs, ys, zs, hs, lo, hi, p.periodic, 2.0 * chi)
-    assert np.array_equal(ex["neigh_off"], off), "neighbour counts"
-    assert np.array_equal(ex["neigh_list"], lst), "neighbour sets / order"
-    # stage-1 lists (per group of 256 key-order slots) are ascending and
-    # cover the leaf of every neighbour of every particle of the group
-    go, gl = ex["group_off"], ex["group_leaves"]
-    leaf_of = np.searchsorted(ids, np.arange(p.n), side="right") - 1
-    for a in range(0, p.n, max(1, p.n // 300)):
-        g = a // 256
-        seg = gl[go[g]:go[g + 1]]
-        assert (np.diff(seg.astype(np.int64)) > 0).all()
-        assert set(leaf_of[lst[off[a]:off[a + 1]]]) <= set(seg.tolist())
-    return ex
+_box_for_oracle = parity_util.box_for_oracle
+check_tree = parity_util.check_tree
 
 
 def _upload(p, torch_cuda):
