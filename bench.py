@@ -205,6 +205,92 @@ def run_lattice(args, shsph, torch, name="uniform128", steps=20, warmup=3):
             "unit": "particle-steps/s"}
 
 
+def run_f64(args, shsph, torch, steps=10, warmup=3):
+    """The Sedov 256^3 workload in FP64 (the paper's arithmetic), CFL steps."""
+    import numpy as np
+    import gen
+    p = gen.sedov(256, gen.SEEDS["sedov"], dtype=np.float64)
+    log(f"[f64] sedov256 FP64, {p.n} particles")
+    ps = shsph.ParticleSet.from_particles(p)
+    ctx = shsph.Context(0, n_red=args.n_red, eps_h=1e-12)
+    ctx.build_tree(ps)
+    ctx.density(ps)
+    ctx.force(ps)
+    for _ in range(warmup):
+        ctx.step(ps, 0.0)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(ps, 0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stages = ctx.stage_times()
+    ctx.close()
+    log(f"[f64] {1e3 * el / steps:.2f} ms/step")
+    return {"workload": "sedov256", "dtype": "f64", "particles": p.n, "steps": steps,
+            "warmup": warmup, "ms_per_step": 1e3 * el / steps, "value": p.n * steps / el,
+            "unit": "particle-steps/s",
+            "stages_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items()}}
+
+
+def run_tree_build_key_bits(args, shsph, torch, reps=5):
+    """Tree build from the input's random order (full radix sort) with 63-bit
+    and 30-bit Morton codes (Sect. 5.2.1 reports about 30% faster builds with
+    32-bit codes): the tree stages (keys, sort, gather, mask/reduction,
+    Karras, boxes) of shsph_build_tree, Sedov 256^3 FP32."""
+    import numpy as np
+    import gen
+    p = gen.sedov(256, gen.SEEDS["sedov"], dtype=np.float32)
+    ps = shsph.ParticleSet.from_particles(p)
+    tree = ("predict_morton", "radix_sort", "gather", "mask_reduce_compact", "karras", "boxes")
+    res = {"workload": "sedov256", "particles": p.n, "repetitions": reps}
+    for bits in (63, 30):
+        ctx = shsph.Context(0, n_red=args.n_red, key_bits=bits)
+        ctx.build_tree(ps)
+        torch.cuda.synchronize()
+        ctx.set_profiling(True)
+        for _ in range(reps):
+            ctx.build_tree(ps)
+        torch.cuda.synchronize()
+        st = ctx.stage_times()
+        ctx.close()
+        ms = sum(st[k][0] for k in tree) / reps
+        res[f"key_bits_{bits}"] = {"tree_ms": round(ms, 4),
+                                   "stages_ms": {k: round(st[k][0] / reps, 4) for k in tree},
+                                   "objects_per_s": p.n / (ms * 1e-3)}
+        log(f"[tree] {bits}-bit codes: {ms:.3f} ms per tree build")
+    res["speedup_30_vs_63"] = res["key_bits_63"]["tree_ms"] / res["key_bits_30"]["tree_ms"]
+    return res
+
+
+def run_m6(args, shsph, torch, steps=10, warmup=3):
+    """The M6 kernel with h_fact = 1.0 (the paper's physics tests, about 113
+    neighbours) on the jittered 128^3 lattice, FP32, CFL steps."""
+    import numpy as np
+    import gen
+    p = gen.lattice(128, gen.SEEDS["uniform"], dtype=np.float32, hfact=1.0)
+    ps = shsph.ParticleSet.from_particles(p)
+    ctx = shsph.Context(0, n_red=args.n_red, kernel="M6", hfact=1.0)
+    ctx.build_tree(ps)
+    ctx.density(ps)
+    ctx.force(ps)
+    for _ in range(warmup):
+        ctx.step(ps, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(ps, 0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = ctx.get_info()
+    ctx.close()
+    log(f"[m6] {1e3 * el / steps:.2f} ms/step")
+    return {"workload": "uniform128", "kernel": "M6", "hfact": 1.0, "particles": p.n,
+            "cache_entries_per_particle": info["n_neigh"] / p.n, "steps": steps,
+            "ms_per_step": 1e3 * el / steps, "value": p.n * steps / el, "unit": "particle-steps/s"}
+
+
 def run_batched(args, shsph, torch):
     """64 uneven instances (half jittered lattices, half Plummer spheres,
     N_i log-uniform in [2^12, 2^20]): K CFL steps as one batched pass per step,
@@ -278,7 +364,9 @@ def serve_templates(seed):
 def run_served(args, shsph, torch, tune=None):
     """Poisson arrivals of STEP (1-10 CFL steps) and EVAL jobs, each bringing
     its own instance, served under a 200 GB budget with continuous batching and,
-    on the same trace, one job at a time."""
+    on the same trace, one job at a time: each policy's saturation capacity
+    (a burst), then a sweep of offered rates below and above the one-at-a-time
+    capacity with p50 / p99 latency and throughput."""
     import numpy as np
     import gen
     kw = dict(n_red=args.n_red) if not tune else dict(n_red=tune["n_red"],
@@ -301,84 +389,88 @@ def run_served(args, shsph, torch, tune=None):
     for j in base:
         k = int(np.argmin(np.abs(logn[j["family"]] - np.log(j["n"]))))
         jobs.append(dict(j, tpl=k, n=tpl[j["family"]][k].n))
-    # passes per job: a STEP job's instance first gets its derivatives
-    work = np.array([j["n"] * (j["nsteps"] + 1 if j["kind"] == "step" else 1) for j in jobs], float)
 
     def submit(ctx, j):
         kind = shsph.JOB_EVAL if j["kind"] == "eval" else shsph.JOB_STEP
         return ctx.submit(init=sets[j["family"]][j["tpl"]], kind=kind, nsteps=j["nsteps"],
                           release=True)
 
-    # capacity of the served mix: a burst of the trace's first jobs, all at once
-    nb = min(300, len(jobs))
-    ctx = shsph.Context(0, **kw)
-    ctx.serve_start(200e9, max_batch=256, max_batch_particles=args.serve_pass_particles)
-    log(f"[served] capacity probe: {nb} jobs at once")
-    t0 = time.perf_counter()
-    for j in jobs[:nb]:
-        submit(ctx, j)
-    while not ctx.serve_wait(5.0):
-        log(f"[served] capacity probe: {ctx.serve_stats()['jobs_done']} of {nb} done")
-    cap_served = work[:nb].sum() / (time.perf_counter() - t0)
-    ctx.serve_stop()
-    ctx.close()
-    rate = args.serve_load * cap_served / work.mean()
-    res = {"workload": "served", "jobs": len(jobs), "rate_jobs_per_s": rate,
-           "capacity_particle_passes_per_s": cap_served,
-           "offered_load_of_capacity": args.serve_load, "budget_GB": 200,
-           "pass_particles_max": args.serve_pass_particles,
-           "templates": 32, "eval_fraction": float(np.mean([j["kind"] == "eval" for j in jobs]))}
-    for name, policy in (("continuous", shsph.SERVE_CONTINUOUS),
-                         ("one_at_a_time", shsph.SERVE_ONE_AT_A_TIME)):
+    def serve(policy, jobs_run, rate, label):
+        """Serve `jobs_run` with one policy; rate None = every job at once
+        (a burst: the policy's saturation capacity), else Poisson arrivals at
+        `rate` jobs/s on the trace's own arrival times."""
         ctx = shsph.Context(0, **kw)
         ctx.serve_start(200e9, max_batch=256, policy=policy,
                         max_batch_particles=args.serve_pass_particles)
-        log(f"[served] {name}: {len(jobs)} jobs at {rate:.1f}/s")
+        log(f"[served] {label}: {len(jobs_run)} jobs" + ("" if rate is None else f" at {rate:.1f}/s"))
         tk = []
         t0 = time.perf_counter()
-        for i, j in enumerate(jobs):
+        t_first = jobs_run[0]["t"]
+        for i, j in enumerate(jobs_run):
             if i and i % 250 == 0:
                 st = ctx.serve_stats()
-                log(f"[served] {name}: {i} submitted, {st['jobs_done']} done, {st['passes']} passes")
-            due = t0 + j["t"] / rate
-            while True:
-                d = due - time.perf_counter()
-                if d <= 0:
-                    break
-                time.sleep(d if d > 2e-3 else 0)
+                log(f"[served] {label}: {i} submitted, {st['jobs_done']} done, {st['passes']} passes")
+            if rate is not None:
+                due = t0 + (j["t"] - t_first) / rate
+                while True:
+                    d = due - time.perf_counter()
+                    if d <= 0:
+                        break
+                    time.sleep(d if d > 2e-3 else 0)
             tk.append(submit(ctx, j))
         t_end = time.perf_counter() + args.serve_timeout
         while not ctx.serve_wait(5.0):
             st = ctx.serve_stats()
-            log(f"[served] {name}: draining, {st['jobs_done']} of {len(jobs)} done")
+            log(f"[served] {label}: draining, {st['jobs_done']} of {len(jobs_run)} done")
             if time.perf_counter() > t_end:
-                raise RuntimeError(f"serving run ({name}) did not finish in {args.serve_timeout} s")
+                raise RuntimeError(f"serving run ({label}) did not finish in {args.serve_timeout} s")
         st = [ctx.poll(t) for t in tk]
         stats = ctx.serve_stats()
         ctx.serve_stop()
         ctx.close()
         errs = {}
-        for s in st:
-            if s["state"] != "done":
-                errs[str(s["error"])] = errs.get(str(s["error"]), 0) + 1
+        for x in st:
+            if x["state"] != "done":
+                errs[str(x["error"])] = errs.get(str(x["error"]), 0) + 1
         if errs:
-            log(f"[served] {name}: failed jobs by error code {errs}")
-        lat = np.array([s["t_done"] - s["t_submit"] for s in st])
-        done = sum(s["state"] == "done" for s in st)
-        span = max(s["t_done"] for s in st) - min(s["t_submit"] for s in st)
-        steps = sum(j["n"] * (j["nsteps"] if j["kind"] == "step" else 1) for j in jobs)
-        res[name] = {"p50_ms": 1e3 * float(np.percentile(lat, 50)),
-                     "p99_ms": 1e3 * float(np.percentile(lat, 99)),
-                     "mean_ms": 1e3 * float(lat.mean()), "jobs_done": int(done),
-                     "throughput_particle_steps_per_s": steps / span, "makespan_s": span,
-                     "failed_by_error": errs,
-                     "passes": stats["passes"], "peak_jobs_per_pass": stats["peak_jobs"],
-                     "peak_GB": stats["peak_bytes"] / 1e9}
-        log(f"[served] {name}: p50 {res[name]['p50_ms']:.1f} ms, p99 {res[name]['p99_ms']:.1f} ms")
-    c, o = res["continuous"], res["one_at_a_time"]
-    res["throughput_vs_one_at_a_time"] = (c["throughput_particle_steps_per_s"] /
-                                          o["throughput_particle_steps_per_s"])
-    res["p99_vs_one_at_a_time"] = c["p99_ms"] / o["p99_ms"]
+            log(f"[served] {label}: failed jobs by error code {errs}")
+        lat = np.array([x["t_done"] - x["t_submit"] for x in st])
+        span = max(x["t_done"] for x in st) - min(x["t_submit"] for x in st)
+        steps = sum(j["n"] * (j["nsteps"] if j["kind"] == "step" else 1) for j in jobs_run)
+        r = {"p50_ms": 1e3 * float(np.percentile(lat, 50)),
+             "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+             "mean_ms": 1e3 * float(lat.mean()),
+             "jobs_done": int(sum(x["state"] == "done" for x in st)),
+             "throughput_particle_steps_per_s": steps / span,
+             "throughput_jobs_per_s": len(jobs_run) / span, "makespan_s": span,
+             "failed_by_error": errs, "passes": stats["passes"],
+             "peak_jobs_per_pass": stats["peak_jobs"], "peak_GB": stats["peak_bytes"] / 1e9}
+        log(f"[served] {label}: {r['throughput_jobs_per_s']:.1f} jobs/s, "
+            f"p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms")
+        return r
+
+    policies = (("continuous", shsph.SERVE_CONTINUOUS), ("one_at_a_time", shsph.SERVE_ONE_AT_A_TIME))
+    # saturation capacity of each policy: the same burst of the trace's first jobs
+    nb = min(args.serve_burst, len(jobs))
+    cap = {name: serve(pol, jobs[:nb], None, f"{name} capacity (burst)") for name, pol in policies}
+    c1 = cap["one_at_a_time"]["throughput_jobs_per_s"]
+    res = {"workload": "served", "jobs_per_rate": args.serve_jobs, "budget_GB": 200,
+           "pass_particles_max": args.serve_pass_particles, "templates": 32,
+           "eval_fraction": float(np.mean([j["kind"] == "eval" for j in jobs])),
+           "capacity_burst_jobs": nb, "capacity": cap,
+           "capacity_vs_one_at_a_time": (cap["continuous"]["throughput_particle_steps_per_s"] /
+                                         cap["one_at_a_time"]["throughput_particle_steps_per_s"]),
+           "rates": []}
+    # offered loads relative to the one-at-a-time capacity, below and above it
+    for f in args.serve_loads:
+        rate = f * c1
+        row = {"offered_load_of_one_at_a_time_capacity": f, "rate_jobs_per_s": rate}
+        for name, pol in policies:
+            row[name] = serve(pol, jobs[:args.serve_jobs], rate, f"{name} at {f:g}x")
+        row["throughput_vs_one_at_a_time"] = (row["continuous"]["throughput_particle_steps_per_s"] /
+                                              row["one_at_a_time"]["throughput_particle_steps_per_s"])
+        row["p99_vs_one_at_a_time"] = row["continuous"]["p99_ms"] / row["one_at_a_time"]["p99_ms"]
+        res["rates"].append(row)
     return res
 
 
@@ -394,15 +486,19 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batch run")
     ap.add_argument("--no-lattice", action="store_true", help="skip the 128^3 lattice run")
     ap.add_argument("--no-served", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the FP64 line, the 30-bit tree build and the M6 line")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-warmup", type=int, default=2)
-    ap.add_argument("--serve-jobs", type=int, default=2000)
+    ap.add_argument("--serve-jobs", type=int, default=600, help="jobs per offered rate")
+    ap.add_argument("--serve-burst", type=int, default=300,
+                    help="jobs submitted at once to measure each policy's capacity")
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0],
+                    help="offered loads as multiples of the one-at-a-time capacity")
     ap.add_argument("--serve-pass-particles", type=int, default=1 << 25,
                     help="particles in one serving pass (bounds working memory and pass time)")
     ap.add_argument("--serve-timeout", type=float, default=300.0,
                     help="give up a serving run that has not drained after this many seconds")
-    ap.add_argument("--serve-load", type=float, default=0.75,
-                    help="offered load as a fraction of the served mix's measured capacity")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against known bytes) and exit")
@@ -503,6 +599,13 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_lattice:
         out["uniform128"] = run_lattice(args, shsph, torch)
+        torch.cuda.empty_cache()
+    if not args.no_extra:
+        out["fp64"] = run_f64(args, shsph, torch)
+        torch.cuda.empty_cache()
+        out["tree_build"] = run_tree_build_key_bits(args, shsph, torch)
+        torch.cuda.empty_cache()
+        out["m6"] = run_m6(args, shsph, torch)
         torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = run_batched(args, shsph, torch)

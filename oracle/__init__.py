@@ -79,6 +79,9 @@ def lib():
     L.orc_interleave.argtypes = [C.c_uint32] * 3
     L.orc_deinterleave.argtypes = [C.c_uint64, vp, vp, vp]
     L.orc_morton.argtypes = [i64, f64p, f64p, f64p, f64p, f64p, u64p]
+    L.orc_morton_bits.argtypes = [i64, f64p, f64p, f64p, f64p, f64p, i32, u64p]
+    L.orc_interleave_bits.restype = C.c_uint64
+    L.orc_interleave_bits.argtypes = [C.c_uint32] * 3 + [i32]
     L.orc_delta.restype = i32
     L.orc_delta.argtypes = [C.c_uint64, C.c_uint64]
     L.orc_sort.argtypes = [i64, u64p, u32p, u64p]
@@ -153,13 +156,21 @@ def delta(a: int, b: int) -> int:
     return int(lib().orc_delta(C.c_uint64(int(a)), C.c_uint64(int(b))))
 
 
-def morton(x, y, z, lo, hi) -> np.ndarray:
-    """64-bit Morton keys, 21 bits per axis, quantised in FP64 (App. B.1)."""
+def morton(x, y, z, lo, hi, bits=21) -> np.ndarray:
+    """Morton keys, `bits` per axis (21: 63-bit codes, 10: 30-bit codes),
+    quantised in FP64 (App. B.1, Sect. 5.2.1)."""
     x, y, z = _d(x), _d(y), _d(z)
     lo, hi = _box(lo, hi)
     key = np.empty(x.shape[0], np.uint64)
-    lib().orc_morton(x.shape[0], x, y, z, lo, hi, key)
+    if bits == 21:
+        lib().orc_morton(x.shape[0], x, y, z, lo, hi, key)
+    else:
+        lib().orc_morton_bits(x.shape[0], x, y, z, lo, hi, int(bits), key)
     return key
+
+
+def interleave_bits(X, Y, Z, bits) -> int:
+    return int(lib().orc_interleave_bits(int(X), int(Y), int(Z), int(bits)))
 
 
 def sort(key):

@@ -63,26 +63,39 @@ void orc_set_threads(int n)
 /* Morton codes (App. B.1): map to [0,1), sample a 2^21 grid per axis,  */
 /* interleave bit by bit with X as the most significant of each triple. */
 /* ------------------------------------------------------------------ */
-static uint32_t quantize(double v, double lo, double scale)
+static uint32_t quantize_bits(double v, double lo, double scale, int bits)
 {
     double t = (v - lo) * scale;
     double f = floor(t);
+    double top = (double)((1u << bits) - 1u);
     if (!(f >= 0.0)) f = 0.0;                     /* also catches NaN */
-    if (f > (double)(ORC_GRID - 1)) f = (double)(ORC_GRID - 1);  /* 1 is excluded */
+    if (f > top) f = top;                         /* 1 is excluded */
     return (uint32_t)f;
 }
 
-uint64_t orc_interleave(uint32_t X, uint32_t Y, uint32_t Z)
+static uint32_t quantize(double v, double lo, double scale)
+{
+    return quantize_bits(v, lo, scale, ORC_BITS);
+}
+
+/* Interleave `bits`-bit integers into a 3*bits-bit code in the low bits:  */
+/* triple k (k = 0 the most significant) holds X_k Y_k Z_k, X first.       */
+uint64_t orc_interleave_bits(uint32_t X, uint32_t Y, uint32_t Z, int bits)
 {
     uint64_t key = 0;
-    for (int k = 0; k < ORC_BITS; ++k) {
-        int src = ORC_BITS - 1 - k;               /* X_k is bit (20-k) of X */
-        int dst = 3 * (ORC_BITS - 1 - k);         /* triple k sits at bits dst+2..dst */
+    for (int k = 0; k < bits; ++k) {
+        int src = bits - 1 - k;                   /* X_k is bit (bits-1-k) of X */
+        int dst = 3 * (bits - 1 - k);             /* triple k sits at bits dst+2..dst */
         key |= (uint64_t)((X >> src) & 1u) << (dst + 2);
         key |= (uint64_t)((Y >> src) & 1u) << (dst + 1);
         key |= (uint64_t)((Z >> src) & 1u) << (dst + 0);
     }
     return key;
+}
+
+uint64_t orc_interleave(uint32_t X, uint32_t Y, uint32_t Z)
+{
+    return orc_interleave_bits(X, Y, Z, ORC_BITS);
 }
 
 void orc_deinterleave(uint64_t key, uint32_t *X, uint32_t *Y, uint32_t *Z)
@@ -96,6 +109,21 @@ void orc_deinterleave(uint64_t key, uint32_t *X, uint32_t *Y, uint32_t *Z)
         c |= (uint32_t)((key >> (dst + 0)) & 1u) << src;
     }
     *X = a; *Y = b; *Z = c;
+}
+
+/* Morton codes with `bits` per axis (App. B.1 with beta = bits; 10 bits  */
+/* per axis gives the 30-bit codes of Sect. 5.2.1).                        */
+void orc_morton_bits(int64_t n, const double *x, const double *y, const double *z,
+                     const double *lo, const double *hi, int bits, uint64_t *key)
+{
+    double s[3];
+    for (int d = 0; d < 3; ++d) s[d] = (double)(1u << bits) / (hi[d] - lo[d]);
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t X = quantize_bits(x[i], lo[0], s[0], bits);
+        uint32_t Y = quantize_bits(y[i], lo[1], s[1], bits);
+        uint32_t Z = quantize_bits(z[i], lo[2], s[2], bits);
+        key[i] = orc_interleave_bits(X, Y, Z, bits);
+    }
 }
 
 void orc_morton(int64_t n, const double *x, const double *y, const double *z,

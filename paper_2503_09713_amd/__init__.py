@@ -211,8 +211,8 @@ class ParticleSet:
         self.t["pid"] = torch.from_numpy(np.ascontiguousarray(np.asarray(pid).astype(np.int32))).to(device)
         al = arrays.get("alpha")
         if al is not None:      # per-particle viscosity alpha (a scalar fills every particle)
-            a = np.broadcast_to(np.asarray(al, dtype=self.dtype), (self.n,))
-            self.t["alpha"] = torch.from_numpy(np.ascontiguousarray(a)).to(device)
+            a = np.array(np.broadcast_to(np.asarray(al, dtype=self.dtype), (self.n,)))
+            self.t["alpha"] = torch.from_numpy(a).to(device)
         self.mass = float(mass)
         self.lo = tuple(float(v) for v in lo)
         self.hi = tuple(float(v) for v in hi)

@@ -86,6 +86,7 @@ struct shsph_ctx {
     int restarts = 0;
     int vals_sel = 0;       // which value buffer holds eps after the sort
     double lambda_cfl = 1.0;  // CFL multiplier of the plain step (App. G)
+    int key_bits_built = 63;  // Morton width of the current tree
     int reruns_last = 0;      // corrector re-runs of the last plain step
     int xi_sel = 0;         // which mask buffer holds the final keep mask
 
@@ -429,18 +430,21 @@ template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const d
     for (const InstDev& in : c->inst_h) any_isolated |= !in.periodic;
     if (any_isolated) launch_bbox<T>(f, n, inst, poff, ninst, dt_dev, P<u64>(c->bbox), st);
     prof_begin(c, S_MORTON);
-    launch_predict_morton<T>(f, n, inst, poff, ninst, dt_dev, P<u64>(c->keys[0]), P<u32>(c->vals[0]), st);
+    const int kbits = c->prm.key_bits == 30 ? 30 : 63;    // 30-bit or 63-bit Morton codes
+    launch_predict_morton<T>(f, n, inst, poff, ninst, dt_dev, P<u64>(c->keys[0]), P<u32>(c->vals[0]),
+                             kbits / 3, st);
     prof_end(c);
     TRY(check_launch(c, "morton"));
     // stable radix sort of (key, index), then gather into key order
     prof_begin(c, S_SORT);
     const int sel = radix_sort_pairs(P<u64>(c->keys[0]), P<u32>(c->vals[0]), P<u64>(c->keys[1]),
-                                     P<u32>(c->vals[1]), n, 63, poff, ninst, P<u32>(c->hist),
+                                     P<u32>(c->vals[1]), n, kbits, poff, ninst, P<u32>(c->hist),
                                      P<u32>(c->flags) + FLAG_SORT, (u32*)c->pinned, st);
     prof_end(c);
     if (sel == -2) return fail(c, SHSPH_EHIP, "radix sort: reading the out-of-place count failed");
     if (sel < 0) return fail(c, SHSPH_ECAPACITY, "more than 2^30 - 2 particles in one pass");
     c->vals_sel = sel;
+    c->key_bits_built = kbits;
     const u64* mu = P<u64>(c->keys[sel]);
     const u32* eps = P<u32>(c->vals[sel]);
     TRY(check_launch(c, "sort"));
@@ -1455,7 +1459,7 @@ int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
         TRY(ensure(c, c->plen, nn * sizeof(i32)));
         launch_prefix_boxes(P<u64>(c->mu_leaf), P<i64>(c->leaf_off_d), P<i64>(c->ioff_d), c->ninst,
                             ni, nl, P<u32>(c->endrange), P<u32>(c->parent), P<u32>(c->pbox),
-                            P<i32>(c->plen), st);
+                            P<i32>(c->plen), c->key_bits_built == 30 ? 33 : 0, st);
         TRY(check_launch(c, "prefix boxes"));
         TRY(cp(o->pbox, c->pbox.p, 6 * nn * 4));
         TRY(cp(o->plen, c->plen.p, nn * 4));

@@ -83,7 +83,8 @@ int radix_sort_pairs(u64* k0, u32* v0, u64* k1, u32* v1, i64 n, int key_bits, co
 // tree.hip
 template <class T>
 void launch_predict_morton(const FieldPtrs<T>& f, i64 n, const InstDev* inst, const i64* p_off,
-                           int ninst, const double* dt_inst, u64* keys, u32* vals, hipStream_t st);
+                           int ninst, const double* dt_inst, u64* keys, u32* vals, int bits,
+                           hipStream_t st);
 template <class T>
 void launch_gather(const FieldPtrs<T>& f, i64 n, const InstDev* inst, const i64* p_off, int ninst,
                    const double* dt_inst, const u32* eps, const SortedPtrs<T>& s, hipStream_t st);
@@ -108,7 +109,7 @@ void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 n_leaf, i64 n_inter
 size_t boxes_rec_count(i64 n_leaf);
 void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
                          i64 n_internal, i64 n_leaf, const u32* endrange, const u32* parent,
-                         u32* pbox, i32* plen, hipStream_t st);
+                         u32* pbox, i32* plen, int shift, hipStream_t st);
 
 // neigh.hip
 template <class T>

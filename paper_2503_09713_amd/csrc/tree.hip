@@ -63,23 +63,26 @@ __device__ inline u64 spread3(u32 v)
     return x;
 }
 
-__device__ inline u32 quantize(double v, double lo, double scale)
+__device__ inline u32 quantize(double v, double lo, double scale, u32 qmax)
 {
 #pragma clang fp contract(off)
     const double d = v - lo;
     const double t = d * scale;
     const double f = floor(t);
     if (!(f >= 0.0)) return 0u;
-    if (f > (double)MORTON_MAX) return MORTON_MAX;
+    if (f > (double)qmax) return qmax;
     return (u32)f;
 }
 
-__device__ inline u64 morton_key(double x, double y, double z, const InstDev& in)
+// `bits` per axis: 21 (63-bit codes) or 10 (30-bit codes, Sect. 5.2.1); the
+// code sits in the low 3 bits bits of the key.
+__device__ inline u64 morton_key(double x, double y, double z, const InstDev& in, int bits)
 {
-    const double g = (double)(1u << MORTON_BITS);
-    const u32 X = quantize(x, in.lo[0], g / (in.hi[0] - in.lo[0]));
-    const u32 Y = quantize(y, in.lo[1], g / (in.hi[1] - in.lo[1]));
-    const u32 Z = quantize(z, in.lo[2], g / (in.hi[2] - in.lo[2]));
+    const double g = (double)(1u << bits);
+    const u32 qmax = (1u << bits) - 1u;
+    const u32 X = quantize(x, in.lo[0], g / (in.hi[0] - in.lo[0]), qmax);
+    const u32 Y = quantize(y, in.lo[1], g / (in.hi[1] - in.lo[1]), qmax);
+    const u32 Z = quantize(z, in.lo[2], g / (in.hi[2] - in.lo[2]), qmax);
     return (spread3(X) << 2) | (spread3(Y) << 1) | spread3(Z);
 }
 
@@ -87,7 +90,7 @@ template <class T>
 __global__ void k_predict_morton(FieldPtrs<T> f, i64 n, const InstDev* __restrict__ inst,
                                  const i64* __restrict__ p_off, int ninst,
                                  const double* __restrict__ dt_inst, u64* __restrict__ keys,
-                                 u32* __restrict__ vals)
+                                 u32* __restrict__ vals, int bits)
 {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -106,7 +109,7 @@ __global__ void k_predict_morton(FieldPtrs<T> f, i64 n, const InstDev* __restric
     } else {
         x = f.x[ic]; y = f.y[ic]; z = f.z[ic];
     }
-    keys[i] = morton_key(x, y, z, in);
+    keys[i] = morton_key(x, y, z, in, bits);
     vals[i] = (u32)i;
 }
 
@@ -504,8 +507,10 @@ __device__ inline u32 compact3(u64 x)
 __global__ void k_prefix_boxes(const u64* __restrict__ mu_leaf, const i64* __restrict__ leaf_off,
                                const i64* __restrict__ ioff, int ninst, i64 n_internal, i64 n_leaf,
                                const u32* __restrict__ endrange, const u32* __restrict__ parent,
-                               u32* __restrict__ pbox, i32* __restrict__ plen)
+                               u32* __restrict__ pbox, i32* __restrict__ plen, int shift)
 {
+    // shorter codes (30 bits in the low bits) are read in the 63-bit layout:
+    // the code moved up by `shift` and its prefix lengths shortened by as much
     const i64 v = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n_internal + n_leaf) return;
     auto range_len = [&](i64 g) {
@@ -526,6 +531,8 @@ __global__ void k_prefix_boxes(const u64* __restrict__ mu_leaf, const i64* __res
         const u32 p = parent[v];
         len = (p == 0xffffffffu) ? 0 : range_len(p) + 1;
     }
+    if (len > 0) len -= shift;
+    code <<= shift;
     const u64 mask = (len >= 64) ? ~0ull : ~((~0ull) >> len);
     const u64 p0 = code & mask;
     const u64 p1 = p0 | (~mask & 0x7fffffffffffffffull);
@@ -649,11 +656,12 @@ void launch_bbox(const FieldPtrs<T>& f, i64 n, InstDev* inst, const i64* p_off, 
 // ------------------------------------------------------------ launchers ----
 template <class T>
 void launch_predict_morton(const FieldPtrs<T>& f, i64 n, const InstDev* inst, const i64* p_off,
-                           int ninst, const double* dt_inst, u64* keys, u32* vals, hipStream_t st)
+                           int ninst, const double* dt_inst, u64* keys, u32* vals, int bits,
+                           hipStream_t st)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL((k_predict_morton<T>), grid_for(n, 256), dim3(256), 0, st, f, n, inst, p_off,
-                       ninst, dt_inst, keys, vals);
+                       ninst, dt_inst, keys, vals, bits);
 }
 
 template <class T>
@@ -734,17 +742,17 @@ size_t boxes_rec_count(i64 n_leaf)
 
 void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
                          i64 n_internal, i64 n_leaf, const u32* endrange, const u32* parent,
-                         u32* pbox, i32* plen, hipStream_t st)
+                         u32* pbox, i32* plen, int shift, hipStream_t st)
 {
     const i64 nn = n_internal + n_leaf;
     if (nn <= 0) return;
     hipLaunchKernelGGL(k_prefix_boxes, grid_for(nn, 256), dim3(256), 0, st, mu_leaf, leaf_off, ioff,
-                       ninst, n_internal, n_leaf, endrange, parent, pbox, plen);
+                       ninst, n_internal, n_leaf, endrange, parent, pbox, plen, shift);
 }
 
 #define INST(T)                                                                                   \
     template void launch_predict_morton<T>(const FieldPtrs<T>&, i64, const InstDev*, const i64*,  \
-                                           int, const double*, u64*, u32*, hipStream_t);          \
+                                           int, const double*, u64*, u32*, int, hipStream_t);     \
     template void launch_gather<T>(const FieldPtrs<T>&, i64, const InstDev*, const i64*, int,     \
                                    const double*, const u32*, const SortedPtrs<T>&, hipStream_t); \
     template void launch_bbox<T>(const FieldPtrs<T>&, i64, InstDev*, const i64*, int,            \

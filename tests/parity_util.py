@@ -16,21 +16,21 @@ def box_for_oracle(p):
             (float(p.x.max()), float(p.y.max()), float(p.z.max())))
 
 
-def _oracle_tree(p, n_red):
+def _oracle_tree(p, n_red, key_bits=63):
     lo, hi = box_for_oracle(p)
-    keys = oracle.morton(p.x, p.y, p.z, lo, hi)
+    keys = oracle.morton(p.x, p.y, p.z, lo, hi, bits=key_bits // 3)
     eps, mu = oracle.sort(keys)
     xi, ids, ml = oracle.leaves(mu, n_red)
     t = oracle.radix_tree(ml)
     return keys, eps, mu, xi, ids, ml, t
 
 
-def check_tree(ctx, p, n_red, chi=1.1, r_kern=2.0):
+def check_tree(ctx, p, n_red, chi=1.1, r_kern=2.0, key_bits=63):
     """Every table of the GPU's last build against the oracle, bit for bit;
     the cache radius is r_kern chi max(h_a, h_b)."""
     T = p.x.dtype
     ex = ctx.export_tree(dtype=T)
-    keys, eps, mu, xi, ids, ml, t = _oracle_tree(p, n_red)
+    keys, eps, mu, xi, ids, ml, t = _oracle_tree(p, n_red, key_bits)
     assert np.array_equal(ex["keys"], keys), "Morton keys"
     assert np.array_equal(ex["eps"], eps), "sort permutation"
     assert np.array_equal(ex["mu"], mu)
@@ -45,7 +45,8 @@ def check_tree(ctx, p, n_red, chi=1.1, r_kern=2.0):
     assert np.array_equal(ex["bmin"].astype(np.float64), bmin), "tight box min"
     assert np.array_equal(ex["bmax"].astype(np.float64), bmax), "tight box max"
     assert np.array_equal(ex["hmax"].astype(np.float64), hmax), "h_max"
-    box, plen = oracle.prefix_boxes(ml, t)
+    # prefix boxes in the 63-bit layout (30-bit codes moved up by 33 bits)
+    box, plen = oracle.prefix_boxes(ml << np.uint64(63 - key_bits), t)
     assert np.array_equal(ex["pbox"], box) and np.array_equal(ex["plen"], plen), "prefix boxes"
     lo, hi = box_for_oracle(p)
     off, lst = oracle.neighbours(xs, ys, zs, hs, lo, hi, p.periodic, r_kern * chi)

@@ -140,7 +140,7 @@ def test_step_batch_vs_oracle(torch_cuda):
     _say("[batch] one fixed-dt step of 2 instances vs oracle step")
     ps = [_random_state(gen.lattice(12, 21, dtype=np.float32), 5, vscale=0.05, uvar=0.2),
           _random_state(gen.lattice(10, 22, dtype=np.float32), 6, vscale=0.05, uvar=0.2)]
-    ps[1].vy = (ps[1].vy - 0.5).astype(np.float32)      # a drift across the periodic faces
+    ps[1].vy = (ps[1].vy - 4.0).astype(np.float32)      # a drift across the periodic faces
     ctx = shsph.Context(0)
     hs = [ctx.instance_create(shsph.ParticleSet.from_particles(p)) for p in ps]
     ctx.eval_batch(hs)

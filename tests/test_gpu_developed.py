@@ -109,9 +109,18 @@ def _developed_step(ctx, ps, p, rows, sample, tag):
     _say(f"[{tag}] force of {len(sample)} particles")
     hg = s1["h"].astype(np.float64)
     rho_g = p.mass * (1.2 / hg) ** 3
-    vs = [s0[v][eps].astype(np.float64) + dt * s0[a][eps].astype(np.float64)
-          for v, a in (("vx", "ax"), ("vy", "ay"), ("vz", "az"))]
-    us = s0["u"][eps].astype(np.float64) + dt * s0["dudt"][eps].astype(np.float64)
+    # v*, u* exactly as the step's predictor forms them in the storage type
+    # (dt/2 a added twice, each operation rounded), so that the comparison
+    # measures the force kernel and not the rounding of its inputs
+    Tt = np.dtype(T).type
+    hdt = Tt(0.5) * Tt(dt)
+
+    def pred(x, a):
+        ka = hdt * a
+        return ((x + ka) + ka).astype(np.float64)
+
+    vs = [pred(s0[v][eps], s0[a][eps]) for v, a in (("vx", "ax"), ("vy", "ay"), ("vz", "az"))]
+    us = pred(s0["u"][eps], s0["dudt"][eps])
     ref = oracle.force(s1["x"], s1["y"], s1["z"], *vs, us, hg, rho_g,
                        s1["omega"].astype(np.float64), lo, hi, True, p.mass, targets=sample)
     gf = {k: s1[k][sample].astype(np.float64) for k in ("ax", "ay", "az", "dudt")}

@@ -73,6 +73,38 @@ def test_tree_and_cache_bit_exact(torch_cuda, name, make, n_red):
     ctx.close()
 
 
+def _nearly_sorted30(p):
+    """In the order of the 30-bit codes, with 200 neighbouring pairs swapped:
+    the input the sort's split / merge path takes."""
+    keys = oracle.morton(p.x, p.y, p.z, p.lo, p.hi, bits=10)
+    eps, _ = oracle.sort(keys)
+    q = p.subset(eps.astype(np.int64))
+    rng = np.random.default_rng(31)
+    for i in rng.choice(q.n - 1, size=200, replace=False):
+        for a in (q.x, q.y, q.z):
+            a[i], a[i + 1] = a[i + 1], a[i]
+    return q
+
+
+@pytest.mark.parametrize("name,make,n_red", [
+    ("lattice16_f32", lambda: gen.lattice(16, gen.SEEDS["tiny"], dtype=np.float32), 3),
+    ("plummer5000_f64", lambda: gen.plummer(5000, 6, dtype=np.float64), 3),
+    ("lattice48_f32_jitter_nred0", lambda: gen.lattice(48, 9, dtype=np.float32, jitter=0.35), 0),
+    ("lattice40_f32_nearly_sorted", lambda: _nearly_sorted30(gen.lattice(40, 10, dtype=np.float32)), 3),
+], ids=["lattice16_f32", "plummer5000_f64", "lattice48_f32_jitter_nred0", "lattice40_f32_nearly_sorted"])
+def test_tree_with_30bit_morton_codes(torch_cuda, name, make, n_red):
+    """key_bits = 30 (10 bits per axis, Sect. 5.2.1): keys, the four-pass
+    sort (and its nearly-sorted path on the sorted lattice), leaves, Karras
+    tables, boxes and the cache bit-exact against the oracle's 30-bit codes.
+    On the 48^3 lattice several particles share a cell: duplicates merge."""
+    _say(f"[tree] {name} with 30-bit Morton codes")
+    p = make()
+    ctx = _ctx(torch_cuda, n_red=n_red, key_bits=30)
+    ctx.build_tree(_upload(p, torch_cuda))
+    check_tree(ctx, p, n_red, key_bits=30)
+    ctx.close()
+
+
 @pytest.mark.parametrize("name,make,n_red", [
     ("plummer40000_f32", lambda: gen.plummer(40000, 4001, dtype=np.float32), 3),
     ("lattice16_f64", lambda: gen.lattice(16, gen.SEEDS["tiny"], dtype=np.float64), 3),
@@ -322,8 +354,9 @@ def test_step_vs_oracle(torch_cuda, T):
     the corrector reductions."""
     _say(f"[step] lattice12 {np.dtype(T).name}")
     p = _random_state(gen.lattice(12, 21, dtype=T), 5, vscale=0.05, uvar=0.2)
-    # a drift across the periodic faces, so that the wrap is exercised
-    p.vx = (p.vx + 0.4).astype(T)
+    # a drift across the periodic faces (several times the distance of the
+    # outermost lattice layer per step), so that the wrap is exercised
+    p.vx = (p.vx + 4.0).astype(T)
     ctx = _ctx(torch_cuda, eps_h=1e-6 if T == np.float32 else 1e-12)
     ps = _upload(p, torch_cuda)
     ctx.build_tree(ps)

@@ -413,3 +413,28 @@ def test_leaf_prefix_boxes_are_the_leaf_blocks():
         assert (g[sl] >= leaf[j, :3]).all() and (g[sl] <= leaf[j, 3:]).all()
     assert box[0].tolist() == [0, 0, 0, (1 << 21) - 1, (1 << 21) - 1, (1 << 21) - 1]
     assert plen[0] == 1            # only the unused top bit is common to all codes
+
+
+# ----------------------------------------------------- 30-bit Morton codes --
+def test_morton30_interleave_hand_values():
+    # 10 bits per axis, X the most significant of each triple (App. B.1), the
+    # 30-bit code in the low bits
+    assert oracle.interleave_bits(1 << 9, 0, 0, 10) == 1 << 29
+    assert oracle.interleave_bits(0, 1 << 9, 0, 10) == 1 << 28
+    assert oracle.interleave_bits(0, 0, 1 << 9, 10) == 1 << 27
+    assert oracle.interleave_bits(0, 0, 1, 10) == 1
+    assert oracle.interleave_bits(1023, 1023, 1023, 10) == (1 << 30) - 1
+
+
+def test_morton30_is_the_top_of_morton63():
+    """Quantising to 2^10 cells is quantising to 2^21 and dropping 11 bits
+    (scaling by powers of two is exact in FP64), so the 30-bit code is the
+    63-bit code shifted right by 33: the two definitions pin each other."""
+    rng = np.random.default_rng(23)
+    p = rng.uniform(0, 1, size=(5000, 3))
+    p[:7] = [[0, 0, 0], [1 - 2 ** -40, 0.5, 0.25], [1.0, 1.0, 1.0], [-0.1, 2.0, 0.5],
+             [2 ** -11, 2 ** -10, 2 ** -22], [0.5 - 2 ** -30, 0.5, 0.5], [0.75, 0.125, 0.999]]
+    k63 = oracle.morton(p[:, 0], p[:, 1], p[:, 2], (0, 0, 0), (1, 1, 1))
+    k30 = oracle.morton(p[:, 0], p[:, 1], p[:, 2], (0, 0, 0), (1, 1, 1), bits=10)
+    assert np.array_equal(k30, k63 >> np.uint64(33))
+    assert int(k30.max()) < (1 << 30)
