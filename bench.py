@@ -122,10 +122,13 @@ def make_input(name):
 
 
 def cpu_baseline(ps_host, p, args):
-    """The CPU oracle (FP64, OpenMP) on a bounded sample of the same workload:
-    density (h root) + force for S random target particles against all N,
-    timed at two sample sizes; the full-step time is extrapolated linearly
-    (slope per particle + the O(N) search-grid builds)."""
+    """The CPU oracle (FP64; its neighbour, density and force loops use OpenMP)
+    on a bounded sample of the same workload.  Tree half at full size: Morton
+    keys, stable sort, keep mask + reduction, radix tree and tight boxes of
+    all N particles.  Particle half on S random targets against all N:
+    neighbour sets, density (h root) and force, timed at two sample sizes and
+    extrapolated linearly (slope per particle + the O(N) search-grid builds).
+    The full step is the sum."""
     import numpy as np
     import oracle
     oracle.lib()
@@ -134,9 +137,20 @@ def cpu_baseline(ps_host, p, args):
     x, y, z = (ps_host[k].astype(np.float64) for k in ("x", "y", "z"))
     vx, vy, vz, u, h = (ps_host[k].astype(np.float64) for k in ("vx", "vy", "vz", "u", "h"))
 
+    def tree():
+        t0 = time.perf_counter()
+        keys = oracle.morton(x, y, z, p.lo, p.hi)
+        eps, mu = oracle.sort(keys)
+        _, ids, ml = oracle.leaves(mu, args.n_red)
+        t = oracle.radix_tree(ml)
+        oracle.tight_boxes(ids, t, x[eps], y[eps], z[eps], h[eps])
+        return time.perf_counter() - t0
+
     def run(S):
         t = np.sort(rng.choice(n, size=S, replace=False))
         t0 = time.perf_counter()
+        oracle.neighbours(ps_host["x"], ps_host["y"], ps_host["z"], ps_host["h"], p.lo, p.hi,
+                          p.periodic, 2.2, targets=t)
         hh, rho, om, _ = oracle.density(x, y, z, h, p.lo, p.hi, p.periodic, p.mass, targets=t)
         hfull = h.copy()
         hfull[t] = hh
@@ -147,14 +161,14 @@ def cpu_baseline(ps_host, p, args):
                      targets=t)
         return time.perf_counter() - t0
 
-    def rate(s1, s2):
+    def rate(s1, s2, t_tree):
         log(f"[cpu] oracle sample {s1} ({oracle.threads()} threads) ...")
         t1 = run(s1)
         log(f"[cpu] oracle sample {s2} ({oracle.threads()} threads) ...")
         t2 = run(s2)
         slope = max((t2 - t1) / (s2 - s1), 1e-12)
         overhead = max(t1 - slope * s1, 0.0)
-        return n / (slope * n + overhead), t1, t2
+        return n / (t_tree + slope * n + overhead), t1, t2
 
     cores = oracle.threads()
     cpu_model = "unknown"
@@ -166,18 +180,23 @@ def cpu_baseline(ps_host, p, args):
                     break
     except OSError:
         pass
+    log(f"[cpu] oracle tree half on all {n} particles ...")
+    t_tree = tree()
     s1, s2 = args.cpu_sample // 8, args.cpu_sample
-    v, t1, t2 = rate(s1, s2)
-    # one thread: a sample a quarter the size (the same extrapolation)
+    v, t1, t2 = rate(s1, s2, t_tree)
+    # one thread: a sample an eighth the size (the same extrapolation; the
+    # tree half is single-threaded already)
     oracle.set_threads(1)
-    v1, u1, u2 = rate(s1 // 4, s2 // 4)
+    v1, u1, u2 = rate(s1 // 8, s2 // 8, t_tree)
     oracle.set_threads(cores)
     return {"value": v, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
             "value_one_thread": v1, "cpu_model": cpu_model, "host_cpus": os.cpu_count(),
-            "sample": (f"{s2} and {s1} random particles of the {args.workload} state, FP64 "
-                       f"density (h root) + force against all {n}; full step extrapolated "
-                       f"({t1:.1f}s, {t2:.1f}s measured; one thread: {s2 // 4} and {s1 // 4} "
-                       f"particles, {u1:.1f}s, {u2:.1f}s)")}
+            "tree_half_s": t_tree,
+            "sample": (f"tree half (keys, sort, reduction, radix tree, boxes) of all {n} "
+                       f"particles of the {args.workload} state in {t_tree:.1f}s; neighbours, "
+                       f"density (h root) and force of {s2} and {s1} random particles against "
+                       f"all {n} ({t1:.1f}s, {t2:.1f}s; one thread: {s2 // 8} and {s1 // 8}, "
+                       f"{u1:.1f}s, {u2:.1f}s), extrapolated to all particles; FP64")}
 
 
 def run_lattice(args, shsph, torch, name="uniform128", steps=20, warmup=3):
@@ -306,7 +325,8 @@ def run_batched(args, shsph, torch):
     ctx = shsph.Context(0, n_red=args.n_red)
     hs = [ctx.instance_create(s) for s in sets]
     tune = ctx.autotune(hs)
-    log(f"[batched] autotuned: n_red {tune['n_red']}, stage-2 walk {tune['stage2_mode']}")
+    log(f"[batched] autotuned: n_red {tune['n_red']}, stage-2 walk {tune['stage2_mode']}, "
+        f"force split {tune['force_split']}")
     res["autotuned"] = tune
     for _ in range(W):
         ctx.step_batch(hs)
@@ -321,7 +341,8 @@ def run_batched(args, shsph, torch):
     ctx.set_profiling(False)
     ctx.close()
     log(f"[batched] batched {1e3 * tb / K:.2f} ms/step")
-    ctx = shsph.Context(0, n_red=tune["n_red"], stage2_mode=tune["stage2_mode"])
+    ctx = shsph.Context(0, n_red=tune["n_red"], stage2_mode=tune["stage2_mode"],
+                        force_split=tune["force_split"])
     hs = [ctx.instance_create(s) for s in sets]
     for _ in range(W):
         for h in hs:
@@ -370,7 +391,8 @@ def run_served(args, shsph, torch, tune=None):
     import numpy as np
     import gen
     kw = dict(n_red=args.n_red) if not tune else dict(n_red=tune["n_red"],
-                                                      stage2_mode=tune["stage2_mode"])
+                                                      stage2_mode=tune["stage2_mode"],
+                                                      force_split=tune["force_split"])
     log("[served] generating templates")
     tpl = serve_templates(gen.SEEDS["serve"])
     sets = {f: [shsph.ParticleSet.from_particles(p) for p in ps] for f, ps in tpl.items()}
@@ -481,7 +503,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sedov256", choices=sorted(WORKLOADS))
     ap.add_argument("--n-red", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=240000)
+    ap.add_argument("--cpu-sample", type=int, default=160000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batch run")
     ap.add_argument("--no-lattice", action="store_true", help="skip the 128^3 lattice run")
