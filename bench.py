@@ -326,7 +326,7 @@ def run_batched(args, shsph, torch):
     hs = [ctx.instance_create(s) for s in sets]
     tune = ctx.autotune(hs)
     log(f"[batched] autotuned: n_red {tune['n_red']}, stage-2 walk {tune['stage2_mode']}, "
-        f"force split {tune['force_split']}")
+        f"force split {tune.get('force_split', 2)}")
     res["autotuned"] = tune
     for _ in range(W):
         ctx.step_batch(hs)
@@ -342,7 +342,7 @@ def run_batched(args, shsph, torch):
     ctx.close()
     log(f"[batched] batched {1e3 * tb / K:.2f} ms/step")
     ctx = shsph.Context(0, n_red=tune["n_red"], stage2_mode=tune["stage2_mode"],
-                        force_split=tune["force_split"])
+                        force_split=tune.get("force_split", 2))
     hs = [ctx.instance_create(s) for s in sets]
     for _ in range(W):
         for h in hs:
@@ -392,7 +392,7 @@ def run_served(args, shsph, torch, tune=None):
     import gen
     kw = dict(n_red=args.n_red) if not tune else dict(n_red=tune["n_red"],
                                                       stage2_mode=tune["stage2_mode"],
-                                                      force_split=tune["force_split"])
+                                                      force_split=tune.get("force_split", 2))
     log("[served] generating templates")
     tpl = serve_templates(gen.SEEDS["serve"])
     sets = {f: [shsph.ParticleSet.from_particles(p) for p in ps] for f, ps in tpl.items()}
