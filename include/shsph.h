@@ -243,6 +243,27 @@ int shsph_force(shsph_ctx *ctx, shsph_particles *p);
  * (optional) receives the dt taken.  Errors as for the calls above. */
 int shsph_step(shsph_ctx *ctx, shsph_particles *p, double dt, double *dt_used);
 
+/* shsph_step without device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as shsph_step, bit for
+ * bit.  All device working memory of the call (keys, tree, caches, sorted
+ * fields, reductions) comes from one static array per device of 128 MiB,
+ * held by that device from the library's first use until the process ends;
+ * its address is taken once per device by shsph_create.  Nothing is
+ * allocated or freed by the call (it makes no hipMalloc, hipFree or
+ * allocating library call); it waits for its stream before returning.
+ * Limits: n <= 131072 particles (ECAPACITY beyond, with nothing enqueued);
+ * a step whose neighbour caches outgrow the array (far more than ~100
+ * neighbours per particle) also fails with ECAPACITY.  The array is shared
+ * by every call on its device and keeps the last call's contents: calls
+ * that overlap on one device (other contexts, other threads, other streams)
+ * race and must be serialised by the caller.  A CFL step (dt <= 0) takes
+ * the CFL dt of this context's previous shsph_step_noalloc (kept on the
+ * host, so other users of the array in between do not disturb it);
+ * ESTATE if there is none.  State of shsph_build_tree / _density / _force /
+ * _step on the same context is neither used nor changed. */
+int shsph_step_noalloc(shsph_ctx *ctx, shsph_particles *p, double dt, double *dt_used);
+
 /* Counters of the last build / density / force / step. */
 int shsph_get_info(shsph_ctx *ctx, shsph_info *out);
 

@@ -138,6 +138,7 @@ def lib():
     for fn in ("shsph_build_tree", "shsph_density", "shsph_force"):
         getattr(L, fn).argtypes = [vp, C.POINTER(CParticles)]
     L.shsph_step.argtypes = [vp, C.POINTER(CParticles), C.c_double, C.POINTER(C.c_double)]
+    L.shsph_step_noalloc.argtypes = [vp, C.POINTER(CParticles), C.c_double, C.POINTER(C.c_double)]
     L.shsph_get_info.argtypes = [vp, C.POINTER(Info)]
     L.shsph_export_tree.argtypes = [vp, C.POINTER(TreeExport)]
     L.shsph_set_profiling.argtypes = [vp, ip]
@@ -309,6 +310,15 @@ class Context:
         used = C.c_double(0.0)
         self._check(self.L.shsph_step(self.h, C.byref(self._cp), float(dt),
                                       C.byref(used) if want_dt else None))
+        return used.value if want_dt else None
+
+    def step_noalloc(self, ps: ParticleSet, dt: float = 0.0, want_dt: bool = False):
+        """shsph_step_noalloc: the step with all device working memory in the
+        library's static per-device scratch array (no allocation)."""
+        self._cp = ps.cstruct()
+        used = C.c_double(0.0)
+        self._check(self.L.shsph_step_noalloc(self.h, C.byref(self._cp), float(dt),
+                                              C.byref(used) if want_dt else None))
         return used.value if want_dt else None
 
     def get_info(self) -> dict:

@@ -121,6 +121,17 @@ struct shsph_ctx {
     int64_t next_handle = 1;
     std::recursive_mutex mu;                    // one API call at a time on this context
     void* server = nullptr;                     // serving loop (serve.cpp), if started
+
+    // shsph_step_noalloc runs on a second context (`sc`) whose device buffers
+    // are all carved, by a bump pointer reset at every call, from the
+    // device's static scratch array (`arena`); it shares the pinned staging
+    // area and upload event of its parent and keeps its per-instance
+    // reductions (the CFL dt of its last step) on the host between calls.
+    shsph_ctx* sc = nullptr;
+    char* arena = nullptr;
+    size_t arena_used = 0;
+    InstStat stat_keep{};
+    bool stat_kept = false;
 };
 
 namespace {
@@ -154,11 +165,48 @@ int fail(shsph_ctx* c, int code, const std::string& msg)
         if (r_ != SHSPH_OK) return r_;                                                   \
     } while (0)
 
-// Make `b` hold at least `bytes`; grows by 25 % beyond the request.
+// Working memory of shsph_step_noalloc: one static array per device, its
+// address taken once per device at context creation.
+constexpr size_t SCRATCH_BYTES = (size_t)128 << 20;
+constexpr int64_t SCRATCH_MAX_N = (int64_t)1 << 17;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+std::mutex scratch_mu;
+std::map<int, char*> scratch_addr;          // device -> its copy of `scratch`
+
+// Address of `scratch` on `device` (the current device), or nullptr.
+char* scratch_on(int device)
+{
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    auto it = scratch_addr.find(device);
+    if (it != scratch_addr.end()) return it->second;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+        (void)hipGetLastError();
+        ptr = nullptr;
+    }
+    scratch_addr[device] = (char*)ptr;
+    return (char*)ptr;
+}
+
+// Make `b` hold at least `bytes`; grows by 25 % beyond the request.  On a
+// context with an arena the bytes come from the arena (exactly, 256-byte
+// aligned) and nothing is allocated; an arena that cannot hold them is a
+// capacity error.
 int ensure(shsph_ctx* c, Buf& b, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
     if (b.cap >= bytes) return SHSPH_OK;
+    if (c->arena) {
+        const size_t off = (c->arena_used + 255) & ~(size_t)255;
+        const size_t want = (bytes + 255) & ~(size_t)255;
+        if (off + want > SCRATCH_BYTES)
+            return fail(c, SHSPH_ECAPACITY, "the static scratch array (" +
+                        std::to_string(SCRATCH_BYTES >> 20) + " MiB) cannot hold this step's working memory");
+        b.p = c->arena + off;
+        b.cap = want;
+        c->arena_used = off + want;
+        return SHSPH_OK;
+    }
     if (b.p) {
         HIPTRY(c, hipStreamSynchronize(c->stream));
         HIPTRY(c, hipFree(b.p));
@@ -323,11 +371,12 @@ int upload_instances(shsph_ctx* c)
 }
 
 // Upload `bytes` from host memory to device through the pinned upload area,
-// after the instance tables (same wait rule).
-int upload_extra(shsph_ctx* c, void* dst, const void* src, size_t bytes)
+// after the instance tables (same wait rule), `at` bytes further on (uploads
+// enqueued without a wait between them use different `at`).
+int upload_extra(shsph_ctx* c, void* dst, const void* src, size_t bytes, size_t at = 0)
 {
     const int k = c->ninst;
-    const size_t off = k * sizeof(InstDev) + 2 * (k + 1) * sizeof(i64);
+    const size_t off = k * sizeof(InstDev) + 2 * (k + 1) * sizeof(i64) + at;
     if (off + bytes > UPLOAD_BYTES) return fail(c, SHSPH_EINVAL, "upload area too small");
     char* up = (char*)c->pinned + PINNED_BYTES + off;
     memcpy(up, src, bytes);
@@ -800,9 +849,11 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
     // dt for this step: caller's value, else the CFL dt of the last force pass
     if (!(dt > 0) && c->state != ST_FORCE)
         return fail(c, SHSPH_ESTATE, "dt <= 0 needs a preceding force evaluation (CFL dt)");
-    const bool keep_stat = c->stat_d.p && c->ninst == 1;
+    const bool keep_stat = (c->arena ? c->stat_kept : c->stat_d.p != nullptr) && c->ninst == 1;
     TRY(set_single_instance(c, p));
     if (!keep_stat && !(dt > 0)) return fail(c, SHSPH_ESTATE, "no CFL dt available");
+    if (c->arena && keep_stat)   // the reductions of this context's last step
+        TRY(upload_extra(c, c->stat_d.p, &c->stat_keep, sizeof(InstStat), 256));
     // a CFL step takes the CFL multiplier (encoded as -lambda)
     const double dt_req = dt > 0 ? dt : -c->lambda_cfl;
     TRY(upload_extra(c, c->dt_host_d.p, &dt_req, sizeof(double)));
@@ -1223,6 +1274,13 @@ int shsph_create(int device, const shsph_params* p, shsph_ctx** out)
         return SHSPH_EHIP;
     }
     c->stream = nullptr;
+    // the allocation-free step's context: buffers in this device's scratch
+    // array, staging shared with this context
+    c->sc = new shsph_ctx();
+    c->sc->device = device;
+    c->sc->pinned = c->pinned;
+    c->sc->up_done = c->up_done;
+    c->sc->arena = scratch_on(device);
     *out = c;
     return SHSPH_OK;
 }
@@ -1237,6 +1295,7 @@ int shsph_destroy(shsph_ctx* c)
     if (c->up_done) hipEventDestroy(c->up_done);
     for (Buf* b : all_bufs(c))
         if (b->p) hipFree(b->p);
+    delete c->sc;                 // its buffers live in the scratch array, its staging is ours
     if (c->pinned) hipHostFree(c->pinned);
     for (hipEvent_t e : c->prof.ev) hipEventDestroy(e);
     delete c;
@@ -1316,6 +1375,47 @@ int shsph_step(shsph_ctx* c, shsph_particles* p, double dt, double* dt_used)
     HIPTRY(c, hipSetDevice(c->device));
     return p->dtype == SHSPH_F32 ? do_step<float>(c, p, dt, dt_used)
                                  : do_step<double>(c, p, dt, dt_used);
+}
+
+int shsph_step_noalloc(shsph_ctx* c, shsph_particles* p, double dt, double* dt_used)
+{
+    if (!c) return SHSPH_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->err.clear();
+    shsph_ctx* s = c->sc;
+    if (!s || !s->arena) return fail(c, SHSPH_EHIP, "the static scratch array is not available on this device");
+    TRY(validate(c, p, true, true));
+    if (!std::isfinite(dt)) return fail(c, SHSPH_EINVAL, "dt must be finite");
+    if (p->n > SCRATCH_MAX_N)
+        return fail(c, SHSPH_ECAPACITY, "shsph_step_noalloc takes at most " +
+                    std::to_string(SCRATCH_MAX_N) + " particles (n = " + std::to_string(p->n) + ")");
+    HIPTRY(c, hipSetDevice(c->device));
+    s->prm = c->prm;
+    s->stream = c->stream;
+    s->err.clear();
+    // every buffer is laid out afresh in the array for this call
+    for (Buf* b : all_bufs(s)) { b->p = nullptr; b->cap = 0; }
+    s->arena_used = 0;
+    int rc = p->dtype == SHSPH_F32 ? do_step<float>(s, p, dt, dt_used)
+                                   : do_step<double>(s, p, dt, dt_used);
+    if (rc == SHSPH_OK) {
+        // keep this step's reductions (its CFL dt) for the next call, and
+        // leave no work of this call running on the array
+        if (s->parts_pending > 0) {
+            launch_fold_parts(P<BlockPart>(s->bpart), s->parts_pending, s->ninst,
+                              P<InstStat>(s->stat_d), s->stream);
+            s->parts_pending = 0;
+        }
+        rc = read_back(s, s->stat_d.p, sizeof(InstStat));
+        if (rc == SHSPH_OK) memcpy(&s->stat_keep, s->pinned, sizeof(InstStat));
+    }
+    s->stat_kept = rc == SHSPH_OK;
+    if (rc != SHSPH_OK) {
+        s->state = ST_NONE;
+        (void)hipStreamSynchronize(s->stream);
+        c->err = s->err;
+    }
+    return rc;
 }
 
 int shsph_set_profiling(shsph_ctx* c, int on)
