@@ -326,7 +326,7 @@ def run_batched(args, shsph, torch):
     hs = [ctx.instance_create(s) for s in sets]
     tune = ctx.autotune(hs)
     log(f"[batched] autotuned: n_red {tune['n_red']}, stage-2 walk {tune['stage2_mode']}, "
-        f"force split {tune.get('force_split', 2)}")
+        f"force split {tune['force_split']}, fused density+force {tune['fused_density_force']}")
     res["autotuned"] = tune
     for _ in range(W):
         ctx.step_batch(hs)
@@ -342,7 +342,8 @@ def run_batched(args, shsph, torch):
     ctx.close()
     log(f"[batched] batched {1e3 * tb / K:.2f} ms/step")
     ctx = shsph.Context(0, n_red=tune["n_red"], stage2_mode=tune["stage2_mode"],
-                        force_split=tune.get("force_split", 2))
+                        force_split=tune["force_split"],
+                        fused_density_force=tune["fused_density_force"])
     hs = [ctx.instance_create(s) for s in sets]
     for _ in range(W):
         for h in hs:
@@ -392,7 +393,8 @@ def run_served(args, shsph, torch, tune=None):
     import gen
     kw = dict(n_red=args.n_red) if not tune else dict(n_red=tune["n_red"],
                                                       stage2_mode=tune["stage2_mode"],
-                                                      force_split=tune.get("force_split", 2))
+                                                      force_split=tune["force_split"],
+                        fused_density_force=tune["fused_density_force"])
     log("[served] generating templates")
     tpl = serve_templates(gen.SEEDS["serve"])
     sets = {f: [shsph.ParticleSet.from_particles(p) for p in ps] for f, ps in tpl.items()}
@@ -603,7 +605,8 @@ def main():
         "config": {"workload": args.workload, "particles": p.n, "kernel": "M4", "hfact": 1.2,
                    "n_red": args.n_red, "dt": "cfl", "periodic": p.periodic,
                    "neighbours_per_particle": info["n_neigh"] / p.n,
-                   "leaves": info["n_leaf"]},
+                   "leaves": info["n_leaf"],
+                   "cache_capacity_entries": info["cache_capacity"]},
         "roofline": roof,
         "step_hbm": {"algorithmic_bytes_per_step": int(step_bytes),
                      "GBs": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),

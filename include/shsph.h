@@ -97,6 +97,19 @@ typedef struct {
                                eps_v > 0 and a CFL dt) */
     double alpha_min, alpha_max;  /* bounds of the switch (0, 1) */
     double sigma_decay;     /* decay time tau = h / (sigma_decay c_s) (0.1) */
+    int32_t force_split;    /* threads per particle in the force kernel: 1 (workgroups
+                               of 256 threads) or 2 (512; default), each summing its
+                               share of the particle's list, combined in a fixed
+                               order.  Work, not results (the sums' rounding order
+                               follows the split).  Chosen by shsph_autotune. */
+    int32_t fused_density_force;  /* 1: the h iteration and the force run in one
+                               persistent cooperative launch (as many workgroups as
+                               the device holds, the grid synchronised between the
+                               two; one thread per particle in the force), falling
+                               back to the separate kernels when a cache rebuild is
+                               needed, the alpha switch is on, or the launch is not
+                               possible.  Same results as force_split = 1.
+                               Default 0; shsph_autotune may choose it. */
 } shsph_params;
 
 #define SHSPH_KERNEL_M4 0
@@ -148,7 +161,8 @@ typedef struct {
     double dv2_sum;          /* sum |dv|^2 */
     double v2_sum;           /* sum |v^{n+1}|^2 */
     int32_t reruns;          /* corrector re-runs of the last step (App. G.1) */
-    int32_t pad;
+    int32_t cache_capacity;  /* neighbour-cache entries per particle the context holds
+                                room for (grows when a build needs more) */
     double cfl_multiplier;   /* CFL multiplier for the next CFL step (App. G) */
 } shsph_info;
 
@@ -273,7 +287,7 @@ int shsph_export_tree(shsph_ctx *ctx, const shsph_tree_export *out);
 /* Optional per-stage timing: with `on`, every stage of the calls above is
  * bracketed by HIP events on the context's stream and the calls wait for
  * them at their end.  Turning it on (or off) clears the totals. */
-#define SHSPH_NUM_STAGES 11
+#define SHSPH_NUM_STAGES 12
 int shsph_set_profiling(shsph_ctx *ctx, int on);
 
 /* Totals since profiling was turned on: ms[i] = summed event time of stage i,
@@ -340,11 +354,16 @@ int shsph_eval_batch(shsph_ctx *ctx, const int64_t *handles, int32_t count);
 
 /* Autotuner for batched passes: times evaluation passes of the listed
  * instances (as shsph_eval_batch: positions, velocities and u unchanged) for
- * leaf sizes n_red = 2, 3, 4 and stage-2 walks 0, 1, 2, and keeps the fastest
- * in the context's parameters for later passes.  Neither changes results.
- * Outputs (optional): the chosen n_red and walk, and its pass time in ms. */
+ * leaf sizes n_red = 2, 3, 4, stage-2 walks 0, 1, 2 and three shapes of the
+ * derivative kernels: the fused persistent density + force launch, or
+ * separate launches with force workgroups of 256 or 512 threads
+ * (force_split 1, 2), and keeps the fastest in the context's parameters for
+ * later passes.  The leaf size and the walk change no result; the force
+ * split changes only the rounding order of the force sums.  Outputs
+ * (optional): the chosen n_red, walk and force shape (0 = fused, else the
+ * force split), and the pass time in ms. */
 int shsph_autotune(shsph_ctx *ctx, const int64_t *handles, int32_t count, int32_t *n_red,
-                   int32_t *stage2_mode, double *pass_ms);
+                   int32_t *stage2_mode, int32_t *force_split, double *pass_ms);
 
 /* Pool occupancy: particles held by instances, pool capacity, instances. */
 int shsph_pool_usage(shsph_ctx *ctx, int64_t *particles_used, int64_t *particles_cap,

@@ -27,7 +27,7 @@ SHSPH_ECAPACITY, SHSPH_EHIP, SHSPH_ESTATE = -4, -5, -6
 ERRORS = {SHSPH_EINVAL: "EINVAL", SHSPH_ENOMEM: "ENOMEM", SHSPH_ENOCONV: "ENOCONV",
           SHSPH_ECAPACITY: "ECAPACITY", SHSPH_EHIP: "EHIP", SHSPH_ESTATE: "ESTATE"}
 F32, F64 = 0, 1
-NUM_STAGES = 11
+NUM_STAGES = 12
 
 
 class ShsphError(RuntimeError):
@@ -46,7 +46,8 @@ class Params(C.Structure):
                 ("kernel", C.c_int32), ("key_bits", C.c_int32), ("eps_v", C.c_double),
                 ("max_reruns", C.c_int32), ("alpha_switch", C.c_int32),
                 ("lambda_stiff", C.c_double), ("alpha_min", C.c_double),
-                ("alpha_max", C.c_double), ("sigma_decay", C.c_double)]
+                ("alpha_max", C.c_double), ("sigma_decay", C.c_double),
+                ("force_split", C.c_int32), ("fused_density_force", C.c_int32)]
 
 
 KERNELS = {"M4": 0, "M5": 1, "M6": 2, "C2": 3, "C4": 4, "C6": 5}
@@ -66,7 +67,8 @@ class Info(C.Structure):
                 ("n_neigh", C.c_int64), ("n_red", C.c_int32), ("restarts", C.c_int32),
                 ("max_iter_seen", C.c_int32), ("n_noconv", C.c_int32), ("dt_cfl", C.c_double),
                 ("dv_max", C.c_double), ("dv2_sum", C.c_double), ("v2_sum", C.c_double),
-                ("reruns", C.c_int32), ("pad", C.c_int32), ("cfl_multiplier", C.c_double)]
+                ("reruns", C.c_int32), ("cache_capacity", C.c_int32),
+                ("cfl_multiplier", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -154,7 +156,8 @@ def lib():
     L.shsph_step_batch.argtypes = [vp, i64p, C.c_int32, dp, dp]
     L.shsph_eval_batch.argtypes = [vp, i64p, C.c_int32]
     L.shsph_pool_usage.argtypes = [vp, i64p, i64p, i64p]
-    L.shsph_autotune.argtypes = [vp, i64p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
+    L.shsph_autotune.argtypes = [vp, i64p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32), dp]
     L.shsph_serve_start.argtypes = [vp, C.POINTER(ServeConfig)]
     L.shsph_submit.argtypes = [vp, C.POINTER(Job), C.POINTER(C.c_uint64)]
     L.shsph_poll.argtypes = [vp, C.c_uint64, C.POINTER(JobStatus)]
@@ -250,6 +253,19 @@ class ParticleSet:
         return out
 
 
+def _apply(params: Params, kw: dict) -> None:
+    """Set fields of a Params from keyword arguments (kernel by name or id);
+    an unknown name is an error."""
+    names = {f for f, _ in Params._fields_}
+    for k, v in kw.items():
+        if k == "kernel" and isinstance(v, str):
+            v = KERNELS[v]
+        f = "lambda_" if k == "lambda" else k
+        if f not in names:
+            raise TypeError(f"unknown parameter {k!r}")
+        setattr(params, f, v)
+
+
 class Context:
     """A shsph context bound to one device and (by default) torch's current stream."""
 
@@ -257,10 +273,7 @@ class Context:
         L = lib()
         if params is None:
             params = default_params()
-        for k, v in kw.items():
-            if k == "kernel" and isinstance(v, str):
-                v = KERNELS[v]
-            setattr(params, "lambda_" if k == "lambda" else k, v)
+        _apply(params, kw)
         self.params = params
         h = C.c_void_p()
         rc = L.shsph_create(int(device), C.byref(params), C.byref(h))
@@ -282,10 +295,7 @@ class Context:
         """Change parameters of the context (shsph_set_params)."""
         p = Params()
         self._check(self.L.shsph_get_params(self.h, C.byref(p)))
-        for k, v in kw.items():
-            if k == "kernel" and isinstance(v, str):
-                v = KERNELS[v]
-            setattr(p, "lambda_" if k == "lambda" else k, v)
+        _apply(p, kw)
         self._check(self.L.shsph_set_params(self.h, C.byref(p)))
         self.params = p
 
@@ -411,12 +421,17 @@ class Context:
         self._check(self.L.shsph_eval_batch(self.h, arr, len(hs)), allow)
 
     def autotune(self, handles) -> dict:
-        """Pick leaf size (n_red) and stage-2 walk for batched passes of these instances."""
+        """Pick leaf size (n_red), stage-2 walk and the force kernel's
+        workgroup size (force_split) for batched passes of these instances."""
         hs, arr = self._handles(handles)
-        nr, md, ms = C.c_int32(), C.c_int32(), C.c_double()
-        self._check(self.L.shsph_autotune(self.h, arr, len(hs), C.byref(nr), C.byref(md), C.byref(ms)))
+        nr, md, fs, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        self._check(self.L.shsph_autotune(self.h, arr, len(hs), C.byref(nr), C.byref(md),
+                                          C.byref(fs), C.byref(ms)))
         self.params.n_red, self.params.stage2_mode = nr.value, md.value
-        return dict(n_red=nr.value, stage2_mode=md.value, pass_ms=ms.value)
+        self.params.force_split = fs.value if fs.value else 1
+        self.params.fused_density_force = 0 if fs.value else 1
+        return dict(n_red=nr.value, stage2_mode=md.value, force_split=self.params.force_split,
+                    fused_density_force=self.params.fused_density_force, pass_ms=ms.value)
 
     def pool_usage(self) -> dict:
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()

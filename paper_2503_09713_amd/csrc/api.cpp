@@ -29,11 +29,11 @@ enum State { ST_NONE = 0, ST_TREE = 1, ST_DENSITY = 2, ST_FORCE = 3 };
 // Stages timed by the optional HIP-event profiler (one entry per launch group).
 enum Stage {
     S_MORTON, S_SORT, S_GATHER, S_LEAVES, S_KARRAS, S_BOXES, S_STAGE1, S_STAGE2, S_DENSITY,
-    S_FORCE, S_CORRECT, S_NUM
+    S_FORCE, S_CORRECT, S_DENSITY_FORCE, S_NUM
 };
 const char* const STAGE_NAMES[S_NUM] = {
     "predict_morton", "radix_sort", "gather", "mask_reduce_compact", "karras", "boxes",
-    "group_leaf_cache", "particle_cache", "density", "force", "correct"
+    "group_leaf_cache", "particle_cache", "density", "force", "correct", "density_force"
 };
 
 // A pooled instance: its fields live at [off, off + n) of the pool arrays.
@@ -81,7 +81,11 @@ struct shsph_ctx {
     i64 n = 0;
     int ninst = 0;
     i64 n_leaf = 0, n_internal = 0, n_groups = 0;
-    i64 cap_leaf = 256, cap_words = 28;         // per-group leaves, per-particle cache words (4 entries)
+    i64 cap_leaf = 256;                         // per-group union leaves (stage 1)
+    // stage-2 cache: capacity per group (words of 4 entries per lane), planned
+    // each build from the need of the previous one (valid for gneed_groups)
+    i64 gneed_groups = -1;
+    u64 cache_words = 0;                        // words laid out by the last build
     int state = ST_NONE;
     int restarts = 0;
     int vals_sel = 0;       // which value buffer holds eps after the sort
@@ -94,11 +98,12 @@ struct shsph_ctx {
     Buf keys[2], vals[2], hist, scan_tmp, bbox;          // hist: radix sort state
     Buf posh, velu, vhalf, hn, hcache, pid_s, thermo, omega, acc, vsig, status;
     Buf alpha_s;                                // viscosity alpha in key order (switch)
-    Buf xi[2], xscan, id, mu_leaf;
+    Buf xi[2], xscan, id, mu_leaf, lvstate;     // lvstate: fused leaf pass (ticket + look-back)
     Buf lchild, rchild, endrange, lflag, rflag, child, parent, arrive, blo, bhi;
     Buf rec, nrec, rscan;                       // bottom-up box records
     Buf glo, ghi, uleaf, uslot, ucnt, ustot;    // stage 1, per group
     Buf nlist, ncnt, flags;                     // stage 2, per particle (ELL)
+    Buf gcap, gbase, gneed, gredo;              // stage 2, per group capacity / layout
     Buf bpart;                                  // corrector partial sums
     Buf work[3];                                // work counters (profiling)
     i64 parts_pending = 0;                      // corrector blocks not yet folded
@@ -138,8 +143,11 @@ namespace {
 
 const size_t PINNED_BYTES = 1 << 20;      // read-back staging
 // device flag words: 0..3 tree traversal / cache capacity (reset per cache
-// build), FLAG_SORT = radix sort look-back overrun
-constexpr int FLAG_WORDS = 8, FLAG_SORT = 4;
+// build), FLAG_SORT = radix sort look-back overrun, FLAG_LEAVES (+1) = fused
+// leaf pass unresolved tile (look-back overrun)
+constexpr int FLAG_WORDS = 8, FLAG_SORT = 4, FLAG_LEAVES = 5;
+// stage-2 capacity of a group without history: 32 words of 4 entries per lane
+constexpr u32 CACHE_WORDS0 = 32;
 const size_t UPLOAD_BYTES = 1 << 20;      // upload staging (instance tables), after it
 const int MAX_BATCH = 2048;           // instances per batched pass (stats fit the staging)
 
@@ -221,6 +229,23 @@ int ensure(shsph_ctx* c, Buf& b, size_t bytes)
         return fail(c, SHSPH_ENOMEM, "device memory exhausted (" + std::to_string(want >> 20) + " MiB)");
     }
     b.cap = want;
+    return SHSPH_OK;
+}
+
+// Grow `b` to at least `bytes` keeping its first `keep` bytes.
+int ensure_keep(shsph_ctx* c, Buf& b, size_t bytes, size_t keep)
+{
+    if (b.cap >= bytes) return SHSPH_OK;
+    Buf nb;
+    TRY(ensure(c, nb, bytes));
+    if (b.p && keep) {
+        HIPTRY(c, hipMemcpyAsync(nb.p, b.p, std::min(keep, b.cap), hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (b.p && !c->arena) {
+        HIPTRY(c, hipStreamSynchronize(c->stream));
+        HIPTRY(c, hipFree(b.p));
+    }
+    b = nb;
     return SHSPH_OK;
 }
 
@@ -311,6 +336,7 @@ SphParams sph_params(const shsph_params& q)
     s.kernel = q.kernel;
     s.r_kern = kernel_support(q.kernel);
     s.alpha_min = q.alpha_min; s.alpha_max = q.alpha_max; s.sigma_decay = q.sigma_decay;
+    s.force_split = q.force_split;
     return s;
 }
 
@@ -429,7 +455,7 @@ CacheView cache_view(shsph_ctx* c)
     v.ucnt = P<u32>(c->ucnt); v.ustot = P<u32>(c->ustot);
     v.cap = c->cap_leaf;
     v.nlist = P<u64>(c->nlist); v.ncnt = P<u32>(c->ncnt);
-    v.capq = (u32)c->cap_words;
+    v.gbase = P<u64>(c->gbase);
     v.glo = c->glo.p; v.ghi = c->ghi.p; v.blo = c->blo.p;
     v.root = P<u32>(c->root_d);
     v.rk = kernel_support(c->prm.kernel) * c->prm.chi;
@@ -502,20 +528,40 @@ template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const d
     launch_gather<T>(f, n, inst, poff, ninst, dt_dev, eps, s, st);
     prof_end(c);
     TRY(check_launch(c, "gather"));
-    // keep mask, reduction passes (double-buffered), compaction
+    // keep mask, reduction passes, scan and compaction: one kernel that runs
+    // the passes tile by tile in LDS; the separate passes (double-buffered
+    // mask) only when some tile could not be resolved within its window
     prof_begin(c, S_LEAVES);
-    launch_mask_init(mu, n, poff, ninst, P<u8>(c->xi[0]), st);
-    int xs = 0;
-    for (int r = 0; r < nred; ++r) {
-        launch_reduce_pass(mu, n, poff, ninst, P<u8>(c->xi[xs]), P<u8>(c->xi[xs ^ 1]), st);
-        xs ^= 1;
-    }
-    c->xi_sel = xs;
-    scan_u8_u32(P<u8>(c->xi[xs]), P<u32>(c->xscan), n, c->scan_tmp.p, st);
-    launch_compact(mu, P<u8>(c->xi[xs]), P<u32>(c->xscan), n, P<u32>(c->id), P<u64>(c->mu_leaf), st);
+    TRY(ensure(c, c->lvstate, leaves_fused_state_words(n) * sizeof(u32)));
+    launch_fill_u32(P<u32>(c->flags) + FLAG_LEAVES, 2, 0u, st);
+    launch_leaves_fused(mu, n, poff, ninst, nred, P<u32>(c->lvstate), P<u8>(c->xi[0]),
+                        P<u32>(c->xscan), P<u32>(c->id), P<u64>(c->mu_leaf),
+                        P<u32>(c->flags) + FLAG_LEAVES, st);
+    c->xi_sel = 0;
     prof_end(c);
-    TRY(check_launch(c, "compact"));
-    TRY(read_back(c, P<u32>(c->xscan) + n, sizeof(u32)));
+    TRY(check_launch(c, "leaves"));
+    HIPTRY(c, hipMemcpyAsync(c->pinned, P<u32>(c->xscan) + n, sizeof(u32), hipMemcpyDeviceToHost, st));
+    HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 8, P<u32>(c->flags) + FLAG_LEAVES, 2 * sizeof(u32),
+                             hipMemcpyDeviceToHost, st));
+    HIPTRY(c, hipStreamSynchronize(st));
+    u32 lvf[2];
+    memcpy(lvf, (char*)c->pinned + 8, sizeof(lvf));
+    if (lvf[1]) return fail(c, SHSPH_EHIP, "leaf pass: a look-back wait ran past its bound");
+    if (lvf[0]) {
+        prof_begin(c, S_LEAVES);
+        launch_mask_init(mu, n, poff, ninst, P<u8>(c->xi[0]), st);
+        int xs = 0;
+        for (int r = 0; r < nred; ++r) {
+            launch_reduce_pass(mu, n, poff, ninst, P<u8>(c->xi[xs]), P<u8>(c->xi[xs ^ 1]), st);
+            xs ^= 1;
+        }
+        c->xi_sel = xs;
+        scan_u8_u32(P<u8>(c->xi[xs]), P<u32>(c->xscan), n, c->scan_tmp.p, st);
+        launch_compact(mu, P<u8>(c->xi[xs]), P<u32>(c->xscan), n, P<u32>(c->id), P<u64>(c->mu_leaf), st);
+        prof_end(c);
+        TRY(check_launch(c, "compact"));
+        TRY(read_back(c, P<u32>(c->xscan) + n, sizeof(u32)));
+    }
     const i64 nl = *(u32*)c->pinned;
     c->n_leaf = nl;
     c->n_internal = nl - ninst;
@@ -582,12 +628,18 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
     launch_group_boxes<T>(posh, gm, G, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), st);
     prof_end(c);
     TRY(check_launch(c, "boxes"));
+    TRY(ensure(c, c->gcap, G * sizeof(u32)));
+    TRY(ensure(c, c->gbase, (G + 1) * sizeof(u64)));
+    TRY(ensure(c, c->gneed, G * sizeof(u32)));
+    TRY(ensure(c, c->gredo, G));
+    const size_t WORD_BYTES = (size_t)GROUP * sizeof(u64);    // one word of every lane of a group
     bool run_stage1 = true;
+    bool plan = redo == nullptr;     // a rebuild of some instances keeps the others' layout
+    const u8* gredo = nullptr;       // regrow retry: only the groups that overflowed
     for (int attempt = 0;; ++attempt) {
         // stage 1: neighbour leaves of each group
         TRY(ensure(c, c->uleaf, (size_t)G * c->cap_leaf * sizeof(u32)));
         TRY(ensure(c, c->uslot, (size_t)G * c->cap_leaf * sizeof(u32)));
-        TRY(ensure(c, c->nlist, (size_t)G * c->cap_words * GROUP * sizeof(u64)));
         if (run_stage1) {
         prof_begin(c, S_STAGE1);
         launch_group_leaves<T>(P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child),
@@ -600,13 +652,25 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
         prof_end(c);
         TRY(check_launch(c, "stage1"));
         }
-        // stage 2: particle neighbours as union slots
+        // stage-2 capacities: each group's need in the previous build (same
+        // groups) or a default, never above its union; laid out by a scan
+        if (plan) {
+            const bool hist = c->gneed_groups == G;
+            launch_cache_plan(P<u32>(c->ustot), hist ? P<u32>(c->gneed) : nullptr, G, CACHE_WORDS0,
+                              P<u32>(c->gcap), P<u64>(c->gbase), c->scan_tmp.p, st);
+            if (!c->nlist.p)    // first build: room for the default capacity
+                TRY(ensure(c, c->nlist, (size_t)G * CACHE_WORDS0 * WORD_BYTES));
+            plan = false;
+        }
+        // stage 2: particle neighbours as union slots (a layout larger than
+        // the buffer is flagged, nothing written)
         prof_begin(c, S_STAGE2);
         launch_group_cache<T>(posh, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->id),
                               P<u32>(c->xscan), ni, gm, G,
                               inst, rk, rk, c->cap_leaf, P<u32>(c->uleaf), P<u32>(c->uslot),
-                              P<u32>(c->ucnt), P<u32>(c->ustot), (u32)c->cap_words, P<u64>(c->nlist),
-                              P<u32>(c->ncnt), P<u32>(c->flags), P<vec4<T>>(c->glo),
+                              P<u32>(c->ucnt), P<u32>(c->ustot), P<u64>(c->gbase), P<u32>(c->gcap),
+                              (u64)(c->nlist.cap / WORD_BYTES), P<u32>(c->gneed), gredo,
+                              P<u64>(c->nlist), P<u32>(c->ncnt), P<u32>(c->flags), P<vec4<T>>(c->glo),
                               P<vec4<T>>(c->ghi), P<u32>(c->root_d), work_ptr(c, 0),
                               c->prm.stage2_mode, attempt ? nullptr : redo, st);
         prof_end(c);
@@ -616,9 +680,14 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
                                  hipMemcpyDeviceToHost, st));
         HIPTRY(c, hipMemcpyAsync((char*)c->pinned + FLAG_WORDS * sizeof(u32), c->rhmax_d.p,
                                  ninst * sizeof(double), hipMemcpyDeviceToHost, st));
+        const size_t tot_at = FLAG_WORDS * sizeof(u32) + ninst * sizeof(double);
+        HIPTRY(c, hipMemcpyAsync((char*)c->pinned + tot_at, P<u64>(c->gbase) + G, sizeof(u64),
+                                 hipMemcpyDeviceToHost, st));
         HIPTRY(c, hipStreamSynchronize(st));
         u32 fl[FLAG_WORDS];
         memcpy(fl, c->pinned, sizeof(fl));
+        u64 words = 0;
+        memcpy(&words, (char*)c->pinned + tot_at, sizeof(u64));
         if (fl[FLAG_SORT]) {
             launch_fill_u32(P<u32>(c->flags) + FLAG_SORT, 1, 0u, st);
             return fail(c, SHSPH_EHIP, "radix sort: a look-back wait ran past its bound");
@@ -637,21 +706,51 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
                     return fail(c, SHSPH_EINVAL, "periodic box smaller than twice the cache radius" +
                                 (ninst > 1 ? " (batch instance " + std::to_string(k) + ")" : std::string()));
         }
-        if (!(fl[0] & 6u)) break;
-        if (attempt >= 4) return fail(c, SHSPH_ECAPACITY, "neighbour cache capacity");
-        // capacities only grow, with half again as much room as the largest
-        // request seen, so that a run settles after few regrows; when only the
-        // particle cache overflowed, stage 1's lists are still valid
-        run_stage1 = (fl[0] & 2u) != 0;
-        if (fl[0] & 2u) c->cap_leaf = std::max<i64>(c->cap_leaf, (i64)fl[1] + fl[1] / 2 + 16);
-        if (fl[0] & 4u) c->cap_words = std::max<i64>(c->cap_words, ((i64)fl[2] + fl[2] / 2 + 8 + 3) / 4);
+        if (!(fl[0] & 38u)) {
+            c->gneed_groups = G;
+            c->cache_words = words;
+            break;
+        }
+        if (attempt >= 6) return fail(c, SHSPH_ECAPACITY, "neighbour cache capacity");
         launch_fill_u32(P<u32>(c->flags), 4, 0u, st);
+        gredo = nullptr;
+        if (fl[0] & 2u) {
+            // stage 1 overflowed: half again the largest request, then stage 1
+            // and a fresh plan for every group
+            c->cap_leaf = std::max<i64>(c->cap_leaf, (i64)fl[1] + fl[1] / 2 + 16);
+            run_stage1 = true;
+            plan = redo == nullptr;
+            continue;
+        }
+        run_stage1 = false;
+        if (fl[0] & 32u) {
+            // the planned layout did not fit the buffer: grow it (nothing was
+            // written) and run stage 2 again
+            TRY(ensure(c, c->nlist, (size_t)(words + words / 4 + G) * WORD_BYTES));
+            continue;
+        }
+        // some groups outgrew their capacity: they get a larger range at the
+        // end of the layout and only they run stage 2 again (the others keep
+        // what they wrote)
+        launch_cache_regrow(P<u32>(c->gneed), G, P<u32>(c->gcap), P<u64>(c->gbase), P<u8>(c->gredo), st);
+        TRY(read_back(c, P<u64>(c->gbase) + G, sizeof(u64)));
+        memcpy(&words, c->pinned, sizeof(u64));
+        TRY(ensure_keep(c, c->nlist, (size_t)(words + words / 8) * WORD_BYTES, c->nlist.cap));
+        gredo = P<u8>(c->gredo);
     }
     return SHSPH_OK;
 }
 
 // Density / h iteration with cache rebuilds while some h leaves chi h_cache.
-template <class T> int run_density(shsph_ctx* c, bool with_thermo)
+// `force` (optional): the first pass runs density and force in one
+// persistent launch (k_density_force); *force_done tells whether that force
+// stands (no particle left chi h_cache), else the caller runs the force.
+template <class T> struct FusedForce {
+    vec4<T>* acc;
+    bool* done;
+};
+
+template <class T> int run_density(shsph_ctx* c, bool with_thermo, const FusedForce<T>* force = nullptr)
 {
     hipStream_t st = c->stream;
     const i64 n = c->n;
@@ -661,6 +760,7 @@ template <class T> int run_density(shsph_ctx* c, bool with_thermo)
     const SphParams sp = sph_params(c->prm);
     SortedPtrs<T> s = sorted<T>(c, false);
     if (!with_thermo) s.velu = nullptr;
+    if (force) *force->done = false;
     // Instances whose h all settled keep their result; only those with a
     // particle past chi h_cache iterate again on the rebuilt caches, so an
     // instance gets the same h whatever else shares the pass.
@@ -668,15 +768,30 @@ template <class T> int run_density(shsph_ctx* c, bool with_thermo)
     std::vector<u8> redo(ninst, 1);
     for (int attempt = 0;; ++attempt) {
         const u8* rd = attempt ? P<u8>(c->redo_d) : nullptr;
-        launch_stat_reset(P<InstStat>(c->stat_d), ninst, 1, rd, st);
-        prof_begin(c, S_DENSITY);
         CacheView cvd = cache_view(c);
         cvd.work = work_ptr(c, 1);
-        launch_density<T>(s, P<u32>(c->id), group_map(c), c->n_groups, P<InstDev>(c->inst_d), sp,
-                          cvd, P<T>(c->omega),
-                          with_thermo ? P<vec4<T>>(c->thermo) : nullptr, P<u8>(c->status),
-                          P<InstStat>(c->stat_d), rd, st);
-        prof_end(c);
+        bool fused = false;
+        if (attempt == 0 && force && with_thermo) {
+            launch_stat_reset(P<InstStat>(c->stat_d), ninst, 3, nullptr, st);
+            CacheView cvf = cache_view(c);
+            cvf.work = work_ptr(c, 2);
+            prof_begin(c, S_DENSITY_FORCE);
+            fused = launch_density_force<T>(s, P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
+                                            c->n_groups, ninst, P<InstDev>(c->inst_d), sp, cvd, cvf,
+                                            P<T>(c->omega), P<u8>(c->status), P<InstStat>(c->stat_d),
+                                            force->acc, nullptr, st) == 0;
+            prof_end(c);
+            if (!fused) (void)hipGetLastError();
+        }
+        if (!fused) {
+            launch_stat_reset(P<InstStat>(c->stat_d), ninst, 1, rd, st);
+            prof_begin(c, S_DENSITY);
+            launch_density<T>(s, P<u32>(c->id), group_map(c), c->n_groups, P<InstDev>(c->inst_d), sp,
+                              cvd, P<T>(c->omega),
+                              with_thermo ? P<vec4<T>>(c->thermo) : nullptr, P<u8>(c->status),
+                              P<InstStat>(c->stat_d), rd, st);
+            prof_end(c);
+        }
         TRY(check_launch(c, "density"));
         TRY(read_back(c, c->stat_d.p, ninst * sizeof(InstStat)));
         const InstStat* hs = (const InstStat*)c->pinned;
@@ -687,6 +802,7 @@ template <class T> int run_density(shsph_ctx* c, bool with_thermo)
             nc += hs[k].n_noconv;
         }
         if (ex == 0) {
+            if (fused) *force->done = true;
             if (nc) return fail(c, SHSPH_ENOCONV, "h iteration did not converge for " + std::to_string(nc) + " particles");
             return SHSPH_OK;
         }
@@ -874,7 +990,10 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
         launch_gather_velu<T>(eps, n, (const T*)p->ax, (const T*)p->ay, (const T*)p->az,
                               (const T*)p->dudt, P<vec4<T>>(c->acc), st);
     }
-    int rc = run_density<T>(c, true);
+    // with the alpha switch the force needs alpha^{n+1} first: no fusion
+    bool fdone = false;
+    const FusedForce<T> ff{P<vec4<T>>(c->acc), &fdone};
+    int rc = run_density<T>(c, true, (c->prm.fused_density_force && !sw) ? &ff : nullptr);
     if (rc != SHSPH_OK) return rc;
     if (sw) {   // alpha^{n+1} from v*, grad v*, grad a^n; alpha c staged for the force
         launch_alpha<T>(sorted<T>(c, true), P<vec4<T>>(c->acc), P<T>(c->omega), P<u32>(c->id),
@@ -882,17 +1001,19 @@ template <class T> int do_step(shsph_ctx* c, shsph_particles* p, double dt, doub
                         cache_view(c), dt_dev, P<T>(c->alpha_s), P<vec4<T>>(c->thermo), st);
         TRY(check_launch(c, "alpha switch"));
     }
-    launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, 2, nullptr, st);
     c->parts_pending = 0;
     const SphParams sp = sph_params(c->prm);
-    prof_begin(c, S_FORCE);
-    CacheView cvf = cache_view(c);
-    cvf.work = work_ptr(c, 2);
-    launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
-                    c->n_groups, P<InstDev>(c->inst_d), sp, cvf, P<vec4<T>>(c->acc),
-                    nullptr, P<InstStat>(c->stat_d), st);
-    prof_end(c);
-    TRY(check_launch(c, "force"));
+    if (!fdone) {
+        launch_stat_reset(P<InstStat>(c->stat_d), c->ninst, 2, nullptr, st);
+        prof_begin(c, S_FORCE);
+        CacheView cvf = cache_view(c);
+        cvf.work = work_ptr(c, 2);
+        launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
+                        c->n_groups, P<InstDev>(c->inst_d), sp, cvf, P<vec4<T>>(c->acc),
+                        nullptr, P<InstStat>(c->stat_d), st);
+        prof_end(c);
+        TRY(check_launch(c, "force"));
+    }
     OutPtrs<T> o;
     o.x = (T*)p->x; o.y = (T*)p->y; o.z = (T*)p->z;
     o.vx = (T*)p->vx; o.vy = (T*)p->vy; o.vz = (T*)p->vz;
@@ -1073,20 +1194,24 @@ template <class T> int batch_pass(shsph_ctx* c, const std::vector<Inst*>& b, con
     launch_stat_reset(P<InstStat>(c->stat_d), ninst, 3, nullptr, st);
     const double* dt_dev = P<double>(c->dt_inst_d);
     TRY(build<T>(c, pool_fields<T>(c), off, dt_dev, true));
-    const int rc = run_density<T>(c, true);
-    if (rc != SHSPH_OK && rc != SHSPH_ENOCONV) return rc;
     const i64 n = c->n;
     TRY(ensure(c, c->acc, n * sizeof(vec4<T>)));
-    launch_stat_reset(P<InstStat>(c->stat_d), ninst, 2, nullptr, st);
+    bool fdone = false;
+    const FusedForce<T> ff{P<vec4<T>>(c->acc), &fdone};
+    const int rc = run_density<T>(c, true, c->prm.fused_density_force ? &ff : nullptr);
+    if (rc != SHSPH_OK && rc != SHSPH_ENOCONV) return rc;
     const SphParams sp = sph_params(c->prm);
-    prof_begin(c, S_FORCE);
-    CacheView cvf = cache_view(c);
-    cvf.work = work_ptr(c, 2);
-    launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
-                    c->n_groups, P<InstDev>(c->inst_d), sp, cvf, P<vec4<T>>(c->acc), nullptr,
-                    P<InstStat>(c->stat_d), st);
-    prof_end(c);
-    TRY(check_launch(c, "force"));
+    if (!fdone) {
+        launch_stat_reset(P<InstStat>(c->stat_d), ninst, 2, nullptr, st);
+        prof_begin(c, S_FORCE);
+        CacheView cvf = cache_view(c);
+        cvf.work = work_ptr(c, 2);
+        launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
+                        c->n_groups, P<InstDev>(c->inst_d), sp, cvf, P<vec4<T>>(c->acc), nullptr,
+                        P<InstStat>(c->stat_d), st);
+        prof_end(c);
+        TRY(check_launch(c, "force"));
+    }
     const i64 nb = (n + GROUP - 1) / GROUP;
     TRY(ensure(c, c->bpart, nb * sizeof(BlockPart)));
     prof_begin(c, S_CORRECT);
@@ -1219,6 +1344,8 @@ void shsph_params_default(shsph_params* p)
     p->alpha_min = 0.0;
     p->alpha_max = 1.0;
     p->sigma_decay = 0.1;
+    p->force_split = 2;
+    p->fused_density_force = 0;
 }
 
 // Every device buffer of a context.
@@ -1234,7 +1361,7 @@ static std::vector<Buf*> all_bufs(shsph_ctx* c)
              &c->goff_d, &c->leaf_off_d, &c->ioff_d, &c->root_d, &c->stat_d,
              &c->dt_inst_d, &c->dt_host_d, &c->pbox, &c->plen, &c->xoff, &c->xlist,
              &c->bpart, &c->work[0], &c->work[1], &c->work[2], &c->redo_d, &c->rhmax_d,
-             &c->alpha_s };
+             &c->alpha_s, &c->lvstate, &c->gcap, &c->gbase, &c->gneed, &c->gredo };
 }
 
 // Parameter ranges accepted by shsph_create and shsph_set_params.
@@ -1246,7 +1373,9 @@ static bool params_valid(const shsph_params& q)
              q.kernel < 0 || q.kernel >= KERNEL_COUNT ||
              (q.key_bits != 63 && q.key_bits != 30) || !(q.eps_v >= 0) ||
              q.max_reruns < 0 || !(q.lambda_stiff >= 0) || !(q.sigma_decay > 0) ||
-             !(q.alpha_min >= 0) || !(q.alpha_max >= q.alpha_min));
+             !(q.alpha_min >= 0) || !(q.alpha_max >= q.alpha_min) ||
+             (q.force_split != 1 && q.force_split != 2) ||
+             (q.fused_density_force != 0 && q.fused_density_force != 1));
 }
 
 int shsph_create(int device, const shsph_params* p, shsph_ctx** out)
@@ -1393,9 +1522,11 @@ int shsph_step_noalloc(shsph_ctx* c, shsph_particles* p, double dt, double* dt_u
     s->prm = c->prm;
     s->stream = c->stream;
     s->err.clear();
-    // every buffer is laid out afresh in the array for this call
+    // every buffer is laid out afresh in the array for this call; device
+    // contents of earlier calls (the cache capacity history) are not kept
     for (Buf* b : all_bufs(s)) { b->p = nullptr; b->cap = 0; }
     s->arena_used = 0;
+    s->gneed_groups = -1;
     int rc = p->dtype == SHSPH_F32 ? do_step<float>(s, p, dt, dt_used)
                                    : do_step<double>(s, p, dt, dt_used);
     if (rc == SHSPH_OK) {
@@ -1474,6 +1605,7 @@ int shsph_get_info(shsph_ctx* c, shsph_info* o)
     o->n_red = c->prm.n_red;
     o->restarts = c->restarts;
     o->reruns = c->reruns_last;
+    o->cache_capacity = c->n > 0 ? (int32_t)(4 * c->cache_words * GROUP / c->n) : 0;
     o->cfl_multiplier = c->lambda_cfl;
     HIPTRY(c, hipSetDevice(c->device));
     if (c->state >= ST_TREE) {
@@ -1587,7 +1719,7 @@ int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
         total = *(u64*)c->pinned;
         TRY(ensure(c, c->xlist, std::max<u64>(total, 1) * sizeof(u32)));
         launch_cache_to_global(P<u32>(c->id), group_map(c), G, c->cap_leaf, P<u32>(c->uleaf),
-                               P<u32>(c->uslot), P<u32>(c->ucnt), (u32)c->cap_words, P<u64>(c->nlist),
+                               P<u32>(c->uslot), P<u32>(c->ucnt), P<u64>(c->gbase), P<u64>(c->nlist),
                                P<u32>(c->ncnt), P<u64>(c->xoff), P<u32>(c->xlist), st);
         TRY(check_launch(c, "cache export"));
         TRY(cp(o->neigh_off, c->xoff.p, (n + 1) * 8));
@@ -1773,7 +1905,7 @@ int shsph_pool_usage(shsph_ctx* c, int64_t* particles_used, int64_t* particles_c
 // Autotuner for batched passes: leaf size (n_red) x stage-2 walk, timed on
 // evaluation passes of the given instances; the fastest is kept.
 int shsph_autotune(shsph_ctx* c, const int64_t* handles, int32_t count, int32_t* n_red_out,
-                   int32_t* mode_out, double* ms_out)
+                   int32_t* mode_out, int32_t* split_out, double* ms_out)
 {
     if (!c) return SHSPH_EINVAL;
     std::lock_guard<std::recursive_mutex> lk(c->mu);
@@ -1784,26 +1916,33 @@ int shsph_autotune(shsph_ctx* c, const int64_t* handles, int32_t count, int32_t*
     const std::vector<double> zero(count, 0.0);
     const shsph_params keep = c->prm;
     double best = 1e300;
-    int best_nr = keep.n_red, best_md = keep.stage2_mode;
+    int best_nr = keep.n_red, best_md = keep.stage2_mode, best_fs = keep.force_split;
     for (int nr = 2; nr <= 4; ++nr) {
         for (int md = 0; md <= 2; ++md) {
-            c->prm.n_red = nr;
-            c->prm.stage2_mode = md;
-            double t = 0;
-            for (int rep = 0; rep < 2; ++rep) {          // the first pass sizes buffers
-                const auto t0 = std::chrono::steady_clock::now();
-                const int rc = run_pass(c, b, zero);
-                if (rc != SHSPH_OK && rc != SHSPH_ENOCONV) { c->prm = keep; return rc; }
-                t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            for (int fs = 0; fs <= 2; ++fs) {     // 0: the fused density + force launch
+                c->prm.n_red = nr;
+                c->prm.stage2_mode = md;
+                c->prm.force_split = fs ? fs : 1;
+                c->prm.fused_density_force = fs ? 0 : 1;
+                double t = 0;
+                for (int rep = 0; rep < 2; ++rep) {      // the first pass sizes buffers
+                    const auto t0 = std::chrono::steady_clock::now();
+                    const int rc = run_pass(c, b, zero);
+                    if (rc != SHSPH_OK && rc != SHSPH_ENOCONV) { c->prm = keep; return rc; }
+                    t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                }
+                if (t < best) { best = t; best_nr = nr; best_md = md; best_fs = fs; }
             }
-            if (t < best) { best = t; best_nr = nr; best_md = md; }
         }
     }
     c->prm = keep;
     c->prm.n_red = best_nr;
     c->prm.stage2_mode = best_md;
+    c->prm.force_split = best_fs ? best_fs : 1;
+    c->prm.fused_density_force = best_fs ? 0 : 1;
     if (n_red_out) *n_red_out = best_nr;
     if (mode_out) *mode_out = best_md;
+    if (split_out) *split_out = best_fs;
     if (ms_out) *ms_out = best;
     return SHSPH_OK;
 }

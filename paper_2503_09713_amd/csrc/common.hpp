@@ -75,6 +75,7 @@ struct GroupMap {
     const i64* p_off;   // ninst+1: first particle of each instance
     int ninst;
     __device__ int inst_of(i64 g) const { return find_seg(goff, ninst, g); }
+    __device__ i64 ngroups_total() const { return goff[ninst]; }
     __device__ void range(i64 g, i64& beg, i64& end, int& k) const
     {
         k = inst_of(g);

@@ -39,14 +39,14 @@ template <class T> struct OutPtrs {
 // The group neighbour cache: per group, its union of neighbour leaves
 // (uleaf, with the union slot where each leaf starts, uslot; ucnt leaves,
 // ustot slots; capacity cap per group), and per particle its neighbours as
-// 16-bit union slots, four per word, ELL layout
-// nlist[(g * capq + j / 4) * GROUP + lane]; ncnt[a] of them.
+// 16-bit union slots, four per word, ELL layout with a capacity per group:
+// nlist[(gbase[g] + j / 4) * GROUP + lane]; ncnt[a] of them.
 struct CacheView {
     const u32 *uleaf, *uslot, *ucnt, *ustot;
     i64 cap;
     const u64* nlist;
     const u32* ncnt;
-    u32 capq;
+    const u64* gbase;         // first word of each group (words of GROUP lanes)
     const void *glo, *ghi;    // group boxes (vec4<T>) for the interior test
     const void* blo;          // node boxes: h_max of each instance's root
     const u32* root;
@@ -67,6 +67,7 @@ struct SphParams {
     int max_iter;
     int kernel;             // KernelId (Sect. 2.1.1)
     double alpha_min, alpha_max, sigma_decay;   // shock-detection switch (App. G)
+    int force_split;        // threads per particle in the force kernel (1 or 2)
 };
 
 // scan.hip
@@ -94,6 +95,13 @@ void launch_bbox(const FieldPtrs<T>& f, i64 n, InstDev* inst, const i64* p_off, 
 void launch_mask_init(const u64* mu, i64 n, const i64* p_off, int ninst, u8* xi, hipStream_t st);
 void launch_reduce_pass(const u64* mu, i64 n, const i64* p_off, int ninst, const u8* xold, u8* xnew,
                         hipStream_t st);
+// Keep mask + nred reduction passes + scan + compaction in one kernel; `state`
+// holds leaves_fused_state_words(n) words (cleared here); flag[0] is set if
+// some tile could not be resolved in its window (then nothing it wrote is
+// valid: run the separate passes), flag[1] on a look-back overrun.
+size_t leaves_fused_state_words(i64 n);
+void launch_leaves_fused(const u64* mu, i64 n, const i64* p_off, int ninst, int nred, u32* state,
+                         u8* xi, u32* xscan, u32* id, u64* mu_leaf, u32* flag, hipStream_t st);
 void launch_compact(const u64* mu, const u8* xi, const u32* xscan, i64 n, u32* id, u64* mu_leaf,
                     hipStream_t st);
 void launch_inst_leaves(const i64* p_off, int ninst, const u32* xscan, i64 n, i64* leaf_off,
@@ -126,11 +134,23 @@ template <class T>
 void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* bhi, const u32* id,
                         const u32* xscan, i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
-                        const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
+                        const u32* ucnt, const u32* ustot, const u64* gbase, const u32* gcap,
+                        u64 words_alloc, u32* gneed, const u8* gredo, u64* nlist, u32* ncnt,
                         u32* flags, const vec4<T>* glo, const vec4<T>* ghi, const u32* root,
                         u64* work, int mode, const u8* redo, hipStream_t st);
+// Per-group cache capacities (words per lane) for a build: from the need the
+// group showed in the previous build (gneed, words; 0 = none yet: `dflt`),
+// with a quarter's headroom, never above what the group's union could fill;
+// gbase = exclusive scan of the capacities (gbase[ngroups] = total words).
+void launch_cache_plan(const u32* ustot, const u32* gneed, i64 ngroups, u32 dflt, u32* gcap,
+                       u64* gbase, void* scan_tmp, hipStream_t st);
+// After an overflow: groups whose need exceeds their capacity get a larger
+// range appended at the end (gbase[ngroups] grows) and gredo = 1; the others
+// keep theirs (gredo = 0).
+void launch_cache_regrow(const u32* gneed, i64 ngroups, u32* gcap, u64* gbase, u8* gredo,
+                         hipStream_t st);
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
-                            const u32* uleaf, const u32* uslot, const u32* ucnt, u32 capq,
+                            const u32* uleaf, const u32* uslot, const u32* ucnt, const u64* gbase,
                             const u64* nlist, const u32* ncnt, const u64* off, u32* list,
                             hipStream_t st);
 
@@ -147,6 +167,14 @@ template <class T>
 void launch_density(const SortedPtrs<T>& s, const u32* id, const GroupMap& gm, i64 ngroups,
                     const InstDev* inst, const SphParams& P, const CacheView& cv, T* omega,
                     vec4<T>* thermo, u8* status, InstStat* stat, const u8* redo, hipStream_t st);
+// Density then force in one persistent cooperative launch (see sph.hip);
+// the force runs only if no particle left chi h_cache.  Returns 0, or -1 if
+// the launch was not possible (the caller then runs the separate kernels).
+template <class T>
+int launch_density_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id,
+                         const GroupMap& gm, i64 ngroups, int ninst, const InstDev* inst,
+                         const SphParams& P, const CacheView& cvd, const CacheView& cvf, T* omega,
+                         u8* status, InstStat* stat, vec4<T>* acc, T* vsig, hipStream_t st);
 template <class T>
 void launch_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id, const GroupMap& gm,
                   i64 ngroups, const InstDev* inst, const SphParams& P, const CacheView& cv,

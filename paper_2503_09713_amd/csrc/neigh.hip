@@ -467,8 +467,24 @@ __device__ inline bool cache_acc(const vec4<T>& pa, T qa, const Box<T>& bx, cons
 // a completed ELL word (the first four entries) is copied to the cache and
 // the rest moves to the front; groups of eight candidates complete up to two
 // words.  At most 3 entries are pending before a group and 11 after it.
+// A lane's queue starts 28 bytes after the previous lane's: an odd number of
+// 4-byte LDS banks, so the lanes' writes at equal fill positions fall in
+// distinct banks.  The queues are then only 4-byte aligned, and their words
+// are moved as two 32-bit halves.
 constexpr u32 QLEN = 12;
-constexpr u32 QSTRIDE = QLEN; // u16 per lane (24 B, 8-byte aligned)
+constexpr u32 QSTRIDE = 14;   // u16 per lane (28 B)
+
+__device__ inline u64 q_ld(const u16* p)
+{
+    const u32* q = (const u32*)p;
+    return (u64)q[0] | ((u64)q[1] << 32);
+}
+__device__ inline void q_st(u16* p, u64 v)
+{
+    u32* q = (u32*)p;
+    q[0] = (u32)v;
+    q[1] = (u32)(v >> 32);
+}
 
 struct LaneQueue {
     u16* e;       // this lane's entries in LDS
@@ -486,11 +502,11 @@ __device__ inline void queue_put(LaneQueue& lq, u32 s, bool acc)
 __device__ inline void queue_flush(LaneQueue& lq, u32 capq)
 {
     if (lq.pos >= 4u) {
-        const u64 w = *(const u64*)lq.e;
+        const u64 w = q_ld(lq.e);
         if (lq.q < capq) *lq.out = w;
         lq.out += GROUP;
         ++lq.q;
-        *(u64*)lq.e = *(const u64*)(lq.e + 4);
+        q_st(lq.e, q_ld(lq.e + 4));
         lq.pos -= 4u;
     }
 }
@@ -499,11 +515,11 @@ __device__ inline void queue_flush(LaneQueue& lq, u32 capq)
 __device__ inline void queue_flush2(LaneQueue& lq, u32 capq)
 {
     if (lq.pos >= 4u) {
-        if (lq.q < capq) *lq.out = *(const u64*)lq.e;
+        if (lq.q < capq) *lq.out = q_ld(lq.e);
         lq.out += GROUP;
         ++lq.q;
-        *(u64*)lq.e = *(const u64*)(lq.e + 4);
-        *(u64*)(lq.e + 4) = *(const u64*)(lq.e + 8);
+        q_st(lq.e, q_ld(lq.e + 4));
+        q_st(lq.e + 4, q_ld(lq.e + 8));
         lq.pos -= 4u;
         queue_flush(lq, capq);
     }
@@ -633,7 +649,7 @@ __device__ inline void queue_append(LaneQueue& lq, u32 s, u32 capq)
 {
     lq.e[lq.pos] = (u16)s;
     if (++lq.pos == 4u) {
-        const u64 w = *(const u64*)lq.e;
+        const u64 w = q_ld(lq.e);
         if (lq.q < capq) *lq.out = w;
         lq.out += GROUP;
         ++lq.q;
@@ -716,7 +732,9 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
               const u32* __restrict__ xscan, i64 n_internal, const GroupMap gm,
               const InstDev* __restrict__ inst, T rk, T rkc, i64 cap,
               const u32* __restrict__ uleaf, const u32* __restrict__ uslot,
-              const u32* __restrict__ ucnt, const u32* __restrict__ ustot, u32 capq,
+              const u32* __restrict__ ucnt, const u32* __restrict__ ustot,
+              const u64* __restrict__ gbase, const u32* __restrict__ gcap, u64 words_alloc,
+              u32* __restrict__ gneed, const u8* __restrict__ gredo,
               u64* __restrict__ nlist, u32* __restrict__ ncnt, u32* __restrict__ flags,
               const vec4<T>* __restrict__ glo, const vec4<T>* __restrict__ ghi,
               const u32* __restrict__ root, u64* __restrict__ work, const u8* __restrict__ redo)
@@ -744,6 +762,12 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     int k;
     gm.range(g, beg, end, k);
     if (redo && !redo[k]) return;             // this instance keeps its caches (block-uniform)
+    if (gredo && !gredo[g]) return;           // this group's cache fitted (regrow retry)
+    if (gbase[gm.ngroups_total()] > words_alloc) {   // the planned layout does not fit
+        if (threadIdx.x == 0) atomicOr(&flags[0], 32u);
+        return;
+    }
+    const u32 capq = gcap[g];
     const Box<T> bx = make_box<T>(inst[k]);
     const T eps_abs = abs_inflation(bx);
     const i64 a = beg + threadIdx.x;
@@ -782,7 +806,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         const T r = rkc * pa.w;
         qa = q_clean(r * r);
     }
-    u64* out = nlist + (u64)g * capq * GROUP + threadIdx.x;
+    u64* out = nlist + gbase[g] * GROUP + threadIdx.x;
     u32 tested = 0;
     u64 wbuf = 0, boxtests = 0;   // wbuf: the queue's pending entries between chunks
     LaneQueue lq{(u16*)s_tbox + threadIdx.x * QSTRIDE, 0u, 0u, out};
@@ -850,7 +874,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
             }
             uniform = 10u * all < 14u * wave_max(mine);
         }
-        if (lq.pos) *(u64*)lq.e = wbuf;   // pending entries
+        if (lq.pos) q_st(lq.e, wbuf);   // pending entries
         if (mode != 1 && uniform) {
             if (in_lds && interior)
                 cache_walk_wave<T, true, false>(pa, qa, live, bx, rkc, wm, s_b0, s_b1, s_slot,
@@ -876,7 +900,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
                 cache_walk_lane<T, false, true>(pa, qa, live, S, nu, bx, rkc, s_mask[ta], s_b0, s_b1,
                                                 s_slot, s_lo, s_hi, s_upos, posh, lq, capq, tested);
         }
-        wbuf = lq.pos ? *(const u64*)lq.e : 0ull;
+        wbuf = lq.pos ? q_ld(lq.e) : 0ull;
     }
     const u32 c = 4u * lq.q + lq.pos;
     if (live) {
@@ -894,11 +918,44 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
             atomicAdd((unsigned long long*)&work[2 * (g & 63) + 1], (unsigned long long)boxtests);
         }
     }
-    const u32 wmax = wave_max(live ? c : 0u);
-    if (__lane_id() == 0) {
-        if (wmax > 4u * capq) atomicOr(&flags[0], 4u);
-        if (wmax > __hip_atomic_load(&flags[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            atomicMax(&flags[2], wmax);
+    // the group's need in words (for the next build's plan and a regrow)
+    const u32 wmax = block_reduce<GROUP>(live ? (c + 3u) >> 2 : 0u, (u32*)s_w,
+                                         [](u32 x, u32 y) { return x > y ? x : y; });
+    if (threadIdx.x == 0) {
+        gneed[g] = wmax;
+        if (wmax > capq) atomicOr(&flags[0], 4u);
+        if (4u * wmax > __hip_atomic_load(&flags[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&flags[2], 4u * wmax);
+    }
+}
+
+// Capacity plan of a build (see kernels.hpp): one thread per group.
+__global__ void k_cache_plan(const u32* __restrict__ ustot, const u32* __restrict__ gneed,
+                             i64 ngroups, u32 dflt, u32* __restrict__ gcap)
+{
+    const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngroups) return;
+    const u32 need = gneed ? gneed[g] : 0u;
+    u32 w = need ? need + need / 4u + 2u : dflt;
+    const u32 top = (ustot[g] + 3u) / 4u + 1u;     // a lane holds at most the union
+    gcap[g] = w < top ? w : top;
+}
+
+// Regrow after an overflow: one thread per group; ranges appended in any
+// order (the layout is free, the contents are not affected).
+__global__ void k_cache_regrow(const u32* __restrict__ gneed, i64 ngroups, u32* __restrict__ gcap,
+                               u64* __restrict__ gbase, u8* __restrict__ gredo)
+{
+    const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngroups) return;
+    const u32 need = gneed[g];
+    if (need > gcap[g]) {
+        const u32 w = need + need / 4u + 2u;
+        gcap[g] = w;
+        gbase[g] = atomicAdd((unsigned long long*)&gbase[ngroups], (unsigned long long)w);
+        gredo[g] = 1;
+    } else {
+        gredo[g] = 0;
     }
 }
 
@@ -907,7 +964,8 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
 __global__ void __launch_bounds__(GROUP)
 k_cache_to_global(const u32* __restrict__ id, const GroupMap gm, i64 cap,
                   const u32* __restrict__ uleaf, const u32* __restrict__ uslot,
-                  const u32* __restrict__ ucnt, u32 capq, const u64* __restrict__ nlist,
+                  const u32* __restrict__ ucnt, const u64* __restrict__ gbase,
+                  const u64* __restrict__ nlist,
                   const u32* __restrict__ ncnt, const u64* __restrict__ off, u32* __restrict__ list)
 {
     const i64 g = blockIdx.x;
@@ -921,7 +979,7 @@ k_cache_to_global(const u32* __restrict__ id, const GroupMap gm, i64 cap,
     const u32* ul = uleaf + g * cap;
     const u32 c = ncnt[a];
     for (u32 j = 0; j < c; ++j) {
-        const u64 w = nlist[((u64)g * capq + (j >> 2)) * GROUP + threadIdx.x];
+        const u64 w = nlist[(gbase[g] + (j >> 2)) * GROUP + threadIdx.x];
         const u32 s = slot_of(w, j & 3u);
         u32 lo = 0, hi = nu - 1;       // last leaf whose start slot <= s
         while (lo < hi) {
@@ -970,7 +1028,8 @@ template <class T>
 void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* bhi, const u32* id,
                         const u32* xscan, i64 n_internal, const GroupMap& gm, i64 ngroups, const InstDev* inst,
                         double rk, double rkc, i64 cap, const u32* uleaf, const u32* uslot,
-                        const u32* ucnt, const u32* ustot, u32 capq, u64* nlist, u32* ncnt,
+                        const u32* ucnt, const u32* ustot, const u64* gbase, const u32* gcap,
+                        u64 words_alloc, u32* gneed, const u8* gredo, u64* nlist, u32* ncnt,
                         u32* flags, const vec4<T>* glo, const vec4<T>* ghi, const u32* root,
                         u64* work, int mode, const u8* redo, hipStream_t st)
 {
@@ -978,17 +1037,35 @@ void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* 
     auto kern = mode == 2 ? k_group_cache<T, 2> : mode == 0 ? k_group_cache<T, 0> : k_group_cache<T, 1>;
     hipLaunchKernelGGL(kern, dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, blo,
                        bhi, id, xscan, n_internal, gm, inst, (T)rk, (T)rkc, cap, uleaf, uslot, ucnt, ustot,
-                       capq, nlist, ncnt, flags, glo, ghi, root, work, redo);
+                       gbase, gcap, words_alloc, gneed, gredo, nlist, ncnt, flags, glo, ghi, root, work,
+                       redo);
+}
+
+void launch_cache_plan(const u32* ustot, const u32* gneed, i64 ngroups, u32 dflt, u32* gcap,
+                       u64* gbase, void* scan_tmp, hipStream_t st)
+{
+    if (ngroups <= 0) return;
+    hipLaunchKernelGGL(k_cache_plan, dim3((unsigned)((ngroups + 255) / 256)), dim3(256), 0, st, ustot, gneed, ngroups,
+                       dflt, gcap);
+    scan_u32_u64(gcap, gbase, ngroups, scan_tmp, st);
+}
+
+void launch_cache_regrow(const u32* gneed, i64 ngroups, u32* gcap, u64* gbase, u8* gredo,
+                         hipStream_t st)
+{
+    if (ngroups <= 0) return;
+    hipLaunchKernelGGL(k_cache_regrow, dim3((unsigned)((ngroups + 255) / 256)), dim3(256), 0, st, gneed, ngroups,
+                       gcap, gbase, gredo);
 }
 
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
-                            const u32* uleaf, const u32* uslot, const u32* ucnt, u32 capq,
+                            const u32* uleaf, const u32* uslot, const u32* ucnt, const u64* gbase,
                             const u64* nlist, const u32* ncnt, const u64* off, u32* list,
                             hipStream_t st)
 {
     if (ngroups <= 0) return;
     hipLaunchKernelGGL(k_cache_to_global, dim3((unsigned)ngroups), dim3(GROUP), 0, st, id, gm, cap,
-                       uleaf, uslot, ucnt, capq, nlist, ncnt, off, list);
+                       uleaf, uslot, ucnt, gbase, nlist, ncnt, off, list);
 }
 
 #define INST(T)                                                                                   \
@@ -1002,7 +1079,8 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
     template void launch_group_cache<T>(const vec4<T>*, const vec4<T>*, const vec4<T>*,           \
                                         const u32*, const u32*, i64, const GroupMap&, i64, const InstDev*,    \
                                         double, double, i64, const u32*, const u32*, const u32*,  \
-                                        const u32*, u32, u64*, u32*, u32*, const vec4<T>*,        \
+                                        const u32*, const u64*, const u32*, u64, u32*, const u8*,  \
+                                        u64*, u32*, u32*, const vec4<T>*,                          \
                                         const vec4<T>*, const u32*, u64*, int, const u8*,         \
                                         hipStream_t);
 INST(float)

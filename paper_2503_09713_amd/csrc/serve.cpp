@@ -32,9 +32,9 @@ namespace {
 // particle -- keys and values of the sort (x2), the three key-order float4
 // arrays, h copies, mask / scan / leaf arrays, tree and box arrays at
 // 8 particles per leaf, thermo / acc / Omega, and the ELL neighbour cache
-// (28 words of 8 B per particle at the default capacity, 25 % headroom).
+// (32 words of 8 B per particle at the default capacity, 25 % headroom).
 double state_per_particle(int dtype) { return 14.0 * (dtype == SHSPH_F32 ? 4 : 8) + 4.0; }
-double work_per_particle(int dtype) { return dtype == SHSPH_F32 ? 440.0 : 720.0; }
+double work_per_particle(int dtype) { return dtype == SHSPH_F32 ? 480.0 : 760.0; }
 
 struct Job {
     shsph_job spec;

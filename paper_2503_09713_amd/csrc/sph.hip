@@ -7,6 +7,10 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
+
+#include <hip/hip_cooperative_groups.h>
+
 namespace shsph {
 
 static inline dim3 grid_for(i64 n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
@@ -174,19 +178,43 @@ __device__ inline void atomic_min_if(u32* p, u32 v)
 // One workgroup per group: the union's positions are staged in LDS once and
 // every Newton pass reads neighbours from there.
 // ---------------------------------------------------------------------------
+template <class T, int CH> struct DensShared {
+    vec4<T> pos[CH];
+    u32 red[GROUP / WAVE];
+    u64 w[GROUP / WAVE];
+    int k;
+};
+
+// Arguments of the density pass (one group at a time).
+template <class T> struct DensArgs {
+    vec4<T>* posh;
+    const T *hn, *hc;
+    const vec4<T>* velu;
+    const u32* id;
+    GroupMap gm;
+    const InstDev* inst;
+    SphParams P;
+    CacheView cv;
+    T* omega;
+    vec4<T>* thermo;
+    u8* status;
+    InstStat* stat;
+    const u8* redo;
+};
+
 template <class T, int CH, int K>
-__global__ void __launch_bounds__(GROUP)
-k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restrict__ hc,
-          const vec4<T>* __restrict__ velu, const u32* __restrict__ id, const GroupMap gm,
-          const InstDev* __restrict__ inst, SphParams P, CacheView cv, T* __restrict__ omega,
-          vec4<T>* __restrict__ thermo, u8* __restrict__ status, InstStat* __restrict__ stat,
-          const u8* __restrict__ redo)
+__device__ __attribute__((always_inline)) inline void
+density_group(const i64 g, vec4<T>* __restrict__ posh, const T* __restrict__ hn,
+              const T* __restrict__ hc, const vec4<T>* __restrict__ velu,
+              const u32* __restrict__ id, const GroupMap gm, const InstDev* __restrict__ inst,
+              const SphParams P, const CacheView cv, T* __restrict__ omega,
+              vec4<T>* __restrict__ thermo, u8* __restrict__ status, InstStat* __restrict__ stat,
+              const u8* __restrict__ redo, DensShared<T, CH>& sh)
 {
-    __shared__ vec4<T> s_pos[CH];
-    __shared__ u32 s_red[GROUP / WAVE];
-    __shared__ u64 s_w[GROUP / WAVE];
-    __shared__ int s_k;
-    const i64 g = blockIdx.x;
+    vec4<T>* const s_pos = sh.pos;
+    u32* const s_red = sh.red;
+    u64* const s_w = sh.w;
+    int* const s_k = &sh.k;
     i64 beg, end;
     int k;
     gm.range(g, beg, end, k);
@@ -205,7 +233,7 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
     const u32 nch = (S + CH - 1) / CH;
     const u32* ul = cv.uleaf + g * cv.cap;
     const u32* us = cv.uslot + g * cv.cap;
-    const u64* my = cv.nlist + (u64)g * cv.capq * GROUP + threadIdx.x;
+    const u64* my = cv.nlist + cv.gbase[g] * GROUP + threadIdx.x;
     const vec4<T>* src[1] = { posh };
     vec4<T>* dst[1] = { s_pos };
     T h = pa.w, h_eval = pa.w, dsum = T(0);
@@ -290,7 +318,7 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
     // per-instance outcome counters (rare events: per-lane atomics)
     if (live && st == 2) atomicAdd(&stat[k].n_exceed, 1u);
     if (live && st == 1) atomicAdd(&stat[k].n_noconv, 1u);
-    if (block_uniform(k, &s_k)) {
+    if (block_uniform(k, s_k)) {
         const u32 mx = block_max<u32>(live ? (u32)iters : 0u, s_red);
         if (threadIdx.x == 0) atomic_max_if(&stat[k].max_iter_seen, mx);
     } else if (live) {
@@ -319,8 +347,29 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
         const T Pr = gm1 * rho * u;
         const T cs = sqrt((T)P.gamma * gm1 * u);
         const T B = T(1) / (rho * om);
-        thermo[a] = mk4<T>(Pr * B / rho, B, (T)P.alpha * cs, Pr);
+        thermo[a] = mk4<T>(Pr * B / rho, T(0.5) * B, (T)P.alpha * cs, Pr);
     }
+}
+
+template <class T, int CH, int K>
+__device__ __attribute__((always_inline)) inline void density_group(const i64 g, const DensArgs<T>& A,
+                                                                    DensShared<T, CH>& sh)
+{
+    density_group<T, CH, K>(g, A.posh, A.hn, A.hc, A.velu, A.id, A.gm, A.inst, A.P, A.cv, A.omega,
+                            A.thermo, A.status, A.stat, A.redo, sh);
+}
+
+template <class T, int CH, int K>
+__global__ void __launch_bounds__(GROUP)
+k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restrict__ hc,
+          const vec4<T>* __restrict__ velu, const u32* __restrict__ id, const GroupMap gm,
+          const InstDev* __restrict__ inst, SphParams P, CacheView cv, T* __restrict__ omega,
+          vec4<T>* __restrict__ thermo, u8* __restrict__ status, InstStat* __restrict__ stat,
+          const u8* __restrict__ redo)
+{
+    __shared__ DensShared<T, CH> sh;
+    density_group<T, CH, K>(blockIdx.x, posh, hn, hc, velu, id, gm, inst, P, cv, omega, thermo,
+                            status, stat, redo, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -330,31 +379,56 @@ k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restr
 // F_x = f'(r/h_x)/(pi h_x^4) (= rhat . grad W), q^x = -rho_x vsig_x w / 2 for
 // w = v_ab . rhat_ab < 0, vsig_x = alpha_x c_x + beta |w| (alpha_x c_x staged
 // per particle: the constant alpha, or the shock detector's alpha_x).  With
-// A = P/(rho^2 Om) and B = 1/(rho Om): (P+q)/(rho^2 Om) = A - vsig w B / 2.
-// Conductivity: m beta_u vsig_u (u_a-u_b) (F_a B_a + F_b B_b)/2 with
-// vsig_u = sqrt(|P_a - P_b| / ((rho_a+rho_b)/2)).
+// A = P/(rho^2 Om) and the staged half B' = 1/(2 rho Om):
+// (P+q)/(rho^2 Om) = A - vsig w B'.
+// Conductivity: m beta_u vsig_u (u_a-u_b) (F_a B'_a + F_b B'_b) with
+// vsig_u = sqrt(|P_a - P_b| / rhobar), rhobar = (rho_a+rho_b)/2, formed as
+// d rsq(d rhobar) for d = |P_a - P_b| > 0 (one reciprocal square root).
 // The timestep signal speed is the largest vsig_a over the pairs (floor c_a);
 // dt_a = min(C_cour h/vsig, C_force sqrt(h/|a|)) is min-reduced per instance.
 // One workgroup per group: the union's position, velocity and pressure terms
 // are staged in LDS.
 // ---------------------------------------------------------------------------
-constexpr int FT = 2 * GROUP;   // force: two threads per particle, each half of its list
+// SPLIT threads per particle (1 or 2: workgroups of 256 or 512 threads),
+// each taking its share of the particle's list; the shares are combined in a
+// fixed order.
+template <class T, int CH, int SPLIT> struct ForceShared {
+    vec4<T> pos[CH], vel[CH], thm[CH];
+    T half[6][SPLIT > 1 ? GROUP : 1];   // second-half sums, added by the first half
+    float red[SPLIT * GROUP / WAVE];
+    u64 w[SPLIT * GROUP / WAVE];
+    int k;
+};
 
-template <class T, int CH, int K>
-__global__ void __launch_bounds__(FT)
-k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
-        const vec4<T>* __restrict__ thermo, const u32* __restrict__ id, const GroupMap gm,
-        const InstDev* __restrict__ inst, SphParams P, CacheView cv, vec4<T>* __restrict__ acc,
-        T* __restrict__ vsig_out, InstStat* __restrict__ stat)
+// Arguments of the force pass (one group at a time).
+template <class T> struct ForceArgs {
+    const vec4<T> *posh, *velu, *thermo;
+    const u32* id;
+    GroupMap gm;
+    const InstDev* inst;
+    SphParams P;
+    CacheView cv;
+    vec4<T>* acc;
+    T* vsig_out;
+    InstStat* stat;
+};
+
+template <class T, int CH, int K, int SPLIT>
+__device__ __attribute__((always_inline)) inline void
+force_group(const i64 g, const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
+            const vec4<T>* __restrict__ thermo, const u32* __restrict__ id, const GroupMap gm,
+            const InstDev* __restrict__ inst, const SphParams P, const CacheView cv,
+            vec4<T>* __restrict__ acc, T* __restrict__ vsig_out, InstStat* __restrict__ stat,
+            ForceShared<T, CH, SPLIT>& sh)
 {
-    __shared__ vec4<T> s_pos[CH];
-    __shared__ vec4<T> s_vel[CH];
-    __shared__ vec4<T> s_thm[CH];
-    __shared__ T s_half[6][GROUP];          // second-half sums, added by the first half
-    __shared__ float s_red[FT / WAVE];
-    __shared__ u64 s_w[FT / WAVE];
-    __shared__ int s_k;
-    const i64 g = blockIdx.x;
+    constexpr int FT = SPLIT * GROUP;
+    vec4<T>* const s_pos = sh.pos;
+    vec4<T>* const s_vel = sh.vel;
+    vec4<T>* const s_thm = sh.thm;
+    auto& s_half = sh.half;
+    float* const s_red = sh.red;
+    u64* const s_w = sh.w;
+    int* const s_k = &sh.k;
     i64 beg, end;
     int k;
     gm.range(g, beg, end, k);
@@ -373,7 +447,8 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     const T hfa = hfact * hia;
     const T rhoa = m * hfa * hfa * hfa;
     const T mhf3 = m * hfact * hfact * hfact;    // rho_b = mhf3 / h_b^3
-    const T Aa = ta.x, Ba = ta.y, aca = ta.z, Pa = ta.w;     // aca = alpha_a c_a
+    const T Aa = ta.x, Ba = ta.y, aca = ta.z, Pa = ta.w;     // Ba = B'_a, aca = alpha_a c_a
+    const T mbu = m * beta_u;
     const T ca = sqrt((T)P.gamma * ((T)P.gamma - T(1)) * va.w);   // c_a: floor of the signal speed
     const u32 cnt = live ? cv.ncnt[a] : 0u;
     const u32 nu = min((u32)cv.cap, cv.ucnt[g]);
@@ -381,12 +456,13 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     const u32 nch = (S + CH - 1) / CH;
     const u32* ul = cv.uleaf + g * cv.cap;
     const u32* us = cv.uslot + g * cv.cap;
-    const u64* my = cv.nlist + (u64)g * cv.capq * GROUP + lt;
+    const u64* my = cv.nlist + cv.gbase[g] * GROUP + lt;
     const vec4<T>* src[3] = { posh, velu, thermo };
     vec4<T>* dst[3] = { s_pos, s_vel, s_thm };
-    // this thread's share of the list: words [q0, q1) (first half: the first
-    // ceil(nq/2) words), entries [e0, e1) for the tiled path
-    const u32 nq = (cnt + 3u) >> 2, qh = (nq + 1u) >> 1;
+    // this thread's share of the list: words [q0, q1) (with two threads the
+    // first takes the first ceil(nq/2) words), entries [e0, e1) for the
+    // tiled path
+    const u32 nq = (cnt + 3u) >> 2, qh = SPLIT > 1 ? (nq + 1u) >> 1 : nq;
     const u32 q0 = half ? qh : 0u, q1 = half ? nq : qh;
     const u32 e0 = min(cnt, 4u * q0), e1 = min(cnt, 4u * q1);
     T ax = T(0), ay = T(0), az = T(0), du = T(0), lam = T(0), vmax = ca;
@@ -397,11 +473,24 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     // staged particle instead of one per pair); r < 2 max(h_a, h_b) is
     // tested as r^2 min(1/h_a, 1/h_b)^2 < 4 (the kernel gradient vanishes
     // at q = 2, so the rounding of that boundary changes no sum)
-    auto pair_d = [&](u32 sl, T dx, T dy, T dz, const vec4<T>& pb) {
+    auto sep = [&](u32 sl, bool img, T& dx, T& dy, T& dz) -> vec4<T> {
+        const vec4<T> pb = s_pos[sl];
+        if (img) {
+            dx = min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic);
+            dy = min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic);
+            dz = min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic);
+        } else {
+            dx = pa.x - pb.x; dy = pa.y - pb.y; dz = pa.z - pb.z;
+        }
+        return pb;
+    };
+    auto interacts = [&](T r2, T hib) -> bool {
+        const T hmi = hia < hib ? hia : hib;
+        return (r2 > T(0)) & (r2 * hmi * hmi < RK * RK);
+    };
+    auto eval_d = [&](u32 sl, T dx, T dy, T dz, const vec4<T>& pb) {   // an interacting pair
         const T r2 = dx * dx + dy * dy + dz * dz;
         const T hib = pb.w;
-        const T hmi = hia < hib ? hia : hib;
-        if (!(r2 > T(0)) || !(r2 * hmi * hmi < RK * RK)) return;
         ++inter;
         const vec4<T> vb = s_vel[sl], tb = s_thm[sl];
         const T rinv = fast_rsq(r2), r = r2 * rinv;
@@ -414,27 +503,28 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         const T vsa = aca + beta * aw;
         const T vsb = tb.z + beta * aw;
         const T wn = w < T(0) ? w : T(0);
-        const T ka = (Aa - T(0.5) * vsa * wn * Ba) * Fa;
-        const T kb = (tb.x - T(0.5) * vsb * wn * tb.y) * Fb;
+        const T ka = (Aa - vsa * wn * Ba) * Fa;
+        const T kb = (tb.x - vsb * wn * tb.y) * Fb;
         const T fab = m * (ka + kb);
         ax -= fab * ex;
         ay -= fab * ey;
         az -= fab * ez;
         du += m * ka * w;
         const T rhob = mhf3 * hib3;
-        const T vsu = fast_sqrt(fabs(Pa - tb.w)) * fast_rsq(T(0.5) * (rhoa + rhob));
-        lam += m * beta_u * vsu * (va.w - vb.w) * T(0.5) * (Fa * Ba + Fb * tb.y);
+        const T dP = fabs(Pa - tb.w);
+        const T vsu = dP > T(0) ? dP * fast_rsq(dP * (T(0.5) * (rhoa + rhob))) : T(0);
+        lam += mbu * vsu * (va.w - vb.w) * (Fa * Ba + Fb * tb.y);
         vmax = vsa > vmax ? vsa : vmax;
     };
     auto pair = [&](u32 sl) {             // any group: minimum image
-        const vec4<T> pb = s_pos[sl];
-        pair_d(sl, min_image(pa.x - pb.x, bx.L[0], bx.halfL[0], bx.periodic),
-               min_image(pa.y - pb.y, bx.L[1], bx.halfL[1], bx.periodic),
-               min_image(pa.z - pb.z, bx.L[2], bx.halfL[2], bx.periodic), pb);
+        T dx, dy, dz;
+        const vec4<T> pb = sep(sl, true, dx, dy, dz);
+        if (interacts(dx * dx + dy * dy + dz * dz, pb.w)) eval_d(sl, dx, dy, dz, pb);
     };
     auto pair_in = [&](u32 sl) {          // interior group: no image can be closer
-        const vec4<T> pb = s_pos[sl];
-        pair_d(sl, pa.x - pb.x, pa.y - pb.y, pa.z - pb.z, pb);
+        T dx, dy, dz;
+        const vec4<T> pb = sep(sl, false, dx, dy, dz);
+        if (interacts(dx * dx + dy * dy + dz * dz, pb.w)) eval_d(sl, dx, dy, dz, pb);
     };
     auto invert_h = [&](u32 n_st) {
         for (u32 t = threadIdx.x; t < n_st; t += FT) s_pos[t].w = fast_rcp(s_pos[t].w);
@@ -459,15 +549,17 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         }
     }
     // first half + second half, in that order
-    if (half) {
-        s_half[0][lt] = ax; s_half[1][lt] = ay; s_half[2][lt] = az;
-        s_half[3][lt] = du; s_half[4][lt] = lam; s_half[5][lt] = vmax;
-    }
-    __syncthreads();
-    if (!half) {
-        ax += s_half[0][lt]; ay += s_half[1][lt]; az += s_half[2][lt];
-        du += s_half[3][lt]; lam += s_half[4][lt];
-        vmax = vmax > s_half[5][lt] ? vmax : s_half[5][lt];
+    if constexpr (SPLIT > 1) {
+        if (half) {
+            s_half[0][lt] = ax; s_half[1][lt] = ay; s_half[2][lt] = az;
+            s_half[3][lt] = du; s_half[4][lt] = lam; s_half[5][lt] = vmax;
+        }
+        __syncthreads();
+        if (!half) {
+            ax += s_half[0][lt]; ay += s_half[1][lt]; az += s_half[2][lt];
+            du += s_half[3][lt]; lam += s_half[4][lt];
+            vmax = vmax > s_half[5][lt] ? vmax : s_half[5][lt];
+        }
     }
     if (cv.work) {   // work counters (profiling): visited entries, interacting pairs
         const u64 t1 = block_reduce<FT>((u64)(e1 - e0), s_w, [](u64 x, u64 y) { return x + y; });
@@ -486,12 +578,32 @@ k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
         const T t2 = am > T(0) ? (T)P.c_force * sqrt(ha / am) : T(INFINITY);
         dta = (float)(t1 < t2 ? t1 : t2);
     }
-    if (block_uniform(k, &s_k)) {
+    if (block_uniform(k, s_k)) {
         const float bmin = block_reduce<FT>(dta, s_red, [](float x, float y) { return x < y ? x : y; });
         if (threadIdx.x == 0) atomic_min_if(&stat[k].dt_bits, __float_as_uint(bmin));
     } else if (live && !half) {
         atomic_min_if(&stat[k].dt_bits, __float_as_uint(dta));
     }
+}
+
+template <class T, int CH, int K, int SPLIT>
+__device__ __attribute__((always_inline)) inline void force_group(const i64 g, const ForceArgs<T>& A,
+                                                                  ForceShared<T, CH, SPLIT>& sh)
+{
+    force_group<T, CH, K, SPLIT>(g, A.posh, A.velu, A.thermo, A.id, A.gm, A.inst, A.P, A.cv, A.acc,
+                                 A.vsig_out, A.stat, sh);
+}
+
+template <class T, int CH, int K, int SPLIT>
+__global__ void __launch_bounds__(SPLIT * GROUP)
+k_force(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
+        const vec4<T>* __restrict__ thermo, const u32* __restrict__ id, const GroupMap gm,
+        const InstDev* __restrict__ inst, SphParams P, CacheView cv, vec4<T>* __restrict__ acc,
+        T* __restrict__ vsig_out, InstStat* __restrict__ stat)
+{
+    __shared__ ForceShared<T, CH, SPLIT> sh;
+    force_group<T, CH, K, SPLIT>(blockIdx.x, posh, velu, thermo, id, gm, inst, P, cv, acc, vsig_out,
+                                 stat, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -538,7 +650,7 @@ k_alpha(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
     const u32 nch = (S + CH - 1) / CH;
     const u32* ul = cv.uleaf + g * cv.cap;
     const u32* us = cv.uslot + g * cv.cap;
-    const u64* my = cv.nlist + (u64)g * cv.capq * GROUP + threadIdx.x;
+    const u64* my = cv.nlist + cv.gbase[g] * GROUP + threadIdx.x;
     const vec4<T>* src[3] = { posh, velu, acc_n };
     vec4<T>* dst[3] = { s_pos, s_vel, s_acc };
     T gv[9], ga[9];
@@ -721,7 +833,7 @@ k_fold_parts(const BlockPart* __restrict__ part, i64 nblocks, InstStat* __restri
 }
 
 // Pressure terms for the force from h, Omega and u* (key order):
-// thermo = (P/(rho^2 Om), 1/(rho Om), c_s, P), P = (gamma-1) rho u,
+// thermo = (P/(rho^2 Om), 1/(2 rho Om), alpha c_s, P), P = (gamma-1) rho u,
 // c_s = sqrt(gamma (gamma-1) u), rho = m (hfact/h)^3.
 template <class T>
 __global__ void k_thermo(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
@@ -738,7 +850,7 @@ __global__ void k_thermo(const vec4<T>* __restrict__ posh, const vec4<T>* __rest
     const T Pr = (g - T(1)) * rho * u;
     const T B = T(1) / (rho * om);
     const T al = alpha_s ? alpha_s[i] : (T)alpha;
-    thermo[i] = mk4<T>(Pr * B / rho, B, al * sqrt(g * (g - T(1)) * u), Pr);
+    thermo[i] = mk4<T>(Pr * B / rho, T(0.5) * B, al * sqrt(g * (g - T(1)) * u), Pr);
 }
 
 // Corrector re-run (App. G.1): v* <- v^{n+1}, u* <- u^{n+1} for the particles
@@ -864,17 +976,99 @@ void launch_density(const SortedPtrs<T>& s, const u32* id, const GroupMap& gm, i
     }
 }
 
+template <class T, int K, int SPLIT>
+void launch_force_s(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id, const GroupMap& gm,
+                    i64 ngroups, const InstDev* inst, const SphParams& P, const CacheView& cv,
+                    vec4<T>* acc, T* vsig, InstStat* stat, hipStream_t st)
+{
+    if (sizeof(T) == 4)
+        hipLaunchKernelGGL((k_force<T, FORCE_CH_F, K, SPLIT>), dim3((unsigned)ngroups),
+                           dim3(SPLIT * GROUP), 0, st, s.posh, s.velu, thermo, id, gm, inst, P, cv,
+                           acc, vsig, stat);
+    else
+        hipLaunchKernelGGL((k_force<T, FORCE_CH_D, K, SPLIT>), dim3((unsigned)ngroups),
+                           dim3(SPLIT * GROUP), 0, st, s.posh, s.velu, thermo, id, gm, inst, P, cv,
+                           acc, vsig, stat);
+}
+
 template <class T, int K>
 void launch_force_k(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id, const GroupMap& gm,
                     i64 ngroups, const InstDev* inst, const SphParams& P, const CacheView& cv,
                     vec4<T>* acc, T* vsig, InstStat* stat, hipStream_t st)
 {
-    if (sizeof(T) == 4)
-        hipLaunchKernelGGL((k_force<T, FORCE_CH_F, K>), dim3((unsigned)ngroups), dim3(FT), 0, st,
-                           s.posh, s.velu, thermo, id, gm, inst, P, cv, acc, vsig, stat);
+    if (P.force_split == 1)
+        launch_force_s<T, K, 1>(s, thermo, id, gm, ngroups, inst, P, cv, acc, vsig, stat, st);
     else
-        hipLaunchKernelGGL((k_force<T, FORCE_CH_D, K>), dim3((unsigned)ngroups), dim3(FT), 0, st,
-                           s.posh, s.velu, thermo, id, gm, inst, P, cv, acc, vsig, stat);
+        launch_force_s<T, K, 2>(s, thermo, id, gm, ngroups, inst, P, cv, acc, vsig, stat, st);
+}
+
+// Density and force in one persistent launch: the workgroups (as many as
+// the device holds at once, launched cooperatively) take the groups
+// g = blockIdx.x, + gridDim.x, ... through the h iteration; the grid then
+// synchronises (every h, rho, Omega and pressure term written and visible to
+// all workgroups), and unless some particle left chi h_cache (its instance's
+// cache must be rebuilt first: the caller then runs the separate passes) the
+// same workgroups take the groups through the force, one thread per
+// particle.  The LDS of the two passes is shared.
+template <class T, int DCH, int FCH, int K>
+__global__ void __launch_bounds__(GROUP)
+k_density_force(const DensArgs<T> D, const ForceArgs<T> F, i64 ngroups, int ninst)
+{
+    constexpr size_t DB = sizeof(DensShared<T, DCH>), FB = sizeof(ForceShared<T, FCH, 1>);
+    __shared__ __align__(16) unsigned char buf[DB > FB ? DB : FB];
+    auto& ds = *reinterpret_cast<DensShared<T, DCH>*>(buf);
+    auto& fs = *reinterpret_cast<ForceShared<T, FCH, 1>*>(buf);
+    for (i64 g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        __syncthreads();
+        density_group<T, DCH, K>(g, D, ds);
+    }
+    cooperative_groups::this_grid().sync();
+    bool exceed = false;
+    for (int k = threadIdx.x; k < ninst; k += GROUP) exceed |= D.stat[k].n_exceed != 0u;
+    if (__syncthreads_or(exceed)) return;
+    for (i64 g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        __syncthreads();
+        force_group<T, FCH, K, 1>(g, F, fs);
+    }
+}
+
+template <class T, int K>
+int launch_density_force_k(const DensArgs<T>& D, const ForceArgs<T>& F, i64 ngroups, int ninst,
+                           hipStream_t st)
+{
+    const void* kern = sizeof(T) == 4
+        ? (const void*)&k_density_force<T, DENS_CH_F, FORCE_CH_F, K>
+        : (const void*)&k_density_force<T, DENS_CH_D, FORCE_CH_D, K>;
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, GROUP, 0) != hipSuccess || per < 1)
+        return -1;
+    const i64 nb = std::min<i64>(ngroups, (i64)per * cus);
+    DensArgs<T> d = D;
+    ForceArgs<T> f = F;
+    void* args[] = { &d, &f, &ngroups, &ninst };
+    return hipLaunchCooperativeKernel(kern, dim3((unsigned)nb), dim3(GROUP), args, 0, st) == hipSuccess ? 0 : -1;
+}
+
+template <class T>
+int launch_density_force(const SortedPtrs<T>& s, const vec4<T>* thermo, const u32* id,
+                         const GroupMap& gm, i64 ngroups, int ninst, const InstDev* inst,
+                         const SphParams& P, const CacheView& cvd, const CacheView& cvf, T* omega,
+                         u8* status, InstStat* stat, vec4<T>* acc, T* vsig, hipStream_t st)
+{
+    if (ngroups <= 0) return 0;
+    const DensArgs<T> D{s.posh, s.hn, s.hcache, s.velu, id, gm, inst, P, cvd, omega,
+                        const_cast<vec4<T>*>(thermo), status, stat, nullptr};
+    const ForceArgs<T> F{s.posh, s.velu, thermo, id, gm, inst, P, cvf, acc, vsig, stat};
+    switch (P.kernel) {
+    case KM5: return launch_density_force_k<T, KM5>(D, F, ngroups, ninst, st);
+    case KM6: return launch_density_force_k<T, KM6>(D, F, ngroups, ninst, st);
+    case KC2: return launch_density_force_k<T, KC2>(D, F, ngroups, ninst, st);
+    case KC4: return launch_density_force_k<T, KC4>(D, F, ngroups, ninst, st);
+    case KC6: return launch_density_force_k<T, KC6>(D, F, ngroups, ninst, st);
+    default:  return launch_density_force_k<T, KM4>(D, F, ngroups, ninst, st);
+    }
 }
 
 template <class T>
@@ -1011,6 +1205,10 @@ void launch_scatter_rho(const u32* eps, i64 n, const vec4<T>* posh, const i64* p
                                     const InstDev*, const SphParams&, const CacheView&, T*,       \
                                     vec4<T>*, u8*, InstStat*, const u8*, hipStream_t);             \
     template void launch_root_hmax<T>(const vec4<T>*, const u32*, int, double*, hipStream_t);     \
+    template int launch_density_force<T>(const SortedPtrs<T>&, const vec4<T>*, const u32*,        \
+                                         const GroupMap&, i64, int, const InstDev*,              \
+                                         const SphParams&, const CacheView&, const CacheView&,    \
+                                         T*, u8*, InstStat*, vec4<T>*, T*, hipStream_t);          \
     template void launch_force<T>(const SortedPtrs<T>&, const vec4<T>*, const u32*,               \
                                   const GroupMap&, i64, const InstDev*, const SphParams&,         \
                                   const CacheView&, vec4<T>*, T*, InstStat*, hipStream_t);         \

@@ -200,6 +200,285 @@ __global__ void k_compact(const u64* __restrict__ mu, const u8* __restrict__ xi,
     if (i == 0) id[xscan[n]] = (u32)n;
 }
 
+// The keep mask, the reduction passes, the scan and the compaction in one
+// kernel, with the results of k_mask_init + n_red k_reduce_pass + scan +
+// k_compact.  Each workgroup takes a tile of LV_TILE sorted codes (tiles
+// numbered by an atomic ticket) and a window reaching LV_HALO codes beyond
+// it on both sides, and runs the mask and the Jacobi passes on the window in
+// LDS.  In each pass the nearest kept code before and after every code come
+// from a block-wide max / min scan over the window (the one before that from
+// the first scan's table).  Codes outside the window are unknown (state 2):
+// a nearest code that would lie outside the window while still inside the
+// instance, or that is unknown itself, makes the result unknown, so every
+// code whose state is 0 or 1 has exactly the value the global passes give
+// it.  A tile with an unknown code of its own (a run of dropped codes longer
+// than the halo, e.g. many coincident particles) sets flag[0], and the caller
+// runs the separate passes instead; the others publish their kept count and
+// find the exclusive prefix by decoupled look-back over the earlier tiles
+// (bounded waits: flag[1] on overrun).  Writes xi, xscan[0..n], id[0..n_leaf]
+// and mu_leaf.
+constexpr int LV_BLOCK = 256, LV_ITEMS = 16, LV_TILE = LV_BLOCK * LV_ITEMS, LV_HALO = 256;
+constexpr int LV_WIN = LV_TILE + 2 * LV_HALO, LV_PER = LV_WIN / LV_BLOCK;
+constexpr u32 LV_AGG = 1u << 30, LV_PREFIX = 2u << 30, LV_VAL = (1u << 30) - 1u;
+constexpr u32 LV_SPIN_LIMIT = 1u << 22;
+constexpr u16 LV_NONE = 0xffffu;
+static_assert(LV_WIN % LV_BLOCK == 0 && LV_WIN < 0xffff, "window split over the threads");
+
+// Exclusive scans over the threads of the block with a max (over lower
+// threads) or min (over higher threads); `lds` holds one value per wave.
+__device__ inline int lv_prefix_max(int v, int* lds)
+{
+    const int lane = __lane_id(), wid = threadIdx.x / WAVE;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const int y = __shfl_up(x, d, WAVE);
+        if (lane >= d) x = x > y ? x : y;
+    }
+    if (lane == WAVE - 1) lds[wid] = x;
+    __syncthreads();
+    int c = -1;
+    for (int w = 0; w < wid; ++w) c = c > lds[w] ? c : lds[w];
+    int e = __shfl_up(x, 1, WAVE);
+    if (lane == 0) e = -1;
+    __syncthreads();
+    return c > e ? c : e;
+}
+
+__device__ inline int lv_suffix_min(int v, int* lds)
+{
+    const int lane = __lane_id(), wid = threadIdx.x / WAVE;
+    constexpr int NW = LV_BLOCK / WAVE;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const int y = __shfl_down(x, d, WAVE);
+        if (lane + d < WAVE) x = x < y ? x : y;
+    }
+    if (lane == 0) lds[wid] = x;
+    __syncthreads();
+    int c = 1 << 30;
+    for (int w = wid + 1; w < NW; ++w) c = c < lds[w] ? c : lds[w];
+    int e = __shfl_down(x, 1, WAVE);
+    if (lane == WAVE - 1) e = 1 << 30;
+    __syncthreads();
+    return c < e ? c : e;
+}
+
+// Nearest kept code found by a scan (`a`: -1 / >= W when none in the window)
+// for a code of the instance [f, l) (window coordinates): the slot, -1 for
+// none inside the instance, -2 for unknown.
+__device__ inline int lv_resolve_prev(const u8* m, int a, int f)
+{
+    if (a >= 0 && a >= f) return m[a] == 2 ? -2 : a;
+    return f >= 0 ? -1 : -2;
+}
+__device__ inline int lv_resolve_next(const u8* m, int c, int l, int W)
+{
+    if (c < W && c < l) return m[c] == 2 ? -2 : c;
+    return l <= W ? -1 : -2;
+}
+
+template <bool MULTI>
+__global__ void __launch_bounds__(LV_BLOCK)
+k_leaves_fused(const u64* __restrict__ mu, i64 n, const i64* __restrict__ p_off, int ninst,
+               int nred, u32* __restrict__ ticket, u32* __restrict__ status, u8* __restrict__ xi,
+               u32* __restrict__ xscan, u32* __restrict__ id, u64* __restrict__ mu_leaf,
+               u32* __restrict__ flag)
+{
+    __shared__ u64 s_mu[LV_WIN];
+    __shared__ u8 s_m[2][LV_WIN];
+    __shared__ u16 s_prev[LV_WIN];
+    __shared__ int s_scr[LV_BLOCK / WAVE];
+    __shared__ u32 s_tile, s_excl;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const i64 tile = s_tile;
+    const i64 ntiles = (n + LV_TILE - 1) / LV_TILE;
+    const i64 t0 = tile * LV_TILE, t1 = (t0 + LV_TILE) < n ? (t0 + LV_TILE) : n;
+    const i64 w0 = t0 > LV_HALO ? t0 - LV_HALO : 0;
+    const i64 w1 = (t1 + LV_HALO) < n ? (t1 + LV_HALO) : n;
+    const int W = (int)(w1 - w0);
+    for (int j = threadIdx.x; j < W; j += LV_BLOCK) s_mu[j] = mu[w0 + j];
+    // this thread's window slots j0 .. j0 + LV_PER - 1 and the instance range
+    // [f, l) of each (window coordinates, clamped into int range)
+    const int j0 = threadIdx.x * LV_PER;
+    int fr[LV_PER], lr[LV_PER];
+    {
+        i64 f = 0, l = n;
+        int k = 0;
+        if (MULTI) {
+            k = find_seg(p_off, ninst, w0 + (j0 < W ? j0 : 0));
+            f = p_off[k];
+            l = p_off[k + 1];
+        }
+#pragma unroll
+        for (int r = 0; r < LV_PER; ++r) {
+            if (MULTI) {
+                const i64 i = w0 + j0 + r;
+                while (k + 1 < ninst && i >= l) { ++k; f = l; l = p_off[k + 1]; }
+            }
+            fr[r] = (int)((f - w0) > -(1 << 30) ? (f - w0) : -(1 << 30));
+            lr[r] = (int)((l - w0) < (1 << 30) ? (l - w0) : (1 << 30));
+        }
+    }
+    __syncthreads();
+    // keep mask: the first code of an instance, else a code unlike the one before
+#pragma unroll
+    for (int r = 0; r < LV_PER; ++r) {
+        const int j = j0 + r;
+        if (j >= W) continue;
+        u8 v;
+        if (j == fr[r]) v = 1;
+        else if (j == 0) v = 2;
+        else v = s_mu[j] != s_mu[j - 1] ? 1 : 0;
+        s_m[0][j] = v;
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int p = 0; p < nred; ++p) {
+        const u8* mo = s_m[cur];
+        u8* mn = s_m[cur ^ 1];
+        // nearest nonzero (kept or unknown) code before / after each slot
+        int last = -1, first = 1 << 30;
+#pragma unroll
+        for (int r = 0; r < LV_PER; ++r) {
+            const int j = j0 + r;
+            if (j < W && mo[j] != 0) { last = j; if (first == (1 << 30)) first = j; }
+        }
+        int run = lv_prefix_max(last, s_scr);
+        int nxt[LV_PER];
+#pragma unroll
+        for (int r = 0; r < LV_PER; ++r) {
+            const int j = j0 + r;
+            if (j < W) {
+                s_prev[j] = run < 0 ? LV_NONE : (u16)run;
+                if (mo[j] != 0) run = j;
+            }
+        }
+        run = lv_suffix_min(first, s_scr);
+#pragma unroll
+        for (int r = LV_PER - 1; r >= 0; --r) {
+            const int j = j0 + r;
+            nxt[r] = run;
+            if (j < W && mo[j] != 0) run = j;
+        }
+        __syncthreads();                      // s_prev complete
+#pragma unroll
+        for (int r = 0; r < LV_PER; ++r) {
+            const int j = j0 + r;
+            if (j >= W) continue;
+            const u8 v = mo[j];
+            if (v != 1) { mn[j] = v; continue; }
+            const int pa = s_prev[j] == LV_NONE ? -1 : (int)s_prev[j];
+            const int a = lv_resolve_prev(mo, pa, fr[r]);
+            const int c = lv_resolve_next(mo, nxt[r], lr[r], W);
+            if (a == -2 || c == -2) { mn[j] = 2; continue; }
+            const u64 m0 = s_mu[j];
+            const int d0 = c >= 0 ? delta_k(m0, s_mu[c]) : -1;
+            const int dm1 = a >= 0 ? delta_k(s_mu[a], m0) : -1;
+            if (!(d0 < dm1)) { mn[j] = 1; continue; }      // kept whatever lies beyond a
+            const int pb = s_prev[a] == LV_NONE ? -1 : (int)s_prev[a];   // a >= 0 here
+            const int b = lv_resolve_prev(mo, pb, fr[r]);
+            if (b == -2) { mn[j] = 2; continue; }
+            const int dm2 = b >= 0 ? delta_k(s_mu[b], s_mu[a]) : -1;
+            mn[j] = (dm2 < dm1) ? 0 : 1;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    const u8* mf = s_m[cur];
+    // the tile's codes, LV_ITEMS consecutive ones per thread
+    const int tb = (int)(t0 - w0) + threadIdx.x * LV_ITEMS;
+    const int te = (int)(t1 - w0);
+    u32 cnt = 0;
+    bool unknown = false;
+#pragma unroll
+    for (int r = 0; r < LV_ITEMS; ++r) {
+        const int j = tb + r;
+        if (j < te) {
+            const u8 v = mf[j];
+            unknown |= v == 2;
+            cnt += v == 1 ? 1u : 0u;
+        }
+    }
+    const bool bad = __syncthreads_or(unknown) != 0;
+    if (bad) {
+        if (threadIdx.x == 0) atomicOr(&flag[0], 1u);
+        cnt = 0;            // keep the look-back of later tiles going
+    }
+    u32 tot;
+    const u32 ex_local = block_excl_scan<LV_BLOCK>(cnt, (u32*)s_scr, tot);
+    // decoupled look-back by the first wave, 64 earlier tiles per round: each
+    // lane reads one status word; the nearest inclusive prefix ends the walk
+    if (threadIdx.x < WAVE) {
+        const int lane = threadIdx.x;
+        u32* mine = status + tile;
+        u32 excl = 0;
+        if (tile == 0) {
+            if (lane == 0)
+                __hip_atomic_store(mine, LV_PREFIX | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (lane == 0)
+                __hip_atomic_store(mine, LV_AGG | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            i64 base = tile - 1;            // the round reads tiles base, base-1, ..., base-63
+            u32 spins = 0;
+            for (;;) {
+                const i64 t2 = base - lane;
+                const u32 sw = t2 >= 0 ? __hip_atomic_load(status + t2, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT)
+                                       : LV_PREFIX;        // before tile 0: prefix 0
+                const u64 pre = __ballot((sw & ~LV_VAL) == LV_PREFIX);
+                const u64 none = __ballot((sw & ~LV_VAL) == 0u);
+                // lanes up to the nearest prefix (all 64 when there is none)
+                const int last = pre ? __ffsll((unsigned long long)pre) - 1 : WAVE - 1;
+                const u64 need = last == WAVE - 1 ? ~0ull : ((1ull << (last + 1)) - 1ull);
+                if (none & need) {
+                    if (++spins > LV_SPIN_LIMIT) {
+                        if (lane == 0) atomicOr(&flag[1], 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                u32 v = lane <= last ? (sw & LV_VAL) : 0u;
+#pragma unroll
+                for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+                excl += v;
+                if (pre) break;
+                base -= WAVE;
+            }
+            if (lane == 0)
+                __hip_atomic_store(mine, LV_PREFIX | ((excl + tot) & LV_VAL), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) {
+            s_excl = excl;
+            if (tile == ntiles - 1) {
+                xscan[n] = excl + tot;
+                id[excl + tot] = (u32)n;
+            }
+        }
+    }
+    __syncthreads();
+    u32 k = s_excl + ex_local;
+#pragma unroll
+    for (int r = 0; r < LV_ITEMS; ++r) {
+        const int j = tb + r;
+        if (j < te) {
+            const i64 i = w0 + j;
+            const u8 v = mf[j];
+            xi[i] = v;
+            xscan[i] = k;
+            if (v == 1 && !bad) {
+                id[k] = (u32)i;
+                mu_leaf[k] = s_mu[j];
+                ++k;
+            }
+        }
+    }
+}
+
 // Per-instance leaf ranges: leaf_off[k] = number of kept codes before the
 // instance's first particle; root node of each instance.
 __global__ void k_inst_leaves(const i64* __restrict__ p_off, int ninst, const u32* __restrict__ xscan,
@@ -689,6 +968,21 @@ void launch_compact(const u64* mu, const u8* xi, const u32* xscan, i64 n, u32* i
                     hipStream_t st)
 {
     hipLaunchKernelGGL(k_compact, grid_for(n, 256), dim3(256), 0, st, mu, xi, xscan, n, id, mu_leaf);
+}
+
+size_t leaves_fused_state_words(i64 n) { return 1 + (size_t)((n + LV_TILE - 1) / LV_TILE); }
+
+void launch_leaves_fused(const u64* mu, i64 n, const i64* p_off, int ninst, int nred, u32* state,
+                         u8* xi, u32* xscan, u32* id, u64* mu_leaf, u32* flag, hipStream_t st)
+{
+    const i64 ntiles = (n + LV_TILE - 1) / LV_TILE;
+    launch_fill_u32(state, (i64)leaves_fused_state_words(n), 0u, st);
+    if (ninst > 1)
+        hipLaunchKernelGGL(k_leaves_fused<true>, dim3((unsigned)ntiles), dim3(LV_BLOCK), 0, st, mu, n,
+                           p_off, ninst, nred, state, state + 1, xi, xscan, id, mu_leaf, flag);
+    else
+        hipLaunchKernelGGL(k_leaves_fused<false>, dim3((unsigned)ntiles), dim3(LV_BLOCK), 0, st, mu, n,
+                           p_off, ninst, nred, state, state + 1, xi, xscan, id, mu_leaf, flag);
 }
 
 void launch_inst_leaves(const i64* p_off, int ninst, const u32* xscan, i64 n, i64* leaf_off,

@@ -285,6 +285,7 @@ def test_leaf_size_and_walk_do_not_change_results(torch_cuda):
     hs = [ctx.instance_create(shsph.ParticleSet.from_particles(p)) for p in ps]
     t = ctx.autotune(hs)
     assert t["n_red"] in (2, 3, 4) and t["stage2_mode"] in (0, 1, 2) and t["pass_ms"] > 0
+    assert t["force_split"] in (1, 2)
     ctx.step_batch(hs)
     ctx.close()
 

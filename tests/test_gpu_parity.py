@@ -216,6 +216,43 @@ def test_tree_with_duplicate_positions(torch_cuda):
     ctx.close()
 
 
+def test_cache_group_regrow(torch_cuda):
+    """Twelve particles of a 20^3 lattice with three times the smoothing length
+    (about 27 times the neighbours): their groups outgrow the default cache
+    capacity and only they are laid out again and rebuilt; a second build on
+    the same context plans every group from the first one's needs.  Both
+    builds bit-exact (neighbour sets and order included)."""
+    _say("[tree] per-group cache capacity regrow")
+    p = gen.lattice(20, 12, dtype=np.float32)
+    big = np.random.default_rng(5).choice(p.n, size=12, replace=False)
+    p.h[big] = (p.h[big] * 3).astype(np.float32)
+    ctx = _ctx(torch_cuda, n_red=3)
+    ps = _upload(p, torch_cuda)
+    ctx.build_tree(ps)
+    ex = check_tree(ctx, p, 3)
+    assert np.diff(ex["neigh_off"].astype(np.int64)).max() > 1000
+    ctx.build_tree(ps)
+    check_tree(ctx, p, 3)
+    ctx.close()
+
+
+def test_tree_leaf_pass_fallback(torch_cuda):
+    """5000 coincident particles in a 20^3 lattice: the run of equal keys is
+    longer than the fused leaf pass's window (a tile plus halos), so the tile
+    after it cannot find its first kept code's predecessor in LDS and the
+    separate mask / reduction / scan / compaction passes run instead.  The
+    tree must be bit-exact all the same."""
+    _say("[tree] leaf pass fallback: 5000 coincident particles")
+    base = gen.lattice(20, 10, dtype=np.float32)
+    idx = np.concatenate([np.arange(base.n), np.full(5000, 123)])
+    p = base.subset(idx)
+    p.mass = base.mass * base.n / p.n
+    ctx = _ctx(torch_cuda, n_red=3)
+    ctx.build_tree(_upload(p, torch_cuda))
+    check_tree(ctx, p, 3)
+    ctx.close()
+
+
 @pytest.mark.parametrize("T", [np.float32, np.float64])
 def test_density_vs_oracle(torch_cuda, T):
     _say(f"[density] lattice16 {np.dtype(T).name}")
@@ -307,9 +344,12 @@ def _force_err(g, ref):
     return ea, eu
 
 
-@pytest.mark.parametrize("case", ["lattice16_f32", "lattice16_f64", "plummer3000_f32", "sedov16_f32"])
-def test_force_vs_oracle(torch_cuda, case):
-    _say(f"[force] {case}")
+@pytest.mark.parametrize("case,split", [("lattice16_f32", 2), ("lattice16_f64", 2),
+                                        ("plummer3000_f32", 2), ("sedov16_f32", 2),
+                                        ("lattice16_f32", 1), ("plummer3000_f32", 1)])
+def test_force_vs_oracle(torch_cuda, case, split):
+    """split: threads per particle in the force kernel (its workgroup size)."""
+    _say(f"[force] {case} force_split={split}")
     if case.startswith("lattice16"):
         T = np.float64 if case.endswith("f64") else np.float32
         p = _random_state(gen.lattice(16, gen.SEEDS["tiny"], dtype=T), 3)
@@ -318,7 +358,7 @@ def test_force_vs_oracle(torch_cuda, case):
     else:
         p = gen.sedov(16, 3, dtype=np.float32)
     T = p.x.dtype
-    ctx = _ctx(torch_cuda, eps_h=1e-6 if T == np.float32 else 1e-12)
+    ctx = _ctx(torch_cuda, eps_h=1e-6 if T == np.float32 else 1e-12, force_split=split)
     ps = _upload(p, torch_cuda)
     ctx.build_tree(ps)
     ctx.density(ps)
