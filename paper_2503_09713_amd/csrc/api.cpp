@@ -693,8 +693,6 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
             return fail(c, SHSPH_EHIP, "radix sort: a look-back wait ran past its bound");
         }
         if (fl[0] & 1u) return fail(c, SHSPH_ECAPACITY, "tree traversal stack overflow");
-        if (fl[0] & 8u)
-            return fail(c, SHSPH_ECAPACITY, "a group's candidate union exceeds 65535 particles");
         if (fl[0] & 16u) return fail(c, SHSPH_ECAPACITY, "bottom-up box records overflow");
         // periodic minimum image needs the cache radius below half the box
         const double* rh = (const double*)((char*)c->pinned + FLAG_WORDS * sizeof(u32));
@@ -1719,7 +1717,8 @@ int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
         total = *(u64*)c->pinned;
         TRY(ensure(c, c->xlist, std::max<u64>(total, 1) * sizeof(u32)));
         launch_cache_to_global(P<u32>(c->id), group_map(c), G, c->cap_leaf, P<u32>(c->uleaf),
-                               P<u32>(c->uslot), P<u32>(c->ucnt), P<u64>(c->gbase), P<u64>(c->nlist),
+                               P<u32>(c->uslot), P<u32>(c->ucnt), P<u32>(c->ustot),
+                               P<u64>(c->gbase), P<u64>(c->nlist),
                                P<u32>(c->ncnt), P<u64>(c->xoff), P<u32>(c->xlist), st);
         TRY(check_launch(c, "cache export"));
         TRY(cp(o->neigh_off, c->xoff.p, (n + 1) * 8));

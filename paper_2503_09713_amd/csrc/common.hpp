@@ -219,10 +219,15 @@ __device__ inline bool group_interior(const vec4<T>& gl, const vec4<T>& gh, T hm
 }
 
 // The group cache stores four 16-bit union slots per 64-bit word, ELL
-// layout word[(g * capq + j / 4) * GROUP + lane], slot j at bits 16 (j % 4);
-// unused slots of the last word hold SLOT_NONE.
+// layout word[(gbase[g] + j / 4) * GROUP + lane], slot j at bits 16 (j % 4);
+// unused slots of the last word hold SLOT_NONE.  A group whose union holds
+// more than 65535 particles (slots_wide) stores 32-bit slots instead, two per
+// word: slot j at bits 32 (j % 2) of word j / 2, padding SLOT32_NONE.
 constexpr u32 SLOT_NONE = 0xffffu;
+constexpr u32 SLOT32_NONE = 0xffffffffu;
 __device__ inline u32 slot_of(u64 w, u32 r) { return (u32)(w >> (16u * r)) & 0xffffu; }
+__device__ inline u32 slot32_of(u64 w, u32 r) { return (u32)(w >> (32u * r)); }
+__host__ __device__ inline bool slots_wide(u32 union_size) { return union_size > 0xffffu; }
 
 // ------------------------------------------------------------- M4 spline --
 // f(q) = 1 - 3/2 q^2 + 3/4 q^3 (q<1), (2-q)^3/4 (1<=q<2), 0 beyond;

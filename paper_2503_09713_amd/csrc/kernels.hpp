@@ -40,7 +40,8 @@ template <class T> struct OutPtrs {
 // (uleaf, with the union slot where each leaf starts, uslot; ucnt leaves,
 // ustot slots; capacity cap per group), and per particle its neighbours as
 // 16-bit union slots, four per word, ELL layout with a capacity per group:
-// nlist[(gbase[g] + j / 4) * GROUP + lane]; ncnt[a] of them.
+// nlist[(gbase[g] + j / 4) * GROUP + lane]; ncnt[a] of them (32-bit slots,
+// two per word, for a union of more than 65535 particles: see slot32_of).
 struct CacheView {
     const u32 *uleaf, *uslot, *ucnt, *ustot;
     i64 cap;
@@ -150,9 +151,9 @@ void launch_cache_plan(const u32* ustot, const u32* gneed, i64 ngroups, u32 dflt
 void launch_cache_regrow(const u32* gneed, i64 ngroups, u32* gcap, u64* gbase, u8* gredo,
                          hipStream_t st);
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
-                            const u32* uleaf, const u32* uslot, const u32* ucnt, const u64* gbase,
-                            const u64* nlist, const u32* ncnt, const u64* off, u32* list,
-                            hipStream_t st);
+                            const u32* uleaf, const u32* uslot, const u32* ucnt, const u32* ustot,
+                            const u64* gbase, const u64* nlist, const u32* ncnt, const u64* off,
+                            u32* list, hipStream_t st);
 
 // sph.hip
 void launch_fill_u32(u32* p, i64 n, u32 v, hipStream_t st);

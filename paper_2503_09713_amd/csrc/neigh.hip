@@ -8,7 +8,8 @@
 // for some target leaf A of the group, with periodic images and a slight
 // outward inflation so that the prune is a superset of the exact particle
 // test.  The kept leaves, in ascending order, form the group's candidate
-// "union"; their particles are numbered by 16-bit slots.
+// "union"; their particles are numbered by 16-bit slots (32-bit slots for a
+// union of more than 65535 particles).
 // Stage 2 runs one workgroup per group: each particle prefilters the union's
 // leaves by box and tests their particles with the exact object-object
 // criterion in the storage type, writing the accepted slots (ascending)
@@ -195,7 +196,6 @@ k_group_leaves_serial(bool only_marked, const vec4<T>* __restrict__ blo, const v
     }
     u32 f = stack_over ? 1u : 0u;
     if (count > cap) f |= 2u;
-    if (slots > 0xffffu) f |= 8u;
     if (f) atomicOr(&flags[0], f);
     // largest leaf count (for the capacity of the next build)
     const u32 wmax = wave_max(count);
@@ -404,7 +404,6 @@ k_group_leaves_wave(const vec4<T>* __restrict__ blo, const vec4<T>* __restrict__
         ustot[g] = slots;
         u32 f = 0;
         if ((i64)count > cap) f |= 2u;
-        if (slots > 0xffffu) f |= 8u;
         if (f) atomicOr(&flags[0], f);
         if (count > __hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(&flags[1], count);
@@ -525,6 +524,36 @@ __device__ inline void queue_flush2(LaneQueue& lq, u32 capq)
     }
 }
 
+// The queue of a group with 32-bit slots (a union of more than 65535
+// particles, rare: a few groups that span a sparse region next to a dense
+// one): two entries per word, the pending one held in a register.
+struct WideQueue {
+    u32 pend;     // an accepted slot waiting for the second half of its word
+    u32 n;        // 1 if pend holds one
+    u32 q;        // ELL words completed so far
+    u32 capq;
+    u64* out;     // where word q goes
+};
+
+__device__ inline void queue_append(WideQueue& wq, u32 s, u32 capq)
+{
+    if (wq.n) {
+        if (wq.q < capq) *wq.out = (u64)wq.pend | ((u64)s << 32);
+        wq.out += GROUP;
+        ++wq.q;
+        wq.n = 0u;
+    } else {
+        wq.pend = s;
+        wq.n = 1u;
+    }
+}
+__device__ inline void queue_put(WideQueue& wq, u32 s, bool acc)
+{
+    if (acc) queue_append(wq, s, wq.capq);
+}
+__device__ inline void queue_flush(WideQueue&, u32) {}
+__device__ inline void queue_flush2(WideQueue&, u32) {}
+
 // Per-particle leaf test (groups that need no minimum image): the gaps from
 // the particle to the leaf's tight box, g = max(lo - x_a, x_a - hi, 0) per
 // axis, give d2 = fma(gz, gz, fma(gy, gy, gx gx)).  For any particle b of the
@@ -550,10 +579,10 @@ __device__ inline bool leaf_reach(const vec4<T>& pa, T qa, const vec4<T>& bl, co
 
 // Tests the particles [b0, b1) of one union leaf (union slots from sl) and
 // queues the accepted ones (the per-lane walk).
-template <class T, bool LDS, bool WRAP>
+template <class T, bool LDS, bool WRAP, class Q>
 __device__ inline void cache_leaf(const vec4<T>& pa, T qa, const Box<T>& bx, T rkc,
                                   u32 b0, u32 b1, u32 sl, const vec4<T>* s_upos,
-                                  const vec4<T>* posh, LaneQueue& lq, u32 capq)
+                                  const vec4<T>* posh, Q& lq, u32 capq)
 {
     u32 b = b0;
     for (; b + 8 <= b1; b += 8) {         // eight candidate loads in flight
@@ -595,13 +624,13 @@ __device__ inline void cache_leaf(const vec4<T>& pa, T qa, const Box<T>& bx, T r
 // lane's copy of the mask, so the walk's iterations follow the leaves the
 // lane really visits (a skip inside the walk would cost the wave the test
 // and the visit).
-template <class T, bool LDS, bool WRAP>
+template <class T, bool LDS, bool WRAP, class Q>
 __device__ inline void cache_walk_lane(const vec4<T>& pa, T qa, bool live, u32 S, u32 nu,
                                        const Box<T>& bx,
                                        T rkc, const u64* mrow, const u32* s_b0, const u32* s_b1,
                                        const u32* s_slot, const vec4<T>* s_lo,
                                        const vec4<T>* s_hi, const vec4<T>* s_upos,
-                                       const vec4<T>* posh, LaneQueue& lq, u32 capq, u32& tested)
+                                       const vec4<T>* posh, Q& lq, u32 capq, u32& tested)
 {
     bool refine = false;
     if (!WRAP) {
@@ -639,7 +668,7 @@ __device__ inline void cache_walk_lane(const vec4<T>& pa, T qa, bool live, u32 S
         cur &= cur - 1;
         const u32 b0 = s_b0[j], b1 = s_b1[j];
         tested += b1 - b0;
-        cache_leaf<T, LDS, WRAP>(pa, qa, bx, rkc, b0, b1, s_slot[j], s_upos, posh, lq, capq);
+        cache_leaf<T, LDS, WRAP, Q>(pa, qa, bx, rkc, b0, b1, s_slot[j], s_upos, posh, lq, capq);
     }
 }
 
@@ -810,6 +839,8 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     u32 tested = 0;
     u64 wbuf = 0, boxtests = 0;   // wbuf: the queue's pending entries between chunks
     LaneQueue lq{(u16*)s_tbox + threadIdx.x * QSTRIDE, 0u, 0u, out};
+    const bool w32 = slots_wide(S);    // block-uniform; then in_lds is false
+    WideQueue wq{0u, 0u, 0u, capq, out};
     for (u32 c0 = 0; c0 < nu; c0 += LCHUNK) {
         const u32 c1 = min(nu, c0 + LCHUNK);
         const u32 nl = c1 - c0;
@@ -875,7 +906,11 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
             uniform = 10u * all < 14u * wave_max(mine);
         }
         if (lq.pos) q_st(lq.e, wbuf);   // pending entries
-        if (mode != 1 && uniform) {
+        if (w32) {
+            // exact for interior groups too: no image is closer there
+            cache_walk_lane<T, false, true>(pa, qa, live, S, nu, bx, rkc, s_mask[ta], s_b0, s_b1,
+                                            s_slot, s_lo, s_hi, s_upos, posh, wq, capq, tested);
+        } else if (mode != 1 && uniform) {
             if (in_lds && interior)
                 cache_walk_wave<T, true, false>(pa, qa, live, bx, rkc, wm, s_b0, s_b1, s_slot,
                                                 s_upos, posh, lq, capq, tested);
@@ -902,9 +937,11 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         }
         wbuf = lq.pos ? q_ld(lq.e) : 0ull;
     }
-    const u32 c = 4u * lq.q + lq.pos;
+    const u32 c = w32 ? 2u * wq.q + wq.n : 4u * lq.q + lq.pos;
     if (live) {
-        if (c & 3u) {
+        if (w32) {
+            if (wq.n && wq.q < capq) *wq.out = (u64)wq.pend | ((u64)SLOT32_NONE << 32);
+        } else if (c & 3u) {
             for (u32 r = c & 3u; r < 4u; ++r) wbuf |= (u64)SLOT_NONE << (16u * r);
             const u32 q = c >> 2;
             if (q < capq) out[(u64)q * GROUP] = wbuf;
@@ -919,13 +956,15 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         }
     }
     // the group's need in words (for the next build's plan and a regrow)
-    const u32 wmax = block_reduce<GROUP>(live ? (c + 3u) >> 2 : 0u, (u32*)s_w,
+    const u32 esh = w32 ? 1u : 2u;     // log2 of the entries per word
+    const u32 wmax = block_reduce<GROUP>(live ? (c + (1u << esh) - 1u) >> esh : 0u, (u32*)s_w,
                                          [](u32 x, u32 y) { return x > y ? x : y; });
     if (threadIdx.x == 0) {
         gneed[g] = wmax;
         if (wmax > capq) atomicOr(&flags[0], 4u);
-        if (4u * wmax > __hip_atomic_load(&flags[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            atomicMax(&flags[2], 4u * wmax);
+        const u32 ecap = wmax << esh;
+        if (ecap > __hip_atomic_load(&flags[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&flags[2], ecap);
     }
 }
 
@@ -937,7 +976,8 @@ __global__ void k_cache_plan(const u32* __restrict__ ustot, const u32* __restric
     if (g >= ngroups) return;
     const u32 need = gneed ? gneed[g] : 0u;
     u32 w = need ? need + need / 4u + 2u : dflt;
-    const u32 top = (ustot[g] + 3u) / 4u + 1u;     // a lane holds at most the union
+    const u32 S = ustot[g];                        // a lane holds at most the union
+    const u32 top = slots_wide(S) ? (S + 1u) / 2u + 1u : (S + 3u) / 4u + 1u;
     gcap[g] = w < top ? w : top;
 }
 
@@ -964,8 +1004,8 @@ __global__ void k_cache_regrow(const u32* __restrict__ gneed, i64 ngroups, u32* 
 __global__ void __launch_bounds__(GROUP)
 k_cache_to_global(const u32* __restrict__ id, const GroupMap gm, i64 cap,
                   const u32* __restrict__ uleaf, const u32* __restrict__ uslot,
-                  const u32* __restrict__ ucnt, const u64* __restrict__ gbase,
-                  const u64* __restrict__ nlist,
+                  const u32* __restrict__ ucnt, const u32* __restrict__ ustot,
+                  const u64* __restrict__ gbase, const u64* __restrict__ nlist,
                   const u32* __restrict__ ncnt, const u64* __restrict__ off, u32* __restrict__ list)
 {
     const i64 g = blockIdx.x;
@@ -978,9 +1018,10 @@ k_cache_to_global(const u32* __restrict__ id, const GroupMap gm, i64 cap,
     const u32* sl = uslot + g * cap;
     const u32* ul = uleaf + g * cap;
     const u32 c = ncnt[a];
+    const bool w32 = slots_wide(ustot[g]);
     for (u32 j = 0; j < c; ++j) {
-        const u64 w = nlist[(gbase[g] + (j >> 2)) * GROUP + threadIdx.x];
-        const u32 s = slot_of(w, j & 3u);
+        const u64 w = nlist[(gbase[g] + (w32 ? j >> 1 : j >> 2)) * GROUP + threadIdx.x];
+        const u32 s = w32 ? slot32_of(w, j & 1u) : slot_of(w, j & 3u);
         u32 lo = 0, hi = nu - 1;       // last leaf whose start slot <= s
         while (lo < hi) {
             const u32 mid = (lo + hi + 1) >> 1;
@@ -1059,13 +1100,13 @@ void launch_cache_regrow(const u32* gneed, i64 ngroups, u32* gcap, u64* gbase, u
 }
 
 void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 cap,
-                            const u32* uleaf, const u32* uslot, const u32* ucnt, const u64* gbase,
-                            const u64* nlist, const u32* ncnt, const u64* off, u32* list,
-                            hipStream_t st)
+                            const u32* uleaf, const u32* uslot, const u32* ucnt, const u32* ustot,
+                            const u64* gbase, const u64* nlist, const u32* ncnt, const u64* off,
+                            u32* list, hipStream_t st)
 {
     if (ngroups <= 0) return;
     hipLaunchKernelGGL(k_cache_to_global, dim3((unsigned)ngroups), dim3(GROUP), 0, st, id, gm, cap,
-                       uleaf, uslot, ucnt, gbase, nlist, ncnt, off, list);
+                       uleaf, uslot, ucnt, ustot, gbase, nlist, ncnt, off, list);
 }
 
 #define INST(T)                                                                                   \

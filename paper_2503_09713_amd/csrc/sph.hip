@@ -82,12 +82,15 @@ template <class T> __global__ void k_copy_h(const vec4<T>* __restrict__ posh, T*
 // One LDS tile: all entries, four per word, padding skipped.  Several
 // tiles: entries with slots in [c0, c1), resuming at entry j.
 // f(slot) for each stored slot (single visits; for heavy per-pair bodies).
+// The next word is loaded while the current one is used; the load is
+// unconditional (the last word is read again at the end) so that no branch
+// around it makes the compiler wait for it before the current word.
 template <class F> __device__ inline void entries_each(const u64* my, u32 cnt, F&& f)
 {
     const u32 nq = (cnt + 3u) >> 2;
     u64 w = nq ? my[0] : 0;
     for (u32 q = 0; q < nq; ++q) {
-        const u64 wn = (q + 1 < nq) ? my[(u64)(q + 1) * GROUP] : 0;   // prefetch
+        const u64 wn = my[(u64)(q + 1 < nq ? q + 1 : q) * GROUP];   // prefetch
 #pragma unroll
         for (u32 r = 0; r < 4u; ++r) {
             const u32 sl = slot_of(w, r);
@@ -103,7 +106,7 @@ template <class F> __device__ inline void entries_words(const u64* my, u32 cnt, 
     const u32 nq = min((cnt + 3u) >> 2, q1);
     u64 w = q0 < nq ? my[(u64)q0 * GROUP] : 0;
     for (u32 q = q0; q < nq; ++q) {
-        const u64 wn = (q + 1 < nq) ? my[(u64)(q + 1) * GROUP] : 0;   // prefetch
+        const u64 wn = my[(u64)(q + 1 < nq ? q + 1 : q) * GROUP];   // prefetch (see entries_each)
 #pragma unroll
         for (u32 r = 0; r < 4u; ++r) {
             const u32 sl = slot_of(w, r);
@@ -113,12 +116,14 @@ template <class F> __device__ inline void entries_words(const u64* my, u32 cnt, 
     }
 }
 
+// (w32: the group stores 32-bit slots, two per word.)
 template <class F>
-__device__ inline void entries_tile(const u64* my, u32 cnt, u32& j, u32 c0, u32 c1, F&& f)
+__device__ inline void entries_tile(const u64* my, u32 cnt, u32& j, u32 c0, u32 c1, bool w32,
+                                    F&& f)
 {
     while (j < cnt) {
-        const u64 w = my[(u64)(j >> 2) * GROUP];
-        const u32 sl = slot_of(w, j & 3u);
+        const u64 w = my[(u64)(w32 ? j >> 1 : j >> 2) * GROUP];
+        const u32 sl = w32 ? slot32_of(w, j & 1u) : slot_of(w, j & 3u);
         if (sl >= c1) break;
         f(sl - c0);
         ++j;
@@ -288,7 +293,7 @@ density_group(const i64 g, vec4<T>* __restrict__ posh, const T* __restrict__ hn,
                 __syncthreads();
                 stage_union<T, 1>(src, dst, id, ul, us, nu, c0, c1);
                 __syncthreads();
-                if (active) entries_tile(my, cnt, j, c0, c1, add);
+                if (active) entries_tile(my, cnt, j, c0, c1, slots_wide(S), add);
             }
         }
         if (active) {
@@ -462,9 +467,11 @@ force_group(const i64 g, const vec4<T>* __restrict__ posh, const vec4<T>* __rest
     // this thread's share of the list: words [q0, q1) (with two threads the
     // first takes the first ceil(nq/2) words), entries [e0, e1) for the
     // tiled path
-    const u32 nq = (cnt + 3u) >> 2, qh = SPLIT > 1 ? (nq + 1u) >> 1 : nq;
+    const bool w32 = slots_wide(S);
+    const u32 esh = w32 ? 1u : 2u;      // log2 of the entries per word
+    const u32 nq = (cnt + (1u << esh) - 1u) >> esh, qh = SPLIT > 1 ? (nq + 1u) >> 1 : nq;
     const u32 q0 = half ? qh : 0u, q1 = half ? nq : qh;
-    const u32 e0 = min(cnt, 4u * q0), e1 = min(cnt, 4u * q1);
+    const u32 e0 = min(cnt, q0 << esh), e1 = min(cnt, q1 << esh);
     T ax = T(0), ay = T(0), az = T(0), du = T(0), lam = T(0), vmax = ca;
     u32 inter = 0;                      // interacting pairs (profiling)
     const bool wrap = !group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
@@ -545,7 +552,7 @@ force_group(const i64 g, const vec4<T>* __restrict__ posh, const vec4<T>* __rest
             __syncthreads();
             invert_h(c1 - c0);
             __syncthreads();
-            entries_tile(my, e1, j, c0, c1, pair);
+            entries_tile(my, e1, j, c0, c1, w32, pair);
         }
     }
     // first half + second half, in that order
@@ -697,7 +704,7 @@ k_alpha(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
             __syncthreads();
             stage_union<T, 3>(src, dst, id, ul, us, nu, c0, c1);
             __syncthreads();
-            if (live) entries_tile(my, cnt, j, c0, c1, pair);
+            if (live) entries_tile(my, cnt, j, c0, c1, slots_wide(S), pair);
         }
     }
     if (!live) return;

@@ -236,6 +236,49 @@ def test_cache_group_regrow(torch_cuda):
     ctx.close()
 
 
+def test_cache_wide_slots(torch_cuda):
+    """A 42^3 clump (74088 particles, isolated) and one particle ten clump
+    widths away: that particle's self-consistent h reaches across the whole
+    clump, so its group's candidate union holds every particle, more than the
+    65535 that 16-bit slots number, and the group stores 32-bit slots.  Tree
+    and every neighbour set bit-exact; then density (h-rho relation) and force
+    of that group's particles and of a sample against the oracle, through the
+    tiled paths of both kernels."""
+    _say("[tree] union of more than 65535 particles: 32-bit slots")
+    base = gen.lattice(42, 97, dtype=np.float32)
+    p = base.subset(np.concatenate([np.arange(base.n), [0]]))
+    p.periodic = False
+    far = p.n - 1
+    p.x[far], p.y[far], p.z[far] = np.float32(10.5), np.float32(0.5), np.float32(0.5)
+    lo, hi = _box_for_oracle(p)
+    h0 = p.h.astype(np.float64)
+    h0[far] = 5.0
+    hf, _, _, fl = oracle.density(p.x, p.y, p.z, h0, lo, hi, False, p.mass, targets=[far])
+    assert fl[0] == 0 and 2.2 * hf[0] > 10.6        # its cache radius covers the clump
+    p.h[far] = np.float32(hf[0])
+    ctx = _ctx(torch_cuda, n_red=3)
+    ps = _upload(p, torch_cuda)
+    ctx.build_tree(ps)
+    ex = check_tree(ctx, p, 3)
+    go, gl, ids = ex["group_off"].astype(np.int64), ex["group_leaves"].astype(np.int64), ex["id"]
+    kpos = int(np.nonzero(ex["eps"] == far)[0][0])
+    gf = kpos // 256
+    seg = gl[go[gf]:go[gf + 1]]
+    assert int((ids[seg + 1].astype(np.int64) - ids[seg]).sum()) > 65535
+    ctx.density(ps)
+    ctx.force(ps)
+    g = {k: v.astype(np.float64) for k, v in ps.host("h", "omega", "ax", "ay", "az", "dudt").items()}
+    t = np.unique(np.concatenate([ex["eps"][256 * gf:min(p.n, 256 * gf + 256)].astype(np.int64),
+                                  np.arange(0, p.n, 499)]))
+    _check_h_rho_relation(p, g["h"], False, subset=t)
+    rho_g = p.mass * (1.2 / g["h"]) ** 3
+    ref = oracle.force(p.x, p.y, p.z, p.vx, p.vy, p.vz, p.u, g["h"], rho_g, g["omega"], lo, hi,
+                       False, p.mass, targets=t)
+    ea, eu = _force_err({k: v[t] for k, v in g.items()}, ref)
+    assert ea.max() <= 1e-4 and eu.max() <= 1e-4, (ea.max(), eu.max())
+    ctx.close()
+
+
 def test_tree_leaf_pass_fallback(torch_cuda):
     """5000 coincident particles in a 20^3 lattice: the run of equal keys is
     longer than the fused leaf pass's window (a tile plus halos), so the tile
