@@ -331,19 +331,30 @@ def run_batched(args, shsph, torch):
     for _ in range(W):
         ctx.step_batch(hs)
     torch.cuda.synchronize()
-    ctx.set_profiling(True)
+    g0 = ctx.get_info()
     t0 = time.perf_counter()
     for _ in range(K):
         ctx.step_batch(hs)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    g1 = ctx.get_info()
+    res["captured_passes"] = g1["graph_passes"] - g0["graph_passes"]
+    res["captured_aborts"] = g1["graph_aborts"] - g0["graph_aborts"]
+    # stage breakdown: two more steps launch by launch with stage events
+    SP = 2
+    ctx.set_profiling(True)
+    for _ in range(SP):
+        ctx.step_batch(hs)
+    torch.cuda.synchronize()
     stages = ctx.stage_times()
     ctx.set_profiling(False)
     ctx.close()
-    log(f"[batched] batched {1e3 * tb / K:.2f} ms/step")
+    log(f"[batched] batched {1e3 * tb / K:.2f} ms/step ({res['captured_passes']} of {K} passes "
+        f"from the captured graph, {res['captured_aborts']} switched off)")
+    # plain: the same kernels, one instance per pass, launch by launch
     ctx = shsph.Context(0, n_red=tune["n_red"], stage2_mode=tune["stage2_mode"],
                         force_split=tune["force_split"],
-                        fused_density_force=tune["fused_density_force"])
+                        fused_density_force=tune["fused_density_force"], graph_batch=0)
     hs = [ctx.instance_create(s) for s in sets]
     for _ in range(W):
         for h in hs:
@@ -360,7 +371,7 @@ def run_batched(args, shsph, torch):
     res.update({"value": ntot * K / tb, "unit": "particle-steps/s", "ms_per_step": 1e3 * tb / K,
                 "plain_value": ntot * K / tp, "plain_ms_per_step": 1e3 * tp / K,
                 "speedup_vs_plain": tp / tb,
-                "stages_ms_per_step": {k: round(v[0] / K, 4) for k, v in stages.items()}})
+                "stages_ms_per_step": {k: round(v[0] / SP, 4) for k, v in stages.items()}})
     return res
 
 

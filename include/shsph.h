@@ -110,6 +110,17 @@ typedef struct {
                                needed, the alpha switch is on, or the launch is not
                                possible.  Same results as force_split = 1.
                                Default 0; shsph_autotune may choose it. */
+    int32_t graph_batch;    /* 1 (default): a batched pass (shsph_step_batch,
+                               shsph_eval_batch, the serving loop) whose shape
+                               repeats the previous pass's (particle and group
+                               counts, instance boundary types, parameters,
+                               buffers) is recorded once as a hipGraph and
+                               replayed, with no host read until the pass ends;
+                               a pass that needs a capacity regrow, a cache
+                               rebuild or a fallback is switched off on the
+                               device and run again launch by launch.  Same
+                               results, bit for bit.  Not used while profiling.
+                               0: every pass launch by launch. */
 } shsph_params;
 
 #define SHSPH_KERNEL_M4 0
@@ -164,6 +175,8 @@ typedef struct {
     int32_t cache_capacity;  /* neighbour-cache entries per particle the context holds
                                 room for (grows when a build needs more) */
     double cfl_multiplier;   /* CFL multiplier for the next CFL step (App. G) */
+    int64_t graph_passes;    /* batched passes run from a captured graph (context total) */
+    int64_t graph_aborts;    /* captured passes switched off and run launch by launch */
 } shsph_info;
 
 /* Host buffers receiving the tree of the last build (test and debug use).

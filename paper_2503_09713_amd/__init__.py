@@ -47,7 +47,8 @@ class Params(C.Structure):
                 ("max_reruns", C.c_int32), ("alpha_switch", C.c_int32),
                 ("lambda_stiff", C.c_double), ("alpha_min", C.c_double),
                 ("alpha_max", C.c_double), ("sigma_decay", C.c_double),
-                ("force_split", C.c_int32), ("fused_density_force", C.c_int32)]
+                ("force_split", C.c_int32), ("fused_density_force", C.c_int32),
+                ("graph_batch", C.c_int32)]
 
 
 KERNELS = {"M4": 0, "M5": 1, "M6": 2, "C2": 3, "C4": 4, "C6": 5}
@@ -68,7 +69,8 @@ class Info(C.Structure):
                 ("max_iter_seen", C.c_int32), ("n_noconv", C.c_int32), ("dt_cfl", C.c_double),
                 ("dv_max", C.c_double), ("dv2_sum", C.c_double), ("v2_sum", C.c_double),
                 ("reruns", C.c_int32), ("cache_capacity", C.c_int32),
-                ("cfl_multiplier", C.c_double)]
+                ("cfl_multiplier", C.c_double), ("graph_passes", C.c_int64),
+                ("graph_aborts", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -81,6 +81,17 @@ struct shsph_ctx {
     i64 n = 0;
     int ninst = 0;
     i64 n_leaf = 0, n_internal = 0, n_groups = 0;
+    i64 lbase = 0;                              // node of leaf 0: n - ninst (fixed per pass shape)
+    bool capturing = false;                     // launches are being captured: no host reads
+    // captured batched passes
+    u64 alloc_gen = 0;                          // counts (re)allocations of device buffers
+    u64 param_gen = 0;                          // counts parameter changes
+    std::vector<i64> gkey;                      // the pass shape gexec was captured for
+    std::vector<i64> last_key;                  // the shape of the last launch-by-launch pass
+    std::vector<i64> nocap_key;                 // a shape whose capture failed (not retried)
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;           // records captures (launches go on `stream`)
+    i64 graph_passes = 0, graph_aborts = 0;
     i64 cap_leaf = 256;                         // per-group union leaves (stage 1)
     // stage-2 cache: capacity per group (words of 4 entries per lane), planned
     // each build from the need of the previous one (valid for gneed_groups)
@@ -103,7 +114,8 @@ struct shsph_ctx {
     Buf rec, nrec, rscan;                       // bottom-up box records
     Buf glo, ghi, uleaf, uslot, ucnt, ustot;    // stage 1, per group
     Buf nlist, ncnt, flags;                     // stage 2, per particle (ELL)
-    Buf gcap, gbase, gneed, gredo;              // stage 2, per group capacity / layout
+    Buf gcap, gbase, gneed, gredo;
+    Buf gstate;                                 // captured passes: gate words, gates, re-runs              // stage 2, per group capacity / layout
     Buf bpart;                                  // corrector partial sums
     Buf work[3];                                // work counters (profiling)
     i64 parts_pending = 0;                      // corrector blocks not yet folded
@@ -204,6 +216,8 @@ int ensure(shsph_ctx* c, Buf& b, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
     if (b.cap >= bytes) return SHSPH_OK;
+    if (c->capturing) return fail(c, SHSPH_EHIP, "a buffer would grow while a pass is captured");
+    ++c->alloc_gen;
     if (c->arena) {
         const size_t off = (c->arena_used + 255) & ~(size_t)255;
         const size_t want = (bytes + 255) & ~(size_t)255;
@@ -451,6 +465,7 @@ CacheView cache_view(shsph_ctx* c)
 {
     CacheView v;
     v.work = nullptr;
+    v.skip = nullptr;
     v.uleaf = P<u32>(c->uleaf); v.uslot = P<u32>(c->uslot);
     v.ucnt = P<u32>(c->ucnt); v.ustot = P<u32>(c->ustot);
     v.cap = c->cap_leaf;
@@ -468,6 +483,7 @@ CacheView cache_view(shsph_ctx* c)
 // ones (stepping); the gather then also forms v*, u*, v^{n+1/2}, u^{n+1/2}.
 // ---------------------------------------------------------------------------
 template <class T> int build_caches(shsph_ctx* c, const u8* redo = nullptr);
+template <class T> int build_tree_tables(shsph_ctx* c, i64 nl);
 
 template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const double* dt_dev, bool step)
 {
@@ -512,9 +528,11 @@ template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const d
     TRY(check_launch(c, "morton"));
     // stable radix sort of (key, index), then gather into key order
     prof_begin(c, S_SORT);
+    // (the nearly-sorted path reads a count on the host: not while capturing)
     const int sel = radix_sort_pairs(P<u64>(c->keys[0]), P<u32>(c->vals[0]), P<u64>(c->keys[1]),
                                      P<u32>(c->vals[1]), n, kbits, poff, ninst, P<u32>(c->hist),
-                                     P<u32>(c->flags) + FLAG_SORT, (u32*)c->pinned, st);
+                                     P<u32>(c->flags) + FLAG_SORT,
+                                     c->capturing ? nullptr : (u32*)c->pinned, st);
     prof_end(c);
     if (sel == -2) return fail(c, SHSPH_EHIP, "radix sort: reading the out-of-place count failed");
     if (sel < 0) return fail(c, SHSPH_ECAPACITY, "more than 2^30 - 2 particles in one pass");
@@ -540,6 +558,8 @@ template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const d
     c->xi_sel = 0;
     prof_end(c);
     TRY(check_launch(c, "leaves"));
+    // captured: the flags go to the pass's gate, the leaf count stays on the device
+    if (c->capturing) return build_tree_tables<T>(c, n);
     HIPTRY(c, hipMemcpyAsync(c->pinned, P<u32>(c->xscan) + n, sizeof(u32), hipMemcpyDeviceToHost, st));
     HIPTRY(c, hipMemcpyAsync((char*)c->pinned + 8, P<u32>(c->flags) + FLAG_LEAVES, 2 * sizeof(u32),
                              hipMemcpyDeviceToHost, st));
@@ -565,8 +585,21 @@ template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const d
     const i64 nl = *(u32*)c->pinned;
     c->n_leaf = nl;
     c->n_internal = nl - ninst;
-    // Karras tables + parents
-    const i64 ni = c->n_internal, nn = ni + nl;
+    return build_tree_tables<T>(c, nl);
+}
+
+// Karras tables, parents, then the boxes and caches.  Leaf j is node
+// lbase + j with lbase = n - ninst; nl bounds the launches (the leaf count,
+// or n while capturing, when the kernels find the count on the device).
+template <class T> int build_tree_tables(shsph_ctx* c, i64 nl)
+{
+    hipStream_t st = c->stream;
+    const i64 n = c->n;
+    const int ninst = c->ninst;
+    const i64* poff = P<i64>(c->poff_d);
+    const i64 lbase = n - ninst;
+    c->lbase = lbase;
+    const i64 ni = nl - ninst, nn = lbase + nl;
     TRY(ensure(c, c->lchild, std::max<i64>(ni, 1) * sizeof(u32)));
     TRY(ensure(c, c->rchild, std::max<i64>(ni, 1) * sizeof(u32)));
     TRY(ensure(c, c->endrange, std::max<i64>(ni, 1) * sizeof(u32)));
@@ -579,12 +612,13 @@ template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const d
     TRY(ensure(c, c->bhi, nn * sizeof(vec4<T>)));
     prof_begin(c, S_KARRAS);
     launch_inst_leaves(poff, ninst, P<u32>(c->xscan), n, P<i64>(c->leaf_off_d), P<i64>(c->ioff_d),
-                       P<u32>(c->root_d), P<u32>(c->parent), ni, st);
+                       P<u32>(c->root_d), P<u32>(c->parent), lbase, st);
     TreePtrs t;
     t.lchild = P<u32>(c->lchild); t.rchild = P<u32>(c->rchild); t.endrange = P<u32>(c->endrange);
     t.lflag = P<u8>(c->lflag); t.rflag = P<u8>(c->rflag);
     t.child = P<u32>(c->child); t.parent = P<u32>(c->parent);
-    launch_karras(P<u64>(c->mu_leaf), P<i64>(c->leaf_off_d), P<i64>(c->ioff_d), ninst, ni, t, st);
+    launch_karras(P<u64>(c->mu_leaf), P<i64>(c->leaf_off_d), P<i64>(c->ioff_d), ninst, lbase, ni,
+                  t, st);
     prof_end(c);
     TRY(check_launch(c, "karras"));
     c->restarts = 0;
@@ -601,7 +635,10 @@ template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const d
 template <class T> int build_caches(shsph_ctx* c, const u8* redo)
 {
     hipStream_t st = c->stream;
-    const i64 n = c->n, nl = c->n_leaf, ni = c->n_internal, G = c->n_groups;
+    // launch bounds: the leaf and internal counts, or their largest values
+    // while capturing (the kernels read the counts on the device)
+    const i64 n = c->n, lb = c->lbase, G = c->n_groups;
+    const i64 nl = c->capturing ? n : c->n_leaf, ni = c->capturing ? lb : c->n_internal;
     const InstDev* inst = P<InstDev>(c->inst_d);
     const int ninst = c->ninst;
     const vec4<T>* posh = P<vec4<T>>(c->posh);
@@ -621,7 +658,7 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
     prof_begin(c, S_BOXES);
     launch_fill_u32(P<u32>(c->arrive), std::max<i64>(ni, 1), 0u, st);
     launch_fill_u32(P<u32>(c->flags), 4, 0u, st);
-    launch_boxes_up<T>(posh, P<u32>(c->id), nl, ni, P<u32>(c->child), P<u32>(c->parent),
+    launch_boxes_up<T>(posh, P<u32>(c->id), nl, lb, P<u32>(c->child), P<u32>(c->parent),
                        P<u32>(c->endrange), P<i64>(c->ioff_d), P<i64>(c->leaf_off_d), ninst,
                        P<u32>(c->arrive), P<u32>(c->rec), P<u32>(c->nrec), P<u32>(c->rscan),
                        c->scan_tmp.p, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->flags), st);
@@ -643,7 +680,7 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
         if (run_stage1) {
         prof_begin(c, S_STAGE1);
         launch_group_leaves<T>(P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->child),
-                               P<u32>(c->id), P<u32>(c->xscan), ni, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), G, gm,
+                               P<u32>(c->id), P<u32>(c->xscan), lb, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), G, gm,
                                P<u32>(c->root_d), inst, rk, c->cap_leaf,
                                (u32)c->prm.spread_slots, c->prm.stage1_serial != 0,
                                P<u32>(c->uleaf),
@@ -666,7 +703,7 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
         // the buffer is flagged, nothing written)
         prof_begin(c, S_STAGE2);
         launch_group_cache<T>(posh, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->id),
-                              P<u32>(c->xscan), ni, gm, G,
+                              P<u32>(c->xscan), lb, gm, G,
                               inst, rk, rk, c->cap_leaf, P<u32>(c->uleaf), P<u32>(c->uslot),
                               P<u32>(c->ucnt), P<u32>(c->ustot), P<u64>(c->gbase), P<u32>(c->gcap),
                               (u64)(c->nlist.cap / WORD_BYTES), P<u32>(c->gneed), gredo,
@@ -676,6 +713,10 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
         prof_end(c);
         TRY(check_launch(c, "stage2"));
         launch_root_hmax<T>(P<vec4<T>>(c->blo), P<u32>(c->root_d), ninst, P<double>(c->rhmax_d), st);
+        if (c->capturing) {      // one attempt; the flags and radii go to the pass's gate
+            c->gneed_groups = G;
+            return SHSPH_OK;
+        }
         HIPTRY(c, hipMemcpyAsync(c->pinned, c->flags.p, FLAG_WORDS * sizeof(u32),
                                  hipMemcpyDeviceToHost, st));
         HIPTRY(c, hipMemcpyAsync((char*)c->pinned + FLAG_WORDS * sizeof(u32), c->rhmax_d.p,
@@ -1107,6 +1148,7 @@ int pool_grow(shsph_ctx* c, i64 need)
     }
     pool_put(q, q.cap, ncap - q.cap);
     q.cap = ncap;
+    ++c->alloc_gen;
     return SHSPH_OK;
 }
 
@@ -1158,9 +1200,269 @@ template <class T> OutPtrs<T> pool_out(shsph_ctx* c)
 // Every stage is one launch over all of them.  Instances whose h iteration
 // does not settle are reported through their stats (SHSPH_ENOCONV); the
 // others are complete.
-template <class T> int batch_pass(shsph_ctx* c, const std::vector<Inst*>& b, const std::vector<double>& dt)
+// ---------------------------------------------------------------------------
+// Captured batched passes.  A pass whose shape repeats the previous pass's
+// (same particle and group counts, instance boundary types, parameters,
+// buffers and stream) is recorded once as a hipGraph and then replayed: the
+// launch sequence is the launch-by-launch pass's, with every decision the
+// host takes between launches moved to the device (no read-back until the
+// end).  Leaf and internal counts stay on the device (leaf j at node lbase +
+// j, launches sized for n leaves, the kernels bounded by the count); the
+// nearly-sorted path of the sort is not used; capacity, sort, leaf-pass and
+// box conditions and an h past chi h_cache set an abort word that switches
+// every later launch off, after which the host runs the pass again launch by
+// launch (the caller's arrays are written only by the corrector, which the
+// abort switches off); the corrector re-runs are max_reruns rounds, each
+// switched on by the previous round's check on the device.  Results are the
+// launch-by-launch pass's, bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int GS_WORDS = 64;                 // gate words: [0] abort, [1 + r] round r off
+constexpr int GS_ROUNDS = GS_WORDS - 2;
+
+bool graph_usable(shsph_ctx* c)
+{
+    return c->prm.graph_batch && !c->prof.on && !c->arena && c->prm.max_reruns <= GS_ROUNDS;
+}
+
+std::vector<i64> pass_key(shsph_ctx* c)
+{
+    std::vector<i64> k = {c->n, c->n_groups, c->ninst, c->dtype, (i64)c->alloc_gen,
+                          (i64)c->param_gen, c->cap_leaf, c->gneed_groups == c->n_groups ? 1 : 0,
+                          (i64)(intptr_t)c->stream};
+    for (const InstDev& in : c->inst_h) k.push_back(in.periodic);
+    return k;
+}
+
+void graph_drop(shsph_ctx* c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->gkey.clear();
+}
+
+// Buffers a captured pass uses at their largest (node tables for n leaves)
+// or with headroom (the neighbour cache), allocated before the capture.
+template <class T> int presize_capture(shsph_ctx* c)
+{
+    const i64 n = c->n, ninst = c->ninst, lb = n - ninst, G = c->n_groups;
+    const i64 ni = std::max<i64>(lb, 1), nn = lb + n;
+    TRY(ensure(c, c->lchild, ni * sizeof(u32)));
+    TRY(ensure(c, c->rchild, ni * sizeof(u32)));
+    TRY(ensure(c, c->endrange, ni * sizeof(u32)));
+    TRY(ensure(c, c->lflag, ni));
+    TRY(ensure(c, c->rflag, ni));
+    TRY(ensure(c, c->child, 2 * ni * sizeof(u32)));
+    TRY(ensure(c, c->arrive, ni * sizeof(u32)));
+    TRY(ensure(c, c->parent, nn * sizeof(u32)));
+    TRY(ensure(c, c->blo, nn * sizeof(vec4<T>)));
+    TRY(ensure(c, c->bhi, nn * sizeof(vec4<T>)));
+    const size_t nrc = boxes_rec_count(n);
+    const i64 nbb = (i64)(nrc / 128) + 1;
+    TRY(ensure(c, c->rec, nrc * sizeof(u32)));
+    TRY(ensure(c, c->nrec, (nbb + 1) * sizeof(u32)));
+    TRY(ensure(c, c->rscan, (nbb + 1) * sizeof(u32)));
+    const size_t WORD_BYTES = (size_t)GROUP * sizeof(u64);
+    TRY(ensure(c, c->nlist, (size_t)(c->cache_words + c->cache_words / 4 + 2 * G) * WORD_BYTES));
+    TRY(ensure(c, c->acc, n * sizeof(vec4<T>)));
+    TRY(ensure(c, c->bpart, ((n + GROUP - 1) / GROUP) * sizeof(BlockPart)));
+    TRY(ensure(c, c->gstate, GS_WORDS * sizeof(u32) + ninst * (sizeof(u32) + 2)));
+    return SHSPH_OK;
+}
+
+// The launches of one captured pass (see above).
+template <class T> int graph_body(shsph_ctx* c)
 {
     hipStream_t st = c->stream;
+    const int ninst = c->ninst;
+    const i64 n = c->n;
+    const double* dt_dev = P<double>(c->dt_inst_d);
+    u32* gs = P<u32>(c->gstate);
+    u32* reruns = gs + GS_WORDS;
+    u8* gate = (u8*)(reruns + ninst);
+    u8* redo = gate + ninst;
+    InstStat* stat = P<InstStat>(c->stat_d);
+    const InstDev* inst = P<InstDev>(c->inst_d);
+    const i64* poff = P<i64>(c->poff_d);
+    launch_stat_reset(stat, ninst, 3, nullptr, st);
+    TRY(build<T>(c, pool_fields<T>(c), n, dt_dev, true));
+    const double rk = kernel_support(c->prm.kernel) * c->prm.chi;
+    launch_gate_build(P<u32>(c->flags), 0x37u, FLAG_SORT, FLAG_LEAVES, P<double>(c->rhmax_d), inst,
+                      ninst, rk, gs, gate, reruns, st);
+    // density: the first attempt of the launch-by-launch pass
+    const SphParams sp = sph_params(c->prm);
+    SphParams sp1 = sp;       // the first force: the fused launch's (one thread per particle)
+    if (c->prm.fused_density_force) sp1.force_split = 1;
+    SortedPtrs<T> s = sorted<T>(c, false);
+    launch_stat_reset(stat, ninst, 1, nullptr, st);
+    launch_density<T>(s, P<u32>(c->id), group_map(c), c->n_groups, inst, sp, cache_view(c),
+                      P<T>(c->omega), P<vec4<T>>(c->thermo), P<u8>(c->status), stat, gate, st);
+    TRY(check_launch(c, "density"));
+    launch_gate_density(stat, ninst, gs, gate, st);
+    // force and corrector
+    const SortedPtrs<T> s1 = sorted<T>(c, true);
+    const OutPtrs<T> o = pool_out<T>(c);
+    const i64 nb = (n + GROUP - 1) / GROUP;
+    auto force_correct = [&](const u32* skip, const SphParams& spf) {
+        launch_stat_reset(stat, ninst, 2, nullptr, st, skip);
+        CacheView cvf = cache_view(c);
+        cvf.skip = skip;
+        launch_force<T>(s1, P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c), c->n_groups, inst,
+                        spf, cvf, P<vec4<T>>(c->acc), nullptr, stat, st);
+        launch_correct<T>(s1, P<vec4<T>>(c->acc), P<T>(c->omega), n, poff, ninst, inst, dt_dev,
+                          c->prm.hfact, o, stat, P<BlockPart>(c->bpart), st, skip);
+    };
+    force_correct(gs, sp1);
+    TRY(check_launch(c, "force"));
+    const int R = c->prm.eps_v > 0 ? c->prm.max_reruns : 0;
+    for (int r = 0; r < R; ++r) {
+        launch_fold_parts(P<BlockPart>(c->bpart), nb, ninst, stat, st, gs + r);
+        launch_rerun_decide(stat, poff, ninst, c->prm.eps_v, c->prm.max_reruns, r, gs, redo, reruns,
+                            st);
+        launch_velu_from_out<T>(o, n, poff, ninst, inst, redo, P<vec4<T>>(c->velu), st);
+        launch_thermo<T>(P<vec4<T>>(c->posh), P<vec4<T>>(c->velu), P<T>(c->omega), n, poff, ninst,
+                         inst, c->prm.hfact, c->prm.gamma, c->prm.alpha_av, nullptr,
+                         P<vec4<T>>(c->thermo), st, gs + 1 + r);
+        force_correct(gs + 1 + r, sp);
+        TRY(check_launch(c, "corrector re-run"));
+    }
+    launch_fold_parts(P<BlockPart>(c->bpart), nb, ninst, stat, st, gs + R);
+    return check_launch(c, "fold");
+}
+
+// Runs the pass from a captured graph when its shape allows (capturing it
+// first when the previous pass had this shape).  *done = false: the caller
+// runs the pass launch by launch (no graph, or the graph's pass aborted).
+// On success the instance stats are in the pinned staging, the re-run
+// counts in rr, and *rc is SHSPH_OK or SHSPH_ENOCONV.
+template <class T> int graph_pass(shsph_ctx* c, std::vector<int>& rr, int* rc, bool* done)
+{
+    *done = false;
+    if (!graph_usable(c)) return SHSPH_OK;
+    hipStream_t st = c->stream;
+    const int ninst = c->ninst;
+    std::vector<i64> key = pass_key(c);
+    if (!(c->gexec && key == c->gkey)) {
+        if (key != c->last_key || key == c->nocap_key) return SHSPH_OK;
+        graph_drop(c);
+        TRY(presize_capture<T>(c));
+        key = pass_key(c);
+        // recorded on a stream of our own (the caller's may be the null
+        // stream, which cannot be captured); nothing runs while recording
+        if (!c->cap_stream) HIPTRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        int brc = SHSPH_EHIP;
+        hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            c->stream = c->cap_stream;
+            c->capturing = true;
+            brc = graph_body<T>(c);
+            c->capturing = false;
+            c->stream = st;
+            e = hipStreamEndCapture(c->cap_stream, &g);
+        }
+        hipGraphExec_t x = nullptr;
+        const bool ok = brc == SHSPH_OK && e == hipSuccess && g &&
+                        hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        if (!ok) {          // this shape runs launch by launch from now on
+            (void)hipGetLastError();
+            c->nocap_key = key;
+            c->err.clear();
+            return SHSPH_OK;
+        }
+        c->gexec = x;
+        c->gkey = key;
+    }
+    HIPTRY(c, hipGraphLaunch(c->gexec, st));
+    // one read-back: stats, re-run counts, abort word, leaf count, cache words
+    const size_t o_rr = (size_t)ninst * sizeof(InstStat), o_gs = o_rr + ninst * sizeof(u32);
+    char* pin = (char*)c->pinned;
+    u32* gs = P<u32>(c->gstate);
+    HIPTRY(c, hipMemcpyAsync(pin, c->stat_d.p, o_rr, hipMemcpyDeviceToHost, st));
+    HIPTRY(c, hipMemcpyAsync(pin + o_rr, gs + GS_WORDS, ninst * sizeof(u32), hipMemcpyDeviceToHost, st));
+    HIPTRY(c, hipMemcpyAsync(pin + o_gs, gs, sizeof(u32), hipMemcpyDeviceToHost, st));
+    HIPTRY(c, hipMemcpyAsync(pin + o_gs + 4, P<u32>(c->xscan) + c->n, sizeof(u32),
+                             hipMemcpyDeviceToHost, st));
+    HIPTRY(c, hipMemcpyAsync(pin + o_gs + 8, P<u64>(c->gbase) + c->n_groups, sizeof(u64),
+                             hipMemcpyDeviceToHost, st));
+    HIPTRY(c, hipStreamSynchronize(st));
+    u32 abort_w = 0, nl = 0;
+    u64 words = 0;
+    memcpy(&abort_w, pin + o_gs, 4);
+    memcpy(&nl, pin + o_gs + 4, 4);
+    memcpy(&words, pin + o_gs + 8, 8);
+    if (abort_w) {
+        ++c->graph_aborts;
+        return SHSPH_OK;
+    }
+    ++c->graph_passes;
+    c->n_leaf = nl;
+    c->n_internal = (i64)nl - ninst;
+    c->cache_words = words;
+    c->restarts = 0;
+    c->parts_pending = 0;
+    rr.assign(ninst, 0);
+    u32 nc = 0;
+    const InstStat* hs = (const InstStat*)pin;
+    for (int k = 0; k < ninst; ++k) {
+        u32 r;
+        memcpy(&r, pin + o_rr + k * sizeof(u32), 4);
+        rr[k] = (int)r;
+        nc += hs[k].n_noconv;
+    }
+    *rc = nc ? fail(c, SHSPH_ENOCONV, "h iteration did not converge for " + std::to_string(nc) + " particles")
+             : SHSPH_OK;
+    *done = true;
+    return SHSPH_OK;
+}
+
+// The pass launch by launch; leaves the stats in the pinned staging.
+template <class T> int eager_pass(shsph_ctx* c, std::vector<int>& rr, int* rc_out)
+{
+    hipStream_t st = c->stream;
+    const int ninst = c->ninst;
+    launch_stat_reset(P<InstStat>(c->stat_d), ninst, 3, nullptr, st);
+    const double* dt_dev = P<double>(c->dt_inst_d);
+    TRY(build<T>(c, pool_fields<T>(c), c->n, dt_dev, true));
+    const i64 n = c->n;
+    TRY(ensure(c, c->acc, n * sizeof(vec4<T>)));
+    bool fdone = false;
+    const FusedForce<T> ff{P<vec4<T>>(c->acc), &fdone};
+    const int rc = run_density<T>(c, true, c->prm.fused_density_force ? &ff : nullptr);
+    if (rc != SHSPH_OK && rc != SHSPH_ENOCONV) return rc;
+    const SphParams sp = sph_params(c->prm);
+    if (!fdone) {
+        launch_stat_reset(P<InstStat>(c->stat_d), ninst, 2, nullptr, st);
+        prof_begin(c, S_FORCE);
+        CacheView cvf = cache_view(c);
+        cvf.work = work_ptr(c, 2);
+        launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
+                        c->n_groups, P<InstDev>(c->inst_d), sp, cvf, P<vec4<T>>(c->acc), nullptr,
+                        P<InstStat>(c->stat_d), st);
+        prof_end(c);
+        TRY(check_launch(c, "force"));
+    }
+    const i64 nb = (n + GROUP - 1) / GROUP;
+    TRY(ensure(c, c->bpart, nb * sizeof(BlockPart)));
+    prof_begin(c, S_CORRECT);
+    launch_correct<T>(sorted<T>(c, true), P<vec4<T>>(c->acc), P<T>(c->omega), n, P<i64>(c->poff_d),
+                      ninst, P<InstDev>(c->inst_d), dt_dev, c->prm.hfact, pool_out<T>(c),
+                      P<InstStat>(c->stat_d), P<BlockPart>(c->bpart), st);
+    prof_end(c);
+    c->parts_pending = nb;
+    TRY(check_launch(c, "correct"));
+    TRY(corrector_reruns<T>(c, pool_out<T>(c), dt_dev, rr));
+    if (c->parts_pending > 0) {
+        launch_fold_parts(P<BlockPart>(c->bpart), c->parts_pending, ninst, P<InstStat>(c->stat_d), st);
+        c->parts_pending = 0;
+    }
+    TRY(read_back(c, c->stat_d.p, ninst * sizeof(InstStat)));
+    *rc_out = rc;
+    return SHSPH_OK;
+}
+
+template <class T> int batch_pass(shsph_ctx* c, const std::vector<Inst*>& b, const std::vector<double>& dt)
+{
     const int ninst = (int)b.size();
     c->state = ST_NONE;
     c->ninst = ninst;
@@ -1189,43 +1491,14 @@ template <class T> int batch_pass(shsph_ctx* c, const std::vector<Inst*>& b, con
     c->dtype = c->pool.dtype;
     TRY(upload_instances(c));
     TRY(upload_extra(c, c->dt_inst_d.p, dt.data(), ninst * sizeof(double)));
-    launch_stat_reset(P<InstStat>(c->stat_d), ninst, 3, nullptr, st);
-    const double* dt_dev = P<double>(c->dt_inst_d);
-    TRY(build<T>(c, pool_fields<T>(c), off, dt_dev, true));
-    const i64 n = c->n;
-    TRY(ensure(c, c->acc, n * sizeof(vec4<T>)));
-    bool fdone = false;
-    const FusedForce<T> ff{P<vec4<T>>(c->acc), &fdone};
-    const int rc = run_density<T>(c, true, c->prm.fused_density_force ? &ff : nullptr);
-    if (rc != SHSPH_OK && rc != SHSPH_ENOCONV) return rc;
-    const SphParams sp = sph_params(c->prm);
-    if (!fdone) {
-        launch_stat_reset(P<InstStat>(c->stat_d), ninst, 2, nullptr, st);
-        prof_begin(c, S_FORCE);
-        CacheView cvf = cache_view(c);
-        cvf.work = work_ptr(c, 2);
-        launch_force<T>(sorted<T>(c, true), P<vec4<T>>(c->thermo), P<u32>(c->id), group_map(c),
-                        c->n_groups, P<InstDev>(c->inst_d), sp, cvf, P<vec4<T>>(c->acc), nullptr,
-                        P<InstStat>(c->stat_d), st);
-        prof_end(c);
-        TRY(check_launch(c, "force"));
-    }
-    const i64 nb = (n + GROUP - 1) / GROUP;
-    TRY(ensure(c, c->bpart, nb * sizeof(BlockPart)));
-    prof_begin(c, S_CORRECT);
-    launch_correct<T>(sorted<T>(c, true), P<vec4<T>>(c->acc), P<T>(c->omega), n, P<i64>(c->poff_d),
-                      ninst, P<InstDev>(c->inst_d), dt_dev, c->prm.hfact, pool_out<T>(c),
-                      P<InstStat>(c->stat_d), P<BlockPart>(c->bpart), st);
-    prof_end(c);
-    c->parts_pending = nb;
-    TRY(check_launch(c, "correct"));
     std::vector<int> rr;
-    TRY(corrector_reruns<T>(c, pool_out<T>(c), dt_dev, rr));
-    if (c->parts_pending > 0) {
-        launch_fold_parts(P<BlockPart>(c->bpart), c->parts_pending, ninst, P<InstStat>(c->stat_d), st);
-        c->parts_pending = 0;
+    int rc = SHSPH_OK;
+    bool done = false;
+    TRY(graph_pass<T>(c, rr, &rc, &done));
+    if (!done) {
+        TRY(eager_pass<T>(c, rr, &rc));
+        c->last_key = pass_key(c);
     }
-    TRY(read_back(c, c->stat_d.p, ninst * sizeof(InstStat)));
     prof_collect(c);
     const InstStat* hs = (const InstStat*)c->pinned;
     for (int k = 0; k < ninst; ++k) {
@@ -1344,6 +1617,7 @@ void shsph_params_default(shsph_params* p)
     p->sigma_decay = 0.1;
     p->force_split = 2;
     p->fused_density_force = 0;
+    p->graph_batch = 1;
 }
 
 // Every device buffer of a context.
@@ -1373,7 +1647,8 @@ static bool params_valid(const shsph_params& q)
              q.max_reruns < 0 || !(q.lambda_stiff >= 0) || !(q.sigma_decay > 0) ||
              !(q.alpha_min >= 0) || !(q.alpha_max >= q.alpha_min) ||
              (q.force_split != 1 && q.force_split != 2) ||
-             (q.fused_density_force != 0 && q.fused_density_force != 1));
+             (q.fused_density_force != 0 && q.fused_density_force != 1) ||
+             (q.graph_batch != 0 && q.graph_batch != 1));
 }
 
 int shsph_create(int device, const shsph_params* p, shsph_ctx** out)
@@ -1419,6 +1694,8 @@ int shsph_destroy(shsph_ctx* c)
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
     pool_release(c);
+    graph_drop(c);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     if (c->up_done) hipEventDestroy(c->up_done);
     for (Buf* b : all_bufs(c))
         if (b->p) hipFree(b->p);
@@ -1437,6 +1714,7 @@ int shsph_set_params(shsph_ctx* c, const shsph_params* p)
     if (c->server) return fail(c, SHSPH_ESTATE, "parameters cannot change while serving");
     if (!params_valid(*p)) return fail(c, SHSPH_EINVAL, "parameter out of range");
     c->prm = *p;
+    ++c->param_gen;
     return SHSPH_OK;
 }
 
@@ -1605,6 +1883,8 @@ int shsph_get_info(shsph_ctx* c, shsph_info* o)
     o->reruns = c->reruns_last;
     o->cache_capacity = c->n > 0 ? (int32_t)(4 * c->cache_words * GROUP / c->n) : 0;
     o->cfl_multiplier = c->lambda_cfl;
+    o->graph_passes = c->graph_passes;
+    o->graph_aborts = c->graph_aborts;
     HIPTRY(c, hipSetDevice(c->device));
     if (c->state >= ST_TREE) {
         u64 t1 = 0, t2 = 0;
@@ -1643,7 +1923,10 @@ int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
     if (c->state < ST_TREE) return fail(c, SHSPH_ESTATE, "no tree built");
     HIPTRY(c, hipSetDevice(c->device));
     hipStream_t st = c->stream;
+    // rows in compact numbering: internal nodes, then leaf j at ni + j (on
+    // the device leaf j is node lbase + j)
     const i64 n = c->n, nl = c->n_leaf, ni = c->n_internal, nn = ni + nl, G = c->n_groups;
+    const i64 lb = c->lbase;
     const size_t T = c->dtype == SHSPH_F32 ? 4 : 8;
     auto cp = [&](void* dst, const void* src, size_t bytes) -> int {
         if (dst && bytes) HIPTRY(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
@@ -1670,11 +1953,19 @@ int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
         TRY(cp(o->lflag, c->lflag.p, ni));
         TRY(cp(o->rflag, c->rflag.p, ni));
     }
-    TRY(cp(o->parent, c->parent.p, nn * 4));
+    if (o->parent) {
+        TRY(cp(o->parent, c->parent.p, ni * 4));
+        TRY(cp(o->parent + ni, P<u32>(c->parent) + lb, nl * 4));
+    }
     if (o->bmin || o->bmax || o->hmax) {
-        std::vector<char> lo(nn * 4 * T), hi(nn * 4 * T);
-        HIPTRY(c, hipMemcpyAsync(lo.data(), c->blo.p, nn * 4 * T, hipMemcpyDeviceToHost, st));
-        HIPTRY(c, hipMemcpyAsync(hi.data(), c->bhi.p, nn * 4 * T, hipMemcpyDeviceToHost, st));
+        const size_t row = 4 * T;
+        std::vector<char> lo(nn * row), hi(nn * row);
+        HIPTRY(c, hipMemcpyAsync(lo.data(), c->blo.p, ni * row, hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipMemcpyAsync(hi.data(), c->bhi.p, ni * row, hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipMemcpyAsync(lo.data() + ni * row, (char*)c->blo.p + lb * row, nl * row,
+                                 hipMemcpyDeviceToHost, st));
+        HIPTRY(c, hipMemcpyAsync(hi.data() + ni * row, (char*)c->bhi.p + lb * row, nl * row,
+                                 hipMemcpyDeviceToHost, st));
         HIPTRY(c, hipStreamSynchronize(st));
         for (i64 v = 0; v < nn; ++v) {
             for (int d = 0; d < 3; ++d) {
@@ -1688,7 +1979,7 @@ int shsph_export_tree(shsph_ctx* c, const shsph_tree_export* o)
         TRY(ensure(c, c->pbox, 6 * nn * sizeof(u32)));
         TRY(ensure(c, c->plen, nn * sizeof(i32)));
         launch_prefix_boxes(P<u64>(c->mu_leaf), P<i64>(c->leaf_off_d), P<i64>(c->ioff_d), c->ninst,
-                            ni, nl, P<u32>(c->endrange), P<u32>(c->parent), P<u32>(c->pbox),
+                            ni, nl, lb, P<u32>(c->endrange), P<u32>(c->parent), P<u32>(c->pbox),
                             P<i32>(c->plen), c->key_bits_built == 30 ? 33 : 0, st);
         TRY(check_launch(c, "prefix boxes"));
         TRY(cp(o->pbox, c->pbox.p, 6 * nn * 4));
@@ -1923,11 +2214,18 @@ int shsph_autotune(shsph_ctx* c, const int64_t* handles, int32_t count, int32_t*
                 c->prm.stage2_mode = md;
                 c->prm.force_split = fs ? fs : 1;
                 c->prm.fused_density_force = fs ? 0 : 1;
+                ++c->param_gen;
                 double t = 0;
-                for (int rep = 0; rep < 2; ++rep) {      // the first pass sizes buffers
+                // the first pass sizes buffers, the second records a captured
+                // pass (when those are on), the third is timed
+                for (int rep = 0; rep < 3; ++rep) {
                     const auto t0 = std::chrono::steady_clock::now();
                     const int rc = run_pass(c, b, zero);
-                    if (rc != SHSPH_OK && rc != SHSPH_ENOCONV) { c->prm = keep; return rc; }
+                    if (rc != SHSPH_OK && rc != SHSPH_ENOCONV) {
+                        c->prm = keep;
+                        ++c->param_gen;
+                        return rc;
+                    }
                     t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
                 }
                 if (t < best) { best = t; best_nr = nr; best_md = md; best_fs = fs; }
@@ -1939,6 +2237,7 @@ int shsph_autotune(shsph_ctx* c, const int64_t* handles, int32_t count, int32_t*
     c->prm.stage2_mode = best_md;
     c->prm.force_split = best_fs ? best_fs : 1;
     c->prm.fused_density_force = best_fs ? 0 : 1;
+    ++c->param_gen;
     if (n_red_out) *n_red_out = best_nr;
     if (mode_out) *mode_out = best_md;
     if (split_out) *split_out = best_fs;

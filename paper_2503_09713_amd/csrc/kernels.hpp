@@ -53,6 +53,7 @@ struct CacheView {
     const u32* root;
     double rk;                // R chi
     u64* work;                // work counters, 64 slots x 2 (profiling), or null
+    const u32* skip;          // force: a device word that switches the launch off, or null
 };
 
 // Per-block partial sums of the corrector (instance id, or -1 if the block
@@ -105,20 +106,26 @@ void launch_leaves_fused(const u64* mu, i64 n, const i64* p_off, int ninst, int 
                          u8* xi, u32* xscan, u32* id, u64* mu_leaf, u32* flag, hipStream_t st);
 void launch_compact(const u64* mu, const u8* xi, const u32* xscan, i64 n, u32* id, u64* mu_leaf,
                     hipStream_t st);
+// Tree node numbering: internal nodes 0 .. ni-1, leaf j at node lbase + j
+// with lbase = n - ninst (the most internal nodes n particles can give), so
+// the layout does not depend on the leaf count.  The Karras and box kernels
+// read the leaf count from leaf_off[ninst] (device); their grids are sized
+// from the caller's bound (the leaf count when known, else n).
 void launch_inst_leaves(const i64* p_off, int ninst, const u32* xscan, i64 n, i64* leaf_off,
-                        i64* ioff, u32* root, u32* parent, i64 n_internal, hipStream_t st);
+                        i64* ioff, u32* root, u32* parent, i64 lbase, hipStream_t st);
 void launch_karras(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
-                   i64 n_internal, const TreePtrs& t, hipStream_t st);
+                   i64 lbase, i64 grid_internal, const TreePtrs& t, hipStream_t st);
 template <class T>
-void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 n_leaf, i64 n_internal,
+void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 grid_leaves, i64 lbase,
                      const u32* child, const u32* parent, const u32* endrange, const i64* ioff,
                      const i64* leaf_off, int ninst, u32* arrive, u32* rec, u32* nrec,
                      u32* rscan, void* scan_tmp, vec4<T>* blo, vec4<T>* bhi, u32* flags,
                      hipStream_t st);
 size_t boxes_rec_count(i64 n_leaf);
+// Export in compact numbering (leaf j at row n_internal + j).
 void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
-                         i64 n_internal, i64 n_leaf, const u32* endrange, const u32* parent,
-                         u32* pbox, i32* plen, int shift, hipStream_t st);
+                         i64 n_internal, i64 n_leaf, i64 lbase, const u32* endrange,
+                         const u32* parent, u32* pbox, i32* plen, int shift, hipStream_t st);
 
 // neigh.hip
 template <class T>
@@ -158,11 +165,23 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
 // sph.hip
 void launch_fill_u32(u32* p, i64 n, u32 v, hipStream_t st);
 void launch_iota_u32(u32* p, i64 n, hipStream_t st);
-void launch_stat_reset(InstStat* s, int ninst, int what, const u8* redo, hipStream_t st);
+// skip (device word, optional) on these launches: when nonzero the launch
+// does nothing (a captured pass switches later stages off on the device).
+void launch_stat_reset(InstStat* s, int ninst, int what, const u8* redo, hipStream_t st,
+                       const u32* skip = nullptr);
 template <class T>
 void launch_root_hmax(const vec4<T>* blo, const u32* root, int ninst, double* out, hipStream_t st);
 void launch_dt_select(double* dt_inst, const InstStat* s, const double* dt_host, int ninst,
                       hipStream_t st);
+// Captured passes (see sph.hip): gs[0] abort word, gs[1 + r] re-run round r
+// switched off; gate[k] the density's per-instance switch; redo[k] and
+// reruns[k] the corrector re-runs.
+void launch_gate_build(const u32* flags, u32 mask0, int w_sort, int w_leaves, const double* rhmax,
+                       const InstDev* inst, int ninst, double rk, u32* gs, u8* gate, u32* reruns,
+                       hipStream_t st);
+void launch_gate_density(const InstStat* stat, int ninst, u32* gs, u8* gate, hipStream_t st);
+void launch_rerun_decide(const InstStat* stat, const i64* p_off, int ninst, double eps_v,
+                         int max_reruns, int r, u32* gs, u8* redo, u32* reruns, hipStream_t st);
 template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStream_t st);
 template <class T>
 void launch_density(const SortedPtrs<T>& s, const u32* id, const GroupMap& gm, i64 ngroups,
@@ -184,8 +203,9 @@ template <class T>
 void launch_correct(const SortedPtrs<T>& s, const vec4<T>* acc, const T* omega, i64 n,
                     const i64* p_off, int ninst, const InstDev* inst, const double* dt_inst,
                     double hfact, const OutPtrs<T>& o, InstStat* stat, BlockPart* part,
-                    hipStream_t st);
-void launch_fold_parts(const BlockPart* part, i64 nblocks, int ninst, InstStat* stat, hipStream_t st);
+                    hipStream_t st, const u32* skip = nullptr);
+void launch_fold_parts(const BlockPart* part, i64 nblocks, int ninst, InstStat* stat, hipStream_t st,
+                       const u32* skip = nullptr);
 template <class T>
 void launch_gather_velu(const u32* eps, i64 n, const T* vx, const T* vy, const T* vz, const T* u,
                         vec4<T>* velu, hipStream_t st);
@@ -201,7 +221,8 @@ void launch_velu_from_out(const OutPtrs<T>& o, i64 n, const i64* p_off, int nins
 template <class T>
 void launch_thermo(const vec4<T>* posh, const vec4<T>* velu, const T* omega, i64 n,
                    const i64* p_off, int ninst, const InstDev* inst, double hfact, double gamma,
-                   double alpha, const T* alpha_s, vec4<T>* thermo, hipStream_t st);
+                   double alpha, const T* alpha_s, vec4<T>* thermo, hipStream_t st,
+                   const u32* skip = nullptr);
 template <class T>
 void launch_scatter(const u32* eps, i64 n, const vec4<T>* src4, int comp, const T* src1,
                     T* dst, hipStream_t st);

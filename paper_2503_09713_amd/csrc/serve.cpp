@@ -30,11 +30,12 @@ namespace {
 // HBM charged per particle by the admission rule.  State: the 14 pooled
 // fields of the dtype plus the 32-bit id.  Work: what one pass allocates per
 // particle -- keys and values of the sort (x2), the three key-order float4
-// arrays, h copies, mask / scan / leaf arrays, tree and box arrays at
-// 8 particles per leaf, thermo / acc / Omega, and the ELL neighbour cache
-// (32 words of 8 B per particle at the default capacity, 25 % headroom).
+// arrays, h copies, mask / scan / leaf arrays, Karras tables at 8 particles
+// per leaf, the parent and box rows (2 n rows in a captured pass: leaves
+// start at row n - instances), thermo / acc / Omega, and the ELL neighbour
+// cache (32 words of 8 B per particle at the default capacity, 25 % headroom).
 double state_per_particle(int dtype) { return 14.0 * (dtype == SHSPH_F32 ? 4 : 8) + 4.0; }
-double work_per_particle(int dtype) { return dtype == SHSPH_F32 ? 480.0 : 760.0; }
+double work_per_particle(int dtype) { return dtype == SHSPH_F32 ? 544.0 : 880.0; }
 
 struct Job {
     shsph_job spec;

@@ -30,10 +30,10 @@ __global__ void k_iota_u32(u32* p, i64 n)
 // Reset per-instance reductions: what & 1 the h-iteration counters (only for
 // instances with redo[k] != 0 when redo is given), what & 2 the timestep and
 // corrector reductions.
-__global__ void k_stat_reset(InstStat* s, int ninst, int what, const u8* redo)
+__global__ void k_stat_reset(InstStat* s, int ninst, int what, const u8* redo, const u32* skip)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ninst) return;
+    if (k >= ninst || (skip && *skip)) return;
     InstStat& z = s[k];
     if ((what & 1) && (!redo || redo[k])) {
         z.n_exceed = 0u;
@@ -55,6 +55,88 @@ __global__ void k_root_hmax(const vec4<T>* __restrict__ blo, const u32* __restri
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < ninst) out[k] = (double)blo[root[k]].w;
+}
+
+// ---------------------------------------------------------------------------
+// Gates of a captured pass (one workgroup each).  gs[0] is the pass's abort
+// word: set when the build met a condition that the launch-by-launch pass
+// handles on the host between launches (a capacity to grow and a stage to
+// redo, the leaf-pass fallback, a look-back overrun, a periodic box below
+// twice the cache radius) or when some h left chi h_cache (a cache rebuild).
+// Every later stage then does nothing, the caller's arrays keep their state
+// and the host runs the pass again launch by launch.  gate[k] = 1 - gs[0]
+// for every instance (the density's per-instance switch).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_gate_build(const u32* __restrict__ flags, u32 mask0, int w_sort, int w_leaves,
+             const double* __restrict__ rhmax, const InstDev* __restrict__ inst, int ninst,
+             double rk, u32* __restrict__ gs, u8* __restrict__ gate, u32* __restrict__ reruns)
+{
+    __shared__ int s_bad;
+    if (threadIdx.x == 0)
+        s_bad = ((flags[0] & mask0) | flags[w_sort] | flags[w_leaves] | flags[w_leaves + 1]) != 0u;
+    __syncthreads();
+    for (int k = threadIdx.x; k < ninst; k += blockDim.x) {
+        reruns[k] = 0u;
+        const InstDev in = inst[k];
+        if (!in.periodic) continue;
+        for (int d = 0; d < 3; ++d)
+            if (rk * rhmax[k] >= 0.5 * (in.hi[d] - in.lo[d])) atomicOr(&s_bad, 1);
+    }
+    __syncthreads();
+    const bool bad = s_bad != 0;
+    if (threadIdx.x == 0) gs[0] = bad ? 1u : 0u;
+    for (int k = threadIdx.x; k < ninst; k += blockDim.x) gate[k] = bad ? 0 : 1;
+}
+
+__global__ void __launch_bounds__(256)
+k_gate_density(const InstStat* __restrict__ stat, int ninst, u32* __restrict__ gs,
+               u8* __restrict__ gate)
+{
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = gs[0] != 0u;
+    __syncthreads();
+    for (int k = threadIdx.x; k < ninst; k += blockDim.x)
+        if (stat[k].n_exceed) atomicOr(&s_bad, 1);
+    __syncthreads();
+    if (!s_bad) return;
+    if (threadIdx.x == 0) gs[0] = 1u;
+    for (int k = threadIdx.x; k < ninst; k += blockDim.x) gate[k] = 0;
+}
+
+// Corrector re-run round r of a captured pass (App. G.1, the reversibility
+// check): instance k runs again when max|dv| > eps_v sqrt(sum|v|^2 / N_k)
+// and it has re-run fewer than max_reruns times, from the reductions of the
+// last corrector that ran (gs[r]: the pass's own for r = 0, else round r-1's;
+// when that one was switched off, so is this round).  gs[1 + r] = 1 when no
+// instance runs again.
+__global__ void __launch_bounds__(256)
+k_rerun_decide(const InstStat* __restrict__ stat, const i64* __restrict__ p_off, int ninst,
+               double eps_v, int max_reruns, int r, u32* __restrict__ gs, u8* __restrict__ redo,
+               u32* __restrict__ reruns)
+{
+    __shared__ int s_any;
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    const bool off = gs[r] != 0u;
+    for (int k = threadIdx.x; k < ninst; k += blockDim.x) {
+        bool want = false;
+        if (!off) {
+            const float dv = __uint_as_float(stat[k].dvmax_bits);
+            double v2 = 0.0;
+            for (int i = 0; i < STAT_SLOTS; ++i) v2 += stat[k].v2_part[i];
+            const i64 cnt = p_off[k + 1] - p_off[k];
+            want = (double)dv > eps_v * sqrt(v2 / (double)(cnt > 1 ? cnt : 1)) &&
+                   reruns[k] < (u32)max_reruns;
+        }
+        redo[k] = want ? 1 : 0;
+        if (want) {
+            ++reruns[k];
+            atomicOr(&s_any, 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) gs[1 + r] = s_any ? 0u : 1u;
 }
 
 // dt for the coming step: the caller's value when positive, else the CFL dt
@@ -434,6 +516,7 @@ force_group(const i64 g, const vec4<T>* __restrict__ posh, const vec4<T>* __rest
     float* const s_red = sh.red;
     u64* const s_w = sh.w;
     int* const s_k = &sh.k;
+    if (cv.skip && *cv.skip) return;      // switched off on the device (uniform)
     i64 beg, end;
     int k;
     gm.range(g, beg, end, k);
@@ -757,11 +840,12 @@ k_correct(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
           const T* __restrict__ omega, const u32* __restrict__ pid, i64 n,
           const i64* __restrict__ p_off, int ninst, const InstDev* __restrict__ inst,
           const double* __restrict__ dt_inst, double hfact, OutPtrs<T> o,
-          InstStat* __restrict__ stat, BlockPart* __restrict__ part)
+          InstStat* __restrict__ stat, BlockPart* __restrict__ part, const u32* __restrict__ skip)
 {
     __shared__ double s_red[GROUP / WAVE];
     __shared__ float s_redf[GROUP / WAVE];
     __shared__ int s_k;
+    if (skip && *skip) return;
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = i < n;
     const i64 ii = live ? i : n - 1;
@@ -822,9 +906,11 @@ k_correct(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
 // Fold the per-block partials of the corrector into the instance stats
 // (one workgroup per instance).
 __global__ void __launch_bounds__(GROUP)
-k_fold_parts(const BlockPart* __restrict__ part, i64 nblocks, InstStat* __restrict__ stat)
+k_fold_parts(const BlockPart* __restrict__ part, i64 nblocks, InstStat* __restrict__ stat,
+             const u32* __restrict__ skip)
 {
     __shared__ double s_red[GROUP / WAVE];
+    if (skip && *skip) return;
     const int k = blockIdx.x;
     double a = 0.0, b = 0.0;
     for (i64 i = threadIdx.x; i < nblocks; i += GROUP) {
@@ -846,10 +932,11 @@ template <class T>
 __global__ void k_thermo(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ velu,
                          const T* __restrict__ omega, i64 n, const i64* __restrict__ p_off,
                          int ninst, const InstDev* __restrict__ inst, double hfact, double gamma,
-                         double alpha, const T* __restrict__ alpha_s, vec4<T>* __restrict__ thermo)
+                         double alpha, const T* __restrict__ alpha_s, vec4<T>* __restrict__ thermo,
+                         const u32* __restrict__ skip)
 {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (skip && *skip)) return;
     const int k = find_seg(p_off, ninst, i);
     const T hf = (T)hfact / posh[i].w;
     const T rho = (T)inst[k].mass * hf * hf * hf;
@@ -927,15 +1014,37 @@ void launch_iota_u32(u32* p, i64 n, hipStream_t st)
     if (n > 0) hipLaunchKernelGGL(k_iota_u32, grid_for(n, 256), dim3(256), 0, st, p, n);
 }
 
-void launch_stat_reset(InstStat* s, int ninst, int what, const u8* redo, hipStream_t st)
+void launch_stat_reset(InstStat* s, int ninst, int what, const u8* redo, hipStream_t st,
+                       const u32* skip)
 {
-    hipLaunchKernelGGL(k_stat_reset, grid_for(ninst, 64), dim3(64), 0, st, s, ninst, what, redo);
+    hipLaunchKernelGGL(k_stat_reset, grid_for(ninst, 64), dim3(64), 0, st, s, ninst, what, redo,
+                       skip);
 }
 
 template <class T>
 void launch_root_hmax(const vec4<T>* blo, const u32* root, int ninst, double* out, hipStream_t st)
 {
     hipLaunchKernelGGL((k_root_hmax<T>), grid_for(ninst, 64), dim3(64), 0, st, blo, root, ninst, out);
+}
+
+void launch_gate_build(const u32* flags, u32 mask0, int w_sort, int w_leaves, const double* rhmax,
+                       const InstDev* inst, int ninst, double rk, u32* gs, u8* gate, u32* reruns,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gate_build, dim3(1), dim3(256), 0, st, flags, mask0, w_sort, w_leaves, rhmax,
+                       inst, ninst, rk, gs, gate, reruns);
+}
+
+void launch_gate_density(const InstStat* stat, int ninst, u32* gs, u8* gate, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gate_density, dim3(1), dim3(256), 0, st, stat, ninst, gs, gate);
+}
+
+void launch_rerun_decide(const InstStat* stat, const i64* p_off, int ninst, double eps_v,
+                         int max_reruns, int r, u32* gs, u8* redo, u32* reruns, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rerun_decide, dim3(1), dim3(256), 0, st, stat, p_off, ninst, eps_v,
+                       max_reruns, r, gs, redo, reruns);
 }
 
 void launch_dt_select(double* dt_inst, const InstStat* s, const double* dt_host, int ninst,
@@ -1145,19 +1254,21 @@ template <class T>
 void launch_correct(const SortedPtrs<T>& s, const vec4<T>* acc, const T* omega, i64 n,
                     const i64* p_off, int ninst, const InstDev* inst, const double* dt_inst,
                     double hfact, const OutPtrs<T>& o, InstStat* stat, BlockPart* part,
-                    hipStream_t st)
+                    hipStream_t st, const u32* skip)
 {
     if (n <= 0) return;
     const i64 nb = (n + GROUP - 1) / GROUP;
     hipLaunchKernelGGL((k_correct<T>), dim3((unsigned)nb), dim3(GROUP), 0, st, s.posh, s.velu,
                        s.vhalf, acc, omega, s.pid, n, p_off, ninst, inst, dt_inst, hfact, o, stat,
-                       part);
+                       part, skip);
 }
 
-void launch_fold_parts(const BlockPart* part, i64 nblocks, int ninst, InstStat* stat, hipStream_t st)
+void launch_fold_parts(const BlockPart* part, i64 nblocks, int ninst, InstStat* stat, hipStream_t st,
+                       const u32* skip)
 {
     if (nblocks > 0)
-        hipLaunchKernelGGL(k_fold_parts, dim3((unsigned)ninst), dim3(GROUP), 0, st, part, nblocks, stat);
+        hipLaunchKernelGGL(k_fold_parts, dim3((unsigned)ninst), dim3(GROUP), 0, st, part, nblocks, stat,
+                           skip);
 }
 
 template <class T>
@@ -1181,11 +1292,12 @@ void launch_velu_from_out(const OutPtrs<T>& o, i64 n, const i64* p_off, int nins
 template <class T>
 void launch_thermo(const vec4<T>* posh, const vec4<T>* velu, const T* omega, i64 n,
                    const i64* p_off, int ninst, const InstDev* inst, double hfact, double gamma,
-                   double alpha, const T* alpha_s, vec4<T>* thermo, hipStream_t st)
+                   double alpha, const T* alpha_s, vec4<T>* thermo, hipStream_t st,
+                   const u32* skip)
 {
     if (n > 0)
         hipLaunchKernelGGL((k_thermo<T>), grid_for(n, 256), dim3(256), 0, st, posh, velu, omega, n,
-                           p_off, ninst, inst, hfact, gamma, alpha, alpha_s, thermo);
+                           p_off, ninst, inst, hfact, gamma, alpha, alpha_s, thermo, skip);
 }
 
 template <class T>
@@ -1221,7 +1333,8 @@ void launch_scatter_rho(const u32* eps, i64 n, const vec4<T>* posh, const i64* p
                                   const CacheView&, vec4<T>*, T*, InstStat*, hipStream_t);         \
     template void launch_correct<T>(const SortedPtrs<T>&, const vec4<T>*, const T*, i64,          \
                                     const i64*, int, const InstDev*, const double*, double,       \
-                                    const OutPtrs<T>&, InstStat*, BlockPart*, hipStream_t);        \
+                                    const OutPtrs<T>&, InstStat*, BlockPart*, hipStream_t,         \
+                                    const u32*);                                                   \
     template void launch_gather_velu<T>(const u32*, i64, const T*, const T*, const T*, const T*,  \
                                         vec4<T>*, hipStream_t);                                   \
     template void launch_alpha<T>(const SortedPtrs<T>&, const vec4<T>*, const T*, const u32*,     \
@@ -1232,7 +1345,7 @@ void launch_scatter_rho(const u32* eps, i64 n, const vec4<T>* posh, const i64* p
                                           const InstDev*, const u8*, vec4<T>*, hipStream_t);      \
     template void launch_thermo<T>(const vec4<T>*, const vec4<T>*, const T*, i64, const i64*,     \
                                    int, const InstDev*, double, double, double, const T*,         \
-                                   vec4<T>*, hipStream_t);                                        \
+                                   vec4<T>*, hipStream_t, const u32*);                            \
     template void launch_scatter<T>(const u32*, i64, const vec4<T>*, int, const T*, T*,           \
                                     hipStream_t);                                                 \
     template void launch_scatter_rho<T>(const u32*, i64, const vec4<T>*, const i64*, int,         \

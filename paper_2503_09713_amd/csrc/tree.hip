@@ -480,10 +480,14 @@ k_leaves_fused(const u64* __restrict__ mu, i64 n, const i64* __restrict__ p_off,
 }
 
 // Per-instance leaf ranges: leaf_off[k] = number of kept codes before the
-// instance's first particle; root node of each instance.
+// instance's first particle (leaf_off[ninst] = all leaves); root node of each
+// instance.
+// Node numbering: internal nodes 0 .. ni-1 (ni = leaves - instances), leaf j
+// at node lbase + j, where lbase >= ni is fixed by the caller (the largest ni
+// the particle count allows), so that no launch needs the leaf count.
 __global__ void k_inst_leaves(const i64* __restrict__ p_off, int ninst, const u32* __restrict__ xscan,
                               i64 n, i64* __restrict__ leaf_off, i64* __restrict__ ioff,
-                              u32* __restrict__ root, u32* __restrict__ parent, i64 n_internal)
+                              u32* __restrict__ root, u32* __restrict__ parent, i64 lbase)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k > ninst) return;
@@ -492,7 +496,7 @@ __global__ void k_inst_leaves(const i64* __restrict__ p_off, int ninst, const u3
     ioff[k] = lo - k;
     if (k < ninst) {
         const i64 hi = xscan[p_off[k + 1]];
-        const u32 r = (hi - lo > 1) ? (u32)(lo - k) : (u32)(n_internal + lo);
+        const u32 r = (hi - lo > 1) ? (u32)(lo - k) : (u32)(lbase + lo);
         root[k] = r;
         parent[r] = 0xffffffffu;
     }
@@ -511,11 +515,10 @@ __device__ inline int dlt(const u64* m, i64 nl, i64 i, i64 j)
 }
 
 __global__ void k_karras(const u64* __restrict__ mu_leaf, const i64* __restrict__ leaf_off,
-                         const i64* __restrict__ ioff, int ninst, i64 n_internal,
-                         TreePtrs t)
+                         const i64* __restrict__ ioff, int ninst, i64 lbase, TreePtrs t)
 {
     const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_internal) return;
+    if (g >= leaf_off[ninst] - ninst) return;     // internal nodes: leaves - instances
     const int k = find_seg(ioff, ninst, g);
     const i64 L0 = leaf_off[k];
     const i64 nl = leaf_off[k + 1] - L0;
@@ -543,8 +546,8 @@ __global__ void k_karras(const u64* __restrict__ mu_leaf, const i64* __restrict_
     t.lflag[g] = lleaf;
     t.rflag[g] = rleaf;
     t.endrange[g] = (u32)j;
-    const u32 cl = lleaf ? (u32)(n_internal + L0 + gam) : (u32)(ioff[k] + gam);
-    const u32 cr = rleaf ? (u32)(n_internal + L0 + gam + 1) : (u32)(ioff[k] + gam + 1);
+    const u32 cl = lleaf ? (u32)(lbase + L0 + gam) : (u32)(ioff[k] + gam);
+    const u32 cr = rleaf ? (u32)(lbase + L0 + gam + 1) : (u32)(ioff[k] + gam + 1);
     t.child[2 * g] = cl;
     t.child[2 * g + 1] = cr;
     t.parent[cl] = (u32)g;
@@ -582,8 +585,8 @@ __device__ inline void node_span(u32 p, const i64* ioff, const i64* leaf_off, in
 
 template <class T>
 __global__ void __launch_bounds__(BOX_BLK)
-k_boxes_local(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 n_leaf,
-              i64 n_internal, const u32* __restrict__ child, const u32* __restrict__ parent,
+k_boxes_local(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 lbase,
+              const u32* __restrict__ child, const u32* __restrict__ parent,
               const u32* __restrict__ endrange, const i64* __restrict__ ioff,
               const i64* __restrict__ leaf_off, int ninst, vec4<T>* __restrict__ blo,
               vec4<T>* __restrict__ bhi, u32* __restrict__ rec, u32* __restrict__ nrec,
@@ -594,6 +597,7 @@ k_boxes_local(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 
     __shared__ u32 s_arr[BOX_BLK];
     __shared__ u32 s_rec[BOX_OUT];
     __shared__ u32 s_nrec;
+    const i64 n_leaf = leaf_off[ninst];
     const i64 B0 = (i64)blockIdx.x * BOX_BLK;
     const i64 B1 = (B0 + BOX_BLK) < n_leaf ? (B0 + BOX_BLK) : n_leaf;
     const int t = threadIdx.x;
@@ -622,12 +626,12 @@ k_boxes_local(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 
         const vec4<T> l = mk4<T>(lo0, lo1, lo2, hm), h = mk4<T>(hi0, hi1, hi2, T(0));
         s_llo[t] = l;
         s_lhi[t] = h;
-        blo[n_internal + g] = l;
-        bhi[n_internal + g] = h;
+        blo[lbase + g] = l;
+        bhi[lbase + g] = h;
     }
     __syncthreads();
     if (live) {
-        u32 node = (u32)(n_internal + g);
+        u32 node = (u32)(lbase + g);
         while (true) {
             const u32 par = parent[node];
             if (par == 0xffffffffu) break;
@@ -645,9 +649,9 @@ k_boxes_local(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 
             const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
             const u32 other = (c0 == node) ? c1 : c0;
             vec4<T> ol, oh;
-            if (other >= n_internal) {
-                ol = s_llo[other - n_internal - B0];
-                oh = s_lhi[other - n_internal - B0];
+            if (other >= lbase) {
+                ol = s_llo[other - lbase - B0];
+                oh = s_lhi[other - lbase - B0];
             } else {
                 i64 f2, l2, k2;
                 node_span(other, ioff, leaf_off, ninst, endrange, f2, l2, k2);
@@ -683,7 +687,7 @@ constexpr int BOX_MID = 64;
 
 template <class T>
 __global__ void __launch_bounds__(BOX_MID)
-k_boxes_mid(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nblocks, i64 n_leaf,
+k_boxes_mid(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nblocks,
             const u32* __restrict__ child, const u32* __restrict__ parent,
             const u32* __restrict__ endrange, const i64* __restrict__ ioff,
             const i64* __restrict__ leaf_off, int ninst, u32* __restrict__ arrive, vec4<T>* blo,
@@ -693,6 +697,7 @@ k_boxes_mid(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nbloc
     __shared__ u32 s_nrec;
     if (threadIdx.x == 0) s_nrec = 0;
     __syncthreads();
+    const i64 n_leaf = leaf_off[ninst];
     const i64 b = (i64)blockIdx.x * BOX_MID + threadIdx.x;
     const i64 C0 = (i64)blockIdx.x * BOX_MID * BOX_BLK;
     const i64 C1 = (C0 + (i64)BOX_MID * BOX_BLK) < n_leaf ? (C0 + (i64)BOX_MID * BOX_BLK) : n_leaf;
@@ -783,10 +788,13 @@ __device__ inline u32 compact3(u64 x)
     return (u32)x;
 }
 
+// Output rows in compact numbering: internal nodes, then leaf j at row
+// n_internal + j (its parent read at node lbase + j).
 __global__ void k_prefix_boxes(const u64* __restrict__ mu_leaf, const i64* __restrict__ leaf_off,
                                const i64* __restrict__ ioff, int ninst, i64 n_internal, i64 n_leaf,
-                               const u32* __restrict__ endrange, const u32* __restrict__ parent,
-                               u32* __restrict__ pbox, i32* __restrict__ plen, int shift)
+                               i64 lbase, const u32* __restrict__ endrange,
+                               const u32* __restrict__ parent, u32* __restrict__ pbox,
+                               i32* __restrict__ plen, int shift)
 {
     // shorter codes (30 bits in the low bits) are read in the 63-bit layout:
     // the code moved up by `shift` and its prefix lengths shortened by as much
@@ -807,7 +815,7 @@ __global__ void k_prefix_boxes(const u64* __restrict__ mu_leaf, const i64* __res
         len = range_len(v);
     } else {
         code = mu_leaf[v - n_internal];
-        const u32 p = parent[v];
+        const u32 p = parent[lbase + (v - n_internal)];
         len = (p == 0xffffffffu) ? 0 : range_len(p) + 1;
     }
     if (len > 0) len -= shift;
@@ -986,31 +994,31 @@ void launch_leaves_fused(const u64* mu, i64 n, const i64* p_off, int ninst, int 
 }
 
 void launch_inst_leaves(const i64* p_off, int ninst, const u32* xscan, i64 n, i64* leaf_off,
-                        i64* ioff, u32* root, u32* parent, i64 n_internal, hipStream_t st)
+                        i64* ioff, u32* root, u32* parent, i64 lbase, hipStream_t st)
 {
     hipLaunchKernelGGL(k_inst_leaves, grid_for(ninst + 1, 64), dim3(64), 0, st, p_off, ninst, xscan,
-                       n, leaf_off, ioff, root, parent, n_internal);
+                       n, leaf_off, ioff, root, parent, lbase);
 }
 
 void launch_karras(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
-                   i64 n_internal, const TreePtrs& t, hipStream_t st)
+                   i64 lbase, i64 grid_internal, const TreePtrs& t, hipStream_t st)
 {
-    if (n_internal <= 0) return;
-    hipLaunchKernelGGL(k_karras, grid_for(n_internal, 256), dim3(256), 0, st, mu_leaf, leaf_off,
-                       ioff, ninst, n_internal, t);
+    if (grid_internal <= 0) return;
+    hipLaunchKernelGGL(k_karras, grid_for(grid_internal, 256), dim3(256), 0, st, mu_leaf, leaf_off,
+                       ioff, ninst, lbase, t);
 }
 
 template <class T>
-void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 n_leaf, i64 n_internal,
+void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 grid_leaves, i64 lbase,
                      const u32* child, const u32* parent, const u32* endrange, const i64* ioff,
                      const i64* leaf_off, int ninst, u32* arrive, u32* rec, u32* nrec,
                      u32* rscan, void* scan_tmp, vec4<T>* blo, vec4<T>* bhi, u32* flags,
                      hipStream_t st)
 {
-    if (n_leaf <= 0) return;
-    const i64 nb = (n_leaf + BOX_BLK - 1) / BOX_BLK;
-    hipLaunchKernelGGL((k_boxes_local<T>), dim3((unsigned)nb), dim3(BOX_BLK), 0, st, posh, id, n_leaf,
-                       n_internal, child, parent, endrange, ioff, leaf_off, ninst, blo, bhi, rec,
+    if (grid_leaves <= 0) return;
+    const i64 nb = (grid_leaves + BOX_BLK - 1) / BOX_BLK;
+    hipLaunchKernelGGL((k_boxes_local<T>), dim3((unsigned)nb), dim3(BOX_BLK), 0, st, posh, id,
+                       lbase, child, parent, endrange, ioff, leaf_off, ninst, blo, bhi, rec,
                        nrec, flags);
     if (nb > 1) {
         // middle level (ranges of BOX_MID local blocks), then one workgroup
@@ -1019,7 +1027,7 @@ void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 n_leaf, i64 n_inter
         u32* rec2 = rec + nb * BOX_OUT;
         u32* nrec2 = nrec + nb;
         hipLaunchKernelGGL((k_boxes_mid<T>), dim3((unsigned)nb2), dim3(BOX_MID), 0, st, rec, nrec,
-                           nb, n_leaf, child, parent, endrange, ioff, leaf_off, ninst, arrive, blo,
+                           nb, child, parent, endrange, ioff, leaf_off, ninst, arrive, blo,
                            bhi, rec2, nrec2, flags);
         if (nb2 > 1)
             hipLaunchKernelGGL((k_boxes_top<T>), dim3(1), dim3(TOP_BLOCK), 0, st, rec2, nrec2, nb2,
@@ -1035,13 +1043,13 @@ size_t boxes_rec_count(i64 n_leaf)
 }
 
 void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
-                         i64 n_internal, i64 n_leaf, const u32* endrange, const u32* parent,
-                         u32* pbox, i32* plen, int shift, hipStream_t st)
+                         i64 n_internal, i64 n_leaf, i64 lbase, const u32* endrange,
+                         const u32* parent, u32* pbox, i32* plen, int shift, hipStream_t st)
 {
     const i64 nn = n_internal + n_leaf;
     if (nn <= 0) return;
     hipLaunchKernelGGL(k_prefix_boxes, grid_for(nn, 256), dim3(256), 0, st, mu_leaf, leaf_off, ioff,
-                       ninst, n_internal, n_leaf, endrange, parent, pbox, plen, shift);
+                       ninst, n_internal, n_leaf, lbase, endrange, parent, pbox, plen, shift);
 }
 
 #define INST(T)                                                                                   \

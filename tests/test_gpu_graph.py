@@ -1,0 +1,130 @@
+"""Captured batched passes (graph_batch = 1) against the same passes launched
+one by one (graph_batch = 0).  The captured pass runs the same kernels in
+the same order, with the host's decisions between launches taken on the
+device, so every field must be bit-identical pass after pass: plain CFL
+steps (FP32 and FP64), steps with corrector re-runs, and steps whose h
+leaves chi h_cache, where the captured pass switches itself off on the
+device and the host runs it again launch by launch."""
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+shsph = pytest.importorskip("paper_2503_09713_amd")
+
+STATE = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay", "az", "dudt", "rho", "omega", "pid")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _random_state(p, seed, vscale=0.1, uvar=0.3):
+    rng = np.random.default_rng(seed)
+    T = p.x.dtype
+    for k in ("vx", "vy", "vz"):
+        setattr(p, k, (rng.standard_normal(p.n) * vscale).astype(T))
+    p.u = (p.u * (1 + uvar * rng.uniform(-1, 1, p.n))).astype(T)
+    return p
+
+
+def _mix(T):
+    return [_random_state(gen.lattice(9, 41, dtype=T), 1),
+            _random_state(gen.plummer(2500, 42, dtype=T), 2, vscale=0.3),
+            gen.sedov(10, 43, dtype=T),
+            _random_state(gen.lattice(6, 44, dtype=T), 3, vscale=0.05),
+            _random_state(gen.plummer(900, 45, dtype=T), 4, vscale=0.1)]
+
+
+def _hubble(seed, rate):
+    """Isolated lattice expanding as v = rate (x - centre): the density drops
+    by (1 + rate dt)^3 per step, so h grows past chi h_cache in every step.
+    It starts from the oracle's self-consistent h (the surface's h is far
+    above the lattice value)."""
+    p = gen.lattice(10, seed, dtype=np.float32)
+    p.periodic = False
+    lo = (float(p.x.min()), float(p.y.min()), float(p.z.min()))
+    hi = (float(p.x.max()), float(p.y.max()), float(p.z.max()))
+    h, _, _, fl = oracle.density(p.x, p.y, p.z, p.h, lo, hi, False, p.mass)
+    assert fl.max() == 0
+    p.h = h.astype(np.float32)
+    for k, c in (("vx", p.x), ("vy", p.y), ("vz", p.z)):
+        setattr(p, k, (rate * (c - 0.5)).astype(np.float32))
+    return p
+
+
+def _run(ps, passes, dt=None, allow_noconv=False, **kw):
+    ctx = shsph.Context(0, **kw)
+    hs = [ctx.instance_create(shsph.ParticleSet.from_particles(p)) for p in ps]
+    out = []
+    for _ in range(passes):
+        used = ctx.step_batch(hs, dt=dt, allow_noconv=allow_noconv)
+        snap = []
+        for h, p in zip(hs, ps):
+            o = shsph.ParticleSet.from_particles(p)
+            ctx.instance_read(h, o)
+            snap.append((o.host(*STATE), ctx.instance_info(h)["reruns"]))
+        out.append((used, snap))
+    info = ctx.get_info()
+    ctx.close()
+    return out, info
+
+
+def _same(a, b):
+    for s, (pa, pb) in enumerate(zip(a, b)):
+        assert pa[0] == pb[0], f"pass {s}: dt used"
+        for k, ((fa, ra), (fb, rb)) in enumerate(zip(pa[1], pb[1])):
+            assert ra == rb, f"pass {s} instance {k}: corrector re-runs"
+            for f in STATE:
+                assert np.array_equal(fa[f], fb[f], equal_nan=True), f"pass {s} instance {k}: {f}"
+
+
+@pytest.mark.parametrize("T", [np.float32, np.float64])
+def test_graph_steps_equal_eager(torch_cuda, T):
+    _say(f"[graph] 5 uneven instances, 5 CFL passes, {np.dtype(T).name}")
+    ps = _mix(T)
+    a, ia = _run(ps, 5, graph_batch=0)
+    b, ib = _run(ps, 5, graph_batch=1)
+    _same(a, b)
+    assert ia["graph_passes"] == 0
+    assert ib["graph_passes"] >= 3 and ib["graph_aborts"] == 0, ib
+
+
+def test_graph_corrector_reruns_equal_eager(torch_cuda):
+    """A tight reversibility bound: instances re-run their corrector (up to
+    two rounds), decided on the device in the captured pass."""
+    _say("[graph] corrector re-runs decided on the device")
+    ps = _mix(np.float32)
+    kw = dict(eps_v=2e-3, max_reruns=2)
+    a, _ = _run(ps, 5, **kw, graph_batch=0)
+    b, ib = _run(ps, 5, **kw, graph_batch=1)
+    _same(a, b)
+    assert sum(r for _, snap in b for _, r in snap) > 0, "no instance re-ran its corrector"
+    assert ib["graph_passes"] >= 3
+
+
+def test_graph_abort_falls_back(torch_cuda):
+    """Expanding instances: h leaves chi h_cache in every step, so each
+    replayed pass switches itself off after the density and is run again
+    launch by launch (with its cache rebuilds); same results."""
+    _say("[graph] every replay aborts (h past chi h_cache) and falls back")
+    ps = [_hubble(51, 1.2), _random_state(gen.lattice(8, 52, dtype=np.float32), 6)]
+    kw = dict(dt=0.1, allow_noconv=True, max_restarts=8)
+    a, _ = _run(ps, 4, **kw, graph_batch=0)
+    b, ib = _run(ps, 4, **kw, graph_batch=1)
+    _same(a, b)
+    assert ib["graph_aborts"] >= 1, ib
