@@ -434,7 +434,10 @@ def run_served(args, shsph, torch, tune=None):
         """Serve `jobs_run` with one policy; rate None = every job at once
         (a burst: the policy's saturation capacity), else Poisson arrivals at
         `rate` jobs/s on the trace's own arrival times."""
-        ctx = shsph.Context(0, **kw)
+        # the one-at-a-time baseline is plain per-job launches (no captured
+        # passes); continuous batching records repeating pass shapes
+        plain = policy == shsph.SERVE_ONE_AT_A_TIME
+        ctx = shsph.Context(0, **kw, graph_batch=0 if plain else 1)
         ctx.serve_start(200e9, max_batch=256, policy=policy,
                         max_batch_particles=args.serve_pass_particles)
         log(f"[served] {label}: {len(jobs_run)} jobs" + ("" if rate is None else f" at {rate:.1f}/s"))

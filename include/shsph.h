@@ -177,6 +177,14 @@ typedef struct {
     double cfl_multiplier;   /* CFL multiplier for the next CFL step (App. G) */
     int64_t graph_passes;    /* batched passes run from a captured graph (context total) */
     int64_t graph_aborts;    /* captured passes switched off and run launch by launch */
+    int32_t graph_abort_why; /* why the last one was: bit 0 a capacity / stack / box-record
+                                overflow of the build (its flag word in bits 8-15: 1 stack,
+                                2 union leaves, 4 ELL words, 16 box records, 32 layout),
+                                1 a sort look-back overrun, 2 the leaf pass's fallback,
+                                3 a periodic box below twice the cache radius, 4 the
+                                same flags in a cache-rebuild round (bits 16-23), 5 an h
+                                still past chi h_cache after the rebuild rounds */
+    int32_t pad1;
 } shsph_info;
 
 /* Host buffers receiving the tree of the last build (test and debug use).

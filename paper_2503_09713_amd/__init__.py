@@ -70,7 +70,7 @@ class Info(C.Structure):
                 ("dv_max", C.c_double), ("dv2_sum", C.c_double), ("v2_sum", C.c_double),
                 ("reruns", C.c_int32), ("cache_capacity", C.c_int32),
                 ("cfl_multiplier", C.c_double), ("graph_passes", C.c_int64),
-                ("graph_aborts", C.c_int64)]
+                ("graph_aborts", C.c_int64), ("graph_abort_why", C.c_int32), ("pad1", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -92,6 +92,8 @@ struct shsph_ctx {
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;           // records captures (launches go on `stream`)
     i64 graph_passes = 0, graph_aborts = 0;
+    int graph_backoff = 0, graph_wait = 0;      // passes run launch by launch after an abort
+    u32 graph_abort_why = 0;                    // abort word of the last switched-off replay
     i64 cap_leaf = 256;                         // per-group union leaves (stage 1)
     // stage-2 cache: capacity per group (words of 4 entries per lane), planned
     // each build from the need of the previous one (valid for gneed_groups)
@@ -482,7 +484,9 @@ CacheView cache_view(shsph_ctx* c)
 // boxes -> caches.  `dt_dev` non-NULL: positions are the leapfrog-predicted
 // ones (stepping); the gather then also forms v*, u*, v^{n+1/2}, u^{n+1/2}.
 // ---------------------------------------------------------------------------
-template <class T> int build_caches(shsph_ctx* c, const u8* redo = nullptr);
+template <class T>
+int build_caches(shsph_ctx* c, const u8* redo = nullptr, const u32* skip = nullptr,
+                 bool plan_anyway = false);
 template <class T> int build_tree_tables(shsph_ctx* c, i64 nl);
 
 template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const double* dt_dev, bool step)
@@ -632,7 +636,10 @@ template <class T> int build_tree_tables(shsph_ctx* c, i64 nl)
 // caches; the others keep the ones of the previous build (valid: their h
 // stayed within chi h_cache).  A capacity regrow changes the layout, so the
 // retry rebuilds every group.
-template <class T> int build_caches(shsph_ctx* c, const u8* redo)
+// While capturing, `skip` (a device word) switches the box launches off and
+// `plan_anyway` lays the cache out afresh even with `redo` (a rebuild round
+// of a single-instance pass, which the launch-by-launch pass replans).
+template <class T> int build_caches(shsph_ctx* c, const u8* redo, const u32* skip, bool plan_anyway)
 {
     hipStream_t st = c->stream;
     // launch bounds: the leaf and internal counts, or their largest values
@@ -661,8 +668,9 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
     launch_boxes_up<T>(posh, P<u32>(c->id), nl, lb, P<u32>(c->child), P<u32>(c->parent),
                        P<u32>(c->endrange), P<i64>(c->ioff_d), P<i64>(c->leaf_off_d), ninst,
                        P<u32>(c->arrive), P<u32>(c->rec), P<u32>(c->nrec), P<u32>(c->rscan),
-                       c->scan_tmp.p, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->flags), st);
-    launch_group_boxes<T>(posh, gm, G, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), st);
+                       c->scan_tmp.p, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->flags), st,
+                       skip);
+    launch_group_boxes<T>(posh, gm, G, P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi), st, skip);
     prof_end(c);
     TRY(check_launch(c, "boxes"));
     TRY(ensure(c, c->gcap, G * sizeof(u32)));
@@ -671,7 +679,7 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
     TRY(ensure(c, c->gredo, G));
     const size_t WORD_BYTES = (size_t)GROUP * sizeof(u64);    // one word of every lane of a group
     bool run_stage1 = true;
-    bool plan = redo == nullptr;     // a rebuild of some instances keeps the others' layout
+    bool plan = redo == nullptr || plan_anyway;   // a rebuild of some instances keeps the others' layout
     const u8* gredo = nullptr;       // regrow retry: only the groups that overflowed
     for (int attempt = 0;; ++attempt) {
         // stage 1: neighbour leaves of each group
@@ -694,7 +702,7 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo)
         if (plan) {
             const bool hist = c->gneed_groups == G;
             launch_cache_plan(P<u32>(c->ustot), hist ? P<u32>(c->gneed) : nullptr, G, CACHE_WORDS0,
-                              P<u32>(c->gcap), P<u64>(c->gbase), c->scan_tmp.p, st);
+                              P<u32>(c->gcap), P<u64>(c->gbase), c->scan_tmp.p, st, skip);
             if (!c->nlist.p)    // first build: room for the default capacity
                 TRY(ensure(c, c->nlist, (size_t)G * CACHE_WORDS0 * WORD_BYTES));
             plan = false;
@@ -1216,8 +1224,9 @@ template <class T> OutPtrs<T> pool_out(shsph_ctx* c)
 // switched on by the previous round's check on the device.  Results are the
 // launch-by-launch pass's, bit for bit.
 // ---------------------------------------------------------------------------
-constexpr int GS_WORDS = 64;                 // gate words: [0] abort, [1 + r] round r off
-constexpr int GS_ROUNDS = GS_WORDS - 2;
+// gate words: [0] abort, [1 + r] corrector re-run round r off (r < GS_ROUNDS),
+// [GS_RB0 + b] cache-rebuild round b off (b < GS_RBMAX)
+constexpr int GS_WORDS = 64, GS_ROUNDS = 40, GS_RB0 = 48, GS_RBMAX = 2;
 
 bool graph_usable(shsph_ctx* c)
 {
@@ -1238,6 +1247,7 @@ void graph_drop(shsph_ctx* c)
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
     c->gkey.clear();
+    c->graph_backoff = c->graph_wait = 0;
 }
 
 // Buffers a captured pass uses at their largest (node tables for n leaves)
@@ -1265,7 +1275,7 @@ template <class T> int presize_capture(shsph_ctx* c)
     TRY(ensure(c, c->nlist, (size_t)(c->cache_words + c->cache_words / 4 + 2 * G) * WORD_BYTES));
     TRY(ensure(c, c->acc, n * sizeof(vec4<T>)));
     TRY(ensure(c, c->bpart, ((n + GROUP - 1) / GROUP) * sizeof(BlockPart)));
-    TRY(ensure(c, c->gstate, GS_WORDS * sizeof(u32) + ninst * (sizeof(u32) + 2)));
+    TRY(ensure(c, c->gstate, GS_WORDS * sizeof(u32) + ninst * (sizeof(u32) + 3)));
     return SHSPH_OK;
 }
 
@@ -1280,6 +1290,7 @@ template <class T> int graph_body(shsph_ctx* c)
     u32* reruns = gs + GS_WORDS;
     u8* gate = (u8*)(reruns + ninst);
     u8* redo = gate + ninst;
+    u8* rx = redo + ninst;                      // instances of a cache-rebuild round
     InstStat* stat = P<InstStat>(c->stat_d);
     const InstDev* inst = P<InstDev>(c->inst_d);
     const i64* poff = P<i64>(c->poff_d);
@@ -1297,6 +1308,22 @@ template <class T> int graph_body(shsph_ctx* c)
     launch_density<T>(s, P<u32>(c->id), group_map(c), c->n_groups, inst, sp, cache_view(c),
                       P<T>(c->omega), P<vec4<T>>(c->thermo), P<u8>(c->status), stat, gate, st);
     TRY(check_launch(c, "density"));
+    // cache-rebuild rounds (the launch-by-launch pass's restarts), each
+    // switched on by a particle past chi h_cache; past the last, the pass
+    // switches itself off
+    const int RB = std::min(c->prm.max_restarts, GS_RBMAX);
+    for (int b = 0; b < RB; ++b) {
+        u32* skw = gs + GS_RB0 + b;
+        launch_gate_exceed(stat, ninst, gs, skw, rx, st);
+        launch_copy_h<T>(s.posh, s.hcache, n, st, skw);
+        TRY(build_caches<T>(c, rx, skw, ninst == 1));
+        launch_gate_round(P<u32>(c->flags), 0x37u, P<double>(c->rhmax_d), inst, ninst, rk, skw, gs,
+                          rx, st);
+        launch_stat_reset(stat, ninst, 1, rx, st);
+        launch_density<T>(s, P<u32>(c->id), group_map(c), c->n_groups, inst, sp, cache_view(c),
+                          P<T>(c->omega), P<vec4<T>>(c->thermo), P<u8>(c->status), stat, rx, st);
+        TRY(check_launch(c, "density (rebuild round)"));
+    }
     launch_gate_density(stat, ninst, gs, gate, st);
     // force and corrector
     const SortedPtrs<T> s1 = sorted<T>(c, true);
@@ -1341,6 +1368,14 @@ template <class T> int graph_pass(shsph_ctx* c, std::vector<int>& rr, int* rc, b
     hipStream_t st = c->stream;
     const int ninst = c->ninst;
     std::vector<i64> key = pass_key(c);
+    // after a replay that switched itself off, the next passes of the shape
+    // (1, 2, 4 .. 16 of them, doubling while replays keep aborting) run
+    // launch by launch: a batch that rebuilds its caches in most passes
+    // would otherwise pay for both
+    if (c->gexec && key == c->gkey && c->graph_wait > 0) {
+        --c->graph_wait;
+        return SHSPH_OK;
+    }
     if (!(c->gexec && key == c->gkey)) {
         if (key != c->last_key || key == c->nocap_key) return SHSPH_OK;
         graph_drop(c);
@@ -1380,26 +1415,33 @@ template <class T> int graph_pass(shsph_ctx* c, std::vector<int>& rr, int* rc, b
     u32* gs = P<u32>(c->gstate);
     HIPTRY(c, hipMemcpyAsync(pin, c->stat_d.p, o_rr, hipMemcpyDeviceToHost, st));
     HIPTRY(c, hipMemcpyAsync(pin + o_rr, gs + GS_WORDS, ninst * sizeof(u32), hipMemcpyDeviceToHost, st));
-    HIPTRY(c, hipMemcpyAsync(pin + o_gs, gs, sizeof(u32), hipMemcpyDeviceToHost, st));
-    HIPTRY(c, hipMemcpyAsync(pin + o_gs + 4, P<u32>(c->xscan) + c->n, sizeof(u32),
+    const size_t o_x = o_gs + GS_WORDS * sizeof(u32);
+    HIPTRY(c, hipMemcpyAsync(pin + o_gs, gs, GS_WORDS * sizeof(u32), hipMemcpyDeviceToHost, st));
+    HIPTRY(c, hipMemcpyAsync(pin + o_x, P<u32>(c->xscan) + c->n, sizeof(u32),
                              hipMemcpyDeviceToHost, st));
-    HIPTRY(c, hipMemcpyAsync(pin + o_gs + 8, P<u64>(c->gbase) + c->n_groups, sizeof(u64),
+    HIPTRY(c, hipMemcpyAsync(pin + o_x + 8, P<u64>(c->gbase) + c->n_groups, sizeof(u64),
                              hipMemcpyDeviceToHost, st));
     HIPTRY(c, hipStreamSynchronize(st));
-    u32 abort_w = 0, nl = 0;
+    u32 gw[GS_WORDS], nl = 0;
     u64 words = 0;
-    memcpy(&abort_w, pin + o_gs, 4);
-    memcpy(&nl, pin + o_gs + 4, 4);
-    memcpy(&words, pin + o_gs + 8, 8);
+    memcpy(gw, pin + o_gs, sizeof(gw));
+    memcpy(&nl, pin + o_x, 4);
+    memcpy(&words, pin + o_x + 8, 8);
+    const u32 abort_w = gw[0];
     if (abort_w) {
         ++c->graph_aborts;
+        c->graph_abort_why = abort_w;
+        c->graph_backoff = std::min(2 * c->graph_backoff + 1, 16);
+        c->graph_wait = c->graph_backoff;
         return SHSPH_OK;
     }
     ++c->graph_passes;
+    c->graph_backoff = 0;
     c->n_leaf = nl;
     c->n_internal = (i64)nl - ninst;
     c->cache_words = words;
     c->restarts = 0;
+    for (int b = 0; b < std::min(c->prm.max_restarts, GS_RBMAX); ++b) c->restarts += gw[GS_RB0 + b] == 0u;
     c->parts_pending = 0;
     rr.assign(ninst, 0);
     u32 nc = 0;
@@ -1885,6 +1927,7 @@ int shsph_get_info(shsph_ctx* c, shsph_info* o)
     o->cfl_multiplier = c->lambda_cfl;
     o->graph_passes = c->graph_passes;
     o->graph_aborts = c->graph_aborts;
+    o->graph_abort_why = (int32_t)c->graph_abort_why;
     HIPTRY(c, hipSetDevice(c->device));
     if (c->state >= ST_TREE) {
         u64 t1 = 0, t2 = 0;

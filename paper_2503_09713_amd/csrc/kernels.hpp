@@ -120,7 +120,7 @@ void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 grid_leaves, i64 lb
                      const u32* child, const u32* parent, const u32* endrange, const i64* ioff,
                      const i64* leaf_off, int ninst, u32* arrive, u32* rec, u32* nrec,
                      u32* rscan, void* scan_tmp, vec4<T>* blo, vec4<T>* bhi, u32* flags,
-                     hipStream_t st);
+                     hipStream_t st, const u32* skip = nullptr);
 size_t boxes_rec_count(i64 n_leaf);
 // Export in compact numbering (leaf j at row n_internal + j).
 void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* ioff, int ninst,
@@ -130,7 +130,7 @@ void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* iof
 // neigh.hip
 template <class T>
 void launch_group_boxes(const vec4<T>* posh, const GroupMap& gm, i64 ngroups, vec4<T>* glo,
-                        vec4<T>* ghi, hipStream_t st);
+                        vec4<T>* ghi, hipStream_t st, const u32* skip = nullptr);
 template <class T>
 void launch_group_leaves(const vec4<T>* blo, const vec4<T>* bhi, const u32* child, const u32* id,
                          const u32* xscan, i64 n_internal, const vec4<T>* glo, const vec4<T>* ghi,
@@ -151,7 +151,7 @@ void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* 
 // with a quarter's headroom, never above what the group's union could fill;
 // gbase = exclusive scan of the capacities (gbase[ngroups] = total words).
 void launch_cache_plan(const u32* ustot, const u32* gneed, i64 ngroups, u32 dflt, u32* gcap,
-                       u64* gbase, void* scan_tmp, hipStream_t st);
+                       u64* gbase, void* scan_tmp, hipStream_t st, const u32* skip = nullptr);
 // After an overflow: groups whose need exceeds their capacity get a larger
 // range appended at the end (gbase[ngroups] grows) and gredo = 1; the others
 // keep theirs (gredo = 0).
@@ -180,9 +180,14 @@ void launch_gate_build(const u32* flags, u32 mask0, int w_sort, int w_leaves, co
                        const InstDev* inst, int ninst, double rk, u32* gs, u8* gate, u32* reruns,
                        hipStream_t st);
 void launch_gate_density(const InstStat* stat, int ninst, u32* gs, u8* gate, hipStream_t st);
+void launch_gate_exceed(const InstStat* stat, int ninst, const u32* gs, u32* skw, u8* rx,
+                        hipStream_t st);
+void launch_gate_round(const u32* flags, u32 mask0, const double* rhmax, const InstDev* inst,
+                       int ninst, double rk, const u32* skw, u32* gs, u8* rx, hipStream_t st);
 void launch_rerun_decide(const InstStat* stat, const i64* p_off, int ninst, double eps_v,
                          int max_reruns, int r, u32* gs, u8* redo, u32* reruns, hipStream_t st);
-template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStream_t st);
+template <class T>
+void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStream_t st, const u32* skip = nullptr);
 template <class T>
 void launch_density(const SortedPtrs<T>& s, const u32* id, const GroupMap& gm, i64 ngroups,
                     const InstDev* inst, const SphParams& P, const CacheView& cv, T* omega,

@@ -88,9 +88,10 @@ __device__ inline bool prune_interior(const vec4<T>& l, const vec4<T>& h, T hmax
 template <class T>
 __global__ void __launch_bounds__(GROUP)
 k_group_boxes(const vec4<T>* __restrict__ posh, const GroupMap gm, vec4<T>* __restrict__ glo,
-              vec4<T>* __restrict__ ghi)
+              vec4<T>* __restrict__ ghi, const u32* __restrict__ skip)
 {
     __shared__ T red[GROUP / WAVE][7];
+    if (skip && *skip) return;
     const i64 g = blockIdx.x;
     i64 beg, end;
     int k;
@@ -225,7 +226,7 @@ k_group_leaves_serial(bool only_marked, const vec4<T>* __restrict__ blo, const v
 // (6 KB per wave, so many more waves hide the tree's load latency) and takes
 // the compact groups, marking the others; FULL = true, with the per-entry
 // target masks and the target boxes, then takes the marked groups.
-constexpr int S1_WAVES = 2;             // waves per workgroup, full walk
+constexpr int S1_WAVES = 1;             // waves per workgroup, full walk
 constexpr int S1_CWAVES = 4;            // waves per workgroup, compact walk
 constexpr int S1_SMAX = 1536;
 constexpr u32 S1_WIDE = 0xfffffffeu;    // ucnt marker: group left to the full walk
@@ -970,10 +971,11 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
 
 // Capacity plan of a build (see kernels.hpp): one thread per group.
 __global__ void k_cache_plan(const u32* __restrict__ ustot, const u32* __restrict__ gneed,
-                             i64 ngroups, u32 dflt, u32* __restrict__ gcap)
+                             i64 ngroups, u32 dflt, u32* __restrict__ gcap,
+                             const u32* __restrict__ skip)
 {
     const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ngroups) return;
+    if (g >= ngroups || (skip && *skip)) return;
     const u32 need = gneed ? gneed[g] : 0u;
     u32 w = need ? need + need / 4u + 2u : dflt;
     const u32 S = ustot[g];                        // a lane holds at most the union
@@ -1033,11 +1035,11 @@ k_cache_to_global(const u32* __restrict__ id, const GroupMap gm, i64 cap,
 
 template <class T>
 void launch_group_boxes(const vec4<T>* posh, const GroupMap& gm, i64 ngroups, vec4<T>* glo,
-                        vec4<T>* ghi, hipStream_t st)
+                        vec4<T>* ghi, hipStream_t st, const u32* skip)
 {
     if (ngroups <= 0) return;
     hipLaunchKernelGGL((k_group_boxes<T>), dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, gm,
-                       glo, ghi);
+                       glo, ghi, skip);
 }
 
 template <class T>
@@ -1083,11 +1085,12 @@ void launch_group_cache(const vec4<T>* posh, const vec4<T>* blo, const vec4<T>* 
 }
 
 void launch_cache_plan(const u32* ustot, const u32* gneed, i64 ngroups, u32 dflt, u32* gcap,
-                       u64* gbase, void* scan_tmp, hipStream_t st)
+                       u64* gbase, void* scan_tmp, hipStream_t st, const u32* skip)
 {
     if (ngroups <= 0) return;
+    // (with skip set the scan recomputes the same layout from the same gcap)
     hipLaunchKernelGGL(k_cache_plan, dim3((unsigned)((ngroups + 255) / 256)), dim3(256), 0, st, ustot, gneed, ngroups,
-                       dflt, gcap);
+                       dflt, gcap, skip);
     scan_u32_u64(gcap, gbase, ngroups, scan_tmp, st);
 }
 
@@ -1111,7 +1114,7 @@ void launch_cache_to_global(const u32* id, const GroupMap& gm, i64 ngroups, i64 
 
 #define INST(T)                                                                                   \
     template void launch_group_boxes<T>(const vec4<T>*, const GroupMap&, i64, vec4<T>*, vec4<T>*, \
-                                        hipStream_t);                                             \
+                                        hipStream_t, const u32*);                                 \
     template void launch_group_leaves<T>(const vec4<T>*, const vec4<T>*, const u32*, const u32*, const u32*,  \
                                          i64, const vec4<T>*, const vec4<T>*, i64,                \
                                          const GroupMap&, const u32*, const InstDev*, double,     \

@@ -65,7 +65,12 @@ __global__ void k_root_hmax(const vec4<T>* __restrict__ blo, const u32* __restri
 // twice the cache radius) or when some h left chi h_cache (a cache rebuild).
 // Every later stage then does nothing, the caller's arrays keep their state
 // and the host runs the pass again launch by launch.  gate[k] = 1 - gs[0]
-// for every instance (the density's per-instance switch).
+// for every instance (the density's per-instance switch).  The word tells
+// why: bit 0 the build's capacity / stack / box-record flags (flag word in
+// bits 8-15), bit 1 a sort look-back overrun, bit 2 the leaf pass's fallback
+// or overrun, bit 3 a periodic box below twice the cache radius, bit 4 a
+// rebuild round's flags (in bits 16-23), bit 5 an h still past chi h_cache
+// after the rebuild rounds.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_gate_build(const u32* __restrict__ flags, u32 mask0, int w_sort, int w_leaves,
@@ -73,19 +78,22 @@ k_gate_build(const u32* __restrict__ flags, u32 mask0, int w_sort, int w_leaves,
              double rk, u32* __restrict__ gs, u8* __restrict__ gate, u32* __restrict__ reruns)
 {
     __shared__ int s_bad;
-    if (threadIdx.x == 0)
-        s_bad = ((flags[0] & mask0) | flags[w_sort] | flags[w_leaves] | flags[w_leaves + 1]) != 0u;
+    if (threadIdx.x == 0) {
+        const u32 f0 = flags[0] & mask0;
+        s_bad = (int)((f0 ? 1u | (f0 << 8) : 0u) | (flags[w_sort] ? 2u : 0u) |
+                      ((flags[w_leaves] | flags[w_leaves + 1]) ? 4u : 0u));
+    }
     __syncthreads();
     for (int k = threadIdx.x; k < ninst; k += blockDim.x) {
         reruns[k] = 0u;
         const InstDev in = inst[k];
         if (!in.periodic) continue;
         for (int d = 0; d < 3; ++d)
-            if (rk * rhmax[k] >= 0.5 * (in.hi[d] - in.lo[d])) atomicOr(&s_bad, 1);
+            if (rk * rhmax[k] >= 0.5 * (in.hi[d] - in.lo[d])) atomicOr(&s_bad, 8);
     }
     __syncthreads();
     const bool bad = s_bad != 0;
-    if (threadIdx.x == 0) gs[0] = bad ? 1u : 0u;
+    if (threadIdx.x == 0) gs[0] = (u32)s_bad;
     for (int k = threadIdx.x; k < ninst; k += blockDim.x) gate[k] = bad ? 0 : 1;
 }
 
@@ -100,8 +108,55 @@ k_gate_density(const InstStat* __restrict__ stat, int ninst, u32* __restrict__ g
         if (stat[k].n_exceed) atomicOr(&s_bad, 1);
     __syncthreads();
     if (!s_bad) return;
-    if (threadIdx.x == 0) gs[0] = 1u;
+    if (threadIdx.x == 0) gs[0] |= 32u;
     for (int k = threadIdx.x; k < ninst; k += blockDim.x) gate[k] = 0;
+}
+
+// Cache-rebuild round of a captured pass: the instances with a particle past
+// chi h_cache (rx[k] = 1) get new caches and run the h iteration again, as
+// the launch-by-launch pass does; *skw = 1 when there are none (or the pass
+// was switched off), which switches the round's launches off.
+__global__ void __launch_bounds__(256)
+k_gate_exceed(const InstStat* __restrict__ stat, int ninst, const u32* __restrict__ gs,
+              u32* __restrict__ skw, u8* __restrict__ rx)
+{
+    __shared__ int s_any;
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    const bool off = gs[0] != 0u;
+    for (int k = threadIdx.x; k < ninst; k += blockDim.x) {
+        const bool x = !off && stat[k].n_exceed != 0u;
+        rx[k] = x ? 1 : 0;
+        if (x) atomicOr(&s_any, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *skw = s_any ? 0u : 1u;
+}
+
+// After a rebuild round's caches: the build's conditions (as k_gate_build)
+// switch the pass off, and the round's h iteration with it.
+__global__ void __launch_bounds__(256)
+k_gate_round(const u32* __restrict__ flags, u32 mask0, const double* __restrict__ rhmax,
+             const InstDev* __restrict__ inst, int ninst, double rk, const u32* __restrict__ skw,
+             u32* __restrict__ gs, u8* __restrict__ rx)
+{
+    __shared__ int s_bad;
+    if (*skw) return;
+    if (threadIdx.x == 0) {
+        const u32 f0 = flags[0] & mask0;
+        s_bad = (int)(f0 ? 16u | (f0 << 16) : 0u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < ninst; k += blockDim.x) {
+        const InstDev in = inst[k];
+        if (!in.periodic) continue;
+        for (int d = 0; d < 3; ++d)
+            if (rk * rhmax[k] >= 0.5 * (in.hi[d] - in.lo[d])) atomicOr(&s_bad, 8);
+    }
+    __syncthreads();
+    if (!s_bad) return;
+    if (threadIdx.x == 0) gs[0] |= (u32)s_bad;
+    for (int k = threadIdx.x; k < ninst; k += blockDim.x) rx[k] = 0;
 }
 
 // Corrector re-run round r of a captured pass (App. G.1, the reversibility
@@ -153,10 +208,11 @@ __global__ void k_dt_select(double* dt_inst, const InstStat* s, const double* dt
     dt_inst[k] = (h > 0.0) ? h : lam * (double)__uint_as_float(s[k].dt_bits);
 }
 
-template <class T> __global__ void k_copy_h(const vec4<T>* __restrict__ posh, T* __restrict__ hc, i64 n)
+template <class T> __global__ void k_copy_h(const vec4<T>* __restrict__ posh, T* __restrict__ hc, i64 n,
+                                            const u32* __restrict__ skip)
 {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) hc[i] = posh[i].w;
+    if (i < n && !(skip && *skip)) hc[i] = posh[i].w;
 }
 
 
@@ -198,17 +254,37 @@ template <class F> __device__ inline void entries_words(const u64* my, u32 cnt, 
     }
 }
 
+// Entries of one particle with slots in [c0, c1), from entry j on (the
+// tiled path: the union staged chunk by chunk, the entries ascending), f(slot
+// - c0) each; j is left at the first entry of a later chunk.  Each word is
+// read once per chunk, the next one loaded while the current one is used.
 // (w32: the group stores 32-bit slots, two per word.)
 template <class F>
 __device__ inline void entries_tile(const u64* my, u32 cnt, u32& j, u32 c0, u32 c1, bool w32,
                                     F&& f)
 {
-    while (j < cnt) {
-        const u64 w = my[(u64)(w32 ? j >> 1 : j >> 2) * GROUP];
-        const u32 sl = w32 ? slot32_of(w, j & 1u) : slot_of(w, j & 3u);
-        if (sl >= c1) break;
-        f(sl - c0);
-        ++j;
+    if (j >= cnt) return;
+    const u32 sh = w32 ? 1u : 2u, per = 1u << sh;
+    const u32 nq = (cnt + per - 1u) >> sh;
+    u32 q = j >> sh;
+    u64 w = my[(u64)q * GROUP];
+    for (;;) {
+        const u64 wn = my[(u64)(q + 1 < nq ? q + 1 : q) * GROUP];   // prefetch
+        const u32 rend = min(per, cnt - (q << sh));
+        for (u32 r = j & (per - 1u); r < rend; ++r) {
+            const u32 sl = w32 ? slot32_of(w, r) : slot_of(w, r);
+            if (sl >= c1) {
+                j = (q << sh) + r;
+                return;
+            }
+            f(sl - c0);
+        }
+        if (++q >= nq) {
+            j = cnt;
+            return;
+        }
+        j = q << sh;
+        w = wn;
     }
 }
 
@@ -1040,6 +1116,19 @@ void launch_gate_density(const InstStat* stat, int ninst, u32* gs, u8* gate, hip
     hipLaunchKernelGGL(k_gate_density, dim3(1), dim3(256), 0, st, stat, ninst, gs, gate);
 }
 
+void launch_gate_exceed(const InstStat* stat, int ninst, const u32* gs, u32* skw, u8* rx,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gate_exceed, dim3(1), dim3(256), 0, st, stat, ninst, gs, skw, rx);
+}
+
+void launch_gate_round(const u32* flags, u32 mask0, const double* rhmax, const InstDev* inst,
+                       int ninst, double rk, const u32* skw, u32* gs, u8* rx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gate_round, dim3(1), dim3(256), 0, st, flags, mask0, rhmax, inst, ninst, rk,
+                       skw, gs, rx);
+}
+
 void launch_rerun_decide(const InstStat* stat, const i64* p_off, int ninst, double eps_v,
                          int max_reruns, int r, u32* gs, u8* redo, u32* reruns, hipStream_t st)
 {
@@ -1053,13 +1142,13 @@ void launch_dt_select(double* dt_inst, const InstStat* s, const double* dt_host,
     hipLaunchKernelGGL(k_dt_select, grid_for(ninst, 64), dim3(64), 0, st, dt_inst, s, dt_host, ninst);
 }
 
-template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStream_t st)
+template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStream_t st, const u32* skip)
 {
-    if (n > 0) hipLaunchKernelGGL((k_copy_h<T>), grid_for(n, 256), dim3(256), 0, st, posh, hc, n);
+    if (n > 0) hipLaunchKernelGGL((k_copy_h<T>), grid_for(n, 256), dim3(256), 0, st, posh, hc, n, skip);
 }
 
 constexpr int DENS_CH_F = 2048, DENS_CH_D = 1024;
-constexpr int FORCE_CH_F = 1280, FORCE_CH_D = 640;
+constexpr int FORCE_CH_F = 1536, FORCE_CH_D = 640;
 
 template <class T, int K>
 void launch_density_k(const SortedPtrs<T>& s, const u32* id, const GroupMap& gm, i64 ngroups,
@@ -1319,7 +1408,7 @@ void launch_scatter_rho(const u32* eps, i64 n, const vec4<T>* posh, const i64* p
 }
 
 #define INST(T)                                                                                   \
-    template void launch_copy_h<T>(const vec4<T>*, T*, i64, hipStream_t);                         \
+    template void launch_copy_h<T>(const vec4<T>*, T*, i64, hipStream_t, const u32*);             \
     template void launch_density<T>(const SortedPtrs<T>&, const u32*, const GroupMap&, i64,       \
                                     const InstDev*, const SphParams&, const CacheView&, T*,       \
                                     vec4<T>*, u8*, InstStat*, const u8*, hipStream_t);             \

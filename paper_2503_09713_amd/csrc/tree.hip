@@ -590,9 +590,10 @@ k_boxes_local(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 
               const u32* __restrict__ endrange, const i64* __restrict__ ioff,
               const i64* __restrict__ leaf_off, int ninst, vec4<T>* __restrict__ blo,
               vec4<T>* __restrict__ bhi, u32* __restrict__ rec, u32* __restrict__ nrec,
-              u32* __restrict__ flags)
+              u32* __restrict__ flags, const u32* __restrict__ skip)
 {
     __shared__ vec4<T> s_llo[BOX_BLK], s_lhi[BOX_BLK];   // leaves of the block
+    if (skip && *skip) return;
     __shared__ vec4<T> s_nlo[BOX_BLK], s_nhi[BOX_BLK];   // internal nodes, by Karras index
     __shared__ u32 s_arr[BOX_BLK];
     __shared__ u32 s_rec[BOX_OUT];
@@ -691,10 +692,12 @@ k_boxes_mid(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nbloc
             const u32* __restrict__ child, const u32* __restrict__ parent,
             const u32* __restrict__ endrange, const i64* __restrict__ ioff,
             const i64* __restrict__ leaf_off, int ninst, u32* __restrict__ arrive, vec4<T>* blo,
-            vec4<T>* bhi, u32* __restrict__ rec2, u32* __restrict__ nrec2, u32* __restrict__ flags)
+            vec4<T>* bhi, u32* __restrict__ rec2, u32* __restrict__ nrec2, u32* __restrict__ flags,
+            const u32* __restrict__ skip)
 {
     __shared__ u32 s_rec[BOX_OUT];
     __shared__ u32 s_nrec;
+    if (skip && *skip) return;
     if (threadIdx.x == 0) s_nrec = 0;
     __syncthreads();
     const i64 n_leaf = leaf_off[ninst];
@@ -745,8 +748,9 @@ template <class T>
 __global__ void __launch_bounds__(TOP_BLOCK)
 k_boxes_top(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nblocks,
             const u32* __restrict__ child, const u32* __restrict__ parent,
-            u32* __restrict__ arrive, vec4<T>* blo, vec4<T>* bhi)
+            u32* __restrict__ arrive, vec4<T>* blo, vec4<T>* bhi, const u32* __restrict__ skip)
 {
+    if (skip && *skip) return;
     // thread t finishes the climbs recorded by blocks t, t + TOP_BLOCK, ...
     for (i64 b = threadIdx.x; b < nblocks; b += TOP_BLOCK) {
         const u32 nr = nrec[b];
@@ -1013,13 +1017,13 @@ void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 grid_leaves, i64 lb
                      const u32* child, const u32* parent, const u32* endrange, const i64* ioff,
                      const i64* leaf_off, int ninst, u32* arrive, u32* rec, u32* nrec,
                      u32* rscan, void* scan_tmp, vec4<T>* blo, vec4<T>* bhi, u32* flags,
-                     hipStream_t st)
+                     hipStream_t st, const u32* skip)
 {
     if (grid_leaves <= 0) return;
     const i64 nb = (grid_leaves + BOX_BLK - 1) / BOX_BLK;
     hipLaunchKernelGGL((k_boxes_local<T>), dim3((unsigned)nb), dim3(BOX_BLK), 0, st, posh, id,
                        lbase, child, parent, endrange, ioff, leaf_off, ninst, blo, bhi, rec,
-                       nrec, flags);
+                       nrec, flags, skip);
     if (nb > 1) {
         // middle level (ranges of BOX_MID local blocks), then one workgroup
         // for the climbs that cross those ranges
@@ -1028,10 +1032,10 @@ void launch_boxes_up(const vec4<T>* posh, const u32* id, i64 grid_leaves, i64 lb
         u32* nrec2 = nrec + nb;
         hipLaunchKernelGGL((k_boxes_mid<T>), dim3((unsigned)nb2), dim3(BOX_MID), 0, st, rec, nrec,
                            nb, child, parent, endrange, ioff, leaf_off, ninst, arrive, blo,
-                           bhi, rec2, nrec2, flags);
+                           bhi, rec2, nrec2, flags, skip);
         if (nb2 > 1)
             hipLaunchKernelGGL((k_boxes_top<T>), dim3(1), dim3(TOP_BLOCK), 0, st, rec2, nrec2, nb2,
-                               child, parent, arrive, blo, bhi);
+                               child, parent, arrive, blo, bhi, skip);
     }
 }
 
@@ -1062,7 +1066,7 @@ void launch_prefix_boxes(const u64* mu_leaf, const i64* leaf_off, const i64* iof
     template void launch_boxes_up<T>(const vec4<T>*, const u32*, i64, i64, const u32*,            \
                                      const u32*, const u32*, const i64*, const i64*, int, u32*,   \
                                      u32*, u32*, u32*, void*, vec4<T>*, vec4<T>*, u32*,           \
-                                     hipStream_t);
+                                     hipStream_t, const u32*);
 INST(float)
 INST(double)
 #undef INST

@@ -2,9 +2,10 @@
 one by one (graph_batch = 0).  The captured pass runs the same kernels in
 the same order, with the host's decisions between launches taken on the
 device, so every field must be bit-identical pass after pass: plain CFL
-steps (FP32 and FP64), steps with corrector re-runs, and steps whose h
-leaves chi h_cache, where the captured pass switches itself off on the
-device and the host runs it again launch by launch."""
+steps (FP32 and FP64), steps with corrector re-runs, steps whose h
+leaves chi h_cache (cache-rebuild rounds inside the captured pass), and
+passes that switch themselves off on the device, which the host then runs
+again launch by launch."""
 import sys
 
 import numpy as np
@@ -51,12 +52,13 @@ def _mix(T):
 
 
 def _hubble(seed, rate):
-    """Isolated lattice expanding as v = rate (x - centre): the density drops
-    by (1 + rate dt)^3 per step, so h grows past chi h_cache in every step.
-    It starts from the oracle's self-consistent h (the surface's h is far
-    above the lattice value)."""
+    """Cold isolated lattice expanding as v = rate (x - centre): the density
+    drops by about (1 + rate dt)^3 per step, so with rate dt = 0.18 h grows
+    past chi h_cache in every step.  It starts from the oracle's
+    self-consistent h (the surface's h is far above the lattice value)."""
     p = gen.lattice(10, seed, dtype=np.float32)
     p.periodic = False
+    p.u = (p.u * 0.1).astype(np.float32)
     lo = (float(p.x.min()), float(p.y.min()), float(p.z.min()))
     hi = (float(p.x.max()), float(p.y.max()), float(p.z.max()))
     h, _, _, fl = oracle.density(p.x, p.y, p.z, p.h, lo, hi, False, p.mass)
@@ -117,14 +119,30 @@ def test_graph_corrector_reruns_equal_eager(torch_cuda):
     assert ib["graph_passes"] >= 3
 
 
-def test_graph_abort_falls_back(torch_cuda):
+def test_graph_rebuild_rounds_equal_eager(torch_cuda):
     """Expanding instances: h leaves chi h_cache in every step, so each
-    replayed pass switches itself off after the density and is run again
-    launch by launch (with its cache rebuilds); same results."""
-    _say("[graph] every replay aborts (h past chi h_cache) and falls back")
-    ps = [_hubble(51, 1.2), _random_state(gen.lattice(8, 52, dtype=np.float32), 6)]
-    kw = dict(dt=0.1, allow_noconv=True, max_restarts=8)
+    captured pass runs its cache-rebuild rounds (new caches for the
+    instances concerned, the h iteration again), decided on the device."""
+    _say("[graph] cache-rebuild rounds inside the captured pass")
+    ps = [_hubble(51, 4.5), _random_state(gen.lattice(8, 52, dtype=np.float32), 6, vscale=0.02)]
+    kw = dict(dt=0.04, allow_noconv=True)
     a, _ = _run(ps, 4, **kw, graph_batch=0)
     b, ib = _run(ps, 4, **kw, graph_batch=1)
+    _same(a, b)
+    for _, snap in b:
+        for f, _r in snap:
+            assert np.isfinite(f["x"]).all() and np.isfinite(f["h"]).all()
+    assert ib["graph_passes"] >= 2, ib
+
+
+def test_graph_abort_falls_back(torch_cuda):
+    """No rebuild allowed (max_restarts = 0): the captured pass switches
+    itself off after the density and the host runs it again launch by launch
+    (which reports the particles that did not converge); same results."""
+    _say("[graph] replays that abort (h past chi h_cache, no rebuilds) fall back")
+    ps = [_hubble(51, 4.5), _random_state(gen.lattice(8, 52, dtype=np.float32), 6, vscale=0.02)]
+    kw = dict(dt=0.04, allow_noconv=True, max_restarts=0)
+    a, _ = _run(ps, 6, **kw, graph_batch=0)
+    b, ib = _run(ps, 6, **kw, graph_batch=1)
     _same(a, b)
     assert ib["graph_aborts"] >= 1, ib
