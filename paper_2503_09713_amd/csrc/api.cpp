@@ -721,9 +721,24 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo, const u32* ski
         prof_end(c);
         TRY(check_launch(c, "stage2"));
         launch_root_hmax<T>(P<vec4<T>>(c->blo), P<u32>(c->root_d), ninst, P<double>(c->rhmax_d), st);
-        if (c->capturing) {      // one attempt; the flags and radii go to the pass's gate
+        if (c->capturing) {
+            // groups that outgrew their capacity get a larger range at the end
+            // of the layout and run stage 2 again, as below (device-side; a
+            // layout past the buffer is flagged); the other flags and the
+            // radii go to the pass's gate
+            launch_cache_regrow(P<u32>(c->gneed), G, P<u32>(c->gcap), P<u64>(c->gbase),
+                                P<u8>(c->gredo), st);
+            launch_flag_and(P<u32>(c->flags), ~4u, st);
+            launch_group_cache<T>(posh, P<vec4<T>>(c->blo), P<vec4<T>>(c->bhi), P<u32>(c->id),
+                                  P<u32>(c->xscan), lb, gm, G, inst, rk, rk, c->cap_leaf,
+                                  P<u32>(c->uleaf), P<u32>(c->uslot), P<u32>(c->ucnt),
+                                  P<u32>(c->ustot), P<u64>(c->gbase), P<u32>(c->gcap),
+                                  (u64)(c->nlist.cap / WORD_BYTES), P<u32>(c->gneed),
+                                  P<u8>(c->gredo), P<u64>(c->nlist), P<u32>(c->ncnt),
+                                  P<u32>(c->flags), P<vec4<T>>(c->glo), P<vec4<T>>(c->ghi),
+                                  P<u32>(c->root_d), nullptr, c->prm.stage2_mode, nullptr, st);
             c->gneed_groups = G;
-            return SHSPH_OK;
+            return check_launch(c, "stage2 (regrow)");
         }
         HIPTRY(c, hipMemcpyAsync(c->pinned, c->flags.p, FLAG_WORDS * sizeof(u32),
                                  hipMemcpyDeviceToHost, st));

@@ -182,6 +182,7 @@ void launch_gate_build(const u32* flags, u32 mask0, int w_sort, int w_leaves, co
 void launch_gate_density(const InstStat* stat, int ninst, u32* gs, u8* gate, hipStream_t st);
 void launch_gate_exceed(const InstStat* stat, int ninst, const u32* gs, u32* skw, u8* rx,
                         hipStream_t st);
+void launch_flag_and(u32* f, u32 mask, hipStream_t st);     // f[0] &= mask
 void launch_gate_round(const u32* flags, u32 mask0, const double* rhmax, const InstDev* inst,
                        int ninst, double rk, const u32* skw, u32* gs, u8* rx, hipStream_t st);
 void launch_rerun_decide(const InstStat* stat, const i64* p_off, int ninst, double eps_v,

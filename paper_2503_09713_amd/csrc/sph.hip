@@ -1116,6 +1116,13 @@ void launch_gate_density(const InstStat* stat, int ninst, u32* gs, u8* gate, hip
     hipLaunchKernelGGL(k_gate_density, dim3(1), dim3(256), 0, st, stat, ninst, gs, gate);
 }
 
+__global__ void k_flag_and(u32* f, u32 mask) { f[0] &= mask; }
+
+void launch_flag_and(u32* f, u32 mask, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flag_and, dim3(1), dim3(1), 0, st, f, mask);
+}
+
 void launch_gate_exceed(const InstStat* stat, int ninst, const u32* gs, u32* skw, u8* rx,
                         hipStream_t st)
 {

@@ -146,3 +146,16 @@ def test_graph_abort_falls_back(torch_cuda):
     b, ib = _run(ps, 6, **kw, graph_batch=1)
     _same(a, b)
     assert ib["graph_aborts"] >= 1, ib
+
+
+def test_graph_batch_with_cache_regrows(torch_cuda):
+    """Twelve instances of the batched workload (lattices and Plummer spheres,
+    2^12 .. 2^17 particles): the Plummer groups' cache needs move between
+    steps, so groups outgrow their planned capacity and get a larger range
+    at the end of the layout inside the captured pass (on the device)."""
+    _say("[graph] batched workload, 12 instances: regrows inside captured passes")
+    ps = gen.batch(seed=gen.SEEDS["batch"], n_inst=12, log2_hi=17.0)
+    a, _ = _run(ps, 5, graph_batch=0)
+    b, ib = _run(ps, 5, graph_batch=1)
+    _same(a, b)
+    assert ib["graph_passes"] >= 2, ib
