@@ -84,35 +84,45 @@ __device__ inline bool prune_interior(const vec4<T>& l, const vec4<T>& h, T hmax
            h.x + r < bx.hi[0] && h.y + r < bx.hi[1] && h.z + r < bx.hi[2];
 }
 
-// Tight box and h_max of each group (one workgroup per group).
+// Tight box and h_max of each group: one wave per group (GB_WAVES groups
+// per workgroup), each lane taking every 64th particle; min / max are exact,
+// so the order of the reduction does not matter.
+constexpr int GB_WAVES = 4;
+
 template <class T>
-__global__ void __launch_bounds__(GROUP)
-k_group_boxes(const vec4<T>* __restrict__ posh, const GroupMap gm, vec4<T>* __restrict__ glo,
-              vec4<T>* __restrict__ ghi, const u32* __restrict__ skip)
+__global__ void __launch_bounds__(GB_WAVES * WAVE)
+k_group_boxes(const vec4<T>* __restrict__ posh, const GroupMap gm, i64 ngroups,
+              vec4<T>* __restrict__ glo, vec4<T>* __restrict__ ghi, const u32* __restrict__ skip)
 {
-    __shared__ T red[GROUP / WAVE][7];
     if (skip && *skip) return;
-    const i64 g = blockIdx.x;
+    const i64 g = (i64)blockIdx.x * GB_WAVES + threadIdx.x / WAVE;
+    if (g >= ngroups) return;                  // per wave; no workgroup barrier below
     i64 beg, end;
     int k;
     gm.range(g, beg, end, k);
-    const i64 a = beg + threadIdx.x;
-    const bool live = a < end;
-    const vec4<T> p = posh[live ? a : beg];
-    T v[7] = { p.x, p.y, p.z, -p.x, -p.y, -p.z, p.w };     // all reduced with min, h with max
-    v[6] = -p.w;
+    const int lane = __lane_id();
+    T v[7];                                    // min of x, y, z, -x, -y, -z, -h
+    {
+        const vec4<T> p = posh[beg];
+        v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = -p.x; v[4] = -p.y; v[5] = -p.z; v[6] = -p.w;
+    }
+#pragma unroll
+    for (int j = 0; j < GROUP / WAVE; ++j) {
+        const i64 a = beg + lane + j * WAVE;
+        if (a < end) {
+            const vec4<T> p = posh[a];
+            v[0] = fmin(v[0], p.x); v[1] = fmin(v[1], p.y); v[2] = fmin(v[2], p.z);
+            v[3] = fmin(v[3], -p.x); v[4] = fmin(v[4], -p.y); v[5] = fmin(v[5], -p.z);
+            v[6] = fmin(v[6], -p.w);
+        }
+    }
+#pragma unroll
     for (int c = 0; c < 7; ++c) {
         T x = v[c];
         for (int d = WAVE / 2; d > 0; d >>= 1) x = fmin(x, __shfl_xor(x, d, WAVE));
         v[c] = x;
     }
-    const int lane = __lane_id(), wid = threadIdx.x / WAVE;
-    if (lane == 0)
-        for (int c = 0; c < 7; ++c) red[wid][c] = v[c];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < GROUP / WAVE; ++w)
-            for (int c = 0; c < 7; ++c) v[c] = fmin(v[c], red[w][c]);
+    if (lane == 0) {
         glo[g] = mk4<T>(v[0], v[1], v[2], -v[6]);
         ghi[g] = mk4<T>(-v[3], -v[4], -v[5], T(0));
     }
@@ -1038,8 +1048,8 @@ void launch_group_boxes(const vec4<T>* posh, const GroupMap& gm, i64 ngroups, ve
                         vec4<T>* ghi, hipStream_t st, const u32* skip)
 {
     if (ngroups <= 0) return;
-    hipLaunchKernelGGL((k_group_boxes<T>), dim3((unsigned)ngroups), dim3(GROUP), 0, st, posh, gm,
-                       glo, ghi, skip);
+    hipLaunchKernelGGL((k_group_boxes<T>), dim3((unsigned)((ngroups + GB_WAVES - 1) / GB_WAVES)),
+                       dim3(GB_WAVES * WAVE), 0, st, posh, gm, ngroups, glo, ghi, skip);
 }
 
 template <class T>
