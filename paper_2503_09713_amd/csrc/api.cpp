@@ -485,8 +485,7 @@ CacheView cache_view(shsph_ctx* c)
 // ones (stepping); the gather then also forms v*, u*, v^{n+1/2}, u^{n+1/2}.
 // ---------------------------------------------------------------------------
 template <class T>
-int build_caches(shsph_ctx* c, const u8* redo = nullptr, const u32* skip = nullptr,
-                 bool plan_anyway = false);
+int build_caches(shsph_ctx* c, const u8* redo = nullptr, const u32* skip = nullptr);
 template <class T> int build_tree_tables(shsph_ctx* c, i64 nl);
 
 template <class T> int build(shsph_ctx* c, const FieldPtrs<T>& f, i64 n, const double* dt_dev, bool step)
@@ -636,10 +635,10 @@ template <class T> int build_tree_tables(shsph_ctx* c, i64 nl)
 // caches; the others keep the ones of the previous build (valid: their h
 // stayed within chi h_cache).  A capacity regrow changes the layout, so the
 // retry rebuilds every group.
-// While capturing, `skip` (a device word) switches the box launches off and
-// `plan_anyway` lays the cache out afresh even with `redo` (a rebuild round
-// of a single-instance pass, which the launch-by-launch pass replans).
-template <class T> int build_caches(shsph_ctx* c, const u8* redo, const u32* skip, bool plan_anyway)
+// While capturing, `skip` (a device word) switches the box launches off.
+// With `redo` the layout is kept: the instances concerned write into their
+// groups' ranges (a group that outgrows its range gets a new one appended).
+template <class T> int build_caches(shsph_ctx* c, const u8* redo, const u32* skip)
 {
     hipStream_t st = c->stream;
     // launch bounds: the leaf and internal counts, or their largest values
@@ -679,7 +678,7 @@ template <class T> int build_caches(shsph_ctx* c, const u8* redo, const u32* ski
     TRY(ensure(c, c->gredo, G));
     const size_t WORD_BYTES = (size_t)GROUP * sizeof(u64);    // one word of every lane of a group
     bool run_stage1 = true;
-    bool plan = redo == nullptr || plan_anyway;   // a rebuild of some instances keeps the others' layout
+    bool plan = redo == nullptr;     // a rebuild of some instances keeps the others' layout
     const u8* gredo = nullptr;       // regrow retry: only the groups that overflowed
     for (int attempt = 0;; ++attempt) {
         // stage 1: neighbour leaves of each group
@@ -1331,7 +1330,11 @@ template <class T> int graph_body(shsph_ctx* c)
         u32* skw = gs + GS_RB0 + b;
         launch_gate_exceed(stat, ninst, gs, skw, rx, st);
         launch_copy_h<T>(s.posh, s.hcache, n, st, skw);
-        TRY(build_caches<T>(c, rx, skw, ninst == 1));
+        // the layout is kept (no new plan inside the pass): a plan's scan
+        // would recompute every group's offset, also in a round that is
+        // switched off, and so move groups that an earlier regrow placed at
+        // the end of the layout away from what stage 2 wrote
+        TRY(build_caches<T>(c, rx, skw));
         launch_gate_round(P<u32>(c->flags), 0x37u, P<double>(c->rhmax_d), inst, ninst, rk, skw, gs,
                           rx, st);
         launch_stat_reset(stat, ninst, 1, rx, st);

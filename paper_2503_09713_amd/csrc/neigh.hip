@@ -24,7 +24,7 @@ namespace shsph {
 constexpr int STACK = 64;   // tree depth is bounded by the 63 key bits
 constexpr int TRAV_BLOCK = 64;
 constexpr int LCHUNK = 256;  // union leaves staged in LDS at a time (stage 2)
-constexpr int UCH = 1536;    // union particles staged in LDS (larger unions read HBM/L2)
+constexpr int UCH = 1280;    // union particles staged in LDS (larger unions read HBM/L2)
 
 template <class T> struct Inflate;
 template <> struct Inflate<float> {
@@ -639,8 +639,8 @@ template <class T, bool LDS, bool WRAP, class Q>
 __device__ inline void cache_walk_lane(const vec4<T>& pa, T qa, bool live, u32 S, u32 nu,
                                        const Box<T>& bx,
                                        T rkc, const u64* mrow, const u32* s_b0, const u32* s_b1,
-                                       const u32* s_slot, const vec4<T>* s_lo,
-                                       const vec4<T>* s_hi, const vec4<T>* s_upos,
+                                       const u32* s_slot, const u32* ulc, const vec4<T>* lblo,
+                                       const vec4<T>* lbhi, const vec4<T>* s_upos,
                                        const vec4<T>* posh, Q& lq, u32 capq, u32& tested)
 {
     bool refine = false;
@@ -662,7 +662,15 @@ __device__ inline void cache_walk_lane(const vec4<T>& pa, T qa, bool live, u32 S
                 const u32 b = (u32)(__ffsll((unsigned long long)cur) - 1);
                 cur &= cur - 1;
                 const u32 j = (u32)(w * 64) + b;
-                if (!leaf_reach<T>(pa, qa, s_lo[j], s_hi[j])) m &= ~(1ull << b);
+                const u32 leaf = ulc[j];
+                const vec4<T> bl = lblo[leaf];
+                vec4<T> bh = lbhi[leaf];
+                {
+#pragma clang fp contract(off)
+                    const T r = rkc * bl.w;
+                    bh.w = q_clean(r * r);
+                }
+                if (!leaf_reach<T>(pa, qa, bl, bh)) m &= ~(1ull << b);
             }
         }
         mk[w] = m;
@@ -786,8 +794,6 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
     __shared__ u32 s_slot[LCHUNK];
     // union-leaf boxes of the chunk (.w of the high corner: q of the leaf's
     // h_max), for the prune and the per-particle leaf test
-    __shared__ vec4<T> s_lo[LCHUNK];
-    __shared__ vec4<T> s_hi[LCHUNK];
     // target-leaf boxes (prune only, loaded per chunk); the walk reuses the
     // space for the lanes' queues (pending entries carried over chunks in a
     // register)
@@ -857,20 +863,14 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         const u32 nl = c1 - c0;
         boxtests += (u64)nt * nl;
         __syncthreads();
+        vec4<T> ul{}, uh{};      // this thread's union leaf of the chunk (prune)
         for (u32 j = c0 + threadIdx.x; j < c1; j += GROUP) {
             const u32 leaf = uleaf[g * cap + j];
             s_b0[j - c0] = id[leaf];
             s_b1[j - c0] = id[leaf + 1];
             s_slot[j - c0] = uslot[g * cap + j];
-            const vec4<T> ul = blo[n_internal + leaf];
-            vec4<T> uh = bhi[n_internal + leaf];
-            {
-#pragma clang fp contract(off)
-                const T r = rkc * ul.w;
-                uh.w = q_clean(r * r);            // q of the leaf's h_max
-            }
-            s_lo[j - c0] = ul;
-            s_hi[j - c0] = uh;
+            ul = blo[n_internal + leaf];
+            uh = bhi[n_internal + leaf];
         }
         for (u32 t = threadIdx.x; t < nt; t += GROUP) {
             s_tlo[t] = blo[n_internal + t0 + t];
@@ -886,7 +886,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
                 for (u32 t = __lane_id(); t < nt; t += WAVE) s_mask[t][wv] = 0ull;
             } else {
                 const bool jv = j < nl;
-                const vec4<T> bl = s_lo[jv ? j : 0], bh = s_hi[jv ? j : 0];
+                const vec4<T> bl = ul, bh = uh;
                 for (u32 t = 0; t < nt; ++t) {
                     const bool hit = jv && (prune_wrap ? box_hit<T, true>(s_tlo[t], s_thi[t], bl, bh, rk, eps_abs, bx)
                                                        : box_hit<T, false>(s_tlo[t], s_thi[t], bl, bh, rk, eps_abs, bx));
@@ -920,7 +920,7 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         if (w32) {
             // exact for interior groups too: no image is closer there
             cache_walk_lane<T, false, true>(pa, qa, live, S, nu, bx, rkc, s_mask[ta], s_b0, s_b1,
-                                            s_slot, s_lo, s_hi, s_upos, posh, wq, capq, tested);
+                                            s_slot, uleaf + g * cap + c0, blo + n_internal, bhi + n_internal, s_upos, posh, wq, capq, tested);
         } else if (mode != 1 && uniform) {
             if (in_lds && interior)
                 cache_walk_wave<T, true, false>(pa, qa, live, bx, rkc, wm, s_b0, s_b1, s_slot,
@@ -934,17 +934,17 @@ k_group_cache(const vec4<T>* __restrict__ posh, const vec4<T>* __restrict__ blo,
         } else if (mode != 2) {
             if (in_lds && interior)
                 cache_walk_lane<T, true, false>(pa, qa, live, S, nu, bx, rkc, s_mask[ta], s_b0, s_b1,
-                                                s_slot, s_lo, s_hi, s_upos, posh, lq, capq, tested);
+                                                s_slot, uleaf + g * cap + c0, blo + n_internal, bhi + n_internal, s_upos, posh, lq, capq, tested);
             else if (in_lds)
                 cache_walk_lane<T, true, true>(pa, qa, live, S, nu, bx, rkc, s_mask[ta], s_b0, s_b1,
-                                               s_slot, s_lo, s_hi, s_upos, posh, lq, capq, tested);
+                                               s_slot, uleaf + g * cap + c0, blo + n_internal, bhi + n_internal, s_upos, posh, lq, capq, tested);
             else if (interior)
                 cache_walk_lane<T, false, false>(pa, qa, live, S, nu, bx, rkc, s_mask[ta], s_b0, s_b1,
-                                                 s_slot, s_lo, s_hi, s_upos, posh, lq, capq,
+                                                 s_slot, uleaf + g * cap + c0, blo + n_internal, bhi + n_internal, s_upos, posh, lq, capq,
                                                  tested);
             else
                 cache_walk_lane<T, false, true>(pa, qa, live, S, nu, bx, rkc, s_mask[ta], s_b0, s_b1,
-                                                s_slot, s_lo, s_hi, s_upos, posh, lq, capq, tested);
+                                                s_slot, uleaf + g * cap + c0, blo + n_internal, bhi + n_internal, s_upos, posh, lq, capq, tested);
         }
         wbuf = lq.pos ? q_ld(lq.e) : 0ull;
     }

@@ -159,3 +159,17 @@ def test_graph_batch_with_cache_regrows(torch_cuda):
     b, ib = _run(ps, 5, graph_batch=1)
     _same(a, b)
     assert ib["graph_passes"] >= 2, ib
+
+
+@pytest.mark.parametrize("seed", [61, 62])
+def test_graph_single_instance_passes(torch_cuda, seed):
+    """Batches of one instance (a Plummer sphere with fast random motions):
+    its groups' cache needs move from step to step, so the captured pass
+    regrows groups on the device, with its cache-rebuild rounds switched off
+    when no h leaves chi h_cache; the layout must stay the one stage 2 wrote."""
+    _say(f"[graph] one-instance batches, Plummer 60000, seed {seed}")
+    ps = [_random_state(gen.plummer(60000, seed, dtype=np.float32), seed, vscale=0.4)]
+    a, _ = _run(ps, 6, graph_batch=0)
+    b, ib = _run(ps, 6, graph_batch=1)
+    _same(a, b)
+    assert ib["graph_passes"] >= 3, ib
