@@ -55,10 +55,14 @@ def stage_bytes_pp(stage, T):
 # kernel's sources at the time: the figure is reported only while they match.
 TRAFFIC = {
     ("particle_cache", "sedov256"): {
-        "bytes_per_launch": 5.1394e9,     # FETCH + WRITE of k_group_cache<float, 1>
-        "sources_sha256": "e202c57852f83ab9d843fc48c20fe423c45fc221299c1e5c17f0f1c07eaed47c"},
+        "bytes_per_launch": 5.4307e9,     # FETCH + WRITE of k_group_cache<float, 1>
+        "sources_sha256": "985476384e2923f10a1bf2d20a323ee54e97c874c468f54dc26314b1b258c3b0"},
+    ("force", "sedov256"): {
+        "bytes_per_launch": 7.0151e9,     # FETCH + WRITE of k_force<float, 1536, 0, 2>
+        "sources_sha256": "907610af550b8c0913070b799331247132387e93d8cf2bb105efd0d95703866f"},
 }
-KERNEL_SOURCES = {"particle_cache": ("neigh.hip", "common.hpp", "kernels.hpp")}
+KERNEL_SOURCES = {"particle_cache": ("neigh.hip", "common.hpp", "kernels.hpp"),
+                  "force": ("sph.hip", "common.hpp", "kernels.hpp")}
 
 # Vector instructions the dominant kernel issues per launch (rocprofv3 --pmc
 # SQ_INSTS_VALU, wave instructions summed over the chip), with the sha256 of
@@ -68,8 +72,11 @@ KERNEL_SOURCES = {"particle_cache": ("neigh.hip", "common.hpp", "kernels.hpp")}
 # figure beside the HBM roofline; the clock under load is not measured here.
 VALU_INSTS = {
     ("particle_cache", "sedov256"): {
-        "valu_insts_per_launch": 1.3719e9,   # k_group_cache<float, 1>
-        "sources_sha256": "e202c57852f83ab9d843fc48c20fe423c45fc221299c1e5c17f0f1c07eaed47c"},
+        "valu_insts_per_launch": 1.3700e9,   # k_group_cache<float, 1>
+        "sources_sha256": "985476384e2923f10a1bf2d20a323ee54e97c874c468f54dc26314b1b258c3b0"},
+    ("force", "sedov256"): {
+        "valu_insts_per_launch": 2.0264e9,   # k_force<float, 1536, 0, 2>
+        "sources_sha256": "907610af550b8c0913070b799331247132387e93d8cf2bb105efd0d95703866f"},
 }
 CU_COUNT, CLOCK_HZ = 256, 2.4e9
 
