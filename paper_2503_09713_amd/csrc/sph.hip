@@ -1154,7 +1154,16 @@ template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStre
     if (n > 0) hipLaunchKernelGGL((k_copy_h<T>), grid_for(n, 256), dim3(256), 0, st, posh, hc, n, skip);
 }
 
-constexpr int DENS_CH_F = 2048, DENS_CH_D = 1024;
+// Union slots staged per LDS chunk.  FP32 density: 1256 slots keep a
+// workgroup's LDS within an eighth of the CU's 160 KiB, so its 62 VGPRs and
+// the LDS both allow eight waves per SIMD (larger unions take several chunks,
+// restaged on every Newton pass: the occupancy pays for that on the Sedov
+// and lattice workloads).  FP64 density is FP64-ALU bound at five waves per
+// SIMD by registers; FP32 force needs its union in one chunk (multi-chunk
+// force is twice as slow), which caps it at two workgroups per CU.
+constexpr int DENS_CH_F = 1256, DENS_CH_D = 1024;
+static_assert(sizeof(DensShared<float, DENS_CH_F>) <= 160 * 1024 / 8,
+              "FP32 density LDS must allow eight workgroups per CU");
 constexpr int FORCE_CH_F = 1536, FORCE_CH_D = 640;
 
 template <class T, int K>

@@ -2,7 +2,8 @@
 per-device scratch array) against shsph_step on the same inputs: bit for bit,
 over two calls in a row, the second with a smaller input, with the scratch
 array used by another context in between, and CFL steps that take the dt of
-the context's own previous allocation-free step.  Also the size limit."""
+the context's own previous allocation-free step; an FP64 step near the
+particle limit; the size limit itself."""
 import sys
 
 import numpy as np
@@ -105,6 +106,26 @@ def test_noalloc_step_equals_step(torch_cuda):
     _same(a2, b2, "call 4")
     for c in (ref, ref2, nal, other):
         c.close()
+
+
+def test_noalloc_at_size_limit(torch_cuda):
+    """FP64 near the particle limit (50^3 = 125000 <= 131072): the working
+    memory of the largest admitted FP64 step, lattice-like neighbour counts,
+    fits the static array, and the step still equals shsph_step."""
+    T = np.float64
+    _say("[noalloc] 50^3 FP64 state (near the particle limit)")
+    p, s, dt = _state(50, 36, T)
+    ref = shsph.Context(0, eps_h=1e-12)
+    nal = shsph.Context(0, eps_h=1e-12)
+    a, b = _set(p, s), _set(p, s)
+    for k, d in enumerate((dt, 0.0)):
+        _say(f"[noalloc] 50^3 FP64 call {k + 1}, dt {d}")
+        u_ref = ref.step(a, d, want_dt=True)
+        u_nal = nal.step_noalloc(b, d, want_dt=True)
+        assert u_ref == u_nal and u_ref > 0
+        _same(a, b, f"50^3 call {k + 1}")
+    ref.close()
+    nal.close()
 
 
 def test_noalloc_limits(torch_cuda):
