@@ -398,21 +398,68 @@ template <int BLOCK, class T, class Op> __device__ inline T block_reduce(T v, T*
 // ---------------------------------------------------------------------------
 // Staging of a group's candidate union into LDS: slots [c0, c1) of the union
 // (its leaves' particles in ascending key order) are copied from the
-// key-order arrays.  One thread per union leaf.
+// key-order arrays.  BATCH = 0: one thread per union leaf copies the leaf's
+// particles, one load after another.  BATCH > 0: one thread per union leaf
+// writes, into the first word of each of its slots, the offset from slot to
+// key-order index; then one thread per slot copies, with BATCH slots' loads
+// in flight per thread (shorter latency, BATCH * NF more live registers).
+// Slots past the last staged leaf (a union larger than the cache capacity)
+// stay unwritten.  Every thread of the block must call it (BATCH > 0 holds a
+// barrier).
 // ---------------------------------------------------------------------------
-template <class T, int NF, int NT = GROUP>
+template <class T, int NF, int NT = GROUP, int BATCH = 0>
 __device__ inline void stage_union(const vec4<T>* const* src, vec4<T>* const* dst, const u32* id,
                                    const u32* ul, const u32* us, u32 nu, u32 c0, u32 c1)
 {
+    if (BATCH == 0) {
+        for (u32 j = threadIdx.x; j < nu; j += NT) {
+            const u32 s0 = us[j];
+            const u32 leaf = ul[j];
+            const u32 b0 = id[leaf], sz = id[leaf + 1] - b0;
+            const u32 lo = s0 > c0 ? s0 : c0;
+            const u32 hi = (s0 + sz) < c1 ? (s0 + sz) : c1;
+            for (u32 s = lo; s < hi; ++s) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) dst[f][s - c0] = src[f][b0 + (s - s0)];
+            }
+        }
+        return;
+    }
+    constexpr int B = BATCH > 0 ? BATCH : 1;
+    u32 se = 0;                                  // end of the staged leaves' slots
+    if (nu > 0) {
+        const u32 lz = ul[nu - 1];
+        se = us[nu - 1] + (id[lz + 1] - id[lz]);
+    }
     for (u32 j = threadIdx.x; j < nu; j += NT) {
         const u32 s0 = us[j];
         const u32 leaf = ul[j];
         const u32 b0 = id[leaf], sz = id[leaf + 1] - b0;
         const u32 lo = s0 > c0 ? s0 : c0;
         const u32 hi = (s0 + sz) < c1 ? (s0 + sz) : c1;
-        for (u32 s = lo; s < hi; ++s) {
+        for (u32 s = lo; s < hi; ++s) *reinterpret_cast<int*>(&dst[0][s - c0]) = (int)(b0 - s0);
+    }
+    __syncthreads();
+    const u32 ce = se < c1 ? se : c1;
+    const u32 cnt = ce > c0 ? ce - c0 : 0u;
+    for (u32 s0 = threadIdx.x; s0 < cnt; s0 += B * NT) {
+        vec4<T> v[B][NF];
 #pragma unroll
-            for (int f = 0; f < NF; ++f) dst[f][s - c0] = src[f][b0 + (s - s0)];
+        for (int b = 0; b < B; ++b) {
+            const u32 s = s0 + b * NT;
+            if (s < cnt) {
+                const i64 i = (i64)c0 + s + *reinterpret_cast<const int*>(&dst[0][s]);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) v[b][f] = src[f][i];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const u32 s = s0 + b * NT;
+            if (s < cnt) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) dst[f][s] = v[b][f];
+            }
         }
     }
 }

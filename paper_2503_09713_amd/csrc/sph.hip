@@ -341,6 +341,11 @@ __device__ inline void atomic_min_if(u32* p, u32 v)
 // One workgroup per group: the union's positions are staged in LDS once and
 // every Newton pass reads neighbours from there.
 // ---------------------------------------------------------------------------
+// Union staging of the density and the force: FP32 with two slots' loads in
+// flight per thread; FP64 one leaf per thread (the batch's registers would
+// cost the FP64 force a wave per SIMD).
+template <class T> constexpr int STAGE_B = sizeof(T) == 4 ? 2 : 0;
+
 template <class T, int CH> struct DensShared {
     vec4<T> pos[CH];
     u32 red[GROUP / WAVE];
@@ -408,6 +413,10 @@ density_group(const i64 g, vec4<T>* __restrict__ posh, const T* __restrict__ hn,
     const bool wrap = !group_interior<T>(((const vec4<T>*)cv.glo)[g], ((const vec4<T>*)cv.ghi)[g],
                                          ((const vec4<T>*)cv.blo)[cv.root[k]].w, (T)cv.rk, bx);
     const T RK = Kern<K>::template R<T>(), CK = Kern<K>::template C<T>();
+    if (nch == 1) {                      // the whole union, staged once for every pass
+        stage_union<T, 1, GROUP, STAGE_B<T>>(src, dst, id, ul, us, nu, 0u, S);
+        __syncthreads();
+    }
     for (int it = 0; it < P.max_iter; ++it) {
         const T hinv = T(1) / h;
         const T hR2 = RK * RK * h * h;
@@ -436,10 +445,6 @@ density_group(const i64 g, vec4<T>* __restrict__ posh, const T* __restrict__ hn,
             add_r2(dx * dx + dy * dy + dz * dz);
         };
         if (nch == 1) {
-            if (it == 0) {
-                stage_union<T, 1>(src, dst, id, ul, us, nu, 0u, S);
-                __syncthreads();
-            }
             if (active) {
                 if (wrap) entries_each(my, cnt, add);
                 else entries_each(my, cnt, add_in);
@@ -449,7 +454,7 @@ density_group(const i64 g, vec4<T>* __restrict__ posh, const T* __restrict__ hn,
             for (u32 ch = 0; ch < nch; ++ch) {
                 const u32 c0 = ch * CH, c1 = min(S, c0 + CH);
                 __syncthreads();
-                stage_union<T, 1>(src, dst, id, ul, us, nu, c0, c1);
+                stage_union<T, 1, GROUP, STAGE_B<T>>(src, dst, id, ul, us, nu, c0, c1);
                 __syncthreads();
                 if (active) entries_tile(my, cnt, j, c0, c1, slots_wide(S), add);
             }
@@ -522,8 +527,10 @@ __device__ __attribute__((always_inline)) inline void density_group(const i64 g,
                             A.thermo, A.status, A.stat, A.redo, sh);
 }
 
+// FP32: at most 64 VGPRs, so that registers allow the eight waves per SIMD
+// that its LDS chunk allows.
 template <class T, int CH, int K>
-__global__ void __launch_bounds__(GROUP)
+__global__ void __launch_bounds__(GROUP, sizeof(T) == 4 ? 8 : 1)
 k_density(vec4<T>* __restrict__ posh, const T* __restrict__ hn, const T* __restrict__ hc,
           const vec4<T>* __restrict__ velu, const u32* __restrict__ id, const GroupMap gm,
           const InstDev* __restrict__ inst, SphParams P, CacheView cv, T* __restrict__ omega,
@@ -696,7 +703,7 @@ force_group(const i64 g, const vec4<T>* __restrict__ posh, const vec4<T>* __rest
         for (u32 t = threadIdx.x; t < n_st; t += FT) s_pos[t].w = fast_rcp(s_pos[t].w);
     };
     if (nch == 1) {
-        stage_union<T, 3, FT>(src, dst, id, ul, us, nu, 0u, S);
+        stage_union<T, 3, FT, STAGE_B<T>>(src, dst, id, ul, us, nu, 0u, S);
         __syncthreads();
         invert_h(S);
         __syncthreads();
@@ -707,7 +714,7 @@ force_group(const i64 g, const vec4<T>* __restrict__ posh, const vec4<T>* __rest
         for (u32 ch = 0; ch < nch; ++ch) {
             const u32 c0 = ch * CH, c1 = min(S, c0 + CH);
             __syncthreads();
-            stage_union<T, 3, FT>(src, dst, id, ul, us, nu, c0, c1);
+            stage_union<T, 3, FT, STAGE_B<T>>(src, dst, id, ul, us, nu, c0, c1);
             __syncthreads();
             invert_h(c1 - c0);
             __syncthreads();

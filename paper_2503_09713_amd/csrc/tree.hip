@@ -205,77 +205,43 @@ __global__ void k_compact(const u64* __restrict__ mu, const u8* __restrict__ xi,
 // k_compact.  Each workgroup takes a tile of LV_TILE sorted codes (tiles
 // numbered by an atomic ticket) and a window reaching LV_HALO codes beyond
 // it on both sides, and runs the mask and the Jacobi passes on the window in
-// LDS.  In each pass the nearest kept code before and after every code come
-// from a block-wide max / min scan over the window (the one before that from
-// the first scan's table).  Codes outside the window are unknown (state 2):
-// a nearest code that would lie outside the window while still inside the
-// instance, or that is unknown itself, makes the result unknown, so every
-// code whose state is 0 or 1 has exactly the value the global passes give
-// it.  A tile with an unknown code of its own (a run of dropped codes longer
-// than the halo, e.g. many coincident particles) sets flag[0], and the caller
-// runs the separate passes instead; the others publish their kept count and
-// find the exclusive prefix by decoupled look-back over the earlier tiles
-// (bounded waits: flag[1] on overrun).  Writes xi, xscan[0..n], id[0..n_leaf]
-// and mu_leaf.
-constexpr int LV_BLOCK = 256, LV_ITEMS = 16, LV_TILE = LV_BLOCK * LV_ITEMS, LV_HALO = 256;
-constexpr int LV_WIN = LV_TILE + 2 * LV_HALO, LV_PER = LV_WIN / LV_BLOCK;
+// LDS.  The window is held in rows of LV_BLOCK codes, code r * LV_BLOCK + t
+// with thread t, so that a wave's LDS accesses and global stores touch
+// consecutive codes.  In each pass the nearest kept code before and after
+// every code come from the wave's ballot of its row and a table of the
+// last / first nonzero code of every (row, wave) (the one before that from
+// the first table's results, kept in LDS).  Codes outside the window are
+// unknown (state 2): a nearest code that would lie outside the window while
+// still inside the instance, or that is unknown itself, makes the result
+// unknown, so every code whose state is 0 or 1 has exactly the value the
+// global passes give it.  A tile with an unknown code of its own (a run of
+// dropped codes longer than the halo, e.g. many coincident particles) sets
+// flag[0], and the caller runs the separate passes instead; the others
+// publish their kept count and find the exclusive prefix by decoupled
+// look-back over the earlier tiles (bounded waits: flag[1] on overrun).
+// Writes xi, xscan[0..n], id[0..n_leaf] and mu_leaf.
+constexpr int LV_BLOCK = 256, LV_ITEMS = 16, LV_TILE = LV_BLOCK * LV_ITEMS, LV_HALO = LV_BLOCK;
+constexpr int LV_WIN = LV_TILE + 2 * LV_HALO, LV_PER = LV_WIN / LV_BLOCK, LV_NW = LV_BLOCK / WAVE;
 constexpr u32 LV_AGG = 1u << 30, LV_PREFIX = 2u << 30, LV_VAL = (1u << 30) - 1u;
 constexpr u32 LV_SPIN_LIMIT = 1u << 22;
 constexpr u16 LV_NONE = 0xffffu;
-static_assert(LV_WIN % LV_BLOCK == 0 && LV_WIN < 0xffff, "window split over the threads");
-
-// Exclusive scans over the threads of the block with a max (over lower
-// threads) or min (over higher threads); `lds` holds one value per wave.
-__device__ inline int lv_prefix_max(int v, int* lds)
-{
-    const int lane = __lane_id(), wid = threadIdx.x / WAVE;
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const int y = __shfl_up(x, d, WAVE);
-        if (lane >= d) x = x > y ? x : y;
-    }
-    if (lane == WAVE - 1) lds[wid] = x;
-    __syncthreads();
-    int c = -1;
-    for (int w = 0; w < wid; ++w) c = c > lds[w] ? c : lds[w];
-    int e = __shfl_up(x, 1, WAVE);
-    if (lane == 0) e = -1;
-    __syncthreads();
-    return c > e ? c : e;
-}
-
-__device__ inline int lv_suffix_min(int v, int* lds)
-{
-    const int lane = __lane_id(), wid = threadIdx.x / WAVE;
-    constexpr int NW = LV_BLOCK / WAVE;
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const int y = __shfl_down(x, d, WAVE);
-        if (lane + d < WAVE) x = x < y ? x : y;
-    }
-    if (lane == 0) lds[wid] = x;
-    __syncthreads();
-    int c = 1 << 30;
-    for (int w = wid + 1; w < NW; ++w) c = c < lds[w] ? c : lds[w];
-    int e = __shfl_down(x, 1, WAVE);
-    if (lane == WAVE - 1) e = 1 << 30;
-    __syncthreads();
-    return c < e ? c : e;
-}
+constexpr int LV_FAR = 1 << 30;          // "no nonzero code after" in the window
+static_assert(LV_WIN % LV_BLOCK == 0 && LV_WIN < 0xffff, "window split into rows");
+static_assert(LV_HALO % LV_BLOCK == 0, "the tile starts on a row");
+static_assert(LV_ITEMS * LV_NW == WAVE, "one (row, wave) kept count per lane of a wave");
 
 // Nearest kept code found by a scan (`a`: -1 / >= W when none in the window)
 // for a code of the instance [f, l) (window coordinates): the slot, -1 for
-// none inside the instance, -2 for unknown.
-__device__ inline int lv_resolve_prev(const u8* m, int a, int f)
+// none inside the instance, -2 for unknown.  `m` holds the current mask in
+// bits sh, sh + 1 of each byte.
+__device__ inline int lv_resolve_prev(const u8* m, int sh, int a, int f)
 {
-    if (a >= 0 && a >= f) return m[a] == 2 ? -2 : a;
+    if (a >= 0 && a >= f) return ((m[a] >> sh) & 3) == 2 ? -2 : a;
     return f >= 0 ? -1 : -2;
 }
-__device__ inline int lv_resolve_next(const u8* m, int c, int l, int W)
+__device__ inline int lv_resolve_next(const u8* m, int sh, int c, int l, int W)
 {
-    if (c < W && c < l) return m[c] == 2 ? -2 : c;
+    if (c < W && c < l) return ((m[c] >> sh) & 3) == 2 ? -2 : c;
     return l <= W ? -1 : -2;
 }
 
@@ -287,35 +253,55 @@ k_leaves_fused(const u64* __restrict__ mu, i64 n, const i64* __restrict__ p_off,
                u32* __restrict__ flag)
 {
     __shared__ u64 s_mu[LV_WIN];
-    __shared__ u8 s_m[2][LV_WIN];
+    // mask of the current pass in bits 2 cur .. 2 cur + 1, the next pass's
+    // in the other two: a thread rewrites only its own codes' bytes and
+    // leaves the current field as it was, so readers of that field race
+    // with nothing
+    __shared__ u8 s_m[LV_WIN];
     __shared__ u16 s_prev[LV_WIN];
-    __shared__ int s_scr[LV_BLOCK / WAVE];
-    __shared__ u32 s_tile, s_excl;
+    __shared__ int s_last[LV_PER][LV_NW], s_first[LV_PER][LV_NW];
+    __shared__ u32 s_cnt[WAVE];
+    __shared__ u32 s_tile, s_excl, s_tot;
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
+    const int lane = __lane_id(), wid = threadIdx.x / WAVE;
+    const u64 below = (1ull << lane) - 1ull;                      // lanes before this one
+    const u64 above = lane == WAVE - 1 ? 0ull : ~0ull << (lane + 1);
     const i64 tile = s_tile;
     const i64 ntiles = (n + LV_TILE - 1) / LV_TILE;
     const i64 t0 = tile * LV_TILE, t1 = (t0 + LV_TILE) < n ? (t0 + LV_TILE) : n;
     const i64 w0 = t0 > LV_HALO ? t0 - LV_HALO : 0;
     const i64 w1 = (t1 + LV_HALO) < n ? (t1 + LV_HALO) : n;
     const int W = (int)(w1 - w0);
-    for (int j = threadIdx.x; j < W; j += LV_BLOCK) s_mu[j] = mu[w0 + j];
-    // this thread's window slots j0 .. j0 + LV_PER - 1 and the instance range
-    // [f, l) of each (window coordinates, clamped into int range)
-    const int j0 = threadIdx.x * LV_PER;
+    {
+        // all the window's loads in flight at once, then to LDS
+        u64 ld[LV_PER];
+#pragma unroll
+        for (int r = 0; r < LV_PER; ++r) {
+            const int j = r * LV_BLOCK + threadIdx.x;
+            ld[r] = j < W ? mu[w0 + j] : 0ull;
+        }
+#pragma unroll
+        for (int r = 0; r < LV_PER; ++r) {
+            const int j = r * LV_BLOCK + threadIdx.x;
+            if (j < W) s_mu[j] = ld[r];
+        }
+    }
+    // the instance range [f, l) of this thread's code in every row (window
+    // coordinates, clamped into int range)
     int fr[LV_PER], lr[LV_PER];
     {
         i64 f = 0, l = n;
         int k = 0;
         if (MULTI) {
-            k = find_seg(p_off, ninst, w0 + (j0 < W ? j0 : 0));
+            k = find_seg(p_off, ninst, w0 + ((int)threadIdx.x < W ? (int)threadIdx.x : 0));
             f = p_off[k];
             l = p_off[k + 1];
         }
 #pragma unroll
         for (int r = 0; r < LV_PER; ++r) {
             if (MULTI) {
-                const i64 i = w0 + j0 + r;
+                const i64 i = w0 + r * LV_BLOCK + threadIdx.x;
                 while (k + 1 < ninst && i >= l) { ++k; f = l; l = p_off[k + 1]; }
             }
             fr[r] = (int)((f - w0) > -(1 << 30) ? (f - w0) : -(1 << 30));
@@ -326,93 +312,129 @@ k_leaves_fused(const u64* __restrict__ mu, i64 n, const i64* __restrict__ p_off,
     // keep mask: the first code of an instance, else a code unlike the one before
 #pragma unroll
     for (int r = 0; r < LV_PER; ++r) {
-        const int j = j0 + r;
+        const int j = r * LV_BLOCK + threadIdx.x;
         if (j >= W) continue;
         u8 v;
         if (j == fr[r]) v = 1;
         else if (j == 0) v = 2;
         else v = s_mu[j] != s_mu[j - 1] ? 1 : 0;
-        s_m[0][j] = v;
+        s_m[j] = v;
     }
     __syncthreads();
     int cur = 0;
     for (int p = 0; p < nred; ++p) {
-        const u8* mo = s_m[cur];
-        u8* mn = s_m[cur ^ 1];
-        // nearest nonzero (kept or unknown) code before / after each slot
-        int last = -1, first = 1 << 30;
+        const int sh = 2 * cur, nsh = 2 - sh;
+        // last and first nonzero (kept or unknown) code of every (row, wave)
 #pragma unroll
         for (int r = 0; r < LV_PER; ++r) {
-            const int j = j0 + r;
-            if (j < W && mo[j] != 0) { last = j; if (first == (1 << 30)) first = j; }
-        }
-        int run = lv_prefix_max(last, s_scr);
-        int nxt[LV_PER];
-#pragma unroll
-        for (int r = 0; r < LV_PER; ++r) {
-            const int j = j0 + r;
-            if (j < W) {
-                s_prev[j] = run < 0 ? LV_NONE : (u16)run;
-                if (mo[j] != 0) run = j;
+            const int j = r * LV_BLOCK + threadIdx.x;
+            const u64 nz = __ballot(j < W && ((s_m[j] >> sh) & 3) != 0);
+            if (lane == 0) {
+                const int base = r * LV_BLOCK + wid * WAVE;
+                s_last[r][wid] = nz ? base + 63 - __clzll(nz) : -1;
+                s_first[r][wid] = nz ? base + __ffsll((unsigned long long)nz) - 1 : LV_FAR;
             }
         }
-        run = lv_suffix_min(first, s_scr);
-#pragma unroll
-        for (int r = LV_PER - 1; r >= 0; --r) {
-            const int j = j0 + r;
-            nxt[r] = run;
-            if (j < W && mo[j] != 0) run = j;
-        }
-        __syncthreads();                      // s_prev complete
+        __syncthreads();
+        // nearest nonzero code before each code, to LDS (the resolution also
+        // needs it at the code found)
+        int run = -1;                         // last nonzero code of the rows before r
 #pragma unroll
         for (int r = 0; r < LV_PER; ++r) {
-            const int j = j0 + r;
+            const int j = r * LV_BLOCK + threadIdx.x;
+            const u64 nz = __ballot(j < W && ((s_m[j] >> sh) & 3) != 0);
+            int bw = run, rowmax = run;
+#pragma unroll
+            for (int w = 0; w < LV_NW; ++w) {
+                const int x = s_last[r][w];
+                if (w < wid) bw = bw > x ? bw : x;
+                rowmax = rowmax > x ? rowmax : x;
+            }
+            const u64 lo = nz & below;
+            const int pv = lo ? r * LV_BLOCK + wid * WAVE + 63 - __clzll(lo) : bw;
+            if (j < W) s_prev[j] = pv < 0 ? LV_NONE : (u16)pv;
+            run = rowmax;
+        }
+        __syncthreads();                      // s_prev complete
+        // resolve the kept codes, last row first; the nearest nonzero code
+        // after each comes from the same ballot and the rows already passed
+        run = LV_FAR;                         // first nonzero code of the rows after r
+#pragma unroll
+        for (int r = LV_PER - 1; r >= 0; --r) {
+            const int j = r * LV_BLOCK + threadIdx.x;
+            const u8 byte = j < W ? s_m[j] : (u8)0;
+            const u8 v = (byte >> sh) & 3;
+            const u64 nz = __ballot(v != 0);
+            int aw = run, rowmin = run;
+#pragma unroll
+            for (int w = 0; w < LV_NW; ++w) {
+                const int x = s_first[r][w];
+                if (w > wid) aw = aw < x ? aw : x;
+                rowmin = rowmin < x ? rowmin : x;
+            }
+            run = rowmin;
             if (j >= W) continue;
-            const u8 v = mo[j];
-            if (v != 1) { mn[j] = v; continue; }
-            const int pa = s_prev[j] == LV_NONE ? -1 : (int)s_prev[j];
-            const int a = lv_resolve_prev(mo, pa, fr[r]);
-            const int c = lv_resolve_next(mo, nxt[r], lr[r], W);
-            if (a == -2 || c == -2) { mn[j] = 2; continue; }
-            const u64 m0 = s_mu[j];
-            const int d0 = c >= 0 ? delta_k(m0, s_mu[c]) : -1;
-            const int dm1 = a >= 0 ? delta_k(s_mu[a], m0) : -1;
-            if (!(d0 < dm1)) { mn[j] = 1; continue; }      // kept whatever lies beyond a
-            const int pb = s_prev[a] == LV_NONE ? -1 : (int)s_prev[a];   // a >= 0 here
-            const int b = lv_resolve_prev(mo, pb, fr[r]);
-            if (b == -2) { mn[j] = 2; continue; }
-            const int dm2 = b >= 0 ? delta_k(s_mu[b], s_mu[a]) : -1;
-            mn[j] = (dm2 < dm1) ? 0 : 1;
+            const u64 hi = nz & above;
+            const int nx = hi ? r * LV_BLOCK + wid * WAVE + __ffsll((unsigned long long)hi) - 1 : aw;
+            u8 out = v;
+            if (v == 1) {
+                const int pa = s_prev[j] == LV_NONE ? -1 : (int)s_prev[j];
+                const int a = lv_resolve_prev(s_m, sh, pa, fr[r]);
+                const int c = lv_resolve_next(s_m, sh, nx, lr[r], W);
+                if (a == -2 || c == -2) {
+                    out = 2;
+                } else {
+                    const u64 m0 = s_mu[j];
+                    const int d0 = c >= 0 ? delta_k(m0, s_mu[c]) : -1;
+                    const int dm1 = a >= 0 ? delta_k(s_mu[a], m0) : -1;
+                    if (d0 < dm1) {                   // else kept whatever lies beyond a
+                        const int pb = s_prev[a] == LV_NONE ? -1 : (int)s_prev[a];   // a >= 0 here
+                        const int b = lv_resolve_prev(s_m, sh, pb, fr[r]);
+                        if (b == -2) out = 2;
+                        else {
+                            const int dm2 = b >= 0 ? delta_k(s_mu[b], s_mu[a]) : -1;
+                            out = (dm2 < dm1) ? 0 : 1;
+                        }
+                    }
+                }
+            }
+            s_m[j] = (u8)((byte & (3u << sh)) | (out << nsh));
         }
         __syncthreads();
         cur ^= 1;
     }
-    const u8* mf = s_m[cur];
-    // the tile's codes, LV_ITEMS consecutive ones per thread
-    const int tb = (int)(t0 - w0) + threadIdx.x * LV_ITEMS;
+    const int fsh = 2 * cur;
+    // the tile's rows: kept counts per (row, wave), scanned by the first wave
+    const int r0 = (int)(t0 - w0) / LV_BLOCK;
     const int te = (int)(t1 - w0);
-    u32 cnt = 0;
     bool unknown = false;
 #pragma unroll
-    for (int r = 0; r < LV_ITEMS; ++r) {
-        const int j = tb + r;
-        if (j < te) {
-            const u8 v = mf[j];
-            unknown |= v == 2;
-            cnt += v == 1 ? 1u : 0u;
-        }
+    for (int q = 0; q < LV_ITEMS; ++q) {
+        const int j = (r0 + q) * LV_BLOCK + threadIdx.x;
+        const u8 v = j < te ? (s_m[j] >> fsh) & 3 : 0;
+        unknown |= v == 2;
+        const u64 km = __ballot(v == 1);
+        if (lane == 0) s_cnt[q * LV_NW + wid] = (u32)__popcll(km);
     }
     const bool bad = __syncthreads_or(unknown) != 0;
-    if (bad) {
-        if (threadIdx.x == 0) atomicOr(&flag[0], 1u);
-        cnt = 0;            // keep the look-back of later tiles going
+    __syncthreads();                          // s_cnt complete
+    if (threadIdx.x < WAVE) {
+        const u32 x = bad ? 0u : s_cnt[lane];    // keep the look-back of later tiles going
+        u32 incl = x;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const u32 y = __shfl_up(incl, d, WAVE);
+            if (lane >= d) incl += y;
+        }
+        s_cnt[lane] = incl - x;
+        if (lane == WAVE - 1) s_tot = incl;
+        if (bad && lane == 0) atomicOr(&flag[0], 1u);
     }
-    u32 tot;
-    const u32 ex_local = block_excl_scan<LV_BLOCK>(cnt, (u32*)s_scr, tot);
+    __syncthreads();
+    const u32 tot = s_tot;
     // decoupled look-back by the first wave, 64 earlier tiles per round: each
     // lane reads one status word; the nearest inclusive prefix ends the walk
     if (threadIdx.x < WAVE) {
-        const int lane = threadIdx.x;
         u32* mine = status + tile;
         u32 excl = 0;
         if (tile == 0) {
@@ -461,19 +483,20 @@ k_leaves_fused(const u64* __restrict__ mu, i64 n, const i64* __restrict__ p_off,
         }
     }
     __syncthreads();
-    u32 k = s_excl + ex_local;
+    const u32 ex = s_excl;
 #pragma unroll
-    for (int r = 0; r < LV_ITEMS; ++r) {
-        const int j = tb + r;
+    for (int q = 0; q < LV_ITEMS; ++q) {
+        const int j = (r0 + q) * LV_BLOCK + threadIdx.x;
+        const u8 v = j < te ? (s_m[j] >> fsh) & 3 : 0;
+        const u64 km = __ballot(v == 1);
         if (j < te) {
             const i64 i = w0 + j;
-            const u8 v = mf[j];
+            const u32 k = ex + s_cnt[q * LV_NW + wid] + (u32)__popcll(km & below);
             xi[i] = v;
             xscan[i] = k;
             if (v == 1 && !bad) {
                 id[k] = (u32)i;
                 mu_leaf[k] = s_mu[j];
-                ++k;
             }
         }
     }
