@@ -322,13 +322,34 @@ __global__ void __launch_bounds__(RS_BLOCK)
 k_ad_minmax(const u64* __restrict__ keys, i64 n, u64* __restrict__ tmin, u64* __restrict__ tmax)
 {
     __shared__ u64 lmax[RS_WAVES], lmin[RS_WAVES];
+    __shared__ u64 s_k[AD_TILE + 2];              // the tile and a key on each side
+    constexpr int R = AD_TILE / RS_BLOCK;
     const i64 t0 = (i64)blockIdx.x * AD_TILE;
+    {
+        // every load of the thread in flight at once, then to LDS
+        u64 ld[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const i64 i = t0 + r * RS_BLOCK + threadIdx.x;
+            ld[r] = i < n ? keys[i] : 0ull;
+        }
+        u64 side = 0;
+        if (threadIdx.x == 0) side = t0 > 0 ? keys[t0 - 1] : 0ull;
+        if (threadIdx.x == 1) side = t0 + AD_TILE < n ? keys[t0 + AD_TILE] : ~0ull;
+#pragma unroll
+        for (int r = 0; r < R; ++r) s_k[1 + r * RS_BLOCK + threadIdx.x] = ld[r];
+        if (threadIdx.x == 0) s_k[0] = side;
+        if (threadIdx.x == 1) s_k[AD_TILE + 1] = side;
+    }
+    __syncthreads();
     u64 mx = 0, mn = ~0ull;
-    for (int j = threadIdx.x; j < AD_TILE; j += RS_BLOCK) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = r * RS_BLOCK + threadIdx.x;
         const i64 i = t0 + j;
         if (i < n) {
-            const u64 k = keys[i];
-            const u64 a = i > 0 ? keys[i - 1] : 0ull, b = i + 1 < n ? keys[i + 1] : ~0ull;
+            const u64 k = s_k[j + 1];
+            const u64 a = s_k[j], b = i + 1 < n ? s_k[j + 2] : ~0ull;
             if (!ad_spike(a, k, b)) {
                 mx = k > mx ? k : mx;
                 mn = k < mn ? k : mn;
@@ -388,7 +409,19 @@ k_ad_classify(const u64* __restrict__ keys, const u32* __restrict__ vals, i64 n,
     __shared__ u32 s_cnt[RS_WAVES];
     const i64 tile = blockIdx.x, t0 = tile * AD_TILE;
     const i64 cnt = (n - t0) < AD_TILE ? (n - t0) : AD_TILE;
-    for (int j = threadIdx.x; j < AD_TILE; j += RS_BLOCK) s_k[ad_sw(j)] = j < cnt ? keys[t0 + j] : ~0ull;
+    constexpr int R = AD_TILE / RS_BLOCK;
+    u32 vl[R];                                    // values of the copy (COMPACT), loaded early
+    {
+        u64 ld[R];                                // all loads in flight, then to LDS
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int j = r * RS_BLOCK + threadIdx.x;
+            ld[r] = j < cnt ? keys[t0 + j] : ~0ull;
+            vl[r] = COMPACT && j < cnt ? vals[t0 + j] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < AD_TILE / RS_BLOCK; ++r) s_k[ad_sw(r * RS_BLOCK + threadIdx.x)] = ld[r];
+    }
     const u64 kprev = t0 > 0 ? keys[t0 - 1] : 0ull;            // neighbours across the tile
     const u64 knext = t0 + cnt < n ? keys[t0 + cnt] : ~0ull;
     __syncthreads();
@@ -466,11 +499,14 @@ k_ad_classify(const u64* __restrict__ keys, const u32* __restrict__ vals, i64 n,
     }
     __syncthreads();
     const u32 base = toff[tile];
-    for (int j = threadIdx.x; j < cnt; j += RS_BLOCK) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int j = q * RS_BLOCK + threadIdx.x;
+        if (j >= cnt) continue;
         const u32 r = s_rank[ad_sw(j)];
         const i64 i = t0 + j;
         const u64 k = s_k[ad_sw(j)];
-        const u32 v = vals[i];
+        const u32 v = vl[q];
         if (r & 0x8000u) {
             const u32 o = base + (r & 0x7fffu);
             ok[o] = k;
