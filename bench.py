@@ -55,11 +55,11 @@ def stage_bytes_pp(stage, T):
 # kernel's sources at the time: the figure is reported only while they match.
 TRAFFIC = {
     ("particle_cache", "sedov256"): {
-        "bytes_per_launch": 5.4307e9,     # FETCH + WRITE of k_group_cache<float, 1>
-        "sources_sha256": "985476384e2923f10a1bf2d20a323ee54e97c874c468f54dc26314b1b258c3b0"},
+        "bytes_per_launch": 5.4318e9,     # FETCH + WRITE of k_group_cache<float, 1>
+        "sources_sha256": "af1c356aecb643bea4c0081975e540ee19a9a28270da9d0a8795014406d320ce"},
     ("force", "sedov256"): {
-        "bytes_per_launch": 7.0151e9,     # FETCH + WRITE of k_force<float, 1536, 0, 2>
-        "sources_sha256": "907610af550b8c0913070b799331247132387e93d8cf2bb105efd0d95703866f"},
+        "bytes_per_launch": 7.0283e9,     # FETCH + WRITE of k_force<float, 1536, 0, 2>
+        "sources_sha256": "f466f47c110d2f1247b9383f85758a36738f149c5a29d41c6b65209ef0f4ad03"},
 }
 KERNEL_SOURCES = {"particle_cache": ("neigh.hip", "common.hpp", "kernels.hpp"),
                   "force": ("sph.hip", "common.hpp", "kernels.hpp")}
@@ -73,10 +73,10 @@ KERNEL_SOURCES = {"particle_cache": ("neigh.hip", "common.hpp", "kernels.hpp"),
 VALU_INSTS = {
     ("particle_cache", "sedov256"): {
         "valu_insts_per_launch": 1.3700e9,   # k_group_cache<float, 1>
-        "sources_sha256": "985476384e2923f10a1bf2d20a323ee54e97c874c468f54dc26314b1b258c3b0"},
+        "sources_sha256": "af1c356aecb643bea4c0081975e540ee19a9a28270da9d0a8795014406d320ce"},
     ("force", "sedov256"): {
-        "valu_insts_per_launch": 2.0264e9,   # k_force<float, 1536, 0, 2>
-        "sources_sha256": "907610af550b8c0913070b799331247132387e93d8cf2bb105efd0d95703866f"},
+        "valu_insts_per_launch": 2.0369e9,   # k_force<float, 1536, 0, 2>
+        "sources_sha256": "f466f47c110d2f1247b9383f85758a36738f149c5a29d41c6b65209ef0f4ad03"},
 }
 CU_COUNT, CLOCK_HZ = 256, 2.4e9
 

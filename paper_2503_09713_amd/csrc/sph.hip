@@ -1162,12 +1162,13 @@ template <class T> void launch_copy_h(const vec4<T>* posh, T* hc, i64 n, hipStre
 }
 
 // Union slots staged per LDS chunk.  FP32 density: 1256 slots keep a
-// workgroup's LDS within an eighth of the CU's 160 KiB, so its 62 VGPRs and
-// the LDS both allow eight waves per SIMD (larger unions take several chunks,
-// restaged on every Newton pass: the occupancy pays for that on the Sedov
-// and lattice workloads).  FP64 density is FP64-ALU bound at five waves per
-// SIMD by registers; FP32 force needs its union in one chunk (multi-chunk
-// force is twice as slow), which caps it at two workgroups per CU.
+// workgroup's LDS within an eighth of the CU's 160 KiB, so the LDS and its
+// registers (held to 64 VGPRs) both allow eight waves per SIMD (larger
+// unions take several chunks, restaged on every Newton pass: the occupancy
+// pays for that on the Sedov and lattice workloads).  FP64 density is
+// FP64-ALU bound: a chunk small enough for a fifth workgroup per CU was no
+// faster.  FP32 force needs its union in one chunk (multi-chunk force is
+// twice as slow), which caps it at two workgroups per CU.
 constexpr int DENS_CH_F = 1256, DENS_CH_D = 1024;
 static_assert(sizeof(DensShared<float, DENS_CH_F>) <= 160 * 1024 / 8,
               "FP32 density LDS must allow eight workgroups per CU");
