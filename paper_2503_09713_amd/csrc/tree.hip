@@ -656,29 +656,34 @@ k_boxes_local(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 
     __syncthreads();
     if (live) {
         u32 node = (u32)(lbase + g);
-        while (true) {
-            const u32 par = parent[node];
-            if (par == 0xffffffffu) break;
+        u32 par = parent[node];
+        while (par != 0xffffffffu) {
+            // the read-only topology of this level (span, children, the next
+            // parent, the sibling's Karras index) before the counter
             i64 f, l, kidx;
             node_span(par, ioff, leaf_off, ninst, endrange, f, l, kidx);
+            const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
+            const u32 gp = parent[par];
             if (f < B0 || l >= B1) {               // parent straddles blocks
                 const u32 q = atomicAdd(&s_nrec, 1u);
                 if (q < BOX_OUT) s_rec[q] = node;
                 break;
             }
             const int ps = (int)(kidx - B0);
+            const u32 other = (c0 == node) ? c1 : c0;
+            i64 k2 = 0;
+            if (other < lbase) {
+                i64 f2, l2;
+                node_span(other, ioff, leaf_off, ninst, endrange, f2, l2, k2);
+            }
             __threadfence_block();
             if (atomicAdd(&s_arr[ps], 1u) == 0) break;   // the sibling's thread continues
             __threadfence_block();
-            const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
-            const u32 other = (c0 == node) ? c1 : c0;
             vec4<T> ol, oh;
             if (other >= lbase) {
                 ol = s_llo[other - lbase - B0];
                 oh = s_lhi[other - lbase - B0];
             } else {
-                i64 f2, l2, k2;
-                node_span(other, ioff, leaf_off, ninst, endrange, f2, l2, k2);
                 ol = s_nlo[k2 - B0];
                 oh = s_nhi[k2 - B0];
             }
@@ -690,6 +695,7 @@ k_boxes_local(const vec4<T>* __restrict__ posh, const u32* __restrict__ id, i64 
             blo[par] = nl;
             bhi[par] = nh;
             node = par;
+            par = gp;
         }
     }
     __syncthreads();
@@ -732,22 +738,26 @@ k_boxes_mid(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nbloc
         for (u32 q = 0; q < nr; ++q) {
             u32 node = rec[b * BOX_OUT + q];
             vec4<T> ml = blo[node], mh = bhi[node];
-            while (true) {
-                const u32 par = parent[node];
-                if (par == 0xffffffffu) break;
+            u32 par = parent[node];
+            while (par != 0xffffffffu) {
+                // the read-only topology of this level (span, children, the
+                // next parent) in one round of loads
                 i64 f, l, kidx;
                 node_span(par, ioff, leaf_off, ninst, endrange, f, l, kidx);
+                const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
+                const u32 gp = parent[par];
                 if (f < C0 || l >= C1) {               // parent straddles this range
                     const u32 r = atomicAdd(&s_nrec, 1u);
                     if (r < BOX_OUT) s_rec[r] = node;
                     break;
                 }
+                // release fence + counter + acquire fence: the second arrival
+                // sees the first one's box
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                const u32 prev = __hip_atomic_fetch_add(&arrive[par], 1u, __ATOMIC_ACQ_REL,
+                const u32 prev = __hip_atomic_fetch_add(&arrive[par], 1u, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (prev == 0) break;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
                 const u32 other = (c0 == node) ? c1 : c0;
                 const vec4<T> ol = blo[other], oh = bhi[other];
                 ml = mk4<T>(fmin(ml.x, ol.x), fmin(ml.y, ol.y), fmin(ml.z, ol.z), fmax(ml.w, ol.w));
@@ -755,6 +765,7 @@ k_boxes_mid(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nbloc
                 blo[par] = ml;
                 bhi[par] = mh;
                 node = par;
+                par = gp;
             }
         }
     }
@@ -780,15 +791,18 @@ k_boxes_top(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nbloc
         for (u32 q = 0; q < nr; ++q) {
             u32 node = rec[b * BOX_OUT + q];
             vec4<T> ml = blo[node], mh = bhi[node];
-            while (true) {
-                const u32 par = parent[node];
-                if (par == 0xffffffffu) break;
+            u32 par = parent[node];
+            while (par != 0xffffffffu) {
+                // release fence + counter + acquire fence: the second arrival
+                // sees the first one's box; the read-only topology of the
+                // level (children, next parent) loads while the counter does
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                const u32 prev = __hip_atomic_fetch_add(&arrive[par], 1u, __ATOMIC_ACQ_REL,
+                const u32 prev = __hip_atomic_fetch_add(&arrive[par], 1u, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
+                const u32 gp = parent[par];
                 if (prev == 0) break;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                const u32 c0 = child[2 * par], c1 = child[2 * par + 1];
                 const u32 other = (c0 == node) ? c1 : c0;
                 const vec4<T> ol = blo[other], oh = bhi[other];
                 ml = mk4<T>(fmin(ml.x, ol.x), fmin(ml.y, ol.y), fmin(ml.z, ol.z), fmax(ml.w, ol.w));
@@ -796,6 +810,7 @@ k_boxes_top(const u32* __restrict__ rec, const u32* __restrict__ nrec, i64 nbloc
                 blo[par] = ml;
                 bhi[par] = mh;
                 node = par;
+                par = gp;
             }
         }
     }
