@@ -56,7 +56,7 @@ def stage_bytes_pp(stage, T):
 TRAFFIC = {
     ("particle_cache", "sedov256"): {
         "bytes_per_launch": 5.4318e9,     # FETCH + WRITE of k_group_cache<float, 1>
-        "sources_sha256": "af1c356aecb643bea4c0081975e540ee19a9a28270da9d0a8795014406d320ce"},
+        "sources_sha256": "112eeb6a4b11c376453a6b27877a8e82b7a2d3978a430d2e95c14c8f9453691d"},
     ("force", "sedov256"): {
         "bytes_per_launch": 7.0283e9,     # FETCH + WRITE of k_force<float, 1536, 0, 2>
         "sources_sha256": "f466f47c110d2f1247b9383f85758a36738f149c5a29d41c6b65209ef0f4ad03"},
@@ -73,7 +73,7 @@ KERNEL_SOURCES = {"particle_cache": ("neigh.hip", "common.hpp", "kernels.hpp"),
 VALU_INSTS = {
     ("particle_cache", "sedov256"): {
         "valu_insts_per_launch": 1.3700e9,   # k_group_cache<float, 1>
-        "sources_sha256": "af1c356aecb643bea4c0081975e540ee19a9a28270da9d0a8795014406d320ce"},
+        "sources_sha256": "112eeb6a4b11c376453a6b27877a8e82b7a2d3978a430d2e95c14c8f9453691d"},
     ("force", "sedov256"): {
         "valu_insts_per_launch": 2.0369e9,   # k_force<float, 1536, 0, 2>
         "sources_sha256": "f466f47c110d2f1247b9383f85758a36738f149c5a29d41c6b65209ef0f4ad03"},

@@ -233,12 +233,15 @@ k_group_leaves_serial(bool only_marked, const vec4<T>* __restrict__ blo, const v
 // A group whose stack outgrows the LDS buffer is marked and left to the
 // serial walk.
 // The walk is compiled twice: FULL = false keeps only the node stack in LDS
-// (6 KB per wave, so many more waves hide the tree's load latency) and takes
+// (4 KB per wave, so many more waves hide the tree's load latency) and takes
 // the compact groups, marking the others; FULL = true, with the per-entry
-// target masks and the target boxes, then takes the marked groups.
+// target masks and the target boxes, then takes the marked groups.  1024
+// stack entries: at 1536 the LDS allowed the compact walk six waves per
+// SIMD instead of eight, and the Sedov and batched workloads ran slower (a
+// group that outgrows the stack takes the serial walk).
 constexpr int S1_WAVES = 1;             // waves per workgroup, full walk
 constexpr int S1_CWAVES = 4;            // waves per workgroup, compact walk
-constexpr int S1_SMAX = 1536;
+constexpr int S1_SMAX = 1024;
 constexpr u32 S1_WIDE = 0xfffffffeu;    // ucnt marker: group left to the full walk
 constexpr int S1_TS = 32;               // target runs (mask bits)
 constexpr u32 S1_FINAL = 0x80000000u;      // stack entry: an accepted leaf
